@@ -1,0 +1,859 @@
+// Plain FP64 CPU oracle of the explicit ideal GLM-MHD block update.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+// this file: only the tests, the package smoke check and the benchmark's
+// cpu_baseline leg use it.  It shares no code, header, table or helper with the
+// HIP library; both sides read the same seeded primitive input arrays and
+// nothing else.
+//
+// What it computes (MPI-AMRVAC 3.0, arXiv 2303.03026):
+//   * conservative cell-centred finite volumes inside a multistage SSP
+//     Runge-Kutta step ("Schemes and limiters for HD and MHD", Table
+//     tab:schemes_time: SSPRK(2,2) and SSPRK(3,3));
+//   * limited linear reconstruction of primitive variables giving a left and
+//     a right state per face, with the 'vanleer' limiter and 2 ghost cells
+//     (Table t:limiters);
+//   * the HLL flux (Table tab:schemes_space; Harten et al. 1983);
+//   * the 'glm' divergence control of Dedner et al. 2002 (Table t:divb);
+//   * the CFL coupling of the time step to the grid spacing ("Schemes and
+//     limiters for HD and MHD");
+//   * small-value checking on entry to the conserved-to-primitive step, with
+//     the optional replacement fix ("Bootstrapping" section);
+//   * a static block-based octree/quadtree AMR hierarchy with refinement
+//     ratio 2 where only leaf blocks are advanced ("Open source strategy"
+//     section and the AMR statement in "Schemes and limiters"); ghost cells
+//     come from same-level neighbours, restriction of finer neighbours,
+//     prolongation of coarser neighbours or physical boundaries.
+//
+// The paper prints none of these formulas; they are written here from the
+// cited textbook definitions in the readings listed in the repository's
+// design notes.  Where the paper is silent the oracle takes these readings:
+//   magnetic units with p_mag = |B|^2/2 (plasma beta 2p/B^2, Alfven shock
+//   section); GLM without the extended source terms, with psi damping as the
+//   explicit source -kappa*psi; c_h and kappa fixed per step from dt;
+//   "max of sum" CFL; Davis wave-speed bounds; van Leer's harmonic slope;
+//   first-order fallback per face on non-positive reconstructed rho or p;
+//   delta-form SSPRK; pairwise restriction sums; minmod-limited conservative
+//   linear prolongation of conserved variables; flux correction (reflux) at
+//   coarse/fine faces; one global dt; face ghost slabs only (the
+//   dimension-by-dimension stencil never reads edge or corner ghosts).
+//
+// Plain loops, no blocking or fusion.  Built with -O2 -ffp-contract=off.
+// OpenMP runs independent blocks of one phase on several threads; the
+// results do not depend on the thread count.
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+constexpr int NV = 9;
+// conserved: rho, m_x, m_y, m_z, e, B_x, B_y, B_z, psi
+enum { RHO = 0, MX = 1, MY = 2, MZ = 3, EN = 4, BX = 5, BY = 6, BZ = 7, PSI = 8 };
+// primitive: rho, v_x, v_y, v_z, p, B_x, B_y, B_z, psi
+enum { VX = 1, VY = 2, VZ = 3, PR = 4 };
+enum { BC_PERIODIC = 0, BC_ZEROGRAD = 1, BC_REFLECT = 2, BC_FIXED = 3 };
+enum { FLAG_SMALL_RHO = 1, FLAG_SMALL_P = 2, FLAG_BAD_DT = 4 };
+
+struct Cell {
+  double v[NV];
+};
+
+struct Phys {
+  double gamma;
+  double small_rho;
+  double small_p;
+  int fix;
+};
+
+// ---------------------------------------------------------------------------
+// Equation of state and variable conversion (ideal MHD, total energy form,
+// Table tab:eqs "mhd"; magnetic pressure |B|^2/2).
+
+Cell prim_to_cons(const Cell& w, double gamma) {
+  Cell u;
+  const double rho = w.v[RHO];
+  u.v[RHO] = rho;
+  u.v[MX] = rho * w.v[VX];
+  u.v[MY] = rho * w.v[VY];
+  u.v[MZ] = rho * w.v[VZ];
+  const double v2 = w.v[VX] * w.v[VX] + w.v[VY] * w.v[VY] + w.v[VZ] * w.v[VZ];
+  const double b2 = w.v[BX] * w.v[BX] + w.v[BY] * w.v[BY] + w.v[BZ] * w.v[BZ];
+  u.v[EN] = w.v[PR] / (gamma - 1.0) + 0.5 * rho * v2 + 0.5 * b2;
+  u.v[BX] = w.v[BX];
+  u.v[BY] = w.v[BY];
+  u.v[BZ] = w.v[BZ];
+  u.v[PSI] = w.v[PSI];
+  return u;
+}
+
+// Conserved -> primitive with the small-value check of the Bootstrapping
+// section: a cell whose density is not above small_rho or whose pressure is
+// not above small_p is reported; with the fix on, the primitive density is
+// replaced first (velocity then uses it), then the primitive pressure.  The
+// conserved state is never modified and B is never touched.
+int cons_to_prim(const Cell& u, const Phys& ph, Cell& w) {
+  int bad = 0;
+  double rho = u.v[RHO];
+  if (!(rho > ph.small_rho)) {
+    bad |= FLAG_SMALL_RHO;
+    if (ph.fix) rho = ph.small_rho;
+  }
+  w.v[RHO] = rho;
+  w.v[VX] = u.v[MX] / rho;
+  w.v[VY] = u.v[MY] / rho;
+  w.v[VZ] = u.v[MZ] / rho;
+  const double m2 = u.v[MX] * u.v[MX] + u.v[MY] * u.v[MY] + u.v[MZ] * u.v[MZ];
+  const double b2 = u.v[BX] * u.v[BX] + u.v[BY] * u.v[BY] + u.v[BZ] * u.v[BZ];
+  double p = (ph.gamma - 1.0) * (u.v[EN] - 0.5 * m2 / rho - 0.5 * b2);
+  if (!(p > ph.small_p)) {
+    bad |= FLAG_SMALL_P;
+    if (ph.fix) p = ph.small_p;
+  }
+  w.v[PR] = p;
+  w.v[BX] = u.v[BX];
+  w.v[BY] = u.v[BY];
+  w.v[BZ] = u.v[BZ];
+  w.v[PSI] = u.v[PSI];
+  return bad;
+}
+
+// Fast magnetosonic speed along direction d.
+double fast_speed(const Cell& w, int d, double gamma) {
+  const double rho = w.v[RHO];
+  const double a2 = gamma * w.v[PR] / rho;
+  const double b2 = (w.v[BX] * w.v[BX] + w.v[BY] * w.v[BY] + w.v[BZ] * w.v[BZ]) / rho;
+  const double bn2 = w.v[BX + d] * w.v[BX + d] / rho;
+  const double s = a2 + b2;
+  double disc = s * s - 4.0 * a2 * bn2;
+  if (disc < 0.0) disc = 0.0;
+  return std::sqrt(0.5 * (s + std::sqrt(disc)));
+}
+
+// van Leer (1974) slope: harmonic mean of the one-sided differences when they
+// share a sign, zero otherwise (the 'vanleer' row of Table t:limiters).
+double vanleer(double dm, double dp) {
+  const double prod = dm * dp;
+  if (prod > 0.0) return 2.0 * prod / (dm + dp);
+  return 0.0;
+}
+
+double minmod(double a, double b) {
+  if (a * b > 0.0) return std::fabs(a) < std::fabs(b) ? a : b;
+  return 0.0;
+}
+
+// Physical ideal-MHD flux along d for every component except B_d and psi,
+// which the GLM interface solve supplies.
+void phys_flux(const Cell& w, const Cell& u, int d, double f[NV]) {
+  const double vn = w.v[VX + d];
+  const double bn = w.v[BX + d];
+  const double b2 = w.v[BX] * w.v[BX] + w.v[BY] * w.v[BY] + w.v[BZ] * w.v[BZ];
+  const double ptot = w.v[PR] + 0.5 * b2;
+  const double vb = w.v[VX] * w.v[BX] + w.v[VY] * w.v[BY] + w.v[VZ] * w.v[BZ];
+  f[RHO] = u.v[MX + d];
+  for (int j = 0; j < 3; ++j) {
+    f[MX + j] = u.v[MX + j] * vn - w.v[BX + j] * bn;
+    if (j == d) f[MX + j] += ptot;
+  }
+  f[EN] = (u.v[EN] + ptot) * vn - bn * vb;
+  for (int j = 0; j < 3; ++j) f[BX + j] = (j == d) ? 0.0 : vn * w.v[BX + j] - bn * w.v[VX + j];
+  f[PSI] = 0.0;
+}
+
+// Exact solution of the linear (B_n, psi) Riemann problem of the mixed GLM
+// system d_t B_n + d_n psi = 0, d_t psi + c_h^2 d_n B_n = 0 (Dedner 2002).
+void glm_interface(double bnl, double bnr, double psl, double psr, double ch, double* bn,
+                   double* ps) {
+  *bn = 0.5 * (bnl + bnr) - (psr - psl) / (2.0 * ch);
+  *ps = 0.5 * (psl + psr) - 0.5 * ch * (bnr - bnl);
+}
+
+// Interface flux from the reconstructed left/right primitive states: GLM
+// interface values for (B_n, psi), then HLL with Davis speed bounds on the
+// other seven components, built from the states with B_n replaced.
+void face_flux(Cell wl, Cell wr, int d, double ch, double gamma, double F[NV]) {
+  double bn, ps;
+  glm_interface(wl.v[BX + d], wr.v[BX + d], wl.v[PSI], wr.v[PSI], ch, &bn, &ps);
+  wl.v[BX + d] = bn;
+  wr.v[BX + d] = bn;
+  const Cell ul = prim_to_cons(wl, gamma);
+  const Cell ur = prim_to_cons(wr, gamma);
+  double fl[NV], fr[NV];
+  phys_flux(wl, ul, d, fl);
+  phys_flux(wr, ur, d, fr);
+  const double cl = fast_speed(wl, d, gamma);
+  const double cr = fast_speed(wr, d, gamma);
+  const double sl = std::min(wl.v[VX + d] - cl, wr.v[VX + d] - cr);
+  const double sr = std::max(wl.v[VX + d] + cl, wr.v[VX + d] + cr);
+  for (int q = 0; q < NV; ++q) {
+    if (q == BX + d || q == PSI) continue;
+    if (sl >= 0.0) {
+      F[q] = fl[q];
+    } else if (sr <= 0.0) {
+      F[q] = fr[q];
+    } else {
+      F[q] = (sr * fl[q] - sl * fr[q] + sl * sr * (ur.v[q] - ul.v[q])) / (sr - sl);
+    }
+  }
+  F[BX + d] = ps;
+  F[PSI] = ch * ch * bn;
+}
+
+// ---------------------------------------------------------------------------
+// Block hierarchy.
+
+struct Key {
+  int l;
+  long i, j, k;
+  bool operator==(const Key& o) const { return l == o.l && i == o.i && j == o.j && k == o.k; }
+};
+struct KeyHash {
+  size_t operator()(const Key& k) const {
+    uint64_t h = (uint64_t)k.l * 0x9E3779B97F4A7C15ull;
+    h ^= (uint64_t)k.i + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)k.j + 0x8CB92BA72F3D8DD7ull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)k.k + 0x52DCE729DA3ED8FBull + (h << 6) + (h >> 2);
+    return (size_t)h;
+  }
+};
+
+using Idx = std::array<long, 3>;
+using BlockData = std::vector<Cell>;
+
+}  // namespace
+
+extern "C" {
+
+// Parameter record shared with the Python test wrapper (ctypes mirror).
+typedef struct {
+  int ndim;
+  int nx;
+  int ng;
+  int nstages;  // 1 = forward Euler, 2 = SSPRK(2,2), 3 = SSPRK(3,3)
+  int reflux;
+  int fix_small_values;
+  int nthreads;
+  int base_blocks[3];
+  int bc_lo[3];
+  int bc_hi[3];
+  double xmin[3];
+  double xmax[3];
+  double bc_fixed_prim[3][2][NV];
+  double gamma;
+  double cfl;
+  double glm_alpha;
+  double small_density;
+  double small_pressure;
+} oracle_params;
+
+}  // extern "C"
+
+namespace {
+
+struct Sim {
+  oracle_params P;
+  Phys ph;
+  int ndim, nx, ng, pn;
+  long pcells;  // padded cells per block (corners included, unused)
+  long icells;  // interior cells per block
+  int nb;
+  int finest;
+  std::vector<int> lev;
+  std::vector<Idx> pos;
+  std::unordered_map<Key, int, KeyHash> leaf;
+  std::unordered_set<Key, KeyHash> refined;
+  Cell fixedU[3][2];
+  std::vector<BlockData> S0, S1, S2;            // state slots
+  std::vector<std::array<BlockData, 3>> flux;  // face fluxes per block and direction
+  int flags = 0;
+  long nfix = 0;
+  double last_dt = 0, last_ch = 0, last_kappa = 0;
+
+  long ncell(int l, int d) const { return d < ndim ? ((long)P.base_blocks[d] * nx) << (l - 1) : 1; }
+  double dx(int l, int d) const { return (P.xmax[d] - P.xmin[d]) / (double)ncell(l, d); }
+
+  // padded index, i/j/k in [-ng, nx+ng)
+  long pidx(long i, long j, long k) const {
+    const long kk = ndim == 3 ? k + ng : 0;
+    return (kk * pn + (j + ng)) * pn + (i + ng);
+  }
+  long pidx(const Idx& c) const { return pidx(c[0], c[1], c[2]); }
+
+  // Conserved value of the level-l cell with global index g, defined from the
+  // leaf interiors alone: same-level leaf copy, periodic wrap, physical
+  // boundary, restriction of the finer leaves covering it, or prolongation of
+  // the coarser leaf covering it.
+  Cell lookup(const std::vector<BlockData>& S, int l, Idx g, bool allow_prolong) const {
+    for (int d = 0; d < ndim; ++d) {
+      const long n = ncell(l, d);
+      if (g[d] >= 0 && g[d] < n) continue;
+      const int side = g[d] < 0 ? 0 : 1;
+      const int bc = side ? P.bc_hi[d] : P.bc_lo[d];
+      if (bc == BC_PERIODIC) {
+        g[d] = ((g[d] % n) + n) % n;
+        continue;
+      }
+      Idx h = g;
+      if (bc == BC_ZEROGRAD) {
+        h[d] = side ? n - 1 : 0;
+        return lookup(S, l, h, allow_prolong);
+      }
+      if (bc == BC_REFLECT) {
+        h[d] = side ? 2 * n - 1 - g[d] : -1 - g[d];
+        Cell c = lookup(S, l, h, allow_prolong);
+        c.v[MX + d] = -c.v[MX + d];
+        c.v[BX + d] = -c.v[BX + d];
+        return c;
+      }
+      if (bc == BC_FIXED) return fixedU[d][side];
+      throw std::logic_error("unknown boundary kind");
+    }
+    Key key{l, g[0] / nx, ndim > 1 ? g[1] / nx : 0, ndim > 2 ? g[2] / nx : 0};
+    auto it = leaf.find(key);
+    if (it != leaf.end()) {
+      const Idx loc{g[0] - key.i * nx, g[1] - key.j * nx, ndim > 2 ? g[2] - key.k * nx : 0};
+      return S[it->second][pidx(loc)];
+    }
+    if (refined.count(key)) return restrict_cell(S, l, g);
+    if (!allow_prolong) throw std::logic_error("ghost stencil needs a prolongation of a prolongation (hierarchy not 2:1 nested)");
+    return prolong_cell(S, l, g);
+  }
+
+  Cell fine_leaf_cell(const std::vector<BlockData>& S, int l, const Idx& g) const {
+    Key key{l, g[0] / nx, ndim > 1 ? g[1] / nx : 0, ndim > 2 ? g[2] / nx : 0};
+    auto it = leaf.find(key);
+    if (it == leaf.end()) throw std::logic_error("restriction source is not a leaf (hierarchy not 2:1 nested)");
+    const Idx loc{g[0] - key.i * nx, g[1] - key.j * nx, ndim > 2 ? g[2] - key.k * nx : 0};
+    return S[it->second][pidx(loc)];
+  }
+
+  // Volume average of the 2^d children, summed pairwise (x pairs, then y,
+  // then z) and scaled by 2^-d.
+  Cell restrict_cell(const std::vector<BlockData>& S, int l, const Idx& g) const {
+    Cell r;
+    if (ndim == 2) {
+      Cell c[2][2];
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) c[b][a] = fine_leaf_cell(S, l + 1, Idx{2 * g[0] + a, 2 * g[1] + b, 0});
+      for (int q = 0; q < NV; ++q)
+        r.v[q] = ((c[0][0].v[q] + c[0][1].v[q]) + (c[1][0].v[q] + c[1][1].v[q])) * 0.25;
+    } else {
+      Cell c[2][2][2];
+      for (int e = 0; e < 2; ++e)
+        for (int b = 0; b < 2; ++b)
+          for (int a = 0; a < 2; ++a)
+            c[e][b][a] = fine_leaf_cell(S, l + 1, Idx{2 * g[0] + a, 2 * g[1] + b, 2 * g[2] + e});
+      for (int q = 0; q < NV; ++q)
+        r.v[q] = (((c[0][0][0].v[q] + c[0][0][1].v[q]) + (c[0][1][0].v[q] + c[0][1][1].v[q])) +
+                  ((c[1][0][0].v[q] + c[1][0][1].v[q]) + (c[1][1][0].v[q] + c[1][1][1].v[q]))) *
+                 0.125;
+    }
+    return r;
+  }
+
+  // Conservative linear prolongation: parent value plus a quarter of the
+  // minmod-limited parent slope per direction, towards the child's side.
+  Cell prolong_cell(const std::vector<BlockData>& S, int l, const Idx& g) const {
+    if (l <= 1) throw std::logic_error("prolongation requested on the base level");
+    Idx gc{g[0] >> 1, ndim > 1 ? g[1] >> 1 : 0, ndim > 2 ? g[2] >> 1 : 0};
+    Key pk{l - 1, gc[0] / nx, ndim > 1 ? gc[1] / nx : 0, ndim > 2 ? gc[2] / nx : 0};
+    if (!leaf.count(pk)) throw std::logic_error("prolongation parent is not a leaf (hierarchy not 2:1 nested)");
+    const Cell uc = lookup(S, l - 1, gc, false);
+    Cell r = uc;
+    for (int d = 0; d < ndim; ++d) {
+      Idx lo = gc, hi = gc;
+      lo[d] -= 1;
+      hi[d] += 1;
+      const Cell um = lookup(S, l - 1, lo, false);
+      const Cell up = lookup(S, l - 1, hi, false);
+      const double s = (g[d] & 1) ? 0.25 : -0.25;
+      for (int q = 0; q < NV; ++q) r.v[q] = r.v[q] + s * minmod(uc.v[q] - um.v[q], up.v[q] - uc.v[q]);
+    }
+    return r;
+  }
+
+  // Fill the face ghost slabs of every block of slot S (all 2*ndim faces,
+  // ng deep, interior-wide in the other directions).
+  void fill_ghosts(std::vector<BlockData>& S) {
+    const std::vector<BlockData>& cS = S;
+    std::vector<std::vector<std::pair<long, Cell>>> out(nb);
+#pragma omp parallel for schedule(dynamic) num_threads(P.nthreads)
+    for (int b = 0; b < nb; ++b) {
+      const int l = lev[b];
+      for (int d = 0; d < ndim; ++d) {
+        for (int side = 0; side < 2; ++side) {
+          const long a0 = side ? nx : -ng, a1 = side ? nx + ng : 0;
+          const long kmax = ndim == 3 ? nx : 1;
+          for (long k = 0; k < kmax; ++k)
+            for (long j = 0; j < nx; ++j)
+              for (long a = a0; a < a1; ++a) {
+                Idx loc;
+                // loc along d is a; the remaining interior directions are j, k
+                if (d == 0) loc = Idx{a, j, k};
+                else if (d == 1) loc = Idx{j, a, k};
+                else loc = Idx{j, k, a};
+                if (ndim == 2) loc[2] = 0;
+                Idx g{pos[b][0] * nx + loc[0], pos[b][1] * nx + loc[1], ndim == 3 ? pos[b][2] * nx + loc[2] : 0};
+                out[b].emplace_back(pidx(loc), lookup(cS, l, g, true));
+              }
+        }
+      }
+    }
+    for (int b = 0; b < nb; ++b)
+      for (auto& pc : out[b]) S[b][pc.first] = pc.second;
+  }
+
+  // Time step, c_h and kappa from the leaf interior cells of S.
+  void cfl(const std::vector<BlockData>& S, double* dt, double* ch, double* kappa) {
+    double rmax = 0.0;
+    bool nan_seen = false;
+    int f = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int l = lev[b];
+      const long kmax = ndim == 3 ? nx : 1;
+      for (long k = 0; k < kmax; ++k)
+        for (long j = 0; j < nx; ++j)
+          for (long i = 0; i < nx; ++i) {
+            Cell w;
+            f |= cons_to_prim(S[b][pidx(i, j, k)], ph, w);
+            double r = 0.0;
+            for (int d = 0; d < ndim; ++d)
+              r += (std::fabs(w.v[VX + d]) + fast_speed(w, d, ph.gamma)) / dx(l, d);
+            if (std::isnan(r)) nan_seen = true;
+            else if (r > rmax) rmax = r;
+          }
+    }
+    double sum_inv = 0.0, min_dx = 0.0;
+    for (int d = 0; d < ndim; ++d) {
+      sum_inv += 1.0 / dx(finest, d);
+      min_dx = d == 0 ? dx(finest, d) : std::min(min_dx, dx(finest, d));
+    }
+    if (nan_seen || !(rmax > 0.0) || !std::isfinite(rmax)) {
+      f |= FLAG_BAD_DT;
+      *dt = 0.0;
+      *ch = 0.0;
+      *kappa = 0.0;
+    } else {
+      *dt = P.cfl / rmax;
+      *ch = P.cfl / (*dt * sum_inv);
+      *kappa = P.glm_alpha * *ch / min_dx;
+    }
+    flags |= f;
+  }
+
+  // One explicit stage: out = base + w*((in + dt*L(in)) - base), or
+  // out = in + dt*L(in) when w == 1 (the advect1 statement of the IMEX
+  // implementation section with the SSPRK combination folded in).
+  void stage(std::vector<BlockData>& in, const std::vector<BlockData>* base,
+             std::vector<BlockData>& out, double w, double dt, double ch, double kappa) {
+    fill_ghosts(in);
+    const long kmax = ndim == 3 ? nx : 1;
+    int fl = 0;
+    long nf = 0;
+#pragma omp parallel for schedule(dynamic) num_threads(P.nthreads) reduction(| : fl) reduction(+ : nf)
+    for (int b = 0; b < nb; ++b) {
+      // primitives on interior and face ghost cells
+      std::vector<Cell> W(pcells);
+      for (long k = (ndim == 3 ? -ng : 0); k < (ndim == 3 ? nx + ng : 1); ++k)
+        for (long j = -ng; j < nx + ng; ++j)
+          for (long i = -ng; i < nx + ng; ++i) {
+            int out_i = (i < 0 || i >= nx), out_j = (j < 0 || j >= nx),
+                out_k = ndim == 3 && (k < 0 || k >= nx);
+            if (out_i + out_j + out_k > 1) continue;  // edge/corner cells are never read
+            const int bad = cons_to_prim(in[b][pidx(i, j, k)], ph, W[pidx(i, j, k)]);
+            fl |= bad;
+            if (bad && ph.fix) ++nf;
+          }
+      for (int d = 0; d < ndim; ++d) {
+        BlockData& F = flux[b][d];
+        // faces f = 0..nx along d, f between cells f-1 and f
+        for (long t2 = 0; t2 < kmax; ++t2)
+          for (long t1 = 0; t1 < nx; ++t1)
+            for (long f = 0; f <= nx; ++f) {
+              auto at = [&](long a) -> const Cell& {
+                if (d == 0) return W[pidx(a, t1, t2)];
+                if (d == 1) return W[pidx(t1, a, t2)];
+                return W[pidx(t1, t2, a)];
+              };
+              const Cell& wmm = at(f - 2);
+              const Cell& wm = at(f - 1);
+              const Cell& wp = at(f);
+              const Cell& wpp = at(f + 1);
+              Cell wl, wr;
+              for (int q = 0; q < NV; ++q) {
+                const double sm = vanleer(wm.v[q] - wmm.v[q], wp.v[q] - wm.v[q]);
+                const double sp = vanleer(wp.v[q] - wm.v[q], wpp.v[q] - wp.v[q]);
+                wl.v[q] = wm.v[q] + 0.5 * sm;
+                wr.v[q] = wp.v[q] - 0.5 * sp;
+              }
+              if (!(wl.v[RHO] > 0.0) || !(wl.v[PR] > 0.0) || !(wr.v[RHO] > 0.0) || !(wr.v[PR] > 0.0)) {
+                wl = wm;
+                wr = wp;
+              }
+              face_flux(wl, wr, d, ch, ph.gamma, F[(t2 * nx + t1) * (nx + 1) + f].v);
+            }
+      }
+    }
+    flags |= fl;
+    nfix += nf;
+    if (P.reflux) do_reflux();
+#pragma omp parallel for schedule(dynamic) num_threads(P.nthreads)
+    for (int b = 0; b < nb; ++b) {
+      const int l = lev[b];
+      for (long k = 0; k < kmax; ++k)
+        for (long j = 0; j < nx; ++j)
+          for (long i = 0; i < nx; ++i) {
+            const long c = pidx(i, j, k);
+            const Cell& u = in[b][c];
+            double L[NV];
+            for (int q = 0; q < NV; ++q) L[q] = 0.0;
+            for (int d = 0; d < ndim; ++d) {
+              long f, t1, t2;
+              if (d == 0) { f = i; t1 = j; t2 = k; }
+              else if (d == 1) { f = j; t1 = i; t2 = k; }
+              else { f = k; t1 = i; t2 = j; }
+              const Cell& flo = flux[b][d][(t2 * nx + t1) * (nx + 1) + f];
+              const Cell& fhi = flux[b][d][(t2 * nx + t1) * (nx + 1) + f + 1];
+              const double h = dx(l, d);
+              for (int q = 0; q < NV; ++q) L[q] = L[q] + (fhi.v[q] - flo.v[q]) / h;
+            }
+            for (int q = 0; q < NV; ++q) L[q] = -L[q];
+            L[PSI] = L[PSI] - kappa * u.v[PSI];
+            Cell& o = out[b][c];
+            for (int q = 0; q < NV; ++q) {
+              const double t = u.v[q] + dt * L[q];
+              if (w == 1.0) {
+                o.v[q] = t;
+              } else {
+                const double u0 = (*base)[b][c].v[q];
+                o.v[q] = u0 + w * (t - u0);
+              }
+            }
+          }
+    }
+  }
+
+  // Flux correction at coarse/fine faces: the coarse face flux becomes the
+  // pairwise mean of the 2^(d-1) fine face fluxes covering it.
+  void do_reflux() {
+    const long kmax = ndim == 3 ? nx : 1;
+    for (int b = 0; b < nb; ++b) {
+      const int l = lev[b];
+      for (int d = 0; d < ndim; ++d)
+        for (int side = 0; side < 2; ++side) {
+          Idx nbp = pos[b];
+          nbp[d] += side ? 1 : -1;
+          const long nblk = (long)P.base_blocks[d] << (l - 1);
+          if (nbp[d] < 0 || nbp[d] >= nblk) {
+            if ((side ? P.bc_hi[d] : P.bc_lo[d]) != BC_PERIODIC) continue;
+            nbp[d] = (nbp[d] + nblk) % nblk;
+          }
+          if (!refined.count(Key{l, nbp[0], nbp[1], nbp[2]})) continue;
+          // fine face index along d, and fine block position along d
+          const long fine_blk_d = side ? 2 * nbp[d] : 2 * nbp[d] + 1;
+          const long ff = side ? 0 : nx;
+          const long cf = side ? nx : 0;
+          for (long t2 = 0; t2 < kmax; ++t2)
+            for (long t1 = 0; t1 < nx; ++t1) {
+              // global coarse transverse cell indices
+              const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
+              Idx gct{0, 0, 0};
+              gct[ta] = pos[b][ta] * nx + t1;
+              if (ndim == 3) gct[tb] = pos[b][tb] * nx + t2;
+              Cell fv[2][2];
+              for (int e = 0; e < (ndim == 3 ? 2 : 1); ++e)
+                for (int a = 0; a < 2; ++a) {
+                  Idx gf{0, 0, 0};
+                  gf[ta] = 2 * gct[ta] + a;
+                  if (ndim == 3) gf[tb] = 2 * gct[tb] + e;
+                  Idx fb{0, 0, 0};
+                  fb[d] = fine_blk_d;
+                  fb[ta] = gf[ta] / nx;
+                  if (ndim == 3) fb[tb] = gf[tb] / nx;
+                  auto it = leaf.find(Key{l + 1, fb[0], fb[1], fb[2]});
+                  if (it == leaf.end()) throw std::logic_error("reflux partner is not a leaf");
+                  const long ft1 = gf[ta] - fb[ta] * nx;
+                  const long ft2 = ndim == 3 ? gf[tb] - fb[tb] * nx : 0;
+                  fv[e][a] = flux[it->second][d][(ft2 * nx + ft1) * (nx + 1) + ff];
+                }
+              Cell& cflux = flux[b][d][(t2 * nx + t1) * (nx + 1) + cf];
+              for (int q = 0; q < NV; ++q) {
+                if (ndim == 2)
+                  cflux.v[q] = (fv[0][0].v[q] + fv[0][1].v[q]) * 0.5;
+                else
+                  cflux.v[q] = ((fv[0][0].v[q] + fv[0][1].v[q]) + (fv[1][0].v[q] + fv[1][1].v[q])) * 0.25;
+              }
+            }
+        }
+    }
+  }
+
+  // One full step.  dt_cap > 0 clamps dt (c_h and kappa keep the CFL value).
+  void step(double dt_cap = 0.0) {
+    double dt, ch, kappa;
+    cfl(S0, &dt, &ch, &kappa);
+    if (dt_cap > 0.0 && dt > dt_cap) dt = dt_cap;
+    last_dt = dt;
+    last_ch = ch;
+    last_kappa = kappa;
+    if (flags & FLAG_BAD_DT) return;
+    const int s = P.nstages;
+    if (s == 1) {
+      stage(S0, nullptr, S1, 1.0, dt, ch, kappa);
+      std::swap(S0, S1);
+    } else if (s == 2) {
+      stage(S0, nullptr, S1, 1.0, dt, ch, kappa);
+      stage(S1, &S0, S0, 0.5, dt, ch, kappa);
+    } else {
+      stage(S0, nullptr, S1, 1.0, dt, ch, kappa);
+      stage(S1, &S0, S2, 0.25, dt, ch, kappa);
+      stage(S2, &S0, S0, 2.0 / 3.0, dt, ch, kappa);
+    }
+  }
+};
+
+Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int* ijk, const double* prim) {
+  Sim* s = new Sim();
+  s->P = *p;
+  s->ph = Phys{p->gamma, p->small_density, p->small_pressure, p->fix_small_values};
+  s->ndim = p->ndim;
+  s->nx = p->nx;
+  s->ng = p->ng;
+  if (s->ndim != 2 && s->ndim != 3) throw std::invalid_argument("ndim must be 2 or 3");
+  if (s->ng != 2) throw std::invalid_argument("the van Leer stencil needs exactly 2 ghost layers");
+  if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
+  if (p->nstages < 1 || p->nstages > 3) throw std::invalid_argument("nstages must be 1, 2 or 3");
+  if (s->P.nthreads < 1) s->P.nthreads = 1;
+  s->pn = s->nx + 2 * s->ng;
+  s->pcells = (long)s->pn * s->pn * (s->ndim == 3 ? s->pn : 1);
+  s->icells = (long)s->nx * s->nx * (s->ndim == 3 ? s->nx : 1);
+  s->nb = nblocks;
+  s->finest = 1;
+  for (int b = 0; b < nblocks; ++b) {
+    const int l = level[b];
+    if (l < 1) throw std::invalid_argument("levels are 1-based");
+    Idx q{ijk[3 * b], ijk[3 * b + 1], s->ndim == 3 ? ijk[3 * b + 2] : 0};
+    for (int d = 0; d < s->ndim; ++d)
+      if (q[d] < 0 || q[d] >= ((long)p->base_blocks[d] << (l - 1))) throw std::invalid_argument("block outside the domain");
+    s->lev.push_back(l);
+    s->pos.push_back(q);
+    if (!s->leaf.emplace(Key{l, q[0], q[1], q[2]}, b).second) throw std::invalid_argument("duplicate block");
+    s->finest = std::max(s->finest, l);
+    Idx a = q;
+    for (int m = l - 1; m >= 1; --m) {
+      for (int d = 0; d < 3; ++d) a[d] >>= 1;
+      s->refined.insert(Key{m, a[0], a[1], a[2]});
+    }
+  }
+  for (const auto& kv : s->leaf)
+    if (s->refined.count(kv.first)) throw std::invalid_argument("a leaf overlaps a refined block");
+  for (int d = 0; d < 3; ++d)
+    for (int side = 0; side < 2; ++side) {
+      Cell w;
+      for (int q = 0; q < NV; ++q) w.v[q] = p->bc_fixed_prim[d][side][q];
+      s->fixedU[d][side] = prim_to_cons(w, p->gamma);
+    }
+  s->S0.assign(nblocks, BlockData(s->pcells));
+  s->S1.assign(nblocks, BlockData(s->pcells));
+  s->S2.assign(nblocks, BlockData(s->pcells));
+  s->flux.resize(nblocks);
+  const long nfaces = (long)(s->nx + 1) * s->nx * (s->ndim == 3 ? s->nx : 1);
+  for (int b = 0; b < nblocks; ++b)
+    for (int d = 0; d < s->ndim; ++d) s->flux[b][d].assign(nfaces, Cell{});
+  const long ic = s->icells;
+  for (int b = 0; b < nblocks; ++b) {
+    for (long c = 0; c < ic; ++c) {
+      const long i = c % s->nx, j = (c / s->nx) % s->nx, k = s->ndim == 3 ? c / ((long)s->nx * s->nx) : 0;
+      Cell w;
+      for (int q = 0; q < NV; ++q) w.v[q] = prim[((long)b * NV + q) * ic + c];
+      s->S0[b][s->pidx(i, j, k)] = prim_to_cons(w, p->gamma);
+    }
+  }
+  return s;
+}
+
+thread_local std::string g_err;
+
+}  // namespace
+
+extern "C" {
+
+const char* oracle_last_error() { return g_err.c_str(); }
+
+void* oracle_create(const oracle_params* p, int nblocks, const int* level, const int* ijk, const double* prim) {
+  try {
+    return build_sim(p, nblocks, level, ijk, prim);
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return nullptr;
+  }
+}
+
+void oracle_destroy(void* h) { delete static_cast<Sim*>(h); }
+
+// Advance nsteps full SSPRK steps; diag receives (dt, c_h, kappa, flags) per
+// step.  Returns 0, or -1 on an exception (message in oracle_last_error), or
+// -4 if a step met a non-physical state or an invalid dt (the run stops there).
+int oracle_steps(void* h, int nsteps, double* diag) {
+  Sim* s = static_cast<Sim*>(h);
+  try {
+    for (int n = 0; n < nsteps; ++n) {
+      s->step();
+      if (diag) {
+        diag[4 * n + 0] = s->last_dt;
+        diag[4 * n + 1] = s->last_ch;
+        diag[4 * n + 2] = s->last_kappa;
+        diag[4 * n + 3] = (double)s->flags;
+      }
+      if (s->flags & FLAG_BAD_DT) return -4;
+      if ((s->flags & (FLAG_SMALL_RHO | FLAG_SMALL_P)) && !s->P.fix_small_values) return -4;
+    }
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return -1;
+  }
+  return 0;
+}
+
+// Advance until time t_end (the last dt clamped so the run ends on it),
+// at most max_steps steps.  Returns the number of steps taken, or a negative
+// status as oracle_steps.
+int oracle_steps_to_time(void* h, double t_end, int max_steps) {
+  Sim* s = static_cast<Sim*>(h);
+  double t = 0.0;
+  int n = 0;
+  try {
+    while (t < t_end && n < max_steps) {
+      s->step(t_end - t);
+      if (s->flags & FLAG_BAD_DT) return -4;
+      if ((s->flags & (FLAG_SMALL_RHO | FLAG_SMALL_P)) && !s->P.fix_small_values) return -4;
+      t += s->last_dt;
+      ++n;
+    }
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return -1;
+  }
+  return n;
+}
+
+// One stage with caller-given dt, c_h, kappa, from slot 0 into slot 0
+// (forward Euler, w = 1).
+int oracle_euler_stage(void* h, double dt, double ch, double kappa) {
+  Sim* s = static_cast<Sim*>(h);
+  try {
+    s->stage(s->S0, nullptr, s->S1, 1.0, dt, ch, kappa);
+    std::swap(s->S0, s->S1);
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return -1;
+  }
+  return 0;
+}
+
+int oracle_cfl(void* h, double* dt, double* ch, double* kappa) {
+  Sim* s = static_cast<Sim*>(h);
+  s->cfl(s->S0, dt, ch, kappa);
+  return s->flags;
+}
+
+int oracle_flags(void* h) { return static_cast<Sim*>(h)->flags; }
+long oracle_fix_count(void* h) { return static_cast<Sim*>(h)->nfix; }
+
+// Interior conserved state of slot 0, [block][var][k][j][i].
+void oracle_get_cons(void* h, double* out) {
+  Sim* s = static_cast<Sim*>(h);
+  const long ic = s->icells;
+  for (int b = 0; b < s->nb; ++b)
+    for (long c = 0; c < ic; ++c) {
+      const long i = c % s->nx, j = (c / s->nx) % s->nx, k = s->ndim == 3 ? c / ((long)s->nx * s->nx) : 0;
+      const Cell& u = s->S0[b][s->pidx(i, j, k)];
+      for (int q = 0; q < NV; ++q) out[((long)b * NV + q) * ic + c] = u.v[q];
+    }
+}
+
+// Replace the interior conserved state of slot 0.
+void oracle_set_cons(void* h, const double* in) {
+  Sim* s = static_cast<Sim*>(h);
+  const long ic = s->icells;
+  for (int b = 0; b < s->nb; ++b)
+    for (long c = 0; c < ic; ++c) {
+      const long i = c % s->nx, j = (c / s->nx) % s->nx, k = s->ndim == 3 ? c / ((long)s->nx * s->nx) : 0;
+      Cell& u = s->S0[b][s->pidx(i, j, k)];
+      for (int q = 0; q < NV; ++q) u.v[q] = in[((long)b * NV + q) * ic + c];
+    }
+}
+
+// Fill the face ghosts of slot 0 and return the padded state,
+// [block][var][pk][pj][pi] with (nx+2ng)^ndim cells; edge and corner cells
+// are returned as NaN.
+int oracle_fill_padded(void* h, double* out) {
+  Sim* s = static_cast<Sim*>(h);
+  try {
+    s->fill_ghosts(s->S0);
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return -1;
+  }
+  const int ng = s->ng, nx = s->nx, pn = s->pn;
+  for (int b = 0; b < s->nb; ++b)
+    for (long c = 0; c < s->pcells; ++c) {
+      const long i = c % pn - ng, j = (c / pn) % pn - ng, k = s->ndim == 3 ? c / ((long)pn * pn) - ng : 0;
+      const int o = (i < 0 || i >= nx) + (j < 0 || j >= nx) + (s->ndim == 3 && (k < 0 || k >= nx));
+      for (int q = 0; q < NV; ++q)
+        out[((long)b * NV + q) * s->pcells + c] = o > 1 ? NAN : s->S0[b][c].v[q];
+    }
+  return 0;
+}
+
+// Point functions, exposed for the unit pins.
+void oracle_prim_to_cons(const double* w, double gamma, double* u) {
+  Cell c;
+  std::memcpy(c.v, w, sizeof(c.v));
+  Cell r = prim_to_cons(c, gamma);
+  std::memcpy(u, r.v, sizeof(r.v));
+}
+int oracle_cons_to_prim(const double* u, double gamma, double small_rho, double small_p, int fix, double* w) {
+  Cell c, r;
+  std::memcpy(c.v, u, sizeof(c.v));
+  const int bad = cons_to_prim(c, Phys{gamma, small_rho, small_p, fix}, r);
+  std::memcpy(w, r.v, sizeof(r.v));
+  return bad;
+}
+double oracle_fast_speed(const double* w, int d, double gamma) {
+  Cell c;
+  std::memcpy(c.v, w, sizeof(c.v));
+  return fast_speed(c, d, gamma);
+}
+double oracle_vanleer(double dm, double dp) { return vanleer(dm, dp); }
+double oracle_minmod(double a, double b) { return minmod(a, b); }
+void oracle_glm_interface(double bnl, double bnr, double psl, double psr, double ch, double* out) {
+  glm_interface(bnl, bnr, psl, psr, ch, &out[0], &out[1]);
+}
+void oracle_face_flux(const double* wl, const double* wr, int d, double ch, double gamma, double* F) {
+  Cell a, b;
+  std::memcpy(a.v, wl, sizeof(a.v));
+  std::memcpy(b.v, wr, sizeof(b.v));
+  face_flux(a, b, d, ch, gamma, F);
+}
+void oracle_phys_flux(const double* w, int d, double gamma, double* F) {
+  Cell c;
+  std::memcpy(c.v, w, sizeof(c.v));
+  const Cell u = prim_to_cons(c, gamma);
+  phys_flux(c, u, d, F);
+}
+
+}  // extern "C"

@@ -1,0 +1,246 @@
+"""ctypes wrapper of the FP64 CPU oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: used by the tests, the package smoke check and the
+benchmark's cpu_baseline leg, never by the product path.  It imports nothing
+from the HIP package; callers hand it a workload description (any object with
+the attributes of ``Workload``) and numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+NV = 9
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int), ("nx", ctypes.c_int), ("ng", ctypes.c_int),
+        ("nstages", ctypes.c_int), ("reflux", ctypes.c_int),
+        ("fix_small_values", ctypes.c_int), ("nthreads", ctypes.c_int),
+        ("base_blocks", ctypes.c_int * 3), ("bc_lo", ctypes.c_int * 3),
+        ("bc_hi", ctypes.c_int * 3), ("xmin", ctypes.c_double * 3),
+        ("xmax", ctypes.c_double * 3), ("bc_fixed_prim", ctypes.c_double * (3 * 2 * NV)),
+        ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("glm_alpha", ctypes.c_double),
+        ("small_density", ctypes.c_double), ("small_pressure", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build
+            _build.build()
+        _lib = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        _lib.oracle_create.restype = ctypes.c_void_p
+        _lib.oracle_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ip, ip, dp]
+        _lib.oracle_destroy.argtypes = [ctypes.c_void_p]
+        _lib.oracle_steps.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+        _lib.oracle_steps_to_time.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
+        _lib.oracle_euler_stage.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        _lib.oracle_cfl.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        _lib.oracle_flags.argtypes = [ctypes.c_void_p]
+        _lib.oracle_fix_count.restype = ctypes.c_long
+        _lib.oracle_fix_count.argtypes = [ctypes.c_void_p]
+        _lib.oracle_get_cons.argtypes = [ctypes.c_void_p, dp]
+        _lib.oracle_set_cons.argtypes = [ctypes.c_void_p, dp]
+        _lib.oracle_fill_padded.argtypes = [ctypes.c_void_p, dp]
+        _lib.oracle_last_error.restype = ctypes.c_char_p
+        _lib.oracle_prim_to_cons.argtypes = [dp, ctypes.c_double, dp]
+        _lib.oracle_cons_to_prim.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+        _lib.oracle_fast_speed.restype = ctypes.c_double
+        _lib.oracle_fast_speed.argtypes = [dp, ctypes.c_int, ctypes.c_double]
+        _lib.oracle_vanleer.restype = ctypes.c_double
+        _lib.oracle_vanleer.argtypes = [ctypes.c_double, ctypes.c_double]
+        _lib.oracle_minmod.restype = ctypes.c_double
+        _lib.oracle_minmod.argtypes = [ctypes.c_double, ctypes.c_double]
+        _lib.oracle_glm_interface.argtypes = [ctypes.c_double] * 5 + [dp]
+        _lib.oracle_face_flux.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        _lib.oracle_phys_flux.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp]
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def make_params(w, nthreads: Optional[int] = None, nstages: Optional[int] = None) -> Params:
+    p = Params()
+    p.ndim = w.ndim
+    p.nx = w.nx
+    p.ng = w.ng
+    p.nstages = w.nstages if nstages is None else nstages
+    p.reflux = w.reflux
+    p.fix_small_values = w.fix_small_values
+    p.nthreads = default_threads() if nthreads is None else nthreads
+    for d in range(3):
+        p.base_blocks[d] = int(w.base_blocks[d]) if d < w.ndim else 1
+        p.bc_lo[d] = int(w.bc_lo[d])
+        p.bc_hi[d] = int(w.bc_hi[d])
+        p.xmin[d] = float(w.xmin[d])
+        p.xmax[d] = float(w.xmax[d])
+    fixed = np.ascontiguousarray(np.asarray(w.bc_fixed_prim, dtype=np.float64).reshape(-1))
+    for i in range(3 * 2 * NV):
+        p.bc_fixed_prim[i] = fixed[i]
+    p.gamma = w.gamma
+    p.cfl = w.cfl
+    p.glm_alpha = w.glm_alpha
+    p.small_density = w.small_density
+    p.small_pressure = w.small_pressure
+    return p
+
+
+class OracleSim:
+    """One oracle simulation; state lives in the C++ library."""
+
+    def __init__(self, w, nthreads: Optional[int] = None, nstages: Optional[int] = None):
+        self.w = w
+        self.params = make_params(w, nthreads, nstages)
+        self.level = np.ascontiguousarray(w.level, dtype=np.int32)
+        self.ijk = np.ascontiguousarray(w.ijk, dtype=np.int32)
+        prim = np.ascontiguousarray(w.prim, dtype=np.float64)
+        self.h = lib().oracle_create(ctypes.byref(self.params), len(self.level), _ip(self.level),
+                                     _ip(self.ijk), _dp(prim))
+        if not self.h:
+            raise ValueError("oracle_create: " + lib().oracle_last_error().decode())
+        self.shape = (len(self.level), NV) + (w.nx,) * w.ndim
+
+    def close(self):
+        if self.h:
+            lib().oracle_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def steps(self, n: int, check: bool = True) -> np.ndarray:
+        """Advance n SSPRK steps; returns [n, 4] (dt, c_h, kappa, flags)."""
+        diag = np.zeros((max(n, 1), 4))
+        rc = lib().oracle_steps(self.h, n, _dp(diag))
+        if rc == -1:
+            raise RuntimeError("oracle: " + lib().oracle_last_error().decode())
+        if rc != 0 and check:
+            raise FloatingPointError("oracle: non-physical state or invalid dt (flags=%d)" % self.flags())
+        return diag[:n]
+
+    def steps_to_time(self, t_end: float, max_steps: int = 1000000) -> int:
+        n = lib().oracle_steps_to_time(self.h, t_end, max_steps)
+        if n == -1:
+            raise RuntimeError("oracle: " + lib().oracle_last_error().decode())
+        if n < 0:
+            raise FloatingPointError("oracle: non-physical state or invalid dt (flags=%d)" % self.flags())
+        return n
+
+    def euler_stage(self, dt: float, ch: float, kappa: float):
+        if lib().oracle_euler_stage(self.h, dt, ch, kappa) != 0:
+            raise RuntimeError("oracle: " + lib().oracle_last_error().decode())
+
+    def cfl(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        fl = lib().oracle_cfl(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return a.value, b.value, c.value, fl
+
+    def flags(self) -> int:
+        return lib().oracle_flags(self.h)
+
+    def fix_count(self) -> int:
+        return lib().oracle_fix_count(self.h)
+
+    def cons(self) -> np.ndarray:
+        out = np.empty(self.shape)
+        lib().oracle_get_cons(self.h, _dp(out))
+        return out
+
+    def set_cons(self, u: np.ndarray):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert u.shape == self.shape
+        lib().oracle_set_cons(self.h, _dp(u))
+
+    def padded(self) -> np.ndarray:
+        pn = self.w.nx + 2 * self.w.ng
+        out = np.empty((len(self.level), NV) + (pn,) * self.w.ndim)
+        if lib().oracle_fill_padded(self.h, _dp(out)) != 0:
+            raise RuntimeError("oracle: " + lib().oracle_last_error().decode())
+        return out
+
+
+def run(w, nsteps: Optional[int] = None, nthreads: Optional[int] = None, check: bool = True):
+    """Run a workload for nsteps (default w.nsteps); returns (cons, diag)."""
+    sim = OracleSim(w, nthreads)
+    try:
+        diag = sim.steps(w.nsteps if nsteps is None else nsteps, check=check)
+        return sim.cons(), diag
+    finally:
+        sim.close()
+
+
+# --- point functions -------------------------------------------------------
+
+def prim_to_cons(w, gamma: float) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    u = np.empty(NV)
+    lib().oracle_prim_to_cons(_dp(w), gamma, _dp(u))
+    return u
+
+
+def cons_to_prim(u, gamma: float, small_rho: float = 0.0, small_p: float = 0.0, fix: int = 0):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    w = np.empty(NV)
+    bad = lib().oracle_cons_to_prim(_dp(u), gamma, small_rho, small_p, fix, _dp(w))
+    return w, bad
+
+
+def fast_speed(w, d: int, gamma: float) -> float:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    return lib().oracle_fast_speed(_dp(w), d, gamma)
+
+
+def vanleer(dm: float, dp: float) -> float:
+    return lib().oracle_vanleer(dm, dp)
+
+
+def minmod(a: float, b: float) -> float:
+    return lib().oracle_minmod(a, b)
+
+
+def glm_interface(bnl, bnr, psl, psr, ch):
+    out = np.empty(2)
+    lib().oracle_glm_interface(bnl, bnr, psl, psr, ch, _dp(out))
+    return out[0], out[1]
+
+
+def face_flux(wl, wr, d: int, ch: float, gamma: float) -> np.ndarray:
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    F = np.empty(NV)
+    lib().oracle_face_flux(_dp(wl), _dp(wr), d, ch, gamma, _dp(F))
+    return F
+
+
+def phys_flux(w, d: int, gamma: float) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    F = np.empty(NV)
+    lib().oracle_phys_flux(_dp(w), d, gamma, _dp(F))
+    return F

@@ -1,0 +1,537 @@
+"""Seeded synthetic inputs: block hierarchies and primitive initial states.
+
+This module is shared by the HIP path and the CPU oracle and therefore holds
+none of the scheme's arithmetic: it only lays out leaf blocks and samples
+primitive variables (rho, v_x, v_y, v_z, p, B_x, B_y, B_z, psi) at cell
+centres.  Each side converts primitives to conserved variables itself.
+
+Workloads are shaped like the paper's MHD tests (Orszag-Tang type 2D vortex,
+random-mode turbulence, a shock hitting a dense cloud on a static AMR
+hierarchy as in the "Shock-cloud in MHD" section, and a thin low-beta current
+sheet as in "Divergence control in MHD"); the paper's own data files are not
+used, every field is drawn from numpy's PCG64 with a fixed draw order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+NV = 9
+RHO, VX, VY, VZ, PR, BX, BY, BZ, PSI = range(NV)
+BC_PERIODIC, BC_ZEROGRAD, BC_REFLECT, BC_FIXED = 0, 1, 2, 3
+
+
+@dataclasses.dataclass
+class Workload:
+    """A leaf-block hierarchy plus its primitive initial state.
+
+    ``prim`` has shape (nblocks, 9, nx, nx) in 2D ([block][var][j][i]) or
+    (nblocks, 9, nx, nx, nx) in 3D ([block][var][k][j][i]); ``level`` is
+    1-based and ``ijk`` holds each block's integer position on its level.
+    """
+
+    name: str
+    ndim: int
+    nx: int
+    base_blocks: Tuple[int, int, int]
+    xmin: Tuple[float, float, float]
+    xmax: Tuple[float, float, float]
+    bc_lo: Tuple[int, int, int]
+    bc_hi: Tuple[int, int, int]
+    level: np.ndarray
+    ijk: np.ndarray
+    prim: np.ndarray
+    gamma: float = 5.0 / 3.0
+    cfl: float = 0.8
+    glm_alpha: float = 0.5
+    nstages: int = 3
+    nsteps: int = 1
+    small_density: float = 0.0
+    small_pressure: float = 0.0
+    fix_small_values: int = 0
+    reflux: int = 1
+    ng: int = 2
+    bc_fixed_prim: np.ndarray = dataclasses.field(
+        default_factory=lambda: np.zeros((3, 2, NV)))
+
+    @property
+    def nblocks(self) -> int:
+        return int(self.level.shape[0])
+
+    @property
+    def interior_cells(self) -> int:
+        return self.nblocks * self.nx ** self.ndim
+
+    @property
+    def max_level(self) -> int:
+        return int(self.level.max())
+
+    def with_prim(self, prim: np.ndarray, **kw) -> "Workload":
+        return dataclasses.replace(self, prim=prim, **kw)
+
+
+# ---------------------------------------------------------------------------
+# geometry helpers
+
+
+def uniform_blocks(ndim: int, base: Sequence[int]) -> Tuple[np.ndarray, np.ndarray]:
+    """All level-1 blocks, lexicographic with the x position fastest."""
+    nbz = base[2] if ndim == 3 else 1
+    ijk = np.array([(i, j, k) for k in range(nbz) for j in range(base[1]) for i in range(base[0])],
+                   dtype=np.int32)
+    return np.ones(len(ijk), dtype=np.int32), ijk
+
+
+def cell_centres(ndim: int, nx: int, base: Sequence[int], xmin, xmax,
+                 level: np.ndarray, ijk: np.ndarray):
+    """Cell-centre coordinates of every interior cell, shaped like one
+    variable of ``prim`` (x, y, z arrays)."""
+    nb = len(level)
+    shape = (nb,) + (nx,) * ndim
+    out = []
+    for d in range(3):
+        if d >= ndim:
+            out.append(np.zeros(shape))
+            continue
+        ncell = (base[d] * nx) * (2.0 ** (level - 1))            # per block
+        h = (xmax[d] - xmin[d]) / ncell                          # [nb]
+        loc = np.arange(nx) + 0.5
+        g = ijk[:, d][:, None] * nx + loc[None, :]               # [nb, nx]
+        c = xmin[d] + g * h[:, None]
+        # broadcast along the right axis: axis order is [.., k, j, i]
+        ax = ndim - d          # position in shape counting from block axis
+        view = [nb] + [1] * ndim
+        view[ax] = nx
+        out.append(np.broadcast_to(c.reshape(view), shape).copy())
+    return out
+
+
+def global_to_blocks(arr: np.ndarray, ndim: int, nx: int) -> np.ndarray:
+    """[..., z, y, x] global array on a uniform level-1 grid -> [..., block, k, j, i]
+    with lexicographic block order."""
+    lead = arr.shape[:-ndim]
+    if ndim == 2:
+        ny, nxx = arr.shape[-2:]
+        a = arr.reshape(lead + (ny // nx, nx, nxx // nx, nx))
+        n = len(lead)
+        a = a.transpose(tuple(range(n)) + (n, n + 2, n + 1, n + 3))
+        return a.reshape(lead + ((ny // nx) * (nxx // nx), nx, nx))
+    nz, ny, nxx = arr.shape[-3:]
+    a = arr.reshape(lead + (nz // nx, nx, ny // nx, nx, nxx // nx, nx))
+    n = len(lead)
+    a = a.transpose(tuple(range(n)) + (n, n + 2, n + 4, n + 1, n + 3, n + 5))
+    return a.reshape(lead + ((nz // nx) * (ny // nx) * (nxx // nx), nx, nx, nx))
+
+
+def blocks_to_global(arr: np.ndarray, ndim: int, nx: int, base: Sequence[int]) -> np.ndarray:
+    """Inverse of :func:`global_to_blocks` for a uniform level-1 grid."""
+    lead = arr.shape[:-(ndim + 1)]
+    n = len(lead)
+    if ndim == 2:
+        a = arr.reshape(lead + (base[1], base[0], nx, nx))
+        a = a.transpose(tuple(range(n)) + (n, n + 2, n + 1, n + 3))
+        return a.reshape(lead + (base[1] * nx, base[0] * nx))
+    a = arr.reshape(lead + (base[2], base[1], base[0], nx, nx, nx))
+    a = a.transpose(tuple(range(n)) + (n, n + 3, n + 1, n + 4, n + 2, n + 5))
+    return a.reshape(lead + (base[2] * nx, base[1] * nx, base[0] * nx))
+
+
+# ---------------------------------------------------------------------------
+# random divergence-free Fourier mode sums
+
+
+def _wavevectors(ndim: int, kmax: int) -> np.ndarray:
+    r = range(-kmax, kmax + 1)
+    out = []
+    for kx in r:
+        for ky in r:
+            for kz in (r if ndim == 3 else [0]):
+                k = (kx, ky, kz)
+                n2 = kx * kx + ky * ky + kz * kz
+                if n2 < 1 or n2 > kmax * kmax:
+                    continue
+                # half space: first non-zero component positive
+                first = next(c for c in k if c != 0)
+                if first > 0:
+                    out.append(k)
+    return np.array(out, dtype=np.int64)
+
+
+def _mode_draw(rng: np.random.Generator, ndim: int, nmodes: int, kmax: int, vector: bool):
+    cand = _wavevectors(ndim, kmax)
+    nmodes = min(nmodes, len(cand))   # 2D has only 24 half-plane vectors with |k| <= 4
+    ks = cand[rng.choice(len(cand), size=nmodes, replace=False)]
+    phases = rng.uniform(0.0, 2.0 * math.pi, size=nmodes)
+    dirs = None
+    if vector:
+        dirs = np.empty((nmodes, 3))
+        for m in range(nmodes):
+            k = ks[m].astype(np.float64)
+            while True:
+                a = rng.normal(size=3)
+                a -= (a @ k) / (k @ k) * k
+                nrm = np.linalg.norm(a)
+                if nrm > 1e-3:
+                    break
+            dirs[m] = a / nrm
+    return ks, phases, dirs
+
+
+def _mode_sum(n: int, ndim: int, ks: np.ndarray, coef: np.ndarray) -> np.ndarray:
+    """Re sum_m coef_m exp(2 pi i k_m . x) at the cell centres of an n^ndim
+    periodic unit grid, as a [z][y][x] array (complex matrix product)."""
+    x = (np.arange(n) + 0.5) / n
+    ax = np.exp(2j * math.pi * np.outer(x, ks[:, 0]))                   # [x, m]
+    if ndim == 2:
+        by = coef[None, :] * np.exp(2j * math.pi * np.outer(x, ks[:, 1]))  # [y, m]
+        return (by @ ax.T).real                                          # [y, x]
+    ey = np.exp(2j * math.pi * np.outer(x, ks[:, 1]))                   # [y, m]
+    ez = np.exp(2j * math.pi * np.outer(x, ks[:, 2]))                   # [z, m]
+    byz = (ez[:, None, :] * ey[None, :, :]).reshape(n * n, -1) * coef[None, :]
+    return (byz @ ax.T).real.reshape(n, n, n)
+
+
+def random_mode_fields(n: int, ndim: int, seed: int, nmodes: int = 32, kmax: int = 4,
+                       rho_amp: float = 0.1, v_amp: float = 0.1, b_amp: float = 1.0,
+                       b0=(1.0, 0.0, 0.0)) -> np.ndarray:
+    """Global [var][z][y][x] primitive arrays of the random-mode state:
+    rho = 1 + rho_amp*S, p = 1, divergence-free v and B mode sums with RMS
+    v_amp and b_amp, plus a uniform B0; psi = 0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (n,) * ndim
+    out = np.zeros((NV,) + shape)
+    ks, ph, _ = _mode_draw(rng, ndim, nmodes, kmax, vector=False)
+    norm = math.sqrt(2.0 / len(ks))
+    out[RHO] = 1.0 + rho_amp * _mode_sum(n, ndim, ks, norm * np.exp(1j * ph))
+    out[PR] = 1.0
+    ks, ph, dv = _mode_draw(rng, ndim, nmodes, kmax, vector=True)
+    for c in range(3):
+        out[VX + c] = v_amp * _mode_sum(n, ndim, ks, norm * dv[:, c] * np.exp(1j * ph))
+    ks, ph, db = _mode_draw(rng, ndim, nmodes, kmax, vector=True)
+    for c in range(3):
+        out[BX + c] = b0[c] + b_amp * _mode_sum(n, ndim, ks, norm * db[:, c] * np.exp(1j * ph))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+
+
+def orszag_tang_2d(seed: int = 0, n: int = 64, nx: int = 16, nsteps: int = 100) -> Workload:
+    """2D Orszag-Tang type vortex on periodic [0, 2pi]^2 with seeded density
+    noise of amplitude 1e-3; SSPRK(2,2), CFL 0.8."""
+    gamma = 5.0 / 3.0
+    base = (n // nx, n // nx, 1)
+    level, ijk = uniform_blocks(2, base)
+    L = 2.0 * math.pi
+    x, y, _ = cell_centres(2, nx, base, (0, 0, 0), (L, L, 1), level, ijk)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = global_to_blocks(rng.uniform(0.0, 1.0, size=(n, n)), 2, nx)
+    prim = np.zeros((len(level), NV, nx, nx))
+    prim[:, RHO] = gamma * gamma + 1e-3 * (2.0 * u - 1.0)
+    prim[:, VX] = -np.sin(y)
+    prim[:, VY] = np.sin(x)
+    prim[:, PR] = gamma
+    prim[:, BX] = -np.sin(y)
+    prim[:, BY] = np.sin(2.0 * x)
+    return Workload("orszag_tang_2d_%d" % n, 2, nx, base, (0.0, 0.0, 0.0), (L, L, 1.0),
+                    (0, 0, 0), (0, 0, 0), level, ijk, prim, gamma=gamma, nstages=2,
+                    nsteps=nsteps)
+
+
+def random_modes(n: int = 256, ndim: int = 3, seed: int = 1, nx: int = 16, nsteps: int = 50,
+                 nstages: int = 3) -> Workload:
+    """Periodic unit box with the random-mode state of :func:`random_mode_fields`."""
+    base = (n // nx, n // nx, n // nx if ndim == 3 else 1)
+    level, ijk = uniform_blocks(ndim, base)
+    g = random_mode_fields(n, ndim, seed)
+    prim = np.ascontiguousarray(global_to_blocks(g, ndim, nx).swapaxes(0, 1))
+    return Workload("random_modes_%dd_%d" % (ndim, n), ndim, nx, base, (0.0, 0.0, 0.0),
+                    (1.0, 1.0, 1.0), (0, 0, 0), (0, 0, 0), level, ijk, prim,
+                    nstages=nstages, nsteps=nsteps)
+
+
+def _box_dist(lo, hi, c):
+    """min and max distance from point c to the axis-aligned box [lo, hi]."""
+    dmin = np.sqrt(sum(np.maximum(0.0, np.maximum(lo[d] - c[d], c[d] - hi[d])) ** 2 for d in range(3)))
+    dmax = np.sqrt(sum(np.maximum(np.abs(lo[d] - c[d]), np.abs(hi[d] - c[d])) ** 2 for d in range(3)))
+    return dmin, dmax
+
+
+def nest_2to1(ndim: int, base: Sequence[int], leaves: dict, periodic=(False, False, False)) -> dict:
+    """Refine coarse leaves until every leaf's face/edge/corner neighbours are
+    at most one level coarser.  ``leaves`` maps (level, i, j, k) -> True."""
+    def nblk(l, d):
+        return base[d] << (l - 1) if d < ndim else 1
+
+    def covering_leaf(l, p):
+        # leaf covering slot p on level l, at level <= l
+        q = list(p)
+        for m in range(l, 0, -1):
+            if (m, q[0], q[1], q[2]) in leaves:
+                return (m, q[0], q[1], q[2])
+            q = [c >> 1 for c in q]
+        return None
+
+    changed = True
+    while changed:
+        changed = False
+        for key in sorted(leaves.keys(), key=lambda t: -t[0]):
+            if key not in leaves:
+                continue
+            l, i, j, k = key
+            if l <= 2:
+                continue
+            offs = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1)
+                    for c in ((-1, 0, 1) if ndim == 3 else (0,)) if (a, b, c) != (0, 0, 0)]
+            for o in offs:
+                p = [i + o[0], j + o[1], k + o[2]]
+                ok = True
+                for d in range(ndim):
+                    n = nblk(l, d)
+                    if p[d] < 0 or p[d] >= n:
+                        if periodic[d]:
+                            p[d] %= n
+                        else:
+                            ok = False
+                if not ok:
+                    continue
+                cov = covering_leaf(l, p)
+                if cov is not None and cov[0] < l - 1:
+                    # refine the too-coarse leaf into its 2^d children
+                    del leaves[cov]
+                    cl, ci, cj, ck = cov
+                    for a in (0, 1):
+                        for b in (0, 1):
+                            for c in ((0, 1) if ndim == 3 else (0,)):
+                                leaves[(cl + 1, 2 * ci + a, 2 * cj + b, 2 * ck + c if ndim == 3 else 0)] = True
+                    changed = True
+    return leaves
+
+
+def shock_cloud_amr(seed: int = 2, nsteps: int = 100, nx: int = 16, base_n: int = 128,
+                    r_cloud: float = 0.25, r_shell: float = 0.2) -> Workload:
+    """3-level static AMR (ratio 2) on a base_n^3 unit cube: level 2 covers a
+    seeded sphere of radius r_cloud, level 3 its shell r_shell..r_cloud, with
+    2:1 nesting enforced.  A dense cloud (rho = 10) sits in rho = 1, p = 1,
+    B = (1, 0, 0); a v_x = 2 inflow enters through the x-min face, the other
+    faces are zero-gradient."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = rng.uniform(0.3, 0.7, size=3)
+    nb1 = base_n // nx
+    base = (nb1, nb1, nb1)
+    leaves = {}
+    for k in range(nb1):
+        for j in range(nb1):
+            for i in range(nb1):
+                lo = np.array([i, j, k]) / nb1
+                hi = lo + 1.0 / nb1
+                dmin, _ = _box_dist(lo, hi, c)
+                if dmin <= r_cloud:
+                    for a in (0, 1):
+                        for b in (0, 1):
+                            for e in (0, 1):
+                                p2 = (2 * i + a, 2 * j + b, 2 * k + e)
+                                lo2 = np.array(p2) / (2 * nb1)
+                                hi2 = lo2 + 0.5 / nb1
+                                dmin2, dmax2 = _box_dist(lo2, hi2, c)
+                                if dmin2 <= r_cloud and dmax2 >= r_shell:
+                                    for a3 in (0, 1):
+                                        for b3 in (0, 1):
+                                            for e3 in (0, 1):
+                                                leaves[(3, 2 * p2[0] + a3, 2 * p2[1] + b3, 2 * p2[2] + e3)] = True
+                                else:
+                                    leaves[(2,) + p2] = True
+                else:
+                    leaves[(1, i, j, k)] = True
+    leaves = nest_2to1(3, base, leaves)
+    keys = sorted(leaves.keys())
+    level = np.array([t[0] for t in keys], dtype=np.int32)
+    ijk = np.array([t[1:] for t in keys], dtype=np.int32)
+    x, y, z = cell_centres(3, nx, base, (0, 0, 0), (1, 1, 1), level, ijk)
+    r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+    prim = np.zeros((len(level), NV, nx, nx, nx))
+    prim[:, RHO] = np.where(r <= r_cloud, 10.0, 1.0)
+    prim[:, PR] = 1.0
+    prim[:, BX] = 1.0
+    fixed = np.zeros((3, 2, NV))
+    fixed[0, 0, RHO] = 1.0
+    fixed[0, 0, VX] = 2.0
+    fixed[0, 0, PR] = 1.0
+    fixed[0, 0, BX] = 1.0
+    return Workload("shock_cloud_amr3", 3, nx, base, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0),
+                    (BC_FIXED, BC_ZEROGRAD, BC_ZEROGRAD), (BC_ZEROGRAD,) * 3, level, ijk, prim,
+                    nstages=3, nsteps=nsteps, bc_fixed_prim=fixed)
+
+
+def current_sheet(n: int = 192, seed: int = 3, nx: int = 16, nsteps: int = 200,
+                  width: float = 0.05) -> Workload:
+    """Low-beta (beta = 0.01) Harris-like sheet on [-0.5, 0.5]^3:
+    B = (tanh(y/w), 0, sech(y/w)) so |B| = 1 and p + |B|^2/2 is uniform,
+    rho = 1, p = 0.005, seeded 1e-2 random velocity per cell and component;
+    periodic in x and z, reflective in y."""
+    base = (n // nx,) * 3
+    level, ijk = uniform_blocks(3, base)
+    x, y, z = cell_centres(3, nx, base, (-0.5,) * 3, (0.5,) * 3, level, ijk)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = global_to_blocks(rng.uniform(0.0, 1.0, size=(3, n, n, n)), 3, nx)
+    prim = np.zeros((len(level), NV, nx, nx, nx))
+    prim[:, RHO] = 1.0
+    prim[:, PR] = 0.005
+    for c in range(3):
+        prim[:, VX + c] = 1e-2 * (2.0 * u[c] - 1.0)
+    prim[:, BX] = np.tanh(y / width)
+    prim[:, BZ] = 1.0 / np.cosh(y / width)
+    return Workload("current_sheet_%d" % n, 3, nx, base, (-0.5,) * 3, (0.5,) * 3,
+                    (BC_PERIODIC, BC_REFLECT, BC_PERIODIC), (BC_PERIODIC, BC_REFLECT, BC_PERIODIC),
+                    level, ijk, prim, nstages=3, nsteps=nsteps)
+
+
+# ---------------------------------------------------------------------------
+# test problems
+
+
+def sod(n: int, ndim: int = 2, nx: int = 16, axis: int = 0) -> Workload:
+    """Sod shock tube along ``axis`` on [0, 1]: (rho, v, p) = (1, 0, 1) left of
+    x = 0.5 and (0.125, 0, 0.1) right, gamma = 1.4, B = 0, zero-gradient ends,
+    one block thick and periodic in the other directions."""
+    base = [1, 1, 1]
+    base[axis] = n // nx
+    base = tuple(base)
+    level, ijk = uniform_blocks(ndim, base)
+    xmax = [1.0, 1.0, 1.0]
+    xmax[axis] = 1.0
+    xmin = (0.0, 0.0, 0.0)
+    cs = cell_centres(ndim, nx, base, xmin, xmax, level, ijk)
+    s = cs[axis]
+    prim = np.zeros((len(level), NV) + (nx,) * ndim)
+    left = s < 0.5
+    prim[:, RHO] = np.where(left, 1.0, 0.125)
+    prim[:, PR] = np.where(left, 1.0, 0.1)
+    lo = [BC_PERIODIC] * 3
+    hi = [BC_PERIODIC] * 3
+    lo[axis] = BC_ZEROGRAD
+    hi[axis] = BC_ZEROGRAD
+    return Workload("sod_%d" % n, ndim, nx, base, xmin, tuple(xmax), tuple(lo), tuple(hi),
+                    level, ijk, prim, gamma=1.4, nstages=3)
+
+
+def alfven_wave(n: int, ndim: int = 2, nx: int = 16, amp: float = 1e-6) -> Workload:
+    """Small-amplitude linear Alfven wave on the periodic unit box with
+    k = 2 pi (1, 1[, 1]), rho = 1, p = 1, B0 = unit vector along k, and a
+    transverse perturbation dB = amp*sin(k.x) e_perp, dv = -dB (propagating
+    along +k at the Alfven speed 1).  e_perp = z in 2D, (1, -1, 0)/sqrt 2 in 3D."""
+    base = (n // nx, n // nx, n // nx if ndim == 3 else 1)
+    level, ijk = uniform_blocks(ndim, base)
+    x, y, z = cell_centres(ndim, nx, base, (0, 0, 0), (1, 1, 1), level, ijk)
+    if ndim == 2:
+        kvec = np.array([1.0, 1.0, 0.0])
+        eperp = np.array([0.0, 0.0, 1.0])
+        phase = 2.0 * math.pi * (x + y)
+    else:
+        kvec = np.array([1.0, 1.0, 1.0])
+        eperp = np.array([1.0, -1.0, 0.0]) / math.sqrt(2.0)
+        phase = 2.0 * math.pi * (x + y + z)
+    khat = kvec / np.linalg.norm(kvec)
+    prim = np.zeros((len(level), NV) + (nx,) * ndim)
+    prim[:, RHO] = 1.0
+    prim[:, PR] = 1.0
+    db = amp * np.sin(phase)
+    for c in range(3):
+        prim[:, BX + c] = khat[c] + db * eperp[c]
+        prim[:, VX + c] = -db * eperp[c]
+    return Workload("alfven_%dd_%d" % (ndim, n), ndim, nx, base, (0.0,) * 3, (1.0,) * 3,
+                    (0, 0, 0), (0, 0, 0), level, ijk, prim, nstages=3)
+
+
+def uniform_state(ndim: int, base: Sequence[int], w: Sequence[float], nx: int = 16,
+                  bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), level=None, ijk=None) -> Workload:
+    """A constant primitive state ``w`` (9 values) on the given blocks."""
+    if level is None:
+        level, ijk = uniform_blocks(ndim, base)
+    prim = np.empty((len(level), NV) + (nx,) * ndim)
+    for q in range(NV):
+        prim[:, q] = w[q]
+    return Workload("uniform", ndim, nx, tuple(base), (0.0,) * 3, (1.0,) * 3, tuple(bc_lo),
+                    tuple(bc_hi), level, ijk, prim)
+
+
+def amr_test_hierarchy(ndim: int = 2, nb1: int = 4, seed: int = 5, nx: int = 16,
+                       periodic: bool = True):
+    """Small 3-level hierarchy for tests: refine a seeded subset of base blocks,
+    refine a seeded subset of their children, then enforce 2:1 nesting."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = (nb1, nb1, nb1 if ndim == 3 else 1)
+    leaves = {}
+    coords = [(i, j, k) for k in range(base[2]) for j in range(nb1) for i in range(nb1)]
+    ref1 = set(tuple(c) for c in np.array(coords)[rng.random(len(coords)) < 0.35].tolist())
+    for c in coords:
+        if c in ref1:
+            kids = [(2 * c[0] + a, 2 * c[1] + b, 2 * c[2] + e) for e in ((0, 1) if ndim == 3 else (0,))
+                    for b in (0, 1) for a in (0, 1)]
+            for kd in kids:
+                if rng.random() < 0.3:
+                    for e in ((0, 1) if ndim == 3 else (0,)):
+                        for b in (0, 1):
+                            for a in (0, 1):
+                                leaves[(3, 2 * kd[0] + a, 2 * kd[1] + b, 2 * kd[2] + e if ndim == 3 else 0)] = True
+                else:
+                    leaves[(2,) + kd] = True
+        else:
+            leaves[(1,) + c] = True
+    leaves = nest_2to1(ndim, base, leaves, periodic=(periodic,) * 3)
+    keys = sorted(leaves.keys())
+    level = np.array([t[0] for t in keys], dtype=np.int32)
+    ijk = np.array([t[1:] for t in keys], dtype=np.int32)
+    return base, level, ijk
+
+
+def smooth_amr_state(ndim: int = 2, nb1: int = 4, seed: int = 5, nx: int = 16) -> Workload:
+    """A smooth periodic MHD state on :func:`amr_test_hierarchy` (used for AMR
+    conservation and parity tests)."""
+    base, level, ijk = amr_test_hierarchy(ndim, nb1, seed, nx)
+    x, y, z = cell_centres(ndim, nx, base, (0, 0, 0), (1, 1, 1), level, ijk)
+    tp = 2.0 * math.pi
+    prim = np.zeros((len(level), NV) + (nx,) * ndim)
+    prim[:, RHO] = 1.0 + 0.3 * np.sin(tp * x) * np.cos(tp * y) + (0.1 * np.sin(tp * z) if ndim == 3 else 0.0)
+    prim[:, VX] = 0.5 * np.sin(tp * y)
+    prim[:, VY] = -0.4 * np.sin(tp * x)
+    prim[:, VZ] = 0.2 * np.cos(tp * (x + y))
+    prim[:, PR] = 1.0 + 0.2 * np.cos(tp * x)
+    prim[:, BX] = 0.8 - 0.3 * np.sin(tp * y)
+    prim[:, BY] = 0.4 * np.sin(tp * x)
+    prim[:, BZ] = 0.3 * np.cos(tp * x) + (0.2 * np.sin(tp * y) if ndim == 3 else 0.0)
+    prim[:, PSI] = 0.01 * np.sin(tp * (x - y))
+    return Workload("smooth_amr_%dd" % ndim, ndim, nx, base, (0.0,) * 3, (1.0,) * 3,
+                    (0, 0, 0), (0, 0, 0), level, ijk, prim, nstages=3)
+
+
+def serving_jobs(njobs: int = 2000, seed: int = 4, rate: float = 1.0) -> list:
+    """Job descriptors of the serving stream: Poisson arrival times (mean gap
+    1/rate), 2D/3D with equal odds, log-uniform linear size rounded to 16
+    (2D 32..256, 3D 32..128), steps uniform in 20..500, FP32-mixed or FP64
+    with equal odds, and a per-job field seed.  Fields are built on demand
+    with :func:`serving_job_workload`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    jobs = []
+    for jid in range(njobs):
+        t += rng.exponential(1.0 / rate)
+        ndim = 2 if rng.random() < 0.5 else 3
+        lo, hi = (32, 256) if ndim == 2 else (32, 128)
+        n = int(16 * round(math.exp(rng.uniform(math.log(lo), math.log(hi))) / 16.0))
+        n = max(lo, min(hi, n))
+        steps = int(rng.integers(20, 501))
+        mixed = bool(rng.random() < 0.5)
+        jobs.append(dict(id=jid, arrival=t, ndim=ndim, n=n, steps=steps, mixed=mixed,
+                         seed=int(rng.integers(0, 2 ** 31 - 1))))
+    return jobs
+
+
+def serving_job_workload(job: dict) -> Workload:
+    w = random_modes(job["n"], job["ndim"], seed=job["seed"], nsteps=job["steps"])
+    w.name = "job%d" % job["id"]
+    return w
