@@ -1,0 +1,167 @@
+/*
+ * amrvac.h - C ABI of the MI355X (gfx950) explicit GLM-MHD block-AMR hot path.
+ *
+ * The library advances the ideal MHD equations with GLM divergence cleaning
+ * on a static block-based quadtree/octree hierarchy (refinement ratio 2,
+ * leaf blocks of block_nx^ndim cells with nghost ghost layers), as described
+ * in MPI-AMRVAC 3.0 (arXiv 2303.03026): conservative finite volumes inside
+ * SSP Runge-Kutta steps ("Schemes and limiters for HD and MHD", Table
+ * tab:schemes_time), van Leer limited reconstruction of primitive variables
+ * with 2 ghost cells (Table t:limiters), HLL fluxes (Table tab:schemes_space)
+ * and the 'glm' monopole control (Table t:divb).
+ *
+ * Conventions used by every call
+ *   - Variables, in this order: rho, m_x, m_y, m_z, e, B_x, B_y, B_z, psi
+ *     (conserved) and rho, v_x, v_y, v_z, p, B_x, B_y, B_z, psi (primitive);
+ *     magnetic pressure |B|^2/2.  2D runs keep all three vector components.
+ *   - State slots are device buffers OWNED BY THE CALLER (e.g. torch tensors),
+ *     registered once in amrvac_init_blocks, never freed by the library.
+ *     Layout is block-major: slot = [block][var][cell] with padded blocks of
+ *     pn^ndim cells, pn = block_nx + 2*nghost, cell index
+ *     ((k+ng)*pn + (j+ng))*pn + (i+ng) (3D; 2D drops k), i fastest.
+ *       AMRVAC_FP64:       9 arrays of double per block (72 B per cell).
+ *       AMRVAC_FP32_MIXED: 8 float arrays (rho, m_x, m_y, m_z, B_x, B_y, B_z,
+ *                          psi) followed by one double array (e) per block
+ *                          (40 B per cell).
+ *     amrvac_slot_bytes gives the size.  Only face ghost slabs are used;
+ *     edge and corner cells of the padded block are never read or written.
+ *   - Every call enqueues work on the stream given at init (a hipStream_t,
+ *     caller-owned) and returns without synchronising, except
+ *     amrvac_sync_flags and amrvac_destroy.
+ *   - Every call returns AMRVAC_OK (0) or a negative status; the context keeps
+ *     a message (amrvac_last_error).  HIP errors keep their hipError_t text.
+ *   - Calls on one context are not thread-safe.
+ */
+#ifndef AMRVAC_H
+#define AMRVAC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amrvac_ctx amrvac_ctx;
+
+enum amrvac_status {
+  AMRVAC_OK = 0,
+  AMRVAC_E_ARG = -1,          /* invalid argument or block table            */
+  AMRVAC_E_HIP = -2,          /* a HIP runtime call failed                  */
+  AMRVAC_E_NOMEM = -3,        /* library-owned device memory unavailable    */
+  AMRVAC_E_NONPHYSICAL = -4,  /* small density/pressure or invalid dt seen  */
+  AMRVAC_E_STATE = -5         /* call not valid in the context's state      */
+};
+
+enum { AMRVAC_FP64 = 0, AMRVAC_FP32_MIXED = 1 };
+enum { AMRVAC_BC_PERIODIC = 0, AMRVAC_BC_ZEROGRAD = 1, AMRVAC_BC_REFLECT = 2, AMRVAC_BC_FIXED = 3 };
+enum { AMRVAC_FLAG_SMALL_RHO = 1, AMRVAC_FLAG_SMALL_P = 2, AMRVAC_FLAG_BAD_DT = 4 };
+enum { AMRVAC_PATH_PLAIN = 0, AMRVAC_PATH_FUSED = 1 };
+
+/* Grid and scheme description.  Physical boundary kinds per face follow the
+ * paper's examples: periodic, zero-gradient ("continuous"), reflective
+ * ((a)symmetric: normal momentum and normal field change sign) and a fixed
+ * inflow state given in primitive variables. */
+typedef struct {
+  int ndim;               /* 2 or 3                                            */
+  int block_nx;           /* interior cells per direction per block (even,     */
+                          /* 4..16; the fused path needs 16)                   */
+  int nghost;             /* ghost layers; must be 2 (van Leer stencil)        */
+  int precision;          /* AMRVAC_FP64 or AMRVAC_FP32_MIXED                  */
+  int base_blocks[3];     /* blocks per direction on level 1 (z ignored in 2D) */
+  int bc_lo[3];           /* AMRVAC_BC_* at the minimum face of each direction */
+  int bc_hi[3];           /* ... and at the maximum face (periodic must match) */
+  int fix_small_values;   /* 0: flag small values only; 1: also replace them   */
+  int reflux;             /* 1: coarse face flux := mean of fine face fluxes   */
+  double xmin[3];         /* domain corner                                     */
+  double xmax[3];
+  double gamma;           /* adiabatic index                                   */
+  double cfl;             /* Courant number C                                  */
+  double glm_alpha;       /* psi damping: kappa = glm_alpha * c_h / min dx     */
+  double small_density;   /* thresholds of the small-value check               */
+  double small_pressure;
+  double bc_fixed_prim[3][2][9]; /* primitive state of AMRVAC_BC_FIXED faces   */
+} amrvac_grid_desc;
+
+/* Device bytes of one state slot for nblocks blocks of this description.
+ * Returns AMRVAC_E_ARG for an invalid description. */
+int amrvac_slot_bytes(const amrvac_grid_desc* g, int nblocks, size_t* bytes);
+
+/* Create a context.  level[nb] (1-based) and ijk[nb][3] (block position on
+ * its level, z ignored in 2D) are HOST arrays describing the leaf blocks;
+ * they must tile the domain without overlap and be 2:1 nested across faces,
+ * edges and corners, else AMRVAC_E_ARG.  slots[nslots] are device pointers
+ * of amrvac_slot_bytes each (nslots >= 3 for SSPRK(3,3) stepping); stream is
+ * a hipStream_t (NULL = the null stream).  The library builds its neighbour
+ * and ghost task tables on the host, uploads them and allocates its own
+ * scratch (primitive and face-flux buffers, reduction scalars). */
+int amrvac_init_blocks(amrvac_ctx** out, const amrvac_grid_desc* g, int nblocks,
+                       const int* level, const int* ijk, void* const* slots, int nslots,
+                       void* stream);
+
+/* Convert a DEVICE array of primitive variables, [block][var][interior cell]
+ * FP64 (block_nx^ndim cells per block, i fastest), to conserved variables in
+ * the interior of slot.  Ghost cells are left untouched. */
+int amrvac_set_primitive(amrvac_ctx* c, int slot, const double* prim_dev);
+
+/* Copy the interior conserved state of slot into a DEVICE FP64 array
+ * [block][var][interior cell]. */
+int amrvac_get_conserved(amrvac_ctx* c, int slot, double* cons_dev);
+
+/* Fill the face ghost slabs of every block of slot: same-level copies with
+ * periodic wrap, restriction (pairwise-summed volume average) of finer
+ * neighbours and physical boundaries, then limited linear prolongation of
+ * coarser neighbours (the paper's internal boundary exchange of the
+ * "Future directions" section, done on the device). */
+int amrvac_fill_ghosts(amrvac_ctx* c, int slot);
+
+/* Time step from the interior of slot: dt = C / max_cells sum_d
+ * (|v_d| + c_fast,d)/dx_d, then c_h = C / (dt * sum_d 1/dx_d) and kappa =
+ * glm_alpha * c_h / min_d dx_d on the finest leaf level (CFL coupling of
+ * the "Schemes and limiters" section).  Results go to DEVICE doubles; a
+ * small value or an invalid dt sets the context's device flag word (read it
+ * with amrvac_sync_flags).  No host synchronisation. */
+int amrvac_cfl_dt(amrvac_ctx* c, int slot, double* dt_dev, double* ch_dev, double* kappa_dev);
+
+/* One explicit stage (the advect1 statement of the IMEX implementation
+ * section, with the SSPRK combination folded in):
+ *   out = in + dt*L(in)                     if w == 1 (base not read),
+ *   out = base + w*((in + dt*L(in)) - base) otherwise,
+ * L = flux divergence of the van Leer + GLM + HLL interface fluxes plus the
+ * psi damping source -kappa*psi.  dt, c_h, kappa are read from DEVICE
+ * pointers (as written by amrvac_cfl_dt).  in must have had its ghosts
+ * filled; in != out; out may equal base. */
+int amrvac_stage(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double w,
+                 const double* dt_dev, const double* ch_dev, const double* kappa_dev);
+
+/* Advance nsteps full SSPRK steps of slot 0 (nstages 1, 2 or 3), using
+ * slots 1 and 2 as stage storage and library-owned dt/c_h/kappa; each step
+ * is cfl -> [fill -> stage] x nstages.  use_graph = 1 captures one step in
+ * a HIP graph on first use and replays it.  No host synchronisation. */
+int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph);
+
+/* Select the stage implementation: AMRVAC_PATH_PLAIN (separate primitive,
+ * per-direction flux, reflux and update kernels) or AMRVAC_PATH_FUSED (one
+ * kernel per stage reading ghosts from the slot and writing the update). */
+int amrvac_set_path(amrvac_ctx* c, int path);
+
+/* Synchronise the stream and read the device flag word (AMRVAC_FLAG_* bits
+ * accumulated since the last reset), the number of cells fixed by the
+ * small-value fix, and the last dt written by amrvac_advance.  Returns
+ * AMRVAC_E_NONPHYSICAL if a flag is set and fixes are off, else AMRVAC_OK.
+ * Any pointer may be NULL. */
+int amrvac_sync_flags(amrvac_ctx* c, int* flags_host, long long* nfix_host, double* dt_host);
+
+/* Clear the device flag word and fix counter (enqueued on the stream). */
+int amrvac_reset_flags(amrvac_ctx* c);
+
+/* Message of the last failed call on this context (never NULL). */
+const char* amrvac_last_error(const amrvac_ctx* c);
+
+/* Synchronise, free library-owned memory and graphs.  Slots stay. */
+int amrvac_destroy(amrvac_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMRVAC_H */

@@ -637,6 +637,9 @@ Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int*
   if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
   if (p->nstages < 1 || p->nstages > 3) throw std::invalid_argument("nstages must be 1, 2 or 3");
   if (s->P.nthreads < 1) s->P.nthreads = 1;
+  for (int d = 0; d < s->ndim; ++d)
+    if ((p->bc_lo[d] == BC_PERIODIC) != (p->bc_hi[d] == BC_PERIODIC))
+      throw std::invalid_argument("periodic boundaries must be periodic on both sides");
   s->pn = s->nx + 2 * s->ng;
   s->pcells = (long)s->pn * s->pn * (s->ndim == 3 ? s->pn : 1);
   s->icells = (long)s->nx * s->nx * (s->ndim == 3 ? s->nx : 1);

@@ -1,0 +1,251 @@
+"""Python binding of the HIP library ``libamrvac.so`` (C ABI in include/amrvac.h).
+
+Argument marshalling only: torch provides device memory and the stream, every
+step of the scheme runs in the library's kernels.  There is no fallback: if
+the library is missing or no HIP device is present, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamrvac.so")
+NV = 9
+
+FP64, FP32_MIXED = 0, 1
+PATH_PLAIN, PATH_FUSED = 0, 1
+FLAG_SMALL_RHO, FLAG_SMALL_P, FLAG_BAD_DT = 1, 2, 4
+E_OK, E_ARG, E_HIP, E_NOMEM, E_NONPHYSICAL, E_STATE = 0, -1, -2, -3, -4, -5
+
+# every entry point declared in include/amrvac.h
+ABI_SYMBOLS = ("amrvac_slot_bytes", "amrvac_init_blocks", "amrvac_set_primitive", "amrvac_get_conserved",
+               "amrvac_fill_ghosts", "amrvac_cfl_dt", "amrvac_stage", "amrvac_advance", "amrvac_set_path",
+               "amrvac_sync_flags", "amrvac_reset_flags", "amrvac_last_error", "amrvac_destroy")
+
+
+class AmrvacError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("amrvac status %d: %s" % (code, msg))
+        self.code = code
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int), ("block_nx", ctypes.c_int), ("nghost", ctypes.c_int),
+        ("precision", ctypes.c_int), ("base_blocks", ctypes.c_int * 3), ("bc_lo", ctypes.c_int * 3),
+        ("bc_hi", ctypes.c_int * 3), ("fix_small_values", ctypes.c_int), ("reflux", ctypes.c_int),
+        ("xmin", ctypes.c_double * 3), ("xmax", ctypes.c_double * 3), ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double), ("glm_alpha", ctypes.c_double), ("small_density", ctypes.c_double),
+        ("small_pressure", ctypes.c_double), ("bc_fixed_prim", ctypes.c_double * (3 * 2 * NV)),
+    ]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libamrvac.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libamrvac.so is not built (run __graft_entry__.build() or "
+                          "python paper_2303_03026_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    lib.amrvac_slot_bytes.argtypes = [ctypes.POINTER(GridDesc), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    lib.amrvac_init_blocks.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(GridDesc), ctypes.c_int, ip, ip,
+                                       ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.amrvac_set_primitive.argtypes = [vp, ctypes.c_int, vp]
+    lib.amrvac_get_conserved.argtypes = [vp, ctypes.c_int, vp]
+    lib.amrvac_fill_ghosts.argtypes = [vp, ctypes.c_int]
+    lib.amrvac_cfl_dt.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.amrvac_stage.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+    lib.amrvac_advance.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.amrvac_set_path.argtypes = [vp, ctypes.c_int]
+    lib.amrvac_sync_flags.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong), dp]
+    lib.amrvac_reset_flags.argtypes = [vp]
+    lib.amrvac_last_error.argtypes = [vp]
+    lib.amrvac_last_error.restype = ctypes.c_char_p
+    lib.amrvac_destroy.argtypes = [vp]
+    _lib = lib
+    return lib
+
+
+def make_desc(w, precision: int = FP64) -> GridDesc:
+    """Grid description of a workload (see paper_2303_03026_amd.inputs.Workload)."""
+    g = GridDesc()
+    g.ndim, g.block_nx, g.nghost, g.precision = w.ndim, w.nx, w.ng, precision
+    for d in range(3):
+        g.base_blocks[d] = int(w.base_blocks[d]) if d < w.ndim else 1
+        g.bc_lo[d] = int(w.bc_lo[d])
+        g.bc_hi[d] = int(w.bc_hi[d])
+        g.xmin[d] = float(w.xmin[d])
+        g.xmax[d] = float(w.xmax[d])
+    g.fix_small_values, g.reflux = int(w.fix_small_values), int(w.reflux)
+    g.gamma, g.cfl, g.glm_alpha = w.gamma, w.cfl, w.glm_alpha
+    g.small_density, g.small_pressure = w.small_density, w.small_pressure
+    fixed = np.ascontiguousarray(np.asarray(w.bc_fixed_prim, dtype=np.float64).reshape(-1))
+    for i in range(3 * 2 * NV):
+        g.bc_fixed_prim[i] = fixed[i]
+    return g
+
+
+class Simulation:
+    """One block hierarchy resident on the device, driven through the C ABI.
+
+    Slots are torch uint8 tensors on ``device``; all work goes to one torch
+    stream (default priority) that is handed to the library.
+    """
+
+    def __init__(self, w, nslots: int = 3, precision: int = FP64, path: int = PATH_PLAIN,
+                 device: str = "cuda", stream=None, set_initial: bool = True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the MI355X path has no CPU fallback")
+        self.torch = torch
+        self.lib = load_library()
+        self.w = w
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.desc = make_desc(w, precision)
+        self.nb = int(w.level.shape[0])
+        size = ctypes.c_size_t()
+        self._check(self.lib.amrvac_slot_bytes(ctypes.byref(self.desc), self.nb, ctypes.byref(size)), None)
+        self.slot_bytes = size.value
+        with torch.cuda.stream(self.stream):
+            self.slots = [torch.empty(self.slot_bytes, dtype=torch.uint8, device=self.device)
+                          for _ in range(nslots)]
+            self.scal = torch.zeros(4, dtype=torch.float64, device=self.device)
+        self.level = np.ascontiguousarray(w.level, dtype=np.int32)
+        self.ijk = np.ascontiguousarray(w.ijk, dtype=np.int32)
+        ptrs = (ctypes.c_void_p * nslots)(*[s.data_ptr() for s in self.slots])
+        ctx = ctypes.c_void_p()
+        torch.cuda.synchronize(self.device)
+        rc = self.lib.amrvac_init_blocks(
+            ctypes.byref(ctx), ctypes.byref(self.desc), self.nb,
+            self.level.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            self.ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ptrs, nslots,
+            ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise AmrvacError(rc, self.lib.amrvac_last_error(None).decode())
+        self.ctx = ctx
+        if path != PATH_PLAIN:
+            self.set_path(path)
+        if set_initial:
+            self.set_primitive(w.prim)
+
+    # -- plumbing -------------------------------------------------------------
+    def _check(self, rc: int, ctx) -> int:
+        if rc != 0:
+            msg = self.lib.amrvac_last_error(ctx).decode() if ctx is not None else "invalid argument"
+            raise AmrvacError(rc, msg)
+        return rc
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.amrvac_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dt_ptr(self):
+        return ctypes.c_void_p(self.scal.data_ptr())
+
+    @property
+    def ch_ptr(self):
+        return ctypes.c_void_p(self.scal.data_ptr() + 8)
+
+    @property
+    def kappa_ptr(self):
+        return ctypes.c_void_p(self.scal.data_ptr() + 16)
+
+    # -- ABI calls ------------------------------------------------------------
+    def set_primitive(self, prim: np.ndarray, slot: int = 0):
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            t = torch.from_numpy(np.ascontiguousarray(prim, dtype=np.float64)).to(self.device, non_blocking=False)
+            self._check(self.lib.amrvac_set_primitive(self.ctx, slot, ctypes.c_void_p(t.data_ptr())), self.ctx)
+            self.stream.synchronize()
+
+    def cons(self, slot: int = 0) -> np.ndarray:
+        torch = self.torch
+        shape = (self.nb, NV) + (self.w.nx,) * self.w.ndim
+        with torch.cuda.stream(self.stream):
+            t = torch.empty(shape, dtype=torch.float64, device=self.device)
+            self._check(self.lib.amrvac_get_conserved(self.ctx, slot, ctypes.c_void_p(t.data_ptr())), self.ctx)
+            out = t.cpu().numpy()
+        self.stream.synchronize()
+        return out
+
+    def padded(self, slot: int = 0) -> np.ndarray:
+        """Raw FP64 slot contents, [block][var][padded cells] (test helper)."""
+        pn = self.w.nx + 2 * self.w.ng
+        self.stream.synchronize()
+        a = self.slots[slot].view(self.torch.float64).cpu().numpy()
+        return a.reshape((self.nb, NV) + (pn,) * self.w.ndim)
+
+    def fill(self, slot: int):
+        self._check(self.lib.amrvac_fill_ghosts(self.ctx, slot), self.ctx)
+
+    def cfl(self, slot: int = 0):
+        self._check(self.lib.amrvac_cfl_dt(self.ctx, slot, self.dt_ptr, self.ch_ptr, self.kappa_ptr), self.ctx)
+
+    def scalars(self):
+        self.stream.synchronize()
+        return tuple(self.scal[:3].cpu().tolist())
+
+    def set_scalars(self, dt: float, ch: float, kappa: float):
+        with self.torch.cuda.stream(self.stream):
+            self.scal[:3] = self.torch.tensor([dt, ch, kappa], dtype=self.torch.float64)
+        self.stream.synchronize()
+
+    def stage(self, in_slot: int, base_slot: int, out_slot: int, weight: float):
+        self._check(self.lib.amrvac_stage(self.ctx, in_slot, base_slot, out_slot, weight, self.dt_ptr,
+                                          self.ch_ptr, self.kappa_ptr), self.ctx)
+
+    def euler_stage(self, in_slot: int = 0, out_slot: int = 1):
+        self.fill(in_slot)
+        self.stage(in_slot, in_slot, out_slot, 1.0)
+
+    def advance(self, nsteps: int, nstages: Optional[int] = None, graph: bool = False):
+        ns = self.w.nstages if nstages is None else nstages
+        self._check(self.lib.amrvac_advance(self.ctx, nsteps, ns, 1 if graph else 0), self.ctx)
+
+    def set_path(self, path: int):
+        self._check(self.lib.amrvac_set_path(self.ctx, path), self.ctx)
+
+    def sync_flags(self, raise_on_error: bool = True):
+        fl = ctypes.c_int()
+        nfix = ctypes.c_longlong()
+        dt = ctypes.c_double()
+        rc = self.lib.amrvac_sync_flags(self.ctx, ctypes.byref(fl), ctypes.byref(nfix), ctypes.byref(dt))
+        if rc != 0 and raise_on_error:
+            raise AmrvacError(rc, self.lib.amrvac_last_error(self.ctx).decode())
+        return fl.value, nfix.value, dt.value, rc
+
+    def reset_flags(self):
+        self._check(self.lib.amrvac_reset_flags(self.ctx), self.ctx)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+def run(w, nsteps: Optional[int] = None, graph: bool = False, path: int = PATH_PLAIN) -> np.ndarray:
+    """Advance a workload on the device and return the interior conserved state."""
+    sim = Simulation(w, path=path)
+    try:
+        sim.advance(w.nsteps if nsteps is None else nsteps, graph=graph)
+        sim.sync_flags()
+        return sim.cons()
+    finally:
+        sim.close()

@@ -1,0 +1,523 @@
+// Plain (one kernel per phase) FP64 path: ghost filling, conserved ->
+// primitive, per-direction reconstruction + GLM + HLL face fluxes, coarse/fine
+// flux correction, flux-difference update with the SSPRK combination, and the
+// CFL reduction.
+//
+// Storage: block-major slots [block][var][padded cell], padded index
+// ((k+ng)*pn + (j+ng))*pn + (i+ng) (2D drops k).  Face fluxes per direction
+// are [block][var][face cell] with the face coordinate along the direction
+// (extent nx+1) and x the fastest index:
+//   x faces: (k*nx + j)*(nx+1) + f,  y faces: (k*(nx+1) + f)*nx + i,
+//   z faces: (f*nx + j)*nx + i.
+#include "kernels.h"
+
+namespace amrvac {
+
+namespace {
+
+__device__ __forceinline__ long pidx(const GridConst& G, int i, int j, int k) {
+  const int kk = G.ndim == 3 ? k + G.ng : 0;
+  return ((long)kk * G.pn + (j + G.ng)) * G.pn + (i + G.ng);
+}
+
+// ---------------------------------------------------------------------------
+// ghost filling: one workgroup per (block, face) task
+
+__global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __restrict__ tasks,
+                                                   const int* __restrict__ link, const int* __restrict__ pos,
+                                                   double* __restrict__ slot, PhysConst P, FixedBC fixed) {
+  const int task = blockIdx.x;
+  const int b = tasks[2 * task];
+  const int face = tasks[2 * task + 1];
+  const int d = face >> 1, side = face & 1;
+  const int* L = link + ((long)b * 6 + face) * LINK_INTS;
+  const int kind = L[0];
+  const int nx = G.nx, ng = G.ng;
+  const int nt2 = G.ndim == 3 ? nx : 1;
+  const int ncell = ng * nx * nt2;
+  const int ta = d == 0 ? 1 : 0;  // first transverse axis
+  const int tb = d == 2 ? 1 : 2;  // second transverse axis (z in 2D: unused)
+  double* dst = slot + (long)b * NV * G.pcells;
+
+  for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
+    int a, t1, t2;
+    if (d == 0) {
+      a = t % ng;
+      t1 = (t / ng) % nx;
+      t2 = t / (ng * nx);
+    } else {
+      t1 = t % nx;
+      a = (t / nx) % ng;
+      t2 = t / (nx * ng);
+    }
+    const int gd = side ? nx + a : a - ng;  // ghost coordinate along d
+    int c[3] = {0, 0, 0};
+    c[d] = gd;
+    c[ta] = t1;
+    if (G.ndim == 3) c[tb] = t2;
+    const long di = pidx(G, c[0], c[1], c[2]);
+
+    if (kind == LINK_SAME) {
+      const double* src = slot + (long)L[1] * NV * G.pcells;
+      int s[3] = {c[0], c[1], c[2]};
+      s[d] = side ? gd - nx : gd + nx;
+      const long si = pidx(G, s[0], s[1], s[2]);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) dst[q * G.pcells + di] = src[q * G.pcells + si];
+    } else if (kind == LINK_FINE) {
+      // restriction: fine cells under this coarse ghost cell, all in one
+      // fine leaf (chosen by the transverse half)
+      int fc[3] = {0, 0, 0};
+      fc[d] = side ? 2 * gd - 2 * nx : 2 * gd + nx;
+      const int oa = (2 * c[ta]) >= nx ? 1 : 0;
+      fc[ta] = 2 * c[ta] - oa * nx;
+      int ob = 0;
+      if (G.ndim == 3) {
+        ob = (2 * c[tb]) >= nx ? 1 : 0;
+        fc[tb] = 2 * c[tb] - ob * nx;
+      }
+      const double* src = slot + (long)L[1 + ob * 2 + oa] * NV * G.pcells;
+      if (G.ndim == 2) {
+        const long i00 = pidx(G, fc[0], fc[1], 0), i10 = pidx(G, fc[0] + 1, fc[1], 0);
+        const long i01 = pidx(G, fc[0], fc[1] + 1, 0), i11 = pidx(G, fc[0] + 1, fc[1] + 1, 0);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const double* s = src + q * G.pcells;
+          dst[q * G.pcells + di] = ((s[i00] + s[i10]) + (s[i01] + s[i11])) * 0.25;
+        }
+      } else {
+        long ix[2][2][2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa) ix[e][bb][aa] = pidx(G, fc[0] + aa, fc[1] + bb, fc[2] + e);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const double* s = src + q * G.pcells;
+          dst[q * G.pcells + di] = (((s[ix[0][0][0]] + s[ix[0][0][1]]) + (s[ix[0][1][0]] + s[ix[0][1][1]])) +
+                                    ((s[ix[1][0][0]] + s[ix[1][0][1]]) + (s[ix[1][1][0]] + s[ix[1][1][1]]))) *
+                                   0.125;
+        }
+      }
+    } else if (kind == LINK_PHYS) {
+      const int bc = L[1];
+      if (bc == 3) {  // fixed inflow state
+        double w[NV], u[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) w[q] = fixed.prim[d][side][q];
+        prim_to_cons(w, u, P);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) dst[q * G.pcells + di] = u[q];
+      } else {
+        int s[3] = {c[0], c[1], c[2]};
+        if (bc == 1)
+          s[d] = side ? nx - 1 : 0;
+        else
+          s[d] = side ? 2 * nx - 1 - gd : -1 - gd;
+        const long si = pidx(G, s[0], s[1], s[2]);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          double v = dst[q * G.pcells + si];
+          if (bc == 2 && (q == I_MX + d || q == I_BX + d)) v = -v;
+          dst[q * G.pcells + di] = v;
+        }
+      }
+    } else {  // LINK_COARSE: conservative minmod-limited linear prolongation
+      const int cb = L[1];
+      const int lev = L[2];
+      const double* src = slot + (long)cb * NV * G.pcells;
+      int lc[3] = {0, 0, 0};
+      int odd[3] = {0, 0, 0};
+      for (int ax = 0; ax < G.ndim; ++ax) {
+        const long n = ((long)G.base[ax] << (lev - 1)) * nx;
+        long g = (long)pos[3 * b + ax] * nx + c[ax];
+        g = (g + n) % n;
+        odd[ax] = (int)(g & 1);
+        lc[ax] = (int)((g >> 1) - (long)pos[3 * cb + ax] * nx);
+      }
+      const long i0 = pidx(G, lc[0], lc[1], lc[2]);
+      long im[3], ip[3];
+      for (int ax = 0; ax < 3; ++ax) {
+        int m[3] = {lc[0], lc[1], lc[2]}, p[3] = {lc[0], lc[1], lc[2]};
+        m[ax] -= 1;
+        p[ax] += 1;
+        im[ax] = ax < G.ndim ? pidx(G, m[0], m[1], m[2]) : i0;
+        ip[ax] = ax < G.ndim ? pidx(G, p[0], p[1], p[2]) : i0;
+      }
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const double* s = src + q * G.pcells;
+        const double uc = s[i0];
+        double r = uc;
+        for (int ax = 0; ax < G.ndim; ++ax) {
+          const double sg = odd[ax] ? 0.25 : -0.25;
+          r = r + sg * minmod2(uc - s[im[ax]], s[ip[ax]] - uc);
+        }
+        dst[q * G.pcells + di] = r;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// conserved -> primitive on interior + face ghost cells
+
+__global__ void __launch_bounds__(256) k_prim(GridConst G, const double* __restrict__ slot, double* __restrict__ prim,
+                                             PhysConst P, DevStatus* st) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long total = (long)G.nb * G.pcells;
+  if (gid >= total) return;
+  const int b = (int)(gid / G.pcells);
+  const long c = gid - (long)b * G.pcells;
+  const int i = (int)(c % G.pn) - G.ng;
+  const int j = (int)((c / G.pn) % G.pn) - G.ng;
+  const int k = G.ndim == 3 ? (int)(c / ((long)G.pn * G.pn)) - G.ng : 0;
+  const int outside = (i < 0 || i >= G.nx) + (j < 0 || j >= G.nx) + (G.ndim == 3 && (k < 0 || k >= G.nx));
+  if (outside > 1) return;
+  const double* u0 = slot + (long)b * NV * G.pcells + c;
+  double u[NV], w[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) u[q] = u0[q * G.pcells];
+  const int bad = cons_to_prim(u, w, P);
+  double* w0 = prim + (long)b * NV * G.pcells + c;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) w0[q * G.pcells] = w[q];
+  if (bad) {
+    atomicOr(&st->flags, (unsigned)bad);
+    if (P.fix) atomicAdd(&st->nfix, 1ull);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// face fluxes along D: one thread per face
+
+template <int D>
+__global__ void __launch_bounds__(256) k_flux(GridConst G, const double* __restrict__ prim, double* __restrict__ flux,
+                                             const double* __restrict__ ch_dev, PhysConst P) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long total = (long)G.nb * G.nfaces;
+  if (gid >= total) return;
+  const int b = (int)(gid / G.nfaces);
+  const int fi = (int)(gid - (long)b * G.nfaces);
+  const int nx = G.nx, n1 = nx + 1;
+  int i, j, k, f;
+  if (D == 0) {
+    f = fi % n1;
+    j = (fi / n1) % nx;
+    k = fi / (n1 * nx);
+    i = 0;
+  } else if (D == 1) {
+    i = fi % nx;
+    f = (fi / nx) % n1;
+    k = fi / (nx * n1);
+    j = 0;
+  } else {
+    i = fi % nx;
+    j = (fi / nx) % nx;
+    f = fi / (nx * nx);
+    k = 0;
+  }
+  const double* base = prim + (long)b * NV * G.pcells;
+  double wm[NV], wa[NV], wb[NV], wp[NV];
+  long idx[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int a = f - 2 + s;
+    idx[s] = D == 0 ? pidx(G, a, j, k) : (D == 1 ? pidx(G, i, a, k) : pidx(G, i, j, a));
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double* p = base + q * G.pcells;
+    wm[q] = p[idx[0]];
+    wa[q] = p[idx[1]];
+    wb[q] = p[idx[2]];
+    wp[q] = p[idx[3]];
+  }
+  double wl[NV], wr[NV], F[NV];
+  reconstruct_face(wm, wa, wb, wp, wl, wr);
+  const double ch = *ch_dev;
+  hll_glm_flux<D>(wl, wr, ch, 0.5 / ch, P, F);
+  double* out = flux + (long)b * NV * G.nfaces + fi;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) out[(long)q * G.nfaces] = F[q];
+}
+
+__device__ __forceinline__ int face_index(const GridConst& G, int d, int f, int t1, int t2) {
+  // t1/t2: the transverse coordinates in axis order (x before y before z)
+  const int nx = G.nx, n1 = nx + 1;
+  if (d == 0) return (t2 * nx + t1) * n1 + f;   // t1 = j, t2 = k
+  if (d == 1) return (t2 * n1 + f) * nx + t1;   // t1 = i, t2 = k
+  return (f * nx + t2) * nx + t1;               // t1 = i, t2 = j
+}
+
+// coarse/fine flux correction: one thread per coarse boundary face cell
+__global__ void __launch_bounds__(256) k_reflux(GridConst G, const int* __restrict__ tasks, int ntasks,
+                                               const int* __restrict__ link, FluxPtrs flux) {
+  const int nx = G.nx;
+  const int per = G.ndim == 3 ? nx * nx : nx;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)ntasks * per) return;
+  const int task = (int)(gid / per);
+  const int t = (int)(gid - (long)task * per);
+  const int b = tasks[2 * task], face = tasks[2 * task + 1];
+  const int d = face >> 1, side = face & 1;
+  const int* L = link + ((long)b * 6 + face) * LINK_INTS;
+  const int t1 = t % nx, t2 = G.ndim == 3 ? t / nx : 0;
+  const int ff = side ? 0 : nx;  // fine face along d
+  const int cf = side ? nx : 0;  // coarse face along d
+  double* F = flux.f[d];
+  double acc[NV];
+  double v[2][2][NV];
+  const int ne = G.ndim == 3 ? 2 : 1;
+  for (int e = 0; e < ne; ++e)
+    for (int a = 0; a < 2; ++a) {
+      const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
+      const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
+      const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
+      const int fidx = face_index(G, d, ff, g1 - o1 * nx, G.ndim == 3 ? g2 - o2 * nx : 0);
+      const double* src = F + (long)fb * NV * G.nfaces + fidx;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[e][a][q] = src[(long)q * G.nfaces];
+    }
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    acc[q] = G.ndim == 3 ? ((v[0][0][q] + v[0][1][q]) + (v[1][0][q] + v[1][1][q])) * 0.25
+                         : (v[0][0][q] + v[0][1][q]) * 0.5;
+  double* dst = F + (long)b * NV * G.nfaces + face_index(G, d, cf, t1, t2);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) dst[(long)q * G.nfaces] = acc[q];
+}
+
+// flux-difference update + SSPRK combination: one thread per interior cell
+__global__ void __launch_bounds__(256) k_update(GridConst G, LevelConst Lc, const int* __restrict__ level,
+                                               const double* __restrict__ in, const double* base,
+                                               double* out, double w, FluxPtrs flux,
+                                               const double* __restrict__ dt_dev,
+                                               const double* __restrict__ kappa_dev) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long total = (long)G.nb * G.icells;
+  if (gid >= total) return;
+  const int b = (int)(gid / G.icells);
+  const int c = (int)(gid - (long)b * G.icells);
+  const int nx = G.nx;
+  const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
+  const int lev = level[b];
+  const long pc = pidx(G, i, j, k);
+  const double dt = *dt_dev, kappa = *kappa_dev;
+  double L[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) L[q] = 0.0;
+  for (int d = 0; d < G.ndim; ++d) {
+    int f, t1, t2;
+    if (d == 0) { f = i; t1 = j; t2 = k; }
+    else if (d == 1) { f = j; t1 = i; t2 = k; }
+    else { f = k; t1 = i; t2 = j; }
+    const double* F = flux.f[d] + (long)b * NV * G.nfaces;
+    const int lo = face_index(G, d, f, t1, t2), hi = face_index(G, d, f + 1, t1, t2);
+    const double idx = Lc.inv_dx[lev][d];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) L[q] = L[q] + (F[(long)q * G.nfaces + hi] - F[(long)q * G.nfaces + lo]) * idx;
+  }
+  const double* u = in + (long)b * NV * G.pcells + pc;
+  double* o = out + (long)b * NV * G.pcells + pc;
+  const double psi = u[I_PSI * G.pcells];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double lq = -L[q];
+    if (q == I_PSI) lq = lq - kappa * psi;
+    const double t = u[q * G.pcells] + dt * lq;
+    if (w == 1.0) {
+      o[q * G.pcells] = t;
+    } else {
+      const double u0 = base[(long)b * NV * G.pcells + pc + q * G.pcells];
+      o[q * G.pcells] = u0 + w * (t - u0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CFL: max over leaf interior cells of sum_d (|v_d| + c_f,d)/dx_d
+
+__global__ void __launch_bounds__(256) k_cfl(GridConst G, LevelConst Lc, const int* __restrict__ level,
+                                            const double* __restrict__ slot, PhysConst P, DevStatus* st) {
+  const long total = (long)G.nb * G.icells;
+  double r = 0.0;
+  int bad = 0, nan_seen = 0;
+  for (long gid = (long)blockIdx.x * blockDim.x + threadIdx.x; gid < total; gid += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(gid / G.icells);
+    const int c = (int)(gid - (long)b * G.icells);
+    const int nx = G.nx;
+    const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
+    const double* u0 = slot + (long)b * NV * G.pcells + pidx(G, i, j, k);
+    double u[NV], w[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) u[q] = u0[q * G.pcells];
+    bad |= cons_to_prim(u, w, P);
+    const int lev = level[b];
+    const double ri = 1.0 / w[I_RHO];
+    const double b2 = w[I_BX] * w[I_BX] + w[I_BY] * w[I_BY] + w[I_BZ] * w[I_BZ];
+    double rate = (fabs(w[1]) + cfast<0>(w, ri, b2, P)) * Lc.inv_dx[lev][0];
+    rate = rate + (fabs(w[2]) + cfast<1>(w, ri, b2, P)) * Lc.inv_dx[lev][1];
+    if (G.ndim == 3) rate = rate + (fabs(w[3]) + cfast<2>(w, ri, b2, P)) * Lc.inv_dx[lev][2];
+    if (isnan(rate))
+      nan_seen = 1;
+    else
+      r = fmax(r, rate);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
+  __shared__ double smax[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) smax[wave] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = smax[0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, smax[q]);
+    atomicMax(&st->rate_bits, (unsigned long long)__double_as_longlong(m));
+  }
+  if (bad) atomicOr(&st->flags, (unsigned)bad);
+  if (nan_seen) atomicOr(&st->cfl_nan, 1u);
+}
+
+__global__ void k_cfl_finalize(LevelConst Lc, DevStatus* st, double* dt_dev, double* ch_dev, double* kappa_dev) {
+  if (threadIdx.x != 0) return;
+  const double rmax = __longlong_as_double((long long)st->rate_bits);
+  const unsigned nan_seen = st->cfl_nan;
+  st->rate_bits = 0ull;
+  st->cfl_nan = 0u;
+  double dt = 0.0, ch = 0.0, kappa = 0.0;
+  if (nan_seen || !(rmax > 0.0) || !isfinite(rmax)) {
+    st->flags |= F_BAD_DT;
+  } else {
+    dt = Lc.cfl / rmax;
+    ch = Lc.cfl / (dt * Lc.sum_inv_dx_fin);
+    kappa = Lc.glm_alpha * ch / Lc.min_dx_fin;
+  }
+  *dt_dev = dt;
+  *ch_dev = ch;
+  *kappa_dev = kappa;
+  st->last_dt = dt;
+}
+
+// ---------------------------------------------------------------------------
+// conversions
+
+__global__ void __launch_bounds__(256) k_set_prim(GridConst G, const double* __restrict__ prim, double* __restrict__ slot,
+                                                 PhysConst P) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)G.nb * G.icells) return;
+  const int b = (int)(gid / G.icells);
+  const int c = (int)(gid - (long)b * G.icells);
+  const int nx = G.nx;
+  const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
+  double w[NV], u[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) w[q] = prim[((long)b * NV + q) * G.icells + c];
+  prim_to_cons(w, u, P);
+  double* o = slot + (long)b * NV * G.pcells + pidx(G, i, j, k);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) o[q * G.pcells] = u[q];
+}
+
+__global__ void __launch_bounds__(256) k_get_cons(GridConst G, const double* __restrict__ slot, double* __restrict__ cons) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)G.nb * G.icells) return;
+  const int b = (int)(gid / G.icells);
+  const int c = (int)(gid - (long)b * G.icells);
+  const int nx = G.nx;
+  const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
+  const double* s = slot + (long)b * NV * G.pcells + pidx(G, i, j, k);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) cons[((long)b * NV + q) * G.icells + c] = s[q * G.pcells];
+}
+
+__global__ void k_reset_status(DevStatus* st) {
+  if (threadIdx.x == 0) {
+    st->flags = 0u;
+    st->cfl_nan = 0u;
+    st->nfix = 0ull;
+    st->rate_bits = 0ull;
+  }
+}
+
+inline unsigned nblocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_fill_faces(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const int* link,
+                             const int* pos, void* slot, const PhysConst& P, const FixedBC& fixed) {
+  if (ntasks <= 0) return hipSuccess;
+  k_fill_faces<<<ntasks, 256, 0, s>>>(G, tasks, link, pos, static_cast<double*>(slot), P, fixed);
+  return hipGetLastError();
+}
+
+hipError_t launch_prim(hipStream_t s, const GridConst& G, const void* slot, double* prim, const PhysConst& P,
+                       DevStatus* st) {
+  const long n = (long)G.nb * G.pcells;
+  k_prim<<<nblocks_for(n, 256), 256, 0, s>>>(G, static_cast<const double*>(slot), prim, P, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux(hipStream_t s, const GridConst& G, int dir, const double* prim, double* flux,
+                       const double* ch_dev, const PhysConst& P) {
+  const long n = (long)G.nb * G.nfaces;
+  const unsigned nbk = nblocks_for(n, 256);
+  if (dir == 0)
+    k_flux<0><<<nbk, 256, 0, s>>>(G, prim, flux, ch_dev, P);
+  else if (dir == 1)
+    k_flux<1><<<nbk, 256, 0, s>>>(G, prim, flux, ch_dev, P);
+  else
+    k_flux<2><<<nbk, 256, 0, s>>>(G, prim, flux, ch_dev, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_reflux(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const int* link,
+                         FluxPtrs flux) {
+  if (ntasks <= 0) return hipSuccess;
+  const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
+  k_reflux<<<nblocks_for(ntasks * per, 256), 256, 0, s>>>(G, tasks, ntasks, link, flux);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(hipStream_t s, const GridConst& G, const LevelConst& L, const int* level, const void* in,
+                         const void* base, void* out, double w, FluxPtrs flux, const double* dt_dev,
+                         const double* kappa_dev) {
+  const long n = (long)G.nb * G.icells;
+  k_update<<<nblocks_for(n, 256), 256, 0, s>>>(G, L, level, static_cast<const double*>(in),
+                                                static_cast<const double*>(base), static_cast<double*>(out), w,
+                                                flux, dt_dev, kappa_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl(hipStream_t s, const GridConst& G, const LevelConst& L, const int* level, const void* slot,
+                      const PhysConst& P, DevStatus* st, double* dt_dev, double* ch_dev, double* kappa_dev) {
+  const long n = (long)G.nb * G.icells;
+  unsigned nbk = nblocks_for(n, 256);
+  if (nbk > 4096) nbk = 4096;
+  k_cfl<<<nbk, 256, 0, s>>>(G, L, level, static_cast<const double*>(slot), P, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_cfl_finalize<<<1, 64, 0, s>>>(L, st, dt_dev, ch_dev, kappa_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_prim(hipStream_t s, const GridConst& G, const double* prim, void* slot, const PhysConst& P) {
+  const long n = (long)G.nb * G.icells;
+  k_set_prim<<<nblocks_for(n, 256), 256, 0, s>>>(G, prim, static_cast<double*>(slot), P);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_cons(hipStream_t s, const GridConst& G, const void* slot, double* cons) {
+  const long n = (long)G.nb * G.icells;
+  k_get_cons<<<nblocks_for(n, 256), 256, 0, s>>>(G, static_cast<const double*>(slot), cons);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_status(hipStream_t s, DevStatus* st) {
+  k_reset_status<<<1, 64, 0, s>>>(st);
+  return hipGetLastError();
+}
+
+}  // namespace amrvac

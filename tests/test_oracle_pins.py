@@ -264,7 +264,7 @@ def test_uniform_state_with_walls_bit_identical(orc):
     """Zero-gradient, reflective (v_n = B_n = 0 there) and fixed-inflow faces
     equal to the interior state keep a uniform state exactly."""
     wv = [1.3, 0.4, 0.0, 0.15, 0.8, 0.6, 0.0, 0.3, 0.0]
-    w = inputs.uniform_state(3, (2, 2, 2), wv, bc_lo=(3, 2, 1), bc_hi=(1, 2, 0))
+    w = inputs.uniform_state(3, (2, 2, 2), wv, bc_lo=(3, 2, 1), bc_hi=(1, 2, 1))
     w.bc_fixed_prim = np.zeros((3, 2, NV))
     w.bc_fixed_prim[0, 0] = wv
     sim = orc.OracleSim(w)
