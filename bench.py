@@ -31,10 +31,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--path", choices=["plain", "fused"], default="plain")
+    ap.add_argument("--path", choices=["plain", "fused"], default="fused")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph-pass", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (calibrates HBM counters)")
     return ap.parse_args()
 
 
@@ -63,6 +65,15 @@ def main():
     import torch
     from paper_2303_03026_amd import amrvac, inputs
 
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        bcopy = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        print("bench: calibration copy of %d bytes done" % a.numel(), file=sys.stderr, flush=True)
+        del a, bcopy
     print("bench: generating %d^3 random-mode input" % args.n, file=sys.stderr, flush=True)
     w = inputs.random_modes(args.n, 3, seed=1)
     path = amrvac.PATH_FUSED if args.path == "fused" else amrvac.PATH_PLAIN

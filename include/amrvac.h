@@ -107,11 +107,14 @@ int amrvac_set_primitive(amrvac_ctx* c, int slot, const double* prim_dev);
  * [block][var][interior cell]. */
 int amrvac_get_conserved(amrvac_ctx* c, int slot, double* cons_dev);
 
-/* Fill the face ghost slabs of every block of slot: same-level copies with
- * periodic wrap, restriction (pairwise-summed volume average) of finer
- * neighbours and physical boundaries, then limited linear prolongation of
- * coarser neighbours (the paper's internal boundary exchange of the
- * "Future directions" section, done on the device). */
+/* Fill the face ghost slabs of slot that amrvac_stage reads on the selected
+ * path: same-level copies with periodic wrap, restriction (pairwise-summed
+ * volume average) of finer neighbours and physical boundaries, then limited
+ * linear prolongation of coarser neighbours (the paper's internal boundary
+ * exchange of the "Future directions" section, done on the device).  On
+ * AMRVAC_PATH_PLAIN every face ghost slab is filled; AMRVAC_PATH_FUSED
+ * reads same-level neighbours in place, so their faces are skipped unless
+ * the block's ghosts feed a prolongation. */
 int amrvac_fill_ghosts(amrvac_ctx* c, int slot);
 
 /* Time step from the interior of slot: dt = C / max_cells sum_d

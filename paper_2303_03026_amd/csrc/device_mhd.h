@@ -37,6 +37,33 @@ struct DevStatus {
   double last_dt;
 };
 
+// Lean FP64 reciprocal, quotient and square root for the normal-range
+// operands of this scheme (no denormal or overflow scaling): a hardware
+// seed (v_rcp_f64 / v_rsq_f64) refined by Newton steps to about one ulp.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(e, r, r);
+  e = fma(-x, r, 1.0);
+  return fma(e, r, r);
+}
+
+__device__ __forceinline__ double div64(double a, double b) {
+  const double r = rcp64(b);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+
+__device__ __forceinline__ double sqrt64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  g = fma(fma(-g, g, x), h, g);
+  return x > 0.0 ? g : 0.0;
+}
+
 // conserved -> primitive; returns the small-value bits of this cell.  With
 // the fix on, density is floored first (velocity uses the floored value),
 // then pressure; conserved values and B are never changed.
@@ -47,7 +74,7 @@ __device__ __forceinline__ int cons_to_prim(const double u[NV], double w[NV], co
     bad |= F_SMALL_RHO;
     if (P.fix) rho = P.small_rho;
   }
-  const double ri = 1.0 / rho;
+  const double ri = rcp64(rho);
   w[I_RHO] = rho;
   w[1] = u[I_MX] * ri;
   w[2] = u[I_MY] * ri;
@@ -85,7 +112,7 @@ __device__ __forceinline__ void prim_to_cons(const double w[NV], double u[NV], c
 // van Leer's harmonic-mean slope
 __device__ __forceinline__ double vl_slope(double dm, double dp) {
   const double q = dm * dp;
-  return q > 0.0 ? 2.0 * q / (dm + dp) : 0.0;
+  return q > 0.0 ? div64(2.0 * q, dm + dp) : 0.0;
 }
 
 __device__ __forceinline__ double minmod2(double a, double b) {
@@ -101,13 +128,15 @@ __device__ __forceinline__ double cfast(const double w[NV], double ri, double b2
   const double s = a2 + bb;
   double disc = s * s - 4.0 * a2 * bn2;
   disc = disc < 0.0 ? 0.0 : disc;
-  return sqrt(0.5 * (s + sqrt(disc)));
+  return sqrt64(0.5 * (s + sqrt64(disc)));
 }
 
 // Interface flux along D from reconstructed left/right primitive states:
 // GLM interface values of (B_n, psi) from the exact solution of the linear
 // subsystem, then HLL (Davis bounds) on rho, m, e and the tangential B,
-// with B_n replaced on both sides.  half_inv_ch = 0.5 / c_h.
+// with B_n replaced on both sides.  half_inv_ch = 0.5 / c_h.  The HLL
+// combination is formed one component at a time so that only the two
+// primitive states and a few per-side scalars stay live.
 template <int D>
 __device__ __forceinline__ void hll_glm_flux(double wl[NV], double wr[NV], double ch, double half_inv_ch,
                                              const PhysConst& P, double F[NV]) {
@@ -117,73 +146,53 @@ __device__ __forceinline__ void hll_glm_flux(double wl[NV], double wr[NV], doubl
   wl[N] = bn;
   wr[N] = bn;
 
-  double ul[NV], ur[NV], fl[NV], fr[NV];
-  double cl, cr;
-  {
-    const double* w = wl;
-    double* u = ul;
-    double* f = fl;
-    const double rho = w[I_RHO], ri = 1.0 / rho;
-    const double v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
-    const double b2 = w[I_BX] * w[I_BX] + w[I_BY] * w[I_BY] + w[I_BZ] * w[I_BZ];
-    const double vb = w[1] * w[I_BX] + w[2] * w[I_BY] + w[3] * w[I_BZ];
-    u[I_RHO] = rho;
-    u[I_MX] = rho * w[1];
-    u[I_MY] = rho * w[2];
-    u[I_MZ] = rho * w[3];
-    u[I_EN] = w[4] * P.inv_gm1 + 0.5 * rho * v2 + 0.5 * b2;
-    const double vn = w[1 + D];
-    const double pt = w[4] + 0.5 * b2;
-    f[I_RHO] = u[I_MX + D];
-    f[I_MX] = u[I_MX] * vn - w[I_BX] * bn;
-    f[I_MY] = u[I_MY] * vn - w[I_BY] * bn;
-    f[I_MZ] = u[I_MZ] * vn - w[I_BZ] * bn;
-    f[I_MX + D] += pt;
-    f[I_EN] = (u[I_EN] + pt) * vn - bn * vb;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      u[I_BX + j] = w[I_BX + j];
-      f[I_BX + j] = vn * w[I_BX + j] - bn * w[1 + j];
-    }
-    cl = cfast<D>(w, ri, b2, P);
-  }
-  {
-    const double* w = wr;
-    double* u = ur;
-    double* f = fr;
-    const double rho = w[I_RHO], ri = 1.0 / rho;
-    const double v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
-    const double b2 = w[I_BX] * w[I_BX] + w[I_BY] * w[I_BY] + w[I_BZ] * w[I_BZ];
-    const double vb = w[1] * w[I_BX] + w[2] * w[I_BY] + w[3] * w[I_BZ];
-    u[I_RHO] = rho;
-    u[I_MX] = rho * w[1];
-    u[I_MY] = rho * w[2];
-    u[I_MZ] = rho * w[3];
-    u[I_EN] = w[4] * P.inv_gm1 + 0.5 * rho * v2 + 0.5 * b2;
-    const double vn = w[1 + D];
-    const double pt = w[4] + 0.5 * b2;
-    f[I_RHO] = u[I_MX + D];
-    f[I_MX] = u[I_MX] * vn - w[I_BX] * bn;
-    f[I_MY] = u[I_MY] * vn - w[I_BY] * bn;
-    f[I_MZ] = u[I_MZ] * vn - w[I_BZ] * bn;
-    f[I_MX + D] += pt;
-    f[I_EN] = (u[I_EN] + pt) * vn - bn * vb;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      u[I_BX + j] = w[I_BX + j];
-      f[I_BX + j] = vn * w[I_BX + j] - bn * w[1 + j];
-    }
-    cr = cfast<D>(w, ri, b2, P);
-  }
+  const double rl = wl[I_RHO], rr = wr[I_RHO];
+  const double b2l = wl[I_BX] * wl[I_BX] + wl[I_BY] * wl[I_BY] + wl[I_BZ] * wl[I_BZ];
+  const double b2r = wr[I_BX] * wr[I_BX] + wr[I_BY] * wr[I_BY] + wr[I_BZ] * wr[I_BZ];
+  const double cl = cfast<D>(wl, rcp64(rl), b2l, P);
+  const double cr = cfast<D>(wr, rcp64(rr), b2r, P);
   const double vnl = wl[1 + D], vnr = wr[1 + D];
   const double sl = fmin(vnl - cl, vnr - cr);
   const double sr = fmax(vnl + cl, vnr + cr);
-  const double inv = 1.0 / (sr - sl);
+  const double inv = rcp64(sr - sl);
+  const double slsr = sl * sr;
+  const bool use_l = sl >= 0.0, use_r = sr <= 0.0;
+  auto hll = [&](double ul, double ur, double fl, double fr) {
+    const double h = (sr * fl - sl * fr + slsr * (ur - ul)) * inv;
+    return use_l ? fl : (use_r ? fr : h);
+  };
+  // mass
+  const double mnl = rl * vnl, mnr = rr * vnr;
+  F[I_RHO] = hll(rl, rr, mnl, mnr);
+  // energy
+  {
+    const double v2l = wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3];
+    const double v2r = wr[1] * wr[1] + wr[2] * wr[2] + wr[3] * wr[3];
+    const double el = wl[4] * P.inv_gm1 + 0.5 * rl * v2l + 0.5 * b2l;
+    const double er = wr[4] * P.inv_gm1 + 0.5 * rr * v2r + 0.5 * b2r;
+    const double vbl = wl[1] * wl[I_BX] + wl[2] * wl[I_BY] + wl[3] * wl[I_BZ];
+    const double vbr = wr[1] * wr[I_BX] + wr[2] * wr[I_BY] + wr[3] * wr[I_BZ];
+    const double ptl = wl[4] + 0.5 * b2l, ptr = wr[4] + 0.5 * b2r;
+    F[I_EN] = hll(el, er, (el + ptl) * vnl - bn * vbl, (er + ptr) * vnr - bn * vbr);
+    // momentum
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    if (q == N) continue;
-    const double hll = (sr * fl[q] - sl * fr[q] + sl * sr * (ur[q] - ul[q])) * inv;
-    F[q] = sl >= 0.0 ? fl[q] : (sr <= 0.0 ? fr[q] : hll);
+    for (int c = 0; c < 3; ++c) {
+      const double ml = rl * wl[1 + c], mr = rr * wr[1 + c];
+      double fl = ml * vnl - wl[I_BX + c] * bn;
+      double fr = mr * vnr - wr[I_BX + c] * bn;
+      if (c == D) {
+        fl += ptl;
+        fr += ptr;
+      }
+      F[I_MX + c] = hll(ml, mr, fl, fr);
+    }
+  }
+  // tangential field
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c == D) continue;
+    F[I_BX + c] = hll(wl[I_BX + c], wr[I_BX + c], vnl * wl[I_BX + c] - bn * wl[1 + c],
+                      vnr * wr[I_BX + c] - bn * wr[1 + c]);
   }
   F[N] = ps;
   F[I_PSI] = ch * ch * bn;

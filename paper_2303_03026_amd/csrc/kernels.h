@@ -60,6 +60,15 @@ hipError_t launch_update(hipStream_t s, const GridConst& G, const LevelConst& L,
                          const void* in, const void* base, void* out, double w,
                          FluxPtrs flux, const double* dt_dev, const double* kappa_dev);
 
+// fused stage (FP64, nx = 16) and the coarse/fine correction that follows it
+hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const LevelConst& L, const int* level,
+                              const int* link, const int* order, const void* in, const void* base, void* out,
+                              double w, const double* dt_dev, const double* ch_dev, const double* kappa_dev,
+                              const PhysConst& P, DevStatus* st);
+hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const LevelConst& L, const int* level,
+                                 const int* tasks, int ntasks, const int* link, const void* in, void* out, double w,
+                                 const double* dt_dev, const double* ch_dev, const PhysConst& P);
+
 // CFL ----------------------------------------------------------------------
 hipError_t launch_cfl(hipStream_t s, const GridConst& G, const LevelConst& L, const int* level,
                       const void* slot, const PhysConst& P, DevStatus* st, double* dt_dev,

@@ -337,6 +337,80 @@ __global__ void __launch_bounds__(256) k_update(GridConst G, LevelConst Lc, cons
   }
 }
 
+// Flux correction after a fused stage, direction D only (so no two tasks
+// touch one cell): for each coarse cell next to finer leaves, replace the
+// coarse face flux used by the stage with the pairwise mean of the fine face
+// fluxes, i.e. out += w*dt*dL.  Both fluxes are recomputed from the stage
+// input (ghosts filled) exactly as the stage kernels compute them.
+template <int D>
+__device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const double* __restrict__ S, int f, int t1,
+                                                    int t2, double ch, double hic, const PhysConst& P,
+                                                    double F[NV]) {
+  double w4[4][NV];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int a = f - 2 + s;
+    long c;
+    if (D == 0) c = pidx(G, a, t1, t2);
+    else if (D == 1) c = pidx(G, t1, a, t2);
+    else c = pidx(G, t1, t2, a);
+    double u[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) u[q] = S[q * G.pcells + c];
+    (void)cons_to_prim(u, w4[s], P);
+  }
+  double wl[NV], wr[NV];
+  reconstruct_face(w4[0], w4[1], w4[2], w4[3], wl, wr);
+  hll_glm_flux<D>(wl, wr, ch, hic, P, F);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, LevelConst Lc, const int* __restrict__ level,
+                                                       const int* __restrict__ tasks, int ntasks,
+                                                       const int* __restrict__ link, const double* __restrict__ in,
+                                                       double* out, double w, const double* __restrict__ dt_dev,
+                                                       const double* __restrict__ ch_dev, PhysConst P) {
+  const int nx = G.nx;
+  const int per = G.ndim == 3 ? nx * nx : nx;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)ntasks * per) return;
+  const int task = (int)(gid / per);
+  const int t = (int)(gid - (long)task * per);
+  const int b = tasks[2 * task], face = tasks[2 * task + 1];
+  if ((face >> 1) != D) return;
+  const int side = face & 1;
+  const int* L = link + ((long)b * 6 + face) * LINK_INTS;
+  const int t1 = t % nx, t2 = G.ndim == 3 ? t / nx : 0;
+  const double ch = *ch_dev, hic = 0.5 / ch, dt = *dt_dev;
+  double Fc[NV], Ff[NV], v[2][2][NV];
+  face_flux_from_slot<D>(G, in + (long)b * NV * G.pcells, side ? nx : 0, t1, t2, ch, hic, P, Fc);
+  const int ne = G.ndim == 3 ? 2 : 1;
+  for (int e = 0; e < ne; ++e)
+    for (int a = 0; a < 2; ++a) {
+      const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
+      const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
+      const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
+      face_flux_from_slot<D>(G, in + (long)fb * NV * G.pcells, side ? 0 : nx, g1 - o1 * nx,
+                             G.ndim == 3 ? g2 - o2 * nx : 0, ch, hic, P, v[e][a]);
+    }
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    Ff[q] = G.ndim == 3 ? ((v[0][0][q] + v[0][1][q]) + (v[1][0][q] + v[1][1][q])) * 0.25
+                        : (v[0][0][q] + v[0][1][q]) * 0.5;
+  const int cell_d = side ? nx - 1 : 0;
+  long c;
+  if (D == 0) c = pidx(G, cell_d, t1, t2);
+  else if (D == 1) c = pidx(G, t1, cell_d, t2);
+  else c = pidx(G, t1, t2, cell_d);
+  const double idx = Lc.inv_dx[level[b]][D];
+  double* o = out + (long)b * NV * G.pcells + c;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double dl = side ? -(Ff[q] - Fc[q]) * idx : (Ff[q] - Fc[q]) * idx;
+    o[q * G.pcells] = o[q * G.pcells] + w * dt * dl;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // CFL: max over leaf interior cells of sum_d (|v_d| + c_f,d)/dx_d
 
@@ -356,7 +430,7 @@ __global__ void __launch_bounds__(256) k_cfl(GridConst G, LevelConst Lc, const i
     for (int q = 0; q < NV; ++q) u[q] = u0[q * G.pcells];
     bad |= cons_to_prim(u, w, P);
     const int lev = level[b];
-    const double ri = 1.0 / w[I_RHO];
+    const double ri = rcp64(w[I_RHO]);
     const double b2 = w[I_BX] * w[I_BX] + w[I_BY] * w[I_BY] + w[I_BZ] * w[I_BZ];
     double rate = (fabs(w[1]) + cfast<0>(w, ri, b2, P)) * Lc.inv_dx[lev][0];
     rate = rate + (fabs(w[2]) + cfast<1>(w, ri, b2, P)) * Lc.inv_dx[lev][1];
@@ -478,6 +552,21 @@ hipError_t launch_reflux(hipStream_t s, const GridConst& G, const int* tasks, in
   if (ntasks <= 0) return hipSuccess;
   const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
   k_reflux<<<nblocks_for(ntasks * per, 256), 256, 0, s>>>(G, tasks, ntasks, link, flux);
+  return hipGetLastError();
+}
+
+hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const LevelConst& L, const int* level,
+                                 const int* tasks, int ntasks, const int* link, const void* in, void* out, double w,
+                                 const double* dt_dev, const double* ch_dev, const PhysConst& P) {
+  if (ntasks <= 0) return hipSuccess;
+  const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
+  const unsigned nbk = nblocks_for(ntasks * per, 256);
+  const double* pin = static_cast<const double*>(in);
+  double* pout = static_cast<double*>(out);
+  k_reflux_correct<0><<<nbk, 256, 0, s>>>(G, L, level, tasks, ntasks, link, pin, pout, w, dt_dev, ch_dev, P);
+  k_reflux_correct<1><<<nbk, 256, 0, s>>>(G, L, level, tasks, ntasks, link, pin, pout, w, dt_dev, ch_dev, P);
+  if (G.ndim == 3)
+    k_reflux_correct<2><<<nbk, 256, 0, s>>>(G, L, level, tasks, ntasks, link, pin, pout, w, dt_dev, ch_dev, P);
   return hipGetLastError();
 }
 

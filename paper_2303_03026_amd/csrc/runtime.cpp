@@ -33,8 +33,11 @@ struct amrvac_ctx {
   int* d_level = nullptr;
   int* d_pos = nullptr;
   int* d_link = nullptr;
-  int* d_tasks_fill = nullptr;
+  int* d_tasks_fill = nullptr;   // every copy/restrict/physical face (plain path)
   int n_tasks_fill = 0;
+  int* d_tasks_fill_fused = nullptr;  // faces the fused stage does not read in place
+  int n_tasks_fill_fused = 0;
+  int* d_order = nullptr;  // Morton order of the blocks (fused stage scheduling)
   int* d_tasks_prolong = nullptr;
   int n_tasks_prolong = 0;
   int* d_tasks_reflux = nullptr;
@@ -109,7 +112,8 @@ long long slot_bytes_of(const amrvac_grid_desc* g, int nb) {
 static int free_all(amrvac_ctx* c) {
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  void* ptrs[] = {c->d_level, c->d_pos, c->d_link, c->d_tasks_fill, c->d_tasks_prolong, c->d_tasks_reflux,
+  void* ptrs[] = {c->d_level, c->d_pos, c->d_link, c->d_tasks_fill, c->d_tasks_fill_fused, c->d_order,
+                  c->d_tasks_prolong, c->d_tasks_reflux,
                   c->d_prim, c->d_flux[0], c->d_flux[1], c->d_flux[2], c->d_status, c->d_scalars};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -335,10 +339,45 @@ int amrvac_init_blocks(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, cons
   c->n_tasks_fill = (int)tfill.size() / 2;
   c->n_tasks_prolong = (int)tprol.size() / 2;
   c->n_tasks_reflux = g->reflux ? (int)trefl.size() / 2 : 0;
+  // The fused stage reads same-level neighbours in place; it needs filled
+  // ghosts only on faces towards finer leaves and physical boundaries, plus
+  // every face of a block whose ghosts feed a prolongation.
+  std::vector<char> prol_src(nb, 0);
+  for (size_t q = 0; q < tprol.size(); q += 2) {
+    const int fb = tprol[q], face = tprol[q + 1];
+    prol_src[link[((size_t)fb * 6 + face) * LINK_INTS + 1]] = 1;
+  }
+  std::vector<int> tfused;
+  for (size_t q = 0; q < tfill.size(); q += 2) {
+    const int fb = tfill[q], face = tfill[q + 1];
+    if (link[((size_t)fb * 6 + face) * LINK_INTS] != LINK_SAME || prol_src[fb]) {
+      tfused.push_back(fb);
+      tfused.push_back(face);
+    }
+  }
+  c->n_tasks_fill_fused = (int)tfused.size() / 2;
+  // Morton order on the finest level's block grid
+  std::vector<std::pair<unsigned long long, int>> keyed(nb);
+  for (int b = 0; b < nb; ++b) {
+    const int sft = finest - level[b];
+    unsigned long long key = 0;
+    const unsigned long long q0 = (unsigned long long)pos[3 * b] << sft, q1 = (unsigned long long)pos[3 * b + 1] << sft,
+                             q2 = (unsigned long long)pos[3 * b + 2] << sft;
+    for (int bit = 0; bit < 20; ++bit) {
+      key |= ((q0 >> bit) & 1ull) << (3 * bit);
+      key |= ((q1 >> bit) & 1ull) << (3 * bit + 1);
+      key |= ((q2 >> bit) & 1ull) << (3 * bit + 2);
+    }
+    keyed[b] = {key, b};
+  }
+  std::sort(keyed.begin(), keyed.end());
+  std::vector<int> order(nb);
+  for (int b = 0; b < nb; ++b) order[b] = keyed[b].second;
 
   int rc;
   if ((rc = upload(c, &c->d_level, lev)) || (rc = upload(c, &c->d_pos, pos)) || (rc = upload(c, &c->d_link, link)) ||
       (rc = upload(c, &c->d_tasks_fill, tfill)) || (rc = upload(c, &c->d_tasks_prolong, tprol)) ||
+      (rc = upload(c, &c->d_tasks_fill_fused, tfused)) || (rc = upload(c, &c->d_order, order)) ||
       (rc = upload(c, &c->d_tasks_reflux, trefl))) {
     g_init_err = c->err;
     free_all(c);
@@ -400,7 +439,9 @@ int amrvac_get_conserved(amrvac_ctx* c, int slot, double* cons_dev) {
 int amrvac_fill_ghosts(amrvac_ctx* c, int slot) {
   if (!c) return AMRVAC_E_ARG;
   if (int rc = check_slot(c, slot)) return rc;
-  HIP_TRY(c, launch_fill_faces(c->stream, c->G, c->d_tasks_fill, c->n_tasks_fill, c->d_link, c->d_pos,
+  const bool fused = c->path == AMRVAC_PATH_FUSED;
+  HIP_TRY(c, launch_fill_faces(c->stream, c->G, fused ? c->d_tasks_fill_fused : c->d_tasks_fill,
+                               fused ? c->n_tasks_fill_fused : c->n_tasks_fill, c->d_link, c->d_pos,
                                c->slots[slot], c->P, c->fixed));
   HIP_TRY(c, launch_fill_faces(c->stream, c->G, c->d_tasks_prolong, c->n_tasks_prolong, c->d_link, c->d_pos,
                                c->slots[slot], c->P, c->fixed));
@@ -428,6 +469,15 @@ static int stage_plain(amrvac_ctx* c, int in, int base, int out, double w, const
   return AMRVAC_OK;
 }
 
+static int stage_fused(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev,
+                       const double* ch_dev, const double* kappa_dev) {
+  HIP_TRY(c, launch_fused_stage(c->stream, c->G, c->L, c->d_level, c->d_link, c->d_order, c->slots[in],
+                                c->slots[base], c->slots[out], w, dt_dev, ch_dev, kappa_dev, c->P, c->d_status));
+  HIP_TRY(c, launch_reflux_correct(c->stream, c->G, c->L, c->d_level, c->d_tasks_reflux, c->n_tasks_reflux,
+                                   c->d_link, c->slots[in], c->slots[out], w, dt_dev, ch_dev, c->P));
+  return AMRVAC_OK;
+}
+
 int amrvac_stage(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
                  const double* kappa_dev) {
   if (!c) return AMRVAC_E_ARG;
@@ -442,13 +492,14 @@ int amrvac_stage(amrvac_ctx* c, int in, int base, int out, double w, const doubl
   if (base == in && w != 1.0) return fail(c, AMRVAC_E_ARG, "base must differ from in");
   if (!dt_dev || !ch_dev || !kappa_dev) return fail(c, AMRVAC_E_ARG, "null dt/c_h/kappa pointer");
   if (!(w > 0.0 && w <= 1.0)) return fail(c, AMRVAC_E_ARG, "stage weight must be in (0, 1]");
+  if (c->path == AMRVAC_PATH_FUSED) return stage_fused(c, in, base, out, w, dt_dev, ch_dev, kappa_dev);
   return stage_plain(c, in, base, out, w, dt_dev, ch_dev, kappa_dev);
 }
 
 int amrvac_set_path(amrvac_ctx* c, int path) {
   if (!c) return AMRVAC_E_ARG;
   if (path != AMRVAC_PATH_PLAIN && path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_ARG, "unknown path");
-  if (path == AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_ARG, "fused path not available in this build");
+  if (path == AMRVAC_PATH_FUSED && c->G.nx != 16) return fail(c, AMRVAC_E_ARG, "the fused path needs block_nx = 16");
   c->path = path;
   return AMRVAC_OK;
 }

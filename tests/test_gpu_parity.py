@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 NV = 9
 RHO, VX, VY, VZ, PR, BX, BY, BZ, PSI = range(NV)
 TOL = 1e-12
-PATHS = ["plain"]
+PATHS = ["plain", "fused"]
 
 
 def vol_weights(w):
@@ -190,12 +190,13 @@ def test_parity_small_current_sheet(amr, orc, path):
     assert_parity(w, gpu, ref, label="current_sheet_32")
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("nstages", [2, 3])
-def test_graph_and_eager_bitwise_equal(amr, nstages):
+def test_graph_and_eager_bitwise_equal(amr, nstages, path):
     w = inputs.random_modes(32, 3, seed=9)
     outs = []
     for graph in (False, True, True):
-        sim = make_sim(amr, w)
+        sim = make_sim(amr, w, path)
         sim.advance(3, nstages=nstages, graph=graph)
         sim.sync_flags()
         outs.append(sim.cons())
@@ -267,9 +268,21 @@ def test_parity_full_shock_cloud_amr(amr, orc, path):
     assert_parity(w, gpu, ref, label="shock_cloud_amr")
 
 
-def test_parity_full_current_sheet_192(amr, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_parity_full_current_sheet_192(amr, orc, path):
     w = inputs.current_sheet(n=192)
     ref, diag = orc.run(w, 1)
-    gpu, fl = run_gpu(amr, w, 1, "plain", graph=True)
+    gpu, fl = run_gpu(amr, w, 1, path, graph=True)
     assert fl[0] == 0
     assert_parity(w, gpu, ref, label="current_sheet_192")
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_fused_matches_plain(amr, ndim):
+    """The fused stage kernel and the per-kernel path agree to rounding
+    (both are also checked against the oracle above)."""
+    w = inputs.random_modes(64 if ndim == 2 else 32, ndim, seed=12)
+    a, _ = run_gpu(amr, w, 5, "plain")
+    b, _ = run_gpu(amr, w, 5, "fused")
+    err = rel_l1(w, b, a)
+    assert np.all(err[:PSI] < 1e-13), err
