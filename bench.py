@@ -20,10 +20,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mcell-updates/s + HBM GB/s (FP64 vs FP32/batched); p50/p99 job latency"
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per cell for one stage launch: read the input state,
+# Algorithmic HBM bytes per cell for one stage launch: read the input state,
 # write the output state, and read the base state when the stage weight is
-# not 1 (72 B per FP64 state)
-STAGE_BYTES_FP64 = {1.0: 144.0, "w": 216.0}
+# not 1; one state is 72 B per cell in FP64 and 40 B in FP32-mixed.
 
 
 def parse():
@@ -33,6 +32,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", choices=["plain", "fused"], default="fused")
     ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", choices=["f64", "mixed"], default="f64",
+                    help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
+    ap.add_argument("--workload", choices=["random_modes", "current_sheet"], default="random_modes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph-pass", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -74,10 +76,17 @@ def main():
         torch.cuda.synchronize()
         print("bench: calibration copy of %d bytes done" % a.numel(), file=sys.stderr, flush=True)
         del a, bcopy
-    print("bench: generating %d^3 random-mode input" % args.n, file=sys.stderr, flush=True)
-    w = inputs.random_modes(args.n, 3, seed=1)
+    print("bench: generating %d^3 %s input" % (args.n, args.workload), file=sys.stderr, flush=True)
+    if args.workload == "random_modes":
+        w = inputs.random_modes(args.n, 3, seed=1)
+    else:
+        w = inputs.current_sheet(n=args.n)
+    mixed = args.precision == "mixed"
+    if mixed:
+        args.path = "fused"
     path = amrvac.PATH_FUSED if args.path == "fused" else amrvac.PATH_PLAIN
-    sim = amrvac.Simulation(w, path=path)
+    sim = amrvac.Simulation(w, path=path, precision=amrvac.FP32_MIXED if mixed else amrvac.FP64)
+    state_bytes = 40.0 if mixed else 72.0
     stream = sim.stream
     weights = [(0, 0, 1, 1.0), (1, 0, 2, 0.25), (2, 0, 0, 2.0 / 3.0)]
 
@@ -117,7 +126,8 @@ def main():
     # dominant kernel: the stage update (per-launch average over the timed region)
     stage_ms = [[evs[k][s][0].elapsed_time(evs[k][s][1]) for k in range(K)] for s in range(3)]
     avg_ms = sum(sum(x) for x in stage_ms) / (3 * K)
-    bytes_per_launch = cells * (STAGE_BYTES_FP64[1.0] + 2 * STAGE_BYTES_FP64["w"]) / 3.0
+    # per cell: stage 1 reads in, writes out; stages 2 and 3 also read base
+    bytes_per_launch = cells * state_bytes * (2 + 3 + 3) / 3.0
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 
     graph_ms = None
@@ -142,12 +152,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: 3D %d^3 periodic unit cube, %d blocks of 16^3 + 2 ghost layers, "
-                               "random-mode GLM-MHD state, SSPRK(3,3), CFL 0.8, FP64" % (w.name, args.n, w.nblocks),
+        "config": {"workload": "%s: 3D %d^3, %d blocks of 16^3 + 2 ghost layers, %s GLM-MHD state, "
+                               "SSPRK(3,3), CFL 0.8, %s" % (w.name, args.n, w.nblocks, args.workload,
+                                                            "FP32-mixed" if mixed else "FP64"),
                    "path": args.path, "cells": cells, "stage_weights": [1.0, 0.25, 2.0 / 3.0]},
-        "algorithmic_hbm_gbs_per_step": cells * 576.0 / (ms_per_step * 1e-3) / 1e9,
+        "algorithmic_hbm_gbs_per_step": cells * 8 * state_bytes / (ms_per_step * 1e-3) / 1e9,
         "graph_ms_per_step": graph_ms,
         "stage_ms": [sum(x) / K for x in stage_ms],
         "roofline": {"bound": "hbm", "kernel": "stage (%s path)" % args.path, "achieved": achieved,

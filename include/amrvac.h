@@ -143,8 +143,10 @@ int amrvac_stage(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double
 int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph);
 
 /* Select the stage implementation: AMRVAC_PATH_PLAIN (separate primitive,
- * per-direction flux, reflux and update kernels) or AMRVAC_PATH_FUSED (one
- * kernel per stage reading ghosts from the slot and writing the update). */
+ * per-direction flux, reflux and update kernels; FP64 only, the default for
+ * FP64 contexts) or AMRVAC_PATH_FUSED (one kernel per stage plus, on AMR
+ * grids, a coarse/fine flux correction; needs block_nx = 16; the only path
+ * of FP32-mixed contexts).  AMRVAC_E_ARG if the context cannot run it. */
 int amrvac_set_path(amrvac_ctx* c, int path);
 
 /* Synchronise the stream and read the device flag word (AMRVAC_FLAG_* bits
@@ -156,6 +158,52 @@ int amrvac_sync_flags(amrvac_ctx* c, int* flags_host, long long* nfix_host, doub
 
 /* Clear the device flag word and fix counter (enqueued on the stream). */
 int amrvac_reset_flags(amrvac_ctx* c);
+
+/* ---------------------------------------------------------------------------
+ * Batch (serving) contexts: many independent jobs resident on the device,
+ * advanced together.  A job is one grid of the same block shape, precision
+ * and physics (gamma, small-value settings, fixed boundary states) as the
+ * batch; it may differ in size, hierarchy, boundaries, Courant number and
+ * step count.  Its blocks occupy a contiguous run of places in the batch's
+ * block pool; each step advances every job with steps left by one
+ * SSPRK(nstages) step with its own dt, c_h and kappa, in one launch per
+ * kernel for all jobs (the fused path).  Jobs join and leave between steps.
+ * -------------------------------------------------------------------------*/
+
+/* Create a batch context.  shape supplies ndim, block_nx (must be 16),
+ * precision and the physics every job must share; slots are 2 (nstages = 2)
+ * or 3 (nstages = 3) caller-owned DEVICE buffers of
+ * amrvac_slot_bytes(shape, capacity_blocks) bytes each (the block pool);
+ * max_jobs bounds the number of resident jobs. */
+int amrvac_batch_create(amrvac_ctx** out, const amrvac_grid_desc* shape, int capacity_blocks, int max_jobs,
+                        int nstages, void* const* slots, void* stream);
+
+/* Admit a job: validate its block table (as amrvac_init_blocks), place its
+ * blocks in the first free run of the pool that fits, and convert its DEVICE
+ * primitive state ([block][var][interior cell] FP64) into the pool.  It will
+ * take nsteps steps.  *job_out receives the job id.  AMRVAC_E_NOMEM when no
+ * job slot or no contiguous run of nblocks places is free (the caller keeps
+ * it queued); AMRVAC_E_ARG when its shape or physics differs. */
+int amrvac_batch_add_job(amrvac_ctx* c, const amrvac_grid_desc* g, int nblocks, const int* level, const int* ijk,
+                         const double* prim_dev, int nsteps, int* job_out);
+
+/* Enqueue one step of every job that has steps left.  No host sync, except
+ * that admitting or finishing jobs makes the next step wait for the stream
+ * while the block lists are rebuilt. */
+int amrvac_batch_step(amrvac_ctx* c);
+
+/* Host-side progress of a job (no device access). */
+int amrvac_batch_job_info(amrvac_ctx* c, int job, int* steps_done, int* steps_left, int* nblocks);
+
+/* Copy a job's interior conserved state to a DEVICE FP64 array
+ * [block][var][interior cell] (enqueued on the stream). */
+int amrvac_batch_get_job(amrvac_ctx* c, int job, double* cons_dev);
+
+/* Retire a job and return its pool places (waits for the stream). */
+int amrvac_batch_remove_job(amrvac_ctx* c, int job);
+
+/* Largest free run and total free places of the pool. */
+int amrvac_batch_free_blocks(amrvac_ctx* c, int* largest_run, int* total_free);
 
 /* Message of the last failed call on this context (never NULL). */
 const char* amrvac_last_error(const amrvac_ctx* c);

@@ -24,7 +24,9 @@ E_OK, E_ARG, E_HIP, E_NOMEM, E_NONPHYSICAL, E_STATE = 0, -1, -2, -3, -4, -5
 # every entry point declared in include/amrvac.h
 ABI_SYMBOLS = ("amrvac_slot_bytes", "amrvac_init_blocks", "amrvac_set_primitive", "amrvac_get_conserved",
                "amrvac_fill_ghosts", "amrvac_cfl_dt", "amrvac_stage", "amrvac_advance", "amrvac_set_path",
-               "amrvac_sync_flags", "amrvac_reset_flags", "amrvac_last_error", "amrvac_destroy")
+               "amrvac_sync_flags", "amrvac_reset_flags", "amrvac_last_error", "amrvac_destroy",
+               "amrvac_batch_create", "amrvac_batch_add_job", "amrvac_batch_step", "amrvac_batch_job_info",
+               "amrvac_batch_get_job", "amrvac_batch_remove_job", "amrvac_batch_free_blocks")
 
 
 class AmrvacError(RuntimeError):
@@ -72,6 +74,14 @@ def load_library():
     lib.amrvac_last_error.argtypes = [vp]
     lib.amrvac_last_error.restype = ctypes.c_char_p
     lib.amrvac_destroy.argtypes = [vp]
+    lib.amrvac_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(GridDesc), ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.POINTER(vp), vp]
+    lib.amrvac_batch_add_job.argtypes = [vp, ctypes.POINTER(GridDesc), ctypes.c_int, ip, ip, vp, ctypes.c_int, ip]
+    lib.amrvac_batch_step.argtypes = [vp]
+    lib.amrvac_batch_job_info.argtypes = [vp, ctypes.c_int, ip, ip, ip]
+    lib.amrvac_batch_get_job.argtypes = [vp, ctypes.c_int, vp]
+    lib.amrvac_batch_remove_job.argtypes = [vp, ctypes.c_int]
+    lib.amrvac_batch_free_blocks.argtypes = [vp, ip, ip]
     _lib = lib
     return lib
 
@@ -249,3 +259,116 @@ def run(w, nsteps: Optional[int] = None, graph: bool = False, path: int = PATH_P
         return sim.cons()
     finally:
         sim.close()
+
+
+class Batch:
+    """A batch (serving) context: a device block pool shared by many jobs of
+    one block shape, precision and physics, advanced together."""
+
+    def __init__(self, shape, capacity_blocks: int, max_jobs: int, nstages: int = 3, precision: int = FP64,
+                 device: str = "cuda", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the MI355X path has no CPU fallback")
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.shape = shape
+        self.desc = make_desc(shape, precision)
+        self.precision = precision
+        self.capacity = capacity_blocks
+        size = ctypes.c_size_t()
+        if self.lib.amrvac_slot_bytes(ctypes.byref(self.desc), capacity_blocks, ctypes.byref(size)) != 0:
+            raise AmrvacError(E_ARG, "bad batch shape")
+        self.block_bytes = size.value // capacity_blocks
+        nslots = 3 if nstages == 3 else 2
+        with torch.cuda.stream(self.stream):
+            self.slots = [torch.empty(size.value, dtype=torch.uint8, device=self.device) for _ in range(nslots)]
+        torch.cuda.synchronize(self.device)
+        ptrs = (ctypes.c_void_p * nslots)(*[t.data_ptr() for t in self.slots])
+        ctx = ctypes.c_void_p()
+        rc = self.lib.amrvac_batch_create(ctypes.byref(ctx), ctypes.byref(self.desc), capacity_blocks, max_jobs,
+                                          nstages, ptrs, ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise AmrvacError(rc, self.lib.amrvac_last_error(None).decode())
+        self.ctx = ctx
+        self.jobs = {}
+
+    def _err(self, rc):
+        raise AmrvacError(rc, self.lib.amrvac_last_error(self.ctx).decode())
+
+    def add_job(self, w, nsteps: Optional[int] = None):
+        """Admit workload w; returns the job id, or None when the pool or the
+        job table is full (the caller keeps the job queued)."""
+        torch = self.torch
+        desc = make_desc(w, self.precision)
+        level = np.ascontiguousarray(w.level, dtype=np.int32)
+        ijk = np.ascontiguousarray(w.ijk, dtype=np.int32)
+        jid = ctypes.c_int()
+        with torch.cuda.stream(self.stream):
+            prim = torch.from_numpy(np.ascontiguousarray(w.prim, dtype=np.float64)).to(self.device)
+            rc = self.lib.amrvac_batch_add_job(
+                self.ctx, ctypes.byref(desc), len(level), level.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.c_void_p(prim.data_ptr()),
+                w.nsteps if nsteps is None else nsteps, ctypes.byref(jid))
+        if rc == E_NOMEM:
+            return None
+        if rc != 0:
+            self._err(rc)
+        self.jobs[jid.value] = (w.nx, w.ndim, len(level))
+        return jid.value
+
+    def step(self):
+        rc = self.lib.amrvac_batch_step(self.ctx)
+        if rc != 0:
+            self._err(rc)
+
+    def job_info(self, job: int):
+        done, left, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        rc = self.lib.amrvac_batch_job_info(self.ctx, job, ctypes.byref(done), ctypes.byref(left), ctypes.byref(nb))
+        if rc != 0:
+            self._err(rc)
+        return done.value, left.value, nb.value
+
+    def get_job(self, job: int) -> np.ndarray:
+        torch = self.torch
+        nx, ndim, nb = self.jobs[job]
+        with torch.cuda.stream(self.stream):
+            t = torch.empty((nb, NV) + (nx,) * ndim, dtype=torch.float64, device=self.device)
+            rc = self.lib.amrvac_batch_get_job(self.ctx, job, ctypes.c_void_p(t.data_ptr()))
+            if rc != 0:
+                self._err(rc)
+            out = t.cpu().numpy()
+        return out
+
+    def remove_job(self, job: int):
+        rc = self.lib.amrvac_batch_remove_job(self.ctx, job)
+        if rc != 0:
+            self._err(rc)
+        self.jobs.pop(job, None)
+
+    def free_blocks(self):
+        big, tot = ctypes.c_int(), ctypes.c_int()
+        rc = self.lib.amrvac_batch_free_blocks(self.ctx, ctypes.byref(big), ctypes.byref(tot))
+        if rc != 0:
+            self._err(rc)
+        return big.value, tot.value
+
+    def sync_flags(self, raise_on_error: bool = True):
+        fl, nfix, dt = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_double()
+        rc = self.lib.amrvac_sync_flags(self.ctx, ctypes.byref(fl), ctypes.byref(nfix), ctypes.byref(dt))
+        if rc != 0 and raise_on_error:
+            self._err(rc)
+        return fl.value, nfix.value, rc
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.amrvac_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,6 +1,8 @@
 // Device-side ideal GLM-MHD arithmetic for gfx950 (register-resident, fully
 // unrolled; the face direction is a template parameter so component
-// selection costs nothing).
+// selection costs nothing).  Face arithmetic is templated on the real type:
+// double on the FP64 path, float on the FP32-mixed path (where the
+// conserved-to-primitive step and the pressure recovery stay in double).
 //
 // Scheme (MPI-AMRVAC 3.0, arXiv 2303.03026): conservative finite volumes
 // ("Schemes and limiters for HD and MHD"), 'vanleer' slopes on primitive
@@ -37,24 +39,29 @@ struct DevStatus {
   double last_dt;
 };
 
-// Lean FP64 reciprocal, quotient and square root for the normal-range
-// operands of this scheme (no denormal or overflow scaling): a hardware
-// seed (v_rcp_f64 / v_rsq_f64) refined by Newton steps to about one ulp.
-__device__ __forceinline__ double rcp64(double x) {
+// ---------------------------------------------------------------------------
+// Lean reciprocal, quotient and square root for the normal-range operands of
+// this scheme (no denormal or overflow scaling).  FP64: a hardware seed
+// (v_rcp_f64 / v_rsq_f64) refined by Newton steps to about one ulp.  FP32:
+// the single-instruction v_rcp_f32 / v_sqrt_f32 (about one ulp).
+
+__device__ __forceinline__ double rcp_(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
   r = fma(e, r, r);
   e = fma(-x, r, 1.0);
   return fma(e, r, r);
 }
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 
-__device__ __forceinline__ double div64(double a, double b) {
-  const double r = rcp64(b);
+__device__ __forceinline__ double div_(double a, double b) {
+  const double r = rcp_(b);
   const double q = a * r;
   return fma(fma(-b, q, a), r, q);
 }
+__device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
-__device__ __forceinline__ double sqrt64(double x) {
+__device__ __forceinline__ double sqrt_(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y, h = 0.5 * y;
   const double r = fma(-g, h, 0.5);
@@ -63,22 +70,28 @@ __device__ __forceinline__ double sqrt64(double x) {
   g = fma(fma(-g, g, x), h, g);
   return x > 0.0 ? g : 0.0;
 }
+__device__ __forceinline__ float sqrt_(float x) { return x > 0.0f ? __builtin_amdgcn_sqrtf(x) : 0.0f; }
 
-// conserved -> primitive; returns the small-value bits of this cell.  With
-// the fix on, density is floored first (velocity uses the floored value),
-// then pressure; conserved values and B are never changed.
-__device__ __forceinline__ int cons_to_prim(const double u[NV], double w[NV], const PhysConst& P) {
+// ---------------------------------------------------------------------------
+// conserved -> primitive; returns the small-value bits of this cell.  The
+// conserved input is double (the FP64 energy and the promoted FP32 rest on
+// the mixed path) and the pressure recovery e - m^2/2rho - B^2/2 is done in
+// double; the primitive is then rounded to R.  With the fix on, density is
+// floored first (velocity uses the floored value), then pressure; conserved
+// values and B are never changed.
+template <class R>
+__device__ __forceinline__ int cons_to_prim(const double u[NV], R w[NV], const PhysConst& P) {
   int bad = 0;
   double rho = u[I_RHO];
   if (!(rho > P.small_rho)) {
     bad |= F_SMALL_RHO;
     if (P.fix) rho = P.small_rho;
   }
-  const double ri = rcp64(rho);
-  w[I_RHO] = rho;
-  w[1] = u[I_MX] * ri;
-  w[2] = u[I_MY] * ri;
-  w[3] = u[I_MZ] * ri;
+  const double ri = rcp_(rho);
+  w[I_RHO] = (R)rho;
+  w[1] = (R)(u[I_MX] * ri);
+  w[2] = (R)(u[I_MY] * ri);
+  w[3] = (R)(u[I_MZ] * ri);
   const double m2 = u[I_MX] * u[I_MX] + u[I_MY] * u[I_MY] + u[I_MZ] * u[I_MZ];
   const double b2 = u[I_BX] * u[I_BX] + u[I_BY] * u[I_BY] + u[I_BZ] * u[I_BZ];
   double p = P.gm1 * (u[I_EN] - 0.5 * m2 * ri - 0.5 * b2);
@@ -86,11 +99,11 @@ __device__ __forceinline__ int cons_to_prim(const double u[NV], double w[NV], co
     bad |= F_SMALL_P;
     if (P.fix) p = P.small_p;
   }
-  w[4] = p;
-  w[I_BX] = u[I_BX];
-  w[I_BY] = u[I_BY];
-  w[I_BZ] = u[I_BZ];
-  w[I_PSI] = u[I_PSI];
+  w[4] = (R)p;
+  w[I_BX] = (R)u[I_BX];
+  w[I_BY] = (R)u[I_BY];
+  w[I_BZ] = (R)u[I_BZ];
+  w[I_PSI] = (R)u[I_PSI];
   return bad;
 }
 
@@ -110,9 +123,10 @@ __device__ __forceinline__ void prim_to_cons(const double w[NV], double u[NV], c
 }
 
 // van Leer's harmonic-mean slope
-__device__ __forceinline__ double vl_slope(double dm, double dp) {
-  const double q = dm * dp;
-  return q > 0.0 ? div64(2.0 * q, dm + dp) : 0.0;
+template <class R>
+__device__ __forceinline__ R vl_slope(R dm, R dp) {
+  const R q = dm * dp;
+  return q > R(0) ? div_(R(2) * q, dm + dp) : R(0);
 }
 
 __device__ __forceinline__ double minmod2(double a, double b) {
@@ -120,15 +134,15 @@ __device__ __forceinline__ double minmod2(double a, double b) {
 }
 
 // Fast magnetosonic speed along D from a primitive state (1/rho given).
-template <int D>
-__device__ __forceinline__ double cfast(const double w[NV], double ri, double b2, const PhysConst& P) {
-  const double a2 = P.gamma * w[4] * ri;
-  const double bb = b2 * ri;
-  const double bn2 = w[I_BX + D] * w[I_BX + D] * ri;
-  const double s = a2 + bb;
-  double disc = s * s - 4.0 * a2 * bn2;
-  disc = disc < 0.0 ? 0.0 : disc;
-  return sqrt64(0.5 * (s + sqrt64(disc)));
+template <int D, class R>
+__device__ __forceinline__ R cfast(const R w[NV], R ri, R b2, R gamma) {
+  const R a2 = gamma * w[4] * ri;
+  const R bb = b2 * ri;
+  const R bn2 = w[I_BX + D] * w[I_BX + D] * ri;
+  const R s = a2 + bb;
+  R disc = s * s - R(4) * a2 * bn2;
+  disc = disc < R(0) ? R(0) : disc;
+  return sqrt_(R(0.5) * (s + sqrt_(disc)));
 }
 
 // Interface flux along D from reconstructed left/right primitive states:
@@ -137,49 +151,49 @@ __device__ __forceinline__ double cfast(const double w[NV], double ri, double b2
 // with B_n replaced on both sides.  half_inv_ch = 0.5 / c_h.  The HLL
 // combination is formed one component at a time so that only the two
 // primitive states and a few per-side scalars stay live.
-template <int D>
-__device__ __forceinline__ void hll_glm_flux(double wl[NV], double wr[NV], double ch, double half_inv_ch,
-                                             const PhysConst& P, double F[NV]) {
+template <int D, class R>
+__device__ __forceinline__ void hll_glm_flux(R wl[NV], R wr[NV], R ch, R half_inv_ch, R gamma, R inv_gm1,
+                                             R F[NV]) {
   constexpr int N = I_BX + D;
-  const double bn = 0.5 * (wl[N] + wr[N]) - (wr[I_PSI] - wl[I_PSI]) * half_inv_ch;
-  const double ps = 0.5 * (wl[I_PSI] + wr[I_PSI]) - 0.5 * ch * (wr[N] - wl[N]);
+  const R bn = R(0.5) * (wl[N] + wr[N]) - (wr[I_PSI] - wl[I_PSI]) * half_inv_ch;
+  const R ps = R(0.5) * (wl[I_PSI] + wr[I_PSI]) - R(0.5) * ch * (wr[N] - wl[N]);
   wl[N] = bn;
   wr[N] = bn;
 
-  const double rl = wl[I_RHO], rr = wr[I_RHO];
-  const double b2l = wl[I_BX] * wl[I_BX] + wl[I_BY] * wl[I_BY] + wl[I_BZ] * wl[I_BZ];
-  const double b2r = wr[I_BX] * wr[I_BX] + wr[I_BY] * wr[I_BY] + wr[I_BZ] * wr[I_BZ];
-  const double cl = cfast<D>(wl, rcp64(rl), b2l, P);
-  const double cr = cfast<D>(wr, rcp64(rr), b2r, P);
-  const double vnl = wl[1 + D], vnr = wr[1 + D];
-  const double sl = fmin(vnl - cl, vnr - cr);
-  const double sr = fmax(vnl + cl, vnr + cr);
-  const double inv = rcp64(sr - sl);
-  const double slsr = sl * sr;
-  const bool use_l = sl >= 0.0, use_r = sr <= 0.0;
-  auto hll = [&](double ul, double ur, double fl, double fr) {
-    const double h = (sr * fl - sl * fr + slsr * (ur - ul)) * inv;
+  const R rl = wl[I_RHO], rr = wr[I_RHO];
+  const R b2l = wl[I_BX] * wl[I_BX] + wl[I_BY] * wl[I_BY] + wl[I_BZ] * wl[I_BZ];
+  const R b2r = wr[I_BX] * wr[I_BX] + wr[I_BY] * wr[I_BY] + wr[I_BZ] * wr[I_BZ];
+  const R cl = cfast<D>(wl, rcp_(rl), b2l, gamma);
+  const R cr = cfast<D>(wr, rcp_(rr), b2r, gamma);
+  const R vnl = wl[1 + D], vnr = wr[1 + D];
+  const R sl = fmin(vnl - cl, vnr - cr);
+  const R sr = fmax(vnl + cl, vnr + cr);
+  const R inv = rcp_(sr - sl);
+  const R slsr = sl * sr;
+  const bool use_l = sl >= R(0), use_r = sr <= R(0);
+  auto hll = [&](R ul, R ur, R fl, R fr) {
+    const R h = (sr * fl - sl * fr + slsr * (ur - ul)) * inv;
     return use_l ? fl : (use_r ? fr : h);
   };
   // mass
-  const double mnl = rl * vnl, mnr = rr * vnr;
+  const R mnl = rl * vnl, mnr = rr * vnr;
   F[I_RHO] = hll(rl, rr, mnl, mnr);
   // energy
   {
-    const double v2l = wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3];
-    const double v2r = wr[1] * wr[1] + wr[2] * wr[2] + wr[3] * wr[3];
-    const double el = wl[4] * P.inv_gm1 + 0.5 * rl * v2l + 0.5 * b2l;
-    const double er = wr[4] * P.inv_gm1 + 0.5 * rr * v2r + 0.5 * b2r;
-    const double vbl = wl[1] * wl[I_BX] + wl[2] * wl[I_BY] + wl[3] * wl[I_BZ];
-    const double vbr = wr[1] * wr[I_BX] + wr[2] * wr[I_BY] + wr[3] * wr[I_BZ];
-    const double ptl = wl[4] + 0.5 * b2l, ptr = wr[4] + 0.5 * b2r;
+    const R v2l = wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3];
+    const R v2r = wr[1] * wr[1] + wr[2] * wr[2] + wr[3] * wr[3];
+    const R el = wl[4] * inv_gm1 + R(0.5) * rl * v2l + R(0.5) * b2l;
+    const R er = wr[4] * inv_gm1 + R(0.5) * rr * v2r + R(0.5) * b2r;
+    const R vbl = wl[1] * wl[I_BX] + wl[2] * wl[I_BY] + wl[3] * wl[I_BZ];
+    const R vbr = wr[1] * wr[I_BX] + wr[2] * wr[I_BY] + wr[3] * wr[I_BZ];
+    const R ptl = wl[4] + R(0.5) * b2l, ptr = wr[4] + R(0.5) * b2r;
     F[I_EN] = hll(el, er, (el + ptl) * vnl - bn * vbl, (er + ptr) * vnr - bn * vbr);
     // momentum
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double ml = rl * wl[1 + c], mr = rr * wr[1 + c];
-      double fl = ml * vnl - wl[I_BX + c] * bn;
-      double fr = mr * vnr - wr[I_BX + c] * bn;
+      const R ml = rl * wl[1 + c], mr = rr * wr[1 + c];
+      R fl = ml * vnl - wl[I_BX + c] * bn;
+      R fr = mr * vnr - wr[I_BX + c] * bn;
       if (c == D) {
         fl += ptl;
         fr += ptr;
@@ -201,16 +215,17 @@ __device__ __forceinline__ void hll_glm_flux(double wl[NV], double wr[NV], doubl
 // Reconstructed left/right states at the face between cells a (=i) and
 // b (=i+1) from four primitive cells m (=i-1), a, b, p (=i+2), with the
 // first-order fallback when rho or p is not positive on either side.
-__device__ __forceinline__ void reconstruct_face(const double wm[NV], const double wa[NV], const double wb[NV],
-                                                 const double wp[NV], double wl[NV], double wr[NV]) {
+template <class R>
+__device__ __forceinline__ void reconstruct_face(const R wm[NV], const R wa[NV], const R wb[NV], const R wp[NV],
+                                                 R wl[NV], R wr[NV]) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    const double sa = vl_slope(wa[q] - wm[q], wb[q] - wa[q]);
-    const double sb = vl_slope(wb[q] - wa[q], wp[q] - wb[q]);
-    wl[q] = wa[q] + 0.5 * sa;
-    wr[q] = wb[q] - 0.5 * sb;
+    const R sa = vl_slope(wa[q] - wm[q], wb[q] - wa[q]);
+    const R sb = vl_slope(wb[q] - wa[q], wp[q] - wb[q]);
+    wl[q] = wa[q] + R(0.5) * sa;
+    wr[q] = wb[q] - R(0.5) * sb;
   }
-  const bool ok = (wl[I_RHO] > 0.0) && (wl[4] > 0.0) && (wr[I_RHO] > 0.0) && (wr[4] > 0.0);
+  const bool ok = (wl[I_RHO] > R(0)) && (wl[4] > R(0)) && (wr[I_RHO] > R(0)) && (wr[4] > R(0));
   if (!ok) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -218,6 +233,49 @@ __device__ __forceinline__ void reconstruct_face(const double wm[NV], const doub
       wr[q] = wb[q];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Slot storage policies.  A slot is [block][...] with pc padded cells per
+// block.  FP64: 9 double arrays.  Mixed: 8 float arrays (rho, m_x, m_y, m_z,
+// B_x, B_y, B_z, psi) then one double array (e).  Values move as double.
+
+struct StoreF64 {
+  using R = double;  // face arithmetic type
+  static constexpr int kBytesPerCell = 72;
+  static constexpr int kWavesPerEU = 2;  // fused-stage occupancy target
+  __device__ static double ld(const void* blk, int q, long c, long pc) {
+    return static_cast<const double*>(blk)[q * pc + c];
+  }
+  __device__ static void st(void* blk, int q, long c, long pc, double v) {
+    static_cast<double*>(blk)[q * pc + c] = v;
+  }
+};
+
+struct StoreMixed {
+  using R = float;
+  static constexpr int kBytesPerCell = 40;
+  static constexpr int kWavesPerEU = 3;
+  __device__ static int fidx(int q) { return q < I_EN ? q : q - 1; }
+  __device__ static double ld(const void* blk, int q, long c, long pc) {
+    if (q == I_EN) return reinterpret_cast<const double*>(static_cast<const char*>(blk) + 32 * pc)[c];
+    return (double)static_cast<const float*>(blk)[fidx(q) * pc + c];
+  }
+  __device__ static void st(void* blk, int q, long c, long pc, double v) {
+    if (q == I_EN)
+      reinterpret_cast<double*>(static_cast<char*>(blk) + 32 * pc)[c] = v;
+    else
+      static_cast<float*>(blk)[fidx(q) * pc + c] = (float)v;
+  }
+};
+
+template <class SP>
+__device__ __forceinline__ const void* block_ptr(const void* slot, long b, long pc) {
+  return static_cast<const char*>(slot) + b * pc * SP::kBytesPerCell;
+}
+template <class SP>
+__device__ __forceinline__ void* block_ptr(void* slot, long b, long pc) {
+  return static_cast<char*>(slot) + b * pc * SP::kBytesPerCell;
 }
 
 }  // namespace amrvac

@@ -23,9 +23,11 @@ __device__ __forceinline__ long pidx(const GridConst& G, int i, int j, int k) {
 // ---------------------------------------------------------------------------
 // ghost filling: one workgroup per (block, face) task
 
-__global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __restrict__ tasks,
-                                                   const int* __restrict__ link, const int* __restrict__ pos,
-                                                   double* __restrict__ slot, PhysConst P, FixedBC fixed) {
+template <class SP>
+__global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __restrict__ tasks, Tables T,
+                                                   void* __restrict__ slot, PhysConst P, FixedBC fixed) {
+  const int* __restrict__ link = T.link;
+  const int* __restrict__ pos = T.pos;
   const int task = blockIdx.x;
   const int b = tasks[2 * task];
   const int face = tasks[2 * task + 1];
@@ -37,7 +39,8 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
   const int ncell = ng * nx * nt2;
   const int ta = d == 0 ? 1 : 0;  // first transverse axis
   const int tb = d == 2 ? 1 : 2;  // second transverse axis (z in 2D: unused)
-  double* dst = slot + (long)b * NV * G.pcells;
+  const long pc = G.pcells;
+  void* dst = block_ptr<SP>(slot, b, pc);
 
   for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
     int a, t1, t2;
@@ -58,12 +61,12 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
     const long di = pidx(G, c[0], c[1], c[2]);
 
     if (kind == LINK_SAME) {
-      const double* src = slot + (long)L[1] * NV * G.pcells;
+      const void* src = block_ptr<SP>(slot, L[1], pc);
       int s[3] = {c[0], c[1], c[2]};
       s[d] = side ? gd - nx : gd + nx;
       const long si = pidx(G, s[0], s[1], s[2]);
 #pragma unroll
-      for (int q = 0; q < NV; ++q) dst[q * G.pcells + di] = src[q * G.pcells + si];
+      for (int q = 0; q < NV; ++q) SP::st(dst, q, di, pc, SP::ld(src, q, si, pc));
     } else if (kind == LINK_FINE) {
       // restriction: fine cells under this coarse ghost cell, all in one
       // fine leaf (chosen by the transverse half)
@@ -76,15 +79,15 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
         ob = (2 * c[tb]) >= nx ? 1 : 0;
         fc[tb] = 2 * c[tb] - ob * nx;
       }
-      const double* src = slot + (long)L[1 + ob * 2 + oa] * NV * G.pcells;
+      const void* src = block_ptr<SP>(slot, L[1 + ob * 2 + oa], pc);
       if (G.ndim == 2) {
         const long i00 = pidx(G, fc[0], fc[1], 0), i10 = pidx(G, fc[0] + 1, fc[1], 0);
         const long i01 = pidx(G, fc[0], fc[1] + 1, 0), i11 = pidx(G, fc[0] + 1, fc[1] + 1, 0);
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          const double* s = src + q * G.pcells;
-          dst[q * G.pcells + di] = ((s[i00] + s[i10]) + (s[i01] + s[i11])) * 0.25;
-        }
+        for (int q = 0; q < NV; ++q)
+          SP::st(dst, q, di, pc,
+                 ((SP::ld(src, q, i00, pc) + SP::ld(src, q, i10, pc)) +
+                  (SP::ld(src, q, i01, pc) + SP::ld(src, q, i11, pc))) * 0.25);
       } else {
         long ix[2][2][2];
 #pragma unroll
@@ -95,10 +98,10 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
             for (int aa = 0; aa < 2; ++aa) ix[e][bb][aa] = pidx(G, fc[0] + aa, fc[1] + bb, fc[2] + e);
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-          const double* s = src + q * G.pcells;
-          dst[q * G.pcells + di] = (((s[ix[0][0][0]] + s[ix[0][0][1]]) + (s[ix[0][1][0]] + s[ix[0][1][1]])) +
-                                    ((s[ix[1][0][0]] + s[ix[1][0][1]]) + (s[ix[1][1][0]] + s[ix[1][1][1]]))) *
-                                   0.125;
+          auto v = [&](int e, int bb, int aa) { return SP::ld(src, q, ix[e][bb][aa], pc); };
+          SP::st(dst, q, di, pc,
+                 (((v(0, 0, 0) + v(0, 0, 1)) + (v(0, 1, 0) + v(0, 1, 1))) +
+                  ((v(1, 0, 0) + v(1, 0, 1)) + (v(1, 1, 0) + v(1, 1, 1)))) * 0.125);
         }
       }
     } else if (kind == LINK_PHYS) {
@@ -109,7 +112,7 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
         for (int q = 0; q < NV; ++q) w[q] = fixed.prim[d][side][q];
         prim_to_cons(w, u, P);
 #pragma unroll
-        for (int q = 0; q < NV; ++q) dst[q * G.pcells + di] = u[q];
+        for (int q = 0; q < NV; ++q) SP::st(dst, q, di, pc, u[q]);
       } else {
         int s[3] = {c[0], c[1], c[2]};
         if (bc == 1)
@@ -119,19 +122,18 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
         const long si = pidx(G, s[0], s[1], s[2]);
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-          double v = dst[q * G.pcells + si];
+          double v = SP::ld(dst, q, si, pc);
           if (bc == 2 && (q == I_MX + d || q == I_BX + d)) v = -v;
-          dst[q * G.pcells + di] = v;
+          SP::st(dst, q, di, pc, v);
         }
       }
     } else {  // LINK_COARSE: conservative minmod-limited linear prolongation
       const int cb = L[1];
-      const int lev = L[2];
-      const double* src = slot + (long)cb * NV * G.pcells;
+      const void* src = block_ptr<SP>(slot, cb, pc);
       int lc[3] = {0, 0, 0};
       int odd[3] = {0, 0, 0};
       for (int ax = 0; ax < G.ndim; ++ax) {
-        const long n = ((long)G.base[ax] << (lev - 1)) * nx;
+        const long n = T.wrap[3 * b + ax];
         long g = (long)pos[3 * b + ax] * nx + c[ax];
         g = (g + n) % n;
         odd[ax] = (int)(g & 1);
@@ -148,14 +150,13 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
       }
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        const double* s = src + q * G.pcells;
-        const double uc = s[i0];
+        const double uc = SP::ld(src, q, i0, pc);
         double r = uc;
         for (int ax = 0; ax < G.ndim; ++ax) {
           const double sg = odd[ax] ? 0.25 : -0.25;
-          r = r + sg * minmod2(uc - s[im[ax]], s[ip[ax]] - uc);
+          r = r + sg * minmod2(uc - SP::ld(src, q, im[ax], pc), SP::ld(src, q, ip[ax], pc) - uc);
         }
-        dst[q * G.pcells + di] = r;
+        SP::st(dst, q, di, pc, r);
       }
     }
   }
@@ -238,7 +239,7 @@ __global__ void __launch_bounds__(256) k_flux(GridConst G, const double* __restr
   double wl[NV], wr[NV], F[NV];
   reconstruct_face(wm, wa, wb, wp, wl, wr);
   const double ch = *ch_dev;
-  hll_glm_flux<D>(wl, wr, ch, 0.5 / ch, P, F);
+  hll_glm_flux<D, double>(wl, wr, ch, 0.5 / ch, P.gamma, P.inv_gm1, F);
   double* out = flux + (long)b * NV * G.nfaces + fi;
 #pragma unroll
   for (int q = 0; q < NV; ++q) out[(long)q * G.nfaces] = F[q];
@@ -291,8 +292,8 @@ __global__ void __launch_bounds__(256) k_reflux(GridConst G, const int* __restri
 }
 
 // flux-difference update + SSPRK combination: one thread per interior cell
-__global__ void __launch_bounds__(256) k_update(GridConst G, LevelConst Lc, const int* __restrict__ level,
-                                               const double* __restrict__ in, const double* base,
+__global__ void __launch_bounds__(256) k_update(GridConst G, Tables T, const double* __restrict__ in,
+                                               const double* base,
                                                double* out, double w, FluxPtrs flux,
                                                const double* __restrict__ dt_dev,
                                                const double* __restrict__ kappa_dev) {
@@ -303,7 +304,6 @@ __global__ void __launch_bounds__(256) k_update(GridConst G, LevelConst Lc, cons
   const int c = (int)(gid - (long)b * G.icells);
   const int nx = G.nx;
   const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
-  const int lev = level[b];
   const long pc = pidx(G, i, j, k);
   const double dt = *dt_dev, kappa = *kappa_dev;
   double L[NV];
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(256) k_update(GridConst G, LevelConst Lc, cons
     else { f = k; t1 = i; t2 = j; }
     const double* F = flux.f[d] + (long)b * NV * G.nfaces;
     const int lo = face_index(G, d, f, t1, t2), hi = face_index(G, d, f + 1, t1, t2);
-    const double idx = Lc.inv_dx[lev][d];
+    const double idx = T.inv_dx[3 * b + d];
 #pragma unroll
     for (int q = 0; q < NV; ++q) L[q] = L[q] + (F[(long)q * G.nfaces + hi] - F[(long)q * G.nfaces + lo]) * idx;
   }
@@ -342,11 +342,12 @@ __global__ void __launch_bounds__(256) k_update(GridConst G, LevelConst Lc, cons
 // coarse face flux used by the stage with the pairwise mean of the fine face
 // fluxes, i.e. out += w*dt*dL.  Both fluxes are recomputed from the stage
 // input (ghosts filled) exactly as the stage kernels compute them.
-template <int D>
-__device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const double* __restrict__ S, int f, int t1,
-                                                    int t2, double ch, double hic, const PhysConst& P,
-                                                    double F[NV]) {
-  double w4[4][NV];
+template <int D, class SP>
+__device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const void* __restrict__ S, int f, int t1,
+                                                    int t2, typename SP::R ch, typename SP::R hic,
+                                                    const PhysConst& P, typename SP::R F[NV]) {
+  using R = typename SP::R;
+  R w4[4][NV];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int a = f - 2 + s;
@@ -356,20 +357,21 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const do
     else c = pidx(G, t1, t2, a);
     double u[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) u[q] = S[q * G.pcells + c];
+    for (int q = 0; q < NV; ++q) u[q] = SP::ld(S, q, c, G.pcells);
     (void)cons_to_prim(u, w4[s], P);
   }
-  double wl[NV], wr[NV];
+  R wl[NV], wr[NV];
   reconstruct_face(w4[0], w4[1], w4[2], w4[3], wl, wr);
-  hll_glm_flux<D>(wl, wr, ch, hic, P, F);
+  hll_glm_flux<D, R>(wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
 }
 
-template <int D>
-__global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, LevelConst Lc, const int* __restrict__ level,
+template <int D, class SP>
+__global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, JobScalars J,
                                                        const int* __restrict__ tasks, int ntasks,
-                                                       const int* __restrict__ link, const double* __restrict__ in,
-                                                       double* out, double w, const double* __restrict__ dt_dev,
-                                                       const double* __restrict__ ch_dev, PhysConst P) {
+                                                       const void* __restrict__ in, void* out, double w,
+                                                       PhysConst P) {
+  const int* __restrict__ link = T.link;
+  using R = typename SP::R;
   const int nx = G.nx;
   const int per = G.ndim == 3 ? nx * nx : nx;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -381,60 +383,65 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, LevelConst 
   const int side = face & 1;
   const int* L = link + ((long)b * 6 + face) * LINK_INTS;
   const int t1 = t % nx, t2 = G.ndim == 3 ? t / nx : 0;
-  const double ch = *ch_dev, hic = 0.5 / ch, dt = *dt_dev;
-  double Fc[NV], Ff[NV], v[2][2][NV];
-  face_flux_from_slot<D>(G, in + (long)b * NV * G.pcells, side ? nx : 0, t1, t2, ch, hic, P, Fc);
+  const int job = T.job[b];
+  const double dt = J.dt[job];
+  const R ch = (R)J.ch[job], hic = (R)(0.5 / J.ch[job]);
+  const long pc = G.pcells;
+  R Fc[NV], Ff[NV], v[2][2][NV];
+  face_flux_from_slot<D, SP>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, Fc);
   const int ne = G.ndim == 3 ? 2 : 1;
   for (int e = 0; e < ne; ++e)
     for (int a = 0; a < 2; ++a) {
       const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
       const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
       const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
-      face_flux_from_slot<D>(G, in + (long)fb * NV * G.pcells, side ? 0 : nx, g1 - o1 * nx,
-                             G.ndim == 3 ? g2 - o2 * nx : 0, ch, hic, P, v[e][a]);
+      face_flux_from_slot<D, SP>(G, block_ptr<SP>(in, fb, pc), side ? 0 : nx, g1 - o1 * nx,
+                                 G.ndim == 3 ? g2 - o2 * nx : 0, ch, hic, P, v[e][a]);
     }
 #pragma unroll
   for (int q = 0; q < NV; ++q)
-    Ff[q] = G.ndim == 3 ? ((v[0][0][q] + v[0][1][q]) + (v[1][0][q] + v[1][1][q])) * 0.25
-                        : (v[0][0][q] + v[0][1][q]) * 0.5;
+    Ff[q] = G.ndim == 3 ? ((v[0][0][q] + v[0][1][q]) + (v[1][0][q] + v[1][1][q])) * R(0.25)
+                        : (v[0][0][q] + v[0][1][q]) * R(0.5);
   const int cell_d = side ? nx - 1 : 0;
   long c;
   if (D == 0) c = pidx(G, cell_d, t1, t2);
   else if (D == 1) c = pidx(G, t1, cell_d, t2);
   else c = pidx(G, t1, t2, cell_d);
-  const double idx = Lc.inv_dx[level[b]][D];
-  double* o = out + (long)b * NV * G.pcells + c;
+  const double idx = T.inv_dx[3 * b + D];
+  void* o = block_ptr<SP>(out, b, pc);
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    const double dl = side ? -(Ff[q] - Fc[q]) * idx : (Ff[q] - Fc[q]) * idx;
-    o[q * G.pcells] = o[q * G.pcells] + w * dt * dl;
+    const double df = (double)Ff[q] - (double)Fc[q];
+    const double dl = side ? -df * idx : df * idx;
+    SP::st(o, q, c, pc, SP::ld(o, q, c, pc) + w * dt * dl);
   }
 }
 
 // ---------------------------------------------------------------------------
 // CFL: max over leaf interior cells of sum_d (|v_d| + c_f,d)/dx_d
 
-__global__ void __launch_bounds__(256) k_cfl(GridConst G, LevelConst Lc, const int* __restrict__ level,
-                                            const double* __restrict__ slot, PhysConst P, DevStatus* st) {
-  const long total = (long)G.nb * G.icells;
+template <class SP>
+__global__ void __launch_bounds__(256) k_cfl(GridConst G, Tables T, const void* __restrict__ slot, PhysConst P,
+                                            DevStatus* st, JobCfl C) {
+  const int b = T.order[blockIdx.x];
+  const int job = T.job[b];
+  const void* blk = block_ptr<SP>(slot, b, G.pcells);
+  const double ix = T.inv_dx[3 * b], iy = T.inv_dx[3 * b + 1], iz = T.inv_dx[3 * b + 2];
   double r = 0.0;
   int bad = 0, nan_seen = 0;
-  for (long gid = (long)blockIdx.x * blockDim.x + threadIdx.x; gid < total; gid += (long)gridDim.x * blockDim.x) {
-    const int b = (int)(gid / G.icells);
-    const int c = (int)(gid - (long)b * G.icells);
-    const int nx = G.nx;
+  const int nx = G.nx;
+  for (int c = threadIdx.x; c < (int)G.icells; c += blockDim.x) {
     const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
-    const double* u0 = slot + (long)b * NV * G.pcells + pidx(G, i, j, k);
+    const long pc = pidx(G, i, j, k);
     double u[NV], w[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) u[q] = u0[q * G.pcells];
+    for (int q = 0; q < NV; ++q) u[q] = SP::ld(blk, q, pc, G.pcells);
     bad |= cons_to_prim(u, w, P);
-    const int lev = level[b];
-    const double ri = rcp64(w[I_RHO]);
+    const double ri = rcp_(w[I_RHO]);
     const double b2 = w[I_BX] * w[I_BX] + w[I_BY] * w[I_BY] + w[I_BZ] * w[I_BZ];
-    double rate = (fabs(w[1]) + cfast<0>(w, ri, b2, P)) * Lc.inv_dx[lev][0];
-    rate = rate + (fabs(w[2]) + cfast<1>(w, ri, b2, P)) * Lc.inv_dx[lev][1];
-    if (G.ndim == 3) rate = rate + (fabs(w[3]) + cfast<2>(w, ri, b2, P)) * Lc.inv_dx[lev][2];
+    double rate = (fabs(w[1]) + cfast<0>(w, ri, b2, P.gamma)) * ix;
+    rate = rate + (fabs(w[2]) + cfast<1>(w, ri, b2, P.gamma)) * iy;
+    if (G.ndim == 3) rate = rate + (fabs(w[3]) + cfast<2>(w, ri, b2, P.gamma)) * iz;
     if (isnan(rate))
       nan_seen = 1;
     else
@@ -449,62 +456,74 @@ __global__ void __launch_bounds__(256) k_cfl(GridConst G, LevelConst Lc, const i
   if (threadIdx.x == 0) {
     double m = smax[0];
     for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, smax[q]);
-    atomicMax(&st->rate_bits, (unsigned long long)__double_as_longlong(m));
+    atomicMax(&C.rate_bits[job], (unsigned long long)__double_as_longlong(m));
   }
   if (bad) atomicOr(&st->flags, (unsigned)bad);
-  if (nan_seen) atomicOr(&st->cfl_nan, 1u);
+  if (nan_seen) atomicOr(&C.nan[job], 1u);
 }
 
-__global__ void k_cfl_finalize(LevelConst Lc, DevStatus* st, double* dt_dev, double* ch_dev, double* kappa_dev) {
-  if (threadIdx.x != 0) return;
-  const double rmax = __longlong_as_double((long long)st->rate_bits);
-  const unsigned nan_seen = st->cfl_nan;
-  st->rate_bits = 0ull;
-  st->cfl_nan = 0u;
+// dt = C / max rate, c_h = C / (dt sum_d 1/dx_d), kappa = alpha c_h / min dx
+// (finest level of the job); one thread per job slot, unused slots skipped.
+__global__ void k_cfl_finalize(JobCfl C, DevStatus* st) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= C.njobs) return;
+  const double* g = C.geom + 4 * j;
+  if (!(g[2] > 0.0)) return;
+  const double rmax = __longlong_as_double((long long)C.rate_bits[j]);
+  const unsigned nan_seen = C.nan[j];
+  C.rate_bits[j] = 0ull;
+  C.nan[j] = 0u;
   double dt = 0.0, ch = 0.0, kappa = 0.0;
   if (nan_seen || !(rmax > 0.0) || !isfinite(rmax)) {
-    st->flags |= F_BAD_DT;
+    atomicOr(&st->flags, (unsigned)F_BAD_DT);
   } else {
-    dt = Lc.cfl / rmax;
-    ch = Lc.cfl / (dt * Lc.sum_inv_dx_fin);
-    kappa = Lc.glm_alpha * ch / Lc.min_dx_fin;
+    dt = g[2] / rmax;
+    ch = g[2] / (dt * g[0]);
+    kappa = g[3] * ch / g[1];
   }
-  *dt_dev = dt;
-  *ch_dev = ch;
-  *kappa_dev = kappa;
-  st->last_dt = dt;
+  C.dt[j] = dt;
+  C.ch[j] = ch;
+  C.kappa[j] = kappa;
+  if (j == 0) st->last_dt = dt;
 }
 
 // ---------------------------------------------------------------------------
 // conversions
 
-__global__ void __launch_bounds__(256) k_set_prim(GridConst G, const double* __restrict__ prim, double* __restrict__ slot,
-                                                 PhysConst P) {
+template <class SP>
+__global__ void __launch_bounds__(256) k_set_prim(GridConst G, int first, int count, const double* __restrict__ prim,
+                                                 void* __restrict__ slot, PhysConst P) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)G.nb * G.icells) return;
-  const int b = (int)(gid / G.icells);
-  const int c = (int)(gid - (long)b * G.icells);
+  if (gid >= (long)count * G.icells) return;
+  const int lb = (int)(gid / G.icells);
+  const int b = first + lb;
+  const int c = (int)(gid - (long)lb * G.icells);
   const int nx = G.nx;
   const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
   double w[NV], u[NV];
 #pragma unroll
-  for (int q = 0; q < NV; ++q) w[q] = prim[((long)b * NV + q) * G.icells + c];
+  for (int q = 0; q < NV; ++q) w[q] = prim[((long)lb * NV + q) * G.icells + c];
   prim_to_cons(w, u, P);
-  double* o = slot + (long)b * NV * G.pcells + pidx(G, i, j, k);
+  void* o = block_ptr<SP>(slot, b, G.pcells);
+  const long c0 = pidx(G, i, j, k);
 #pragma unroll
-  for (int q = 0; q < NV; ++q) o[q * G.pcells] = u[q];
+  for (int q = 0; q < NV; ++q) SP::st(o, q, c0, G.pcells, u[q]);
 }
 
-__global__ void __launch_bounds__(256) k_get_cons(GridConst G, const double* __restrict__ slot, double* __restrict__ cons) {
+template <class SP>
+__global__ void __launch_bounds__(256) k_get_cons(GridConst G, int first, int count, const void* __restrict__ slot,
+                                                 double* __restrict__ cons) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)G.nb * G.icells) return;
-  const int b = (int)(gid / G.icells);
-  const int c = (int)(gid - (long)b * G.icells);
+  if (gid >= (long)count * G.icells) return;
+  const int lb = (int)(gid / G.icells);
+  const int b = first + lb;
+  const int c = (int)(gid - (long)lb * G.icells);
   const int nx = G.nx;
   const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
-  const double* s = slot + (long)b * NV * G.pcells + pidx(G, i, j, k);
+  const void* s = block_ptr<SP>(slot, b, G.pcells);
+  const long c0 = pidx(G, i, j, k);
 #pragma unroll
-  for (int q = 0; q < NV; ++q) cons[((long)b * NV + q) * G.icells + c] = s[q * G.pcells];
+  for (int q = 0; q < NV; ++q) cons[((long)lb * NV + q) * G.icells + c] = SP::ld(s, q, c0, G.pcells);
 }
 
 __global__ void k_reset_status(DevStatus* st) {
@@ -520,10 +539,13 @@ inline unsigned nblocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / b
 
 }  // namespace
 
-hipError_t launch_fill_faces(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const int* link,
-                             const int* pos, void* slot, const PhysConst& P, const FixedBC& fixed) {
+hipError_t launch_fill_faces(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const Tables& T,
+                             void* slot, const PhysConst& P, const FixedBC& fixed) {
   if (ntasks <= 0) return hipSuccess;
-  k_fill_faces<<<ntasks, 256, 0, s>>>(G, tasks, link, pos, static_cast<double*>(slot), P, fixed);
+  if (G.precision == 0)
+    k_fill_faces<StoreF64><<<ntasks, 256, 0, s>>>(G, tasks, T, slot, P, fixed);
+  else
+    k_fill_faces<StoreMixed><<<ntasks, 256, 0, s>>>(G, tasks, T, slot, P, fixed);
   return hipGetLastError();
 }
 
@@ -547,60 +569,73 @@ hipError_t launch_flux(hipStream_t s, const GridConst& G, int dir, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_reflux(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const int* link,
+hipError_t launch_reflux(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const Tables& T,
                          FluxPtrs flux) {
   if (ntasks <= 0) return hipSuccess;
   const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
-  k_reflux<<<nblocks_for(ntasks * per, 256), 256, 0, s>>>(G, tasks, ntasks, link, flux);
+  k_reflux<<<nblocks_for(ntasks * per, 256), 256, 0, s>>>(G, tasks, ntasks, T.link, flux);
   return hipGetLastError();
 }
 
-hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const LevelConst& L, const int* level,
-                                 const int* tasks, int ntasks, const int* link, const void* in, void* out, double w,
-                                 const double* dt_dev, const double* ch_dev, const PhysConst& P) {
+hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
+                                 const int* tasks, int ntasks, const void* in, void* out, double w,
+                                 const PhysConst& P) {
   if (ntasks <= 0) return hipSuccess;
   const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
   const unsigned nbk = nblocks_for(ntasks * per, 256);
-  const double* pin = static_cast<const double*>(in);
-  double* pout = static_cast<double*>(out);
-  k_reflux_correct<0><<<nbk, 256, 0, s>>>(G, L, level, tasks, ntasks, link, pin, pout, w, dt_dev, ch_dev, P);
-  k_reflux_correct<1><<<nbk, 256, 0, s>>>(G, L, level, tasks, ntasks, link, pin, pout, w, dt_dev, ch_dev, P);
-  if (G.ndim == 3)
-    k_reflux_correct<2><<<nbk, 256, 0, s>>>(G, L, level, tasks, ntasks, link, pin, pout, w, dt_dev, ch_dev, P);
+  if (G.precision == 0) {
+    k_reflux_correct<0, StoreF64><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
+    k_reflux_correct<1, StoreF64><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
+    if (G.ndim == 3) k_reflux_correct<2, StoreF64><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
+  } else {
+    k_reflux_correct<0, StoreMixed><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
+    k_reflux_correct<1, StoreMixed><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
+    if (G.ndim == 3) k_reflux_correct<2, StoreMixed><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_update(hipStream_t s, const GridConst& G, const LevelConst& L, const int* level, const void* in,
-                         const void* base, void* out, double w, FluxPtrs flux, const double* dt_dev,
-                         const double* kappa_dev) {
+hipError_t launch_update(hipStream_t s, const GridConst& G, const Tables& T, const void* in, const void* base,
+                         void* out, double w, FluxPtrs flux, const double* dt_dev, const double* kappa_dev) {
   const long n = (long)G.nb * G.icells;
-  k_update<<<nblocks_for(n, 256), 256, 0, s>>>(G, L, level, static_cast<const double*>(in),
-                                                static_cast<const double*>(base), static_cast<double*>(out), w,
-                                                flux, dt_dev, kappa_dev);
+  k_update<<<nblocks_for(n, 256), 256, 0, s>>>(G, T, static_cast<const double*>(in), static_cast<const double*>(base),
+                                                static_cast<double*>(out), w, flux, dt_dev, kappa_dev);
   return hipGetLastError();
 }
 
-hipError_t launch_cfl(hipStream_t s, const GridConst& G, const LevelConst& L, const int* level, const void* slot,
-                      const PhysConst& P, DevStatus* st, double* dt_dev, double* ch_dev, double* kappa_dev) {
-  const long n = (long)G.nb * G.icells;
-  unsigned nbk = nblocks_for(n, 256);
-  if (nbk > 4096) nbk = 4096;
-  k_cfl<<<nbk, 256, 0, s>>>(G, L, level, static_cast<const double*>(slot), P, st);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_cfl_finalize<<<1, 64, 0, s>>>(L, st, dt_dev, ch_dev, kappa_dev);
+hipError_t launch_cfl(hipStream_t s, const GridConst& G, const Tables& T, const void* slot, const PhysConst& P,
+                      DevStatus* st, const JobCfl& C) {
+  if (T.nactive > 0) {
+    if (G.precision == 0)
+      k_cfl<StoreF64><<<T.nactive, 256, 0, s>>>(G, T, slot, P, st, C);
+    else
+      k_cfl<StoreMixed><<<T.nactive, 256, 0, s>>>(G, T, slot, P, st, C);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  k_cfl_finalize<<<nblocks_for(C.njobs, 64), 64, 0, s>>>(C, st);
   return hipGetLastError();
 }
 
-hipError_t launch_set_prim(hipStream_t s, const GridConst& G, const double* prim, void* slot, const PhysConst& P) {
-  const long n = (long)G.nb * G.icells;
-  k_set_prim<<<nblocks_for(n, 256), 256, 0, s>>>(G, prim, static_cast<double*>(slot), P);
+hipError_t launch_set_prim(hipStream_t s, const GridConst& G, int first, int count, const double* prim, void* slot,
+                           const PhysConst& P) {
+  const long n = (long)count * G.icells;
+  if (n <= 0) return hipSuccess;
+  if (G.precision == 0)
+    k_set_prim<StoreF64><<<nblocks_for(n, 256), 256, 0, s>>>(G, first, count, prim, slot, P);
+  else
+    k_set_prim<StoreMixed><<<nblocks_for(n, 256), 256, 0, s>>>(G, first, count, prim, slot, P);
   return hipGetLastError();
 }
 
-hipError_t launch_get_cons(hipStream_t s, const GridConst& G, const void* slot, double* cons) {
-  const long n = (long)G.nb * G.icells;
-  k_get_cons<<<nblocks_for(n, 256), 256, 0, s>>>(G, static_cast<const double*>(slot), cons);
+hipError_t launch_get_cons(hipStream_t s, const GridConst& G, int first, int count, const void* slot,
+                           double* cons) {
+  const long n = (long)count * G.icells;
+  if (n <= 0) return hipSuccess;
+  if (G.precision == 0)
+    k_get_cons<StoreF64><<<nblocks_for(n, 256), 256, 0, s>>>(G, first, count, slot, cons);
+  else
+    k_get_cons<StoreMixed><<<nblocks_for(n, 256), 256, 0, s>>>(G, first, count, slot, cons);
   return hipGetLastError();
 }
 

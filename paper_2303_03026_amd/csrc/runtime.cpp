@@ -1,6 +1,13 @@
-// Host runtime of the C ABI declared in include/amrvac.h: validates the block
-// hierarchy, builds the face-neighbour and ghost-task tables, owns scratch
-// memory and the per-step HIP graph, and enqueues the kernels.
+// Host runtime of the C ABI declared in include/amrvac.h.
+//
+// A context owns a pool of block places (the caller's slots hold the data)
+// and a set of jobs, each a 2:1-nested leaf-block hierarchy occupying a
+// contiguous run of pool places.  For every job the runtime validates the
+// hierarchy, builds face-neighbour links and ghost-task lists, and keeps
+// per-block tables (level, job, spacing, links) and per-job CFL geometry on
+// the device.  A single-job context (amrvac_init_blocks) is one job over
+// the whole pool; a batch context (amrvac_batch_create) admits and retires
+// jobs between steps and advances all active jobs together.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,42 +26,6 @@
 
 using namespace amrvac;
 
-struct amrvac_ctx {
-  amrvac_grid_desc g{};
-  GridConst G{};
-  LevelConst L{};
-  PhysConst P{};
-  FixedBC fixed{};
-  hipStream_t stream = nullptr;
-  int device = 0;
-  std::vector<void*> slots;
-  int path = AMRVAC_PATH_PLAIN;
-  // device tables
-  int* d_level = nullptr;
-  int* d_pos = nullptr;
-  int* d_link = nullptr;
-  int* d_tasks_fill = nullptr;   // every copy/restrict/physical face (plain path)
-  int n_tasks_fill = 0;
-  int* d_tasks_fill_fused = nullptr;  // faces the fused stage does not read in place
-  int n_tasks_fill_fused = 0;
-  int* d_order = nullptr;  // Morton order of the blocks (fused stage scheduling)
-  int* d_tasks_prolong = nullptr;
-  int n_tasks_prolong = 0;
-  int* d_tasks_reflux = nullptr;
-  int n_tasks_reflux = 0;
-  // scratch
-  double* d_prim = nullptr;
-  double* d_flux[3] = {nullptr, nullptr, nullptr};
-  DevStatus* d_status = nullptr;
-  double* d_scalars = nullptr;  // dt, c_h, kappa for amrvac_advance
-  // graph of one step
-  hipGraphExec_t graph_exec = nullptr;
-  hipGraph_t graph = nullptr;
-  int graph_stages = 0;
-  int graph_path = -1;
-  std::string err;
-};
-
 namespace {
 
 struct KeyL {
@@ -63,28 +34,31 @@ struct KeyL {
   bool operator<(const KeyL& o) const { return std::tie(l, i, j, k) < std::tie(o.l, o.i, o.j, o.k); }
 };
 
-int fail(amrvac_ctx* c, int code, const std::string& msg) {
-  if (c) c->err = msg;
-  return code;
-}
+// Validated tables of one job's hierarchy (pool ids already offset).
+struct JobBuild {
+  std::string err;
+  int finest = 1;
+  std::vector<int> level, link, pos, wrap, order_local;
+  std::vector<double> invdx;
+  std::vector<int> tfill, tfused, tprol, trefl;  // (pool block, face) pairs
+  double geom[4] = {0, 0, 0, 0};  // sum_d 1/dx_d (finest), min_d dx_d (finest), cfl, glm_alpha
+};
 
-#define HIP_TRY(ctx, expr)                                                            \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess)                                                             \
-      return fail((ctx), AMRVAC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-thread_local std::string g_init_err;
+// Per-job host record.
+struct JobRec {
+  bool used = false;
+  int first = 0;
+  int nb = 0;
+  int steps_left = 0;
+  int steps_done = 0;
+  JobBuild t;
+};
 
 int check_desc(const amrvac_grid_desc* g, std::string* why) {
   if (!g) { *why = "null descriptor"; return AMRVAC_E_ARG; }
   if (g->ndim != 2 && g->ndim != 3) { *why = "ndim must be 2 or 3"; return AMRVAC_E_ARG; }
   if (g->nghost != 2) { *why = "nghost must be 2 (van Leer stencil)"; return AMRVAC_E_ARG; }
-  if (g->block_nx < 4 || g->block_nx > 16 || (g->block_nx & 1)) {
-    *why = "block_nx must be even, 4..16";
-    return AMRVAC_E_ARG;
-  }
+  if (g->block_nx < 4 || g->block_nx > 16 || (g->block_nx & 1)) { *why = "block_nx must be even, 4..16"; return AMRVAC_E_ARG; }
   if (g->precision != AMRVAC_FP64 && g->precision != AMRVAC_FP32_MIXED) { *why = "bad precision"; return AMRVAC_E_ARG; }
   for (int d = 0; d < g->ndim; ++d) {
     if (g->base_blocks[d] < 1) { *why = "base_blocks must be >= 1"; return AMRVAC_E_ARG; }
@@ -102,31 +76,452 @@ int check_desc(const amrvac_grid_desc* g, std::string* why) {
   return AMRVAC_OK;
 }
 
-long long slot_bytes_of(const amrvac_grid_desc* g, int nb) {
+long long slot_bytes_of(const amrvac_grid_desc* g, long nb) {
   const long pn = g->block_nx + 2 * g->nghost;
   const long pc = pn * pn * (g->ndim == 3 ? pn : 1);
   const long per = g->precision == AMRVAC_FP64 ? 72 : 40;
   return (long long)nb * pc * per;
 }
 
-static int free_all(amrvac_ctx* c) {
-  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  void* ptrs[] = {c->d_level, c->d_pos, c->d_link, c->d_tasks_fill, c->d_tasks_fill_fused, c->d_order,
-                  c->d_tasks_prolong, c->d_tasks_reflux,
-                  c->d_prim, c->d_flux[0], c->d_flux[1], c->d_flux[2], c->d_status, c->d_scalars};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+// Validate a job's leaf blocks and build its tables with pool ids starting
+// at `first`.  Host only: no device call.
+int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ijk, int first, JobBuild* out) {
+  JobBuild& J = *out;
+  const int ndim = g->ndim, nx = g->block_nx;
+  std::map<KeyL, int> leaf;
+  std::set<KeyL> refined;
+  double vol = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const int l = level[b];
+    if (l < 1 || l > MAXLEV) { J.err = "level out of range 1..12"; return AMRVAC_E_ARG; }
+    long p[3] = {ijk[3 * b], ijk[3 * b + 1], ndim == 3 ? ijk[3 * b + 2] : 0};
+    for (int d = 0; d < ndim; ++d)
+      if (p[d] < 0 || p[d] >= ((long)g->base_blocks[d] << (l - 1))) { J.err = "block outside the domain"; return AMRVAC_E_ARG; }
+    if (!leaf.emplace(KeyL{l, p[0], p[1], p[2]}, b).second) { J.err = "duplicate block"; return AMRVAC_E_ARG; }
+    J.finest = std::max(J.finest, l);
+    vol += std::ldexp(1.0, -ndim * (l - 1));
+    for (int m = l - 1; m >= 1; --m) {
+      for (int d = 0; d < 3; ++d) p[d] >>= 1;
+      refined.insert(KeyL{m, p[0], p[1], p[2]});
+    }
+  }
+  for (const auto& kv : leaf)
+    if (refined.count(kv.first)) { J.err = "blocks overlap (a leaf is also refined)"; return AMRVAC_E_ARG; }
+  const double nbase = (double)g->base_blocks[0] * g->base_blocks[1] * (ndim == 3 ? g->base_blocks[2] : 1);
+  if (std::fabs(vol - nbase) > 1e-9 * nbase) { J.err = "blocks do not tile the domain"; return AMRVAC_E_ARG; }
+
+  auto nblk = [&](int l, int d) -> long { return d < ndim ? ((long)g->base_blocks[d] << (l - 1)) : 1; };
+  auto periodic = [&](int d) { return g->bc_lo[d] == AMRVAC_BC_PERIODIC; };
+  // 2:1 nesting over faces, edges and corners: every slot next to a leaf of
+  // level l is a leaf, refined into leaves, or inside a leaf of level l-1.
+  for (const auto& kv : leaf) {
+    const int l = kv.first.l;
+    const long p[3] = {kv.first.i, kv.first.j, kv.first.k};
+    for (int oz = (ndim == 3 ? -1 : 0); oz <= (ndim == 3 ? 1 : 0); ++oz)
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          long q[3] = {p[0] + ox, p[1] + oy, p[2] + oz};
+          bool skip = false;
+          for (int d = 0; d < ndim; ++d)
+            if (q[d] < 0 || q[d] >= nblk(l, d)) {
+              if (periodic(d)) q[d] = (q[d] + nblk(l, d)) % nblk(l, d);
+              else skip = true;
+            }
+          if (skip) continue;
+          const KeyL k{l, q[0], q[1], q[2]};
+          if (leaf.count(k)) continue;
+          if (refined.count(k)) {
+            const long off[3] = {ox, oy, oz};
+            for (int cz = 0; cz < (ndim == 3 ? 2 : 1); ++cz)
+              for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx) {
+                  const long cc[3] = {cx, cy, cz};
+                  bool adjacent = true;
+                  for (int d = 0; d < ndim; ++d) {
+                    if (off[d] == 1 && cc[d] != 0) adjacent = false;
+                    if (off[d] == -1 && cc[d] != 1) adjacent = false;
+                  }
+                  if (!adjacent) continue;
+                  const KeyL ck{l + 1, 2 * q[0] + cx, 2 * q[1] + cy, ndim == 3 ? 2 * q[2] + cz : 0};
+                  if (!leaf.count(ck)) { J.err = "hierarchy is not 2:1 nested (finer by two)"; return AMRVAC_E_ARG; }
+                }
+            continue;
+          }
+          if (l >= 2 && leaf.count(KeyL{l - 1, q[0] >> 1, q[1] >> 1, ndim == 3 ? q[2] >> 1 : 0})) continue;
+          J.err = "hierarchy is not 2:1 nested (coarser by two)";
+          return AMRVAC_E_ARG;
+        }
+  }
+
+  J.level.assign(nb, 0);
+  J.pos.assign((size_t)nb * 3, 0);
+  J.wrap.assign((size_t)nb * 3, 1);
+  J.invdx.assign((size_t)nb * 3, 1.0);
+  J.link.assign((size_t)nb * 6 * LINK_INTS, -1);
+  for (int b = 0; b < nb; ++b) {
+    const int l = level[b];
+    J.level[b] = l;
+    const long p[3] = {ijk[3 * b], ijk[3 * b + 1], ndim == 3 ? ijk[3 * b + 2] : 0};
+    for (int d = 0; d < 3; ++d) {
+      J.pos[3 * b + d] = (int)p[d];
+      J.wrap[3 * b + d] = (int)(nblk(l, d) * nx);
+      J.invdx[3 * b + d] = d < ndim ? 1.0 / ((g->xmax[d] - g->xmin[d]) / (double)(nblk(l, d) * nx)) : 1.0;
+    }
+    for (int d = 0; d < ndim; ++d)
+      for (int side = 0; side < 2; ++side) {
+        int* Lk = &J.link[((size_t)b * 6 + d * 2 + side) * LINK_INTS];
+        long q[3] = {p[0], p[1], p[2]};
+        q[d] += side ? 1 : -1;
+        if (q[d] < 0 || q[d] >= nblk(l, d)) {
+          if (!periodic(d)) {
+            Lk[0] = LINK_PHYS;
+            Lk[1] = side ? g->bc_hi[d] : g->bc_lo[d];
+            J.tfill.push_back(first + b);
+            J.tfill.push_back(d * 2 + side);
+            continue;
+          }
+          q[d] = (q[d] + nblk(l, d)) % nblk(l, d);
+        }
+        auto it = leaf.find(KeyL{l, q[0], q[1], q[2]});
+        if (it != leaf.end()) {
+          Lk[0] = LINK_SAME;
+          Lk[1] = first + it->second;
+          J.tfill.push_back(first + b);
+          J.tfill.push_back(d * 2 + side);
+          continue;
+        }
+        if (refined.count(KeyL{l, q[0], q[1], q[2]})) {
+          Lk[0] = LINK_FINE;
+          const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
+          for (int ob = 0; ob < (ndim == 3 ? 2 : 1); ++ob)
+            for (int oa = 0; oa < 2; ++oa) {
+              long cq[3] = {2 * q[0], 2 * q[1], ndim == 3 ? 2 * q[2] : 0};
+              cq[d] += side ? 0 : 1;
+              cq[ta] += oa;
+              if (ndim == 3) cq[tb] += ob;
+              auto ci = leaf.find(KeyL{l + 1, cq[0], cq[1], cq[2]});
+              if (ci == leaf.end()) { J.err = "fine neighbour is not a leaf"; return AMRVAC_E_ARG; }
+              Lk[1 + ob * 2 + oa] = first + ci->second;
+            }
+          J.tfill.push_back(first + b);
+          J.tfill.push_back(d * 2 + side);
+          J.trefl.push_back(first + b);
+          J.trefl.push_back(d * 2 + side);
+          continue;
+        }
+        auto pi = leaf.find(KeyL{l - 1, q[0] >> 1, q[1] >> 1, ndim == 3 ? q[2] >> 1 : 0});
+        if (l < 2 || pi == leaf.end()) { J.err = "face neighbour not found (hierarchy not 2:1 nested)"; return AMRVAC_E_ARG; }
+        Lk[0] = LINK_COARSE;
+        Lk[1] = first + pi->second;
+        Lk[2] = l;
+        J.tprol.push_back(first + b);
+        J.tprol.push_back(d * 2 + side);
+      }
+  }
+  if (!g->reflux) J.trefl.clear();
+  // The fused stage reads same-level neighbours in place; it needs filled
+  // ghosts only on faces towards finer leaves and physical boundaries, plus
+  // every face of a block whose ghosts feed a prolongation.
+  std::vector<char> prol_src(nb, 0);
+  for (size_t q = 0; q < J.tprol.size(); q += 2) {
+    const int lb = J.tprol[q] - first, face = J.tprol[q + 1];
+    prol_src[J.link[((size_t)lb * 6 + face) * LINK_INTS + 1] - first] = 1;
+  }
+  for (size_t q = 0; q < J.tfill.size(); q += 2) {
+    const int lb = J.tfill[q] - first, face = J.tfill[q + 1];
+    if (J.link[((size_t)lb * 6 + face) * LINK_INTS] != LINK_SAME || prol_src[lb]) {
+      J.tfused.push_back(J.tfill[q]);
+      J.tfused.push_back(face);
+    }
+  }
+  // Morton order on the finest level's block grid
+  std::vector<std::pair<unsigned long long, int>> keyed(nb);
+  for (int b = 0; b < nb; ++b) {
+    const int sft = J.finest - J.level[b];
+    unsigned long long key = 0;
+    const unsigned long long q0 = (unsigned long long)J.pos[3 * b] << sft;
+    const unsigned long long q1 = (unsigned long long)J.pos[3 * b + 1] << sft;
+    const unsigned long long q2 = (unsigned long long)J.pos[3 * b + 2] << sft;
+    for (int bit = 0; bit < 20; ++bit) {
+      key |= ((q0 >> bit) & 1ull) << (3 * bit);
+      key |= ((q1 >> bit) & 1ull) << (3 * bit + 1);
+      key |= ((q2 >> bit) & 1ull) << (3 * bit + 2);
+    }
+    keyed[b] = {key, b};
+  }
+  std::sort(keyed.begin(), keyed.end());
+  J.order_local.resize(nb);
+  for (int b = 0; b < nb; ++b) J.order_local[b] = first + keyed[b].second;
+  // CFL geometry on the finest level
+  double sum_inv = 0.0, min_dx = 0.0;
+  for (int d = 0; d < ndim; ++d) {
+    const double dx = (g->xmax[d] - g->xmin[d]) / (double)(nblk(J.finest, d) * nx);
+    sum_inv += 1.0 / dx;
+    min_dx = d == 0 ? dx : std::min(min_dx, dx);
+  }
+  J.geom[0] = sum_inv;
+  J.geom[1] = min_dx;
+  J.geom[2] = g->cfl;
+  J.geom[3] = g->glm_alpha;
   return AMRVAC_OK;
 }
 
-template <class T>
-static int upload(amrvac_ctx* c, T** dptr, const std::vector<T>& h) {
-  const size_t n = std::max<size_t>(h.size(), 1) * sizeof(T);
-  HIP_TRY(c, hipMalloc((void**)dptr, n));
-  if (!h.empty()) HIP_TRY(c, hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+thread_local std::string g_init_err;
+
+}  // namespace
+
+struct amrvac_ctx {
+  amrvac_grid_desc g{};  // single-job: the grid; batch: shape and physics template
+  GridConst G{};
+  PhysConst P{};
+  FixedBC fixed{};
+  bool batch = false;
+  int batch_stages = 3;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<void*> slots;
+  int path = AMRVAC_PATH_PLAIN;
+  int cap = 0;       // pool places
+  int njob_cap = 1;  // job slots
+  std::vector<JobRec> jobs;
+  std::vector<std::pair<int, int>> free_runs;  // (first, count) of free pool places
+  bool dirty = true;
+  // device tables (pool-sized) and lists
+  int *d_level = nullptr, *d_job = nullptr, *d_link = nullptr, *d_pos = nullptr, *d_wrap = nullptr;
+  double* d_invdx = nullptr;
+  int *d_order = nullptr, *d_tfill = nullptr, *d_tfused = nullptr, *d_tprol = nullptr, *d_trefl = nullptr;
+  size_t cap_order = 0, cap_tfill = 0, cap_tfused = 0, cap_tprol = 0, cap_trefl = 0;
+  int n_order = 0, n_tfill = 0, n_tfused = 0, n_tprol = 0, n_trefl = 0;
+  // per-job device arrays
+  double* d_geom = nullptr;
+  unsigned long long* d_rate = nullptr;
+  unsigned int* d_nan = nullptr;
+  double* d_jdt = nullptr;  // dt, c_h, kappa of each job slot (library-owned)
+  double* d_jch = nullptr;
+  double* d_jkappa = nullptr;
+  // plain-path scratch (single-job FP64 contexts)
+  double* d_prim = nullptr;
+  double* d_flux[3] = {nullptr, nullptr, nullptr};
+  DevStatus* d_status = nullptr;
+  // graph of one step (single-job amrvac_advance)
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_stages = 0;
+  int graph_path = -1;
+  std::string err;
+
+  Tables tables() const { return Tables{d_level, d_job, d_invdx, d_link, d_pos, d_wrap, d_order, n_order}; }
+};
+
+namespace {
+
+int fail(amrvac_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((ctx), AMRVAC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void free_all(amrvac_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  void* ptrs[] = {c->d_level, c->d_job,   c->d_link,  c->d_pos,   c->d_wrap,    c->d_invdx,   c->d_order, c->d_tfill,
+                  c->d_tfused, c->d_tprol, c->d_trefl, c->d_geom,  c->d_rate,    c->d_nan,     c->d_jdt,   c->d_jch,
+                  c->d_jkappa, c->d_prim,  c->d_flux[0], c->d_flux[1], c->d_flux[2], c->d_status};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+int dev_alloc(amrvac_ctx* c, void** p, size_t n) {
+  hipError_t e = hipMalloc(p, std::max<size_t>(n, 8));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, AMRVAC_E_NOMEM, std::string("hipMalloc of library memory failed: ") + hipGetErrorString(e));
+  }
   return AMRVAC_OK;
 }
+
+// Upload a host list into a device buffer, growing it when needed (called
+// with the stream idle).
+template <class T>
+int upload_list(amrvac_ctx* c, T** d, size_t* capn, const std::vector<T>& h) {
+  if (h.size() > *capn || !*d) {
+    if (*d) (void)hipFree(*d);
+    *d = nullptr;
+    const size_t n = std::max<size_t>(h.size(), 64);
+    if (int rc = dev_alloc(c, (void**)d, n * sizeof(T))) return rc;
+    *capn = n;
+  }
+  if (!h.empty()) HIP_TRY(c, hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return AMRVAC_OK;
+}
+
+// Rebuild the active lists and per-job geometry from the job records and
+// upload them (called with the stream idle).  A job is active while it has
+// steps left (always, in a single-job context).
+int rebuild(amrvac_ctx* c) {
+  std::vector<int> order, tfill, tfused, tprol, trefl;
+  std::vector<double> geom((size_t)c->njob_cap * 4, 0.0);
+  for (int j = 0; j < c->njob_cap; ++j) {
+    const JobRec& J = c->jobs[j];
+    const bool active = J.used && (!c->batch || J.steps_left > 0);
+    if (!active) continue;
+    order.insert(order.end(), J.t.order_local.begin(), J.t.order_local.end());
+    tfill.insert(tfill.end(), J.t.tfill.begin(), J.t.tfill.end());
+    tfused.insert(tfused.end(), J.t.tfused.begin(), J.t.tfused.end());
+    tprol.insert(tprol.end(), J.t.tprol.begin(), J.t.tprol.end());
+    trefl.insert(trefl.end(), J.t.trefl.begin(), J.t.trefl.end());
+    for (int q = 0; q < 4; ++q) geom[4 * j + q] = J.t.geom[q];
+  }
+  int rc;
+  if ((rc = upload_list(c, &c->d_order, &c->cap_order, order)) ||
+      (rc = upload_list(c, &c->d_tfill, &c->cap_tfill, tfill)) ||
+      (rc = upload_list(c, &c->d_tfused, &c->cap_tfused, tfused)) ||
+      (rc = upload_list(c, &c->d_tprol, &c->cap_tprol, tprol)) ||
+      (rc = upload_list(c, &c->d_trefl, &c->cap_trefl, trefl)))
+    return rc;
+  HIP_TRY(c, hipMemcpy(c->d_geom, geom.data(), geom.size() * sizeof(double), hipMemcpyHostToDevice));
+  c->n_order = (int)order.size();
+  c->n_tfill = (int)tfill.size() / 2;
+  c->n_tfused = (int)tfused.size() / 2;
+  c->n_tprol = (int)tprol.size() / 2;
+  c->n_trefl = (int)trefl.size() / 2;
+  c->dirty = false;
+  return AMRVAC_OK;
+}
+
+int ensure_tables(amrvac_ctx* c) {
+  if (!c->dirty) return AMRVAC_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->graph_exec) {
+    (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return rebuild(c);
+}
+
+// Copy a job's per-block tables into the pool-sized device tables.
+int upload_job_blocks(amrvac_ctx* c, const JobRec& J, int jslot) {
+  const size_t f = J.first, n = J.nb;
+  std::vector<int> jobv(n, jslot);
+  HIP_TRY(c, hipMemcpy(c->d_level + f, J.t.level.data(), n * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_job + f, jobv.data(), n * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_pos + 3 * f, J.t.pos.data(), 3 * n * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_wrap + 3 * f, J.t.wrap.data(), 3 * n * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_invdx + 3 * f, J.t.invdx.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_link + f * 6 * LINK_INTS, J.t.link.data(), n * 6 * LINK_INTS * sizeof(int),
+                       hipMemcpyHostToDevice));
+  return AMRVAC_OK;
+}
+
+// Allocate the pool-sized tables and per-job arrays of a new context.
+int alloc_context(amrvac_ctx* c) {
+  const size_t cap = c->cap, nj = c->njob_cap;
+  int rc;
+  if ((rc = dev_alloc(c, (void**)&c->d_level, cap * sizeof(int))) ||
+      (rc = dev_alloc(c, (void**)&c->d_job, cap * sizeof(int))) ||
+      (rc = dev_alloc(c, (void**)&c->d_link, cap * 6 * LINK_INTS * sizeof(int))) ||
+      (rc = dev_alloc(c, (void**)&c->d_pos, cap * 3 * sizeof(int))) ||
+      (rc = dev_alloc(c, (void**)&c->d_wrap, cap * 3 * sizeof(int))) ||
+      (rc = dev_alloc(c, (void**)&c->d_invdx, cap * 3 * sizeof(double))) ||
+      (rc = dev_alloc(c, (void**)&c->d_geom, nj * 4 * sizeof(double))) ||
+      (rc = dev_alloc(c, (void**)&c->d_rate, nj * sizeof(unsigned long long))) ||
+      (rc = dev_alloc(c, (void**)&c->d_nan, nj * sizeof(unsigned int))) ||
+      (rc = dev_alloc(c, (void**)&c->d_jdt, nj * sizeof(double))) ||
+      (rc = dev_alloc(c, (void**)&c->d_jch, nj * sizeof(double))) ||
+      (rc = dev_alloc(c, (void**)&c->d_jkappa, nj * sizeof(double))) ||
+      (rc = dev_alloc(c, (void**)&c->d_status, sizeof(DevStatus))))
+    return rc;
+  HIP_TRY(c, hipMemset(c->d_rate, 0, nj * sizeof(unsigned long long)));
+  HIP_TRY(c, hipMemset(c->d_nan, 0, nj * sizeof(unsigned int)));
+  HIP_TRY(c, hipMemset(c->d_jdt, 0, nj * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->d_jch, 0, nj * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->d_jkappa, 0, nj * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->d_status, 0, sizeof(DevStatus)));
+  HIP_TRY(c, hipMemset(c->d_job, 0, cap * sizeof(int)));
+  return AMRVAC_OK;
+}
+
+void setup_shape(amrvac_ctx* c, const amrvac_grid_desc* g) {
+  c->g = *g;
+  GridConst& G = c->G;
+  G.ndim = g->ndim;
+  G.nx = g->block_nx;
+  G.ng = g->nghost;
+  G.pn = G.nx + 2 * G.ng;
+  G.nb = c->cap;
+  G.nfaces = (G.nx + 1) * G.nx * (G.ndim == 3 ? G.nx : 1);
+  G.pcells = (long)G.pn * G.pn * (G.ndim == 3 ? G.pn : 1);
+  G.icells = (long)G.nx * G.nx * (G.ndim == 3 ? G.nx : 1);
+  G.precision = g->precision;
+  c->P = PhysConst{g->gamma, g->gamma - 1.0, 1.0 / (g->gamma - 1.0), g->small_density, g->small_pressure,
+                   g->fix_small_values};
+  std::memcpy(c->fixed.prim, g->bc_fixed_prim, sizeof(c->fixed.prim));
+  if (g->precision == AMRVAC_FP32_MIXED) c->path = AMRVAC_PATH_FUSED;
+}
+
+int check_slot(amrvac_ctx* c, int s) {
+  if (s < 0 || s >= (int)c->slots.size()) return fail(c, AMRVAC_E_ARG, "slot index out of range");
+  return AMRVAC_OK;
+}
+
+int fill_slot(amrvac_ctx* c, int slot) {
+  const Tables T = c->tables();
+  const bool fused = c->path == AMRVAC_PATH_FUSED;
+  HIP_TRY(c, launch_fill_faces(c->stream, c->G, fused ? c->d_tfused : c->d_tfill, fused ? c->n_tfused : c->n_tfill,
+                               T, c->slots[slot], c->P, c->fixed));
+  HIP_TRY(c, launch_fill_faces(c->stream, c->G, c->d_tprol, c->n_tprol, T, c->slots[slot], c->P, c->fixed));
+  return AMRVAC_OK;
+}
+
+int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScalars& J) {
+  const Tables T = c->tables();
+  if (c->path == AMRVAC_PATH_FUSED) {
+    HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->slots[in], c->slots[base], c->slots[out], w, c->P,
+                                  c->d_status));
+    HIP_TRY(c, launch_reflux_correct(c->stream, c->G, T, J, c->d_trefl, c->n_trefl, c->slots[in], c->slots[out], w,
+                                     c->P));
+    return AMRVAC_OK;
+  }
+  HIP_TRY(c, launch_prim(c->stream, c->G, c->slots[in], c->d_prim, c->P, c->d_status));
+  for (int d = 0; d < c->G.ndim; ++d)
+    HIP_TRY(c, launch_flux(c->stream, c->G, d, c->d_prim, c->d_flux[d], J.ch, c->P));
+  FluxPtrs fp{{c->d_flux[0], c->d_flux[1], c->d_flux[2]}};
+  HIP_TRY(c, launch_reflux(c->stream, c->G, c->d_trefl, c->n_trefl, T, fp));
+  HIP_TRY(c, launch_update(c->stream, c->G, T, c->slots[in], c->slots[base], c->slots[out], w, fp, J.dt, J.kappa));
+  return AMRVAC_OK;
+}
+
+JobCfl cfl_state(amrvac_ctx* c, double* dt, double* ch, double* kappa) {
+  return JobCfl{c->d_rate, c->d_nan, c->d_geom, dt, ch, kappa, c->njob_cap};
+}
+
+// cfl -> [fill -> stage] x nstages on slots 0, 1, 2 with per-job scalars
+int enqueue_step(amrvac_ctx* c, int nstages, double* dt, double* ch, double* kap) {
+  HIP_TRY(c, launch_cfl(c->stream, c->G, c->tables(), c->slots[0], c->P, c->d_status, cfl_state(c, dt, ch, kap)));
+  const JobScalars J{dt, ch, kap};
+  int rc;
+  if (nstages == 2) {
+    if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, J))) return rc;
+    if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 0, 0.5, J))) return rc;
+    return AMRVAC_OK;
+  }
+  if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, J))) return rc;
+  if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 2, 0.25, J))) return rc;
+  if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 0, 2.0 / 3.0, J))) return rc;
+  return AMRVAC_OK;
+}
+
+bool job_ok(const amrvac_ctx* c, int job) { return c->batch && job >= 0 && job < c->njob_cap && c->jobs[job].used; }
 
 }  // namespace
 
@@ -158,329 +553,91 @@ int amrvac_init_blocks(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, cons
   *out = nullptr;
   std::string why;
   if (check_desc(g, &why) != AMRVAC_OK) { g_init_err = why; return AMRVAC_E_ARG; }
-  if (g->precision != AMRVAC_FP64) { g_init_err = "FP32-mixed storage is not available in this build"; return AMRVAC_E_ARG; }
+  if (g->precision == AMRVAC_FP32_MIXED && g->block_nx != 16) {
+    g_init_err = "FP32-mixed storage runs on the fused path, which needs block_nx = 16";
+    return AMRVAC_E_ARG;
+  }
   if (nb < 1 || !level || !ijk || !slots || nslots < 1) { g_init_err = "need blocks, tables and slots"; return AMRVAC_E_ARG; }
   for (int s = 0; s < nslots; ++s)
     if (!slots[s]) { g_init_err = "null slot pointer"; return AMRVAC_E_ARG; }
-
-  const int ndim = g->ndim, nx = g->block_nx;
-  // ---- block set validation -------------------------------------------------
-  std::map<KeyL, int> leaf;
-  std::set<KeyL> refined;
-  int finest = 1;
-  double vol = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    const int l = level[b];
-    if (l < 1 || l > MAXLEV) { g_init_err = "level out of range 1..12"; return AMRVAC_E_ARG; }
-    long p[3] = {ijk[3 * b], ijk[3 * b + 1], ndim == 3 ? ijk[3 * b + 2] : 0};
-    for (int d = 0; d < ndim; ++d)
-      if (p[d] < 0 || p[d] >= ((long)g->base_blocks[d] << (l - 1))) { g_init_err = "block outside the domain"; return AMRVAC_E_ARG; }
-    if (!leaf.emplace(KeyL{l, p[0], p[1], p[2]}, b).second) { g_init_err = "duplicate block"; return AMRVAC_E_ARG; }
-    finest = std::max(finest, l);
-    vol += std::ldexp(1.0, -ndim * (l - 1));
-    for (int m = l - 1; m >= 1; --m) {
-      for (int d = 0; d < 3; ++d) p[d] >>= 1;
-      refined.insert(KeyL{m, p[0], p[1], p[2]});
-    }
-  }
-  for (const auto& kv : leaf)
-    if (refined.count(kv.first)) { g_init_err = "blocks overlap (a leaf is also refined)"; return AMRVAC_E_ARG; }
-  const double nbase = (double)g->base_blocks[0] * g->base_blocks[1] * (ndim == 3 ? g->base_blocks[2] : 1);
-  if (std::fabs(vol - nbase) > 1e-9 * nbase) { g_init_err = "blocks do not tile the domain"; return AMRVAC_E_ARG; }
-
-  auto nblk = [&](int l, int d) -> long { return d < ndim ? ((long)g->base_blocks[d] << (l - 1)) : 1; };
-  auto periodic = [&](int d) { return g->bc_lo[d] == AMRVAC_BC_PERIODIC; };
-  // 2:1 nesting over faces, edges and corners: every slot next to a leaf of
-  // level l is a leaf, refined, or inside a leaf of level l-1.
-  for (const auto& kv : leaf) {
-    const int l = kv.first.l;
-    const long p[3] = {kv.first.i, kv.first.j, kv.first.k};
-    for (int oz = (ndim == 3 ? -1 : 0); oz <= (ndim == 3 ? 1 : 0); ++oz)
-      for (int oy = -1; oy <= 1; ++oy)
-        for (int ox = -1; ox <= 1; ++ox) {
-          long q[3] = {p[0] + ox, p[1] + oy, p[2] + oz};
-          bool skip = false;
-          for (int d = 0; d < ndim; ++d) {
-            if (q[d] < 0 || q[d] >= nblk(l, d)) {
-              if (periodic(d)) q[d] = (q[d] + nblk(l, d)) % nblk(l, d);
-              else skip = true;
-            }
-          }
-          if (skip) continue;
-          const KeyL k{l, q[0], q[1], q[2]};
-          if (leaf.count(k)) continue;
-          if (refined.count(k)) {
-            // children facing this leaf must be leaves (not refined further)
-            const long off[3] = {ox, oy, oz};
-            for (int cz = 0; cz < (ndim == 3 ? 2 : 1); ++cz)
-              for (int cy = 0; cy < 2; ++cy)
-                for (int cx = 0; cx < 2; ++cx) {
-                  const long cc[3] = {cx, cy, cz};
-                  bool adjacent = true;
-                  for (int d = 0; d < ndim; ++d) {
-                    if (off[d] == 1 && cc[d] != 0) adjacent = false;
-                    if (off[d] == -1 && cc[d] != 1) adjacent = false;
-                  }
-                  if (!adjacent) continue;
-                  const KeyL ck{l + 1, 2 * q[0] + cx, 2 * q[1] + cy, ndim == 3 ? 2 * q[2] + cz : 0};
-                  if (!leaf.count(ck)) { g_init_err = "hierarchy is not 2:1 nested (finer by two)"; return AMRVAC_E_ARG; }
-                }
-            continue;
-          }
-          if (l >= 2 && leaf.count(KeyL{l - 1, q[0] >> 1, q[1] >> 1, ndim == 3 ? q[2] >> 1 : 0})) continue;
-          g_init_err = "hierarchy is not 2:1 nested (coarser by two)";
-          return AMRVAC_E_ARG;
-        }
-  }
+  JobRec J;
+  if (build_job(g, nb, level, ijk, 0, &J.t) != AMRVAC_OK) { g_init_err = J.t.err; return AMRVAC_E_ARG; }
 
   amrvac_ctx* c = new amrvac_ctx();
-  c->g = *g;
+  c->cap = nb;
+  c->njob_cap = 1;
+  setup_shape(c, g);
   c->stream = static_cast<hipStream_t>(stream);
   c->slots.assign(slots, slots + nslots);
   (void)hipGetDevice(&c->device);
-  GridConst& G = c->G;
-  G.ndim = ndim;
-  G.nx = nx;
-  G.ng = g->nghost;
-  G.pn = nx + 2 * G.ng;
-  G.nb = nb;
-  G.nfaces = (nx + 1) * nx * (ndim == 3 ? nx : 1);
-  G.pcells = (long)G.pn * G.pn * (ndim == 3 ? G.pn : 1);
-  G.icells = (long)nx * nx * (ndim == 3 ? nx : 1);
-  for (int d = 0; d < 3; ++d) G.base[d] = d < ndim ? g->base_blocks[d] : 1;
-  G.precision = g->precision;
-
-  LevelConst& L = c->L;
-  for (int l = 1; l <= MAXLEV; ++l)
-    for (int d = 0; d < 3; ++d) {
-      const double dx = d < ndim ? (g->xmax[d] - g->xmin[d]) / (double)(nblk(l, d) * nx) : 1.0;
-      L.dx[l][d] = dx;
-      L.inv_dx[l][d] = 1.0 / dx;
-    }
-  L.sum_inv_dx_fin = 0.0;
-  L.min_dx_fin = L.dx[finest][0];
-  for (int d = 0; d < ndim; ++d) {
-    L.sum_inv_dx_fin += 1.0 / L.dx[finest][d];
-    L.min_dx_fin = std::min(L.min_dx_fin, L.dx[finest][d]);
+  J.used = true;
+  J.first = 0;
+  J.nb = nb;
+  c->jobs.push_back(std::move(J));
+  int rc = alloc_context(c);
+  if (!rc && g->precision == AMRVAC_FP64) {
+    // primitive and face-flux scratch of the plain (per-kernel) FP64 path
+    const size_t pcs = (size_t)nb * NV * c->G.pcells * sizeof(double);
+    const size_t fcs = (size_t)nb * NV * c->G.nfaces * sizeof(double);
+    rc = dev_alloc(c, (void**)&c->d_prim, pcs);
+    for (int d = 0; d < g->ndim && !rc; ++d) rc = dev_alloc(c, (void**)&c->d_flux[d], fcs);
   }
-  L.cfl = g->cfl;
-  L.glm_alpha = g->glm_alpha;
-  c->P = PhysConst{g->gamma, g->gamma - 1.0, 1.0 / (g->gamma - 1.0), g->small_density, g->small_pressure,
-                   g->fix_small_values};
-  std::memcpy(c->fixed.prim, g->bc_fixed_prim, sizeof(c->fixed.prim));
-
-  // ---- face links and task lists -------------------------------------------
-  std::vector<int> link((size_t)nb * 6 * LINK_INTS, -1), pos((size_t)nb * 3), lev(nb);
-  std::vector<int> tfill, tprol, trefl;
-  for (int b = 0; b < nb; ++b) {
-    const int l = level[b];
-    lev[b] = l;
-    const long p[3] = {ijk[3 * b], ijk[3 * b + 1], ndim == 3 ? ijk[3 * b + 2] : 0};
-    for (int d = 0; d < 3; ++d) pos[3 * b + d] = (int)p[d];
-    for (int d = 0; d < ndim; ++d)
-      for (int side = 0; side < 2; ++side) {
-        int* Lk = &link[((size_t)b * 6 + d * 2 + side) * LINK_INTS];
-        long q[3] = {p[0], p[1], p[2]};
-        q[d] += side ? 1 : -1;
-        if (q[d] < 0 || q[d] >= nblk(l, d)) {
-          if (!periodic(d)) {
-            Lk[0] = LINK_PHYS;
-            Lk[1] = side ? g->bc_hi[d] : g->bc_lo[d];
-            tfill.push_back(b);
-            tfill.push_back(d * 2 + side);
-            continue;
-          }
-          q[d] = (q[d] + nblk(l, d)) % nblk(l, d);
-        }
-        auto it = leaf.find(KeyL{l, q[0], q[1], q[2]});
-        if (it != leaf.end()) {
-          Lk[0] = LINK_SAME;
-          Lk[1] = it->second;
-          tfill.push_back(b);
-          tfill.push_back(d * 2 + side);
-          continue;
-        }
-        if (refined.count(KeyL{l, q[0], q[1], q[2]})) {
-          Lk[0] = LINK_FINE;
-          const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
-          for (int ob = 0; ob < (ndim == 3 ? 2 : 1); ++ob)
-            for (int oa = 0; oa < 2; ++oa) {
-              long cq[3] = {2 * q[0], 2 * q[1], ndim == 3 ? 2 * q[2] : 0};
-              cq[d] += side ? 0 : 1;
-              cq[ta] += oa;
-              if (ndim == 3) cq[tb] += ob;
-              auto ci = leaf.find(KeyL{l + 1, cq[0], cq[1], cq[2]});
-              if (ci == leaf.end()) {
-                delete c;
-                g_init_err = "fine neighbour is not a leaf";
-                return AMRVAC_E_ARG;
-              }
-              Lk[1 + ob * 2 + oa] = ci->second;
-            }
-          tfill.push_back(b);
-          tfill.push_back(d * 2 + side);
-          trefl.push_back(b);
-          trefl.push_back(d * 2 + side);
-          continue;
-        }
-        auto pi = leaf.find(KeyL{l - 1, q[0] >> 1, q[1] >> 1, ndim == 3 ? q[2] >> 1 : 0});
-        if (l < 2 || pi == leaf.end()) {
-          delete c;
-          g_init_err = "face neighbour not found (hierarchy not 2:1 nested)";
-          return AMRVAC_E_ARG;
-        }
-        Lk[0] = LINK_COARSE;
-        Lk[1] = pi->second;
-        Lk[2] = l;
-        tprol.push_back(b);
-        tprol.push_back(d * 2 + side);
-      }
+  if (!rc) rc = upload_job_blocks(c, c->jobs[0], 0);
+  if (!rc) rc = rebuild(c);
+  if (!rc) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = fail(c, AMRVAC_E_HIP, std::string("init: ") + hipGetErrorString(e));
   }
-  c->n_tasks_fill = (int)tfill.size() / 2;
-  c->n_tasks_prolong = (int)tprol.size() / 2;
-  c->n_tasks_reflux = g->reflux ? (int)trefl.size() / 2 : 0;
-  // The fused stage reads same-level neighbours in place; it needs filled
-  // ghosts only on faces towards finer leaves and physical boundaries, plus
-  // every face of a block whose ghosts feed a prolongation.
-  std::vector<char> prol_src(nb, 0);
-  for (size_t q = 0; q < tprol.size(); q += 2) {
-    const int fb = tprol[q], face = tprol[q + 1];
-    prol_src[link[((size_t)fb * 6 + face) * LINK_INTS + 1]] = 1;
-  }
-  std::vector<int> tfused;
-  for (size_t q = 0; q < tfill.size(); q += 2) {
-    const int fb = tfill[q], face = tfill[q + 1];
-    if (link[((size_t)fb * 6 + face) * LINK_INTS] != LINK_SAME || prol_src[fb]) {
-      tfused.push_back(fb);
-      tfused.push_back(face);
-    }
-  }
-  c->n_tasks_fill_fused = (int)tfused.size() / 2;
-  // Morton order on the finest level's block grid
-  std::vector<std::pair<unsigned long long, int>> keyed(nb);
-  for (int b = 0; b < nb; ++b) {
-    const int sft = finest - level[b];
-    unsigned long long key = 0;
-    const unsigned long long q0 = (unsigned long long)pos[3 * b] << sft, q1 = (unsigned long long)pos[3 * b + 1] << sft,
-                             q2 = (unsigned long long)pos[3 * b + 2] << sft;
-    for (int bit = 0; bit < 20; ++bit) {
-      key |= ((q0 >> bit) & 1ull) << (3 * bit);
-      key |= ((q1 >> bit) & 1ull) << (3 * bit + 1);
-      key |= ((q2 >> bit) & 1ull) << (3 * bit + 2);
-    }
-    keyed[b] = {key, b};
-  }
-  std::sort(keyed.begin(), keyed.end());
-  std::vector<int> order(nb);
-  for (int b = 0; b < nb; ++b) order[b] = keyed[b].second;
-
-  int rc;
-  if ((rc = upload(c, &c->d_level, lev)) || (rc = upload(c, &c->d_pos, pos)) || (rc = upload(c, &c->d_link, link)) ||
-      (rc = upload(c, &c->d_tasks_fill, tfill)) || (rc = upload(c, &c->d_tasks_prolong, tprol)) ||
-      (rc = upload(c, &c->d_tasks_fill_fused, tfused)) || (rc = upload(c, &c->d_order, order)) ||
-      (rc = upload(c, &c->d_tasks_reflux, trefl))) {
+  if (rc) {
     g_init_err = c->err;
     free_all(c);
     delete c;
     return rc;
   }
-  auto alloc = [&](void** p, size_t n) -> int {
-    hipError_t e = hipMalloc(p, n);
-    if (e != hipSuccess) {
-      g_init_err = std::string("hipMalloc of library scratch failed: ") + hipGetErrorString(e);
-      return AMRVAC_E_NOMEM;
-    }
-    return AMRVAC_OK;
-  };
-  if ((rc = alloc((void**)&c->d_prim, (size_t)nb * NV * G.pcells * sizeof(double))) ||
-      (rc = alloc((void**)&c->d_flux[0], (size_t)nb * NV * G.nfaces * sizeof(double))) ||
-      (rc = alloc((void**)&c->d_flux[1], (size_t)nb * NV * G.nfaces * sizeof(double))) ||
-      (ndim == 3 && (rc = alloc((void**)&c->d_flux[2], (size_t)nb * NV * G.nfaces * sizeof(double)))) ||
-      (rc = alloc((void**)&c->d_status, sizeof(DevStatus))) ||
-      (rc = alloc((void**)&c->d_scalars, 4 * sizeof(double)))) {
-    free_all(c);
-    delete c;
-    return rc;
-  }
-  hipError_t e = hipMemset(c->d_status, 0, sizeof(DevStatus));
-  if (e == hipSuccess) e = hipMemset(c->d_scalars, 0, 4 * sizeof(double));
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    g_init_err = std::string("init: ") + hipGetErrorString(e);
-    free_all(c);
-    delete c;
-    return AMRVAC_E_HIP;
-  }
   *out = c;
-  return AMRVAC_OK;
-}
-
-static int check_slot(amrvac_ctx* c, int s) {
-  if (s < 0 || s >= (int)c->slots.size()) return fail(c, AMRVAC_E_ARG, "slot index out of range");
   return AMRVAC_OK;
 }
 
 int amrvac_set_primitive(amrvac_ctx* c, int slot, const double* prim_dev) {
   if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts take initial states in amrvac_batch_add_job");
   if (int rc = check_slot(c, slot)) return rc;
   if (!prim_dev) return fail(c, AMRVAC_E_ARG, "null primitive array");
-  HIP_TRY(c, launch_set_prim(c->stream, c->G, prim_dev, c->slots[slot], c->P));
+  HIP_TRY(c, launch_set_prim(c->stream, c->G, 0, c->cap, prim_dev, c->slots[slot], c->P));
   return AMRVAC_OK;
 }
 
 int amrvac_get_conserved(amrvac_ctx* c, int slot, double* cons_dev) {
   if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "use amrvac_batch_get_job on batch contexts");
   if (int rc = check_slot(c, slot)) return rc;
   if (!cons_dev) return fail(c, AMRVAC_E_ARG, "null output array");
-  HIP_TRY(c, launch_get_cons(c->stream, c->G, c->slots[slot], cons_dev));
+  HIP_TRY(c, launch_get_cons(c->stream, c->G, 0, c->cap, c->slots[slot], cons_dev));
   return AMRVAC_OK;
 }
 
 int amrvac_fill_ghosts(amrvac_ctx* c, int slot) {
   if (!c) return AMRVAC_E_ARG;
   if (int rc = check_slot(c, slot)) return rc;
-  const bool fused = c->path == AMRVAC_PATH_FUSED;
-  HIP_TRY(c, launch_fill_faces(c->stream, c->G, fused ? c->d_tasks_fill_fused : c->d_tasks_fill,
-                               fused ? c->n_tasks_fill_fused : c->n_tasks_fill, c->d_link, c->d_pos,
-                               c->slots[slot], c->P, c->fixed));
-  HIP_TRY(c, launch_fill_faces(c->stream, c->G, c->d_tasks_prolong, c->n_tasks_prolong, c->d_link, c->d_pos,
-                               c->slots[slot], c->P, c->fixed));
-  return AMRVAC_OK;
+  if (int rc = ensure_tables(c)) return rc;
+  return fill_slot(c, slot);
 }
 
 int amrvac_cfl_dt(amrvac_ctx* c, int slot, double* dt_dev, double* ch_dev, double* kappa_dev) {
   if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts compute per-job dt in amrvac_batch_step");
   if (int rc = check_slot(c, slot)) return rc;
   if (!dt_dev || !ch_dev || !kappa_dev) return fail(c, AMRVAC_E_ARG, "null dt/c_h/kappa pointer");
-  HIP_TRY(c, launch_cfl(c->stream, c->G, c->L, c->d_level, c->slots[slot], c->P, c->d_status, dt_dev, ch_dev,
-                        kappa_dev));
-  return AMRVAC_OK;
-}
-
-static int stage_plain(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev,
-                       const double* ch_dev, const double* kappa_dev) {
-  HIP_TRY(c, launch_prim(c->stream, c->G, c->slots[in], c->d_prim, c->P, c->d_status));
-  for (int d = 0; d < c->G.ndim; ++d)
-    HIP_TRY(c, launch_flux(c->stream, c->G, d, c->d_prim, c->d_flux[d], ch_dev, c->P));
-  FluxPtrs fp{{c->d_flux[0], c->d_flux[1], c->d_flux[2]}};
-  HIP_TRY(c, launch_reflux(c->stream, c->G, c->d_tasks_reflux, c->n_tasks_reflux, c->d_link, fp));
-  HIP_TRY(c, launch_update(c->stream, c->G, c->L, c->d_level, c->slots[in], c->slots[base], c->slots[out], w, fp,
-                           dt_dev, kappa_dev));
-  return AMRVAC_OK;
-}
-
-static int stage_fused(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev,
-                       const double* ch_dev, const double* kappa_dev) {
-  HIP_TRY(c, launch_fused_stage(c->stream, c->G, c->L, c->d_level, c->d_link, c->d_order, c->slots[in],
-                                c->slots[base], c->slots[out], w, dt_dev, ch_dev, kappa_dev, c->P, c->d_status));
-  HIP_TRY(c, launch_reflux_correct(c->stream, c->G, c->L, c->d_level, c->d_tasks_reflux, c->n_tasks_reflux,
-                                   c->d_link, c->slots[in], c->slots[out], w, dt_dev, ch_dev, c->P));
+  if (int rc = ensure_tables(c)) return rc;
+  HIP_TRY(c, launch_cfl(c->stream, c->G, c->tables(), c->slots[slot], c->P, c->d_status,
+                        cfl_state(c, dt_dev, ch_dev, kappa_dev)));
   return AMRVAC_OK;
 }
 
 int amrvac_stage(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
                  const double* kappa_dev) {
   if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts step with amrvac_batch_step");
   if (int rc = check_slot(c, in)) return rc;
   if (int rc = check_slot(c, out)) return rc;
   if (w != 1.0) {
@@ -492,43 +649,31 @@ int amrvac_stage(amrvac_ctx* c, int in, int base, int out, double w, const doubl
   if (base == in && w != 1.0) return fail(c, AMRVAC_E_ARG, "base must differ from in");
   if (!dt_dev || !ch_dev || !kappa_dev) return fail(c, AMRVAC_E_ARG, "null dt/c_h/kappa pointer");
   if (!(w > 0.0 && w <= 1.0)) return fail(c, AMRVAC_E_ARG, "stage weight must be in (0, 1]");
-  if (c->path == AMRVAC_PATH_FUSED) return stage_fused(c, in, base, out, w, dt_dev, ch_dev, kappa_dev);
-  return stage_plain(c, in, base, out, w, dt_dev, ch_dev, kappa_dev);
+  if (int rc = ensure_tables(c)) return rc;
+  return stage_any(c, in, base, out, w, JobScalars{dt_dev, ch_dev, kappa_dev});
 }
 
 int amrvac_set_path(amrvac_ctx* c, int path) {
   if (!c) return AMRVAC_E_ARG;
   if (path != AMRVAC_PATH_PLAIN && path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_ARG, "unknown path");
   if (path == AMRVAC_PATH_FUSED && c->G.nx != 16) return fail(c, AMRVAC_E_ARG, "the fused path needs block_nx = 16");
+  if (path == AMRVAC_PATH_PLAIN && (c->g.precision != AMRVAC_FP64 || c->batch))
+    return fail(c, AMRVAC_E_ARG, "the plain path is for single-job FP64 contexts");
   c->path = path;
-  return AMRVAC_OK;
-}
-
-static int enqueue_step(amrvac_ctx* c, int nstages) {
-  double* dt = c->d_scalars;
-  double* ch = c->d_scalars + 1;
-  double* kap = c->d_scalars + 2;
-  int rc;
-  if ((rc = amrvac_cfl_dt(c, 0, dt, ch, kap))) return rc;
-  if (nstages == 2) {
-    if ((rc = amrvac_fill_ghosts(c, 0)) || (rc = amrvac_stage(c, 0, 0, 1, 1.0, dt, ch, kap))) return rc;
-    if ((rc = amrvac_fill_ghosts(c, 1)) || (rc = amrvac_stage(c, 1, 0, 0, 0.5, dt, ch, kap))) return rc;
-    return AMRVAC_OK;
-  }
-  if ((rc = amrvac_fill_ghosts(c, 0)) || (rc = amrvac_stage(c, 0, 0, 1, 1.0, dt, ch, kap))) return rc;
-  if ((rc = amrvac_fill_ghosts(c, 1)) || (rc = amrvac_stage(c, 1, 0, 2, 0.25, dt, ch, kap))) return rc;
-  if ((rc = amrvac_fill_ghosts(c, 2)) || (rc = amrvac_stage(c, 2, 0, 0, 2.0 / 3.0, dt, ch, kap))) return rc;
   return AMRVAC_OK;
 }
 
 int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph) {
   if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts step with amrvac_batch_step");
   if (nstages != 2 && nstages != 3) return fail(c, AMRVAC_E_ARG, "amrvac_advance supports 2 or 3 stages");
   if ((int)c->slots.size() < (nstages == 3 ? 3 : 2)) return fail(c, AMRVAC_E_ARG, "not enough slots");
   if (nsteps < 0) return fail(c, AMRVAC_E_ARG, "negative step count");
+  if (int rc = ensure_tables(c)) return rc;
+  double *dt = c->d_jdt, *ch = c->d_jch, *kap = c->d_jkappa;
   if (!use_graph) {
     for (int n = 0; n < nsteps; ++n)
-      if (int rc = enqueue_step(c, nstages)) return rc;
+      if (int rc = enqueue_step(c, nstages, dt, ch, kap)) return rc;
     return AMRVAC_OK;
   }
   if (!c->graph_exec || c->graph_stages != nstages || c->graph_path != c->path) {
@@ -542,7 +687,7 @@ int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph) {
     }
     if (c->stream == nullptr) return fail(c, AMRVAC_E_STATE, "graph capture needs a non-null stream");
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_step(c, nstages);
+    int rc = enqueue_step(c, nstages, dt, ch, kap);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &gr);
     if (rc) {
@@ -575,6 +720,160 @@ int amrvac_sync_flags(amrvac_ctx* c, int* flags_host, long long* nfix_host, doub
 int amrvac_reset_flags(amrvac_ctx* c) {
   if (!c) return AMRVAC_E_ARG;
   HIP_TRY(c, launch_reset_status(c->stream, c->d_status));
+  return AMRVAC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch (serving) contexts
+
+int amrvac_batch_create(amrvac_ctx** out, const amrvac_grid_desc* shape, int capacity_blocks, int max_jobs,
+                        int nstages, void* const* slots, void* stream) {
+  if (!out) return AMRVAC_E_ARG;
+  *out = nullptr;
+  std::string why;
+  if (check_desc(shape, &why) != AMRVAC_OK) { g_init_err = why; return AMRVAC_E_ARG; }
+  if (shape->block_nx != 16) { g_init_err = "batch contexts run the fused path: block_nx must be 16"; return AMRVAC_E_ARG; }
+  if (capacity_blocks < 1 || max_jobs < 1 || (nstages != 2 && nstages != 3) || !slots) {
+    g_init_err = "bad capacity, job count, stage count or slots";
+    return AMRVAC_E_ARG;
+  }
+  const int nslots = nstages == 3 ? 3 : 2;
+  for (int s = 0; s < nslots; ++s)
+    if (!slots[s]) { g_init_err = "null slot pointer"; return AMRVAC_E_ARG; }
+  amrvac_ctx* c = new amrvac_ctx();
+  c->batch = true;
+  c->batch_stages = nstages;
+  c->cap = capacity_blocks;
+  c->njob_cap = max_jobs;
+  setup_shape(c, shape);
+  c->path = AMRVAC_PATH_FUSED;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->slots.assign(slots, slots + nslots);
+  (void)hipGetDevice(&c->device);
+  c->jobs.resize(max_jobs);
+  c->free_runs.push_back({0, capacity_blocks});
+  int rc = alloc_context(c);
+  if (!rc) rc = rebuild(c);
+  if (rc) {
+    g_init_err = c->err;
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return AMRVAC_OK;
+}
+
+int amrvac_batch_add_job(amrvac_ctx* c, const amrvac_grid_desc* g, int nb, const int* level, const int* ijk,
+                         const double* prim_dev, int nsteps, int* job_out) {
+  if (!c || !job_out) return AMRVAC_E_ARG;
+  if (!c->batch) return fail(c, AMRVAC_E_STATE, "not a batch context");
+  std::string why;
+  if (check_desc(g, &why) != AMRVAC_OK) return fail(c, AMRVAC_E_ARG, why);
+  const amrvac_grid_desc& s = c->g;
+  if (g->ndim != s.ndim || g->block_nx != s.block_nx || g->precision != s.precision || g->gamma != s.gamma ||
+      g->small_density != s.small_density || g->small_pressure != s.small_pressure ||
+      g->fix_small_values != s.fix_small_values ||
+      std::memcmp(g->bc_fixed_prim, s.bc_fixed_prim, sizeof(s.bc_fixed_prim)) != 0)
+    return fail(c, AMRVAC_E_ARG, "job shape or physics differs from the batch");
+  if (nb < 1 || !level || !ijk || !prim_dev || nsteps < 0) return fail(c, AMRVAC_E_ARG, "bad job arguments");
+  int jslot = -1;
+  for (int j = 0; j < c->njob_cap; ++j)
+    if (!c->jobs[j].used) {
+      jslot = j;
+      break;
+    }
+  if (jslot < 0) return fail(c, AMRVAC_E_NOMEM, "no free job slot");
+  int run = -1;  // first fit in the free runs of the pool
+  for (size_t r = 0; r < c->free_runs.size(); ++r)
+    if (c->free_runs[r].second >= nb) {
+      run = (int)r;
+      break;
+    }
+  if (run < 0) return fail(c, AMRVAC_E_NOMEM, "no contiguous room for the job's blocks");
+  const int first = c->free_runs[run].first;
+  JobRec J;
+  if (build_job(g, nb, level, ijk, first, &J.t) != AMRVAC_OK) return fail(c, AMRVAC_E_ARG, J.t.err);
+  J.used = true;
+  J.first = first;
+  J.nb = nb;
+  J.steps_left = nsteps;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (int rc = upload_job_blocks(c, J, jslot)) return rc;
+  HIP_TRY(c, launch_set_prim(c->stream, c->G, first, nb, prim_dev, c->slots[0], c->P));
+  c->free_runs[run].first += nb;
+  c->free_runs[run].second -= nb;
+  if (c->free_runs[run].second == 0) c->free_runs.erase(c->free_runs.begin() + run);
+  c->jobs[jslot] = std::move(J);
+  c->dirty = true;
+  *job_out = jslot;
+  return AMRVAC_OK;
+}
+
+int amrvac_batch_step(amrvac_ctx* c) {
+  if (!c) return AMRVAC_E_ARG;
+  if (!c->batch) return fail(c, AMRVAC_E_STATE, "not a batch context");
+  if (int rc = ensure_tables(c)) return rc;
+  if (c->n_order == 0) return AMRVAC_OK;
+  if (int rc = enqueue_step(c, c->batch_stages, c->d_jdt, c->d_jch, c->d_jkappa)) return rc;
+  for (int j = 0; j < c->njob_cap; ++j) {
+    JobRec& J = c->jobs[j];
+    if (J.used && J.steps_left > 0) {
+      --J.steps_left;
+      ++J.steps_done;
+      if (J.steps_left == 0) c->dirty = true;
+    }
+  }
+  return AMRVAC_OK;
+}
+
+int amrvac_batch_job_info(amrvac_ctx* c, int job, int* steps_done, int* steps_left, int* nblocks) {
+  if (!c) return AMRVAC_E_ARG;
+  if (!job_ok(c, job)) return fail(c, AMRVAC_E_ARG, "no such job");
+  if (steps_done) *steps_done = c->jobs[job].steps_done;
+  if (steps_left) *steps_left = c->jobs[job].steps_left;
+  if (nblocks) *nblocks = c->jobs[job].nb;
+  return AMRVAC_OK;
+}
+
+int amrvac_batch_get_job(amrvac_ctx* c, int job, double* cons_dev) {
+  if (!c || !cons_dev) return AMRVAC_E_ARG;
+  if (!job_ok(c, job)) return fail(c, AMRVAC_E_ARG, "no such job");
+  const JobRec& J = c->jobs[job];
+  HIP_TRY(c, launch_get_cons(c->stream, c->G, J.first, J.nb, c->slots[0], cons_dev));
+  return AMRVAC_OK;
+}
+
+int amrvac_batch_remove_job(amrvac_ctx* c, int job) {
+  if (!c) return AMRVAC_E_ARG;
+  if (!job_ok(c, job)) return fail(c, AMRVAC_E_ARG, "no such job");
+  JobRec& J = c->jobs[job];
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->free_runs.push_back({J.first, J.nb});  // return the run, merging neighbours
+  std::sort(c->free_runs.begin(), c->free_runs.end());
+  std::vector<std::pair<int, int>> merged;
+  for (const auto& r : c->free_runs) {
+    if (!merged.empty() && merged.back().first + merged.back().second == r.first)
+      merged.back().second += r.second;
+    else
+      merged.push_back(r);
+  }
+  c->free_runs.swap(merged);
+  J = JobRec();
+  c->dirty = true;
+  return AMRVAC_OK;
+}
+
+int amrvac_batch_free_blocks(amrvac_ctx* c, int* largest_run, int* total_free) {
+  if (!c) return AMRVAC_E_ARG;
+  if (!c->batch) return fail(c, AMRVAC_E_STATE, "not a batch context");
+  int big = 0, tot = 0;
+  for (const auto& r : c->free_runs) {
+    big = std::max(big, r.second);
+    tot += r.second;
+  }
+  if (largest_run) *largest_run = big;
+  if (total_free) *total_free = tot;
   return AMRVAC_OK;
 }
 

@@ -1,0 +1,130 @@
+"""Batch (serving) contexts: several independent jobs resident in one block
+pool, advanced together with per-job dt; each job's result is the same alone
+and in the mix (bit for bit: no arithmetic couples jobs), and matches the
+CPU oracle."""
+import numpy as np
+import pytest
+
+from paper_2303_03026_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def amr():
+    from paper_2303_03026_amd import amrvac
+    return amrvac
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def rel_l1(a, b):
+    return np.array([np.sum(np.abs(a[:, q] - b[:, q])) / max(np.sum(np.abs(b[:, q])), 1e-300) for q in range(9)])
+
+
+def alone(amr, w, nsteps, precision):
+    sim = amr.Simulation(w, path=amr.PATH_FUSED, precision=precision)
+    sim.advance(nsteps)
+    sim.sync_flags()
+    out = sim.cons()
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_job_alone_equals_in_mix_3d(amr, orc, precision):
+    shape = inputs.random_modes(32, 3, seed=0)
+    batch = amr.Batch(shape, capacity_blocks=300, max_jobs=8, precision=precision)
+    ws = [inputs.random_modes(32, 3, seed=11, nsteps=7),
+          inputs.random_modes(48, 3, seed=12, nsteps=12),
+          inputs.smooth_amr_state(3, nb1=2, seed=7),
+          inputs.random_modes(32, 3, seed=13, nsteps=3)]
+    ws[2].nsteps = 5
+    ids = [batch.add_job(w) for w in ws]
+    assert all(i is not None for i in ids)
+    rounds = 0
+    while any(batch.job_info(i)[1] > 0 for i in ids):
+        batch.step()
+        rounds += 1
+    assert rounds == 12
+    outs = [batch.get_job(i) for i in ids]
+    batch.sync_flags()
+    batch.close()
+    for w, got in zip(ws, outs):
+        ref = alone(amr, w, w.nsteps, precision)
+        assert np.array_equal(got, ref), w.name
+    if precision == 0:
+        for w, got in zip(ws, outs):
+            ref, _ = orc.run(w)
+            assert np.all(rel_l1(got, ref)[:8] <= 1e-12), w.name
+
+
+def test_job_alone_equals_in_mix_2d(amr):
+    shape = inputs.random_modes(32, 2, seed=0)
+    batch = amr.Batch(shape, capacity_blocks=200, max_jobs=8)
+    ws = [inputs.random_modes(64, 2, seed=21, nsteps=9), inputs.random_modes(128, 2, seed=22, nsteps=4),
+          inputs.orszag_tang_2d(nsteps=6)]
+    ws[2].nstages = 3  # a batch steps SSPRK(3,3)
+    ids = [batch.add_job(w) for w in ws]
+    while any(batch.job_info(i)[1] > 0 for i in ids):
+        batch.step()
+    outs = [batch.get_job(i) for i in ids]
+    batch.close()
+    for w, got in zip(ws, outs):
+        ref = alone(amr, w, w.nsteps, 0)
+        assert np.array_equal(got, ref), w.name
+
+
+def test_admission_by_pool_room_and_reuse(amr):
+    shape = inputs.random_modes(32, 3, seed=0)
+    batch = amr.Batch(shape, capacity_blocks=20, max_jobs=4)
+    w = inputs.random_modes(32, 3, seed=1, nsteps=2)  # 8 blocks
+    a = batch.add_job(w)
+    b = batch.add_job(w)
+    assert a is not None and b is not None
+    assert batch.add_job(w) is None           # 4 places left: no room
+    assert batch.free_blocks() == (4, 4)
+    batch.remove_job(a)
+    assert batch.free_blocks() == (8, 12)
+    c = batch.add_job(w)
+    assert c is not None
+    while batch.job_info(c)[1] > 0:
+        batch.step()
+    got = batch.get_job(c)
+    batch.close()
+    assert np.array_equal(got, alone(amr, w, 2, 0))
+
+
+def test_batch_rejects_other_physics(amr):
+    shape = inputs.random_modes(32, 3, seed=0)
+    batch = amr.Batch(shape, capacity_blocks=50, max_jobs=2)
+    w = inputs.random_modes(32, 3, seed=1, nsteps=2)
+    w.gamma = 1.4
+    with pytest.raises(amr.AmrvacError):
+        batch.add_job(w)
+    batch.close()
+
+
+def test_serving_engine_small_stream(amr):
+    from paper_2303_03026_amd import serve
+    jobs = inputs.serving_jobs(24, seed=8)
+    rng = np.random.Generator(np.random.PCG64(3))
+    for j in jobs:
+        j["n"] = int(rng.choice([32, 48, 64] if j["ndim"] == 2 else [32, 48]))
+        j["steps"] = int(rng.integers(3, 12))
+    eng = serve.ServingEngine(budget_bytes=2e9, max_jobs=16)
+    keep = {jobs[0]["id"], jobs[5]["id"]}
+    res = eng.run(jobs, time_scale=0.002, keep_results=keep)
+    eng.close()
+    assert res["jobs"] == 24
+    assert res["latency_p99_s"] >= res["latency_p50_s"] > 0
+    for j in jobs:
+        if j["id"] in keep:
+            w = inputs.serving_job_workload(j)
+            ref = alone(amr, w, j["steps"], 1 if j["mixed"] else 0)
+            assert np.array_equal(res["results"][j["id"]], ref)
