@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64",
                     help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
-    ap.add_argument("--workload", choices=["random_modes", "current_sheet"], default="random_modes")
+    ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud"], default="random_modes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph-pass", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -79,8 +79,10 @@ def main():
     print("bench: generating %d^3 %s input" % (args.n, args.workload), file=sys.stderr, flush=True)
     if args.workload == "random_modes":
         w = inputs.random_modes(args.n, 3, seed=1)
-    else:
+    elif args.workload == "current_sheet":
         w = inputs.current_sheet(n=args.n)
+    else:
+        w = inputs.shock_cloud_amr()
     mixed = args.precision == "mixed"
     if mixed:
         args.path = "fused"
@@ -154,9 +156,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: 3D %d^3, %d blocks of 16^3 + 2 ghost layers, %s GLM-MHD state, "
-                               "SSPRK(3,3), CFL 0.8, %s" % (w.name, args.n, w.nblocks, args.workload,
-                                                            "FP32-mixed" if mixed else "FP64"),
+        "config": {"workload": "%s: 3D, %d leaf blocks of 16^3 + 2 ghost layers on %d level(s), %s GLM-MHD "
+                               "state, SSPRK(3,3), CFL 0.8, %s" % (w.name, w.nblocks, w.max_level, args.workload,
+                                                                  "FP32-mixed" if mixed else "FP64"),
                    "path": args.path, "cells": cells, "stage_weights": [1.0, 0.25, 2.0 / 3.0]},
         "algorithmic_hbm_gbs_per_step": cells * 8 * state_bytes / (ms_per_step * 1e-3) / 1e9,
         "graph_ms_per_step": graph_ms,
