@@ -122,11 +122,14 @@ __device__ __forceinline__ void prim_to_cons(const double w[NV], double u[NV], c
   u[I_PSI] = w[I_PSI];
 }
 
-// van Leer's harmonic-mean slope
+// van Leer's harmonic-mean slope.  The quotient is formed for every lane and
+// then selected (no branch), so the nine slopes of a cell can interleave; it
+// is discarded where dm * dp <= 0, which includes a zero denominator.
 template <class R>
 __device__ __forceinline__ R vl_slope(R dm, R dp) {
   const R q = dm * dp;
-  return q > R(0) ? div_(R(2) * q, dm + dp) : R(0);
+  const R v = div_(R(2) * q, dm + dp);
+  return q > R(0) ? v : R(0);
 }
 
 __device__ __forceinline__ double minmod2(double a, double b) {

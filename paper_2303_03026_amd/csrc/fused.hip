@@ -127,7 +127,8 @@ __device__ __forceinline__ void plane_direction(const R (*Wp)[BP * BP], R (*Sl)[
   }
 }
 
-template <int NDIM, class SP>
+// W1: the stage weight is 1 (out = in + dt L(in)), so base is not read.
+template <int NDIM, class SP, bool W1>
 __global__ void __launch_bounds__(256, SP::kWavesPerEU)
 k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __restrict__ in, const void* base,
               void* out, double wgt, PhysConst P, DevStatus* st) {
@@ -162,6 +163,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
   const double dt = J.dt[job], kappa = J.kappa[job], chd = J.ch[job];
   const FaceConst<R> K{(R)chd, (R)(0.5 / chd), (R)P.gamma, (R)P.inv_gm1};
   const double idx = T.inv_dx[3 * b], idy = T.inv_dx[3 * b + 1], idz = T.inv_dx[3 * b + 2];
+  const R idzr = (R)idz;
   int bad = 0;
   unsigned nfix = 0;
 
@@ -193,41 +195,57 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
     }
   };
 
-  // z pipeline (3D): wa = W(k), wb = W(k+1), wla = left state of face k+1/2
-  // (W(k) + sigma(k)/2), fzlo = z flux at face k-1/2.
-  R wa[NV], wb[NV], wla[NV], fzlo[NV];
-  if (NDIM == 3) {
+  // z pipeline (3D).  Registers carry wb = W(k+1), wla = the left state of
+  // face k+1/2 (W(k) + sigma(k)/2) and acc, which enters plane k already
+  // holding the contribution -F_z(k-1/2)/dz of the face below; W(k) itself
+  // sits in this thread's cell of the LDS plane.
+  R wb[NV], wla[NV], acc[NV];
+  double acc_e = 0.0;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = R(0);
+  {
     double u[NV];
-    R wm2[NV], wm1[NV];
-    load_cons<SP>(Uzlo, PC, PD::at(i, j, -2 + shzlo), u);
-    convert(u, wm2);
-    load_cons<SP>(Uzlo, PC, PD::at(i, j, -1 + shzlo), u);
-    convert(u, wm1);
+    R wa[NV];
     load_cons<SP>(U, PC, PD::at(i, j, 0), u);
     convert(u, wa);
-    load_cons<SP>(U, PC, PD::at(i, j, 1), u);
-    convert(u, wb);
-    R wl[NV], wr[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const R sm = vl_slope(wm1[q] - wm2[q], wa[q] - wm1[q]);
-      const R s0 = vl_slope(wa[q] - wm1[q], wb[q] - wa[q]);
-      wl[q] = wm1[q] + R(0.5) * sm;
-      wr[q] = wa[q] - R(0.5) * s0;
-      wla[q] = wa[q] + R(0.5) * s0;
-    }
-    if (!((wl[I_RHO] > R(0)) && (wl[4] > R(0)) && (wr[I_RHO] > R(0)) && (wr[4] > R(0)))) {
+    for (int q = 0; q < NV; ++q) Wp[q][(j + 2) * BP + (i + 2)] = wa[q];
+    if (NDIM == 3) {
+      R wm2[NV], wm1[NV];
+      load_cons<SP>(Uzlo, PC, PD::at(i, j, -2 + shzlo), u);
+      convert(u, wm2);
+      load_cons<SP>(Uzlo, PC, PD::at(i, j, -1 + shzlo), u);
+      convert(u, wm1);
+      load_cons<SP>(U, PC, PD::at(i, j, 1), u);
+      convert(u, wb);
+      R wl[NV], wr[NV], fz[NV];
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        wl[q] = wm1[q];
-        wr[q] = wa[q];
+        const R sm = vl_slope(wm1[q] - wm2[q], wa[q] - wm1[q]);
+        const R s0 = vl_slope(wa[q] - wm1[q], wb[q] - wa[q]);
+        wl[q] = wm1[q] + R(0.5) * sm;
+        wr[q] = wa[q] - R(0.5) * s0;
+        wla[q] = wa[q] + R(0.5) * s0;
+      }
+      if (!((wl[I_RHO] > R(0)) && (wl[4] > R(0)) && (wr[I_RHO] > R(0)) && (wr[4] > R(0)))) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          wl[q] = wm1[q];
+          wr[q] = wa[q];
+        }
+      }
+      hll_glm_flux<2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        if (q == I_EN) {
+          const double d = (double)fz[q] * idz;
+          acc_e = -d;
+        } else {
+          const R d = fz[q] * idzr;
+          acc[q] = -d;
+        }
       }
     }
-    hll_glm_flux<2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fzlo);
-  } else {
-    double u[NV];
-    load_cons<SP>(U, PC, PD::at(i, j, 0), u);
-    convert(u, wa);
   }
 
   constexpr int NK = NDIM == 3 ? BN : 1;
@@ -241,9 +259,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
         load_cons<SP>(Uzhi, PC, PD::at(i, j, k + 2 + shzhi), uc);
     }
 
-    // ---- plane k primitives into LDS (interior from the queue, halo loaded)
-#pragma unroll
-    for (int q = 0; q < NV; ++q) Wp[q][(j + 2) * BP + (i + 2)] = wa[q];
+    // ---- plane k halo into LDS (this thread's own cell is already there)
     if (has_halo) {
       double u[NV];
       R w[NV];
@@ -254,18 +270,23 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
     }
     __syncthreads();
 
-    R acc[NV];
-    double acc_e = 0.0;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = R(0);
     plane_direction<0, R>(Wp, Sl, Fl, t, i, j, K, idx, acc, acc_e);
     plane_direction<1, R>(Wp, Sl, Fl, t, i, j, K, idy, acc, acc_e);
 
-    // ---- z direction (registers)
+    // this plane's conserved state and the stage base, issued as one group
+    const long c = PD::at(i, j, k);
+    double u[NV], ub[NV];
+
+    // ---- z direction (registers; W(k) from this thread's LDS cell, which
+    // no other thread reads after the last barrier of the plane)
+    R fz[NV];
+    double fze = 0.0;
     if (NDIM == 3) {
-      R wc[NV];
+      R wa[NV], wc[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) wa[q] = Wp[q][(j + 2) * BP + (i + 2)];
       convert(uc, wc);
-      R wl[NV], wr[NV], fz[NV];
+      R wl[NV], wr[NV];
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
         const R s1 = vl_slope(wb[q] - wa[q], wc[q] - wb[q]);
@@ -281,44 +302,57 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
         }
       }
       hll_glm_flux<2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
-      const R idzr = (R)idz;
+      // fz becomes F_z(k+1/2)/dz (the energy term in double, in fze); it is
+      // added here and its negative seeds the next plane's accumulator
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        if (q == I_EN)
-          acc_e = acc_e + ((double)fz[q] - (double)fzlo[q]) * idz;
-        else
-          acc[q] = acc[q] + (fz[q] - fzlo[q]) * idzr;
-        fzlo[q] = fz[q];
-        wa[q] = wb[q];
+        if (q == I_EN) {
+          fze = (double)fz[q] * idz;
+          acc_e = acc_e + fze;
+        } else {
+          fz[q] = fz[q] * idzr;
+          acc[q] = acc[q] + fz[q];
+        }
+        // W(k+1) goes into this thread's LDS cell for the next plane
+        Wp[q][(j + 2) * BP + (i + 2)] = wb[q];
         wb[q] = wc[q];
       }
     }
 
     // ---- update: L = -(sum_d dF_d / dx_d) - kappa psi; SSPRK combination
     // (the energy in double, the rest in the face precision)
-    const long c = PD::at(i, j, k);
-    double u[NV];
     load_cons<SP>(U, PC, c, u);
-    void* __restrict__ o = block_ptr<SP>(out, b, PC);
-    const void* bs = block_ptr<SP>(base, b, PC);
+    if (!W1) load_cons<SP>(block_ptr<SP>(base, b, PC), PC, c, ub);
+    // (out may be the base slot: each cell is read before it is written, by
+    // the same thread)
+    void* o = block_ptr<SP>(out, b, PC);
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       double res;
       if (q == I_EN) {
         const double tq = u[q] + dt * (-acc_e);
-        res = wgt == 1.0 ? tq : SP::ld(bs, q, c, PC) + wgt * (tq - SP::ld(bs, q, c, PC));
+        res = W1 ? tq : ub[q] + wgt * (tq - ub[q]);
       } else {
         R lq = -acc[q];
         if (q == I_PSI) lq = lq - (R)kappa * (R)u[I_PSI];
         const R tq = (R)u[q] + (R)dt * lq;
-        if (wgt == 1.0) {
+        if (W1) {
           res = (double)tq;
         } else {
-          const R u0 = (R)SP::ld(bs, q, c, PC);
+          const R u0 = (R)ub[q];
           res = (double)(u0 + (R)wgt * (tq - u0));
         }
       }
       SP::st(o, q, c, PC, res);
+    }
+    if (NDIM == 3) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        if (q == I_EN)
+          acc_e = -fze;
+        else
+          acc[q] = -fz[q];
+      }
     }
   }
   if (bad) atomicOr(&st->flags, (unsigned)bad);
@@ -334,8 +368,13 @@ hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T
   if (T.nactive <= 0) return hipSuccess;
   const int per_xcd = (T.nactive + 7) / 8;
   const unsigned grid = 8u * (unsigned)per_xcd;
-#define AMRVAC_FUSED_LAUNCH(ND, SPT) \
-  k_stage_fused<ND, SPT><<<grid, 256, 0, s>>>(G, T, J, per_xcd, in, base, out, w, P, st)
+#define AMRVAC_FUSED_LAUNCH(ND, SPT)                                                       \
+  do {                                                                                     \
+    if (w == 1.0)                                                                          \
+      k_stage_fused<ND, SPT, true><<<grid, 256, 0, s>>>(G, T, J, per_xcd, in, base, out, w, P, st); \
+    else                                                                                   \
+      k_stage_fused<ND, SPT, false><<<grid, 256, 0, s>>>(G, T, J, per_xcd, in, base, out, w, P, st); \
+  } while (0)
   if (G.precision == 0) {
     if (G.ndim == 3)
       AMRVAC_FUSED_LAUNCH(3, StoreF64);
