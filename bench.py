@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64",
                     help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
     ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud"], default="random_modes")
+    ap.add_argument("--tune", default="auto",
+                    help="fused-stage launch shape: 'auto' (autotuner, before the warmup), 'default', or z,r,x")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph-pass", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -90,6 +92,14 @@ def main():
     sim = amrvac.Simulation(w, path=path, precision=amrvac.FP32_MIXED if mixed else amrvac.FP64)
     state_bytes = 40.0 if mixed else 72.0
     stream = sim.stream
+    tune_times = {}
+    if path == amrvac.PATH_FUSED and args.tune != "default":
+        if args.tune == "auto":
+            print("bench: autotuning the fused stage", file=sys.stderr, flush=True)
+            _, tune_times = sim.autotune(in_slot=0, out_slot=1, reps=3)
+        else:
+            sim.set_tune(*[int(v) for v in args.tune.split(",")])
+    tune = sim.get_tune() if path == amrvac.PATH_FUSED else None
     weights = [(0, 0, 1, 1.0), (1, 0, 2, 0.25), (2, 0, 0, 2.0 / 3.0)]
 
     def step(events=None):
@@ -159,7 +169,9 @@ def main():
         "config": {"workload": "%s: 3D, %d leaf blocks of 16^3 + 2 ghost layers on %d level(s), %s GLM-MHD "
                                "state, SSPRK(3,3), CFL 0.8, %s" % (w.name, w.nblocks, w.max_level, args.workload,
                                                                   "FP32-mixed" if mixed else "FP64"),
-                   "path": args.path, "cells": cells, "stage_weights": [1.0, 0.25, 2.0 / 3.0]},
+                   "path": args.path, "cells": cells, "stage_weights": [1.0, 0.25, 2.0 / 3.0],
+                   "tune": None if tune is None else {"zseg": tune[0], "rotate": tune[1], "xcd": tune[2]}},
+        "autotune_ms_per_launch": {"%d,%d,%d" % k: round(v, 4) for k, v in tune_times.items()},
         "algorithmic_hbm_gbs_per_step": cells * 8 * state_bytes / (ms_per_step * 1e-3) / 1e9,
         "graph_ms_per_step": graph_ms,
         "stage_ms": [sum(x) / K for x in stage_ms],

@@ -149,6 +149,42 @@ int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph);
  * of FP32-mixed contexts).  AMRVAC_E_ARG if the context cannot run it. */
 int amrvac_set_path(amrvac_ctx* c, int path);
 
+/* Launch shape of the fused stage.  Every shape gives bit-identical results;
+ * they differ only in speed.
+ *   zseg:   workgroups per 3D block, each marching 16/zseg of its z planes
+ *           (1, 2 or 4; 1 in 2D).  More, shorter workgroups fill the GPU on
+ *           small grids at the cost of re-reading 4 planes per segment.
+ *   rotate: 1 rotates the per-plane extra work (halo cells, halo slopes and
+ *           the 17th face of each line) over the four waves of a workgroup,
+ *           0 leaves it to the first waves.
+ *   xcd:    1 gives each of the 8 XCDs a contiguous run of the Morton-ordered
+ *           block list (neighbours share an L2), 0 deals workgroups out in
+ *           list order.
+ * The default is {1, 0, 1}. */
+typedef struct {
+  int zseg;
+  int rotate;
+  int xcd;
+} amrvac_tune;
+
+#define AMRVAC_TUNE_MAX_CANDIDATES 12
+
+/* Set / read the launch shape.  AMRVAC_E_ARG for an invalid shape.  A
+ * change synchronises the stream and drops the captured step graph. */
+int amrvac_set_tune(amrvac_ctx* c, const amrvac_tune* t);
+int amrvac_get_tune(const amrvac_ctx* c, amrvac_tune* t);
+
+/* Autotuner: time every launch shape (zseg-major, then rotate, then xcd;
+ * 12 candidates in 3D, 4 in 2D) on this context's own grid, as reps fused
+ * stages of weight 1 from in_slot into out_slot after one untimed launch,
+ * with dt, c_h and kappa from the CFL of in_slot, and keep the fastest.
+ * Needs a single-job context on the fused path.  out_slot is overwritten;
+ * in_slot's ghost cells are filled; the flag word and fix count are left as
+ * they were.  Synchronises the stream.  best (may be NULL) receives the
+ * chosen shape, ms (may be NULL; AMRVAC_TUNE_MAX_CANDIDATES floats) the mean
+ * time per launch of each candidate, ncand (may be NULL) their number. */
+int amrvac_autotune(amrvac_ctx* c, int in_slot, int out_slot, int reps, amrvac_tune* best, float* ms, int* ncand);
+
 /* Synchronise the stream and read the device flag word (AMRVAC_FLAG_* bits
  * accumulated since the last reset), the number of cells fixed by the
  * small-value fix, and the last dt written by amrvac_advance.  Returns

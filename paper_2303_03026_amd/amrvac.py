@@ -26,7 +26,9 @@ ABI_SYMBOLS = ("amrvac_slot_bytes", "amrvac_init_blocks", "amrvac_set_primitive"
                "amrvac_fill_ghosts", "amrvac_cfl_dt", "amrvac_stage", "amrvac_advance", "amrvac_set_path",
                "amrvac_sync_flags", "amrvac_reset_flags", "amrvac_last_error", "amrvac_destroy",
                "amrvac_batch_create", "amrvac_batch_add_job", "amrvac_batch_step", "amrvac_batch_job_info",
-               "amrvac_batch_get_job", "amrvac_batch_remove_job", "amrvac_batch_free_blocks")
+               "amrvac_batch_get_job", "amrvac_batch_remove_job", "amrvac_batch_free_blocks",
+               "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune")
+TUNE_MAX_CANDIDATES = 12
 
 
 class AmrvacError(RuntimeError):
@@ -44,6 +46,20 @@ class GridDesc(ctypes.Structure):
         ("cfl", ctypes.c_double), ("glm_alpha", ctypes.c_double), ("small_density", ctypes.c_double),
         ("small_pressure", ctypes.c_double), ("bc_fixed_prim", ctypes.c_double * (3 * 2 * NV)),
     ]
+
+
+class Tune(ctypes.Structure):
+    """Launch shape of the fused stage (amrvac_tune)."""
+    _fields_ = [("zseg", ctypes.c_int), ("rotate", ctypes.c_int), ("xcd", ctypes.c_int)]
+
+    def as_tuple(self):
+        return (self.zseg, self.rotate, self.xcd)
+
+
+def tune_candidates(ndim: int):
+    """The autotuner's candidates in its enumeration order."""
+    zs = (1, 2, 4) if ndim == 3 else (1,)
+    return [(z, r, x) for z in zs for r in (0, 1) for x in (0, 1)]
 
 
 _lib = None
@@ -82,6 +98,10 @@ def load_library():
     lib.amrvac_batch_get_job.argtypes = [vp, ctypes.c_int, vp]
     lib.amrvac_batch_remove_job.argtypes = [vp, ctypes.c_int]
     lib.amrvac_batch_free_blocks.argtypes = [vp, ip, ip]
+    lib.amrvac_set_tune.argtypes = [vp, ctypes.POINTER(Tune)]
+    lib.amrvac_get_tune.argtypes = [vp, ctypes.POINTER(Tune)]
+    lib.amrvac_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Tune),
+                                    ctypes.POINTER(ctypes.c_float), ip]
     _lib = lib
     return lib
 
@@ -246,8 +266,65 @@ class Simulation:
     def reset_flags(self):
         self._check(self.lib.amrvac_reset_flags(self.ctx), self.ctx)
 
+    def set_tune(self, zseg: int, rotate: int, xcd: int):
+        t = Tune(zseg, rotate, xcd)
+        self._check(self.lib.amrvac_set_tune(self.ctx, ctypes.byref(t)), self.ctx)
+
+    def get_tune(self):
+        t = Tune()
+        self._check(self.lib.amrvac_get_tune(self.ctx, ctypes.byref(t)), self.ctx)
+        return t.as_tuple()
+
+    def autotune(self, in_slot: int = 0, out_slot: int = 1, reps: int = 5, cache: Optional[str] = None):
+        """Pick the fused stage's launch shape by timing every candidate on
+        this grid (amrvac_autotune) and keep it.  With ``cache`` (a JSON file
+        path) a shape measured before for the same grid shape is reused
+        without timing, and a new measurement is added to the file.  Returns
+        (shape, {candidate: ms per launch}); the times are empty on a hit."""
+        key = tune_key(self.w, self.desc.precision)
+        if cache is not None:
+            hit = _cache_load(cache).get(key)
+            if hit is not None:
+                self.set_tune(*hit)
+                return tuple(hit), {}
+        best = Tune()
+        ms = (ctypes.c_float * TUNE_MAX_CANDIDATES)()
+        n = ctypes.c_int()
+        self._check(self.lib.amrvac_autotune(self.ctx, in_slot, out_slot, reps, ctypes.byref(best), ms,
+                                             ctypes.byref(n)), self.ctx)
+        times = dict(zip(tune_candidates(self.w.ndim), [float(ms[k]) for k in range(n.value)]))
+        if cache is not None:
+            _cache_store(cache, key, best.as_tuple())
+        return best.as_tuple(), times
+
     def synchronize(self):
         self.stream.synchronize()
+
+
+def tune_key(w, precision: int) -> str:
+    """Autotune cache key: dimension, precision, level count and leaf blocks
+    per level (the launch shape's speed depends on these, not on the data)."""
+    levels = np.bincount(np.asarray(w.level, dtype=np.int64))[1:]
+    return "d%d-p%d-%s" % (w.ndim, precision, ".".join(str(int(n)) for n in levels))
+
+
+def _cache_load(path: str) -> dict:
+    import json
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _cache_store(path: str, key: str, shape) -> None:
+    import json
+    d = _cache_load(path)
+    d[key] = list(shape)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 def run(w, nsteps: Optional[int] = None, graph: bool = False, path: int = PATH_PLAIN) -> np.ndarray:
@@ -347,6 +424,19 @@ class Batch:
         if rc != 0:
             self._err(rc)
         self.jobs.pop(job, None)
+
+    def set_tune(self, zseg: int, rotate: int, xcd: int):
+        t = Tune(zseg, rotate, xcd)
+        rc = self.lib.amrvac_set_tune(self.ctx, ctypes.byref(t))
+        if rc != 0:
+            self._err(rc)
+
+    def get_tune(self):
+        t = Tune()
+        rc = self.lib.amrvac_get_tune(self.ctx, ctypes.byref(t))
+        if rc != 0:
+            self._err(rc)
+        return t.as_tuple()
 
     def free_blocks(self):
         big, tot = ctypes.c_int(), ctypes.c_int()

@@ -20,7 +20,10 @@ namespace {
 
 constexpr int BN = 16;          // block cells per direction
 constexpr int BP = BN + 4;      // padded extent
-constexpr int SLOPE_ROW = BN + 2;
+// LDS row strides, one double (or float) longer than the data so that the
+// strided (y-direction and 17th-face) accesses of 16 lanes hit distinct banks
+constexpr int WROW = BP + 1;       // plane of primitives: BP rows of BP cells
+constexpr int SLOPE_ROW = BN + 3;  // slopes: BN lines of cells -1..16
 
 template <int NDIM>
 struct Pad {
@@ -40,17 +43,17 @@ __device__ __forceinline__ void load_cons(const void* __restrict__ U, long pc, l
 // from the plane primitives and the slopes of the two cells; first-order
 // fallback when rho or p is not positive on either side.
 template <int DIR, class R>
-__device__ __forceinline__ void face_states(const R (*Wp)[BP * BP], const R (*Sl)[SLOPE_ROW * BN], int line, int f,
+__device__ __forceinline__ void face_states(const R (*Wp)[BP * WROW], const R (*Sl)[SLOPE_ROW * BN], int line, int f,
                                             R wl[NV], R wr[NV]) {
   R wm[NV], wp[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     if (DIR == 0) {
-      wm[q] = Wp[q][(line + 2) * BP + f + 1];
-      wp[q] = Wp[q][(line + 2) * BP + f + 2];
+      wm[q] = Wp[q][(line + 2) * WROW + f + 1];
+      wp[q] = Wp[q][(line + 2) * WROW + f + 2];
     } else {
-      wm[q] = Wp[q][(f + 1) * BP + line + 2];
-      wp[q] = Wp[q][(f + 2) * BP + line + 2];
+      wm[q] = Wp[q][(f + 1) * WROW + line + 2];
+      wp[q] = Wp[q][(f + 2) * WROW + line + 2];
     }
     wl[q] = wm[q] + R(0.5) * Sl[q][line * SLOPE_ROW + f];
     wr[q] = wp[q] - R(0.5) * Sl[q][line * SLOPE_ROW + f + 1];
@@ -66,18 +69,18 @@ __device__ __forceinline__ void face_states(const R (*Wp)[BP * BP], const R (*Sl
 
 // van Leer slope along DIR of LDS cell (line, a), a in -1..16
 template <int DIR, class R>
-__device__ __forceinline__ void cell_slope(const R (*Wp)[BP * BP], R (*Sl)[SLOPE_ROW * BN], int line, int a) {
+__device__ __forceinline__ void cell_slope(const R (*Wp)[BP * WROW], R (*Sl)[SLOPE_ROW * BN], int line, int a) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     R m, c, p;
     if (DIR == 0) {
-      m = Wp[q][(line + 2) * BP + a + 1];
-      c = Wp[q][(line + 2) * BP + a + 2];
-      p = Wp[q][(line + 2) * BP + a + 3];
+      m = Wp[q][(line + 2) * WROW + a + 1];
+      c = Wp[q][(line + 2) * WROW + a + 2];
+      p = Wp[q][(line + 2) * WROW + a + 3];
     } else {
-      m = Wp[q][(a + 1) * BP + line + 2];
-      c = Wp[q][(a + 2) * BP + line + 2];
-      p = Wp[q][(a + 3) * BP + line + 2];
+      m = Wp[q][(a + 1) * WROW + line + 2];
+      c = Wp[q][(a + 2) * WROW + line + 2];
+      p = Wp[q][(a + 3) * WROW + line + 2];
     }
     Sl[q][line * SLOPE_ROW + a + 1] = vl_slope(c - m, p - c);
   }
@@ -92,14 +95,17 @@ struct FaceConst {
 // One in-plane direction: slopes -> sync -> face fluxes -> sync -> flux
 // difference of this thread's cell added to acc (scaled by 1/dx); the
 // energy difference is accumulated in double (acc_e).
+// The halo slopes (cells -1 and 16 of every line) and the 17th face of every
+// line are done by the lanes of wave xw (extra lane e = t - 64 xw).
 template <int DIR, class R>
-__device__ __forceinline__ void plane_direction(const R (*Wp)[BP * BP], R (*Sl)[SLOPE_ROW * BN],
-                                                R (*Fl)[(BN + 1) * BN], int t, int i, int j, const FaceConst<R>& K,
-                                                double inv_dx, R acc[NV], double& acc_e) {
+__device__ __forceinline__ void plane_direction(const R (*Wp)[BP * WROW], R (*Sl)[SLOPE_ROW * BN],
+                                                R (*Fl)[(BN + 1) * BN], int t, int i, int j, int xw,
+                                                const FaceConst<R>& K, double inv_dx, R acc[NV], double& acc_e) {
   const int line = DIR == 0 ? j : i;
   const int f = DIR == 0 ? i : j;
+  const int e = t - 64 * xw;
   cell_slope<DIR>(Wp, Sl, line, f);
-  if (t < 32) cell_slope<DIR>(Wp, Sl, t & 15, t < 16 ? -1 : BN);
+  if ((unsigned)e < 32u) cell_slope<DIR>(Wp, Sl, e & 15, e < 16 ? -1 : BN);
   __syncthreads();
   {
     R wl[NV], wr[NV], F[NV];
@@ -108,12 +114,12 @@ __device__ __forceinline__ void plane_direction(const R (*Wp)[BP * BP], R (*Sl)[
 #pragma unroll
     for (int q = 0; q < NV; ++q) Fl[q][line * (BN + 1) + f] = F[q];
   }
-  if (t < 16) {  // the 17th face of line t
+  if ((unsigned)e < 16u) {  // the 17th face of line e
     R wl[NV], wr[NV], F[NV];
-    face_states<DIR>(Wp, Sl, t, BN, wl, wr);
+    face_states<DIR>(Wp, Sl, e, BN, wl, wr);
     hll_glm_flux<DIR, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, F);
 #pragma unroll
-    for (int q = 0; q < NV; ++q) Fl[q][t * (BN + 1) + BN] = F[q];
+    for (int q = 0; q < NV; ++q) Fl[q][e * (BN + 1) + BN] = F[q];
   }
   __syncthreads();
   const R idr = (R)inv_dx;
@@ -128,22 +134,28 @@ __device__ __forceinline__ void plane_direction(const R (*Wp)[BP * BP], R (*Sl)[
 }
 
 // W1: the stage weight is 1 (out = in + dt L(in)), so base is not read.
+// Work item w (one z segment of one block) is run by workgroup g with
+// w = (g % 8) * per_xcd + g / 8 when tune.xcd is set (each XCD gets a
+// contiguous run of the Morton-ordered list), else w = g.
 template <int NDIM, class SP, bool W1>
 __global__ void __launch_bounds__(256, SP::kWavesPerEU)
-k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __restrict__ in, const void* base,
-              void* out, double wgt, PhysConst P, DevStatus* st) {
+k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, const void* __restrict__ in,
+              const void* base, void* out, double wgt, PhysConst P, DevStatus* st) {
   using R = typename SP::R;
   using PD = Pad<NDIM>;
   constexpr long PC = PD::cells;
-  __shared__ R Wp[NV][BP * BP];          // primitives of the current plane (+ x/y halo)
+  __shared__ R Wp[NV][BP * WROW];          // primitives of the current plane (+ x/y halo)
   __shared__ R Sl[NV][SLOPE_ROW * BN];   // slopes of one direction, cells -1..16 per line
   __shared__ R Fl[NV][(BN + 1) * BN];    // face fluxes of one direction, faces 0..16 per line
 
-  // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
-  // contiguous run of the Morton-ordered block list so that neighbouring
-  // blocks run together on one L2.
-  const int slot = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  // Workgroups are dealt to the 8 XCDs round-robin; with tune.xcd each XCD
+  // gets a contiguous run of the Morton-ordered block list so that
+  // neighbouring blocks (and the segments of one block) share one L2.
+  const int wi = tune.xcd ? (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+  const int nseg = NDIM == 3 ? tune.zseg : 1;
+  const int slot = wi / nseg;
   if (slot >= T.nactive) return;
+  const int seg = wi - slot * nseg;
   const int b = T.order[slot];
   const int t = threadIdx.x;
   const int i = t & 15, j = t >> 4;
@@ -167,18 +179,23 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
   int bad = 0;
   unsigned nfix = 0;
 
-  // halo cell of this thread for the x/y stencil of a plane (threads 0..127)
-  int hx = 0, hy = 0;
-  const bool has_halo = t < 128;
-  if (t < 64) {
-    hy = t >> 2;
-    const int o = t & 3;
-    hx = o < 2 ? o - 2 : BN + o - 2;
-  } else if (t < 128) {
-    hx = t & 15;
-    const int o = (t >> 4) & 3;
-    hy = o < 2 ? o - 2 : BN + o - 2;
+  // Halo cell of this thread for the x/y stencil of a plane: 128 cells, done
+  // by threads 0..127 on planes of parity 0 and by threads 128..255 on planes
+  // of parity 1, where a plane's parity is 0 unless tune.rot is set.
+  int hx, hy;
+  {
+    const int h = t & 127;
+    if (h < 64) {
+      hy = h >> 2;
+      const int o = h & 3;
+      hx = o < 2 ? o - 2 : BN + o - 2;
+    } else {
+      hx = h & 15;
+      const int o = (h >> 4) & 3;
+      hy = o < 2 ? o - 2 : BN + o - 2;
+    }
   }
+  const int hpar = t >> 7;
   const int hf = hx < 0 ? 0 : (hx >= BN ? 1 : (hy < 0 ? 2 : 3));
   const void* __restrict__ Uh = block_ptr<SP>(in, srcb[hf], PC);
   const int hxs = hx + (hf < 2 ? sh[hf] : 0), hys = hy + (hf >= 2 ? sh[hf] : 0);
@@ -199,6 +216,20 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
   // face k+1/2 (W(k) + sigma(k)/2) and acc, which enters plane k already
   // holding the contribution -F_z(k-1/2)/dz of the face below; W(k) itself
   // sits in this thread's cell of the LDS plane.
+  // This workgroup marches planes k0 .. k1-1 (the whole block unless the z
+  // range is split into segments).
+  const int klen = BN / nseg;
+  const int k0 = NDIM == 3 ? seg * klen : 0;
+  const int k1 = NDIM == 3 ? k0 + klen : 1;
+  // conserved state of this thread's column at plane p, -2 <= p < BN + 2
+  auto load_z = [&](int p, double u[NV]) {
+    if (p < 0)
+      load_cons<SP>(Uzlo, PC, PD::at(i, j, p + shzlo), u);
+    else if (p >= BN)
+      load_cons<SP>(Uzhi, PC, PD::at(i, j, p + shzhi), u);
+    else
+      load_cons<SP>(U, PC, PD::at(i, j, p), u);
+  };
   R wb[NV], wla[NV], acc[NV];
   double acc_e = 0.0;
 #pragma unroll
@@ -206,17 +237,17 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
   {
     double u[NV];
     R wa[NV];
-    load_cons<SP>(U, PC, PD::at(i, j, 0), u);
+    load_cons<SP>(U, PC, PD::at(i, j, k0), u);
     convert(u, wa);
 #pragma unroll
-    for (int q = 0; q < NV; ++q) Wp[q][(j + 2) * BP + (i + 2)] = wa[q];
+    for (int q = 0; q < NV; ++q) Wp[q][(j + 2) * WROW + (i + 2)] = wa[q];
     if (NDIM == 3) {
       R wm2[NV], wm1[NV];
-      load_cons<SP>(Uzlo, PC, PD::at(i, j, -2 + shzlo), u);
+      load_z(k0 - 2, u);
       convert(u, wm2);
-      load_cons<SP>(Uzlo, PC, PD::at(i, j, -1 + shzlo), u);
+      load_z(k0 - 1, u);
       convert(u, wm1);
-      load_cons<SP>(U, PC, PD::at(i, j, 1), u);
+      load_z(k0 + 1, u);
       convert(u, wb);
       R wl[NV], wr[NV], fz[NV];
 #pragma unroll
@@ -248,30 +279,33 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
     }
   }
 
-  constexpr int NK = NDIM == 3 ? BN : 1;
-  for (int k = 0; k < NK; ++k) {
+  for (int k = k0; k < k1; ++k) {
     // prefetch the conserved state of plane k+2 (consumed by the z step)
     double uc[NV];
-    if (NDIM == 3) {
-      if (k + 2 < BN)
-        load_cons<SP>(U, PC, PD::at(i, j, k + 2), uc);
-      else
-        load_cons<SP>(Uzhi, PC, PD::at(i, j, k + 2 + shzhi), uc);
-    }
+    if (NDIM == 3) load_z(k + 2, uc);
+
+    // who does this plane's extra work: the halo threads of parity par and
+    // the waves xw / yw for the x / y halo slopes and 17th faces; with
+    // tune.rot the four parts go to four different waves, rotating with the
+    // plane, else to threads 0..127 and wave 0
+    const int rk = k + slot;
+    const int par = tune.rot ? (rk & 1) : 0;
+    const int xw = tune.rot ? 2 * (1 - par) + ((rk >> 1) & 1) : 0;
+    const int yw = tune.rot ? (xw ^ 1) : 0;
 
     // ---- plane k halo into LDS (this thread's own cell is already there)
-    if (has_halo) {
+    if (hpar == par) {
       double u[NV];
       R w[NV];
       load_cons<SP>(Uh, PC, PD::at(hxs, hys, k), u);
       convert(u, w);
 #pragma unroll
-      for (int q = 0; q < NV; ++q) Wp[q][(hy + 2) * BP + (hx + 2)] = w[q];
+      for (int q = 0; q < NV; ++q) Wp[q][(hy + 2) * WROW + (hx + 2)] = w[q];
     }
     __syncthreads();
 
-    plane_direction<0, R>(Wp, Sl, Fl, t, i, j, K, idx, acc, acc_e);
-    plane_direction<1, R>(Wp, Sl, Fl, t, i, j, K, idy, acc, acc_e);
+    plane_direction<0, R>(Wp, Sl, Fl, t, i, j, xw, K, idx, acc, acc_e);
+    plane_direction<1, R>(Wp, Sl, Fl, t, i, j, yw, K, idy, acc, acc_e);
 
     // this plane's conserved state and the stage base, issued as one group
     const long c = PD::at(i, j, k);
@@ -284,7 +318,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
     if (NDIM == 3) {
       R wa[NV], wc[NV];
 #pragma unroll
-      for (int q = 0; q < NV; ++q) wa[q] = Wp[q][(j + 2) * BP + (i + 2)];
+      for (int q = 0; q < NV; ++q) wa[q] = Wp[q][(j + 2) * WROW + (i + 2)];
       convert(uc, wc);
       R wl[NV], wr[NV];
 #pragma unroll
@@ -314,7 +348,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
           acc[q] = acc[q] + fz[q];
         }
         // W(k+1) goes into this thread's LDS cell for the next plane
-        Wp[q][(j + 2) * BP + (i + 2)] = wb[q];
+        Wp[q][(j + 2) * WROW + (i + 2)] = wb[q];
         wb[q] = wc[q];
       }
     }
@@ -362,18 +396,20 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, int per_xcd, const void* __re
 }  // namespace
 
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
-                              const void* in, const void* base, void* out, double w, const PhysConst& P,
-                              DevStatus* st) {
+                              const FusedTune& tune, const void* in, const void* base, void* out, double w,
+                              const PhysConst& P, DevStatus* st) {
   if (G.nx != BN) return hipErrorInvalidValue;
+  if (tune.zseg != 1 && tune.zseg != 2 && tune.zseg != 4) return hipErrorInvalidValue;
   if (T.nactive <= 0) return hipSuccess;
-  const int per_xcd = (T.nactive + 7) / 8;
-  const unsigned grid = 8u * (unsigned)per_xcd;
+  const long items = (long)T.nactive * (G.ndim == 3 ? tune.zseg : 1);
+  const int per_xcd = (int)((items + 7) / 8);
+  const unsigned grid = tune.xcd ? 8u * (unsigned)per_xcd : (unsigned)items;
 #define AMRVAC_FUSED_LAUNCH(ND, SPT)                                                       \
   do {                                                                                     \
     if (w == 1.0)                                                                          \
-      k_stage_fused<ND, SPT, true><<<grid, 256, 0, s>>>(G, T, J, per_xcd, in, base, out, w, P, st); \
+      k_stage_fused<ND, SPT, true><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st); \
     else                                                                                   \
-      k_stage_fused<ND, SPT, false><<<grid, 256, 0, s>>>(G, T, J, per_xcd, in, base, out, w, P, st); \
+      k_stage_fused<ND, SPT, false><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st); \
   } while (0)
   if (G.precision == 0) {
     if (G.ndim == 3)

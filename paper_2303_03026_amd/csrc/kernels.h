@@ -83,9 +83,20 @@ hipError_t launch_update(hipStream_t s, const GridConst& G, const Tables& T, con
                          void* out, double w, FluxPtrs flux, const double* dt_dev, const double* kappa_dev);
 
 // fused stage (nx = 16) and the coarse/fine correction that follows it -------
+// Launch shape of the fused stage (results do not depend on it):
+//   zseg: workgroups per block, each marching BN / zseg z planes (1, 2, 4;
+//         3D only)
+//   rot:  rotate the per-plane extra work (halo cells, halo slopes, 17th
+//         faces) over the four waves of a workgroup
+//   xcd:  give each XCD a contiguous run of the block list
+struct FusedTune {
+  int zseg;
+  int rot;
+  int xcd;
+};
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
-                              const void* in, const void* base, void* out, double w, const PhysConst& P,
-                              DevStatus* st);
+                              const FusedTune& tune, const void* in, const void* base, void* out, double w,
+                              const PhysConst& P, DevStatus* st);
 hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                                  const int* tasks, int ntasks, const void* in, void* out, double w,
                                  const PhysConst& P);

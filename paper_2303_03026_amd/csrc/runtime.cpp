@@ -308,6 +308,7 @@ struct amrvac_ctx {
   hipGraph_t graph = nullptr;
   int graph_stages = 0;
   int graph_path = -1;
+  FusedTune tune{1, 0, 1};  // launch shape of the fused stage
   std::string err;
 
   Tables tables() const { return Tables{d_level, d_job, d_invdx, d_link, d_pos, d_wrap, d_order, n_order}; }
@@ -395,9 +396,7 @@ int rebuild(amrvac_ctx* c) {
   return AMRVAC_OK;
 }
 
-int ensure_tables(amrvac_ctx* c) {
-  if (!c->dirty) return AMRVAC_OK;
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+void drop_graph(amrvac_ctx* c) {
   if (c->graph_exec) {
     (void)hipGraphExecDestroy(c->graph_exec);
     c->graph_exec = nullptr;
@@ -406,6 +405,12 @@ int ensure_tables(amrvac_ctx* c) {
     (void)hipGraphDestroy(c->graph);
     c->graph = nullptr;
   }
+}
+
+int ensure_tables(amrvac_ctx* c) {
+  if (!c->dirty) return AMRVAC_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
   return rebuild(c);
 }
 
@@ -486,8 +491,8 @@ int fill_slot(amrvac_ctx* c, int slot) {
 int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScalars& J) {
   const Tables T = c->tables();
   if (c->path == AMRVAC_PATH_FUSED) {
-    HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->slots[in], c->slots[base], c->slots[out], w, c->P,
-                                  c->d_status));
+    HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->tune, c->slots[in], c->slots[base], c->slots[out], w,
+                                  c->P, c->d_status));
     HIP_TRY(c, launch_reflux_correct(c->stream, c->G, T, J, c->d_trefl, c->n_trefl, c->slots[in], c->slots[out], w,
                                      c->P));
     return AMRVAC_OK;
@@ -677,14 +682,7 @@ int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph) {
     return AMRVAC_OK;
   }
   if (!c->graph_exec || c->graph_stages != nstages || c->graph_path != c->path) {
-    if (c->graph_exec) {
-      (void)hipGraphExecDestroy(c->graph_exec);
-      c->graph_exec = nullptr;
-    }
-    if (c->graph) {
-      (void)hipGraphDestroy(c->graph);
-      c->graph = nullptr;
-    }
+    drop_graph(c);
     if (c->stream == nullptr) return fail(c, AMRVAC_E_STATE, "graph capture needs a non-null stream");
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_step(c, nstages, dt, ch, kap);
@@ -701,6 +699,93 @@ int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph) {
     c->graph_path = c->path;
   }
   for (int n = 0; n < nsteps; ++n) HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+  return AMRVAC_OK;
+}
+
+int amrvac_set_tune(amrvac_ctx* c, const amrvac_tune* t) {
+  if (!c) return AMRVAC_E_ARG;
+  if (!t) return fail(c, AMRVAC_E_ARG, "null tune");
+  if (t->zseg != 1 && t->zseg != 2 && t->zseg != 4) return fail(c, AMRVAC_E_ARG, "zseg must be 1, 2 or 4");
+  if (c->G.ndim == 2 && t->zseg != 1) return fail(c, AMRVAC_E_ARG, "zseg must be 1 in 2D");
+  if ((t->rotate != 0 && t->rotate != 1) || (t->xcd != 0 && t->xcd != 1))
+    return fail(c, AMRVAC_E_ARG, "rotate and xcd are 0 or 1");
+  const FusedTune nt{t->zseg, t->rotate, t->xcd};
+  if (nt.zseg != c->tune.zseg || nt.rot != c->tune.rot || nt.xcd != c->tune.xcd) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->tune = nt;
+  }
+  return AMRVAC_OK;
+}
+
+int amrvac_get_tune(const amrvac_ctx* c, amrvac_tune* t) {
+  if (!c || !t) return AMRVAC_E_ARG;
+  t->zseg = c->tune.zseg;
+  t->rotate = c->tune.rot;
+  t->xcd = c->tune.xcd;
+  return AMRVAC_OK;
+}
+
+int amrvac_autotune(amrvac_ctx* c, int in, int out, int reps, amrvac_tune* best, float* ms, int* ncand) {
+  if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "autotune a single-job context of the same shape");
+  if (c->path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_STATE, "autotune needs the fused path");
+  if (int rc = check_slot(c, in)) return rc;
+  if (int rc = check_slot(c, out)) return rc;
+  if (in == out) return fail(c, AMRVAC_E_ARG, "in and out slots must differ");
+  if (reps < 1 || reps > 1000) return fail(c, AMRVAC_E_ARG, "reps must be in 1..1000");
+  if (int rc = ensure_tables(c)) return rc;
+  // candidates, zseg-major then rotate then xcd
+  std::vector<FusedTune> cand;
+  for (int z : {1, 2, 4}) {
+    if (c->G.ndim == 2 && z != 1) continue;
+    for (int r = 0; r < 2; ++r)
+      for (int x = 0; x < 2; ++x) cand.push_back(FusedTune{z, r, x});
+  }
+  // the status record (flags, fix count, last dt) is restored afterwards
+  DevStatus* saved = nullptr;
+  HIP_TRY(c, hipMalloc(&saved, sizeof(DevStatus)));
+  std::vector<float> times(cand.size(), 0.0f);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMemcpyAsync(saved, c->d_status, sizeof(DevStatus), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess)
+    e = launch_cfl(c->stream, c->G, c->tables(), c->slots[in], c->P, c->d_status,
+                   cfl_state(c, c->d_jdt, c->d_jch, c->d_jkappa));
+  int rc = AMRVAC_OK;
+  if (e == hipSuccess) rc = fill_slot(c, in);
+  const JobScalars J{c->d_jdt, c->d_jch, c->d_jkappa};
+  const Tables T = c->tables();
+  for (size_t k = 0; k < cand.size() && e == hipSuccess && rc == AMRVAC_OK; ++k) {
+    e = launch_fused_stage(c->stream, c->G, T, J, cand[k], c->slots[in], c->slots[out], c->slots[out], 1.0, c->P,
+                           c->d_status);
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+      e = launch_fused_stage(c->stream, c->G, T, J, cand[k], c->slots[in], c->slots[out], c->slots[out], 1.0,
+                             c->P, c->d_status);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&times[k], e0, e1);
+    times[k] /= (float)reps;
+  }
+  if (e == hipSuccess && rc == AMRVAC_OK)
+    e = hipMemcpyAsync(c->d_status, saved, sizeof(DevStatus), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && rc == AMRVAC_OK) e = hipStreamSynchronize(c->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(saved);
+  if (rc != AMRVAC_OK) return rc;
+  if (e != hipSuccess) return fail(c, AMRVAC_E_HIP, std::string("autotune: ") + hipGetErrorString(e));
+  size_t kb = 0;
+  for (size_t k = 1; k < cand.size(); ++k)
+    if (times[k] < times[kb]) kb = k;
+  drop_graph(c);
+  c->tune = cand[kb];
+  if (best) amrvac_get_tune(c, best);
+  if (ms)
+    for (size_t k = 0; k < cand.size(); ++k) ms[k] = times[k];
+  if (ncand) *ncand = (int)cand.size();
   return AMRVAC_OK;
 }
 
