@@ -25,6 +25,19 @@ constexpr int BP = BN + 4;      // padded extent
 constexpr int WROW = BP + 1;       // plane of primitives: BP rows of BP cells
 constexpr int SLOPE_ROW = BN + 3;  // slopes: BN lines of cells -1..16
 
+// Workgroup barrier that orders LDS accesses only.  Every exchange between
+// the threads of a workgroup in this kernel goes through LDS, so global loads
+// in flight (the z-plane prefetch, the halo staging) stay in flight across it
+// instead of being drained as a full fence would.
+// (The compiler-level memory clobbers keep LDS accesses on their side; the
+// wait makes this wave's LDS writes complete before it arrives.)
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt untouched
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <int NDIM>
 struct Pad {
   static constexpr long cells = NDIM == 3 ? (long)BP * BP * BP : (long)BP * BP;
@@ -43,7 +56,7 @@ __device__ __forceinline__ void load_cons(const void* __restrict__ U, long pc, l
 // from the plane primitives and the slopes of the two cells; first-order
 // fallback when rho or p is not positive on either side.
 template <int DIR, class R>
-__device__ __forceinline__ void face_states(const R (*Wp)[BP * WROW], const R (*Sl)[SLOPE_ROW * BN], int line, int f,
+__device__ __forceinline__ void face_states(const R (*__restrict__ Wp)[BP * WROW], const R (*__restrict__ Sl)[SLOPE_ROW * BN], int line, int f,
                                             R wl[NV], R wr[NV]) {
   R wm[NV], wp[NV];
 #pragma unroll
@@ -69,7 +82,7 @@ __device__ __forceinline__ void face_states(const R (*Wp)[BP * WROW], const R (*
 
 // van Leer slope along DIR of LDS cell (line, a), a in -1..16
 template <int DIR, class R>
-__device__ __forceinline__ void cell_slope(const R (*Wp)[BP * WROW], R (*Sl)[SLOPE_ROW * BN], int line, int a) {
+__device__ __forceinline__ void cell_slope(const R (*__restrict__ Wp)[BP * WROW], R (*__restrict__ Sl)[SLOPE_ROW * BN], int line, int a) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     R m, c, p;
@@ -86,6 +99,25 @@ __device__ __forceinline__ void cell_slope(const R (*Wp)[BP * WROW], R (*Sl)[SLO
   }
 }
 
+// Halo cell h (0..127) of a plane's x/y stencil: h < 64 are the x-halo
+// cells (x = -2, -1, 16, 17 of row h / 4), the rest the y-halo rows
+// (y = -2, -1, 16, 17, x = h % 16).  Cells 2m and 2m+1 are neighbours in x.
+struct HaloXY {
+  int x, y;
+};
+__device__ __forceinline__ HaloXY halo_cell(int h) {
+  const bool xh = h < 64;
+  const int o = xh ? (h & 3) : ((h >> 4) & 3);
+  const int edge = o < 2 ? o - 2 : BN + o - 2;
+  return HaloXY{xh ? edge : (h & 15), xh ? (h >> 2) : edge};
+}
+
+// LDS address of a __shared__ object, for the direct global->LDS loads
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(3))) void* lds_addr(T* p) {
+  return (__attribute__((address_space(3))) void*)p;
+}
+
 // Face-arithmetic constants of one launch, in the face precision.
 template <class R>
 struct FaceConst {
@@ -98,15 +130,16 @@ struct FaceConst {
 // The halo slopes (cells -1 and 16 of every line) and the 17th face of every
 // line are done by the lanes of wave xw (extra lane e = t - 64 xw).
 template <int DIR, class R>
-__device__ __forceinline__ void plane_direction(const R (*Wp)[BP * WROW], R (*Sl)[SLOPE_ROW * BN],
-                                                R (*Fl)[(BN + 1) * BN], int t, int i, int j, int xw,
-                                                const FaceConst<R>& K, double inv_dx, R acc[NV], double& acc_e) {
+__device__ __forceinline__ void plane_direction(const R (*__restrict__ Wp)[BP * WROW], R (*__restrict__ Sl)[SLOPE_ROW * BN],
+                                                R (*__restrict__ Fl)[(BN + 1) * BN], int t, int i, int j, int xw,
+                                                const FaceConst<R>& K, double inv_dx, R acc[NV], double& acc_e,
+                                                bool drain_vmem) {
   const int line = DIR == 0 ? j : i;
   const int f = DIR == 0 ? i : j;
   const int e = t - 64 * xw;
   cell_slope<DIR>(Wp, Sl, line, f);
   if ((unsigned)e < 32u) cell_slope<DIR>(Wp, Sl, e & 15, e < 16 ? -1 : BN);
-  __syncthreads();
+  lds_barrier();
   {
     R wl[NV], wr[NV], F[NV];
     face_states<DIR>(Wp, Sl, line, f, wl, wr);
@@ -121,7 +154,10 @@ __device__ __forceinline__ void plane_direction(const R (*Wp)[BP * WROW], R (*Sl
 #pragma unroll
     for (int q = 0; q < NV; ++q) Fl[q][e * (BN + 1) + BN] = F[q];
   }
-  __syncthreads();
+  // a wave with direct global->LDS loads in flight completes them before the
+  // barrier that publishes them (vmcnt(0); expcnt and lgkmcnt untouched)
+  if (drain_vmem) __builtin_amdgcn_s_waitcnt(0x0F70);
+  lds_barrier();
   const R idr = (R)inv_dx;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -147,6 +183,19 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
   __shared__ R Wp[NV][BP * WROW];          // primitives of the current plane (+ x/y halo)
   __shared__ R Sl[NV][SLOPE_ROW * BN];   // slopes of one direction, cells -1..16 per line
   __shared__ R Fl[NV][(BN + 1) * BN];    // face fluxes of one direction, faces 0..16 per line
+  // LDS staging of the next plane's 128 halo cells (3D; conserved, storage
+  // precision), written by direct global->LDS loads (global_load_lds) of one
+  // wave while the current plane is computed, so the halo's memory latency
+  // is off the critical path.  One such load of a wave writes 64 consecutive
+  // lane slots: 16 bytes (cells 2m, 2m+1 of a double array) or 4 bytes (cell
+  // m of a float array).
+  // (Only the arrays of the instantiation's storage are referenced; the
+  // others are dropped.  Their sizes are not template-dependent, which
+  // clang's host pass needs for the 16-byte form of the builtin.)
+  constexpr bool kF64 = SP::kBytesPerCell == 72;
+  __shared__ double HsD[NV * 128];     // FP64 state, [var][cell]
+  __shared__ float HsF[(NV - 1) * 128];  // mixed: rho, m, B, psi
+  __shared__ double HsE[128];          // mixed: e
 
   // Workgroups are dealt to the 8 XCDs round-robin; with tune.xcd each XCD
   // gets a contiguous run of the Morton-ordered block list so that
@@ -163,14 +212,18 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
   // Halo source per face: a same-level neighbour is read in place (its
   // interior, shifted by one block); other faces use this block's ghost
   // cells, filled by the ghost kernels.
-  int srcb[6], sh[6];
-#pragma unroll
-  for (int f = 0; f < 2 * NDIM; ++f) {
+  // (named scalars, not arrays: the per-lane selects below would otherwise
+  // turn an array into scratch memory)
+  auto face_src = [&](int f) {
     const int* Lk = T.link + ((long)b * 6 + f) * LINK_INTS;
-    const bool same = Lk[0] == LINK_SAME;
-    srcb[f] = same ? Lk[1] : b;
-    sh[f] = same ? ((f & 1) ? -BN : BN) : 0;
-  }
+    return Lk[0] == LINK_SAME ? Lk[1] : b;
+  };
+  auto face_shift = [&](int f) {
+    const int* Lk = T.link + ((long)b * 6 + f) * LINK_INTS;
+    return Lk[0] == LINK_SAME ? ((f & 1) ? -BN : BN) : 0;
+  };
+  const int sb0 = face_src(0), sb1 = face_src(1), sb2 = face_src(2), sb3 = face_src(3);
+  const int sh0 = face_shift(0), sh1 = face_shift(1), sh2 = face_shift(2), sh3 = face_shift(3);
   const int job = T.job[b];
   const double dt = J.dt[job], kappa = J.kappa[job], chd = J.ch[job];
   const FaceConst<R> K{(R)chd, (R)(0.5 / chd), (R)P.gamma, (R)P.inv_gm1};
@@ -182,27 +235,71 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
   // Halo cell of this thread for the x/y stencil of a plane: 128 cells, done
   // by threads 0..127 on planes of parity 0 and by threads 128..255 on planes
   // of parity 1, where a plane's parity is 0 unless tune.rot is set.
-  int hx, hy;
-  {
-    const int h = t & 127;
-    if (h < 64) {
-      hy = h >> 2;
-      const int o = h & 3;
-      hx = o < 2 ? o - 2 : BN + o - 2;
+  const HaloXY hc = halo_cell(t & 127);
+  const int hx = hc.x, hy = hc.y;
+  const int hpar = t >> 7;
+  // source block of halo cell (x, y) and the cell's index there in plane p
+  struct HaloSrc {
+    const void* blk;
+    long cell0;  // padded index of the cell in plane 0
+  };
+  auto halo_src = [&](HaloXY c) {
+    const bool xlo = c.x < 0, xhi = c.x >= BN, ylo = c.y < 0;
+    const int sb = xlo ? sb0 : (xhi ? sb1 : (ylo ? sb2 : sb3));
+    const int xs = c.x + (xlo ? sh0 : (xhi ? sh1 : 0));
+    const int ys = c.y + (xlo || xhi ? 0 : (ylo ? sh2 : sh3));
+    return HaloSrc{block_ptr<SP>(in, sb, PC), PD::at(xs, ys, 0)};
+  };
+  // padded cells between consecutive z planes
+  constexpr long PLANE = (long)BP * BP;
+  const HaloSrc hs = halo_src(hc);
+  // wave 3 stages the next plane's halo (3D).  Lane m's sources in plane 0:
+  // FP64, the pair 2m, 2m+1 of every variable; mixed, float cells m and
+  // 64 + m and the energy pair 2m, 2m+1.
+  const double* stg_d = nullptr;
+  const float *stg_f1 = nullptr, *stg_f2 = nullptr;
+  if (NDIM == 3) {
+    const int m = t & 63;
+    const HaloSrc a = halo_src(halo_cell(2 * m));
+    if constexpr (kF64) {
+      stg_d = static_cast<const double*>(a.blk) + a.cell0;
     } else {
-      hx = h & 15;
-      const int o = (h >> 4) & 3;
-      hy = o < 2 ? o - 2 : BN + o - 2;
+      const HaloSrc s1 = halo_src(halo_cell(m)), s2 = halo_src(halo_cell(64 + m));
+      stg_f1 = static_cast<const float*>(s1.blk) + s1.cell0;
+      stg_f2 = static_cast<const float*>(s2.blk) + s2.cell0;
+      stg_d = reinterpret_cast<const double*>(static_cast<const char*>(a.blk) + 32 * PC) + a.cell0;
     }
   }
-  const int hpar = t >> 7;
-  const int hf = hx < 0 ? 0 : (hx >= BN ? 1 : (hy < 0 ? 2 : 3));
-  const void* __restrict__ Uh = block_ptr<SP>(in, srcb[hf], PC);
-  const int hxs = hx + (hf < 2 ? sh[hf] : 0), hys = hy + (hf >= 2 ? sh[hf] : 0);
+  const bool stager = NDIM == 3 && t >= 192;
+  auto stage_halo = [&](int p) {
+    const long off = p * PLANE;
+    if constexpr (kF64) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q)
+        __builtin_amdgcn_global_load_lds(stg_d + off + q * PC, lds_addr(&HsD[q * 128]), 16, 0, 0);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NV - 1; ++q) {
+        __builtin_amdgcn_global_load_lds(stg_f1 + off + q * PC, lds_addr(&HsF[q * 128]), 4, 0, 0);
+        __builtin_amdgcn_global_load_lds(stg_f2 + off + q * PC, lds_addr(&HsF[q * 128 + 64]), 4, 0, 0);
+      }
+      __builtin_amdgcn_global_load_lds(stg_d + off, lds_addr(&HsE[0]), 16, 0, 0);
+    }
+  };
+  // staged conserved values of halo cell h
+  auto staged = [&](int h, double u[NV]) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if constexpr (kF64)
+        u[q] = HsD[q * 128 + h];
+      else
+        u[q] = q == I_EN ? HsE[h] : (double)HsF[StoreMixed::fidx(q) * 128 + h];
+    }
+  };
   // z ghost planes come from faces 4 (below) and 5 (above)
-  const void* __restrict__ Uzlo = block_ptr<SP>(in, srcb[NDIM == 3 ? 4 : 0], PC);
-  const void* __restrict__ Uzhi = block_ptr<SP>(in, srcb[NDIM == 3 ? 5 : 0], PC);
-  const int shzlo = NDIM == 3 ? sh[4] : 0, shzhi = NDIM == 3 ? sh[5] : 0;
+  const void* __restrict__ Uzlo = block_ptr<SP>(in, NDIM == 3 ? face_src(4) : b, PC);
+  const void* __restrict__ Uzhi = block_ptr<SP>(in, NDIM == 3 ? face_src(5) : b, PC);
+  const int shzlo = NDIM == 3 ? face_shift(4) : 0, shzhi = NDIM == 3 ? face_shift(5) : 0;
 
   auto convert = [&](const double u[NV], R w[NV]) {
     const int bb = cons_to_prim(u, w, P);
@@ -279,6 +376,19 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
     }
   }
 
+  // halo parity of plane k: halo cells are converted by threads 0..127 on
+  // planes of parity 0 and by 128..255 on planes of parity 1
+  auto parity = [&](int k) { return tune.rot ? ((k + slot) & 1) : 0; };
+  // plane k0's halo straight from memory
+  if (hpar == parity(k0)) {
+    double u[NV];
+    R w[NV];
+    load_cons<SP>(hs.blk, PC, hs.cell0 + k0 * PLANE, u);
+    convert(u, w);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Wp[q][(hy + 2) * WROW + (hx + 2)] = w[q];
+  }
+
   for (int k = k0; k < k1; ++k) {
     // prefetch the conserved state of plane k+2 (consumed by the z step)
     double uc[NV];
@@ -289,23 +399,18 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
     // tune.rot the four parts go to four different waves, rotating with the
     // plane, else to threads 0..127 and wave 0
     const int rk = k + slot;
-    const int par = tune.rot ? (rk & 1) : 0;
+    const int par = parity(k);
     const int xw = tune.rot ? 2 * (1 - par) + ((rk >> 1) & 1) : 0;
     const int yw = tune.rot ? (xw ^ 1) : 0;
 
-    // ---- plane k halo into LDS (this thread's own cell is already there)
-    if (hpar == par) {
-      double u[NV];
-      R w[NV];
-      load_cons<SP>(Uh, PC, PD::at(hxs, hys, k), u);
-      convert(u, w);
-#pragma unroll
-      for (int q = 0; q < NV; ++q) Wp[q][(hy + 2) * WROW + (hx + 2)] = w[q];
-    }
-    __syncthreads();
+    // plane k's primitives (own cells and halo) are complete in LDS, and the
+    // staging buffer has been read
+    lds_barrier();
+    const bool staging = stager && k + 1 < k1;
+    if (staging) stage_halo(k + 1);
 
-    plane_direction<0, R>(Wp, Sl, Fl, t, i, j, xw, K, idx, acc, acc_e);
-    plane_direction<1, R>(Wp, Sl, Fl, t, i, j, yw, K, idy, acc, acc_e);
+    plane_direction<0, R>(Wp, Sl, Fl, t, i, j, xw, K, idx, acc, acc_e, false);
+    plane_direction<1, R>(Wp, Sl, Fl, t, i, j, yw, K, idy, acc, acc_e, staging);
 
     // this plane's conserved state and the stage base, issued as one group
     const long c = PD::at(i, j, k);
@@ -386,6 +491,16 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
           acc_e = -fze;
         else
           acc[q] = -fz[q];
+      }
+      // ---- plane k+1 halo: staged conserved values -> primitives in LDS
+      // (no thread reads this plane's halo after its last barrier)
+      if (k + 1 < k1 && hpar == parity(k + 1)) {
+        double uh[NV];
+        R w[NV];
+        staged(t & 127, uh);
+        convert(uh, w);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Wp[q][(hy + 2) * WROW + (hx + 2)] = w[q];
       }
     }
   }
