@@ -20,6 +20,68 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mcell-updates/s + HBM GB/s (FP64 vs FP32/batched); p50/p99 job latency"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per stage launch measured with rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch; FETCH scaled by 2.0 and WRITE by 1.0, the
+# factors a plain 1 GiB device copy gives), on the random-mode 256^3 grid,
+# per launch shape (zseg, rotate, xcd): (w == 1, w < 1) pairs of (fetch KiB,
+# write KiB), from `bench.py --sweep-shapes --calib-copy` under
+# `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE`.  They describe the
+# kernel sources whose hash is the key; after any change to those sources the
+# figure is reported as null.
+KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
+                  "paper_2303_03026_amd/csrc/kernels.h")
+MEASURED_TRAFFIC = {
+    ("a782f5dcb1783247", "f64"): {
+        (1, 0, 0): ((2856960, 1475061), (3640047, 1475287)),
+        (1, 0, 1): ((2709979, 1474976), (3562642, 1475329)),
+        (1, 1, 0): ((2864772, 1475030), (3653727, 1475668)),
+        (1, 1, 1): ((2697050, 1475097), (3553997, 1475749)),
+        (2, 0, 0): ((3068991, 1474832), (3858776, 1475222)),
+        (2, 0, 1): ((2940788, 1474872), (3800966, 1475246)),
+        (2, 1, 0): ((3089740, 1475004), (3859245, 1475414)),
+        (2, 1, 1): ((2923931, 1475051), (3783512, 1475501)),
+        (4, 0, 0): ((3515325, 1474654), (4303498, 1474833)),
+        (4, 0, 1): ((3181707, 1474696), (4046468, 1474819)),
+        (4, 1, 0): ((3514119, 1474790), (4304565, 1474957)),
+        (4, 1, 1): ((3163182, 1474777), (4091852, 1474937)),
+    },
+    ("a782f5dcb1783247", "mixed"): {
+        (1, 0, 0): ((1711338, 819543), (2175214, 819600)),
+        (1, 0, 1): ((1570069, 819541), (2074973, 819649)),
+        (1, 1, 0): ((1709398, 819487), (2169409, 819744)),
+        (1, 1, 1): ((1569922, 819532), (2075415, 819837)),
+        (2, 0, 0): ((1824828, 819419), (2299417, 819485)),
+        (2, 0, 1): ((1703348, 819415), (2215840, 819466)),
+        (2, 1, 0): ((1830279, 819458), (2304422, 819614)),
+        (2, 1, 1): ((1708713, 819458), (2216367, 819604)),
+        (4, 0, 0): ((2097987, 819267), (2560220, 819368)),
+        (4, 0, 1): ((1829178, 819245), (2369586, 819333)),
+        (4, 1, 0): ((2103255, 819294), (2564128, 819356)),
+        (4, 1, 1): ((1827771, 819264), (2371650, 819362)),
+    },
+}
+FETCH_CAL, WRITE_CAL = 2.0, 1.0
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision, tune, workload, n):
+    """Counter bytes per stage launch (mean over one step's three stages),
+    or None when no measurement matches the current kernel and shape."""
+    if workload != "random_modes" or n != 256 or tune is None:
+        return None
+    m = MEASURED_TRAFFIC.get((kernel_hash(), precision), {}).get(tuple(tune))
+    if m is None:
+        return None
+    per = [(f * FETCH_CAL + w * WRITE_CAL) * 1024.0 for f, w in m]
+    return (per[0] + 2 * per[1]) / 3.0
 # Algorithmic HBM bytes per cell for one stage launch: read the input state,
 # write the output state, and read the base state when the stage weight is
 # not 1; one state is 72 B per cell in FP64 and 40 B in FP32-mixed.
@@ -39,6 +101,9 @@ def parse():
                     help="fused-stage launch shape: 'auto' (autotuner, before the warmup), 'default', or z,r,x")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph-pass", action="store_true")
+    ap.add_argument("--sweep-shapes", action="store_true",
+                    help="profiling helper: run one w=1 and one w<1 fused stage per launch shape, in the "
+                         "autotuner's order, print the order and exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (calibrates HBM counters)")
     return ap.parse_args()
@@ -92,6 +157,19 @@ def main():
     sim = amrvac.Simulation(w, path=path, precision=amrvac.FP32_MIXED if mixed else amrvac.FP64)
     state_bytes = 40.0 if mixed else 72.0
     stream = sim.stream
+    if args.sweep_shapes:
+        order = amrvac.tune_candidates(3)
+        sim.cfl(0)
+        for shape in order:
+            sim.set_tune(*shape)
+            sim.fill(0)
+            sim.stage(0, 0, 1, 1.0)
+            sim.fill(1)
+            sim.stage(1, 0, 2, 0.25)
+        sim.sync_flags()
+        sim.close()
+        print(json.dumps({"sweep_shapes": order, "launches_per_shape": ["w=1", "w<1"]}), flush=True)
+        return
     tune_times = {}
     if path == amrvac.PATH_FUSED and args.tune != "default":
         if args.tune == "auto":
@@ -142,6 +220,8 @@ def main():
     bytes_per_launch = cells * state_bytes * (2 + 3 + 3) / 3.0
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 
+    traffic = measured_traffic(args.precision, tune, args.workload, args.n) if args.path == "fused" else None
+
     graph_ms = None
     if not args.no_graph_pass:
         sim.advance(2, graph=True)
@@ -176,7 +256,7 @@ def main():
         "graph_ms_per_step": graph_ms,
         "stage_ms": [sum(x) / K for x in stage_ms],
         "roofline": {"bound": "hbm", "kernel": "stage (%s path)" % args.path, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms},
     }
     if not args.no_cpu_baseline:
