@@ -181,12 +181,14 @@ def main():
     weights = [(0, 0, 1, 1.0), (1, 0, 2, 0.25), (2, 0, 0, 2.0 / 3.0)]
 
     def step(events=None):
+        # the last stage folds the next step's CFL rate in (fused path), so
+        # cfl() is then only the final reduction
         sim.cfl(0)
         for s, (i, b, o, wt) in enumerate(weights):
             sim.fill(i)
             if events is not None:
                 events[s][0].record(stream)
-            sim.stage(i, b, o, wt)
+            sim.stage(i, b, o, wt, cfl=(s == len(weights) - 1))
             if events is not None:
                 events[s][1].record(stream)
 

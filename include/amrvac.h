@@ -124,6 +124,8 @@ int amrvac_fill_ghosts(amrvac_ctx* c, int slot);
  * small value or an invalid dt sets the context's device flag word (read it
  * with amrvac_sync_flags).  No host synchronisation. */
 int amrvac_cfl_dt(amrvac_ctx* c, int slot, double* dt_dev, double* ch_dev, double* kappa_dev);
+/* (When the last call that wrote slot was amrvac_stage_cfl and its rate is
+ * still held, only the final reduction runs; the result is identical.) */
 
 /* One explicit stage (the advect1 statement of the IMEX implementation
  * section, with the SSPRK combination folded in):
@@ -135,6 +137,17 @@ int amrvac_cfl_dt(amrvac_ctx* c, int slot, double* dt_dev, double* ch_dev, doubl
  * filled; in != out; out may equal base. */
 int amrvac_stage(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double w,
                  const double* dt_dev, const double* ch_dev, const double* kappa_dev);
+
+/* amrvac_stage that also folds the CFL rate of every output cell (the
+ * quantity amrvac_cfl_dt maximises, from the values as stored) into the
+ * context's per-job running maximum, so that a following amrvac_cfl_dt on
+ * out_slot skips its pass over the state: the usual last stage of an SSPRK
+ * step.  The held rate is dropped when anything else writes out_slot, when
+ * amrvac_cfl_dt runs on another slot or when the block tables change.  On
+ * the plain path and on grids with coarse/fine flux corrections (which
+ * change the output after the stage) it is exactly amrvac_stage. */
+int amrvac_stage_cfl(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double w,
+                     const double* dt_dev, const double* ch_dev, const double* kappa_dev);
 
 /* Advance nsteps full SSPRK steps of slot 0 (nstages 1, 2 or 3), using
  * slots 1 and 2 as stage storage and library-owned dt/c_h/kappa; each step

@@ -27,7 +27,7 @@ ABI_SYMBOLS = ("amrvac_slot_bytes", "amrvac_init_blocks", "amrvac_set_primitive"
                "amrvac_sync_flags", "amrvac_reset_flags", "amrvac_last_error", "amrvac_destroy",
                "amrvac_batch_create", "amrvac_batch_add_job", "amrvac_batch_step", "amrvac_batch_job_info",
                "amrvac_batch_get_job", "amrvac_batch_remove_job", "amrvac_batch_free_blocks",
-               "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune")
+               "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune", "amrvac_stage_cfl")
 TUNE_MAX_CANDIDATES = 12
 
 
@@ -83,6 +83,7 @@ def load_library():
     lib.amrvac_fill_ghosts.argtypes = [vp, ctypes.c_int]
     lib.amrvac_cfl_dt.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.amrvac_stage.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+    lib.amrvac_stage_cfl.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
     lib.amrvac_advance.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.amrvac_set_path.argtypes = [vp, ctypes.c_int]
     lib.amrvac_sync_flags.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong), dp]
@@ -239,9 +240,12 @@ class Simulation:
             self.scal[:3] = self.torch.tensor([dt, ch, kappa], dtype=self.torch.float64)
         self.stream.synchronize()
 
-    def stage(self, in_slot: int, base_slot: int, out_slot: int, weight: float):
-        self._check(self.lib.amrvac_stage(self.ctx, in_slot, base_slot, out_slot, weight, self.dt_ptr,
-                                          self.ch_ptr, self.kappa_ptr), self.ctx)
+    def stage(self, in_slot: int, base_slot: int, out_slot: int, weight: float, cfl: bool = False):
+        """One stage; with cfl=True (amrvac_stage_cfl) the output's CFL rate
+        is folded in for the next cfl() on out_slot."""
+        fn = self.lib.amrvac_stage_cfl if cfl else self.lib.amrvac_stage
+        self._check(fn(self.ctx, in_slot, base_slot, out_slot, weight, self.dt_ptr, self.ch_ptr, self.kappa_ptr),
+                    self.ctx)
 
     def euler_stage(self, in_slot: int = 0, out_slot: int = 1):
         self.fill(in_slot)

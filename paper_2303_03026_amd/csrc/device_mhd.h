@@ -151,6 +151,23 @@ __device__ __forceinline__ R cfast(const R w[NV], R ri, R b2, R gamma) {
   return sqrt_(R(0.5) * (s + sqrt_(disc)));
 }
 
+// CFL rate of one cell from its conserved state (always FP64): the sum over
+// directions of (|v_d| + c_fast,d) / dx_d, after the small-value check of the
+// conserved-to-primitive step (its bits are or-ed into bad).  The time-step
+// pass and the fused last stage both use this, so they agree bit for bit.
+template <int NDIM>
+__device__ __forceinline__ double cell_rate(const double u[NV], const PhysConst& P, double ix, double iy, double iz,
+                                            int& bad) {
+  double w[NV];
+  bad |= cons_to_prim(u, w, P);
+  const double ri = rcp_(w[I_RHO]);
+  const double b2 = w[I_BX] * w[I_BX] + w[I_BY] * w[I_BY] + w[I_BZ] * w[I_BZ];
+  double rate = (fabs(w[1]) + cfast<0>(w, ri, b2, P.gamma)) * ix;
+  rate = rate + (fabs(w[2]) + cfast<1>(w, ri, b2, P.gamma)) * iy;
+  if (NDIM == 3) rate = rate + (fabs(w[3]) + cfast<2>(w, ri, b2, P.gamma)) * iz;
+  return rate;
+}
+
 // Interface flux along D from reconstructed left/right primitive states:
 // GLM interface values of (B_n, psi) from the exact solution of the linear
 // subsystem, then HLL (Davis bounds) on rho, m, e and the tangential B,
@@ -257,6 +274,8 @@ struct StoreF64 {
   __device__ static void st(void* blk, int q, long c, long pc, double v) {
     static_cast<double*>(blk)[q * pc + c] = v;
   }
+  // the value a later load of variable q returns after st(v)
+  __device__ static double as_stored(int, double v) { return v; }
 };
 
 struct StoreMixed {
@@ -274,6 +293,7 @@ struct StoreMixed {
     else
       static_cast<float*>(blk)[fidx(q) * pc + c] = (float)v;
   }
+  __device__ static double as_stored(int q, double v) { return q == I_EN ? v : (double)(float)v; }
 };
 
 template <class SP>

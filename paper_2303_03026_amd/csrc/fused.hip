@@ -170,13 +170,15 @@ __device__ __forceinline__ void plane_direction(const R (*__restrict__ Wp)[BP * 
 }
 
 // W1: the stage weight is 1 (out = in + dt L(in)), so base is not read.
+// CFL: also fold the CFL rate of every output cell into the job's running
+// maximum (C.rate_bits, C.nan), as the time-step pass would from out.
 // Work item w (one z segment of one block) is run by workgroup g with
 // w = (g % 8) * per_xcd + g / 8 when tune.xcd is set (each XCD gets a
 // contiguous run of the Morton-ordered list), else w = g.
-template <int NDIM, class SP, bool W1>
+template <int NDIM, class SP, bool W1, bool CFL>
 __global__ void __launch_bounds__(256, SP::kWavesPerEU)
 k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, const void* __restrict__ in,
-              const void* base, void* out, double wgt, PhysConst P, DevStatus* st) {
+              const void* base, void* out, double wgt, PhysConst P, DevStatus* st, JobCfl C) {
   using R = typename SP::R;
   using PD = Pad<NDIM>;
   constexpr long PC = PD::cells;
@@ -231,6 +233,8 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
   const R idzr = (R)idz;
   int bad = 0;
   unsigned nfix = 0;
+  double rmax = 0.0;  // CFL: running max of this thread's output cells
+  int rnan = 0;
 
   // Halo cell of this thread for the x/y stencil of a plane: 128 cells, done
   // by threads 0..127 on planes of parity 0 and by threads 128..255 on planes
@@ -465,6 +469,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
     // (out may be the base slot: each cell is read before it is written, by
     // the same thread)
     void* o = block_ptr<SP>(out, b, PC);
+    double un[NV];  // CFL: the output cell as a later load would see it
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       double res;
@@ -483,6 +488,14 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
         }
       }
       SP::st(o, q, c, PC, res);
+      if (CFL) un[q] = SP::as_stored(q, res);
+    }
+    if (CFL) {
+      const double rate = cell_rate<NDIM>(un, P, idx, idy, idz, bad);
+      if (isnan(rate))
+        rnan = 1;
+      else
+        rmax = fmax(rmax, rate);
     }
     if (NDIM == 3) {
 #pragma unroll
@@ -504,6 +517,27 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
       }
     }
   }
+  if (CFL) {
+    // workgroup max (wave max, then over the four waves in LDS), one atomic
+    // per workgroup on the job's word (non-negative doubles order as their
+    // bit patterns)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+    __shared__ double wmax[4];
+    __shared__ int wnan[4];
+    const int lane = t & 63, wave = t >> 6;
+    const int anynan = __any(rnan);
+    if (lane == 0) {
+      wmax[wave] = rmax;
+      wnan[wave] = anynan;
+    }
+    lds_barrier();
+    if (t == 0) {
+      const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+      atomicMax(&C.rate_bits[job], (unsigned long long)__double_as_longlong(m));
+      if (wnan[0] | wnan[1] | wnan[2] | wnan[3]) atomicOr(&C.nan[job], 1u);
+    }
+  }
   if (bad) atomicOr(&st->flags, (unsigned)bad);
   if (nfix) atomicAdd(&st->nfix, (unsigned long long)nfix);
 }
@@ -512,19 +546,29 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
 
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                               const FusedTune& tune, const void* in, const void* base, void* out, double w,
-                              const PhysConst& P, DevStatus* st) {
+                              const PhysConst& P, DevStatus* st, const JobCfl* cfl) {
   if (G.nx != BN) return hipErrorInvalidValue;
   if (tune.zseg != 1 && tune.zseg != 2 && tune.zseg != 4) return hipErrorInvalidValue;
   if (T.nactive <= 0) return hipSuccess;
   const long items = (long)T.nactive * (G.ndim == 3 ? tune.zseg : 1);
   const int per_xcd = (int)((items + 7) / 8);
   const unsigned grid = tune.xcd ? 8u * (unsigned)per_xcd : (unsigned)items;
-#define AMRVAC_FUSED_LAUNCH(ND, SPT)                                                       \
-  do {                                                                                     \
-    if (w == 1.0)                                                                          \
-      k_stage_fused<ND, SPT, true><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st); \
-    else                                                                                   \
-      k_stage_fused<ND, SPT, false><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st); \
+  const JobCfl C = cfl ? *cfl : JobCfl{};
+#define AMRVAC_FUSED_KERNEL(ND, SPT, W1, CF) \
+  k_stage_fused<ND, SPT, W1, CF><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st, C)
+#define AMRVAC_FUSED_LAUNCH(ND, SPT)               \
+  do {                                             \
+    if (cfl) {                                     \
+      if (w == 1.0)                                \
+        AMRVAC_FUSED_KERNEL(ND, SPT, true, true);  \
+      else                                         \
+        AMRVAC_FUSED_KERNEL(ND, SPT, false, true); \
+    } else {                                       \
+      if (w == 1.0)                                \
+        AMRVAC_FUSED_KERNEL(ND, SPT, true, false); \
+      else                                         \
+        AMRVAC_FUSED_KERNEL(ND, SPT, false, false); \
+    }                                              \
   } while (0)
   if (G.precision == 0) {
     if (G.ndim == 3)
@@ -538,6 +582,7 @@ hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T
       AMRVAC_FUSED_LAUNCH(2, StoreMixed);
   }
 #undef AMRVAC_FUSED_LAUNCH
+#undef AMRVAC_FUSED_KERNEL
   return hipGetLastError();
 }
 

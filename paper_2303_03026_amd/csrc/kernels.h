@@ -94,16 +94,24 @@ struct FusedTune {
   int rot;
   int xcd;
 };
+// cfl (may be null): also fold each job's CFL rate of the output interior
+// into cfl->rate_bits / cfl->nan (as launch_cfl_accumulate would from out).
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                               const FusedTune& tune, const void* in, const void* base, void* out, double w,
-                              const PhysConst& P, DevStatus* st);
+                              const PhysConst& P, DevStatus* st, const JobCfl* cfl);
 hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                                  const int* tasks, int ntasks, const void* in, void* out, double w,
                                  const PhysConst& P);
 
-// CFL: per-job max rate over the active blocks, then per-job dt, c_h, kappa
+// CFL: per-job max rate over the active blocks (accumulate), then per-job
+// dt, c_h, kappa, which also empties the accumulators (finalize); launch_cfl
+// does both.  launch_cfl_clear empties the accumulators.
+hipError_t launch_cfl_accumulate(hipStream_t s, const GridConst& G, const Tables& T, const void* slot,
+                                 const PhysConst& P, DevStatus* st, const JobCfl& C);
+hipError_t launch_cfl_finalize(hipStream_t s, DevStatus* st, const JobCfl& C);
 hipError_t launch_cfl(hipStream_t s, const GridConst& G, const Tables& T, const void* slot, const PhysConst& P,
                       DevStatus* st, const JobCfl& C);
+hipError_t launch_cfl_clear(hipStream_t s, const JobCfl& C);
 
 // conversion over the block range [first, first + count) ------------------
 hipError_t launch_set_prim(hipStream_t s, const GridConst& G, int first, int count, const double* prim, void* slot,

@@ -433,15 +433,10 @@ __global__ void __launch_bounds__(256) k_cfl(GridConst G, Tables T, const void* 
   for (int c = threadIdx.x; c < (int)G.icells; c += blockDim.x) {
     const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
     const long pc = pidx(G, i, j, k);
-    double u[NV], w[NV];
+    double u[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) u[q] = SP::ld(blk, q, pc, G.pcells);
-    bad |= cons_to_prim(u, w, P);
-    const double ri = rcp_(w[I_RHO]);
-    const double b2 = w[I_BX] * w[I_BX] + w[I_BY] * w[I_BY] + w[I_BZ] * w[I_BZ];
-    double rate = (fabs(w[1]) + cfast<0>(w, ri, b2, P.gamma)) * ix;
-    rate = rate + (fabs(w[2]) + cfast<1>(w, ri, b2, P.gamma)) * iy;
-    if (G.ndim == 3) rate = rate + (fabs(w[3]) + cfast<2>(w, ri, b2, P.gamma)) * iz;
+    const double rate = G.ndim == 3 ? cell_rate<3>(u, P, ix, iy, iz, bad) : cell_rate<2>(u, P, ix, iy, iz, bad);
     if (isnan(rate))
       nan_seen = 1;
     else
@@ -460,6 +455,15 @@ __global__ void __launch_bounds__(256) k_cfl(GridConst G, Tables T, const void* 
   }
   if (bad) atomicOr(&st->flags, (unsigned)bad);
   if (nan_seen) atomicOr(&C.nan[job], 1u);
+}
+
+// Empty the per-job rate accumulators (a kernel rather than a memset, so
+// that the clear can sit in a captured graph).
+__global__ void k_cfl_clear(JobCfl C) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= C.njobs) return;
+  C.rate_bits[j] = 0ull;
+  C.nan[j] = 0u;
 }
 
 // dt = C / max rate, c_h = C / (dt sum_d 1/dx_d), kappa = alpha c_h / min dx
@@ -603,17 +607,30 @@ hipError_t launch_update(hipStream_t s, const GridConst& G, const Tables& T, con
   return hipGetLastError();
 }
 
+hipError_t launch_cfl_accumulate(hipStream_t s, const GridConst& G, const Tables& T, const void* slot,
+                                 const PhysConst& P, DevStatus* st, const JobCfl& C) {
+  if (T.nactive <= 0) return hipSuccess;
+  if (G.precision == 0)
+    k_cfl<StoreF64><<<T.nactive, 256, 0, s>>>(G, T, slot, P, st, C);
+  else
+    k_cfl<StoreMixed><<<T.nactive, 256, 0, s>>>(G, T, slot, P, st, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_finalize(hipStream_t s, DevStatus* st, const JobCfl& C) {
+  k_cfl_finalize<<<nblocks_for(C.njobs, 64), 64, 0, s>>>(C, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_cfl(hipStream_t s, const GridConst& G, const Tables& T, const void* slot, const PhysConst& P,
                       DevStatus* st, const JobCfl& C) {
-  if (T.nactive > 0) {
-    if (G.precision == 0)
-      k_cfl<StoreF64><<<T.nactive, 256, 0, s>>>(G, T, slot, P, st, C);
-    else
-      k_cfl<StoreMixed><<<T.nactive, 256, 0, s>>>(G, T, slot, P, st, C);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  k_cfl_finalize<<<nblocks_for(C.njobs, 64), 64, 0, s>>>(C, st);
+  hipError_t e = launch_cfl_accumulate(s, G, T, slot, P, st, C);
+  if (e != hipSuccess) return e;
+  return launch_cfl_finalize(s, st, C);
+}
+
+hipError_t launch_cfl_clear(hipStream_t s, const JobCfl& C) {
+  k_cfl_clear<<<nblocks_for(C.njobs, 64), 64, 0, s>>>(C);
   return hipGetLastError();
 }
 

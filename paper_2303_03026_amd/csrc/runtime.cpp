@@ -309,6 +309,12 @@ struct amrvac_ctx {
   int graph_stages = 0;
   int graph_path = -1;
   FusedTune tune{1, 0, 1};  // launch shape of the fused stage
+  // CFL rate accumulators (d_rate, d_nan): carry_slot >= 0 means they hold
+  // the rate of that slot's current interior, folded in by the fused stage
+  // that wrote it; acc_dirty means they may hold anything and must be
+  // emptied before the next accumulation.  Otherwise they are empty.
+  int carry_slot = -1;
+  bool acc_dirty = false;
   std::string err;
 
   Tables tables() const { return Tables{d_level, d_job, d_invdx, d_link, d_pos, d_wrap, d_order, n_order}; }
@@ -407,10 +413,27 @@ void drop_graph(amrvac_ctx* c) {
   }
 }
 
+// The accumulators no longer describe slot s (it is being written).
+void touch_slot(amrvac_ctx* c, int s) {
+  if (c->carry_slot == s) {
+    c->carry_slot = -1;
+    c->acc_dirty = true;
+  }
+}
+
+// Forget any carried rate (the accumulators must be emptied before use).
+void drop_carry(amrvac_ctx* c) {
+  if (c->carry_slot >= 0) {
+    c->carry_slot = -1;
+    c->acc_dirty = true;
+  }
+}
+
 int ensure_tables(amrvac_ctx* c) {
   if (!c->dirty) return AMRVAC_OK;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   drop_graph(c);
+  drop_carry(c);  // job slots and block lists change
   return rebuild(c);
 }
 
@@ -488,11 +511,54 @@ int fill_slot(amrvac_ctx* c, int slot) {
   return AMRVAC_OK;
 }
 
-int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScalars& J) {
+JobCfl cfl_state(amrvac_ctx* c, double* dt, double* ch, double* kappa) {
+  return JobCfl{c->d_rate, c->d_nan, c->d_geom, dt, ch, kappa, c->njob_cap};
+}
+
+// The fused stage can fold the next step's CFL rate into its output only
+// where nothing changes that output afterwards (no coarse/fine flux
+// correction).
+bool can_carry(const amrvac_ctx* c) { return c->path == AMRVAC_PATH_FUSED && c->n_trefl == 0; }
+
+int clear_if_dirty(amrvac_ctx* c) {
+  if (c->acc_dirty) {
+    HIP_TRY(c, launch_cfl_clear(c->stream, cfl_state(c, nullptr, nullptr, nullptr)));
+    c->acc_dirty = false;
+  }
+  return AMRVAC_OK;
+}
+
+// dt, c_h, kappa from slot: only the finalize kernel when the accumulators
+// carry slot's rate, else empty them if needed, accumulate and finalize.
+int cfl_of_slot(amrvac_ctx* c, int slot, double* dt, double* ch, double* kap) {
+  const JobCfl C = cfl_state(c, dt, ch, kap);
+  if (c->carry_slot != slot) {
+    drop_carry(c);
+    if (int rc = clear_if_dirty(c)) return rc;
+    HIP_TRY(c, launch_cfl_accumulate(c->stream, c->G, c->tables(), c->slots[slot], c->P, c->d_status, C));
+  }
+  HIP_TRY(c, launch_cfl_finalize(c->stream, c->d_status, C));
+  c->carry_slot = -1;
+  c->acc_dirty = false;
+  return AMRVAC_OK;
+}
+
+// fold_cfl: on the fused path without flux corrections, also leave the CFL
+// rate of out in the accumulators (carry_slot = out).
+int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScalars& J, bool fold_cfl = false) {
   const Tables T = c->tables();
+  touch_slot(c, out);
   if (c->path == AMRVAC_PATH_FUSED) {
+    const bool fold = fold_cfl && can_carry(c);
+    JobCfl C{};
+    if (fold) {
+      drop_carry(c);
+      if (int rc = clear_if_dirty(c)) return rc;
+      C = cfl_state(c, nullptr, nullptr, nullptr);
+    }
     HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->tune, c->slots[in], c->slots[base], c->slots[out], w,
-                                  c->P, c->d_status));
+                                  c->P, c->d_status, fold ? &C : nullptr));
+    if (fold) c->carry_slot = out;
     HIP_TRY(c, launch_reflux_correct(c->stream, c->G, T, J, c->d_trefl, c->n_trefl, c->slots[in], c->slots[out], w,
                                      c->P));
     return AMRVAC_OK;
@@ -506,24 +572,41 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
   return AMRVAC_OK;
 }
 
-JobCfl cfl_state(amrvac_ctx* c, double* dt, double* ch, double* kappa) {
-  return JobCfl{c->d_rate, c->d_nan, c->d_geom, dt, ch, kappa, c->njob_cap};
-}
-
-// cfl -> [fill -> stage] x nstages on slots 0, 1, 2 with per-job scalars
+// cfl -> [fill -> stage] x nstages on slots 0, 1, 2 with per-job scalars;
+// the last stage folds the next step's CFL rate in where it can, so the next
+// step's cfl is only the finalize kernel.
 int enqueue_step(amrvac_ctx* c, int nstages, double* dt, double* ch, double* kap) {
-  HIP_TRY(c, launch_cfl(c->stream, c->G, c->tables(), c->slots[0], c->P, c->d_status, cfl_state(c, dt, ch, kap)));
+  if (int rc = cfl_of_slot(c, 0, dt, ch, kap)) return rc;
   const JobScalars J{dt, ch, kap};
   int rc;
   if (nstages == 2) {
     if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, J))) return rc;
-    if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 0, 0.5, J))) return rc;
+    if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 0, 0.5, J, true))) return rc;
     return AMRVAC_OK;
   }
   if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, J))) return rc;
   if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 2, 0.25, J))) return rc;
-  if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 0, 2.0 / 3.0, J))) return rc;
+  if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 0, 2.0 / 3.0, J, true))) return rc;
   return AMRVAC_OK;
+}
+
+int stage_entry(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
+                const double* kappa_dev, bool fold_cfl) {
+  if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts step with amrvac_batch_step");
+  if (int rc = check_slot(c, in)) return rc;
+  if (int rc = check_slot(c, out)) return rc;
+  if (w != 1.0) {
+    if (int rc = check_slot(c, base)) return rc;
+  } else {
+    base = out;
+  }
+  if (in == out) return fail(c, AMRVAC_E_ARG, "in and out slots must differ");
+  if (base == in && w != 1.0) return fail(c, AMRVAC_E_ARG, "base must differ from in");
+  if (!dt_dev || !ch_dev || !kappa_dev) return fail(c, AMRVAC_E_ARG, "null dt/c_h/kappa pointer");
+  if (!(w > 0.0 && w <= 1.0)) return fail(c, AMRVAC_E_ARG, "stage weight must be in (0, 1]");
+  if (int rc = ensure_tables(c)) return rc;
+  return stage_any(c, in, base, out, w, JobScalars{dt_dev, ch_dev, kappa_dev}, fold_cfl);
 }
 
 bool job_ok(const amrvac_ctx* c, int job) { return c->batch && job >= 0 && job < c->njob_cap && c->jobs[job].used; }
@@ -608,6 +691,7 @@ int amrvac_set_primitive(amrvac_ctx* c, int slot, const double* prim_dev) {
   if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts take initial states in amrvac_batch_add_job");
   if (int rc = check_slot(c, slot)) return rc;
   if (!prim_dev) return fail(c, AMRVAC_E_ARG, "null primitive array");
+  touch_slot(c, slot);
   HIP_TRY(c, launch_set_prim(c->stream, c->G, 0, c->cap, prim_dev, c->slots[slot], c->P));
   return AMRVAC_OK;
 }
@@ -634,28 +718,18 @@ int amrvac_cfl_dt(amrvac_ctx* c, int slot, double* dt_dev, double* ch_dev, doubl
   if (int rc = check_slot(c, slot)) return rc;
   if (!dt_dev || !ch_dev || !kappa_dev) return fail(c, AMRVAC_E_ARG, "null dt/c_h/kappa pointer");
   if (int rc = ensure_tables(c)) return rc;
-  HIP_TRY(c, launch_cfl(c->stream, c->G, c->tables(), c->slots[slot], c->P, c->d_status,
-                        cfl_state(c, dt_dev, ch_dev, kappa_dev)));
-  return AMRVAC_OK;
+  return cfl_of_slot(c, slot, dt_dev, ch_dev, kappa_dev);
 }
+
 
 int amrvac_stage(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
                  const double* kappa_dev) {
-  if (!c) return AMRVAC_E_ARG;
-  if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts step with amrvac_batch_step");
-  if (int rc = check_slot(c, in)) return rc;
-  if (int rc = check_slot(c, out)) return rc;
-  if (w != 1.0) {
-    if (int rc = check_slot(c, base)) return rc;
-  } else {
-    base = out;
-  }
-  if (in == out) return fail(c, AMRVAC_E_ARG, "in and out slots must differ");
-  if (base == in && w != 1.0) return fail(c, AMRVAC_E_ARG, "base must differ from in");
-  if (!dt_dev || !ch_dev || !kappa_dev) return fail(c, AMRVAC_E_ARG, "null dt/c_h/kappa pointer");
-  if (!(w > 0.0 && w <= 1.0)) return fail(c, AMRVAC_E_ARG, "stage weight must be in (0, 1]");
-  if (int rc = ensure_tables(c)) return rc;
-  return stage_any(c, in, base, out, w, JobScalars{dt_dev, ch_dev, kappa_dev});
+  return stage_entry(c, in, base, out, w, dt_dev, ch_dev, kappa_dev, false);
+}
+
+int amrvac_stage_cfl(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
+                     const double* kappa_dev) {
+  return stage_entry(c, in, base, out, w, dt_dev, ch_dev, kappa_dev, true);
 }
 
 int amrvac_set_path(amrvac_ctx* c, int path) {
@@ -680,6 +754,16 @@ int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph) {
     for (int n = 0; n < nsteps; ++n)
       if (int rc = enqueue_step(c, nstages, dt, ch, kap)) return rc;
     return AMRVAC_OK;
+  }
+  // A captured step starts with the finalize-only cfl when its last stage
+  // folds the CFL rate in; every replay then leaves the rate of slot 0 for
+  // the next one.  Before the first replay the accumulators must hold it.
+  if (can_carry(c) && c->carry_slot != 0) {
+    drop_carry(c);
+    if (int rc = clear_if_dirty(c)) return rc;
+    HIP_TRY(c, launch_cfl_accumulate(c->stream, c->G, c->tables(), c->slots[0], c->P, c->d_status,
+                                     cfl_state(c, dt, ch, kap)));
+    c->carry_slot = 0;
   }
   if (!c->graph_exec || c->graph_stages != nstages || c->graph_path != c->path) {
     drop_graph(c);
@@ -750,20 +834,25 @@ int amrvac_autotune(amrvac_ctx* c, int in, int out, int reps, amrvac_tune* best,
   hipError_t e = hipMemcpyAsync(saved, c->d_status, sizeof(DevStatus), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e == hipSuccess)
+  int rc = AMRVAC_OK;
+  if (e == hipSuccess) {
+    drop_carry(c);
+    touch_slot(c, out);
+    rc = clear_if_dirty(c);
+  }
+  if (e == hipSuccess && rc == AMRVAC_OK)
     e = launch_cfl(c->stream, c->G, c->tables(), c->slots[in], c->P, c->d_status,
                    cfl_state(c, c->d_jdt, c->d_jch, c->d_jkappa));
-  int rc = AMRVAC_OK;
-  if (e == hipSuccess) rc = fill_slot(c, in);
+  if (e == hipSuccess && rc == AMRVAC_OK) rc = fill_slot(c, in);
   const JobScalars J{c->d_jdt, c->d_jch, c->d_jkappa};
   const Tables T = c->tables();
   for (size_t k = 0; k < cand.size() && e == hipSuccess && rc == AMRVAC_OK; ++k) {
     e = launch_fused_stage(c->stream, c->G, T, J, cand[k], c->slots[in], c->slots[out], c->slots[out], 1.0, c->P,
-                           c->d_status);
+                           c->d_status, nullptr);
     if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
     for (int r = 0; r < reps && e == hipSuccess; ++r)
       e = launch_fused_stage(c->stream, c->G, T, J, cand[k], c->slots[in], c->slots[out], c->slots[out], 1.0,
-                             c->P, c->d_status);
+                             c->P, c->d_status, nullptr);
     if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&times[k], e0, e1);
