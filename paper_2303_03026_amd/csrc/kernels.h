@@ -99,9 +99,11 @@ struct FusedTune {
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                               const FusedTune& tune, const void* in, const void* base, void* out, double w,
                               const PhysConst& P, DevStatus* st, const JobCfl* cfl);
+// tasks: (block, face) pairs grouped by direction; direction d's are pairs
+// first[d] .. first[d] + count[d] - 1 (host arrays)
 hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
-                                 const int* tasks, int ntasks, const void* in, void* out, double w,
-                                 const PhysConst& P);
+                                 const int* tasks, const int first[3], const int count[3], const void* in,
+                                 void* out, double w, const PhysConst& P);
 
 // CFL: per-job max rate over the active blocks (accumulate), then per-job
 // dt, c_h, kappa, which also empties the accumulators (finalize); launch_cfl

@@ -272,8 +272,12 @@ __global__ void __launch_bounds__(256) k_reflux(GridConst G, const int* __restri
   double acc[NV];
   double v[2][2][NV];
   const int ne = G.ndim == 3 ? 2 : 1;
-  for (int e = 0; e < ne; ++e)
+  // (unrolled: a run-time index into v would place it in scratch memory)
+#pragma unroll
+  for (int e = 0; e < 2; ++e)
+#pragma unroll
     for (int a = 0; a < 2; ++a) {
+      if (e >= ne) continue;
       const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
       const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
       const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
@@ -390,8 +394,12 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, J
   R Fc[NV], Ff[NV], v[2][2][NV];
   face_flux_from_slot<D, SP>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, Fc);
   const int ne = G.ndim == 3 ? 2 : 1;
-  for (int e = 0; e < ne; ++e)
+  // (unrolled: a run-time index into v would place it in scratch memory)
+#pragma unroll
+  for (int e = 0; e < 2; ++e)
+#pragma unroll
     for (int a = 0; a < 2; ++a) {
+      if (e >= ne) continue;
       const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
       const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
       const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
@@ -582,20 +590,25 @@ hipError_t launch_reflux(hipStream_t s, const GridConst& G, const int* tasks, in
 }
 
 hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
-                                 const int* tasks, int ntasks, const void* in, void* out, double w,
-                                 const PhysConst& P) {
-  if (ntasks <= 0) return hipSuccess;
+                                 const int* tasks, const int first[3], const int count[3], const void* in,
+                                 void* out, double w, const PhysConst& P) {
+  // one launch per direction, in order: a coarse cell next to finer leaves
+  // across faces of two directions is corrected once per direction
   const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
-  const unsigned nbk = nblocks_for(ntasks * per, 256);
+#define AMRVAC_REFLUX_LAUNCH(D, SPT)                                                                   \
+  if (count[D] > 0)                                                                                   \
+  k_reflux_correct<D, SPT><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(G, T, J, tasks + 2 * first[D], \
+                                                                           count[D], in, out, w, P)
   if (G.precision == 0) {
-    k_reflux_correct<0, StoreF64><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
-    k_reflux_correct<1, StoreF64><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
-    if (G.ndim == 3) k_reflux_correct<2, StoreF64><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
+    AMRVAC_REFLUX_LAUNCH(0, StoreF64);
+    AMRVAC_REFLUX_LAUNCH(1, StoreF64);
+    if (G.ndim == 3) AMRVAC_REFLUX_LAUNCH(2, StoreF64);
   } else {
-    k_reflux_correct<0, StoreMixed><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
-    k_reflux_correct<1, StoreMixed><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
-    if (G.ndim == 3) k_reflux_correct<2, StoreMixed><<<nbk, 256, 0, s>>>(G, T, J, tasks, ntasks, in, out, w, P);
+    AMRVAC_REFLUX_LAUNCH(0, StoreMixed);
+    AMRVAC_REFLUX_LAUNCH(1, StoreMixed);
+    if (G.ndim == 3) AMRVAC_REFLUX_LAUNCH(2, StoreMixed);
   }
+#undef AMRVAC_REFLUX_LAUNCH
   return hipGetLastError();
 }
 

@@ -292,6 +292,7 @@ struct amrvac_ctx {
   int *d_order = nullptr, *d_tfill = nullptr, *d_tfused = nullptr, *d_tprol = nullptr, *d_trefl = nullptr;
   size_t cap_order = 0, cap_tfill = 0, cap_tfused = 0, cap_tprol = 0, cap_trefl = 0;
   int n_order = 0, n_tfill = 0, n_tfused = 0, n_tprol = 0, n_trefl = 0;
+  int refl_first[3] = {0, 0, 0}, refl_count[3] = {0, 0, 0};  // trefl by direction
   // per-job device arrays
   double* d_geom = nullptr;
   unsigned long long* d_rate = nullptr;
@@ -384,6 +385,21 @@ int rebuild(amrvac_ctx* c) {
     tprol.insert(tprol.end(), J.t.tprol.begin(), J.t.tprol.end());
     trefl.insert(trefl.end(), J.t.trefl.begin(), J.t.trefl.end());
     for (int q = 0; q < 4; ++q) geom[4 * j + q] = J.t.geom[q];
+  }
+  // flux-correction faces grouped by direction (one correction launch each)
+  {
+    std::vector<int> by_dir;
+    by_dir.reserve(trefl.size());
+    for (int d = 0; d < 3; ++d) {
+      c->refl_first[d] = (int)by_dir.size() / 2;
+      for (size_t k = 0; k < trefl.size(); k += 2)
+        if ((trefl[k + 1] >> 1) == d) {
+          by_dir.push_back(trefl[k]);
+          by_dir.push_back(trefl[k + 1]);
+        }
+      c->refl_count[d] = (int)by_dir.size() / 2 - c->refl_first[d];
+    }
+    trefl.swap(by_dir);
   }
   int rc;
   if ((rc = upload_list(c, &c->d_order, &c->cap_order, order)) ||
@@ -559,7 +575,8 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
     HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->tune, c->slots[in], c->slots[base], c->slots[out], w,
                                   c->P, c->d_status, fold ? &C : nullptr));
     if (fold) c->carry_slot = out;
-    HIP_TRY(c, launch_reflux_correct(c->stream, c->G, T, J, c->d_trefl, c->n_trefl, c->slots[in], c->slots[out], w,
+    HIP_TRY(c, launch_reflux_correct(c->stream, c->G, T, J, c->d_trefl, c->refl_first, c->refl_count,
+                                     c->slots[in], c->slots[out], w,
                                      c->P));
     return AMRVAC_OK;
   }
