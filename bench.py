@@ -29,35 +29,35 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources whose hash is the key; after any change to those sources the
 # figure is reported as null.
 KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
-                  "paper_2303_03026_amd/csrc/kernels.h")
+                  "paper_2303_03026_amd/csrc/kernels.h", "paper_2303_03026_amd/csrc/runtime.cpp")
 MEASURED_TRAFFIC = {
-    ("a782f5dcb1783247", "f64"): {
-        (1, 0, 0): ((2856960, 1475061), (3640047, 1475287)),
-        (1, 0, 1): ((2709979, 1474976), (3562642, 1475329)),
-        (1, 1, 0): ((2864772, 1475030), (3653727, 1475668)),
-        (1, 1, 1): ((2697050, 1475097), (3553997, 1475749)),
-        (2, 0, 0): ((3068991, 1474832), (3858776, 1475222)),
-        (2, 0, 1): ((2940788, 1474872), (3800966, 1475246)),
-        (2, 1, 0): ((3089740, 1475004), (3859245, 1475414)),
-        (2, 1, 1): ((2923931, 1475051), (3783512, 1475501)),
-        (4, 0, 0): ((3515325, 1474654), (4303498, 1474833)),
-        (4, 0, 1): ((3181707, 1474696), (4046468, 1474819)),
-        (4, 1, 0): ((3514119, 1474790), (4304565, 1474957)),
-        (4, 1, 1): ((3163182, 1474777), (4091852, 1474937)),
+    ("e233fd93c002420c", "f64"): {
+        (1, 0, 0): ((2852525, 1180154), (3632534, 1180338)),
+        (1, 0, 1): ((2713938, 1180123), (3558531, 1180323)),
+        (1, 1, 0): ((2858361, 1179987), (3647400, 1180259)),
+        (1, 1, 1): ((2696963, 1180019), (3553821, 1180411)),
+        (2, 0, 0): ((3061731, 1179908), (3849541, 1180228)),
+        (2, 0, 1): ((2942546, 1179915), (3800971, 1180248)),
+        (2, 1, 0): ((3076517, 1179997), (3858867, 1180220)),
+        (2, 1, 1): ((2920720, 1179957), (3789844, 1180269)),
+        (4, 0, 0): ((3517106, 1179743), (4307937, 1179876)),
+        (4, 0, 1): ((3191323, 1179773), (4065639, 1179871)),
+        (4, 1, 0): ((3515005, 1179827), (4306162, 1179940)),
+        (4, 1, 1): ((3165402, 1179785), (4080273, 1179922)),
     },
-    ("a782f5dcb1783247", "mixed"): {
-        (1, 0, 0): ((1711338, 819543), (2175214, 819600)),
-        (1, 0, 1): ((1570069, 819541), (2074973, 819649)),
-        (1, 1, 0): ((1709398, 819487), (2169409, 819744)),
-        (1, 1, 1): ((1569922, 819532), (2075415, 819837)),
-        (2, 0, 0): ((1824828, 819419), (2299417, 819485)),
-        (2, 0, 1): ((1703348, 819415), (2215840, 819466)),
-        (2, 1, 0): ((1830279, 819458), (2304422, 819614)),
-        (2, 1, 1): ((1708713, 819458), (2216367, 819604)),
-        (4, 0, 0): ((2097987, 819267), (2560220, 819368)),
-        (4, 0, 1): ((1829178, 819245), (2369586, 819333)),
-        (4, 1, 0): ((2103255, 819294), (2564128, 819356)),
-        (4, 1, 1): ((1827771, 819264), (2371650, 819362)),
+    ("e233fd93c002420c", "mixed"): {
+        (1, 0, 0): ((1707994, 819548), (2180998, 819585)),
+        (1, 0, 1): ((1572006, 819509), (2075949, 819631)),
+        (1, 1, 0): ((1706914, 819475), (2165047, 819738)),
+        (1, 1, 1): ((1571172, 819481), (2077380, 819760)),
+        (2, 0, 0): ((1824189, 819400), (2297525, 819493)),
+        (2, 0, 1): ((1705969, 819381), (2215694, 819478)),
+        (2, 1, 0): ((1827506, 819428), (2303804, 819563)),
+        (2, 1, 1): ((1710590, 819442), (2220957, 819593)),
+        (4, 0, 0): ((2097801, 819264), (2561820, 819335)),
+        (4, 0, 1): ((1826336, 819249), (2370395, 819328)),
+        (4, 1, 0): ((2101740, 819273), (2563036, 819341)),
+        (4, 1, 1): ((1827499, 819267), (2370972, 819351)),
     },
 }
 FETCH_CAL, WRITE_CAL = 2.0, 1.0

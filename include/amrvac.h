@@ -23,8 +23,12 @@
  *       AMRVAC_FP32_MIXED: 8 float arrays (rho, m_x, m_y, m_z, B_x, B_y, B_z,
  *                          psi) followed by one double array (e) per block
  *                          (40 B per cell).
- *     amrvac_slot_bytes gives the size.  Only face ghost slabs are used;
- *     edge and corner cells of the padded block are never read or written.
+ *     An FP64 slot's blocks start AMRVAC_SLOT_LEAD_FP64 bytes into the
+ *     buffer, so that with a 32-byte aligned buffer every interior row
+ *     (i = 0 .. block_nx-1) begins on a 32-byte memory sector; FP32-mixed
+ *     slots start at byte 0.  amrvac_slot_bytes gives the size, lead
+ *     included.  Only face ghost slabs are used; edge and corner cells of
+ *     the padded block are never read or written.
  *   - Every call enqueues work on the stream given at init (a hipStream_t,
  *     caller-owned) and returns without synchronising, except
  *     amrvac_sync_flags and amrvac_destroy.
@@ -85,6 +89,9 @@ typedef struct {
 /* Device bytes of one state slot for nblocks blocks of this description.
  * Returns AMRVAC_E_ARG for an invalid description. */
 int amrvac_slot_bytes(const amrvac_grid_desc* g, int nblocks, size_t* bytes);
+
+/* Bytes before the first block in an FP64 slot (see the layout above). */
+#define AMRVAC_SLOT_LEAD_FP64 16
 
 /* Create a context.  level[nb] (1-based) and ijk[nb][3] (block position on
  * its level, z ignored in 2D) are HOST arrays describing the leaf blocks;

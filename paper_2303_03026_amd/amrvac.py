@@ -29,6 +29,11 @@ ABI_SYMBOLS = ("amrvac_slot_bytes", "amrvac_init_blocks", "amrvac_set_primitive"
                "amrvac_batch_get_job", "amrvac_batch_remove_job", "amrvac_batch_free_blocks",
                "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune", "amrvac_stage_cfl")
 TUNE_MAX_CANDIDATES = 12
+SLOT_LEAD_FP64 = 16  # bytes before the first block of an FP64 slot
+
+
+def slot_lead(precision: int) -> int:
+    return SLOT_LEAD_FP64 if precision == FP64 else 0
 
 
 class AmrvacError(RuntimeError):
@@ -220,10 +225,15 @@ class Simulation:
 
     def padded(self, slot: int = 0) -> np.ndarray:
         """Raw FP64 slot contents, [block][var][padded cells] (test helper)."""
+        return self.padded_view(slot).cpu().numpy()
+
+    def padded_view(self, slot: int = 0):
+        """Device view of an FP64 slot as [block][var][padded cells] (test
+        helper; skips the slot's lead bytes)."""
         pn = self.w.nx + 2 * self.w.ng
         self.stream.synchronize()
-        a = self.slots[slot].view(self.torch.float64).cpu().numpy()
-        return a.reshape((self.nb, NV) + (pn,) * self.w.ndim)
+        raw = self.slots[slot][slot_lead(self.desc.precision):]
+        return raw.view(self.torch.float64).view((self.nb, NV) + (pn,) * self.w.ndim)
 
     def fill(self, slot: int):
         self._check(self.lib.amrvac_fill_ghosts(self.ctx, slot), self.ctx)
@@ -362,7 +372,7 @@ class Batch:
         size = ctypes.c_size_t()
         if self.lib.amrvac_slot_bytes(ctypes.byref(self.desc), capacity_blocks, ctypes.byref(size)) != 0:
             raise AmrvacError(E_ARG, "bad batch shape")
-        self.block_bytes = size.value // capacity_blocks
+        self.block_bytes = (size.value - slot_lead(precision)) // capacity_blocks
         nslots = 3 if nstages == 3 else 2
         with torch.cuda.stream(self.stream):
             self.slots = [torch.empty(size.value, dtype=torch.uint8, device=self.device) for _ in range(nslots)]

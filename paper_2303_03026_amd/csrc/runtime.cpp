@@ -76,11 +76,16 @@ int check_desc(const amrvac_grid_desc* g, std::string* why) {
   return AMRVAC_OK;
 }
 
+// bytes before the first block of a slot (FP64: interior rows start at
+// x = 2 doubles = 16 B into a padded row; the lead moves them onto 32 B
+// memory sectors, which every pitch of the FP64 layout is a multiple of)
+long slot_lead(int precision) { return precision == AMRVAC_FP64 ? AMRVAC_SLOT_LEAD_FP64 : 0; }
+
 long long slot_bytes_of(const amrvac_grid_desc* g, long nb) {
   const long pn = g->block_nx + 2 * g->nghost;
   const long pc = pn * pn * (g->ndim == 3 ? pn : 1);
   const long per = g->precision == AMRVAC_FP64 ? 72 : 40;
-  return (long long)nb * pc * per;
+  return (long long)nb * pc * per + slot_lead(g->precision);
 }
 
 // Validate a job's leaf blocks and build its tables with pool ids starting
@@ -673,7 +678,8 @@ int amrvac_init_blocks(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, cons
   c->njob_cap = 1;
   setup_shape(c, g);
   c->stream = static_cast<hipStream_t>(stream);
-  c->slots.assign(slots, slots + nslots);
+  c->slots.clear();
+  for (int k = 0; k < nslots; ++k) c->slots.push_back(static_cast<char*>(slots[k]) + slot_lead(g->precision));
   (void)hipGetDevice(&c->device);
   J.used = true;
   J.first = 0;
@@ -939,7 +945,8 @@ int amrvac_batch_create(amrvac_ctx** out, const amrvac_grid_desc* shape, int cap
   setup_shape(c, shape);
   c->path = AMRVAC_PATH_FUSED;
   c->stream = static_cast<hipStream_t>(stream);
-  c->slots.assign(slots, slots + nslots);
+  c->slots.clear();
+  for (int k = 0; k < nslots; ++k) c->slots.push_back(static_cast<char*>(slots[k]) + slot_lead(shape->precision));
   (void)hipGetDevice(&c->device);
   c->jobs.resize(max_jobs);
   c->free_runs.push_back({0, capacity_blocks});

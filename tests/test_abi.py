@@ -37,7 +37,9 @@ def test_slot_bytes(lib):
     g = amrvac.make_desc(w)
     n = ctypes.c_size_t()
     assert lib.amrvac_slot_bytes(ctypes.byref(g), 16, ctypes.byref(n)) == 0
-    assert n.value == 16 * 20 * 20 * 72
+    # FP64: 16 lead bytes put interior rows on 32-byte sectors
+    assert n.value == 16 * 20 * 20 * 72 + amrvac.SLOT_LEAD_FP64 == 16 * 20 * 20 * 72 + 16
+    assert amrvac.SLOT_LEAD_FP64 % 32 == 16 and (20 * 8) % 32 == 0
     g.precision = amrvac.FP32_MIXED
     assert lib.amrvac_slot_bytes(ctypes.byref(g), 16, ctypes.byref(n)) == 0
     assert n.value == 16 * 20 * 20 * 40

@@ -22,8 +22,8 @@ def poison_ghosts(sim):
     torch = sim.torch
     nx, ng, nd = sim.w.nx, sim.w.ng, sim.w.ndim
     pn = nx + 2 * ng
-    for s in sim.slots:
-        a = s.view(torch.float64).view((sim.nb, 9) + (pn,) * nd)
+    for k in range(len(sim.slots)):
+        a = sim.padded_view(k)
         mask = torch.ones((pn,) * nd, dtype=torch.bool, device=a.device)
         inner = (slice(ng, ng + nx),) * nd
         mask[inner] = False
