@@ -39,7 +39,7 @@ class ServingEngine:
     CLASSES = [(2, False), (2, True), (3, False), (3, True)]
 
     def __init__(self, budget_bytes: float = 32e9, shares=(0.05, 0.05, 0.6, 0.3), max_jobs: int = 1024,
-                 device: str = "cuda", prefetch_workers: int = 8):
+                 device: str = "cuda", prefetch_workers: int = 8, autotune: bool = True):
         import torch
         self.torch = torch
         self.device = device
@@ -52,7 +52,20 @@ class ServingEngine:
             self.pools[cls] = amrvac.Batch(shape, max(cap, 1), max_jobs, nstages=3,
                                            precision=amrvac.FP32_MIXED if mixed else amrvac.FP64, device=device)
             self.capacity[cls] = max(cap, 1)
+            if autotune:
+                self.pools[cls].set_tune(*self.tune_for(ndim, mixed))
         self.pool_exec = concurrent.futures.ThreadPoolExecutor(max_workers=prefetch_workers)
+
+    def tune_for(self, ndim: int, mixed: bool):
+        """Launch shape of a class's pool: the autotuner's choice on a
+        representative resident set (a 128^3 grid in 3D, 512^2 in 2D, about
+        the block count of a few dozen typical jobs)."""
+        w = inputs.random_modes(128 if ndim == 3 else 512, ndim, seed=0)
+        sim = amrvac.Simulation(w, path=amrvac.PATH_FUSED, precision=amrvac.FP32_MIXED if mixed else amrvac.FP64,
+                                device=self.device)
+        shape, _ = sim.autotune(reps=3)
+        sim.close()
+        return shape
 
     def close(self):
         for b in self.pools.values():
@@ -77,6 +90,9 @@ class ServingEngine:
         next_prefetch = ahead
         queues = {cls: collections.deque() for cls in self.CLASSES}
         resident = {cls: {} for cls in self.CLASSES}  # job id in pool -> job index
+        # steps left per resident job, kept here in step with the pool (every
+        # round advances each resident job with steps left by one step)
+        left = {cls: {} for cls in self.CLASSES}
         arrived = 0
         results = {}
         rec = {}
@@ -108,6 +124,7 @@ class ServingEngine:
                         break
                     q.popleft()
                     resident[cls][jid] = i
+                    left[cls][jid] = int(w.nsteps)
                     rec[i]["admitted"] = time.perf_counter() - t0
                     rec[i]["cells"] = w.interior_cells
                     del futures[i]
@@ -115,12 +132,13 @@ class ServingEngine:
             stepped = False
             for cls in self.CLASSES:
                 pool = self.pools[cls]
-                active = [jid for jid in resident[cls] if pool.job_info(jid)[1] > 0]
+                active = [jid for jid, n in left[cls].items() if n > 0]
                 if not active:
                     continue
                 pool.step()
                 stepped = True
                 for jid in active:
+                    left[cls][jid] -= 1
                     cell_steps += rec[resident[cls][jid]]["cells"]
                 ev = torch.cuda.Event()
                 ev.record(pool.stream)
@@ -131,16 +149,15 @@ class ServingEngine:
             # completions
             for cls in self.CLASSES:
                 pool = self.pools[cls]
-                for jid in list(resident[cls]):
-                    done, left, nb = pool.job_info(jid)
-                    if left == 0:
-                        i = resident[cls].pop(jid)
-                        if keep_results is not None and jobs[i]["id"] in keep_results:
-                            results[jobs[i]["id"]] = pool.get_job(jid)
-                        else:
-                            pool.stream.synchronize()
-                        rec[i]["done"] = time.perf_counter() - t0
-                        pool.remove_job(jid)
+                for jid in [j for j, n in left[cls].items() if n == 0]:
+                    del left[cls][jid]
+                    i = resident[cls].pop(jid)
+                    if keep_results is not None and jobs[i]["id"] in keep_results:
+                        results[jobs[i]["id"]] = pool.get_job(jid)
+                    else:
+                        pool.stream.synchronize()
+                    rec[i]["done"] = time.perf_counter() - t0
+                    pool.remove_job(jid)
             if not stepped:
                 nxt = jobs[order[arrived]]["arrival"] * time_scale if arrived < len(order) else None
                 if nxt is not None and not any(queues[c] for c in self.CLASSES):
@@ -183,9 +200,11 @@ def main(argv=None):
     ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of the saturated rate")
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape in every pool")
     args = ap.parse_args(argv)
     jobs = inputs.serving_jobs(args.jobs, seed=args.seed, rate=1.0)
-    eng = ServingEngine(budget_bytes=args.budget_gb * 1e9)
+    eng = ServingEngine(budget_bytes=args.budget_gb * 1e9, autotune=not args.no_autotune)
+    shapes = {"%dd_%s" % (c[0], "mixed" if c[1] else "f64"): eng.pools[c].get_tune() for c in eng.CLASSES}
     # saturated throughput: every job arrives at once
     sat = eng.run([dict(j, arrival=0.0) for j in jobs])
     rate_sat = len(jobs) / sat["wall_s"]
@@ -194,7 +213,7 @@ def main(argv=None):
     eng.close()
     for r in (sat, res):
         r.pop("results", None)
-    print(json.dumps({"saturated": sat, "load": args.load, "served": res}))
+    print(json.dumps({"saturated": sat, "load": args.load, "served": res, "pool_launch_shapes": shapes}))
 
 
 if __name__ == "__main__":
