@@ -119,9 +119,9 @@ int amrvac_get_conserved(amrvac_ctx* c, int slot, double* cons_dev);
  * volume average) of finer neighbours and physical boundaries, then limited
  * linear prolongation of coarser neighbours (the paper's internal boundary
  * exchange of the "Future directions" section, done on the device).  On
- * AMRVAC_PATH_PLAIN every face ghost slab is filled; AMRVAC_PATH_FUSED
- * reads same-level neighbours in place, so their faces are skipped unless
- * the block's ghosts feed a prolongation. */
+ * AMRVAC_PATH_PLAIN every face ghost slab is filled; on AMRVAC_PATH_FUSED
+ * the stage and the prolongation read same-level neighbours in place, so
+ * faces between same-level leaves are skipped. */
 int amrvac_fill_ghosts(amrvac_ctx* c, int slot);
 
 /* Time step from the interior of slot: dt = C / max_cells sum_d

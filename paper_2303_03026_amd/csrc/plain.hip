@@ -139,12 +139,36 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
         odd[ax] = (int)(g & 1);
         lc[ax] = (int)((g >> 1) - (long)pos[3 * cb + ax] * nx);
       }
+      // The coarse cell lc is interior to cb (the fine ghost lies over cb's
+      // face); a slope neighbour steps out of cb by one cell along one axis
+      // at most, into a face ghost slab of cb.  With a same-level leaf across
+      // that face the cell is read in place from its interior (that slab is
+      // not filled on the fused path); across faces towards finer leaves or
+      // the domain boundary it is cb's own ghost cell, filled before this
+      // pass.  (A face of cb towards a coarser leaf is never reached: the
+      // fine block would then touch that leaf across an edge, which 2:1
+      // nesting excludes.)
       const long i0 = pidx(G, lc[0], lc[1], lc[2]);
+      const void* sm[3] = {src, src, src};
+      const void* sp[3] = {src, src, src};
       long im[3], ip[3];
+#pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
         int m[3] = {lc[0], lc[1], lc[2]}, p[3] = {lc[0], lc[1], lc[2]};
         m[ax] -= 1;
         p[ax] += 1;
+        if (ax < G.ndim) {
+          const int* Lm = link + ((long)cb * 6 + 2 * ax) * LINK_INTS;
+          const int* Lp = link + ((long)cb * 6 + 2 * ax + 1) * LINK_INTS;
+          if (m[ax] < 0 && Lm[0] == LINK_SAME) {
+            sm[ax] = block_ptr<SP>(slot, Lm[1], pc);
+            m[ax] += nx;
+          }
+          if (p[ax] >= nx && Lp[0] == LINK_SAME) {
+            sp[ax] = block_ptr<SP>(slot, Lp[1], pc);
+            p[ax] -= nx;
+          }
+        }
         im[ax] = ax < G.ndim ? pidx(G, m[0], m[1], m[2]) : i0;
         ip[ax] = ax < G.ndim ? pidx(G, p[0], p[1], p[2]) : i0;
       }
@@ -154,7 +178,7 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
         double r = uc;
         for (int ax = 0; ax < G.ndim; ++ax) {
           const double sg = odd[ax] ? 0.25 : -0.25;
-          r = r + sg * minmod2(uc - SP::ld(src, q, im[ax], pc), SP::ld(src, q, ip[ax], pc) - uc);
+          r = r + sg * minmod2(uc - SP::ld(sm[ax], q, im[ax], pc), SP::ld(sp[ax], q, ip[ax], pc) - uc);
         }
         SP::st(dst, q, di, pc, r);
       }

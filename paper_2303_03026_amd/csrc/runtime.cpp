@@ -224,17 +224,12 @@ int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ij
       }
   }
   if (!g->reflux) J.trefl.clear();
-  // The fused stage reads same-level neighbours in place; it needs filled
-  // ghosts only on faces towards finer leaves and physical boundaries, plus
-  // every face of a block whose ghosts feed a prolongation.
-  std::vector<char> prol_src(nb, 0);
-  for (size_t q = 0; q < J.tprol.size(); q += 2) {
-    const int lb = J.tprol[q] - first, face = J.tprol[q + 1];
-    prol_src[J.link[((size_t)lb * 6 + face) * LINK_INTS + 1] - first] = 1;
-  }
+  // The fused stage and the prolongation read same-level neighbours in place;
+  // the fused path fills ghosts only on faces towards finer leaves and
+  // physical boundaries (then prolongs the faces towards coarser ones).
   for (size_t q = 0; q < J.tfill.size(); q += 2) {
     const int lb = J.tfill[q] - first, face = J.tfill[q + 1];
-    if (J.link[((size_t)lb * 6 + face) * LINK_INTS] != LINK_SAME || prol_src[lb]) {
+    if (J.link[((size_t)lb * 6 + face) * LINK_INTS] != LINK_SAME) {
       J.tfused.push_back(J.tfill[q]);
       J.tfused.push_back(face);
     }
