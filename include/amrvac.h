@@ -156,10 +156,16 @@ int amrvac_stage(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double
 int amrvac_stage_cfl(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double w,
                      const double* dt_dev, const double* ch_dev, const double* kappa_dev);
 
-/* Advance nsteps full SSPRK steps of slot 0 (nstages 1, 2 or 3), using
- * slots 1 and 2 as stage storage and library-owned dt/c_h/kappa; each step
- * is cfl -> [fill -> stage] x nstages.  use_graph = 1 captures one step in
- * a HIP graph on first use and replays it.  No host synchronisation. */
+/* Advance nsteps full SSP Runge-Kutta steps of slot 0 (Table
+ * tab:schemes_time), using slots 1 and 2 as stage storage and library-owned
+ * dt/c_h/kappa; each step is cfl -> [fill -> stage] x nstages:
+ *   nstages = 2: SSPRK(2,2), stage weights (1, 1/2);
+ *   nstages = 3: SSPRK(3,3), stage weights (1, 1/4, 2/3);
+ *   nstages = 4: SSPRK(4,3), four stages advancing by dt/2 each, weights
+ *                (1, 1, 1/3, 1) (the third returns to the step's start).
+ * The last stage folds in the next step's CFL rate where it can
+ * (amrvac_stage_cfl).  use_graph = 1 captures one step in a HIP graph on
+ * first use and replays it.  No host synchronisation. */
 int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph);
 
 /* Select the stage implementation: AMRVAC_PATH_PLAIN (separate primitive,
@@ -227,8 +233,9 @@ int amrvac_reset_flags(amrvac_ctx* c);
  * -------------------------------------------------------------------------*/
 
 /* Create a batch context.  shape supplies ndim, block_nx (must be 16),
- * precision and the physics every job must share; slots are 2 (nstages = 2)
- * or 3 (nstages = 3) caller-owned DEVICE buffers of
+ * precision and the physics every job must share; nstages as in
+ * amrvac_advance; slots are 2 (nstages = 2) or 3 (nstages = 3, 4)
+ * caller-owned DEVICE buffers of
  * amrvac_slot_bytes(shape, capacity_blocks) bytes each (the block pool);
  * max_jobs bounds the number of resident jobs. */
 int amrvac_batch_create(amrvac_ctx** out, const amrvac_grid_desc* shape, int capacity_blocks, int max_jobs,

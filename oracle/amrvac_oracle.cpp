@@ -9,7 +9,7 @@
 // What it computes (MPI-AMRVAC 3.0, arXiv 2303.03026):
 //   * conservative cell-centred finite volumes inside a multistage SSP
 //     Runge-Kutta step ("Schemes and limiters for HD and MHD", Table
-//     tab:schemes_time: SSPRK(2,2) and SSPRK(3,3));
+//     tab:schemes_time: SSPRK(2,2), SSPRK(3,3) and SSPRK(4,3));
 //   * limited linear reconstruction of primitive variables giving a left and
 //     a right state per face, with the 'vanleer' limiter and 2 ghost cells
 //     (Table t:limiters);
@@ -242,7 +242,7 @@ typedef struct {
   int ndim;
   int nx;
   int ng;
-  int nstages;  // 1 = forward Euler, 2 = SSPRK(2,2), 3 = SSPRK(3,3)
+  int nstages;  // 1 = forward Euler, 2 = SSPRK(2,2), 3 = SSPRK(3,3), 4 = SSPRK(4,3)
   int reflux;
   int fix_small_values;
   int nthreads;
@@ -617,10 +617,20 @@ struct Sim {
     } else if (s == 2) {
       stage(S0, nullptr, S1, 1.0, dt, ch, kappa);
       stage(S1, &S0, S0, 0.5, dt, ch, kappa);
-    } else {
+    } else if (s == 3) {
       stage(S0, nullptr, S1, 1.0, dt, ch, kappa);
       stage(S1, &S0, S2, 0.25, dt, ch, kappa);
       stage(S2, &S0, S0, 2.0 / 3.0, dt, ch, kappa);
+    } else {
+      // SSPRK(4,3) (Table tab:schemes_time): four forward-Euler stages of
+      // dt/2; the third returns to u0 with weight 1/3:
+      //   u1 = u0 + h L(u0), u2 = u1 + h L(u1),
+      //   u3 = 2/3 u0 + 1/3 (u2 + h L(u2)), u4 = u3 + h L(u3),  h = dt/2
+      const double h = 0.5 * dt;
+      stage(S0, nullptr, S1, 1.0, h, ch, kappa);
+      stage(S1, nullptr, S2, 1.0, h, ch, kappa);
+      stage(S2, &S0, S1, 1.0 / 3.0, h, ch, kappa);
+      stage(S1, nullptr, S0, 1.0, h, ch, kappa);
     }
   }
 };
@@ -635,7 +645,7 @@ Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int*
   if (s->ndim != 2 && s->ndim != 3) throw std::invalid_argument("ndim must be 2 or 3");
   if (s->ng != 2) throw std::invalid_argument("the van Leer stencil needs exactly 2 ghost layers");
   if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
-  if (p->nstages < 1 || p->nstages > 3) throw std::invalid_argument("nstages must be 1, 2 or 3");
+  if (p->nstages < 1 || p->nstages > 4) throw std::invalid_argument("nstages must be 1, 2, 3 or 4");
   if (s->P.nthreads < 1) s->P.nthreads = 1;
   for (int d = 0; d < s->ndim; ++d)
     if ((p->bc_lo[d] == BC_PERIODIC) != (p->bc_hi[d] == BC_PERIODIC))

@@ -373,7 +373,7 @@ class Batch:
         if self.lib.amrvac_slot_bytes(ctypes.byref(self.desc), capacity_blocks, ctypes.byref(size)) != 0:
             raise AmrvacError(E_ARG, "bad batch shape")
         self.block_bytes = (size.value - slot_lead(precision)) // capacity_blocks
-        nslots = 3 if nstages == 3 else 2
+        nslots = 3 if nstages >= 3 else 2
         with torch.cuda.stream(self.stream):
             self.slots = [torch.empty(size.value, dtype=torch.uint8, device=self.device) for _ in range(nslots)]
         torch.cuda.synchronize(self.device)

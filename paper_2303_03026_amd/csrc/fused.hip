@@ -227,7 +227,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
   const int sb0 = face_src(0), sb1 = face_src(1), sb2 = face_src(2), sb3 = face_src(3);
   const int sh0 = face_shift(0), sh1 = face_shift(1), sh2 = face_shift(2), sh3 = face_shift(3);
   const int job = T.job[b];
-  const double dt = J.dt[job], kappa = J.kappa[job], chd = J.ch[job];
+  const double dt = J.dt_scale * J.dt[job], kappa = J.kappa[job], chd = J.ch[job];
   const FaceConst<R> K{(R)chd, (R)(0.5 / chd), (R)P.gamma, (R)P.inv_gm1};
   const double idx = T.inv_dx[3 * b], idy = T.inv_dx[3 * b + 1], idz = T.inv_dx[3 * b + 2];
   const R idzr = (R)idz;

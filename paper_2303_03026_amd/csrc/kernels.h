@@ -38,11 +38,13 @@ struct Tables {
   int nactive;
 };
 
-// Per-job time-step scalars, indexed by job slot.
+// Per-job time-step scalars, indexed by job slot; a stage advances by
+// dt_scale * dt (1 for SSPRK(2,2)/(3,3), 1/2 for the SSPRK(4,3) stages).
 struct JobScalars {
   const double* dt;
   const double* ch;
   const double* kappa;
+  double dt_scale = 1.0;
 };
 
 // Per-job CFL state: running max rate (non-negative double bits), NaN mark,
@@ -80,7 +82,8 @@ struct FluxPtrs {
 hipError_t launch_reflux(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const Tables& T,
                          FluxPtrs flux);
 hipError_t launch_update(hipStream_t s, const GridConst& G, const Tables& T, const void* in, const void* base,
-                         void* out, double w, FluxPtrs flux, const double* dt_dev, const double* kappa_dev);
+                         void* out, double w, FluxPtrs flux, const double* dt_dev, double dt_scale,
+                         const double* kappa_dev);
 
 // fused stage (nx = 16) and the coarse/fine correction that follows it -------
 // Launch shape of the fused stage (results do not depend on it):

@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(256) k_reflux(GridConst G, const int* __restri
 __global__ void __launch_bounds__(256) k_update(GridConst G, Tables T, const double* __restrict__ in,
                                                const double* base,
                                                double* out, double w, FluxPtrs flux,
-                                               const double* __restrict__ dt_dev,
+                                               const double* __restrict__ dt_dev, double dt_scale,
                                                const double* __restrict__ kappa_dev) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long total = (long)G.nb * G.icells;
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(256) k_update(GridConst G, Tables T, const dou
   const int nx = G.nx;
   const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
   const long pc = pidx(G, i, j, k);
-  const double dt = *dt_dev, kappa = *kappa_dev;
+  const double dt = dt_scale * *dt_dev, kappa = *kappa_dev;
   double L[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) L[q] = 0.0;
@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, J
   const int* L = link + ((long)b * 6 + face) * LINK_INTS;
   const int t1 = t % nx, t2 = G.ndim == 3 ? t / nx : 0;
   const int job = T.job[b];
-  const double dt = J.dt[job];
+  const double dt = J.dt_scale * J.dt[job];
   const R ch = (R)J.ch[job], hic = (R)(0.5 / J.ch[job]);
   const long pc = G.pcells;
   R Fc[NV], Ff[NV], v[2][2][NV];
@@ -637,10 +637,11 @@ hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables
 }
 
 hipError_t launch_update(hipStream_t s, const GridConst& G, const Tables& T, const void* in, const void* base,
-                         void* out, double w, FluxPtrs flux, const double* dt_dev, const double* kappa_dev) {
+                         void* out, double w, FluxPtrs flux, const double* dt_dev, double dt_scale,
+                         const double* kappa_dev) {
   const long n = (long)G.nb * G.icells;
   k_update<<<nblocks_for(n, 256), 256, 0, s>>>(G, T, static_cast<const double*>(in), static_cast<const double*>(base),
-                                                static_cast<double*>(out), w, flux, dt_dev, kappa_dev);
+                                                static_cast<double*>(out), w, flux, dt_dev, dt_scale, kappa_dev);
   return hipGetLastError();
 }
 

@@ -585,7 +585,8 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
     HIP_TRY(c, launch_flux(c->stream, c->G, d, c->d_prim, c->d_flux[d], J.ch, c->P));
   FluxPtrs fp{{c->d_flux[0], c->d_flux[1], c->d_flux[2]}};
   HIP_TRY(c, launch_reflux(c->stream, c->G, c->d_trefl, c->n_trefl, T, fp));
-  HIP_TRY(c, launch_update(c->stream, c->G, T, c->slots[in], c->slots[base], c->slots[out], w, fp, J.dt, J.kappa));
+  HIP_TRY(c, launch_update(c->stream, c->G, T, c->slots[in], c->slots[base], c->slots[out], w, fp, J.dt, J.dt_scale,
+                           J.kappa));
   return AMRVAC_OK;
 }
 
@@ -601,9 +602,19 @@ int enqueue_step(amrvac_ctx* c, int nstages, double* dt, double* ch, double* kap
     if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 0, 0.5, J, true))) return rc;
     return AMRVAC_OK;
   }
-  if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, J))) return rc;
-  if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 2, 0.25, J))) return rc;
-  if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 0, 2.0 / 3.0, J, true))) return rc;
+  if (nstages == 3) {
+    if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, J))) return rc;
+    if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 2, 0.25, J))) return rc;
+    if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 0, 2.0 / 3.0, J, true))) return rc;
+    return AMRVAC_OK;
+  }
+  // SSPRK(4,3): four stages of dt/2; u3 = u0 + (1/3)((u2 + h L(u2)) - u0)
+  JobScalars H = J;
+  H.dt_scale = 0.5;
+  if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, H))) return rc;
+  if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 1, 2, 1.0, H))) return rc;
+  if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 1, 1.0 / 3.0, H))) return rc;
+  if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 1, 0, 1.0, H, true))) return rc;
   return AMRVAC_OK;
 }
 
@@ -763,8 +774,8 @@ int amrvac_set_path(amrvac_ctx* c, int path) {
 int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph) {
   if (!c) return AMRVAC_E_ARG;
   if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts step with amrvac_batch_step");
-  if (nstages != 2 && nstages != 3) return fail(c, AMRVAC_E_ARG, "amrvac_advance supports 2 or 3 stages");
-  if ((int)c->slots.size() < (nstages == 3 ? 3 : 2)) return fail(c, AMRVAC_E_ARG, "not enough slots");
+  if (nstages < 2 || nstages > 4) return fail(c, AMRVAC_E_ARG, "amrvac_advance supports 2, 3 or 4 stages");
+  if ((int)c->slots.size() < (nstages >= 3 ? 3 : 2)) return fail(c, AMRVAC_E_ARG, "not enough slots");
   if (nsteps < 0) return fail(c, AMRVAC_E_ARG, "negative step count");
   if (int rc = ensure_tables(c)) return rc;
   double *dt = c->d_jdt, *ch = c->d_jch, *kap = c->d_jkappa;
@@ -925,11 +936,11 @@ int amrvac_batch_create(amrvac_ctx** out, const amrvac_grid_desc* shape, int cap
   std::string why;
   if (check_desc(shape, &why) != AMRVAC_OK) { g_init_err = why; return AMRVAC_E_ARG; }
   if (shape->block_nx != 16) { g_init_err = "batch contexts run the fused path: block_nx must be 16"; return AMRVAC_E_ARG; }
-  if (capacity_blocks < 1 || max_jobs < 1 || (nstages != 2 && nstages != 3) || !slots) {
+  if (capacity_blocks < 1 || max_jobs < 1 || nstages < 2 || nstages > 4 || !slots) {
     g_init_err = "bad capacity, job count, stage count or slots";
     return AMRVAC_E_ARG;
   }
-  const int nslots = nstages == 3 ? 3 : 2;
+  const int nslots = nstages >= 3 ? 3 : 2;
   for (int s = 0; s < nslots; ++s)
     if (!slots[s]) { g_init_err = "null slot pointer"; return AMRVAC_E_ARG; }
   amrvac_ctx* c = new amrvac_ctx();

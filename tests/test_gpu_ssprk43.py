@@ -1,0 +1,96 @@
+"""SSPRK(4,3) (the four-step scheme of the paper's time-integration table):
+four forward-Euler stages of dt/2 with the third returning to the step's
+start with weight 1/3, on the plain and fused paths, in graphs and batches,
+against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_2303_03026_amd import inputs
+from test_gpu_parity import assert_parity, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+PATHS = ["plain", "fused"]
+
+
+@pytest.fixture(scope="module")
+def amr():
+    from paper_2303_03026_amd import amrvac
+    return amrvac
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def run_gpu(amr, w, nsteps, path, precision=0, graph=False):
+    sim = amr.Simulation(w, path=amr.PATH_FUSED if path == "fused" else amr.PATH_PLAIN, precision=precision)
+    sim.advance(nsteps, nstages=4, graph=graph)
+    fl = sim.sync_flags()
+    out = sim.cons()
+    sim.close()
+    return out, fl
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_uniform_state_bit_identical(amr, path):
+    w = inputs.uniform_state(3, (2, 2, 2), [1.3, 0.4, -0.25, 0.15, 0.8, 0.6, -0.9, 0.3, 0.0])
+    sim = amr.Simulation(w, path=amr.PATH_FUSED if path == "fused" else amr.PATH_PLAIN)
+    u0 = sim.cons()
+    sim.advance(4, nstages=4)
+    assert np.array_equal(sim.cons(), u0)
+    sim.close()
+
+
+CASES = [("random_modes_3d_48", lambda: inputs.random_modes(48, 3, seed=21, nsteps=10)),
+         ("orszag_tang_2d", lambda: inputs.orszag_tang_2d(nsteps=40)),
+         ("smooth_amr_3d", lambda: inputs.smooth_amr_state(3, nb1=2, seed=22)),
+         ("current_sheet_32", lambda: inputs.current_sheet(32, nsteps=10))]
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_parity_with_oracle(amr, orc, name, make, path):
+    w = make()
+    if name == "smooth_amr_3d":
+        w.nsteps = 4
+    w.nstages = 4
+    ref, _ = orc.run(w)
+    gpu, fl = run_gpu(amr, w, w.nsteps, path)
+    assert fl[0] == 0
+    assert_parity(w, gpu, ref, label="ssprk43 %s %s" % (name, path))
+
+
+def test_graph_equals_eager(amr):
+    w = inputs.smooth_amr_state(3, nb1=2, seed=23)
+    a, _ = run_gpu(amr, w, 4, "fused", graph=False)
+    b, _ = run_gpu(amr, w, 4, "fused", graph=True)
+    assert np.array_equal(a, b)
+
+
+def test_batch_job_equals_alone(amr):
+    shape = inputs.random_modes(32, 3, seed=0)
+    ws = [inputs.random_modes(32, 3, seed=24, nsteps=5), inputs.random_modes(48, 3, seed=25, nsteps=3)]
+    batch = amr.Batch(shape, capacity_blocks=100, max_jobs=4, nstages=4)
+    ids = [batch.add_job(w) for w in ws]
+    while any(batch.job_info(i)[1] > 0 for i in ids):
+        batch.step()
+    outs = [batch.get_job(i) for i in ids]
+    batch.close()
+    for w, got in zip(ws, outs):
+        ref, _ = run_gpu(amr, w, w.nsteps, "fused")
+        assert np.array_equal(got, ref)
+
+
+def test_mixed_precision_bound(amr, orc):
+    w = inputs.random_modes(48, 3, seed=26, nsteps=10)
+    w.nstages = 4
+    ref, _ = orc.run(w)
+    got, fl = run_gpu(amr, w, w.nsteps, "fused", precision=1)
+    assert fl[0] == 0
+    err = rel_l1(w, got, ref)
+    # rho and e relative; the small components by the field / momentum scale
+    assert err[0] < 1e-6 and err[4] < 1e-6, err

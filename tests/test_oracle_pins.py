@@ -238,7 +238,7 @@ def _uniform_w():
     return [1.3, 0.4, -0.25, 0.15, 0.8, 0.6, -0.9, 0.3, 0.0]
 
 
-@pytest.mark.parametrize("ndim,nstages", [(2, 1), (2, 2), (2, 3), (3, 3)])
+@pytest.mark.parametrize("ndim,nstages", [(2, 1), (2, 2), (2, 3), (3, 3), (2, 4), (3, 4)])
 def test_uniform_state_bit_identical(orc, ndim, nstages):
     w = inputs.uniform_state(ndim, (3, 2, 2), _uniform_w())
     w.nstages = nstages
@@ -317,7 +317,7 @@ def _scale(w, u):
     return np.array([math.fsum(np.abs(u[:, q]).ravel()) for q in range(NV)]) / u[:, 0].size
 
 
-@pytest.mark.parametrize("nstages", [2, 3])
+@pytest.mark.parametrize("nstages", [2, 3, 4])
 def test_conservation_periodic(orc, nstages):
     w = inputs.orszag_tang_2d(n=64)
     w.nstages = nstages
@@ -368,6 +368,9 @@ def test_conservation_periodic_amr_3d(orc):
     (1, lambda z: 1 + z),
     (2, lambda z: 1 + z + z * z / 2),
     (3, lambda z: 1 + z + z * z / 2 + z ** 3 / 6),
+    # SSPRK(4,3): four dt/2 stages, third order; the z^4 term is 1/48, not
+    # the exponential's 1/24
+    (4, lambda z: 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 48),
 ])
 def test_glm_damping_stability_polynomial(orc, nstages, poly):
     """A uniform state with psi != 0 only feels the damping source
