@@ -398,7 +398,12 @@ class Batch:
         ijk = np.ascontiguousarray(w.ijk, dtype=np.int32)
         jid = ctypes.c_int()
         with torch.cuda.stream(self.stream):
-            prim = torch.from_numpy(np.ascontiguousarray(w.prim, dtype=np.float64)).to(self.device)
+            if isinstance(w.prim, torch.Tensor):
+                # pinned host or device tensor: queued on this stream without a
+                # host wait
+                prim = w.prim.to(self.device, dtype=torch.float64, non_blocking=True)
+            else:
+                prim = torch.from_numpy(np.ascontiguousarray(w.prim, dtype=np.float64)).to(self.device)
             rc = self.lib.amrvac_batch_add_job(
                 self.ctx, ctypes.byref(desc), len(level), level.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                 ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.c_void_p(prim.data_ptr()),

@@ -316,6 +316,13 @@ struct amrvac_ctx {
   // emptied before the next accumulation.  Otherwise they are empty.
   int carry_slot = -1;
   bool acc_dirty = false;
+  // Pinned staging buffers for table uploads (see upload_async).
+  static constexpr int kStaging = 8;
+  void* stg_host[kStaging] = {};
+  size_t stg_cap[kStaging] = {};
+  hipEvent_t stg_done[kStaging] = {};
+  bool stg_pending[kStaging] = {};
+  int stg_next = 0;
   std::string err;
 
   Tables tables() const { return Tables{d_level, d_job, d_invdx, d_link, d_pos, d_wrap, d_order, n_order}; }
@@ -343,6 +350,10 @@ void free_all(amrvac_ctx* c) {
                   c->d_jkappa, c->d_prim,  c->d_flux[0], c->d_flux[1], c->d_flux[2], c->d_status};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (int k = 0; k < amrvac_ctx::kStaging; ++k) {
+    if (c->stg_host[k]) (void)hipHostFree(c->stg_host[k]);
+    if (c->stg_done[k]) (void)hipEventDestroy(c->stg_done[k]);
+  }
 }
 
 int dev_alloc(amrvac_ctx* c, void** p, size_t n) {
@@ -354,24 +365,75 @@ int dev_alloc(amrvac_ctx* c, void** p, size_t n) {
   return AMRVAC_OK;
 }
 
-// Upload a host list into a device buffer, growing it when needed (called
-// with the stream idle).
+// Host-to-device table uploads ordered on the context's stream: the data is
+// copied into a pinned staging buffer and sent with hipMemcpyAsync, so the
+// copies queue behind the kernels already enqueued (which still read the old
+// tables) and a table change never drains the stream.  A ring of staging
+// buffers keeps the host from overwriting one before its copy has run.
+struct UploadItem {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+
+int upload_async(amrvac_ctx* c, const std::vector<UploadItem>& items) {
+  auto padded = [](size_t n) { return (n + 255) & ~size_t(255); };
+  size_t total = 0;
+  for (const auto& it : items) total += padded(it.bytes);
+  if (total == 0) return AMRVAC_OK;
+  const int k = c->stg_next;
+  c->stg_next = (k + 1) % amrvac_ctx::kStaging;
+  if (c->stg_pending[k]) {
+    HIP_TRY(c, hipEventSynchronize(c->stg_done[k]));
+    c->stg_pending[k] = false;
+  }
+  if (!c->stg_done[k]) HIP_TRY(c, hipEventCreateWithFlags(&c->stg_done[k], hipEventDisableTiming));
+  if (c->stg_cap[k] < total) {
+    if (c->stg_host[k]) (void)hipHostFree(c->stg_host[k]);
+    c->stg_host[k] = nullptr;
+    c->stg_cap[k] = 0;
+    const size_t n = std::max(total + total / 2, size_t(4096));
+    if (hipHostMalloc(&c->stg_host[k], n, hipHostMallocDefault) != hipSuccess) {
+      c->stg_host[k] = nullptr;
+      return fail(c, AMRVAC_E_NOMEM, "pinned staging allocation failed");
+    }
+    c->stg_cap[k] = n;
+  }
+  char* h = static_cast<char*>(c->stg_host[k]);
+  size_t off = 0;
+  for (const auto& it : items) {
+    if (it.bytes == 0) continue;
+    std::memcpy(h + off, it.src, it.bytes);
+    HIP_TRY(c, hipMemcpyAsync(it.dst, h + off, it.bytes, hipMemcpyHostToDevice, c->stream));
+    off += padded(it.bytes);
+  }
+  HIP_TRY(c, hipEventRecord(c->stg_done[k], c->stream));
+  c->stg_pending[k] = true;
+  return AMRVAC_OK;
+}
+
+// Make room for a host list in a device buffer (growing it by half again
+// when needed; a reallocation waits for the stream, since queued kernels may
+// still read the old buffer) and add its upload to items.
 template <class T>
-int upload_list(amrvac_ctx* c, T** d, size_t* capn, const std::vector<T>& h) {
+int stage_list(amrvac_ctx* c, T** d, size_t* capn, const std::vector<T>& h, std::vector<UploadItem>& items) {
   if (h.size() > *capn || !*d) {
-    if (*d) (void)hipFree(*d);
+    if (*d) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      (void)hipFree(*d);
+    }
     *d = nullptr;
-    const size_t n = std::max<size_t>(h.size(), 64);
+    const size_t n = std::max<size_t>(h.size() + h.size() / 2, 64);
     if (int rc = dev_alloc(c, (void**)d, n * sizeof(T))) return rc;
     *capn = n;
   }
-  if (!h.empty()) HIP_TRY(c, hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (!h.empty()) items.push_back(UploadItem{*d, h.data(), h.size() * sizeof(T)});
   return AMRVAC_OK;
 }
 
 // Rebuild the active lists and per-job geometry from the job records and
-// upload them (called with the stream idle).  A job is active while it has
-// steps left (always, in a single-job context).
+// upload them behind the work already on the stream.  A job is active while
+// it has steps left (always, in a single-job context).
 int rebuild(amrvac_ctx* c) {
   std::vector<int> order, tfill, tfused, tprol, trefl;
   std::vector<double> geom((size_t)c->njob_cap * 4, 0.0);
@@ -402,13 +464,15 @@ int rebuild(amrvac_ctx* c) {
     trefl.swap(by_dir);
   }
   int rc;
-  if ((rc = upload_list(c, &c->d_order, &c->cap_order, order)) ||
-      (rc = upload_list(c, &c->d_tfill, &c->cap_tfill, tfill)) ||
-      (rc = upload_list(c, &c->d_tfused, &c->cap_tfused, tfused)) ||
-      (rc = upload_list(c, &c->d_tprol, &c->cap_tprol, tprol)) ||
-      (rc = upload_list(c, &c->d_trefl, &c->cap_trefl, trefl)))
+  std::vector<UploadItem> items;
+  if ((rc = stage_list(c, &c->d_order, &c->cap_order, order, items)) ||
+      (rc = stage_list(c, &c->d_tfill, &c->cap_tfill, tfill, items)) ||
+      (rc = stage_list(c, &c->d_tfused, &c->cap_tfused, tfused, items)) ||
+      (rc = stage_list(c, &c->d_tprol, &c->cap_tprol, tprol, items)) ||
+      (rc = stage_list(c, &c->d_trefl, &c->cap_trefl, trefl, items)))
     return rc;
-  HIP_TRY(c, hipMemcpy(c->d_geom, geom.data(), geom.size() * sizeof(double), hipMemcpyHostToDevice));
+  items.push_back(UploadItem{c->d_geom, geom.data(), geom.size() * sizeof(double)});
+  if ((rc = upload_async(c, items))) return rc;
   c->n_order = (int)order.size();
   c->n_tfill = (int)tfill.size() / 2;
   c->n_tfused = (int)tfused.size() / 2;
@@ -447,8 +511,10 @@ void drop_carry(amrvac_ctx* c) {
 
 int ensure_tables(amrvac_ctx* c) {
   if (!c->dirty) return AMRVAC_OK;
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  drop_graph(c);
+  if (c->graph_exec) {  // a replay in flight reads the old lists
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+  }
   drop_carry(c);  // job slots and block lists change
   return rebuild(c);
 }
@@ -457,14 +523,13 @@ int ensure_tables(amrvac_ctx* c) {
 int upload_job_blocks(amrvac_ctx* c, const JobRec& J, int jslot) {
   const size_t f = J.first, n = J.nb;
   std::vector<int> jobv(n, jslot);
-  HIP_TRY(c, hipMemcpy(c->d_level + f, J.t.level.data(), n * sizeof(int), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->d_job + f, jobv.data(), n * sizeof(int), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->d_pos + 3 * f, J.t.pos.data(), 3 * n * sizeof(int), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->d_wrap + 3 * f, J.t.wrap.data(), 3 * n * sizeof(int), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->d_invdx + 3 * f, J.t.invdx.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->d_link + f * 6 * LINK_INTS, J.t.link.data(), n * 6 * LINK_INTS * sizeof(int),
-                       hipMemcpyHostToDevice));
-  return AMRVAC_OK;
+  return upload_async(c, {UploadItem{c->d_level + f, J.t.level.data(), n * sizeof(int)},
+                          UploadItem{c->d_job + f, jobv.data(), n * sizeof(int)},
+                          UploadItem{c->d_pos + 3 * f, J.t.pos.data(), 3 * n * sizeof(int)},
+                          UploadItem{c->d_wrap + 3 * f, J.t.wrap.data(), 3 * n * sizeof(int)},
+                          UploadItem{c->d_invdx + 3 * f, J.t.invdx.data(), 3 * n * sizeof(double)},
+                          UploadItem{c->d_link + f * 6 * LINK_INTS, J.t.link.data(),
+                                     n * 6 * LINK_INTS * sizeof(int)}});
 }
 
 // Allocate the pool-sized tables and per-job arrays of a new context.
@@ -1002,7 +1067,7 @@ int amrvac_batch_add_job(amrvac_ctx* c, const amrvac_grid_desc* g, int nb, const
   J.first = first;
   J.nb = nb;
   J.steps_left = nsteps;
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // (stream-ordered: kernels already queued still see the blocks' old tables)
   if (int rc = upload_job_blocks(c, J, jslot)) return rc;
   HIP_TRY(c, launch_set_prim(c->stream, c->G, first, nb, prim_dev, c->slots[0], c->P));
   c->free_runs[run].first += nb;
@@ -1052,7 +1117,8 @@ int amrvac_batch_remove_job(amrvac_ctx* c, int job) {
   if (!c) return AMRVAC_E_ARG;
   if (!job_ok(c, job)) return fail(c, AMRVAC_E_ARG, "no such job");
   JobRec& J = c->jobs[job];
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // host bookkeeping only: a later job placed in these blocks is written by
+  // work queued behind everything already on the stream
   c->free_runs.push_back({J.first, J.nb});  // return the run, merging neighbours
   std::sort(c->free_runs.begin(), c->free_runs.end());
   std::vector<std::pair<int, int>> merged;

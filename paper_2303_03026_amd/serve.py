@@ -85,8 +85,16 @@ class ServingEngine:
         order = sorted(range(len(jobs)), key=lambda i: jobs[i]["arrival"])
         futures = {}
         ahead = 64
+
+        def prepare(job):
+            # generate the job's initial state and pin it (worker thread), so
+            # that admission queues its upload without a host wait
+            w = inputs.serving_job_workload(job)
+            w.prim = torch.from_numpy(np.ascontiguousarray(w.prim, dtype=np.float64)).pin_memory()
+            return w
+
         for i in order[:ahead]:
-            futures[i] = self.pool_exec.submit(inputs.serving_job_workload, jobs[i])
+            futures[i] = self.pool_exec.submit(prepare, jobs[i])
         next_prefetch = ahead
         queues = {cls: collections.deque() for cls in self.CLASSES}
         resident = {cls: {} for cls in self.CLASSES}  # job id in pool -> job index
@@ -100,7 +108,9 @@ class ServingEngine:
         t0 = time.perf_counter()
         last_log = t0
         pending_events = {cls: collections.deque() for cls in self.CLASSES}
-        while arrived < len(order) or any(queues[c] for c in self.CLASSES) or any(resident[c] for c in self.CLASSES):
+        finishing = collections.deque()  # (event after a job's last step, job index)
+        while (arrived < len(order) or finishing or any(queues[c] for c in self.CLASSES)
+               or any(resident[c] for c in self.CLASSES)):
             now = time.perf_counter() - t0
             # arrivals
             while arrived < len(order) and jobs[order[arrived]]["arrival"] * time_scale <= now:
@@ -110,7 +120,7 @@ class ServingEngine:
                 arrived += 1
                 if next_prefetch < len(order):
                     j = order[next_prefetch]
-                    futures[j] = self.pool_exec.submit(inputs.serving_job_workload, jobs[j])
+                    futures[j] = self.pool_exec.submit(prepare, jobs[j])
                     next_prefetch += 1
             # admissions: first come, first served within each class
             for cls in self.CLASSES:
@@ -146,7 +156,9 @@ class ServingEngine:
                 # bound the host's run-ahead to two rounds per class
                 while len(pending_events[cls]) > 2:
                     pending_events[cls].popleft().synchronize()
-            # completions
+            # completions: the job leaves the pool at once (a job placed in
+            # its blocks is written behind its last step on the stream); its
+            # completion time is taken when an event after that step fires
             for cls in self.CLASSES:
                 pool = self.pools[cls]
                 for jid in [j for j, n in left[cls].items() if n == 0]:
@@ -154,14 +166,23 @@ class ServingEngine:
                     i = resident[cls].pop(jid)
                     if keep_results is not None and jobs[i]["id"] in keep_results:
                         results[jobs[i]["id"]] = pool.get_job(jid)
-                    else:
-                        pool.stream.synchronize()
-                    rec[i]["done"] = time.perf_counter() - t0
+                    ev = torch.cuda.Event()
+                    ev.record(pool.stream)
+                    finishing.append((ev, i))
                     pool.remove_job(jid)
+            now = time.perf_counter() - t0
+            for _ in range(len(finishing)):
+                ev, i = finishing.popleft()
+                if ev.query():
+                    rec[i]["done"] = now
+                else:
+                    finishing.append((ev, i))
             if not stepped:
                 nxt = jobs[order[arrived]]["arrival"] * time_scale if arrived < len(order) else None
                 if nxt is not None and not any(queues[c] for c in self.CLASSES):
                     time.sleep(max(0.0, min(0.01, nxt - (time.perf_counter() - t0))))
+                elif finishing:
+                    time.sleep(0.0002)
             if time.perf_counter() - last_log > log_every:
                 last_log = time.perf_counter()
                 ndone = sum(1 for r in rec.values() if "done" in r)

@@ -5,7 +5,9 @@ Bar: relative L1 per conserved variable <= 1e-12 (volume-weighted over leaf
 interior cells); variables that are identically zero in the oracle must be
 exactly zero on the GPU.  Uniform states must stay bit-identical.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -42,6 +44,11 @@ def assert_parity(w, gpu, ref, tol=TOL, label=""):
     assert np.all(np.isfinite(gpu)), label
     err = rel_l1(w, gpu, ref)
     print("%s rel-L1 per var: %s" % (label, " ".join("%.2e" % e for e in err)), flush=True)
+    report = os.environ.get("AMRVAC_PARITY_REPORT")
+    if report:  # one JSON line per comparison (collected for the design notes)
+        with open(report, "a") as f:
+            f.write(json.dumps({"case": label, "max_rel_l1": float(np.max(err)),
+                                "rel_l1": [float(e) for e in err]}) + "\n")
     for q in range(NV):
         if np.all(ref[:, q] == 0):
             assert np.all(gpu[:, q] == 0), (label, q)
