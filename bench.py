@@ -31,33 +31,33 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
                   "paper_2303_03026_amd/csrc/kernels.h", "paper_2303_03026_amd/csrc/runtime.cpp")
 MEASURED_TRAFFIC = {
-    ("e233fd93c002420c", "f64"): {
-        (1, 0, 0): ((2852525, 1180154), (3632534, 1180338)),
-        (1, 0, 1): ((2713938, 1180123), (3558531, 1180323)),
-        (1, 1, 0): ((2858361, 1179987), (3647400, 1180259)),
-        (1, 1, 1): ((2696963, 1180019), (3553821, 1180411)),
-        (2, 0, 0): ((3061731, 1179908), (3849541, 1180228)),
-        (2, 0, 1): ((2942546, 1179915), (3800971, 1180248)),
-        (2, 1, 0): ((3076517, 1179997), (3858867, 1180220)),
-        (2, 1, 1): ((2920720, 1179957), (3789844, 1180269)),
-        (4, 0, 0): ((3517106, 1179743), (4307937, 1179876)),
-        (4, 0, 1): ((3191323, 1179773), (4065639, 1179871)),
-        (4, 1, 0): ((3515005, 1179827), (4306162, 1179940)),
-        (4, 1, 1): ((3165402, 1179785), (4080273, 1179922)),
+    ("888a6bfbae904141", "f64"): {
+        (1, 0, 0): ((2854456, 1180272), (3636666, 1180173)),
+        (1, 0, 1): ((2713068, 1180119), (3562262, 1180301)),
+        (1, 1, 0): ((2860809, 1180018), (3648858, 1180384)),
+        (1, 1, 1): ((2698450, 1180006), (3556036, 1180410)),
+        (2, 0, 0): ((3077022, 1179881), (3870654, 1180149)),
+        (2, 0, 1): ((2944293, 1179952), (3801956, 1180218)),
+        (2, 1, 0): ((3080715, 1179951), (3863486, 1180267)),
+        (2, 1, 1): ((2932507, 1179991), (3775964, 1180374)),
+        (4, 0, 0): ((3515989, 1179738), (4310477, 1179809)),
+        (4, 0, 1): ((3171074, 1179762), (4043540, 1179822)),
+        (4, 1, 0): ((3516884, 1179748), (4305657, 1179837)),
+        (4, 1, 1): ((3157870, 1179774), (4058107, 1179851)),
     },
-    ("e233fd93c002420c", "mixed"): {
-        (1, 0, 0): ((1707994, 819548), (2180998, 819585)),
-        (1, 0, 1): ((1572006, 819509), (2075949, 819631)),
-        (1, 1, 0): ((1706914, 819475), (2165047, 819738)),
-        (1, 1, 1): ((1571172, 819481), (2077380, 819760)),
-        (2, 0, 0): ((1824189, 819400), (2297525, 819493)),
-        (2, 0, 1): ((1705969, 819381), (2215694, 819478)),
-        (2, 1, 0): ((1827506, 819428), (2303804, 819563)),
-        (2, 1, 1): ((1710590, 819442), (2220957, 819593)),
-        (4, 0, 0): ((2097801, 819264), (2561820, 819335)),
-        (4, 0, 1): ((1826336, 819249), (2370395, 819328)),
-        (4, 1, 0): ((2101740, 819273), (2563036, 819341)),
-        (4, 1, 1): ((1827499, 819267), (2370972, 819351)),
+    ("888a6bfbae904141", "mixed"): {
+        (1, 0, 0): ((1715068, 819481), (2180635, 819500)),
+        (1, 0, 1): ((1569338, 819484), (2074791, 819529)),
+        (1, 1, 0): ((1709294, 819455), (2175942, 819643)),
+        (1, 1, 1): ((1569191, 819486), (2073226, 819709)),
+        (2, 0, 0): ((1825990, 819350), (2301521, 819468)),
+        (2, 0, 1): ((1703195, 819342), (2212812, 819441)),
+        (2, 1, 0): ((1830320, 819413), (2302729, 819528)),
+        (2, 1, 1): ((1708012, 819409), (2216438, 819532)),
+        (4, 0, 0): ((2096305, 819252), (2557316, 819356)),
+        (4, 0, 1): ((1825201, 819230), (2365479, 819345)),
+        (4, 1, 0): ((2100570, 819265), (2563254, 819368)),
+        (4, 1, 1): ((1828384, 819238), (2366534, 819339)),
     },
 }
 FETCH_CAL, WRITE_CAL = 2.0, 1.0

@@ -236,6 +236,25 @@ __device__ __forceinline__ void hll_glm_flux(R wl[NV], R wr[NV], R ch, R half_in
   F[I_PSI] = ch * ch * bn;
 }
 
+// First-order fallback at a face: where rho or p of either reconstructed
+// state is not positive, both states become the two cell states (cl, cr).
+// It is rare, so the selects run only in waves where some lane needs them
+// (a wave-uniform branch on the vote).
+template <class R>
+__device__ __forceinline__ void positivity_fallback(R wl[NV], R wr[NV], const R cl[NV], const R cr[NV]) {
+  const bool bad = !((wl[I_RHO] > R(0)) && (wl[4] > R(0)) && (wr[I_RHO] > R(0)) && (wr[4] > R(0)));
+  if (__any(bad)) {
+    asm volatile("");  // keeps the branch: the compiler would otherwise select unconditionally
+    if (bad) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        wl[q] = cl[q];
+        wr[q] = cr[q];
+      }
+    }
+  }
+}
+
 // Reconstructed left/right states at the face between cells a (=i) and
 // b (=i+1) from four primitive cells m (=i-1), a, b, p (=i+2), with the
 // first-order fallback when rho or p is not positive on either side.
@@ -249,14 +268,7 @@ __device__ __forceinline__ void reconstruct_face(const R wm[NV], const R wa[NV],
     wl[q] = wa[q] + R(0.5) * sa;
     wr[q] = wb[q] - R(0.5) * sb;
   }
-  const bool ok = (wl[I_RHO] > R(0)) && (wl[4] > R(0)) && (wr[I_RHO] > R(0)) && (wr[4] > R(0));
-  if (!ok) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      wl[q] = wa[q];
-      wr[q] = wb[q];
-    }
-  }
+  positivity_fallback(wl, wr, wa, wb);
 }
 
 // ---------------------------------------------------------------------------

@@ -71,13 +71,7 @@ __device__ __forceinline__ void face_states(const R (*__restrict__ Wp)[BP * WROW
     wl[q] = wm[q] + R(0.5) * Sl[q][line * SLOPE_ROW + f];
     wr[q] = wp[q] - R(0.5) * Sl[q][line * SLOPE_ROW + f + 1];
   }
-  if (!((wl[I_RHO] > R(0)) && (wl[4] > R(0)) && (wr[I_RHO] > R(0)) && (wr[4] > R(0)))) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      wl[q] = wm[q];
-      wr[q] = wp[q];
-    }
-  }
+  positivity_fallback(wl, wr, wm, wp);
 }
 
 // van Leer slope along DIR of LDS cell (line, a), a in -1..16
@@ -359,13 +353,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
         wr[q] = wa[q] - R(0.5) * s0;
         wla[q] = wa[q] + R(0.5) * s0;
       }
-      if (!((wl[I_RHO] > R(0)) && (wl[4] > R(0)) && (wr[I_RHO] > R(0)) && (wr[4] > R(0)))) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          wl[q] = wm1[q];
-          wr[q] = wa[q];
-        }
-      }
+      positivity_fallback(wl, wr, wm1, wa);
       hll_glm_flux<2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
@@ -437,13 +425,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
         wr[q] = wb[q] - R(0.5) * s1;
         wla[q] = wb[q] + R(0.5) * s1;
       }
-      if (!((wl[I_RHO] > R(0)) && (wl[4] > R(0)) && (wr[I_RHO] > R(0)) && (wr[4] > R(0)))) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          wl[q] = wa[q];
-          wr[q] = wb[q];
-        }
-      }
+      positivity_fallback(wl, wr, wa, wb);
       hll_glm_flux<2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
       // fz becomes F_z(k+1/2)/dz (the energy term in double, in fze); it is
       // added here and its negative seeds the next plane's accumulator

@@ -253,6 +253,53 @@ def test_small_value_flag_and_fix(amr, orc):
     assert_parity(w, gpu, o.cons(), label="fixed")
 
 
+def fallback_state():
+    """Random modes 32^3 with negative pressure in a few cells (fix off): every
+    face of such a cell reconstructs a non-positive p and drops to first order
+    in all variables, while the smooth rho, v, B around it have nonzero slopes.
+    The cells sit inside blocks, on low and high block faces in x, y and z, and
+    in monotone pairs along x and z (so that a neighbour's slope is nonzero
+    too).  Without the fallback the oracle's result moves by 1e-6 .. 1e-3
+    relative L1 on this state."""
+    w = inputs.random_modes(32, 3, seed=31)
+    bad = [(0, 5, 6, 7), (1, 0, 8, 8), (2, 8, 15, 3), (3, 7, 7, 0), (4, 15, 0, 15),
+           (5, 6, 6, 6), (5, 6, 6, 7), (6, 9, 6, 6), (6, 10, 6, 6)]
+    for b, k, j, i in bad:
+        w.prim[b, PR, k, j, i] = -1e-3
+    w.prim[5, PR, 6, 6, 6] = -0.5e-3
+    w.prim[6, PR, 9, 6, 6] = -0.5e-3
+    return w
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_parity_first_order_fallback(amr, orc, path):
+    w = fallback_state()
+    ref, diag = orc.run(w, 1, check=False)
+    assert diag[0, 3] != 0  # the oracle flags the state too
+    sim = make_sim(amr, w, path)
+    sim.advance(1, nstages=3)
+    fl, nfix, _, rc = sim.sync_flags(raise_on_error=False)
+    gpu = sim.cons()
+    sim.close()
+    assert rc == amr.E_NONPHYSICAL and fl & amr.FLAG_SMALL_P
+    assert_parity(w, gpu, ref, label="fallback_%s" % path)
+
+
+def test_fallback_mixed_precision(amr, orc):
+    """The FP32 faces take the same fallback decisions (the pressures are far
+    from zero in FP32), so the mixed path stays within its usual bound."""
+    w = fallback_state()
+    ref, _ = orc.run(w, 1, check=False)
+    sim = amr.Simulation(w, path=amr.PATH_FUSED, precision=amr.FP32_MIXED)
+    sim.advance(1, nstages=3)
+    fl, nfix, _, rc = sim.sync_flags(raise_on_error=False)
+    gpu = sim.cons()
+    sim.close()
+    assert rc == amr.E_NONPHYSICAL and fl & amr.FLAG_SMALL_P
+    err = rel_l1(w, gpu, ref)
+    assert err[RHO] < 1e-6 and err[PR] < 1e-6, err
+
+
 # ---------------------------------------------------------------------------
 # full-size workloads, one step, in the configuration the benchmark times
 
