@@ -21,169 +21,183 @@ __device__ __forceinline__ long pidx(const GridConst& G, int i, int j, int k) {
 }
 
 // ---------------------------------------------------------------------------
-// ghost filling: one workgroup per (block, face) task
+// ghost filling: one thread per ghost cell of a (block, face) task
+//
+// Every load a ghost cell needs is issued before any of its stores.  Sources
+// and destination lie in the same slot, so a store the compiler cannot tell
+// apart from the loads after it would cost one memory round trip per
+// variable.
 
-template <class SP>
-__global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __restrict__ tasks, Tables T,
+template <int NDIM>
+__device__ __forceinline__ long pidx_n(const GridConst& G, int i, int j, int k) {
+  const int kk = NDIM == 3 ? k + G.ng : 0;
+  return ((long)kk * G.pn + (j + G.ng)) * G.pn + (i + G.ng);
+}
+
+template <int NDIM, class SP>
+__global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __restrict__ tasks, int ntasks, Tables T,
                                                    void* __restrict__ slot, PhysConst P, FixedBC fixed) {
   const int* __restrict__ link = T.link;
   const int* __restrict__ pos = T.pos;
-  const int task = blockIdx.x;
+  const int nx = G.nx, ng = G.ng;
+  const int ncell = NDIM == 3 ? ng * nx * nx : ng * nx;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)ntasks * ncell) return;
+  const int task = (int)(gid / ncell);
+  const int t = (int)(gid - (long)task * ncell);
   const int b = tasks[2 * task];
   const int face = tasks[2 * task + 1];
   const int d = face >> 1, side = face & 1;
   const int* L = link + ((long)b * 6 + face) * LINK_INTS;
   const int kind = L[0];
-  const int nx = G.nx, ng = G.ng;
-  const int nt2 = G.ndim == 3 ? nx : 1;
-  const int ncell = ng * nx * nt2;
   const int ta = d == 0 ? 1 : 0;  // first transverse axis
   const int tb = d == 2 ? 1 : 2;  // second transverse axis (z in 2D: unused)
   const long pc = G.pcells;
   void* dst = block_ptr<SP>(slot, b, pc);
 
-  for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
-    int a, t1, t2;
-    if (d == 0) {
-      a = t % ng;
-      t1 = (t / ng) % nx;
-      t2 = t / (ng * nx);
-    } else {
-      t1 = t % nx;
-      a = (t / nx) % ng;
-      t2 = t / (nx * ng);
-    }
-    const int gd = side ? nx + a : a - ng;  // ghost coordinate along d
-    int c[3] = {0, 0, 0};
-    c[d] = gd;
-    c[ta] = t1;
-    if (G.ndim == 3) c[tb] = t2;
-    const long di = pidx(G, c[0], c[1], c[2]);
+  int a, t1, t2;
+  if (d == 0) {
+    a = t % ng;
+    t1 = (t / ng) % nx;
+    t2 = t / (ng * nx);
+  } else {
+    t1 = t % nx;
+    a = (t / nx) % ng;
+    t2 = t / (nx * ng);
+  }
+  const int gd = side ? nx + a : a - ng;  // ghost coordinate along d
+  int c[3] = {0, 0, 0};
+  c[d] = gd;
+  c[ta] = t1;
+  if (NDIM == 3) c[tb] = t2;
+  const long di = pidx_n<NDIM>(G, c[0], c[1], c[2]);
 
-    if (kind == LINK_SAME) {
-      const void* src = block_ptr<SP>(slot, L[1], pc);
-      int s[3] = {c[0], c[1], c[2]};
-      s[d] = side ? gd - nx : gd + nx;
-      const long si = pidx(G, s[0], s[1], s[2]);
+  double out[NV];
+  if (kind == LINK_SAME) {
+    const void* src = block_ptr<SP>(slot, L[1], pc);
+    int s[3] = {c[0], c[1], c[2]};
+    s[d] = side ? gd - nx : gd + nx;
+    const long si = pidx_n<NDIM>(G, s[0], s[1], s[2]);
 #pragma unroll
-      for (int q = 0; q < NV; ++q) SP::st(dst, q, di, pc, SP::ld(src, q, si, pc));
-    } else if (kind == LINK_FINE) {
-      // restriction: fine cells under this coarse ghost cell, all in one
-      // fine leaf (chosen by the transverse half)
-      int fc[3] = {0, 0, 0};
-      fc[d] = side ? 2 * gd - 2 * nx : 2 * gd + nx;
-      const int oa = (2 * c[ta]) >= nx ? 1 : 0;
-      fc[ta] = 2 * c[ta] - oa * nx;
-      int ob = 0;
-      if (G.ndim == 3) {
-        ob = (2 * c[tb]) >= nx ? 1 : 0;
-        fc[tb] = 2 * c[tb] - ob * nx;
-      }
-      const void* src = block_ptr<SP>(slot, L[1 + ob * 2 + oa], pc);
-      if (G.ndim == 2) {
-        const long i00 = pidx(G, fc[0], fc[1], 0), i10 = pidx(G, fc[0] + 1, fc[1], 0);
-        const long i01 = pidx(G, fc[0], fc[1] + 1, 0), i11 = pidx(G, fc[0] + 1, fc[1] + 1, 0);
+    for (int q = 0; q < NV; ++q) out[q] = SP::ld(src, q, si, pc);
+  } else if (kind == LINK_FINE) {
+    // restriction: fine cells under this coarse ghost cell, all in one fine
+    // leaf (chosen by the transverse half)
+    int fc[3] = {0, 0, 0};
+    fc[d] = side ? 2 * gd - 2 * nx : 2 * gd + nx;
+    const int oa = (2 * c[ta]) >= nx ? 1 : 0;
+    fc[ta] = 2 * c[ta] - oa * nx;
+    int ob = 0;
+    if (NDIM == 3) {
+      ob = (2 * c[tb]) >= nx ? 1 : 0;
+      fc[tb] = 2 * c[tb] - ob * nx;
+    }
+    const void* src = block_ptr<SP>(slot, L[1 + ob * 2 + oa], pc);
+    if (NDIM == 2) {
+      const long i00 = pidx_n<2>(G, fc[0], fc[1], 0), i10 = pidx_n<2>(G, fc[0] + 1, fc[1], 0);
+      const long i01 = pidx_n<2>(G, fc[0], fc[1] + 1, 0), i11 = pidx_n<2>(G, fc[0] + 1, fc[1] + 1, 0);
 #pragma unroll
-        for (int q = 0; q < NV; ++q)
-          SP::st(dst, q, di, pc,
-                 ((SP::ld(src, q, i00, pc) + SP::ld(src, q, i10, pc)) +
-                  (SP::ld(src, q, i01, pc) + SP::ld(src, q, i11, pc))) * 0.25);
-      } else {
-        long ix[2][2][2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-#pragma unroll
-          for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int aa = 0; aa < 2; ++aa) ix[e][bb][aa] = pidx(G, fc[0] + aa, fc[1] + bb, fc[2] + e);
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          auto v = [&](int e, int bb, int aa) { return SP::ld(src, q, ix[e][bb][aa], pc); };
-          SP::st(dst, q, di, pc,
-                 (((v(0, 0, 0) + v(0, 0, 1)) + (v(0, 1, 0) + v(0, 1, 1))) +
-                  ((v(1, 0, 0) + v(1, 0, 1)) + (v(1, 1, 0) + v(1, 1, 1)))) * 0.125);
-        }
-      }
-    } else if (kind == LINK_PHYS) {
-      const int bc = L[1];
-      if (bc == 3) {  // fixed inflow state
-        double w[NV], u[NV];
-#pragma unroll
-        for (int q = 0; q < NV; ++q) w[q] = fixed.prim[d][side][q];
-        prim_to_cons(w, u, P);
-#pragma unroll
-        for (int q = 0; q < NV; ++q) SP::st(dst, q, di, pc, u[q]);
-      } else {
-        int s[3] = {c[0], c[1], c[2]};
-        if (bc == 1)
-          s[d] = side ? nx - 1 : 0;
-        else
-          s[d] = side ? 2 * nx - 1 - gd : -1 - gd;
-        const long si = pidx(G, s[0], s[1], s[2]);
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          double v = SP::ld(dst, q, si, pc);
-          if (bc == 2 && (q == I_MX + d || q == I_BX + d)) v = -v;
-          SP::st(dst, q, di, pc, v);
-        }
-      }
-    } else {  // LINK_COARSE: conservative minmod-limited linear prolongation
-      const int cb = L[1];
-      const void* src = block_ptr<SP>(slot, cb, pc);
-      int lc[3] = {0, 0, 0};
-      int odd[3] = {0, 0, 0};
-      for (int ax = 0; ax < G.ndim; ++ax) {
-        const long n = T.wrap[3 * b + ax];
-        long g = (long)pos[3 * b + ax] * nx + c[ax];
-        g = (g + n) % n;
-        odd[ax] = (int)(g & 1);
-        lc[ax] = (int)((g >> 1) - (long)pos[3 * cb + ax] * nx);
-      }
-      // The coarse cell lc is interior to cb (the fine ghost lies over cb's
-      // face); a slope neighbour steps out of cb by one cell along one axis
-      // at most, into a face ghost slab of cb.  With a same-level leaf across
-      // that face the cell is read in place from its interior (that slab is
-      // not filled on the fused path); across faces towards finer leaves or
-      // the domain boundary it is cb's own ghost cell, filled before this
-      // pass.  (A face of cb towards a coarser leaf is never reached: the
-      // fine block would then touch that leaf across an edge, which 2:1
-      // nesting excludes.)
-      const long i0 = pidx(G, lc[0], lc[1], lc[2]);
-      const void* sm[3] = {src, src, src};
-      const void* sp[3] = {src, src, src};
-      long im[3], ip[3];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        int m[3] = {lc[0], lc[1], lc[2]}, p[3] = {lc[0], lc[1], lc[2]};
-        m[ax] -= 1;
-        p[ax] += 1;
-        if (ax < G.ndim) {
-          const int* Lm = link + ((long)cb * 6 + 2 * ax) * LINK_INTS;
-          const int* Lp = link + ((long)cb * 6 + 2 * ax + 1) * LINK_INTS;
-          if (m[ax] < 0 && Lm[0] == LINK_SAME) {
-            sm[ax] = block_ptr<SP>(slot, Lm[1], pc);
-            m[ax] += nx;
-          }
-          if (p[ax] >= nx && Lp[0] == LINK_SAME) {
-            sp[ax] = block_ptr<SP>(slot, Lp[1], pc);
-            p[ax] -= nx;
-          }
-        }
-        im[ax] = ax < G.ndim ? pidx(G, m[0], m[1], m[2]) : i0;
-        ip[ax] = ax < G.ndim ? pidx(G, p[0], p[1], p[2]) : i0;
-      }
+      for (int q = 0; q < NV; ++q)
+        out[q] = ((SP::ld(src, q, i00, pc) + SP::ld(src, q, i10, pc)) +
+                  (SP::ld(src, q, i01, pc) + SP::ld(src, q, i11, pc))) * 0.25;
+    } else {
+      // the 2x2x2 fine cells are two x-pairs in each of two z planes
+      const long i000 = pidx_n<3>(G, fc[0], fc[1], fc[2]);
+      const long sy = G.pn, sz = (long)G.pn * G.pn;
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        const double uc = SP::ld(src, q, i0, pc);
-        double r = uc;
-        for (int ax = 0; ax < G.ndim; ++ax) {
-          const double sg = odd[ax] ? 0.25 : -0.25;
-          r = r + sg * minmod2(uc - SP::ld(sm[ax], q, im[ax], pc), SP::ld(sp[ax], q, ip[ax], pc) - uc);
-        }
-        SP::st(dst, q, di, pc, r);
+        auto v = [&](int e, int bb, int aa) { return SP::ld(src, q, i000 + e * sz + bb * sy + aa, pc); };
+        out[q] = (((v(0, 0, 0) + v(0, 0, 1)) + (v(0, 1, 0) + v(0, 1, 1))) +
+                  ((v(1, 0, 0) + v(1, 0, 1)) + (v(1, 1, 0) + v(1, 1, 1)))) * 0.125;
       }
     }
+  } else if (kind == LINK_PHYS) {
+    const int bc = L[1];
+    if (bc == 3) {  // fixed inflow state
+      double w[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) w[q] = fixed.prim[d][side][q];
+      prim_to_cons(w, out, P);
+    } else {
+      int s[3] = {c[0], c[1], c[2]};
+      if (bc == 1)
+        s[d] = side ? nx - 1 : 0;
+      else
+        s[d] = side ? 2 * nx - 1 - gd : -1 - gd;
+      const long si = pidx_n<NDIM>(G, s[0], s[1], s[2]);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const double v = SP::ld(dst, q, si, pc);
+        out[q] = (bc == 2 && (q == I_MX + d || q == I_BX + d)) ? -v : v;
+      }
+    }
+  } else {  // LINK_COARSE: conservative minmod-limited linear prolongation
+    const int cb = L[1];
+    const void* src = block_ptr<SP>(slot, cb, pc);
+    int lc[3] = {0, 0, 0};
+    int odd[3] = {0, 0, 0};
+#pragma unroll
+    for (int ax = 0; ax < NDIM; ++ax) {
+      const long n = T.wrap[3 * b + ax];
+      long g = (long)pos[3 * b + ax] * nx + c[ax];
+      g = (g + n) % n;
+      odd[ax] = (int)(g & 1);
+      lc[ax] = (int)((g >> 1) - (long)pos[3 * cb + ax] * nx);
+    }
+    // The coarse cell lc is interior to cb (the fine ghost lies over cb's
+    // face); a slope neighbour steps out of cb by one cell along one axis
+    // at most, into a face ghost slab of cb.  With a same-level leaf across
+    // that face the cell is read in place from its interior (that slab is
+    // not filled on the fused path); across faces towards finer leaves or
+    // the domain boundary it is cb's own ghost cell, filled before this
+    // pass.  (A face of cb towards a coarser leaf is never reached: the
+    // fine block would then touch that leaf across an edge, which 2:1
+    // nesting excludes.)
+    const long i0 = pidx_n<NDIM>(G, lc[0], lc[1], lc[2]);
+    // block ids, not pointers, are selected (keeps the loads global ones);
+    // the links of all of cb's faces are read at once
+    int lk[2 * NDIM], ln[2 * NDIM];
+#pragma unroll
+    for (int f = 0; f < 2 * NDIM; ++f) {
+      lk[f] = link[((long)cb * 6 + f) * LINK_INTS];
+      ln[f] = link[((long)cb * 6 + f) * LINK_INTS + 1];
+    }
+    int bm[3], bp[3];
+    long im[3], ip[3];
+#pragma unroll
+    for (int ax = 0; ax < NDIM; ++ax) {
+      int m[3] = {lc[0], lc[1], lc[2]}, p[3] = {lc[0], lc[1], lc[2]};
+      m[ax] -= 1;
+      p[ax] += 1;
+      bm[ax] = cb;
+      bp[ax] = cb;
+      if (m[ax] < 0 && lk[2 * ax] == LINK_SAME) {
+        bm[ax] = ln[2 * ax];
+        m[ax] += nx;
+      }
+      if (p[ax] >= nx && lk[2 * ax + 1] == LINK_SAME) {
+        bp[ax] = ln[2 * ax + 1];
+        p[ax] -= nx;
+      }
+      im[ax] = pidx_n<NDIM>(G, m[0], m[1], m[2]);
+      ip[ax] = pidx_n<NDIM>(G, p[0], p[1], p[2]);
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double uc = SP::ld(src, q, i0, pc);
+      double r = uc;
+#pragma unroll
+      for (int ax = 0; ax < NDIM; ++ax) {
+        const double sg = odd[ax] ? 0.25 : -0.25;
+        const double um = SP::ld(block_ptr<SP>(static_cast<const void*>(slot), bm[ax], pc), q, im[ax], pc);
+        const double up = SP::ld(block_ptr<SP>(static_cast<const void*>(slot), bp[ax], pc), q, ip[ax], pc);
+        r = r + sg * minmod2(uc - um, up - uc);
+      }
+      out[q] = r;
+    }
   }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) SP::st(dst, q, di, pc, out[q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -578,10 +592,19 @@ inline unsigned nblocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / b
 hipError_t launch_fill_faces(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const Tables& T,
                              void* slot, const PhysConst& P, const FixedBC& fixed) {
   if (ntasks <= 0) return hipSuccess;
-  if (G.precision == 0)
-    k_fill_faces<StoreF64><<<ntasks, 256, 0, s>>>(G, tasks, T, slot, P, fixed);
-  else
-    k_fill_faces<StoreMixed><<<ntasks, 256, 0, s>>>(G, tasks, T, slot, P, fixed);
+  const long ncell = (long)G.ng * G.nx * (G.ndim == 3 ? G.nx : 1);
+  const unsigned nbk = nblocks_for((long)ntasks * ncell, 256);
+  if (G.ndim == 3) {
+    if (G.precision == 0)
+      k_fill_faces<3, StoreF64><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+    else
+      k_fill_faces<3, StoreMixed><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+  } else {
+    if (G.precision == 0)
+      k_fill_faces<2, StoreF64><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+    else
+      k_fill_faces<2, StoreMixed><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+  }
   return hipGetLastError();
 }
 
