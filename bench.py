@@ -109,9 +109,22 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, small):
     """The oracle (unchanged) on the host cores: one SSPRK(3,3) step of the
-    full grid, reported as Mcell-updates/s."""
+    full grid on all cores, reported as Mcell-updates/s; beside it, one
+    thread on a smaller grid of the same construction (the per-cell work of
+    a block does not depend on the grid size)."""
     from oracle import oracle
     cores = oracle.default_threads()
     sim = oracle.OracleSim(w, nthreads=cores)
@@ -119,10 +132,19 @@ def cpu_baseline(w):
     sim.steps(1)
     t1 = time.perf_counter()
     sim.close()
+    one = oracle.OracleSim(small, nthreads=1)
+    s0 = time.perf_counter()
+    one.steps(2)
+    s1 = time.perf_counter()
+    one.close()
     return {"value": w.interior_cells / (t1 - t0) / 1e6, "unit": "Mcell-updates/s", "cores": cores,
             "kind": "oracle", "seconds": t1 - t0,
             "sample": "1 of the %d SSPRK(3,3) steps on the full %s grid (%d cells), OpenMP over blocks"
-                      % (w.nsteps, w.name, w.interior_cells)}
+                      % (w.nsteps, w.name, w.interior_cells),
+            "single_thread": {"value": 2 * small.interior_cells / (s1 - s0) / 1e6, "seconds": s1 - s0,
+                              "sample": "2 SSPRK(3,3) steps of %s (%d cells), 1 thread"
+                                        % (small.name, small.interior_cells)},
+            "cpu_model": cpu_model()}
 
 
 def main():
@@ -259,11 +281,20 @@ def main():
         "stage_ms": [sum(x) / K for x in stage_ms],
         "roofline": {"bound": "hbm", "kernel": "stage (%s path)" % args.path, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms},
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
+                     # the counter traffic of this launch shape over the live launch time
+                     "traffic_gbs": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
+                     "traffic_frac": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
+        if args.workload == "random_modes":
+            small = inputs.random_modes(64, 3, seed=1)
+        elif args.workload == "current_sheet":
+            small = inputs.current_sheet(n=48)
+        else:
+            small = inputs.shock_cloud_amr(base_n=32)
+        out["cpu_baseline"] = cpu_baseline(w, small)
     print(json.dumps(out), flush=True)
 
 

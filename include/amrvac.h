@@ -156,13 +156,27 @@ int amrvac_stage(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double
 int amrvac_stage_cfl(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double w,
                      const double* dt_dev, const double* ch_dev, const double* kappa_dev);
 
+/* Two-state combination on the leaf interior cells of every block:
+ *   out = a + coef*(b - a)
+ * (arithmetic in double; FP32-mixed slots round the result to their storage
+ * precision).  It is the stage-free row of a Shu-Osher scheme written around
+ * a: the last SSPRK(5,4) stage takes its base state from it.  a, b and out
+ * are slot indices; out may equal a or b (each cell reads its own values
+ * before writing); ghost cells of out are not written.  AMRVAC_E_ARG for a
+ * bad slot or a non-finite coef.  No host synchronisation. */
+int amrvac_combine(amrvac_ctx* c, int a_slot, int b_slot, double coef, int out_slot);
+
 /* Advance nsteps full SSP Runge-Kutta steps of slot 0 (Table
- * tab:schemes_time), using slots 1 and 2 as stage storage and library-owned
+ * tab:schemes_time), using slots 1 .. 3 as stage storage and library-owned
  * dt/c_h/kappa; each step is cfl -> [fill -> stage] x nstages:
  *   nstages = 2: SSPRK(2,2), stage weights (1, 1/2);
  *   nstages = 3: SSPRK(3,3), stage weights (1, 1/4, 2/3);
  *   nstages = 4: SSPRK(4,3), four stages advancing by dt/2 each, weights
- *                (1, 1, 1/3, 1) (the third returns to the step's start).
+ *                (1, 1, 1/3, 1) (the third returns to the step's start);
+ *   nstages = 5: SSPRK(5,4) of Spiteri and Ruuth, Shu-Osher coefficients:
+ *                four stages around the step's start u0, then
+ *                amrvac_combine(u0, u2) and a fifth stage from u4 with that
+ *                base (its L(u3) term is carried by u4).  Needs 4 slots.
  * The last stage folds in the next step's CFL rate where it can
  * (amrvac_stage_cfl).  use_graph = 1 captures one step in a HIP graph on
  * first use and replays it.  No host synchronisation. */
@@ -234,7 +248,7 @@ int amrvac_reset_flags(amrvac_ctx* c);
 
 /* Create a batch context.  shape supplies ndim, block_nx (must be 16),
  * precision and the physics every job must share; nstages as in
- * amrvac_advance; slots are 2 (nstages = 2) or 3 (nstages = 3, 4)
+ * amrvac_advance; slots are 2 (nstages = 2), 3 (nstages = 3, 4) or 4 (nstages = 5)
  * caller-owned DEVICE buffers of
  * amrvac_slot_bytes(shape, capacity_blocks) bytes each (the block pool);
  * max_jobs bounds the number of resident jobs. */

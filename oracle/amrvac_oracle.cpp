@@ -9,7 +9,7 @@
 // What it computes (MPI-AMRVAC 3.0, arXiv 2303.03026):
 //   * conservative cell-centred finite volumes inside a multistage SSP
 //     Runge-Kutta step ("Schemes and limiters for HD and MHD", Table
-//     tab:schemes_time: SSPRK(2,2), SSPRK(3,3) and SSPRK(4,3));
+//     tab:schemes_time: SSPRK(2,2), SSPRK(3,3), SSPRK(4,3) and SSPRK(5,4));
 //   * limited linear reconstruction of primitive variables giving a left and
 //     a right state per face, with the 'vanleer' limiter and 2 ghost cells
 //     (Table t:limiters);
@@ -52,6 +52,8 @@
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
+#include <utility>
+#include <initializer_list>
 #include <vector>
 #ifdef _OPENMP
 #include <omp.h>
@@ -242,7 +244,7 @@ typedef struct {
   int ndim;
   int nx;
   int ng;
-  int nstages;  // 1 = forward Euler, 2 = SSPRK(2,2), 3 = SSPRK(3,3), 4 = SSPRK(4,3)
+  int nstages;  // 1 = forward Euler, 2 = SSPRK(2,2), 3 = SSPRK(3,3), 4 = SSPRK(4,3), 5 = SSPRK(5,4)
   int reflux;
   int fix_small_values;
   int nthreads;
@@ -277,6 +279,8 @@ struct Sim {
   std::unordered_set<Key, KeyHash> refined;
   Cell fixedU[3][2];
   std::vector<BlockData> S0, S1, S2;            // state slots
+  std::vector<BlockData> S3, S4, L3;            // SSPRK(5,4) only: u3, u4 and L(u3)
+  std::vector<BlockData> Lb;                    // L of the current stage input
   std::vector<std::array<BlockData, 3>> flux;  // face fluxes per block and direction
   int flags = 0;
   long nfix = 0;
@@ -454,11 +458,12 @@ struct Sim {
     flags |= f;
   }
 
-  // One explicit stage: out = base + w*((in + dt*L(in)) - base), or
-  // out = in + dt*L(in) when w == 1 (the advect1 statement of the IMEX
-  // implementation section with the SSPRK combination folded in).
-  void stage(std::vector<BlockData>& in, const std::vector<BlockData>* base,
-             std::vector<BlockData>& out, double w, double dt, double ch, double kappa) {
+  // L(in) on the interior cells of every block: ghost fill, primitives,
+  // reconstructed face states, face fluxes, the flux correction at
+  // coarse/fine faces, then minus the flux difference over dx plus the psi
+  // damping source (the right-hand side of the method-of-lines form).
+  void rhs(std::vector<BlockData>& in, std::vector<BlockData>& L_out, double ch, double kappa) {
+    if (L_out.size() != (size_t)nb) L_out.assign(nb, BlockData(pcells));
     fill_ghosts(in);
     const long kmax = ndim == 3 ? nx : 1;
     int fl = 0;
@@ -532,9 +537,29 @@ struct Sim {
             }
             for (int q = 0; q < NV; ++q) L[q] = -L[q];
             L[PSI] = L[PSI] - kappa * u.v[PSI];
+            for (int q = 0; q < NV; ++q) L_out[b][c].v[q] = L[q];
+          }
+    }
+  }
+
+  // One explicit stage: out = base + w*((in + dt*L(in)) - base), or
+  // out = in + dt*L(in) when w == 1 (the advect1 statement of the IMEX
+  // implementation section with the SSPRK combination folded in).
+  void stage(std::vector<BlockData>& in, const std::vector<BlockData>* base,
+             std::vector<BlockData>& out, double w, double dt, double ch, double kappa) {
+    rhs(in, Lb, ch, kappa);
+    const long kmax = ndim == 3 ? nx : 1;
+#pragma omp parallel for schedule(dynamic) num_threads(P.nthreads)
+    for (int b = 0; b < nb; ++b)
+      for (long k = 0; k < kmax; ++k)
+        for (long j = 0; j < nx; ++j)
+          for (long i = 0; i < nx; ++i) {
+            const long c = pidx(i, j, k);
+            const Cell& u = in[b][c];
+            const Cell& L = Lb[b][c];
             Cell& o = out[b][c];
             for (int q = 0; q < NV; ++q) {
-              const double t = u.v[q] + dt * L[q];
+              const double t = u.v[q] + dt * L.v[q];
               if (w == 1.0) {
                 o.v[q] = t;
               } else {
@@ -543,7 +568,29 @@ struct Sim {
               }
             }
           }
-    }
+  }
+
+  // One row of a Shu-Osher scheme whose state weights sum to one, evaluated
+  // around u0 (delta form, so a uniform state stays exact):
+  //   out = u0 + sum_j a_j (u_j - u0) + sum_j b_j dt L_j   (interior cells)
+  using Term = std::pair<double, const std::vector<BlockData>*>;
+  void shu_osher(std::vector<BlockData>& out, const std::vector<BlockData>& u0, std::initializer_list<Term> us,
+                 std::initializer_list<Term> ls, double dt) {
+    const long kmax = ndim == 3 ? nx : 1;
+#pragma omp parallel for schedule(dynamic) num_threads(P.nthreads)
+    for (int b = 0; b < nb; ++b)
+      for (long k = 0; k < kmax; ++k)
+        for (long j = 0; j < nx; ++j)
+          for (long i = 0; i < nx; ++i) {
+            const long c = pidx(i, j, k);
+            for (int q = 0; q < NV; ++q) {
+              const double z = u0[b][c].v[q];
+              double acc = 0.0;
+              for (const Term& t : us) acc = acc + t.first * ((*t.second)[b][c].v[q] - z);
+              for (const Term& t : ls) acc = acc + t.first * (dt * (*t.second)[b][c].v[q]);
+              out[b][c].v[q] = z + acc;
+            }
+          }
   }
 
   // Flux correction at coarse/fine faces: the coarse face flux becomes the
@@ -621,7 +668,7 @@ struct Sim {
       stage(S0, nullptr, S1, 1.0, dt, ch, kappa);
       stage(S1, &S0, S2, 0.25, dt, ch, kappa);
       stage(S2, &S0, S0, 2.0 / 3.0, dt, ch, kappa);
-    } else {
+    } else if (s == 4) {
       // SSPRK(4,3) (Table tab:schemes_time): four forward-Euler stages of
       // dt/2; the third returns to u0 with weight 1/3:
       //   u1 = u0 + h L(u0), u2 = u1 + h L(u1),
@@ -631,6 +678,36 @@ struct Sim {
       stage(S1, nullptr, S2, 1.0, h, ch, kappa);
       stage(S2, &S0, S1, 1.0 / 3.0, h, ch, kappa);
       stage(S1, nullptr, S0, 1.0, h, ch, kappa);
+    } else {
+      // SSPRK(5,4) (five-step row of Table tab:schemes_time; Spiteri and
+      // Ruuth 2002), Shu-Osher form with their published coefficients:
+      //   u1 = u0 + b10 dt L(u0)
+      //   u2 = a20 u0 + a21 u1 + b21 dt L(u1)
+      //   u3 = a30 u0 + a32 u2 + b32 dt L(u2)
+      //   u4 = a40 u0 + a43 u3 + b43 dt L(u3)
+      //   u5 = a52 u2 + a53 u3 + b53 dt L(u3) + a54 u4 + b54 dt L(u4)
+      // (a_k0 = 1 - the other state weights of the row: the delta form).
+      const double b10 = 0.391752226571890;
+      const double a21 = 0.555629506348765, b21 = 0.368410593050371;
+      const double a32 = 0.379898148511597, b32 = 0.251891774271694;
+      const double a43 = 0.821920045606868, b43 = 0.544974750228521;
+      const double a52 = 0.517231671970585, a53 = 0.096059710526147, b53 = 0.063692468666290;
+      const double a54 = 0.386708617503269, b54 = 0.226007483236906;
+      if (S3.size() != (size_t)nb) {
+        S3.assign(nb, BlockData(pcells));
+        S4.assign(nb, BlockData(pcells));
+      }
+      rhs(S0, Lb, ch, kappa);
+      shu_osher(S1, S0, {}, {{b10, &Lb}}, dt);
+      rhs(S1, Lb, ch, kappa);
+      shu_osher(S2, S0, {{a21, &S1}}, {{b21, &Lb}}, dt);
+      rhs(S2, Lb, ch, kappa);
+      shu_osher(S3, S0, {{a32, &S2}}, {{b32, &Lb}}, dt);
+      rhs(S3, L3, ch, kappa);
+      shu_osher(S4, S0, {{a43, &S3}}, {{b43, &L3}}, dt);
+      rhs(S4, Lb, ch, kappa);
+      shu_osher(S1, S0, {{a52, &S2}, {a53, &S3}, {a54, &S4}}, {{b53, &L3}, {b54, &Lb}}, dt);
+      std::swap(S0, S1);
     }
   }
 };
@@ -645,7 +722,7 @@ Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int*
   if (s->ndim != 2 && s->ndim != 3) throw std::invalid_argument("ndim must be 2 or 3");
   if (s->ng != 2) throw std::invalid_argument("the van Leer stencil needs exactly 2 ghost layers");
   if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
-  if (p->nstages < 1 || p->nstages > 4) throw std::invalid_argument("nstages must be 1, 2, 3 or 4");
+  if (p->nstages < 1 || p->nstages > 5) throw std::invalid_argument("nstages must be 1 .. 5");
   if (s->P.nthreads < 1) s->P.nthreads = 1;
   for (int d = 0; d < s->ndim; ++d)
     if ((p->bc_lo[d] == BC_PERIODIC) != (p->bc_hi[d] == BC_PERIODIC))

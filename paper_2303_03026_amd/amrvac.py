@@ -27,7 +27,7 @@ ABI_SYMBOLS = ("amrvac_slot_bytes", "amrvac_init_blocks", "amrvac_set_primitive"
                "amrvac_sync_flags", "amrvac_reset_flags", "amrvac_last_error", "amrvac_destroy",
                "amrvac_batch_create", "amrvac_batch_add_job", "amrvac_batch_step", "amrvac_batch_job_info",
                "amrvac_batch_get_job", "amrvac_batch_remove_job", "amrvac_batch_free_blocks",
-               "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune", "amrvac_stage_cfl")
+               "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune", "amrvac_stage_cfl", "amrvac_combine")
 TUNE_MAX_CANDIDATES = 12
 SLOT_LEAD_FP64 = 16  # bytes before the first block of an FP64 slot
 
@@ -89,6 +89,7 @@ def load_library():
     lib.amrvac_cfl_dt.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.amrvac_stage.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
     lib.amrvac_stage_cfl.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+    lib.amrvac_combine.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]
     lib.amrvac_advance.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.amrvac_set_path.argtypes = [vp, ctypes.c_int]
     lib.amrvac_sync_flags.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong), dp]
@@ -138,9 +139,11 @@ class Simulation:
     stream (default priority) that is handed to the library.
     """
 
-    def __init__(self, w, nslots: int = 3, precision: int = FP64, path: int = PATH_PLAIN,
+    def __init__(self, w, nslots: Optional[int] = None, precision: int = FP64, path: int = PATH_PLAIN,
                  device: str = "cuda", stream=None, set_initial: bool = True):
         import torch
+        if nslots is None:  # SSPRK(5,4) steps need a fourth slot
+            nslots = 4 if w.nstages == 5 else 3
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the MI355X path has no CPU fallback")
         self.torch = torch
@@ -256,6 +259,10 @@ class Simulation:
         fn = self.lib.amrvac_stage_cfl if cfl else self.lib.amrvac_stage
         self._check(fn(self.ctx, in_slot, base_slot, out_slot, weight, self.dt_ptr, self.ch_ptr, self.kappa_ptr),
                     self.ctx)
+
+    def combine(self, a_slot: int, b_slot: int, coef: float, out_slot: int):
+        """out = a + coef (b - a) on the leaf interior cells (amrvac_combine)."""
+        self._check(self.lib.amrvac_combine(self.ctx, a_slot, b_slot, coef, out_slot), self.ctx)
 
     def euler_stage(self, in_slot: int = 0, out_slot: int = 1):
         self.fill(in_slot)
@@ -373,7 +380,7 @@ class Batch:
         if self.lib.amrvac_slot_bytes(ctypes.byref(self.desc), capacity_blocks, ctypes.byref(size)) != 0:
             raise AmrvacError(E_ARG, "bad batch shape")
         self.block_bytes = (size.value - slot_lead(precision)) // capacity_blocks
-        nslots = 3 if nstages >= 3 else 2
+        nslots = 4 if nstages >= 5 else (3 if nstages >= 3 else 2)
         with torch.cuda.stream(self.stream):
             self.slots = [torch.empty(size.value, dtype=torch.uint8, device=self.device) for _ in range(nslots)]
         torch.cuda.synchronize(self.device)

@@ -39,7 +39,8 @@ struct Tables {
 };
 
 // Per-job time-step scalars, indexed by job slot; a stage advances by
-// dt_scale * dt (1 for SSPRK(2,2)/(3,3), 1/2 for the SSPRK(4,3) stages).
+// dt_scale * dt (1 for SSPRK(2,2)/(3,3), 1/2 for the SSPRK(4,3) stages, the
+// beta/alpha ratios of the SSPRK(5,4) stages).
 struct JobScalars {
   const double* dt;
   const double* ch;
@@ -107,6 +108,10 @@ hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T
 hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                                  const int* tasks, const int first[3], const int count[3], const void* in,
                                  void* out, double w, const PhysConst& P);
+
+// out = a + coef (b - a) on the leaf interior cells of the active blocks
+hipError_t launch_combine(hipStream_t s, const GridConst& G, const Tables& T, const void* a, const void* b,
+                          double coef, void* out);
 
 // CFL: per-job max rate over the active blocks (accumulate), then per-job
 // dt, c_h, kappa, which also empties the accumulators (finalize); launch_cfl

@@ -464,6 +464,34 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, J
 }
 
 // ---------------------------------------------------------------------------
+// out = a + coef (b - a) on the leaf interior cells, one thread per cell.
+// Both loads of a cell come before its store, so out may be a or b.
+
+template <class SP>
+__global__ void __launch_bounds__(256) k_combine(GridConst G, Tables T, const void* a, const void* b, double coef,
+                                                void* out) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)T.nactive * G.icells) return;
+  const int n = (int)(gid / G.icells);
+  const int c = (int)(gid - (long)n * G.icells);
+  const int blk = T.order[n];
+  const int nx = G.nx;
+  const int i = c % nx, j = (c / nx) % nx, k = G.ndim == 3 ? c / (nx * nx) : 0;
+  const long pc = pidx(G, i, j, k);
+  const void* pa = block_ptr<SP>(a, blk, G.pcells);
+  const void* pb = block_ptr<SP>(b, blk, G.pcells);
+  void* po = block_ptr<SP>(out, blk, G.pcells);
+  double r[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double x = SP::ld(pa, q, pc, G.pcells);
+    r[q] = x + coef * (SP::ld(pb, q, pc, G.pcells) - x);
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) SP::st(po, q, pc, G.pcells, r[q]);
+}
+
+// ---------------------------------------------------------------------------
 // CFL: max over leaf interior cells of sum_d (|v_d| + c_f,d)/dx_d
 
 template <class SP>
@@ -688,6 +716,17 @@ hipError_t launch_cfl(hipStream_t s, const GridConst& G, const Tables& T, const 
   hipError_t e = launch_cfl_accumulate(s, G, T, slot, P, st, C);
   if (e != hipSuccess) return e;
   return launch_cfl_finalize(s, st, C);
+}
+
+hipError_t launch_combine(hipStream_t s, const GridConst& G, const Tables& T, const void* a, const void* b,
+                          double coef, void* out) {
+  const long n = (long)T.nactive * G.icells;
+  if (n <= 0) return hipSuccess;
+  if (G.precision == 0)
+    k_combine<StoreF64><<<nblocks_for(n, 256), 256, 0, s>>>(G, T, a, b, coef, out);
+  else
+    k_combine<StoreMixed><<<nblocks_for(n, 256), 256, 0, s>>>(G, T, a, b, coef, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_cfl_clear(hipStream_t s, const JobCfl& C) {

@@ -673,15 +673,53 @@ int enqueue_step(amrvac_ctx* c, int nstages, double* dt, double* ch, double* kap
     if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 0, 2.0 / 3.0, J, true))) return rc;
     return AMRVAC_OK;
   }
-  // SSPRK(4,3): four stages of dt/2; u3 = u0 + (1/3)((u2 + h L(u2)) - u0)
-  JobScalars H = J;
-  H.dt_scale = 0.5;
-  if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, H))) return rc;
-  if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 1, 2, 1.0, H))) return rc;
-  if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 1, 1.0 / 3.0, H))) return rc;
-  if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 1, 0, 1.0, H, true))) return rc;
+  if (nstages == 4) {
+    // SSPRK(4,3): four stages of dt/2; u3 = u0 + (1/3)((u2 + h L(u2)) - u0)
+    JobScalars H = J;
+    H.dt_scale = 0.5;
+    if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, H))) return rc;
+    if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 1, 2, 1.0, H))) return rc;
+    if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 1, 1.0 / 3.0, H))) return rc;
+    if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 1, 0, 1.0, H, true))) return rc;
+    return AMRVAC_OK;
+  }
+  // SSPRK(5,4) of Spiteri and Ruuth, Shu-Osher coefficients (alpha_kj for
+  // states, beta_kj for dt L; each row's alphas sum to one):
+  //   u1 = u0 + b10 dt L(u0)
+  //   u_k = u0 + a_k,k-1 ((u_k-1 + (b_k,k-1/a_k,k-1) dt L(u_k-1)) - u0),  k = 2, 3, 4
+  //   u5 = a52 u2 + a53 u3 + b53 dt L(u3) + a54 u4 + b54 dt L(u4)
+  // The fourth row gives dt L(u3) = ((u4 - u0) - a43 (u3 - u0)) / b43, so
+  //   u5 = u0 + g2 (u2 - u0) + g3 (u3 - u0) + g4 (u4 - u0) + b54 dt L(u4)
+  // with g2 = a52, g3 = a53 - b53 a43 / b43, g4 = a54 + b53 / b43.  g3 is zero
+  // for this scheme (the published 15-digit values give -1.8e-16), so the
+  // fifth stage is a stage from u4 with weight g4 and scale b54 / g4 whose
+  // base is u0 + (g2 / (1 - g4)) (u2 - u0).  Slots: u0 0, u1 1, u2 2, u3 1,
+  // u4 3, fifth-stage base 1.
+  constexpr double b10 = 0.391752226571890;
+  constexpr double a21 = 0.555629506348765, b21 = 0.368410593050371;
+  constexpr double a32 = 0.379898148511597, b32 = 0.251891774271694;
+  constexpr double a43 = 0.821920045606868, b43 = 0.544974750228521;
+  constexpr double a52 = 0.517231671970585, b53 = 0.063692468666290;
+  constexpr double a54 = 0.386708617503269, b54 = 0.226007483236906;
+  constexpr double g4 = a54 + b53 / b43;
+  constexpr double c2 = a52 / (1.0 - g4);
+  JobScalars S = J;
+  S.dt_scale = b10;
+  if ((rc = fill_slot(c, 0)) || (rc = stage_any(c, 0, 0, 1, 1.0, S))) return rc;
+  S.dt_scale = b21 / a21;
+  if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 2, a21, S))) return rc;
+  S.dt_scale = b32 / a32;
+  if ((rc = fill_slot(c, 2)) || (rc = stage_any(c, 2, 0, 1, a32, S))) return rc;
+  S.dt_scale = b43 / a43;
+  if ((rc = fill_slot(c, 1)) || (rc = stage_any(c, 1, 0, 3, a43, S))) return rc;
+  touch_slot(c, 1);
+  HIP_TRY(c, launch_combine(c->stream, c->G, c->tables(), c->slots[0], c->slots[2], c2, c->slots[1]));
+  S.dt_scale = b54 / g4;
+  if ((rc = fill_slot(c, 3)) || (rc = stage_any(c, 3, 1, 0, g4, S, true))) return rc;
   return AMRVAC_OK;
 }
+
+int slots_for_stages(int nstages) { return nstages >= 5 ? 4 : (nstages >= 3 ? 3 : 2); }
 
 int stage_entry(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
                 const double* kappa_dev, bool fold_cfl) {
@@ -826,6 +864,19 @@ int amrvac_stage_cfl(amrvac_ctx* c, int in, int base, int out, double w, const d
   return stage_entry(c, in, base, out, w, dt_dev, ch_dev, kappa_dev, true);
 }
 
+int amrvac_combine(amrvac_ctx* c, int a, int b, double coef, int out) {
+  if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts step with amrvac_batch_step");
+  if (int rc = check_slot(c, a)) return rc;
+  if (int rc = check_slot(c, b)) return rc;
+  if (int rc = check_slot(c, out)) return rc;
+  if (!std::isfinite(coef)) return fail(c, AMRVAC_E_ARG, "non-finite combination coefficient");
+  if (int rc = ensure_tables(c)) return rc;
+  touch_slot(c, out);
+  HIP_TRY(c, launch_combine(c->stream, c->G, c->tables(), c->slots[a], c->slots[b], coef, c->slots[out]));
+  return AMRVAC_OK;
+}
+
 int amrvac_set_path(amrvac_ctx* c, int path) {
   if (!c) return AMRVAC_E_ARG;
   if (path != AMRVAC_PATH_PLAIN && path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_ARG, "unknown path");
@@ -839,8 +890,8 @@ int amrvac_set_path(amrvac_ctx* c, int path) {
 int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph) {
   if (!c) return AMRVAC_E_ARG;
   if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts step with amrvac_batch_step");
-  if (nstages < 2 || nstages > 4) return fail(c, AMRVAC_E_ARG, "amrvac_advance supports 2, 3 or 4 stages");
-  if ((int)c->slots.size() < (nstages >= 3 ? 3 : 2)) return fail(c, AMRVAC_E_ARG, "not enough slots");
+  if (nstages < 2 || nstages > 5) return fail(c, AMRVAC_E_ARG, "amrvac_advance supports 2 .. 5 stages");
+  if ((int)c->slots.size() < slots_for_stages(nstages)) return fail(c, AMRVAC_E_ARG, "not enough slots");
   if (nsteps < 0) return fail(c, AMRVAC_E_ARG, "negative step count");
   if (int rc = ensure_tables(c)) return rc;
   double *dt = c->d_jdt, *ch = c->d_jch, *kap = c->d_jkappa;
@@ -1001,11 +1052,11 @@ int amrvac_batch_create(amrvac_ctx** out, const amrvac_grid_desc* shape, int cap
   std::string why;
   if (check_desc(shape, &why) != AMRVAC_OK) { g_init_err = why; return AMRVAC_E_ARG; }
   if (shape->block_nx != 16) { g_init_err = "batch contexts run the fused path: block_nx must be 16"; return AMRVAC_E_ARG; }
-  if (capacity_blocks < 1 || max_jobs < 1 || nstages < 2 || nstages > 4 || !slots) {
+  if (capacity_blocks < 1 || max_jobs < 1 || nstages < 2 || nstages > 5 || !slots) {
     g_init_err = "bad capacity, job count, stage count or slots";
     return AMRVAC_E_ARG;
   }
-  const int nslots = nstages >= 3 ? 3 : 2;
+  const int nslots = slots_for_stages(nstages);
   for (int s = 0; s < nslots; ++s)
     if (!slots[s]) { g_init_err = "null slot pointer"; return AMRVAC_E_ARG; }
   amrvac_ctx* c = new amrvac_ctx();

@@ -1,0 +1,123 @@
+"""SSPRK(5,4) (the five-step row of the paper's time-integration table;
+Spiteri and Ruuth's coefficients) on the plain and fused paths, in graphs and
+batches, against the FP64 oracle.  The oracle takes the published Shu-Osher
+form literally (it keeps L(u3) for the last row); the library eliminates
+L(u3) through the fourth row and runs the last row as amrvac_combine plus one
+stage, so parity also checks that rewriting."""
+import numpy as np
+import pytest
+
+from paper_2303_03026_amd import inputs
+from test_gpu_parity import assert_parity, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+PATHS = ["plain", "fused"]
+
+
+@pytest.fixture(scope="module")
+def amr():
+    from paper_2303_03026_amd import amrvac
+    return amrvac
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def run_gpu(amr, w, nsteps, path, precision=0, graph=False):
+    print("GPU ssprk54 %s nsteps=%d path=%s graph=%s prec=%d" % (w.name, nsteps, path, graph, precision), flush=True)
+    sim = amr.Simulation(w, nslots=4, path=amr.PATH_FUSED if path == "fused" else amr.PATH_PLAIN,
+                         precision=precision)
+    sim.advance(nsteps, nstages=5, graph=graph)
+    fl = sim.sync_flags()
+    out = sim.cons()
+    sim.close()
+    return out, fl
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_uniform_state_bit_identical(amr, path):
+    w = inputs.uniform_state(3, (2, 2, 2), [1.3, 0.4, -0.25, 0.15, 0.8, 0.6, -0.9, 0.3, 0.0])
+    sim = amr.Simulation(w, nslots=4, path=amr.PATH_FUSED if path == "fused" else amr.PATH_PLAIN)
+    u0 = sim.cons()
+    sim.advance(3, nstages=5)
+    assert np.array_equal(sim.cons(), u0)
+    sim.close()
+
+
+CASES = [("random_modes_3d_48", lambda: inputs.random_modes(48, 3, seed=41, nsteps=10)),
+         ("orszag_tang_2d", lambda: inputs.orszag_tang_2d(nsteps=40)),
+         ("smooth_amr_3d", lambda: inputs.smooth_amr_state(3, nb1=2, seed=42)),
+         ("current_sheet_32", lambda: inputs.current_sheet(32, nsteps=10))]
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_parity_with_oracle(amr, orc, name, make, path):
+    w = make()
+    if name == "smooth_amr_3d":
+        w.nsteps = 4
+    w.nstages = 5
+    ref, _ = orc.run(w)
+    gpu, fl = run_gpu(amr, w, w.nsteps, path)
+    assert fl[0] == 0
+    assert_parity(w, gpu, ref, label="ssprk54 %s %s" % (name, path))
+
+
+def test_graph_equals_eager(amr):
+    w = inputs.smooth_amr_state(3, nb1=2, seed=43)
+    w.nstages = 5
+    a, _ = run_gpu(amr, w, 3, "fused", graph=False)
+    b, _ = run_gpu(amr, w, 3, "fused", graph=True)
+    assert np.array_equal(a, b)
+
+
+def test_batch_job_equals_alone(amr):
+    shape = inputs.random_modes(32, 3, seed=0)
+    ws = [inputs.random_modes(32, 3, seed=44, nsteps=4), inputs.random_modes(48, 3, seed=45, nsteps=2)]
+    for w in ws:
+        w.nstages = 5
+    batch = amr.Batch(shape, capacity_blocks=100, max_jobs=4, nstages=5)
+    ids = [batch.add_job(w) for w in ws]
+    while any(batch.job_info(i)[1] > 0 for i in ids):
+        batch.step()
+    outs = [batch.get_job(i) for i in ids]
+    batch.close()
+    for w, got in zip(ws, outs):
+        ref, _ = run_gpu(amr, w, w.nsteps, "fused")
+        assert np.array_equal(got, ref)
+
+
+def test_mixed_precision_bound(amr, orc):
+    w = inputs.random_modes(48, 3, seed=46, nsteps=10)
+    w.nstages = 5
+    ref, _ = orc.run(w)
+    got, fl = run_gpu(amr, w, w.nsteps, "fused", precision=1)
+    assert fl[0] == 0
+    err = rel_l1(w, got, ref)
+    # rho and e relative; the small components by the field / momentum scale
+    assert err[0] < 1e-6 and err[4] < 1e-6, err
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_combine_matches_its_definition(amr, precision):
+    """out = a + coef (b - a) on interior cells, also in place."""
+    wa = inputs.random_modes(32, 3, seed=47)
+    wb = inputs.random_modes(32, 3, seed=48)
+    sim = amr.Simulation(wa, nslots=3, path=amr.PATH_FUSED, precision=precision)
+    a = sim.cons()
+    sim.set_primitive(wb.prim, slot=1)
+    b = sim.cons(slot=1)
+    coef = 1.0419255043037299
+    sim.combine(0, 1, coef, 2)
+    got = sim.cons(slot=2)
+    want = a + coef * (b - a)
+    tol = 1e-15 if precision == 0 else 2e-7
+    np.testing.assert_allclose(got, want, rtol=tol, atol=tol * np.abs(want).max())
+    sim.combine(0, 1, coef, 0)  # in place over a
+    assert np.array_equal(sim.cons(), got)
+    sim.close()

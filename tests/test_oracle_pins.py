@@ -238,7 +238,7 @@ def _uniform_w():
     return [1.3, 0.4, -0.25, 0.15, 0.8, 0.6, -0.9, 0.3, 0.0]
 
 
-@pytest.mark.parametrize("ndim,nstages", [(2, 1), (2, 2), (2, 3), (3, 3), (2, 4), (3, 4)])
+@pytest.mark.parametrize("ndim,nstages", [(2, 1), (2, 2), (2, 3), (3, 3), (2, 4), (3, 4), (2, 5), (3, 5)])
 def test_uniform_state_bit_identical(orc, ndim, nstages):
     w = inputs.uniform_state(ndim, (3, 2, 2), _uniform_w())
     w.nstages = nstages
@@ -317,7 +317,7 @@ def _scale(w, u):
     return np.array([math.fsum(np.abs(u[:, q]).ravel()) for q in range(NV)]) / u[:, 0].size
 
 
-@pytest.mark.parametrize("nstages", [2, 3, 4])
+@pytest.mark.parametrize("nstages", [2, 3, 4, 5])
 def test_conservation_periodic(orc, nstages):
     w = inputs.orszag_tang_2d(n=64)
     w.nstages = nstages
@@ -352,8 +352,10 @@ def test_conservation_periodic_amr_needs_reflux(orc):
     assert np.max(res[0][cons_vars]) > 1e-9, res[0]
 
 
-def test_conservation_periodic_amr_3d(orc):
+@pytest.mark.parametrize("nstages", [3, 5])
+def test_conservation_periodic_amr_3d(orc, nstages):
     w = inputs.smooth_amr_state(3, nb1=2, seed=7)
+    w.nstages = nstages
     assert w.max_level == 3
     sim = orc.OracleSim(w)
     u0 = sim.cons()
@@ -388,6 +390,34 @@ def test_glm_damping_stability_polynomial(orc, nstages, poly):
     assert np.array_equal(u1[:, :PSI], u0[:, :PSI])
     assert np.allclose(u1[:, PSI], poly(-kappa * dt) * 0.37, rtol=1e-14, atol=0)
     assert kappa * dt > 0.05  # the damping is actually exercised
+
+
+def test_ssprk54_damping_is_fourth_order(orc):
+    """SSPRK(5,4) on the damping ODE of a uniform state: one step multiplies
+    psi by the scheme's stability polynomial R(-kappa dt), which must agree
+    with exp(-kappa dt) through z^4 (fourth order).  kappa dt = alpha C / d, so
+    halving the Courant number C must shrink |R - exp| by 2^5 (the local
+    error of a fourth-order step); a third-order scheme gives 2^4."""
+    def one_step_error(nstages, C):
+        wv = _uniform_w()
+        wv[PSI] = 0.37
+        w = inputs.uniform_state(2, (2, 2), wv)
+        w.nstages = nstages
+        w.cfl = C
+        sim = orc.OracleSim(w)
+        u0 = sim.cons()
+        dt, ch, kappa = sim.steps(1)[0, :3]
+        u1 = sim.cons()
+        assert np.array_equal(u1[:, :PSI], u0[:, :PSI])
+        assert kappa * dt == pytest.approx(w.glm_alpha * C / 2, rel=1e-14)
+        ratio = u1[:, PSI] / 0.37
+        assert np.all(ratio == ratio.flat[0])
+        return abs(ratio.flat[0] - math.exp(-kappa * dt))
+    e = [one_step_error(5, C) for C in (0.8, 0.4, 0.2)]
+    assert e[2] > 1e-12  # well above rounding
+    assert 28 < e[0] / e[1] < 36 and 28 < e[1] / e[2] < 36, e
+    e3 = [one_step_error(3, C) for C in (0.8, 0.4)]
+    assert 14 < e3[0] / e3[1] < 18, e3
 
 
 def test_cfl_closed_form(orc):
