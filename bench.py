@@ -87,6 +87,9 @@ def measured_traffic(precision, tune, workload, n):
 # not 1; one state is 72 B per cell in FP64 and 40 B in FP32-mixed.
 
 
+LIMITERS = ("vanleer", "koren", "cada3")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +100,7 @@ def parse():
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64",
                     help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
     ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud"], default="random_modes")
+    ap.add_argument("--limiter", choices=["vanleer", "koren", "cada3"], default="vanleer")
     ap.add_argument("--tune", default="auto",
                     help="fused-stage launch shape: 'auto' (autotuner, before the warmup), 'default', or z,r,x")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -172,6 +176,7 @@ def main():
         w = inputs.current_sheet(n=args.n)
     else:
         w = inputs.shock_cloud_amr()
+    w.limiter = LIMITERS.index(args.limiter)
     mixed = args.precision == "mixed"
     if mixed:
         args.path = "fused"
@@ -244,7 +249,8 @@ def main():
     bytes_per_launch = cells * state_bytes * (2 + 3 + 3) / 3.0
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 
-    traffic = measured_traffic(args.precision, tune, args.workload, args.n) if args.path == "fused" else None
+    traffic = (measured_traffic(args.precision, tune, args.workload, args.n)
+               if args.path == "fused" and args.limiter == "vanleer" else None)
 
     graph_ms = None
     if not args.no_graph_pass:
@@ -271,8 +277,9 @@ def main():
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": "%s: 3D, %d leaf blocks of 16^3 + 2 ghost layers on %d level(s), %s GLM-MHD "
-                               "state, SSPRK(3,3), CFL 0.8, %s" % (w.name, w.nblocks, w.max_level, args.workload,
-                                                                  "FP32-mixed" if mixed else "FP64"),
+                               "state, SSPRK(3,3), CFL 0.8, %s, %s limiter"
+                               % (w.name, w.nblocks, w.max_level, args.workload, "FP32-mixed" if mixed else "FP64",
+                                  args.limiter),
                    "path": args.path, "cells": cells, "stage_weights": [1.0, 0.25, 2.0 / 3.0],
                    "tune": None if tune is None else {"zseg": tune[0], "rotate": tune[1], "xcd": tune[2]}},
         "autotune_ms_per_launch": {"%d,%d,%d" % k: round(v, 4) for k, v in tune_times.items()},
@@ -294,6 +301,7 @@ def main():
             small = inputs.current_sheet(n=48)
         else:
             small = inputs.shock_cloud_amr(base_n=32)
+        small.limiter = w.limiter
         out["cpu_baseline"] = cpu_baseline(w, small)
     print(json.dumps(out), flush=True)
 

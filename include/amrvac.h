@@ -60,6 +60,15 @@ enum { AMRVAC_FP64 = 0, AMRVAC_FP32_MIXED = 1 };
 enum { AMRVAC_BC_PERIODIC = 0, AMRVAC_BC_ZEROGRAD = 1, AMRVAC_BC_REFLECT = 2, AMRVAC_BC_FIXED = 3 };
 enum { AMRVAC_FLAG_SMALL_RHO = 1, AMRVAC_FLAG_SMALL_P = 2, AMRVAC_FLAG_BAD_DT = 4 };
 enum { AMRVAC_PATH_PLAIN = 0, AMRVAC_PATH_FUSED = 1 };
+/* Reconstruction limiters (Table t:limiters; all on the 2-ghost-cell
+ * stencil): 'vanleer' (van Leer 1974, the harmonic slope), 'koren' (Koren
+ * 1993) and 'cada3' (Cada and Torrilhon 2009, their third-order limiter
+ * function without the smooth-extremum switch).  With d- and d+ the backward
+ * and forward differences of a primitive variable, a cell's right and left
+ * face values are w + phi d+ / 2 and w - phi' d- / 2; koren and cada3 give
+ * the unlimited third-order values (2 d+ + d-)/6 and (2 d- + d+)/6 in smooth
+ * monotone regions. */
+enum { AMRVAC_LIM_VANLEER = 0, AMRVAC_LIM_KOREN = 1, AMRVAC_LIM_CADA3 = 2 };
 
 /* Grid and scheme description.  Physical boundary kinds per face follow the
  * paper's examples: periodic, zero-gradient ("continuous"), reflective
@@ -84,6 +93,7 @@ typedef struct {
   double small_density;   /* thresholds of the small-value check               */
   double small_pressure;
   double bc_fixed_prim[3][2][9]; /* primitive state of AMRVAC_BC_FIXED faces   */
+  int limiter;            /* AMRVAC_LIM_*                                      */
 } amrvac_grid_desc;
 
 /* Device bytes of one state slot for nblocks blocks of this description.

@@ -11,8 +11,8 @@
 //     Runge-Kutta step ("Schemes and limiters for HD and MHD", Table
 //     tab:schemes_time: SSPRK(2,2), SSPRK(3,3), SSPRK(4,3) and SSPRK(5,4));
 //   * limited linear reconstruction of primitive variables giving a left and
-//     a right state per face, with the 'vanleer' limiter and 2 ghost cells
-//     (Table t:limiters);
+//     a right state per face, with the 'vanleer', 'koren' or 'cada3'
+//     limiter and 2 ghost cells (Table t:limiters);
 //   * the HLL flux (Table tab:schemes_space; Harten et al. 1983);
 //   * the 'glm' divergence control of Dedner et al. 2002 (Table t:divb);
 //   * the CFL coupling of the time step to the grid spacing ("Schemes and
@@ -31,7 +31,9 @@
 //   magnetic units with p_mag = |B|^2/2 (plasma beta 2p/B^2, Alfven shock
 //   section); GLM without the extended source terms, with psi damping as the
 //   explicit source -kappa*psi; c_h and kappa fixed per step from dt;
-//   "max of sum" CFL; Davis wave-speed bounds; van Leer's harmonic slope;
+//   "max of sum" CFL; Davis wave-speed bounds; van Leer's harmonic slope,
+//   Koren's limiter function, Cada and Torrilhon's third-order limiter
+//   function without its smooth-extremum switch;
 //   first-order fallback per face on non-positive reconstructed rho or p;
 //   delta-form SSPRK; pairwise restriction sums; minmod-limited conservative
 //   linear prolongation of conserved variables; flux correction (reflux) at
@@ -157,6 +159,41 @@ double minmod(double a, double b) {
   return 0.0;
 }
 
+// Koren (1993) limiter function (the 'koren' row of Table t:limiters) of
+// r = d+/d-, the ratio of the forward to the backward difference; the face
+// value on the forward side is w + phi(r) d- / 2, which is the kappa = 1/3
+// third-order value w + d-/6 + d+/3 for 0.4 <= r <= 4.
+double koren_phi(double r) { return std::max(0.0, std::min(std::min(2.0 * r, (1.0 + 2.0 * r) / 3.0), 2.0)); }
+
+// Cada and Torrilhon (2009) third-order limiter function (the 'cada3' row of
+// Table t:limiters) of theta = d-/d+; the face value on the forward side is
+// w + phi(theta) d+ / 2.  It follows the unlimited third-order polynomial
+// (2 + theta)/3 where that lies between the lower bounds -theta/2 (which lets
+// extrema keep a slope) and the upper bounds 2 theta and 1.6.
+double cada3_phi(double th) {
+  const double p3 = (2.0 + th) / 3.0;
+  return std::max(0.0, std::min(p3, std::max(-0.5 * th, std::min(std::min(2.0 * th, p3), 1.6))));
+}
+
+enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2 };
+
+// The two face values of a cell with backward and forward differences dm, dp:
+// right face w + inc_right/2, left face w - inc_left/2.  The left face is the
+// right face of the mirrored stencil (dm, dp -> -dp, -dm).  A zero difference
+// in a ratio's denominator gives a zero increment (its limit).
+void face_increments(int lim, double dm, double dp, double* inc_right, double* inc_left) {
+  if (lim == LIM_KOREN) {
+    *inc_right = dm != 0.0 ? koren_phi(dp / dm) * dm : 0.0;
+    *inc_left = dp != 0.0 ? koren_phi(dm / dp) * dp : 0.0;
+  } else if (lim == LIM_CADA3) {
+    *inc_right = dp != 0.0 ? cada3_phi(dm / dp) * dp : 0.0;
+    *inc_left = dm != 0.0 ? cada3_phi(dp / dm) * dm : 0.0;
+  } else {
+    *inc_right = vanleer(dm, dp);
+    *inc_left = *inc_right;
+  }
+}
+
 // Physical ideal-MHD flux along d for every component except B_d and psi,
 // which the GLM interface solve supplies.
 void phys_flux(const Cell& w, const Cell& u, int d, double f[NV]) {
@@ -259,6 +296,7 @@ typedef struct {
   double glm_alpha;
   double small_density;
   double small_pressure;
+  int limiter;  // 0 = 'vanleer', 1 = 'koren', 2 = 'cada3'
 } oracle_params;
 
 }  // extern "C"
@@ -499,10 +537,11 @@ struct Sim {
               const Cell& wpp = at(f + 1);
               Cell wl, wr;
               for (int q = 0; q < NV; ++q) {
-                const double sm = vanleer(wm.v[q] - wmm.v[q], wp.v[q] - wm.v[q]);
-                const double sp = vanleer(wp.v[q] - wm.v[q], wpp.v[q] - wp.v[q]);
-                wl.v[q] = wm.v[q] + 0.5 * sm;
-                wr.v[q] = wp.v[q] - 0.5 * sp;
+                double rm, lm, rp, lp;
+                face_increments(P.limiter, wm.v[q] - wmm.v[q], wp.v[q] - wm.v[q], &rm, &lm);
+                face_increments(P.limiter, wp.v[q] - wm.v[q], wpp.v[q] - wp.v[q], &rp, &lp);
+                wl.v[q] = wm.v[q] + 0.5 * rm;
+                wr.v[q] = wp.v[q] - 0.5 * lp;
               }
               if (!(wl.v[RHO] > 0.0) || !(wl.v[PR] > 0.0) || !(wr.v[RHO] > 0.0) || !(wr.v[PR] > 0.0)) {
                 wl = wm;
@@ -723,6 +762,7 @@ Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int*
   if (s->ng != 2) throw std::invalid_argument("the van Leer stencil needs exactly 2 ghost layers");
   if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
   if (p->nstages < 1 || p->nstages > 5) throw std::invalid_argument("nstages must be 1 .. 5");
+  if (p->limiter < LIM_VANLEER || p->limiter > LIM_CADA3) throw std::invalid_argument("unknown limiter");
   if (s->P.nthreads < 1) s->P.nthreads = 1;
   for (int d = 0; d < s->ndim; ++d)
     if ((p->bc_lo[d] == BC_PERIODIC) != (p->bc_hi[d] == BC_PERIODIC))
@@ -930,6 +970,11 @@ double oracle_fast_speed(const double* w, int d, double gamma) {
 }
 double oracle_vanleer(double dm, double dp) { return vanleer(dm, dp); }
 double oracle_minmod(double a, double b) { return minmod(a, b); }
+int oracle_face_increments(int lim, double dm, double dp, double* inc_right, double* inc_left) {
+  if (lim < LIM_VANLEER || lim > LIM_CADA3) return -1;
+  face_increments(lim, dm, dp, inc_right, inc_left);
+  return 0;
+}
 void oracle_glm_interface(double bnl, double bnr, double psl, double psr, double ch, double* out) {
   glm_interface(bnl, bnr, psl, psr, ch, &out[0], &out[1]);
 }

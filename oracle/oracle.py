@@ -28,6 +28,7 @@ class Params(ctypes.Structure):
         ("xmax", ctypes.c_double * 3), ("bc_fixed_prim", ctypes.c_double * (3 * 2 * NV)),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("glm_alpha", ctypes.c_double),
         ("small_density", ctypes.c_double), ("small_pressure", ctypes.c_double),
+        ("limiter", ctypes.c_int),
     ]
 
 
@@ -61,6 +62,7 @@ def lib():
         _lib.oracle_cons_to_prim.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
         _lib.oracle_fast_speed.restype = ctypes.c_double
         _lib.oracle_fast_speed.argtypes = [dp, ctypes.c_int, ctypes.c_double]
+        _lib.oracle_face_increments.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
         _lib.oracle_vanleer.restype = ctypes.c_double
         _lib.oracle_vanleer.argtypes = [ctypes.c_double, ctypes.c_double]
         _lib.oracle_minmod.restype = ctypes.c_double
@@ -109,6 +111,7 @@ def make_params(w, nthreads: Optional[int] = None, nstages: Optional[int] = None
     p.glm_alpha = w.glm_alpha
     p.small_density = w.small_density
     p.small_pressure = w.small_pressure
+    p.limiter = int(getattr(w, "limiter", 0))
     return p
 
 
@@ -215,6 +218,15 @@ def cons_to_prim(u, gamma: float, small_rho: float = 0.0, small_p: float = 0.0, 
 def fast_speed(w, d: int, gamma: float) -> float:
     w = np.ascontiguousarray(w, dtype=np.float64)
     return lib().oracle_fast_speed(_dp(w), d, gamma)
+
+
+def face_increments(lim: int, dm: float, dp: float):
+    """(inc_right, inc_left): a cell's face values are w + inc_right/2 and
+    w - inc_left/2 for backward / forward differences dm, dp."""
+    r, l = ctypes.c_double(), ctypes.c_double()
+    if lib().oracle_face_increments(lim, dm, dp, ctypes.byref(r), ctypes.byref(l)) != 0:
+        raise ValueError("unknown limiter %d" % lim)
+    return r.value, l.value
 
 
 def vanleer(dm: float, dp: float) -> float:

@@ -28,6 +28,7 @@ struct PhysConst {
   double small_rho;
   double small_p;
   int fix;
+  int limiter;  // LIM_* (the fused stage takes it as a template argument)
 };
 
 // Library-owned device status record.
@@ -133,6 +134,40 @@ __device__ __forceinline__ R vl_slope(R dm, R dp) {
   const R q = dm * dp;
   const R v = div_(R(2) * q, dm + dp);
   return q > R(0) ? v : R(0);
+}
+
+// Limiters of Table t:limiters that work on the 2-ghost-cell stencil.  With
+// d- = w_i - w_(i-1) and d+ = w_(i+1) - w_i, cell i's face values are
+//   right face:  w_i + lim(d+, d-) / 2,    left face:  w_i - lim(d-, d+) / 2,
+// lim(near, far) being the limited difference across the face (odd in its
+// arguments).  van Leer's is symmetric: lim(d+, d-) = lim(d-, d+) = the
+// harmonic slope.  Koren's and Cada-Torrilhon's third-order ones are not;
+// written division-free with s = sign(near), b = |near|, a = s far, they are
+//   koren:  s max(0, min(2a, (2b + a)/3, 2b))
+//   cada3:  s max(0, min((2b + a)/3, max(-a/2, min(2a, (2b + a)/3, 1.6 b))))
+// (the unlimited third-order value (2b + a)/3 in smooth monotone regions).
+enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2 };
+
+template <int LIM, class R>
+__device__ __forceinline__ R lim_diff(R near, R far) {
+  const R s = near < R(0) ? R(-1) : R(1);
+  const R b = s * near, a = s * far;
+  const R p3 = (R(2) * b + a) * R(1.0 / 3.0);
+  if (LIM == LIM_KOREN) return s * fmax(R(0), fmin(fmin(R(2) * a, p3), R(2) * b));
+  return s * fmax(R(0), fmin(p3, fmax(R(-0.5) * a, fmin(fmin(R(2) * a, p3), R(1.6) * b))));
+}
+
+// Limited differences of a cell for its right (inc_r) and left (inc_l)
+// face values: w + inc_r / 2 and w - inc_l / 2.
+template <int LIM, class R>
+__device__ __forceinline__ void cell_increments(R dm, R dp, R& inc_r, R& inc_l) {
+  if (LIM == LIM_VANLEER) {
+    inc_r = vl_slope(dm, dp);
+    inc_l = inc_r;
+  } else {
+    inc_r = lim_diff<LIM>(dp, dm);
+    inc_l = lim_diff<LIM>(dm, dp);
+  }
 }
 
 __device__ __forceinline__ double minmod2(double a, double b) {
@@ -258,17 +293,31 @@ __device__ __forceinline__ void positivity_fallback(R wl[NV], R wr[NV], const R 
 // Reconstructed left/right states at the face between cells a (=i) and
 // b (=i+1) from four primitive cells m (=i-1), a, b, p (=i+2), with the
 // first-order fallback when rho or p is not positive on either side.
-template <class R>
-__device__ __forceinline__ void reconstruct_face(const R wm[NV], const R wa[NV], const R wb[NV], const R wp[NV],
-                                                 R wl[NV], R wr[NV]) {
+template <int LIM, class R>
+__device__ __forceinline__ void reconstruct_face_lim(const R wm[NV], const R wa[NV], const R wb[NV], const R wp[NV],
+                                                     R wl[NV], R wr[NV]) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    const R sa = vl_slope(wa[q] - wm[q], wb[q] - wa[q]);
-    const R sb = vl_slope(wb[q] - wa[q], wp[q] - wb[q]);
-    wl[q] = wa[q] + R(0.5) * sa;
-    wr[q] = wb[q] - R(0.5) * sb;
+    R ra, la, rb, lb;
+    cell_increments<LIM>(wa[q] - wm[q], wb[q] - wa[q], ra, la);
+    cell_increments<LIM>(wb[q] - wa[q], wp[q] - wb[q], rb, lb);
+    wl[q] = wa[q] + R(0.5) * ra;
+    wr[q] = wb[q] - R(0.5) * lb;
   }
   positivity_fallback(wl, wr, wa, wb);
+}
+
+// the same with the limiter chosen at run time (the per-kernel path and the
+// coarse/fine flux correction)
+template <class R>
+__device__ __forceinline__ void reconstruct_face(int lim, const R wm[NV], const R wa[NV], const R wb[NV],
+                                                 const R wp[NV], R wl[NV], R wr[NV]) {
+  if (lim == LIM_KOREN)
+    reconstruct_face_lim<LIM_KOREN>(wm, wa, wb, wp, wl, wr);
+  else if (lim == LIM_CADA3)
+    reconstruct_face_lim<LIM_CADA3>(wm, wa, wb, wp, wl, wr);
+  else
+    reconstruct_face_lim<LIM_VANLEER>(wm, wa, wb, wp, wl, wr);
 }
 
 // ---------------------------------------------------------------------------

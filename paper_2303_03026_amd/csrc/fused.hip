@@ -1,6 +1,7 @@
-// Fused FP64 stage kernel for 16^ndim blocks: conserved -> primitive, van Leer
-// reconstruction, GLM interface + HLL fluxes in every direction, flux
-// difference, psi damping and the SSPRK combination, in one launch.
+// Fused stage kernel for 16^ndim blocks: conserved -> primitive, limited
+// linear reconstruction (van Leer, Koren or Cada-Torrilhon), GLM interface +
+// HLL fluxes in every direction, flux difference, psi damping and the SSPRK
+// combination, in one launch.
 //
 // One 256-thread workgroup per block; thread t owns the (x, y) column
 // i = t % 16, j = t / 16.  In 3D the workgroup marches through the z planes:
@@ -53,9 +54,12 @@ __device__ __forceinline__ void load_cons(const void* __restrict__ U, long pc, l
 }
 
 // Reconstruct the face between LDS cells (line, f-1) and (line, f) along DIR
-// from the plane primitives and the slopes of the two cells; first-order
-// fallback when rho or p is not positive on either side.
-template <int DIR, class R>
+// from the plane primitives and the slope buffer, which holds each cell's
+// right-face difference (van Leer: the slope, the same for both faces; the
+// asymmetric limiters form cell f's left-face difference here, from the
+// cell after it); first-order fallback when rho or p is not positive on
+// either side.
+template <int DIR, int LIM, class R>
 __device__ __forceinline__ void face_states(const R (*__restrict__ Wp)[BP * WROW], const R (*__restrict__ Sl)[SLOPE_ROW * BN], int line, int f,
                                             R wl[NV], R wr[NV]) {
   R wm[NV], wp[NV];
@@ -69,13 +73,19 @@ __device__ __forceinline__ void face_states(const R (*__restrict__ Wp)[BP * WROW
       wp[q] = Wp[q][(f + 2) * WROW + line + 2];
     }
     wl[q] = wm[q] + R(0.5) * Sl[q][line * SLOPE_ROW + f];
-    wr[q] = wp[q] - R(0.5) * Sl[q][line * SLOPE_ROW + f + 1];
+    if (LIM == LIM_VANLEER) {
+      wr[q] = wp[q] - R(0.5) * Sl[q][line * SLOPE_ROW + f + 1];
+    } else {
+      const R wpp = DIR == 0 ? Wp[q][(line + 2) * WROW + f + 3] : Wp[q][(f + 3) * WROW + line + 2];
+      wr[q] = wp[q] - R(0.5) * lim_diff<LIM>(wp[q] - wm[q], wpp - wp[q]);
+    }
   }
   positivity_fallback(wl, wr, wm, wp);
 }
 
-// van Leer slope along DIR of LDS cell (line, a), a in -1..16
-template <int DIR, class R>
+// Right-face limited difference along DIR of LDS cell (line, a), a in -1..16
+// (van Leer: the slope)
+template <int DIR, int LIM, class R>
 __device__ __forceinline__ void cell_slope(const R (*__restrict__ Wp)[BP * WROW], R (*__restrict__ Sl)[SLOPE_ROW * BN], int line, int a) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -89,7 +99,7 @@ __device__ __forceinline__ void cell_slope(const R (*__restrict__ Wp)[BP * WROW]
       c = Wp[q][(a + 2) * WROW + line + 2];
       p = Wp[q][(a + 3) * WROW + line + 2];
     }
-    Sl[q][line * SLOPE_ROW + a + 1] = vl_slope(c - m, p - c);
+    Sl[q][line * SLOPE_ROW + a + 1] = LIM == LIM_VANLEER ? vl_slope(c - m, p - c) : lim_diff<LIM>(p - c, c - m);
   }
 }
 
@@ -123,7 +133,7 @@ struct FaceConst {
 // energy difference is accumulated in double (acc_e).
 // The halo slopes (cells -1 and 16 of every line) and the 17th face of every
 // line are done by the lanes of wave xw (extra lane e = t - 64 xw).
-template <int DIR, class R>
+template <int DIR, int LIM, class R>
 __device__ __forceinline__ void plane_direction(const R (*__restrict__ Wp)[BP * WROW], R (*__restrict__ Sl)[SLOPE_ROW * BN],
                                                 R (*__restrict__ Fl)[(BN + 1) * BN], int t, int i, int j, int xw,
                                                 const FaceConst<R>& K, double inv_dx, R acc[NV], double& acc_e,
@@ -131,19 +141,19 @@ __device__ __forceinline__ void plane_direction(const R (*__restrict__ Wp)[BP * 
   const int line = DIR == 0 ? j : i;
   const int f = DIR == 0 ? i : j;
   const int e = t - 64 * xw;
-  cell_slope<DIR>(Wp, Sl, line, f);
-  if ((unsigned)e < 32u) cell_slope<DIR>(Wp, Sl, e & 15, e < 16 ? -1 : BN);
+  cell_slope<DIR, LIM>(Wp, Sl, line, f);
+  if ((unsigned)e < 32u) cell_slope<DIR, LIM>(Wp, Sl, e & 15, e < 16 ? -1 : BN);
   lds_barrier();
   {
     R wl[NV], wr[NV], F[NV];
-    face_states<DIR>(Wp, Sl, line, f, wl, wr);
+    face_states<DIR, LIM>(Wp, Sl, line, f, wl, wr);
     hll_glm_flux<DIR, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, F);
 #pragma unroll
     for (int q = 0; q < NV; ++q) Fl[q][line * (BN + 1) + f] = F[q];
   }
   if ((unsigned)e < 16u) {  // the 17th face of line e
     R wl[NV], wr[NV], F[NV];
-    face_states<DIR>(Wp, Sl, e, BN, wl, wr);
+    face_states<DIR, LIM>(Wp, Sl, e, BN, wl, wr);
     hll_glm_flux<DIR, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, F);
 #pragma unroll
     for (int q = 0; q < NV; ++q) Fl[q][e * (BN + 1) + BN] = F[q];
@@ -169,7 +179,7 @@ __device__ __forceinline__ void plane_direction(const R (*__restrict__ Wp)[BP * 
 // Work item w (one z segment of one block) is run by workgroup g with
 // w = (g % 8) * per_xcd + g / 8 when tune.xcd is set (each XCD gets a
 // contiguous run of the Morton-ordered list), else w = g.
-template <int NDIM, class SP, bool W1, bool CFL>
+template <int NDIM, class SP, bool W1, bool CFL, int LIM>
 __global__ void __launch_bounds__(256, SP::kWavesPerEU)
 k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, const void* __restrict__ in,
               const void* base, void* out, double wgt, PhysConst P, DevStatus* st, JobCfl C) {
@@ -347,11 +357,12 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
       R wl[NV], wr[NV], fz[NV];
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        const R sm = vl_slope(wm1[q] - wm2[q], wa[q] - wm1[q]);
-        const R s0 = vl_slope(wa[q] - wm1[q], wb[q] - wa[q]);
-        wl[q] = wm1[q] + R(0.5) * sm;
-        wr[q] = wa[q] - R(0.5) * s0;
-        wla[q] = wa[q] + R(0.5) * s0;
+        R rm, lm, r0, l0;
+        cell_increments<LIM>(wm1[q] - wm2[q], wa[q] - wm1[q], rm, lm);
+        cell_increments<LIM>(wa[q] - wm1[q], wb[q] - wa[q], r0, l0);
+        wl[q] = wm1[q] + R(0.5) * rm;
+        wr[q] = wa[q] - R(0.5) * l0;
+        wla[q] = wa[q] + R(0.5) * r0;
       }
       positivity_fallback(wl, wr, wm1, wa);
       hll_glm_flux<2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
@@ -401,8 +412,8 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
     const bool staging = stager && k + 1 < k1;
     if (staging) stage_halo(k + 1);
 
-    plane_direction<0, R>(Wp, Sl, Fl, t, i, j, xw, K, idx, acc, acc_e, false);
-    plane_direction<1, R>(Wp, Sl, Fl, t, i, j, yw, K, idy, acc, acc_e, staging);
+    plane_direction<0, LIM, R>(Wp, Sl, Fl, t, i, j, xw, K, idx, acc, acc_e, false);
+    plane_direction<1, LIM, R>(Wp, Sl, Fl, t, i, j, yw, K, idy, acc, acc_e, staging);
 
     // this plane's conserved state and the stage base, issued as one group
     const long c = PD::at(i, j, k);
@@ -420,10 +431,11 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
       R wl[NV], wr[NV];
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        const R s1 = vl_slope(wb[q] - wa[q], wc[q] - wb[q]);
+        R r1, l1;
+        cell_increments<LIM>(wb[q] - wa[q], wc[q] - wb[q], r1, l1);
         wl[q] = wla[q];
-        wr[q] = wb[q] - R(0.5) * s1;
-        wla[q] = wb[q] + R(0.5) * s1;
+        wr[q] = wb[q] - R(0.5) * l1;
+        wla[q] = wb[q] + R(0.5) * r1;
       }
       positivity_fallback(wl, wr, wa, wb);
       hll_glm_flux<2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
@@ -536,33 +548,43 @@ hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T
   const int per_xcd = (int)((items + 7) / 8);
   const unsigned grid = tune.xcd ? 8u * (unsigned)per_xcd : (unsigned)items;
   const JobCfl C = cfl ? *cfl : JobCfl{};
-#define AMRVAC_FUSED_KERNEL(ND, SPT, W1, CF) \
-  k_stage_fused<ND, SPT, W1, CF><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st, C)
-#define AMRVAC_FUSED_LAUNCH(ND, SPT)               \
-  do {                                             \
-    if (cfl) {                                     \
-      if (w == 1.0)                                \
-        AMRVAC_FUSED_KERNEL(ND, SPT, true, true);  \
-      else                                         \
-        AMRVAC_FUSED_KERNEL(ND, SPT, false, true); \
-    } else {                                       \
-      if (w == 1.0)                                \
-        AMRVAC_FUSED_KERNEL(ND, SPT, true, false); \
-      else                                         \
-        AMRVAC_FUSED_KERNEL(ND, SPT, false, false); \
-    }                                              \
+#define AMRVAC_FUSED_KERNEL(ND, SPT, W1, CF, LM) \
+  k_stage_fused<ND, SPT, W1, CF, LM><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st, C)
+#define AMRVAC_FUSED_LAUNCH(ND, SPT, LM)               \
+  do {                                                 \
+    if (cfl) {                                         \
+      if (w == 1.0)                                    \
+        AMRVAC_FUSED_KERNEL(ND, SPT, true, true, LM);  \
+      else                                             \
+        AMRVAC_FUSED_KERNEL(ND, SPT, false, true, LM); \
+    } else {                                           \
+      if (w == 1.0)                                    \
+        AMRVAC_FUSED_KERNEL(ND, SPT, true, false, LM); \
+      else                                             \
+        AMRVAC_FUSED_KERNEL(ND, SPT, false, false, LM); \
+    }                                                  \
+  } while (0)
+#define AMRVAC_FUSED_LIMITER(ND, SPT)                 \
+  do {                                                \
+    if (P.limiter == LIM_KOREN)                       \
+      AMRVAC_FUSED_LAUNCH(ND, SPT, LIM_KOREN);        \
+    else if (P.limiter == LIM_CADA3)                  \
+      AMRVAC_FUSED_LAUNCH(ND, SPT, LIM_CADA3);        \
+    else                                              \
+      AMRVAC_FUSED_LAUNCH(ND, SPT, LIM_VANLEER);      \
   } while (0)
   if (G.precision == 0) {
     if (G.ndim == 3)
-      AMRVAC_FUSED_LAUNCH(3, StoreF64);
+      AMRVAC_FUSED_LIMITER(3, StoreF64);
     else
-      AMRVAC_FUSED_LAUNCH(2, StoreF64);
+      AMRVAC_FUSED_LIMITER(2, StoreF64);
   } else {
     if (G.ndim == 3)
-      AMRVAC_FUSED_LAUNCH(3, StoreMixed);
+      AMRVAC_FUSED_LIMITER(3, StoreMixed);
     else
-      AMRVAC_FUSED_LAUNCH(2, StoreMixed);
+      AMRVAC_FUSED_LIMITER(2, StoreMixed);
   }
+#undef AMRVAC_FUSED_LIMITER
 #undef AMRVAC_FUSED_LAUNCH
 #undef AMRVAC_FUSED_KERNEL
   return hipGetLastError();

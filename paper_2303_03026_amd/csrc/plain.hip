@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(256) k_flux(GridConst G, const double* __restr
     wp[q] = p[idx[3]];
   }
   double wl[NV], wr[NV], F[NV];
-  reconstruct_face(wm, wa, wb, wp, wl, wr);
+  reconstruct_face(P.limiter, wm, wa, wb, wp, wl, wr);
   const double ch = *ch_dev;
   hll_glm_flux<D, double>(wl, wr, ch, 0.5 / ch, P.gamma, P.inv_gm1, F);
   double* out = flux + (long)b * NV * G.nfaces + fi;
@@ -403,7 +403,7 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
     (void)cons_to_prim(u, w4[s], P);
   }
   R wl[NV], wr[NV];
-  reconstruct_face(w4[0], w4[1], w4[2], w4[3], wl, wr);
+  reconstruct_face(P.limiter, w4[0], w4[1], w4[2], w4[3], wl, wr);
   hll_glm_flux<D, R>(wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
 }
 

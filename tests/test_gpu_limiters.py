@@ -1,0 +1,129 @@
+"""The third-order limiters of the paper's limiter table that use the same
+2-ghost-cell stencil as van Leer ('koren', 'cada3') on the plain and fused
+paths, in graphs, batches and every launch shape, against the FP64 oracle.
+The oracle writes them in their published ratio forms (phi(r) d-, phi(theta)
+d+); the kernels use a division-free product form, so parity also checks
+that rewriting."""
+import numpy as np
+import pytest
+
+from paper_2303_03026_amd import inputs
+from test_gpu_parity import assert_parity, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+PATHS = ["plain", "fused"]
+LIMS = [(1, "koren"), (2, "cada3")]
+
+
+@pytest.fixture(scope="module")
+def amr():
+    from paper_2303_03026_amd import amrvac
+    return amrvac
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def run_gpu(amr, w, nsteps, path, precision=0, graph=False, tune=None):
+    print("GPU limiter %d %s nsteps=%d path=%s graph=%s prec=%d tune=%s"
+          % (w.limiter, w.name, nsteps, path, graph, precision, tune), flush=True)
+    sim = amr.Simulation(w, path=amr.PATH_FUSED if path == "fused" else amr.PATH_PLAIN, precision=precision)
+    if tune is not None:
+        sim.set_tune(*tune)
+    sim.advance(nsteps, graph=graph)
+    fl = sim.sync_flags()
+    out = sim.cons()
+    sim.close()
+    return out, fl
+
+
+CASES = [("random_modes_3d_48", lambda: inputs.random_modes(48, 3, seed=51, nsteps=10)),
+         ("orszag_tang_2d", lambda: inputs.orszag_tang_2d(nsteps=40)),
+         ("smooth_amr_3d", lambda: inputs.smooth_amr_state(3, nb1=2, seed=52)),
+         ("current_sheet_32", lambda: inputs.current_sheet(32, nsteps=10)),
+         ("shock_cloud_32", lambda: inputs.shock_cloud_amr(base_n=32, nsteps=6))]
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("lim,lname", LIMS, ids=[n for _, n in LIMS])
+def test_parity_with_oracle(amr, orc, lim, lname, name, make, path):
+    w = make()
+    if name == "smooth_amr_3d":
+        w.nsteps = 4
+    w.limiter = lim
+    ref, _ = orc.run(w)
+    gpu, fl = run_gpu(amr, w, w.nsteps, path)
+    assert fl[0] == 0
+    assert_parity(w, gpu, ref, label="%s %s %s" % (lname, name, path))
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("lim,lname", LIMS, ids=[n for _, n in LIMS])
+def test_uniform_state_bit_identical(amr, lim, lname, path):
+    w = inputs.uniform_state(3, (2, 2, 2), [1.3, 0.4, -0.25, 0.15, 0.8, 0.6, -0.9, 0.3, 0.0])
+    w.limiter = lim
+    sim = amr.Simulation(w, path=amr.PATH_FUSED if path == "fused" else amr.PATH_PLAIN)
+    u0 = sim.cons()
+    sim.advance(3, nstages=3)
+    assert np.array_equal(sim.cons(), u0)
+    sim.close()
+
+
+@pytest.mark.parametrize("lim,lname", LIMS, ids=[n for _, n in LIMS])
+def test_every_launch_shape_bit_identical(amr, lim, lname):
+    w = inputs.random_modes(64, 3, seed=53, nsteps=2)
+    w.limiter = lim
+    outs = [run_gpu(amr, w, 2, "fused", tune=t)[0] for t in amr.tune_candidates(3)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("lim,lname", LIMS, ids=[n for _, n in LIMS])
+def test_graph_and_batch_equal_eager(amr, lim, lname):
+    w = inputs.smooth_amr_state(3, nb1=2, seed=54)
+    w.limiter = lim
+    a, _ = run_gpu(amr, w, 3, "fused", graph=False)
+    b, _ = run_gpu(amr, w, 3, "fused", graph=True)
+    assert np.array_equal(a, b)
+    shape = inputs.random_modes(32, 3, seed=0)
+    shape.limiter = lim
+    ws = [inputs.random_modes(32, 3, seed=55, nsteps=3), inputs.random_modes(48, 3, seed=56, nsteps=2)]
+    batch = amr.Batch(shape, capacity_blocks=100, max_jobs=4, nstages=3)
+    ids = []
+    for wj in ws:
+        wj.limiter = lim
+        ids.append(batch.add_job(wj))
+    while any(batch.job_info(i)[1] > 0 for i in ids):
+        batch.step()
+    outs = [batch.get_job(i) for i in ids]
+    batch.close()
+    for wj, got in zip(ws, outs):
+        ref, _ = run_gpu(amr, wj, wj.nsteps, "fused")
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("lim,lname", LIMS, ids=[n for _, n in LIMS])
+def test_mixed_precision_bound(amr, orc, lim, lname):
+    w = inputs.random_modes(48, 3, seed=57, nsteps=10)
+    w.limiter = lim
+    ref, _ = orc.run(w)
+    got, fl = run_gpu(amr, w, w.nsteps, "fused", precision=1)
+    assert fl[0] == 0
+    err = rel_l1(w, got, ref)
+    assert err[0] < 1e-6 and err[4] < 1e-6, err
+
+
+def test_batch_rejects_a_job_with_another_limiter(amr):
+    shape = inputs.random_modes(32, 3, seed=0)
+    batch = amr.Batch(shape, capacity_blocks=100, max_jobs=2, nstages=3)
+    w = inputs.random_modes(32, 3, seed=58)
+    w.limiter = 1
+    with pytest.raises(amr.AmrvacError):
+        batch.add_job(w)
+    batch.close()

@@ -680,3 +680,104 @@ def test_alfven_wave_second_order(orc):
     assert math.log2(e2 / e3) >= 1.8, (e1, e2, e3)
     assert math.log2(e1 / e2) >= 1.6, (e1, e2, e3)
     assert e3 < 0.02
+
+
+# ---------------------------------------------------------------------------
+# the third-order limiters of Table t:limiters on the 2-ghost-cell stencil
+
+LIMS = [(1, "koren"), (2, "cada3")]
+
+
+@pytest.mark.parametrize("lim,name", LIMS)
+def test_limiter_exact_for_quadratic_averages(orc, lim, name):
+    """Where the data are smooth and monotone the face values are the
+    unlimited third-order ones, which reproduce the point value of a
+    quadratic at the face from its cell averages (h = 1 cells)."""
+    r = np.random.Generator(np.random.PCG64(21))
+    for _ in range(200):
+        c0, c1 = r.uniform(-2, 2), r.uniform(0.5, 2.0) * r.choice([-1, 1])
+        c2 = r.uniform(-0.05, 0.05) * abs(c1)  # gentle: ratios stay near 1
+        f = lambda x: c0 + c1 * x + c2 * x * x
+        avg = lambda i: f(i) + c2 / 12.0  # mean of f over [i - 1/2, i + 1/2]
+        wm, w0, wp = avg(-1), avg(0), avg(1)
+        inc_r, inc_l = orc.face_increments(lim, w0 - wm, wp - w0)
+        assert w0 + inc_r / 2 == pytest.approx(f(0.5), rel=1e-13, abs=1e-13)
+        assert w0 - inc_l / 2 == pytest.approx(f(-0.5), rel=1e-13, abs=1e-13)
+
+
+@pytest.mark.parametrize("lim,name", LIMS)
+def test_limiter_symmetries_and_bounds(orc, lim, name):
+    """Odd in the data, mirror-symmetric (the left face is the right face of
+    the reflected stencil), zero at a zero difference towards the face, and
+    (koren, which is TVD) face values between the neighbouring cell values;
+    cada3 also stays between them on monotone data."""
+    r = np.random.Generator(np.random.PCG64(22))
+    for _ in range(2000):
+        dm, dp = r.normal(size=2) * 10.0 ** r.uniform(-3, 1, size=2)
+        ir, il = orc.face_increments(lim, dm, dp)
+        assert orc.face_increments(lim, -dm, -dp) == (-ir, -il)
+        assert orc.face_increments(lim, dp, dm)[0] == il
+        if lim == 1 or dm * dp > 0:
+            # (the ratio forms round (d/e) * e, hence the ulp of slack)
+            assert 0.0 <= ir / 2 / dp <= 1.0 + 1e-15 if dp != 0 else ir == 0
+            assert 0.0 <= il / 2 / dm <= 1.0 + 1e-15 if dm != 0 else il == 0
+        assert orc.face_increments(lim, dm, 0.0)[0] == 0.0  # flat towards the right face
+        assert orc.face_increments(lim, 0.0, dp)[1] == 0.0  # flat towards the left face
+
+
+@pytest.mark.parametrize("lim,name", LIMS)
+def test_limiter_alfven_wave_beats_van_leer(orc, lim, name):
+    """On the smooth linear Alfven wave the third-order limiters converge at
+    order >= 2 and their error is well below van Leer's at the same grid."""
+    def err(n, lm):
+        w = inputs.alfven_wave(n, 2)
+        w.limiter = lm
+        sim = orc.OracleSim(w)
+        sim.steps_to_time(1.0 / math.sqrt(2.0))
+        e = np.mean(np.abs(sim.cons()[:, BZ] - w.prim[:, BZ])) / 1e-6
+        sim.close()
+        return e
+    e64, e128 = err(64, lim), err(128, lim)
+    assert math.log2(e64 / e128) >= 2.0, (e64, e128)
+    assert e128 < 0.5 * err(128, 0), (e128,)
+
+
+@pytest.mark.parametrize("lim,name", LIMS)
+def test_limiter_sod(orc, lim, name):
+    """Sod with the third-order limiters: L1(rho) against the exact Riemann
+    solution converges at order >= 0.6 and is below van Leer's."""
+    import exact_riemann as er
+
+    def l1(n, lm):
+        w = inputs.sod(n, ndim=2)
+        w.limiter = lm
+        sim = orc.OracleSim(w)
+        sim.steps_to_time(0.2)
+        g = inputs.blocks_to_global(sim.cons().swapaxes(0, 1), 2, w.nx, w.base_blocks)[RHO]
+        sim.close()
+        ex = er.cell_average_density(n, 0.2, 0.5, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+        return np.mean(np.abs(g[0] - ex))
+    ns = [64, 128, 256]
+    errs = [l1(n, lim) for n in ns]
+    assert min(math.log2(errs[i] / errs[i + 1]) for i in range(2)) >= 0.6, errs
+    assert all(e <= l1(n, 0) for e, n in zip(errs, ns)), errs
+
+
+@pytest.mark.parametrize("lim,name", LIMS)
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_limiter_uniform_and_conservation(orc, lim, name, ndim):
+    w = inputs.uniform_state(ndim, (3, 2, 2), _uniform_w())
+    w.limiter = lim
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    sim.steps(3)
+    assert np.array_equal(sim.cons(), u0)
+    w = inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5 if ndim == 2 else 7)
+    w.limiter = lim
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    t0 = _totals(w, u0)
+    sim.steps(3 if ndim == 3 else 10)
+    t1 = _totals(w, sim.cons())
+    rel = np.abs(t1 - t0) / _scale(w, u0)
+    assert np.all(rel[[RHO, VX, VY, VZ, PR, BX, BY, BZ]] < 1e-13), rel
