@@ -101,6 +101,7 @@ def parse():
                     help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
     ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud"], default="random_modes")
     ap.add_argument("--limiter", choices=["vanleer", "koren", "cada3"], default="vanleer")
+    ap.add_argument("--flux", choices=["hll", "hlld"], default="hll")
     ap.add_argument("--tune", default="auto",
                     help="fused-stage launch shape: 'auto' (autotuner, before the warmup), 'default', or z,r,x")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -177,6 +178,7 @@ def main():
     else:
         w = inputs.shock_cloud_amr()
     w.limiter = LIMITERS.index(args.limiter)
+    w.flux = 1 if args.flux == "hlld" else 0
     mixed = args.precision == "mixed"
     if mixed:
         args.path = "fused"
@@ -250,7 +252,7 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 
     traffic = (measured_traffic(args.precision, tune, args.workload, args.n)
-               if args.path == "fused" and args.limiter == "vanleer" else None)
+               if args.path == "fused" and args.limiter == "vanleer" and args.flux == "hll" else None)
 
     graph_ms = None
     if not args.no_graph_pass:
@@ -277,9 +279,9 @@ def main():
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": "%s: 3D, %d leaf blocks of 16^3 + 2 ghost layers on %d level(s), %s GLM-MHD "
-                               "state, SSPRK(3,3), CFL 0.8, %s, %s limiter"
+                               "state, SSPRK(3,3), CFL 0.8, %s, %s limiter, %s flux"
                                % (w.name, w.nblocks, w.max_level, args.workload, "FP32-mixed" if mixed else "FP64",
-                                  args.limiter),
+                                  args.limiter, args.flux.upper()),
                    "path": args.path, "cells": cells, "stage_weights": [1.0, 0.25, 2.0 / 3.0],
                    "tune": None if tune is None else {"zseg": tune[0], "rotate": tune[1], "xcd": tune[2]}},
         "autotune_ms_per_launch": {"%d,%d,%d" % k: round(v, 4) for k, v in tune_times.items()},
@@ -301,7 +303,7 @@ def main():
             small = inputs.current_sheet(n=48)
         else:
             small = inputs.shock_cloud_amr(base_n=32)
-        small.limiter = w.limiter
+        small.limiter, small.flux = w.limiter, w.flux
         out["cpu_baseline"] = cpu_baseline(w, small)
     print(json.dumps(out), flush=True)
 

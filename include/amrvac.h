@@ -69,6 +69,11 @@ enum { AMRVAC_PATH_PLAIN = 0, AMRVAC_PATH_FUSED = 1 };
  * the unlimited third-order values (2 d+ + d-)/6 and (2 d- + d+)/6 in smooth
  * monotone regions. */
 enum { AMRVAC_LIM_VANLEER = 0, AMRVAC_LIM_KOREN = 1, AMRVAC_LIM_CADA3 = 2 };
+/* Interface flux schemes (Table tab:schemes_space), both on top of the GLM
+ * interface values of (B_n, psi): HLL with Davis speed bounds, or HLLD
+ * (Miyoshi and Kusano 2005: contact, Alfven and fast waves, resolving
+ * isolated contact and rotational discontinuities exactly). */
+enum { AMRVAC_FLUX_HLL = 0, AMRVAC_FLUX_HLLD = 1 };
 
 /* Grid and scheme description.  Physical boundary kinds per face follow the
  * paper's examples: periodic, zero-gradient ("continuous"), reflective
@@ -94,6 +99,7 @@ typedef struct {
   double small_pressure;
   double bc_fixed_prim[3][2][9]; /* primitive state of AMRVAC_BC_FIXED faces   */
   int limiter;            /* AMRVAC_LIM_*                                      */
+  int flux;               /* AMRVAC_FLUX_*                                     */
 } amrvac_grid_desc;
 
 /* Device bytes of one state slot for nblocks blocks of this description.

@@ -13,7 +13,8 @@
 //   * limited linear reconstruction of primitive variables giving a left and
 //     a right state per face, with the 'vanleer', 'koren' or 'cada3'
 //     limiter and 2 ghost cells (Table t:limiters);
-//   * the HLL flux (Table tab:schemes_space; Harten et al. 1983);
+//   * the HLL flux (Table tab:schemes_space; Harten et al. 1983), or HLLD
+//     (Miyoshi and Kusano 2005);
 //   * the 'glm' divergence control of Dedner et al. 2002 (Table t:divb);
 //   * the CFL coupling of the time step to the grid spacing ("Schemes and
 //     limiters for HD and MHD");
@@ -220,10 +221,108 @@ void glm_interface(double bnl, double bnr, double psl, double psr, double ch, do
   *ps = 0.5 * (psl + psr) - 0.5 * ch * (bnr - bnl);
 }
 
+enum { FLUX_HLL = 0, FLUX_HLLD = 1 };
+
+// HLLD (Miyoshi and Kusano 2005; the 'hlld' entry of Table
+// tab:schemes_space, used there with glm) on the seven components other than
+// B_n and psi; bx is the normal field, the same on both sides.  Notation: u
+// the normal velocity, pT = p + |B|^2/2 the total pressure, t the two
+// tangential directions.  Wave speeds: S_L, S_R bracket both fast speeds
+// around both normal velocities; S_M is the contact (entropy) speed; S*_L,
+// S*_R the rotational (Alfven) waves S_M -/+ |bx| / sqrt(rho*).
+void hlld_flux(const Cell& wl, const Cell& wr, const Cell& ul, const Cell& ur, const double fl[NV],
+               const double fr[NV], int d, double bx, double gamma, double F[NV]) {
+  const int MN = MX + d;
+  int tan[2], k = 0;
+  for (int j = 0; j < 3; ++j)
+    if (j != d) tan[k++] = j;
+  const double rho[2] = {wl.v[RHO], wr.v[RHO]};
+  const double un[2] = {wl.v[VX + d], wr.v[VX + d]};
+  double pt[2];
+  for (int a = 0; a < 2; ++a) {
+    const Cell& w = a ? wr : wl;
+    pt[a] = w.v[PR] + 0.5 * (w.v[BX] * w.v[BX] + w.v[BY] * w.v[BY] + w.v[BZ] * w.v[BZ]);
+  }
+  const double cfmax = std::max(fast_speed(wl, d, gamma), fast_speed(wr, d, gamma));
+  const double S[2] = {std::min(un[0], un[1]) - cfmax, std::max(un[0], un[1]) + cfmax};
+  auto copy7 = [&](const double* f) {
+    for (int q = 0; q < NV; ++q)
+      if (q != BX + d && q != PSI) F[q] = f[q];
+  };
+  if (S[0] > 0.0) { copy7(fl); return; }
+  if (S[1] < 0.0) { copy7(fr); return; }
+  // contact speed and the total pressure of the star region
+  const double dl = (S[0] - un[0]) * rho[0], dr = (S[1] - un[1]) * rho[1];
+  const double sm = (dr * un[1] - dl * un[0] - pt[1] + pt[0]) / (dr - dl);
+  const double pts = (dr * pt[0] - dl * pt[1] + rho[0] * rho[1] * (S[1] - un[1]) * (S[0] - un[0]) * (un[1] - un[0])) /
+                     (dr - dl);
+  // single-star states U*_L, U*_R
+  Cell us[2];
+  double rs[2], vs[2][2], bs[2][2];
+  for (int a = 0; a < 2; ++a) {
+    const Cell& w = a ? wr : wl;
+    const Cell& u = a ? ur : ul;
+    const double sa = S[a] - un[a], sb = S[a] - sm;
+    rs[a] = rho[a] * sa / sb;
+    const double den = rho[a] * sa * sb - bx * bx;
+    const bool degenerate = std::fabs(den) <= 1e-12 * rho[a] * sa * sa;
+    for (int t = 0; t < 2; ++t) {
+      const double vt = w.v[VX + tan[t]], bt = w.v[BX + tan[t]];
+      if (degenerate) {
+        vs[a][t] = vt;
+        bs[a][t] = bt;
+      } else {
+        vs[a][t] = vt - bx * bt * (sm - un[a]) / den;
+        bs[a][t] = bt * (rho[a] * sa * sa - bx * bx) / den;
+      }
+    }
+    const double vb = un[a] * bx + w.v[VX + tan[0]] * w.v[BX + tan[0]] + w.v[VX + tan[1]] * w.v[BX + tan[1]];
+    const double vbs = sm * bx + vs[a][0] * bs[a][0] + vs[a][1] * bs[a][1];
+    Cell& x = us[a];
+    x = u;  // B_n and psi are not HLLD components
+    x.v[RHO] = rs[a];
+    x.v[MN] = rs[a] * sm;
+    x.v[EN] = (sa * u.v[EN] - pt[a] * un[a] + pts * sm + bx * (vb - vbs)) / sb;
+    for (int t = 0; t < 2; ++t) {
+      x.v[MX + tan[t]] = rs[a] * vs[a][t];
+      x.v[BX + tan[t]] = bs[a][t];
+    }
+  }
+  // the side of the contact the interface lies on
+  const int a = sm >= 0.0 ? 0 : 1;
+  const Cell& ua = a ? ur : ul;
+  const double* fa = a ? fr : fl;
+  double Fs[NV];
+  for (int q = 0; q < NV; ++q) Fs[q] = fa[q] + S[a] * (us[a].v[q] - ua.v[q]);
+  const double sql = std::sqrt(rs[0]), sqr = std::sqrt(rs[1]);
+  const double sas = a == 0 ? sm - std::fabs(bx) / sql : sm + std::fabs(bx) / sqr;  // S*_L or S*_R
+  const bool inner = a == 0 ? sas < 0.0 : sas > 0.0;  // between the Alfven wave and the contact
+  if (!inner) { copy7(Fs); return; }
+  // double-star state U**_a
+  const double sg = bx > 0.0 ? 1.0 : (bx < 0.0 ? -1.0 : 0.0);
+  double vss[2], bss[2];
+  for (int t = 0; t < 2; ++t) {
+    vss[t] = (sql * vs[0][t] + sqr * vs[1][t] + (bs[1][t] - bs[0][t]) * sg) / (sql + sqr);
+    bss[t] = (sql * bs[1][t] + sqr * bs[0][t] + sql * sqr * (vs[1][t] - vs[0][t]) * sg) / (sql + sqr);
+  }
+  const double vbs_a = sm * bx + vs[a][0] * bs[a][0] + vs[a][1] * bs[a][1];
+  const double vbss = sm * bx + vss[0] * bss[0] + vss[1] * bss[1];
+  Cell uss = us[a];
+  uss.v[EN] = a == 0 ? us[0].v[EN] - sql * (vbs_a - vbss) * sg : us[1].v[EN] + sqr * (vbs_a - vbss) * sg;
+  for (int t = 0; t < 2; ++t) {
+    uss.v[MX + tan[t]] = rs[a] * vss[t];
+    uss.v[BX + tan[t]] = bss[t];
+  }
+  double Fss[NV];
+  for (int q = 0; q < NV; ++q) Fss[q] = Fs[q] + sas * (uss.v[q] - us[a].v[q]);
+  copy7(Fss);
+}
+
 // Interface flux from the reconstructed left/right primitive states: GLM
-// interface values for (B_n, psi), then HLL with Davis speed bounds on the
-// other seven components, built from the states with B_n replaced.
-void face_flux(Cell wl, Cell wr, int d, double ch, double gamma, double F[NV]) {
+// interface values for (B_n, psi), then HLL with Davis speed bounds (or
+// HLLD) on the other seven components, built from the states with B_n
+// replaced.
+void face_flux(Cell wl, Cell wr, int d, double ch, double gamma, double F[NV], int flux = FLUX_HLL) {
   double bn, ps;
   glm_interface(wl.v[BX + d], wr.v[BX + d], wl.v[PSI], wr.v[PSI], ch, &bn, &ps);
   wl.v[BX + d] = bn;
@@ -233,6 +332,12 @@ void face_flux(Cell wl, Cell wr, int d, double ch, double gamma, double F[NV]) {
   double fl[NV], fr[NV];
   phys_flux(wl, ul, d, fl);
   phys_flux(wr, ur, d, fr);
+  F[BX + d] = ps;
+  F[PSI] = ch * ch * bn;
+  if (flux == FLUX_HLLD) {
+    hlld_flux(wl, wr, ul, ur, fl, fr, d, bn, gamma, F);
+    return;
+  }
   const double cl = fast_speed(wl, d, gamma);
   const double cr = fast_speed(wr, d, gamma);
   const double sl = std::min(wl.v[VX + d] - cl, wr.v[VX + d] - cr);
@@ -297,6 +402,7 @@ typedef struct {
   double small_density;
   double small_pressure;
   int limiter;  // 0 = 'vanleer', 1 = 'koren', 2 = 'cada3'
+  int flux;     // 0 = HLL, 1 = HLLD
 } oracle_params;
 
 }  // extern "C"
@@ -547,7 +653,7 @@ struct Sim {
                 wl = wm;
                 wr = wp;
               }
-              face_flux(wl, wr, d, ch, ph.gamma, F[(t2 * nx + t1) * (nx + 1) + f].v);
+              face_flux(wl, wr, d, ch, ph.gamma, F[(t2 * nx + t1) * (nx + 1) + f].v, P.flux);
             }
       }
     }
@@ -763,6 +869,7 @@ Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int*
   if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
   if (p->nstages < 1 || p->nstages > 5) throw std::invalid_argument("nstages must be 1 .. 5");
   if (p->limiter < LIM_VANLEER || p->limiter > LIM_CADA3) throw std::invalid_argument("unknown limiter");
+  if (p->flux != FLUX_HLL && p->flux != FLUX_HLLD) throw std::invalid_argument("unknown flux scheme");
   if (s->P.nthreads < 1) s->P.nthreads = 1;
   for (int d = 0; d < s->ndim; ++d)
     if ((p->bc_lo[d] == BC_PERIODIC) != (p->bc_hi[d] == BC_PERIODIC))
@@ -983,6 +1090,14 @@ void oracle_face_flux(const double* wl, const double* wr, int d, double ch, doub
   std::memcpy(a.v, wl, sizeof(a.v));
   std::memcpy(b.v, wr, sizeof(b.v));
   face_flux(a, b, d, ch, gamma, F);
+}
+int oracle_face_flux_kind(const double* wl, const double* wr, int d, double ch, double gamma, int flux, double* F) {
+  if (flux != FLUX_HLL && flux != FLUX_HLLD) return -1;
+  Cell a, b;
+  std::memcpy(a.v, wl, sizeof(a.v));
+  std::memcpy(b.v, wr, sizeof(b.v));
+  face_flux(a, b, d, ch, gamma, F, flux);
+  return 0;
 }
 void oracle_phys_flux(const double* w, int d, double gamma, double* F) {
   Cell c;

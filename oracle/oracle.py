@@ -28,7 +28,7 @@ class Params(ctypes.Structure):
         ("xmax", ctypes.c_double * 3), ("bc_fixed_prim", ctypes.c_double * (3 * 2 * NV)),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("glm_alpha", ctypes.c_double),
         ("small_density", ctypes.c_double), ("small_pressure", ctypes.c_double),
-        ("limiter", ctypes.c_int),
+        ("limiter", ctypes.c_int), ("flux", ctypes.c_int),
     ]
 
 
@@ -70,6 +70,7 @@ def lib():
         _lib.oracle_glm_interface.argtypes = [ctypes.c_double] * 5 + [dp]
         _lib.oracle_face_flux.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         _lib.oracle_phys_flux.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp]
+        _lib.oracle_face_flux_kind.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
     return _lib
 
 
@@ -112,6 +113,7 @@ def make_params(w, nthreads: Optional[int] = None, nstages: Optional[int] = None
     p.small_density = w.small_density
     p.small_pressure = w.small_pressure
     p.limiter = int(getattr(w, "limiter", 0))
+    p.flux = int(getattr(w, "flux", 0))
     return p
 
 
@@ -243,11 +245,16 @@ def glm_interface(bnl, bnr, psl, psr, ch):
     return out[0], out[1]
 
 
-def face_flux(wl, wr, d: int, ch: float, gamma: float) -> np.ndarray:
+def face_flux(wl, wr, d: int, ch: float, gamma: float, flux: int = 0) -> np.ndarray:
+    """Interface flux of the primitive states wl, wr along d: GLM interface
+    values, then HLL (flux = 0) or HLLD (flux = 1)."""
     wl = np.ascontiguousarray(wl, dtype=np.float64)
     wr = np.ascontiguousarray(wr, dtype=np.float64)
     F = np.empty(NV)
-    lib().oracle_face_flux(_dp(wl), _dp(wr), d, ch, gamma, _dp(F))
+    if flux == 0:
+        lib().oracle_face_flux(_dp(wl), _dp(wr), d, ch, gamma, _dp(F))
+    elif lib().oracle_face_flux_kind(_dp(wl), _dp(wr), d, ch, gamma, flux, _dp(F)) != 0:
+        raise ValueError("unknown flux scheme %d" % flux)
     return F
 
 

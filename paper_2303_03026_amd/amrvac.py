@@ -18,6 +18,7 @@ NV = 9
 
 FP64, FP32_MIXED = 0, 1
 LIM_VANLEER, LIM_KOREN, LIM_CADA3 = 0, 1, 2
+FLUX_HLL, FLUX_HLLD = 0, 1
 PATH_PLAIN, PATH_FUSED = 0, 1
 FLAG_SMALL_RHO, FLAG_SMALL_P, FLAG_BAD_DT = 1, 2, 4
 E_OK, E_ARG, E_HIP, E_NOMEM, E_NONPHYSICAL, E_STATE = 0, -1, -2, -3, -4, -5
@@ -51,7 +52,7 @@ class GridDesc(ctypes.Structure):
         ("xmin", ctypes.c_double * 3), ("xmax", ctypes.c_double * 3), ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double), ("glm_alpha", ctypes.c_double), ("small_density", ctypes.c_double),
         ("small_pressure", ctypes.c_double), ("bc_fixed_prim", ctypes.c_double * (3 * 2 * NV)),
-        ("limiter", ctypes.c_int),
+        ("limiter", ctypes.c_int), ("flux", ctypes.c_int),
     ]
 
 
@@ -132,6 +133,7 @@ def make_desc(w, precision: int = FP64) -> GridDesc:
     for i in range(3 * 2 * NV):
         g.bc_fixed_prim[i] = fixed[i]
     g.limiter = int(getattr(w, "limiter", LIM_VANLEER))
+    g.flux = int(getattr(w, "flux", FLUX_HLL))
     return g
 
 

@@ -29,6 +29,7 @@ struct PhysConst {
   double small_p;
   int fix;
   int limiter;  // LIM_* (the fused stage takes it as a template argument)
+  int flux;     // FLUX_HLL or FLUX_HLLD (likewise)
 };
 
 // Library-owned device status record.
@@ -269,6 +270,121 @@ __device__ __forceinline__ void hll_glm_flux(R wl[NV], R wr[NV], R ch, R half_in
   }
   F[N] = ps;
   F[I_PSI] = ch * ch * bn;
+}
+
+// HLLD (Miyoshi and Kusano 2005) with the same GLM interface values as
+// hll_glm_flux: B_n := B_n* on both sides, F(B_n) = psi*, F(psi) = c_h^2 B_n*,
+// and HLLD on the other seven components.  S_L, S_R bracket both fast speeds
+// around both normal velocities; S_M is the contact speed and p_T* the total
+// pressure of the star region; the single-star states follow from the jump
+// conditions across S_L / S_R (their tangential parts unchanged where
+// rho (S - u)(S - S_M) - B_n^2 vanishes), the Alfven waves sit at
+// S_M -/+ |B_n| / sqrt(rho*), and the double-star states between them and the
+// contact.  Only the side of the contact that the interface lies on is
+// assembled: F = F_a + S_a (U*_a - U_a) [+ S*_a (U**_a - U*_a) between the
+// Alfven wave and the contact]; selects (not arithmetic) drop the star terms
+// when every wave moves one way.
+template <int D, class R>
+__device__ __forceinline__ void hlld_glm_flux(R wl[NV], R wr[NV], R ch, R half_inv_ch, R gamma, R inv_gm1,
+                                              R F[NV]) {
+  constexpr int N = I_BX + D;
+  constexpr int T1 = D == 0 ? 1 : 0, T2 = D == 2 ? 1 : 2;  // tangential axes
+  const R bn = R(0.5) * (wl[N] + wr[N]) - (wr[I_PSI] - wl[I_PSI]) * half_inv_ch;
+  const R ps = R(0.5) * (wl[I_PSI] + wr[I_PSI]) - R(0.5) * ch * (wr[N] - wl[N]);
+  wl[N] = bn;
+  wr[N] = bn;
+  const R rl = wl[I_RHO], rr = wr[I_RHO];
+  const R ul = wl[1 + D], ur = wr[1 + D];
+  const R b2l = wl[I_BX] * wl[I_BX] + wl[I_BY] * wl[I_BY] + wl[I_BZ] * wl[I_BZ];
+  const R b2r = wr[I_BX] * wr[I_BX] + wr[I_BY] * wr[I_BY] + wr[I_BZ] * wr[I_BZ];
+  const R ptl = wl[4] + R(0.5) * b2l, ptr = wr[4] + R(0.5) * b2r;
+  const R cfm = fmax(cfast<D>(wl, rcp_(rl), b2l, gamma), cfast<D>(wr, rcp_(rr), b2r, gamma));
+  const R sl = fmin(ul, ur) - cfm, sr = fmax(ul, ur) + cfm;
+  const R dl = (sl - ul) * rl, dr = (sr - ur) * rr;
+  const R idd = rcp_(dr - dl);
+  const R sm = (dr * ur - dl * ul - ptr + ptl) * idd;
+  const R pts = (dr * ptl - dl * ptr + dl * dr * (ur - ul)) * idd;
+  const R bn2 = bn * bn;
+  // single-star density and tangential parts, both sides
+  R rs[2], vs1[2], vs2[2], bs1[2], bs2[2], isb[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const R* w = a ? wr : wl;
+    const R rho = a ? rr : rl, u = a ? ur : ul, sa = (a ? sr : sl) - u, sb = (a ? sr : sl) - sm;
+    isb[a] = rcp_(sb);
+    rs[a] = rho * sa * isb[a];
+    const R den = rho * sa * sb - bn2;
+    const bool deg = fabs(den) <= R(1e-12) * rho * sa * sa;
+    const R iden = rcp_(den);
+    const R f1 = deg ? R(0) : bn * (sm - u) * iden;
+    const R f2 = deg ? R(1) : (rho * sa * sa - bn2) * iden;
+    vs1[a] = w[1 + T1] - f1 * w[I_BX + T1];
+    vs2[a] = w[1 + T2] - f1 * w[I_BX + T2];
+    bs1[a] = f2 * w[I_BX + T1];
+    bs2[a] = f2 * w[I_BX + T2];
+  }
+  // double-star tangential parts
+  const R sql = sqrt_(rs[0]), sqr = sqrt_(rs[1]);
+  const R isum = rcp_(sql + sqr);
+  const R sg = bn > R(0) ? R(1) : (bn < R(0) ? R(-1) : R(0));
+  const R vss1 = (sql * vs1[0] + sqr * vs1[1] + (bs1[1] - bs1[0]) * sg) * isum;
+  const R vss2 = (sql * vs2[0] + sqr * vs2[1] + (bs2[1] - bs2[0]) * sg) * isum;
+  const R bss1 = (sql * bs1[1] + sqr * bs1[0] + sql * sqr * (vs1[1] - vs1[0]) * sg) * isum;
+  const R bss2 = (sql * bs2[1] + sqr * bs2[0] + sql * sqr * (vs2[1] - vs2[0]) * sg) * isum;
+  // the side a of the contact the interface lies on, and its states
+  const bool right = sr < R(0) || (!(sl > R(0)) && sm < R(0));
+  const R* w = right ? wr : wl;
+  const R rho = right ? rr : rl, u = right ? ur : ul, pt = right ? ptr : ptl, b2 = right ? b2r : b2l;
+  const R S = right ? sr : sl, sa = S - u;
+  const R rsa = right ? rs[1] : rs[0], isba = right ? isb[1] : isb[0];
+  const R vs1a = right ? vs1[1] : vs1[0], vs2a = right ? vs2[1] : vs2[0];
+  const R bs1a = right ? bs1[1] : bs1[0], bs2a = right ? bs2[1] : bs2[0];
+  const R v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+  const R e = w[4] * inv_gm1 + R(0.5) * rho * v2 + R(0.5) * b2;
+  const R vb = w[1] * w[I_BX] + w[2] * w[I_BY] + w[3] * w[I_BZ];
+  const R vbs = sm * bn + vs1a * bs1a + vs2a * bs2a;
+  const R es = (sa * e - pt * u + pts * sm + bn * (vb - vbs)) * isba;
+  const R vbss = sm * bn + vss1 * bss1 + vss2 * bss2;
+  const R sqa = right ? sqr : sql, sgn_a = right ? R(1) : R(-1);
+  const R ess = es + sgn_a * sqa * (vbs - vbss) * sg;
+  const R sas = sm + sgn_a * fabs(bn) * rcp_(sqa);  // S*_a
+  const bool super = sl > R(0) || sr < R(0);       // every wave moves one way: F = F_a
+  const bool inner = sgn_a * sas > R(0);            // between the Alfven wave and the contact
+  auto hlld = [&](R uq, R usq, R ussq, R fq) {
+    const R fs = fq + S * (usq - uq);
+    const R f = inner ? fs + sas * (ussq - usq) : fs;
+    return super ? fq : f;
+  };
+  F[I_RHO] = hlld(rho, rsa, rsa, rho * u);
+  F[1 + D] = hlld(rho * u, rsa * sm, rsa * sm, rho * u * u + pt - bn2);
+  F[1 + T1] = hlld(rho * w[1 + T1], rsa * vs1a, rsa * vss1, rho * w[1 + T1] * u - w[I_BX + T1] * bn);
+  F[1 + T2] = hlld(rho * w[1 + T2], rsa * vs2a, rsa * vss2, rho * w[1 + T2] * u - w[I_BX + T2] * bn);
+  F[I_EN] = hlld(e, es, ess, (e + pt) * u - bn * vb);
+  F[I_BX + T1] = hlld(w[I_BX + T1], bs1a, bss1, u * w[I_BX + T1] - bn * w[1 + T1]);
+  F[I_BX + T2] = hlld(w[I_BX + T2], bs2a, bss2, u * w[I_BX + T2] - bn * w[1 + T2]);
+  F[N] = ps;
+  F[I_PSI] = ch * ch * bn;
+}
+
+enum { FLUX_HLL = 0, FLUX_HLLD = 1 };
+
+// interface flux of the scheme chosen at compile time
+template <int FLX, int D, class R>
+__device__ __forceinline__ void face_flux(R wl[NV], R wr[NV], R ch, R half_inv_ch, R gamma, R inv_gm1, R F[NV]) {
+  if (FLX == FLUX_HLLD)
+    hlld_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
+  else
+    hll_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
+}
+
+// ... and at run time (the per-kernel path and the flux correction)
+template <int D, class R>
+__device__ __forceinline__ void face_flux_rt(int flux, R wl[NV], R wr[NV], R ch, R half_inv_ch, R gamma, R inv_gm1,
+                                             R F[NV]) {
+  if (flux == FLUX_HLLD)
+    hlld_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
+  else
+    hll_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
 }
 
 // First-order fallback at a face: where rho or p of either reconstructed

@@ -1,6 +1,6 @@
 // Fused stage kernel for 16^ndim blocks: conserved -> primitive, limited
 // linear reconstruction (van Leer, Koren or Cada-Torrilhon), GLM interface +
-// HLL fluxes in every direction, flux difference, psi damping and the SSPRK
+// HLL (or HLLD) fluxes in every direction, flux difference, psi damping and the SSPRK
 // combination, in one launch.
 //
 // One 256-thread workgroup per block; thread t owns the (x, y) column
@@ -133,7 +133,7 @@ struct FaceConst {
 // energy difference is accumulated in double (acc_e).
 // The halo slopes (cells -1 and 16 of every line) and the 17th face of every
 // line are done by the lanes of wave xw (extra lane e = t - 64 xw).
-template <int DIR, int LIM, class R>
+template <int DIR, int LIM, int FLX, class R>
 __device__ __forceinline__ void plane_direction(const R (*__restrict__ Wp)[BP * WROW], R (*__restrict__ Sl)[SLOPE_ROW * BN],
                                                 R (*__restrict__ Fl)[(BN + 1) * BN], int t, int i, int j, int xw,
                                                 const FaceConst<R>& K, double inv_dx, R acc[NV], double& acc_e,
@@ -147,14 +147,14 @@ __device__ __forceinline__ void plane_direction(const R (*__restrict__ Wp)[BP * 
   {
     R wl[NV], wr[NV], F[NV];
     face_states<DIR, LIM>(Wp, Sl, line, f, wl, wr);
-    hll_glm_flux<DIR, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, F);
+    face_flux<FLX, DIR, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, F);
 #pragma unroll
     for (int q = 0; q < NV; ++q) Fl[q][line * (BN + 1) + f] = F[q];
   }
   if ((unsigned)e < 16u) {  // the 17th face of line e
     R wl[NV], wr[NV], F[NV];
     face_states<DIR, LIM>(Wp, Sl, e, BN, wl, wr);
-    hll_glm_flux<DIR, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, F);
+    face_flux<FLX, DIR, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, F);
 #pragma unroll
     for (int q = 0; q < NV; ++q) Fl[q][e * (BN + 1) + BN] = F[q];
   }
@@ -179,7 +179,7 @@ __device__ __forceinline__ void plane_direction(const R (*__restrict__ Wp)[BP * 
 // Work item w (one z segment of one block) is run by workgroup g with
 // w = (g % 8) * per_xcd + g / 8 when tune.xcd is set (each XCD gets a
 // contiguous run of the Morton-ordered list), else w = g.
-template <int NDIM, class SP, bool W1, bool CFL, int LIM>
+template <int NDIM, class SP, bool W1, bool CFL, int LIM, int FLX>
 __global__ void __launch_bounds__(256, SP::kWavesPerEU)
 k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, const void* __restrict__ in,
               const void* base, void* out, double wgt, PhysConst P, DevStatus* st, JobCfl C) {
@@ -365,7 +365,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
         wla[q] = wa[q] + R(0.5) * r0;
       }
       positivity_fallback(wl, wr, wm1, wa);
-      hll_glm_flux<2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
+      face_flux<FLX, 2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
         if (q == I_EN) {
@@ -412,8 +412,8 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
     const bool staging = stager && k + 1 < k1;
     if (staging) stage_halo(k + 1);
 
-    plane_direction<0, LIM, R>(Wp, Sl, Fl, t, i, j, xw, K, idx, acc, acc_e, false);
-    plane_direction<1, LIM, R>(Wp, Sl, Fl, t, i, j, yw, K, idy, acc, acc_e, staging);
+    plane_direction<0, LIM, FLX, R>(Wp, Sl, Fl, t, i, j, xw, K, idx, acc, acc_e, false);
+    plane_direction<1, LIM, FLX, R>(Wp, Sl, Fl, t, i, j, yw, K, idy, acc, acc_e, staging);
 
     // this plane's conserved state and the stage base, issued as one group
     const long c = PD::at(i, j, k);
@@ -438,7 +438,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
         wla[q] = wb[q] + R(0.5) * r1;
       }
       positivity_fallback(wl, wr, wa, wb);
-      hll_glm_flux<2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
+      face_flux<FLX, 2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
       // fz becomes F_z(k+1/2)/dz (the energy term in double, in fze); it is
       // added here and its negative seeds the next plane's accumulator
 #pragma unroll
@@ -548,30 +548,37 @@ hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T
   const int per_xcd = (int)((items + 7) / 8);
   const unsigned grid = tune.xcd ? 8u * (unsigned)per_xcd : (unsigned)items;
   const JobCfl C = cfl ? *cfl : JobCfl{};
-#define AMRVAC_FUSED_KERNEL(ND, SPT, W1, CF, LM) \
-  k_stage_fused<ND, SPT, W1, CF, LM><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st, C)
-#define AMRVAC_FUSED_LAUNCH(ND, SPT, LM)               \
+#define AMRVAC_FUSED_KERNEL(ND, SPT, W1, CF, LM, FX) \
+  k_stage_fused<ND, SPT, W1, CF, LM, FX><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st, C)
+#define AMRVAC_FUSED_LAUNCH(ND, SPT, LM, FX)               \
+  do {                                                     \
+    if (cfl) {                                             \
+      if (w == 1.0)                                        \
+        AMRVAC_FUSED_KERNEL(ND, SPT, true, true, LM, FX);  \
+      else                                                 \
+        AMRVAC_FUSED_KERNEL(ND, SPT, false, true, LM, FX); \
+    } else {                                               \
+      if (w == 1.0)                                        \
+        AMRVAC_FUSED_KERNEL(ND, SPT, true, false, LM, FX); \
+      else                                                 \
+        AMRVAC_FUSED_KERNEL(ND, SPT, false, false, LM, FX); \
+    }                                                      \
+  } while (0)
+#define AMRVAC_FUSED_FLUX(ND, SPT, LM)                 \
   do {                                                 \
-    if (cfl) {                                         \
-      if (w == 1.0)                                    \
-        AMRVAC_FUSED_KERNEL(ND, SPT, true, true, LM);  \
-      else                                             \
-        AMRVAC_FUSED_KERNEL(ND, SPT, false, true, LM); \
-    } else {                                           \
-      if (w == 1.0)                                    \
-        AMRVAC_FUSED_KERNEL(ND, SPT, true, false, LM); \
-      else                                             \
-        AMRVAC_FUSED_KERNEL(ND, SPT, false, false, LM); \
-    }                                                  \
+    if (P.flux == FLUX_HLLD)                           \
+      AMRVAC_FUSED_LAUNCH(ND, SPT, LM, FLUX_HLLD);     \
+    else                                               \
+      AMRVAC_FUSED_LAUNCH(ND, SPT, LM, FLUX_HLL);      \
   } while (0)
 #define AMRVAC_FUSED_LIMITER(ND, SPT)                 \
   do {                                                \
     if (P.limiter == LIM_KOREN)                       \
-      AMRVAC_FUSED_LAUNCH(ND, SPT, LIM_KOREN);        \
+      AMRVAC_FUSED_FLUX(ND, SPT, LIM_KOREN);          \
     else if (P.limiter == LIM_CADA3)                  \
-      AMRVAC_FUSED_LAUNCH(ND, SPT, LIM_CADA3);        \
+      AMRVAC_FUSED_FLUX(ND, SPT, LIM_CADA3);          \
     else                                              \
-      AMRVAC_FUSED_LAUNCH(ND, SPT, LIM_VANLEER);      \
+      AMRVAC_FUSED_FLUX(ND, SPT, LIM_VANLEER);        \
   } while (0)
   if (G.precision == 0) {
     if (G.ndim == 3)
@@ -585,6 +592,7 @@ hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T
       AMRVAC_FUSED_LIMITER(2, StoreMixed);
   }
 #undef AMRVAC_FUSED_LIMITER
+#undef AMRVAC_FUSED_FLUX
 #undef AMRVAC_FUSED_LAUNCH
 #undef AMRVAC_FUSED_KERNEL
   return hipGetLastError();

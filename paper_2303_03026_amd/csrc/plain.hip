@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) k_flux(GridConst G, const double* __restr
   double wl[NV], wr[NV], F[NV];
   reconstruct_face(P.limiter, wm, wa, wb, wp, wl, wr);
   const double ch = *ch_dev;
-  hll_glm_flux<D, double>(wl, wr, ch, 0.5 / ch, P.gamma, P.inv_gm1, F);
+  face_flux_rt<D, double>(P.flux, wl, wr, ch, 0.5 / ch, P.gamma, P.inv_gm1, F);
   double* out = flux + (long)b * NV * G.nfaces + fi;
 #pragma unroll
   for (int q = 0; q < NV; ++q) out[(long)q * G.nfaces] = F[q];
@@ -404,7 +404,7 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
   }
   R wl[NV], wr[NV];
   reconstruct_face(P.limiter, w4[0], w4[1], w4[2], w4[3], wl, wr);
-  hll_glm_flux<D, R>(wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
+  face_flux_rt<D, R>(P.flux, wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
 }
 
 template <int D, class SP>

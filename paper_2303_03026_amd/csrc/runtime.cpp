@@ -74,6 +74,7 @@ int check_desc(const amrvac_grid_desc* g, std::string* why) {
   }
   if (!(g->gamma > 1.0) || !(g->cfl > 0.0) || !(g->glm_alpha >= 0.0)) { *why = "bad gamma/cfl/glm_alpha"; return AMRVAC_E_ARG; }
   if (g->limiter < AMRVAC_LIM_VANLEER || g->limiter > AMRVAC_LIM_CADA3) { *why = "bad limiter"; return AMRVAC_E_ARG; }
+  if (g->flux != AMRVAC_FLUX_HLL && g->flux != AMRVAC_FLUX_HLLD) { *why = "bad flux scheme"; return AMRVAC_E_ARG; }
   return AMRVAC_OK;
 }
 
@@ -574,7 +575,7 @@ void setup_shape(amrvac_ctx* c, const amrvac_grid_desc* g) {
   G.icells = (long)G.nx * G.nx * (G.ndim == 3 ? G.nx : 1);
   G.precision = g->precision;
   c->P = PhysConst{g->gamma, g->gamma - 1.0, 1.0 / (g->gamma - 1.0), g->small_density, g->small_pressure,
-                   g->fix_small_values, g->limiter};
+                   g->fix_small_values, g->limiter, g->flux};
   std::memcpy(c->fixed.prim, g->bc_fixed_prim, sizeof(c->fixed.prim));
   if (g->precision == AMRVAC_FP32_MIXED) c->path = AMRVAC_PATH_FUSED;
 }
@@ -1094,7 +1095,7 @@ int amrvac_batch_add_job(amrvac_ctx* c, const amrvac_grid_desc* g, int nb, const
   const amrvac_grid_desc& s = c->g;
   if (g->ndim != s.ndim || g->block_nx != s.block_nx || g->precision != s.precision || g->gamma != s.gamma ||
       g->small_density != s.small_density || g->small_pressure != s.small_pressure ||
-      g->fix_small_values != s.fix_small_values || g->limiter != s.limiter ||
+      g->fix_small_values != s.fix_small_values || g->limiter != s.limiter || g->flux != s.flux ||
       std::memcmp(g->bc_fixed_prim, s.bc_fixed_prim, sizeof(s.bc_fixed_prim)) != 0)
     return fail(c, AMRVAC_E_ARG, "job shape or physics differs from the batch");
   if (nb < 1 || !level || !ijk || !prim_dev || nsteps < 0) return fail(c, AMRVAC_E_ARG, "bad job arguments");

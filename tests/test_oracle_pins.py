@@ -781,3 +781,168 @@ def test_limiter_uniform_and_conservation(orc, lim, name, ndim):
     t1 = _totals(w, sim.cons())
     rel = np.abs(t1 - t0) / _scale(w, u0)
     assert np.all(rel[[RHO, VX, VY, VZ, PR, BX, BY, BZ]] < 1e-13), rel
+
+
+# ---------------------------------------------------------------------------
+# HLLD (Miyoshi and Kusano 2005) with the GLM interface values
+
+
+def _rand_state(r):
+    return np.array([r.uniform(0.5, 2.0), r.uniform(-0.5, 0.5), r.uniform(-0.5, 0.5), r.uniform(-0.5, 0.5),
+                     r.uniform(0.3, 2.0), r.uniform(-1.5, 1.5), r.uniform(-1.5, 1.5), r.uniform(-1.5, 1.5), 0.0])
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_hlld_consistency_and_upwinding(orc, d):
+    """F(U, U) = F(U); every wave moving one way gives exactly the upwind
+    physical flux (seven HLLD components; B_n and psi are the GLM values)."""
+    r = rng(31)
+    for _ in range(200):
+        w = _rand_state(r)
+        F = orc.face_flux(w, w, d, 1.3, G53, flux=1)
+        P = orc.phys_flux(w, d, G53)
+        comps = [q for q in range(NV) if q not in (BX + d, PSI)]
+        np.testing.assert_allclose(F[comps], P[comps], rtol=1e-13, atol=1e-14)
+        wl, wr = _rand_state(r), _rand_state(r)
+        wl[1 + d] = wr[1 + d] = 12.0  # far beyond every fast speed
+        wr[BX + d] = wl[BX + d]
+        F = orc.face_flux(wl, wr, d, 1.3, G53, flux=1)
+        assert np.array_equal(F[comps], orc.phys_flux(wl, d, G53)[comps])
+
+
+def _contact(r, d, u):
+    wl = _rand_state(r)
+    wl[1 + d] = u
+    wr = wl.copy()
+    wr[RHO] = wl[RHO] * r.uniform(0.2, 5.0)
+    return wl, wr
+
+
+def _rotational(r, d, family, s):
+    """An isolated rotational (Alfven) discontinuity of the left (-1) or
+    right (+1) family moving at speed s: rho, p, u_n, B_n and |B_t| equal on
+    both sides, B_t rotated, [v_t] = -family sign(B_n) [B_t] / sqrt(rho)."""
+    w = _rand_state(r)
+    rho, bn = w[RHO], w[BX + d]
+    if abs(bn) < 0.3:
+        bn = 0.3 if bn >= 0 else -0.3
+        w[BX + d] = bn
+    ca = abs(bn) / math.sqrt(rho)
+    w[1 + d] = s - family * ca  # the wave speed u + family c_A equals s
+    t = [j for j in range(3) if j != d]
+    wl, wr = w.copy(), w.copy()
+    ang = r.uniform(0.3, 3.0)
+    b1, b2 = w[BX + t[0]], w[BX + t[1]]
+    wr[BX + t[0]] = b1 * math.cos(ang) - b2 * math.sin(ang)
+    wr[BX + t[1]] = b1 * math.sin(ang) + b2 * math.cos(ang)
+    for k in range(2):
+        db = wr[BX + t[k]] - wl[BX + t[k]]
+        wr[1 + t[k]] = wl[1 + t[k]] - family * math.copysign(1.0, bn) * db / math.sqrt(rho)
+    return wl, wr
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_hlld_resolves_isolated_contacts_and_rotational_discontinuities(orc, d):
+    """The defining property of HLLD: an isolated contact or rotational
+    discontinuity gets exactly the upwind physical flux (that of the side the
+    discontinuity moves away from), whatever its speed, where HLL adds
+    numerical diffusion."""
+    r = rng(32)
+    comps = [q for q in range(NV) if q not in (BX + d, PSI)]
+    hll_miss = 0.0
+    for case in range(120):
+        s = r.uniform(-0.4, 0.4)
+        if case % 3 == 0:
+            wl, wr = _contact(r, d, s)
+        else:
+            wl, wr = _rotational(r, d, -1 if case % 3 == 1 else 1, s)
+        # sanity: the pair satisfies the jump conditions at speed s
+        Ul, Ur = orc.prim_to_cons(wl, G53), orc.prim_to_cons(wr, G53)
+        Fl, Fr = orc.phys_flux(wl, d, G53), orc.phys_flux(wr, d, G53)
+        np.testing.assert_allclose((Fr - Fl)[comps], s * (Ur - Ul)[comps], rtol=1e-12, atol=1e-12)
+        exact = Fl if s > 0 else Fr
+        F = orc.face_flux(wl, wr, d, 1.3, G53, flux=1)
+        np.testing.assert_allclose(F[comps], exact[comps], rtol=1e-11, atol=1e-12)
+        H = orc.face_flux(wl, wr, d, 1.3, G53, flux=0)
+        hll_miss = max(hll_miss, np.max(np.abs(H - exact)[comps]))
+    assert hll_miss > 1e-2
+
+
+def test_hlld_alfven_wave_beats_hll(orc):
+    """The smooth linear Alfven wave with HLLD converges at second order
+    with less error than with HLL."""
+    def err(n, flux):
+        w = inputs.alfven_wave(n, 2)
+        w.flux = flux
+        sim = orc.OracleSim(w)
+        sim.steps_to_time(1.0 / math.sqrt(2.0))
+        e = np.mean(np.abs(sim.cons()[:, BZ] - w.prim[:, BZ])) / 1e-6
+        sim.close()
+        return e
+    e64, e128 = err(64, 1), err(128, 1)
+    assert math.log2(e64 / e128) >= 1.8, (e64, e128)
+    assert e128 < 0.85 * err(128, 0), e128  # measured 0.73: the reconstruction error dominates here
+
+
+def test_hlld_sod(orc):
+    """Pure hydro (B = 0): L1(rho) against the exact Riemann solution
+    converges at order >= 0.6 and is below HLL's (the contact is sharper)."""
+    import exact_riemann as er
+
+    def l1(n, flux):
+        w = inputs.sod(n, ndim=2)
+        w.flux = flux
+        sim = orc.OracleSim(w)
+        sim.steps_to_time(0.2)
+        g = inputs.blocks_to_global(sim.cons().swapaxes(0, 1), 2, w.nx, w.base_blocks)[RHO]
+        sim.close()
+        ex = er.cell_average_density(n, 0.2, 0.5, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+        return np.mean(np.abs(g[0] - ex))
+    ns = [64, 128, 256]
+    errs = [l1(n, 1) for n in ns]
+    assert min(math.log2(errs[i] / errs[i + 1]) for i in range(2)) >= 0.6, errs
+    assert all(e < l1(n, 0) for e, n in zip(errs, ns)), errs
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_hlld_uniform_and_conservation(orc, ndim):
+    w = inputs.uniform_state(ndim, (3, 2, 2), _uniform_w())
+    w.flux = 1
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    sim.steps(3)
+    assert np.array_equal(sim.cons(), u0)
+    w = inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5 if ndim == 2 else 7)
+    w.flux = 1
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    t0 = _totals(w, u0)
+    sim.steps(3 if ndim == 3 else 10)
+    t1 = _totals(w, sim.cons())
+    rel = np.abs(t1 - t0) / _scale(w, u0)
+    assert np.all(rel[[RHO, VX, VY, VZ, PR, BX, BY, BZ]] < 1e-13), rel
+
+
+def test_hlld_conditioning_on_the_low_beta_sheet(orc):
+    """Roundoff amplification on the beta = 0.01 current sheet (32^3, 10
+    steps): a one-ulp raise of the input moves HLL's result by at most about
+    1e-12 (psi, which starts at zero) but HLLD's by several times more, since
+    HLLD's star states divide by rho (S - u)(S - S_M) - B_n^2, which nearly
+    vanishes where the fast and Alfven speeds almost coincide (B_t ~ 1e-4
+    away from the sheet).  The HLLD parity test on this case is held to ten
+    times this floor."""
+    floors = []
+    for flux in (0, 1):
+        w = inputs.current_sheet(32, nsteps=10)
+        w.flux = flux
+        a = orc.OracleSim(w)
+        a.steps(10)
+        wp = inputs.current_sheet(32, nsteps=10)
+        wp.flux = flux
+        wp.prim = np.nextafter(wp.prim, np.inf)
+        b = orc.OracleSim(wp)
+        b.steps(10)
+        ua, ub = a.cons(), b.cons()
+        floors.append(np.array([np.sum(np.abs(ub[:, q] - ua[:, q])) / np.sum(np.abs(ua[:, q])) for q in range(NV)]))
+    assert np.max(floors[0][:PSI]) < 1e-13 and floors[0][PSI] < 2e-12, floors[0]
+    assert np.max(floors[1]) > 2 * np.max(floors[0]), floors
