@@ -31,33 +31,33 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
                   "paper_2303_03026_amd/csrc/kernels.h", "paper_2303_03026_amd/csrc/runtime.cpp")
 MEASURED_TRAFFIC = {
-    ("888a6bfbae904141", "f64"): {
-        (1, 0, 0): ((2854456, 1180272), (3636666, 1180173)),
-        (1, 0, 1): ((2713068, 1180119), (3562262, 1180301)),
-        (1, 1, 0): ((2860809, 1180018), (3648858, 1180384)),
-        (1, 1, 1): ((2698450, 1180006), (3556036, 1180410)),
-        (2, 0, 0): ((3077022, 1179881), (3870654, 1180149)),
-        (2, 0, 1): ((2944293, 1179952), (3801956, 1180218)),
-        (2, 1, 0): ((3080715, 1179951), (3863486, 1180267)),
-        (2, 1, 1): ((2932507, 1179991), (3775964, 1180374)),
-        (4, 0, 0): ((3515989, 1179738), (4310477, 1179809)),
-        (4, 0, 1): ((3171074, 1179762), (4043540, 1179822)),
-        (4, 1, 0): ((3516884, 1179748), (4305657, 1179837)),
-        (4, 1, 1): ((3157870, 1179774), (4058107, 1179851)),
+    ("419e65d90b3727cd", "f64"): {
+        (1, 0, 0): ((2854788, 1180193), (3636289, 1180191)),
+        (1, 0, 1): ((2714547, 1180115), (3560473, 1180268)),
+        (1, 1, 0): ((2859788, 1180036), (3645293, 1180425)),
+        (1, 1, 1): ((2697721, 1180027), (3552230, 1180479)),
+        (2, 0, 0): ((3058496, 1179932), (3850194, 1180132)),
+        (2, 0, 1): ((2945101, 1179940), (3802535, 1180154)),
+        (2, 1, 0): ((3078675, 1179925), (3861019, 1180223)),
+        (2, 1, 1): ((2930461, 1179969), (3782944, 1180302)),
+        (4, 0, 0): ((3511628, 1179727), (4302220, 1179847)),
+        (4, 0, 1): ((3165760, 1179755), (4043193, 1179817)),
+        (4, 1, 0): ((3520354, 1179781), (4303124, 1179841)),
+        (4, 1, 1): ((3149653, 1179769), (4073182, 1179840)),
     },
-    ("888a6bfbae904141", "mixed"): {
-        (1, 0, 0): ((1715068, 819481), (2180635, 819500)),
-        (1, 0, 1): ((1569338, 819484), (2074791, 819529)),
-        (1, 1, 0): ((1709294, 819455), (2175942, 819643)),
-        (1, 1, 1): ((1569191, 819486), (2073226, 819709)),
-        (2, 0, 0): ((1825990, 819350), (2301521, 819468)),
-        (2, 0, 1): ((1703195, 819342), (2212812, 819441)),
-        (2, 1, 0): ((1830320, 819413), (2302729, 819528)),
-        (2, 1, 1): ((1708012, 819409), (2216438, 819532)),
-        (4, 0, 0): ((2096305, 819252), (2557316, 819356)),
-        (4, 0, 1): ((1825201, 819230), (2365479, 819345)),
-        (4, 1, 0): ((2100570, 819265), (2563254, 819368)),
-        (4, 1, 1): ((1828384, 819238), (2366534, 819339)),
+    ("419e65d90b3727cd", "mixed"): {
+        (1, 0, 0): ((1712810, 819472), (2186679, 819517)),
+        (1, 0, 1): ((1569941, 819438), (2072822, 819593)),
+        (1, 1, 0): ((1707001, 819455), (2173182, 819696)),
+        (1, 1, 1): ((1569254, 819462), (2073239, 819703)),
+        (2, 0, 0): ((1825204, 819362), (2303265, 819463)),
+        (2, 0, 1): ((1703662, 819357), (2212146, 819443)),
+        (2, 1, 0): ((1835171, 819392), (2306934, 819542)),
+        (2, 1, 1): ((1709562, 819388), (2214669, 819571)),
+        (4, 0, 0): ((2097072, 819237), (2558576, 819356)),
+        (4, 0, 1): ((1822827, 819235), (2366772, 819344)),
+        (4, 1, 0): ((2100911, 819260), (2561769, 819366)),
+        (4, 1, 1): ((1825759, 819242), (2365061, 819358)),
     },
 }
 FETCH_CAL, WRITE_CAL = 2.0, 1.0
