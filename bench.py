@@ -15,6 +15,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -102,6 +104,8 @@ def parse():
     ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud"], default="random_modes")
     ap.add_argument("--limiter", choices=["vanleer", "koren", "cada3"], default="vanleer")
     ap.add_argument("--flux", choices=["hll", "hlld"], default="hll")
+    ap.add_argument("--regrid", action="store_true",
+                    help="also time one regrid (coarsen the top level, refine every eighth block below)")
     ap.add_argument("--tune", default="auto",
                     help="fused-stage launch shape: 'auto' (autotuner, before the warmup), 'default', or z,r,x")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -263,6 +267,25 @@ def main():
         torch.cuda.synchronize()
         graph_ms = (time.perf_counter() - g0) * 1e3 / K
         sim.sync_flags()
+    regrid = None
+    if args.regrid:
+        # one regrid of the current state: coarsen every top-level sibling
+        # set, refine every eighth block of the level below (2:1 restored)
+        top = int(w.level.max())
+        flags = np.where(w.level == top, -1, np.where((w.level == top - 1) & (np.arange(w.nblocks) % 8 == 0), 1, 0))
+        lv, ij = sim.regrid_plan(flags)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            r0 = time.perf_counter()
+            new = sim.regrid(lv, ij)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - r0) * 1e3)
+            new.close()
+        regrid = {"ms": min(times), "blocks_in": int(w.nblocks), "blocks_out": int(len(lv)),
+                  "cells_out": int(len(lv)) * w.nx ** 3,
+                  "what": "amrvac_regrid wall time (new context, tables, ghost fill of the old slot, "
+                          "transfer kernel, stream sync), best of 3"}
     sim.close()
 
     out = {
@@ -287,6 +310,7 @@ def main():
         "autotune_ms_per_launch": {"%d,%d,%d" % k: round(v, 4) for k, v in tune_times.items()},
         "algorithmic_hbm_gbs_per_step": cells * 8 * state_bytes / (ms_per_step * 1e-3) / 1e9,
         "graph_ms_per_step": graph_ms,
+        "regrid": regrid,
         "stage_ms": [sum(x) / K for x in stage_ms],
         "roofline": {"bound": "hbm", "kernel": "stage (%s path)" % args.path, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

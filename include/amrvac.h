@@ -198,6 +198,39 @@ int amrvac_combine(amrvac_ctx* c, int a_slot, int b_slot, double coef, int out_s
  * first use and replays it.  No host synchronisation. */
 int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph);
 
+/* ---------------------------------------------------------------------------
+ * Regrid: change a single-job context's leaf set (the block-based AMR of the
+ * "Open source strategy" section, with refinement ratio 2), each block
+ * changing by at most one level.
+ * -------------------------------------------------------------------------*/
+
+/* Plan a new leaf set (host only; no context, no device work) from the
+ * grid g and its current leaf set (nb blocks: level, ijk as in
+ * amrvac_init_blocks): refine the blocks with flags[b] > 0 (levels capped
+ * at max_level), restore 2:1 nesting over faces, edges and corners by
+ * refining leaves that became two levels coarser than a neighbour, then
+ * coarsen every complete set of 2^ndim sibling leaves that are all flagged
+ * < 0, where the parent would not sit next to a leaf two levels finer.
+ * Writes nb_new, and, when cap >= nb_new, the new blocks' levels and
+ * positions (ijk_out: 3 ints per block) in (level, i, j, k) order;
+ * AMRVAC_E_NOMEM (with nb_new set) when cap is too small, AMRVAC_E_ARG for
+ * an invalid grid or leaf set (message in amrvac_last_error(NULL)). */
+int amrvac_regrid_plan(const amrvac_grid_desc* g, int nb, const int* level, const int* ijk, const int* flags,
+                       int max_level, int cap, int* nb_new, int* level_out, int* ijk_out);
+
+/* Move the state in slot to a new leaf set and return a new context on
+ * caller-owned slots for it (nslots slots of amrvac_slot_bytes(nb) bytes;
+ * the state lands in its slot 0), with the old context's grid, path, launch
+ * shape and stream.  Every new block must be an old block (copied), a child
+ * of an old leaf (conservative linear prolongation: the parent value plus a
+ * quarter of the minmod-limited parent slope per direction, as for the
+ * ghost cells) or the parent of 2^ndim old leaves (their volume average,
+ * pairwise sums); otherwise AMRVAC_E_ARG.  The old slot's ghost cells are
+ * filled on the way; the old context is left usable and is not destroyed.
+ * Synchronises the stream. */
+int amrvac_regrid(amrvac_ctx* c, int slot, int nb, const int* level, const int* ijk, void* const* slots, int nslots,
+                  amrvac_ctx** out);
+
 /* Select the stage implementation: AMRVAC_PATH_PLAIN (separate primitive,
  * per-direction flux, reflux and update kernels; FP64 only, the default for
  * FP64 contexts) or AMRVAC_PATH_FUSED (one kernel per stage plus, on AMR

@@ -941,6 +941,68 @@ void* oracle_create(const oracle_params* p, int nblocks, const int* level, const
 
 void oracle_destroy(void* h) { delete static_cast<Sim*>(h); }
 
+// Regrid: a new simulation on another leaf set whose every block is a block
+// of the old one, a child of an old leaf (refinement) or the parent of 2^d
+// old leaves (coarsening).  Its state: copies of unchanged blocks; for a
+// child, the conservative linear prolongation of its parent (parent value
+// plus a quarter of the minmod-limited slope per direction, the slope
+// neighbours taken from the parent's ghost-filled block); for a parent, the
+// volume average of its children (the restriction of the ghost fill).  The
+// old simulation's state slot 0 has its ghosts filled as a side effect.
+void* oracle_regrid(void* h, int nblocks, const int* level, const int* ijk) {
+  try {
+    Sim* o = static_cast<Sim*>(h);
+    o->fill_ghosts(o->S0);
+    const int nd = o->ndim;
+    const long nxo = o->nx;
+    std::vector<double> zero((size_t)nblocks * NV * (size_t)o->icells, 0.0);
+    Sim* s = build_sim(&o->P, nblocks, level, ijk, zero.data());
+    const long kmax = nd == 3 ? nxo : 1;
+    for (int b = 0; b < nblocks; ++b) {
+      const int l = level[b];
+      const Idx bi{ijk[3 * b], ijk[3 * b + 1], nd > 2 ? ijk[3 * b + 2] : 0};
+      const Key same{l, bi[0], bi[1], bi[2]};
+      const Key par{l - 1, bi[0] >> 1, bi[1] >> 1, bi[2] >> 1};
+      auto it = o->leaf.find(same);
+      auto ip = l > 1 ? o->leaf.find(par) : o->leaf.end();
+      const bool coarsened = o->refined.count(same) > 0;
+      if (it == o->leaf.end() && ip == o->leaf.end() && !coarsened)
+        throw std::invalid_argument("regrid block is not an old block, child or parent of old leaves");
+      for (long k = 0; k < kmax; ++k)
+        for (long j = 0; j < nxo; ++j)
+          for (long i = 0; i < nxo; ++i) {
+            const long c = s->pidx(i, j, k);
+            const Idx g{bi[0] * nxo + i, bi[1] * nxo + j, nd > 2 ? bi[2] * nxo + k : 0};
+            Cell v;
+            if (it != o->leaf.end()) {
+              v = o->S0[it->second][o->pidx(i, j, k)];
+            } else if (ip != o->leaf.end()) {
+              const BlockData& P = o->S0[ip->second];
+              const Idx lc{(g[0] >> 1) - par.i * nxo, (g[1] >> 1) - par.j * nxo, nd > 2 ? (g[2] >> 1) - par.k * nxo : 0};
+              const Cell uc = P[o->pidx(lc)];
+              v = uc;
+              for (int d = 0; d < nd; ++d) {
+                Idx lo = lc, hi = lc;
+                lo[d] -= 1;
+                hi[d] += 1;
+                const Cell& um = P[o->pidx(lo)];
+                const Cell& up = P[o->pidx(hi)];
+                const double sg = (g[d] & 1) ? 0.25 : -0.25;
+                for (int q = 0; q < NV; ++q) v.v[q] = v.v[q] + sg * minmod(uc.v[q] - um.v[q], up.v[q] - uc.v[q]);
+              }
+            } else {
+              v = o->restrict_cell(o->S0, l, g);
+            }
+            s->S0[b][c] = v;
+          }
+    }
+    return s;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return nullptr;
+  }
+}
+
 // Advance nsteps full SSPRK steps; diag receives (dt, c_h, kappa, flags) per
 // step.  Returns 0, or -1 on an exception (message in oracle_last_error), or
 // -4 if a step met a non-physical state or an invalid dt (the run stops there).

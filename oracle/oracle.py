@@ -47,6 +47,8 @@ def lib():
         _lib.oracle_create.restype = ctypes.c_void_p
         _lib.oracle_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ip, ip, dp]
         _lib.oracle_destroy.argtypes = [ctypes.c_void_p]
+        _lib.oracle_regrid.restype = ctypes.c_void_p
+        _lib.oracle_regrid.argtypes = [ctypes.c_void_p, ctypes.c_int, ip, ip]
         _lib.oracle_steps.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
         _lib.oracle_steps_to_time.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
         _lib.oracle_euler_stage.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -131,6 +133,24 @@ class OracleSim:
         if not self.h:
             raise ValueError("oracle_create: " + lib().oracle_last_error().decode())
         self.shape = (len(self.level), NV) + (w.nx,) * w.ndim
+
+    def regrid(self, level, ijk) -> "OracleSim":
+        """A new simulation on the leaf set (level, ijk), every block of which
+        is an old block, a child of an old leaf or the parent of old leaves,
+        holding the old state copied, prolonged or restricted
+        (oracle_regrid)."""
+        import dataclasses
+        level = np.ascontiguousarray(level, dtype=np.int32)
+        ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
+        w = dataclasses.replace(self.w, level=level, ijk=ijk,
+                                prim=np.zeros((len(level), NV) + (self.w.nx,) * self.w.ndim))
+        new = OracleSim.__new__(OracleSim)
+        new.w, new.params, new.level, new.ijk = w, self.params, level, ijk
+        new.h = lib().oracle_regrid(self.h, len(level), _ip(level), _ip(ijk))
+        if not new.h:
+            raise ValueError("oracle_regrid: " + lib().oracle_last_error().decode())
+        new.shape = (len(level), NV) + (w.nx,) * w.ndim
+        return new
 
     def close(self):
         if self.h:

@@ -29,7 +29,8 @@ ABI_SYMBOLS = ("amrvac_slot_bytes", "amrvac_init_blocks", "amrvac_set_primitive"
                "amrvac_sync_flags", "amrvac_reset_flags", "amrvac_last_error", "amrvac_destroy",
                "amrvac_batch_create", "amrvac_batch_add_job", "amrvac_batch_step", "amrvac_batch_job_info",
                "amrvac_batch_get_job", "amrvac_batch_remove_job", "amrvac_batch_free_blocks",
-               "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune", "amrvac_stage_cfl", "amrvac_combine")
+               "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune", "amrvac_stage_cfl", "amrvac_combine",
+               "amrvac_regrid_plan", "amrvac_regrid")
 TUNE_MAX_CANDIDATES = 12
 SLOT_LEAD_FP64 = 16  # bytes before the first block of an FP64 slot
 
@@ -93,6 +94,10 @@ def load_library():
     lib.amrvac_stage.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
     lib.amrvac_stage_cfl.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
     lib.amrvac_combine.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+    lib.amrvac_regrid_plan.argtypes = [ctypes.POINTER(GridDesc), ctypes.c_int, ip, ip, ip, ctypes.c_int, ctypes.c_int,
+                                       ip, ip, ip]
+    lib.amrvac_regrid.argtypes = [vp, ctypes.c_int, ctypes.c_int, ip, ip, ctypes.POINTER(vp), ctypes.c_int,
+                                  ctypes.POINTER(vp)]
     lib.amrvac_advance.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.amrvac_set_path.argtypes = [vp, ctypes.c_int]
     lib.amrvac_sync_flags.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong), dp]
@@ -135,6 +140,32 @@ def make_desc(w, precision: int = FP64) -> GridDesc:
     g.limiter = int(getattr(w, "limiter", LIM_VANLEER))
     g.flux = int(getattr(w, "flux", FLUX_HLL))
     return g
+
+
+def regrid_plan(w, flags, max_level: int = 12, precision: int = FP64, level=None, ijk=None):
+    """New leaf set (level, ijk) for workload w's grid from per-block flags:
+    > 0 refine, < 0 coarsen (complete sibling sets only), 0 keep; 2:1 nesting
+    restored (amrvac_regrid_plan; host only, no device needed)."""
+    lib = load_library()
+    desc = make_desc(w, precision)
+    level = np.ascontiguousarray(w.level if level is None else level, dtype=np.int32).reshape(-1)
+    ijk = np.ascontiguousarray(w.ijk if ijk is None else ijk, dtype=np.int32).reshape(-1, 3)
+    flags = np.ascontiguousarray(flags, dtype=np.int32).reshape(-1)
+    if flags.shape[0] != level.shape[0]:
+        raise ValueError("one flag per block")
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))  # noqa: E731
+    nb_new = ctypes.c_int()
+    rc = lib.amrvac_regrid_plan(ctypes.byref(desc), len(level), P(level), P(ijk), P(flags), max_level, 0,
+                                ctypes.byref(nb_new), None, None, None)
+    if rc not in (0, E_NOMEM):
+        raise AmrvacError(rc, lib.amrvac_last_error(None).decode())
+    lv = np.empty(nb_new.value, dtype=np.int32)
+    ij = np.empty((nb_new.value, 3), dtype=np.int32)
+    rc = lib.amrvac_regrid_plan(ctypes.byref(desc), len(level), P(level), P(ijk), P(flags), max_level, nb_new.value,
+                                ctypes.byref(nb_new), P(lv), P(ij))
+    if rc != 0:
+        raise AmrvacError(rc, lib.amrvac_last_error(None).decode())
+    return lv, ij
 
 
 class Simulation:
@@ -268,6 +299,39 @@ class Simulation:
     def combine(self, a_slot: int, b_slot: int, coef: float, out_slot: int):
         """out = a + coef (b - a) on the leaf interior cells (amrvac_combine)."""
         self._check(self.lib.amrvac_combine(self.ctx, a_slot, b_slot, coef, out_slot), self.ctx)
+
+    def regrid_plan(self, flags, max_level: int = 12):
+        """New leaf set (level, ijk) from per-block flags (see regrid_plan)."""
+        return regrid_plan(self.w, flags, max_level, precision=self.desc.precision, level=self.level, ijk=self.ijk)
+
+    def regrid(self, level, ijk, slot: int = 0, nslots: Optional[int] = None) -> "Simulation":
+        """A new Simulation on the leaf set (level, ijk) holding the state of
+        slot moved over (copied, prolonged or restricted per block;
+        amrvac_regrid).  This one stays usable."""
+        import dataclasses
+        torch = self.torch
+        level = np.ascontiguousarray(level, dtype=np.int32).reshape(-1)
+        ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
+        nslots = len(self.slots) if nslots is None else nslots
+        new = Simulation.__new__(Simulation)
+        new.torch, new.lib, new.device, new.stream, new.desc = torch, self.lib, self.device, self.stream, self.desc
+        new.w = dataclasses.replace(self.w, level=level, ijk=ijk,
+                                    prim=np.zeros((len(level), NV) + (self.w.nx,) * self.w.ndim))
+        new.nb = len(level)
+        size = ctypes.c_size_t()
+        self._check(self.lib.amrvac_slot_bytes(ctypes.byref(self.desc), new.nb, ctypes.byref(size)), None)
+        new.slot_bytes = size.value
+        with torch.cuda.stream(self.stream):
+            new.slots = [torch.empty(new.slot_bytes, dtype=torch.uint8, device=self.device) for _ in range(nslots)]
+            new.scal = torch.zeros(4, dtype=torch.float64, device=self.device)
+        new.level, new.ijk = level, ijk
+        ptrs = (ctypes.c_void_p * nslots)(*[t.data_ptr() for t in new.slots])
+        ctx = ctypes.c_void_p()
+        self._check(self.lib.amrvac_regrid(self.ctx, slot, new.nb, level.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                           ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ptrs, nslots,
+                                           ctypes.byref(ctx)), self.ctx)
+        new.ctx = ctx
+        return new
 
     def euler_stage(self, in_slot: int = 0, out_slot: int = 1):
         self.fill(in_slot)

@@ -109,6 +109,12 @@ hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables
                                  const int* tasks, const int first[3], const int count[3], const void* in,
                                  void* out, double w, const PhysConst& P);
 
+// regrid transfer tasks: kind, new block, up to 8 sources (see k_regrid)
+enum { REGRID_COPY = 0, REGRID_PROLONG = 1, REGRID_RESTRICT = 2 };
+constexpr int REGRID_TASK_INTS = 10;
+hipError_t launch_regrid(hipStream_t s, const GridConst& G, const Tables& Told, const int* tasks, int ntasks,
+                         const void* old_slot, void* new_slot);
+
 // out = a + coef (b - a) on the leaf interior cells of the active blocks
 hipError_t launch_combine(hipStream_t s, const GridConst& G, const Tables& T, const void* a, const void* b,
                           double coef, void* out);

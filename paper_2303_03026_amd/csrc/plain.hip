@@ -464,6 +464,104 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, J
 }
 
 // ---------------------------------------------------------------------------
+// Regrid transfer: one thread per interior cell of a block of the new leaf
+// set.  Tasks are REGRID_TASK_INTS ints: kind, new block, sources.
+//   COPY:     s0 = the same block in the old set;
+//   PROLONG:  s0 = the old parent, s1..s3 = the child's octant (x, y, z):
+//             parent cell plus a quarter of the minmod-limited slope per
+//             direction towards the child's side; slope neighbours outside
+//             the parent come from a same-level neighbour's interior in
+//             place, else from the parent's own ghost cells (filled before);
+//   RESTRICT: s0..s7 = the old children by octant x + 2y + 4z: the pairwise
+//             mean of the 2^d cells under the new cell.
+
+template <int NDIM, class SP>
+__global__ void __launch_bounds__(256) k_regrid(GridConst G, Tables Told, const int* __restrict__ tasks, int ntasks,
+                                               const void* __restrict__ old_slot, void* __restrict__ new_slot) {
+  const int* __restrict__ link = Told.link;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)ntasks * G.icells) return;
+  const int tk = (int)(gid / G.icells);
+  const int c = (int)(gid - (long)tk * G.icells);
+  const int* T = tasks + (long)tk * REGRID_TASK_INTS;
+  const int kind = T[0];
+  const int nx = G.nx;
+  const long pc = G.pcells;
+  const int i = c % nx, j = (c / nx) % nx, k = NDIM == 3 ? c / (nx * nx) : 0;
+  const long di = pidx_n<NDIM>(G, i, j, k);
+  double out[NV];
+  if (kind == REGRID_COPY) {
+    const void* src = block_ptr<SP>(old_slot, T[2], pc);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] = SP::ld(src, q, di, pc);
+  } else if (kind == REGRID_PROLONG) {
+    const int pb = T[2];
+    const int o[3] = {T[3], T[4], T[5]};
+    const int g[3] = {o[0] * nx + i, o[1] * nx + j, o[2] * nx + k};
+    int lc[3] = {g[0] >> 1, g[1] >> 1, NDIM == 3 ? g[2] >> 1 : 0};
+    const void* src = block_ptr<SP>(old_slot, pb, pc);
+    const long i0 = pidx_n<NDIM>(G, lc[0], lc[1], lc[2]);
+    int lk[2 * NDIM], ln[2 * NDIM];
+#pragma unroll
+    for (int f = 0; f < 2 * NDIM; ++f) {
+      lk[f] = link[((long)pb * 6 + f) * LINK_INTS];
+      ln[f] = link[((long)pb * 6 + f) * LINK_INTS + 1];
+    }
+    int bm[3], bp[3];
+    long im[3], ip[3];
+#pragma unroll
+    for (int ax = 0; ax < NDIM; ++ax) {
+      int m[3] = {lc[0], lc[1], lc[2]}, p[3] = {lc[0], lc[1], lc[2]};
+      m[ax] -= 1;
+      p[ax] += 1;
+      bm[ax] = pb;
+      bp[ax] = pb;
+      if (m[ax] < 0 && lk[2 * ax] == LINK_SAME) {
+        bm[ax] = ln[2 * ax];
+        m[ax] += nx;
+      }
+      if (p[ax] >= nx && lk[2 * ax + 1] == LINK_SAME) {
+        bp[ax] = ln[2 * ax + 1];
+        p[ax] -= nx;
+      }
+      im[ax] = pidx_n<NDIM>(G, m[0], m[1], m[2]);
+      ip[ax] = pidx_n<NDIM>(G, p[0], p[1], p[2]);
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double uc = SP::ld(src, q, i0, pc);
+      double r = uc;
+#pragma unroll
+      for (int ax = 0; ax < NDIM; ++ax) {
+        const double sg = (g[ax] & 1) ? 0.25 : -0.25;
+        const double um = SP::ld(block_ptr<SP>(old_slot, bm[ax], pc), q, im[ax], pc);
+        const double up = SP::ld(block_ptr<SP>(old_slot, bp[ax], pc), q, ip[ax], pc);
+        r = r + sg * minmod2(uc - um, up - uc);
+      }
+      out[q] = r;
+    }
+  } else {  // REGRID_RESTRICT
+    const int ox = 2 * i >= nx, oy = 2 * j >= nx, oz = NDIM == 3 && 2 * k >= nx;
+    const void* src = block_ptr<SP>(old_slot, T[2 + ox + 2 * oy + 4 * oz], pc);
+    const int fi = 2 * i - ox * nx, fj = 2 * j - oy * nx, fk = NDIM == 3 ? 2 * k - oz * nx : 0;
+    const long i000 = pidx_n<NDIM>(G, fi, fj, fk);
+    const long sy = G.pn, sz = (long)G.pn * G.pn;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      auto v = [&](int e, int bb, int aa) { return SP::ld(src, q, i000 + e * sz + bb * sy + aa, pc); };
+      if (NDIM == 2)
+        out[q] = ((v(0, 0, 0) + v(0, 0, 1)) + (v(0, 1, 0) + v(0, 1, 1))) * 0.25;
+      else
+        out[q] = (((v(0, 0, 0) + v(0, 0, 1)) + (v(0, 1, 0) + v(0, 1, 1))) +
+                  ((v(1, 0, 0) + v(1, 0, 1)) + (v(1, 1, 0) + v(1, 1, 1)))) * 0.125;
+    }
+  }
+  void* dst = block_ptr<SP>(new_slot, T[1], pc);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) SP::st(dst, q, di, pc, out[q]);
+}
+
+// ---------------------------------------------------------------------------
 // out = a + coef (b - a) on the leaf interior cells, one thread per cell.
 // Both loads of a cell come before its store, so out may be a or b.
 
@@ -716,6 +814,25 @@ hipError_t launch_cfl(hipStream_t s, const GridConst& G, const Tables& T, const 
   hipError_t e = launch_cfl_accumulate(s, G, T, slot, P, st, C);
   if (e != hipSuccess) return e;
   return launch_cfl_finalize(s, st, C);
+}
+
+hipError_t launch_regrid(hipStream_t s, const GridConst& G, const Tables& Told, const int* tasks, int ntasks,
+                         const void* old_slot, void* new_slot) {
+  const long n = (long)ntasks * G.icells;
+  if (n <= 0) return hipSuccess;
+  const unsigned nbk = nblocks_for(n, 256);
+  if (G.ndim == 3) {
+    if (G.precision == 0)
+      k_regrid<3, StoreF64><<<nbk, 256, 0, s>>>(G, Told, tasks, ntasks, old_slot, new_slot);
+    else
+      k_regrid<3, StoreMixed><<<nbk, 256, 0, s>>>(G, Told, tasks, ntasks, old_slot, new_slot);
+  } else {
+    if (G.precision == 0)
+      k_regrid<2, StoreF64><<<nbk, 256, 0, s>>>(G, Told, tasks, ntasks, old_slot, new_slot);
+    else
+      k_regrid<2, StoreMixed><<<nbk, 256, 0, s>>>(G, Told, tasks, ntasks, old_slot, new_slot);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_combine(hipStream_t s, const GridConst& G, const Tables& T, const void* a, const void* b,

@@ -746,30 +746,12 @@ bool job_ok(const amrvac_ctx* c, int job) { return c->batch && job >= 0 && job <
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int amrvac_slot_bytes(const amrvac_grid_desc* g, int nblocks, size_t* bytes) {
-  std::string why;
-  if (check_desc(g, &why) != AMRVAC_OK || nblocks < 1 || !bytes) return AMRVAC_E_ARG;
-  *bytes = (size_t)slot_bytes_of(g, nblocks);
-  return AMRVAC_OK;
-}
-
-const char* amrvac_last_error(const amrvac_ctx* c) {
-  if (!c) return g_init_err.c_str();
-  return c->err.c_str();
-}
-
-int amrvac_destroy(amrvac_ctx* c) {
-  if (!c) return AMRVAC_E_ARG;
-  (void)hipStreamSynchronize(c->stream);
-  free_all(c);
-  delete c;
-  return AMRVAC_OK;
-}
-
-int amrvac_init_blocks(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, const int* level, const int* ijk,
-                       void* const* slots, int nslots, void* stream) {
+// A single-job context on caller-owned slots (amrvac_init_blocks, and the
+// new context of a regrid).
+int create_single(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, const int* level, const int* ijk,
+                  void* const* slots, int nslots, void* stream) {
   if (!out) return AMRVAC_E_ARG;
   *out = nullptr;
   std::string why;
@@ -818,6 +800,131 @@ int amrvac_init_blocks(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, cons
   }
   *out = c;
   return AMRVAC_OK;
+}
+
+// Leaf-set planning for a regrid (host only).  Slots of a level are block
+// positions; a slot is covered by the leaf at or above it.
+struct Planner {
+  int ndim = 2;
+  long base[3] = {1, 1, 1};
+  bool per[3] = {false, false, false};
+  std::set<KeyL> leaves;
+
+  long nblk(int l, int d) const { return d < ndim ? base[d] << (l - 1) : 1; }
+  // wrap q into the domain of level l; false outside a non-periodic side
+  bool wrap(int l, long q[3]) const {
+    for (int d = 0; d < ndim; ++d)
+      if (q[d] < 0 || q[d] >= nblk(l, d)) {
+        if (!per[d]) return false;
+        q[d] = (q[d] + nblk(l, d)) % nblk(l, d);
+      }
+    return true;
+  }
+  // level of the leaf covering slot q of level l, 0 if the slot is refined
+  int cover(int l, const long q[3]) const {
+    long p[3] = {q[0], q[1], q[2]};
+    for (int m = l; m >= 1; --m) {
+      if (leaves.count(KeyL{m, p[0], p[1], p[2]})) return m;
+      for (int d = 0; d < 3; ++d) p[d] >>= 1;
+    }
+    return 0;
+  }
+  KeyL cover_key(int l, const long q[3]) const {
+    long p[3] = {q[0], q[1], q[2]};
+    for (int m = l; m >= 1; --m) {
+      const KeyL k{m, p[0], p[1], p[2]};
+      if (leaves.count(k)) return k;
+      for (int d = 0; d < 3; ++d) p[d] >>= 1;
+    }
+    return KeyL{0, 0, 0, 0};
+  }
+  void refine(const KeyL& k) {
+    leaves.erase(k);
+    for (int cz = 0; cz < (ndim == 3 ? 2 : 1); ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) leaves.insert(KeyL{k.l + 1, 2 * k.i + cx, 2 * k.j + cy, ndim == 3 ? 2 * k.k + cz : 0});
+  }
+  template <class F>
+  void for_neighbours(const KeyL& k, F f) const {
+    for (int oz = (ndim == 3 ? -1 : 0); oz <= (ndim == 3 ? 1 : 0); ++oz)
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          if (!ox && !oy && !oz) continue;
+          long q[3] = {k.i + ox, k.j + oy, k.k + oz};
+          if (!wrap(k.l, q)) continue;
+          const long off[3] = {ox, oy, oz};
+          f(q, off);
+        }
+  }
+  // refine leaves that are two levels coarser than a neighbour of a leaf
+  void nest() {
+    for (bool changed = true; changed;) {
+      changed = false;
+      std::vector<KeyL> todo;
+      for (const KeyL& k : leaves)
+        for_neighbours(k, [&](const long q[3], const long*) {
+          const int m = cover(k.l, q);
+          if (m != 0 && m < k.l - 1) todo.push_back(cover_key(k.l, q));
+        });
+      for (const KeyL& t : todo)
+        if (leaves.count(t)) {
+          refine(t);
+          changed = true;
+        }
+    }
+  }
+  // would the leaf parent (replacing its children) be next to a leaf two
+  // levels finer?
+  bool coarsening_ok(const KeyL& par) const {
+    bool ok = true;
+    for_neighbours(par, [&](const long q[3], const long* off) {
+      if (!ok || cover(par.l, q) != 0) return;
+      // slot q is refined: its children next to par must be leaves
+      for (int cz = 0; cz < (ndim == 3 ? 2 : 1); ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+          for (int cx = 0; cx < 2; ++cx) {
+            const long cc[3] = {cx, cy, cz};
+            bool adjacent = true;
+            for (int d = 0; d < ndim; ++d) {
+              if (off[d] == 1 && cc[d] != 0) adjacent = false;
+              if (off[d] == -1 && cc[d] != 1) adjacent = false;
+            }
+            if (!adjacent) continue;
+            const long c[3] = {2 * q[0] + cx, 2 * q[1] + cy, ndim == 3 ? 2 * q[2] + cz : 0};
+            if (!leaves.count(KeyL{par.l + 1, c[0], c[1], c[2]})) ok = false;
+          }
+    });
+    return ok;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int amrvac_slot_bytes(const amrvac_grid_desc* g, int nblocks, size_t* bytes) {
+  std::string why;
+  if (check_desc(g, &why) != AMRVAC_OK || nblocks < 1 || !bytes) return AMRVAC_E_ARG;
+  *bytes = (size_t)slot_bytes_of(g, nblocks);
+  return AMRVAC_OK;
+}
+
+const char* amrvac_last_error(const amrvac_ctx* c) {
+  if (!c) return g_init_err.c_str();
+  return c->err.c_str();
+}
+
+int amrvac_destroy(amrvac_ctx* c) {
+  if (!c) return AMRVAC_E_ARG;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return AMRVAC_OK;
+}
+
+int amrvac_init_blocks(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, const int* level, const int* ijk,
+                       void* const* slots, int nslots, void* stream) {
+  return create_single(out, g, nb, level, ijk, slots, nslots, stream);
 }
 
 int amrvac_set_primitive(amrvac_ctx* c, int slot, const double* prim_dev) {
@@ -876,6 +983,146 @@ int amrvac_combine(amrvac_ctx* c, int a, int b, double coef, int out) {
   if (int rc = ensure_tables(c)) return rc;
   touch_slot(c, out);
   HIP_TRY(c, launch_combine(c->stream, c->G, c->tables(), c->slots[a], c->slots[b], coef, c->slots[out]));
+  return AMRVAC_OK;
+}
+
+int amrvac_regrid_plan(const amrvac_grid_desc* g, int nb, const int* level, const int* ijk, const int* flags,
+                       int max_level, int cap, int* nb_new, int* level_out, int* ijk_out) {
+  if (!g || !level || !ijk || !flags || !nb_new || nb < 1) return AMRVAC_E_ARG;
+  std::string why;
+  if (check_desc(g, &why) != AMRVAC_OK) { g_init_err = why; return AMRVAC_E_ARG; }
+  JobBuild J;
+  if (build_job(g, nb, level, ijk, 0, &J) != AMRVAC_OK) { g_init_err = J.err; return AMRVAC_E_ARG; }
+  Planner P;
+  P.ndim = g->ndim;
+  for (int d = 0; d < 3; ++d) {
+    P.base[d] = d < P.ndim ? g->base_blocks[d] : 1;
+    P.per[d] = d < P.ndim && g->bc_lo[d] == AMRVAC_BC_PERIODIC;
+  }
+  const int lmax = std::min(std::max(max_level, 1), MAXLEV);
+  std::map<KeyL, int> old;
+  for (int b = 0; b < nb; ++b) {
+    const KeyL k{J.level[b], J.pos[3 * b], J.pos[3 * b + 1], J.pos[3 * b + 2]};
+    old[k] = b;
+    P.leaves.insert(k);
+  }
+  for (const auto& kv : old)
+    if (flags[kv.second] > 0 && kv.first.l < lmax) P.refine(kv.first);
+  P.nest();
+  // coarsen complete sibling sets of old leaves that are all flagged, one
+  // parent at a time, where nesting allows
+  std::set<KeyL> parents;
+  for (const auto& kv : old)
+    if (flags[kv.second] < 0 && kv.first.l > 1)
+      parents.insert(KeyL{kv.first.l - 1, kv.first.i >> 1, kv.first.j >> 1, kv.first.k >> 1});
+  // (repeated until nothing changes: a set blocked by a finer neighbour set
+  // merges once that set has merged)
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (auto pit = parents.begin(); pit != parents.end();) {
+      const KeyL par = *pit;
+      std::vector<KeyL> kids;
+      bool all = true;
+      for (int cz = 0; cz < (P.ndim == 3 ? 2 : 1) && all; ++cz)
+        for (int cy = 0; cy < 2 && all; ++cy)
+          for (int cx = 0; cx < 2 && all; ++cx) {
+            const KeyL k{par.l + 1, 2 * par.i + cx, 2 * par.j + cy, P.ndim == 3 ? 2 * par.k + cz : 0};
+            auto it = old.find(k);
+            if (it == old.end() || flags[it->second] >= 0 || !P.leaves.count(k)) all = false;
+            kids.push_back(k);
+          }
+      if (!all) {
+        pit = parents.erase(pit);  // never mergeable
+        continue;
+      }
+      if (!P.coarsening_ok(par)) {
+        ++pit;
+        continue;
+      }
+      for (const KeyL& k : kids) P.leaves.erase(k);
+      P.leaves.insert(par);
+      pit = parents.erase(pit);
+      changed = true;
+    }
+  }
+  *nb_new = (int)P.leaves.size();
+  if (!level_out || !ijk_out || cap < *nb_new) return AMRVAC_E_NOMEM;
+  int n = 0;
+  for (const KeyL& k : P.leaves) {
+    level_out[n] = k.l;
+    ijk_out[3 * n] = (int)k.i;
+    ijk_out[3 * n + 1] = (int)k.j;
+    ijk_out[3 * n + 2] = (int)k.k;
+    ++n;
+  }
+  return AMRVAC_OK;
+}
+
+int amrvac_regrid(amrvac_ctx* c, int slot, int nb, const int* level, const int* ijk, void* const* slots, int nslots,
+                  amrvac_ctx** out) {
+  if (!out) return AMRVAC_E_ARG;
+  *out = nullptr;
+  if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "regrid needs a single-job context");
+  if (int rc = check_slot(c, slot)) return rc;
+  if (nb < 1 || !level || !ijk) return fail(c, AMRVAC_E_ARG, "regrid needs a block table");
+  // transfer tasks from the old leaf set
+  const JobBuild& J = c->jobs[0].t;
+  const int ndim = c->g.ndim;
+  std::map<KeyL, int> old;
+  for (int b = 0; b < (int)J.level.size(); ++b) old[KeyL{J.level[b], J.pos[3 * b], J.pos[3 * b + 1], J.pos[3 * b + 2]}] = b;
+  std::vector<int> tasks((size_t)nb * REGRID_TASK_INTS, 0);
+  for (int n = 0; n < nb; ++n) {
+    int* T = &tasks[(size_t)n * REGRID_TASK_INTS];
+    const long p[3] = {ijk[3 * n], ijk[3 * n + 1], ndim == 3 ? ijk[3 * n + 2] : 0};
+    const int l = level[n];
+    T[1] = n;
+    auto it = old.find(KeyL{l, p[0], p[1], p[2]});
+    if (it != old.end()) {
+      T[0] = REGRID_COPY;
+      T[2] = it->second;
+      continue;
+    }
+    auto ip = l > 1 ? old.find(KeyL{l - 1, p[0] >> 1, p[1] >> 1, p[2] >> 1}) : old.end();
+    if (ip != old.end()) {
+      T[0] = REGRID_PROLONG;
+      T[2] = ip->second;
+      for (int d = 0; d < 3; ++d) T[3 + d] = (int)(p[d] & 1);
+      continue;
+    }
+    T[0] = REGRID_RESTRICT;
+    for (int cz = 0; cz < (ndim == 3 ? 2 : 1); ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          auto ic = old.find(KeyL{l + 1, 2 * p[0] + cx, 2 * p[1] + cy, ndim == 3 ? 2 * p[2] + cz : 0});
+          if (ic == old.end())
+            return fail(c, AMRVAC_E_ARG, "regrid block is not an old block, a child of an old leaf or a parent of old leaves");
+          T[2 + cx + 2 * cy + 4 * cz] = ic->second;
+        }
+  }
+  amrvac_ctx* nc = nullptr;
+  if (int rc = create_single(&nc, &c->g, nb, level, ijk, slots, nslots, c->stream))
+    return fail(c, rc, "regrid: " + g_init_err);
+  nc->tune = c->tune;
+  int rc = AMRVAC_OK;
+  if (nc->path != c->path) rc = amrvac_set_path(nc, c->path);
+  if (!rc) rc = ensure_tables(c);
+  if (!rc) rc = fill_slot(c, slot);
+  int* d_tasks = nullptr;
+  const size_t bytes = tasks.size() * sizeof(int);
+  if (!rc && hipMalloc(&d_tasks, bytes) != hipSuccess) rc = fail(c, AMRVAC_E_NOMEM, "regrid task buffer");
+  if (!rc && hipMemcpyAsync(d_tasks, tasks.data(), bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    rc = fail(c, AMRVAC_E_HIP, "regrid task upload");
+  if (!rc && launch_regrid(c->stream, c->G, c->tables(), d_tasks, nb, c->slots[slot], nc->slots[0]) != hipSuccess)
+    rc = fail(c, AMRVAC_E_HIP, "regrid transfer launch");
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  if (!rc && e != hipSuccess) rc = fail(c, AMRVAC_E_HIP, std::string("regrid: ") + hipGetErrorString(e));
+  if (d_tasks) (void)hipFree(d_tasks);
+  if (rc) {
+    amrvac_destroy(nc);
+    return rc;
+  }
+  *out = nc;
   return AMRVAC_OK;
 }
 

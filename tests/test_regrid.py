@@ -1,0 +1,258 @@
+"""Regrid (the block AMR of the paper's "Open source strategy" section, ratio
+2): the leaf-set planner of the library (host code, no device needed) and
+the oracle's state transfer, pinned against what refinement and coarsening
+must preserve."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from paper_2303_03026_amd import inputs
+
+NV = 9
+RHO, VX, VY, VZ, PR, BX, BY, BZ, PSI = range(NV)
+
+
+@pytest.fixture(scope="module")
+def amr():
+    from paper_2303_03026_amd import amrvac
+    amrvac.load_library()
+    return amrvac
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def keys(level, ijk):
+    return set((int(l),) + tuple(int(x) for x in p) for l, p in zip(level, ijk))
+
+
+def check_one_level_change(ndim, old, new):
+    """Every new leaf is an old leaf, a child of one, or the parent of old
+    leaves."""
+    for (l, i, j, k) in new:
+        if (l, i, j, k) in old or (l - 1, i >> 1, j >> 1, k >> 1) in old:
+            continue
+        kids = [(l + 1, 2 * i + a, 2 * j + b, 2 * k + c if ndim == 3 else 0)
+                for a in (0, 1) for b in (0, 1) for c in ((0, 1) if ndim == 3 else (0,))]
+        assert all(kd in old for kd in kids), (l, i, j, k)
+
+
+def plan(amr, w, flags, max_level=12):
+    level, ijk = amr.regrid_plan(w, flags, max_level)
+    # the planned set is itself a valid 2:1-nested tiling (the planner
+    # validates its input, so re-planning it with no flags checks it)
+    l2, i2 = amr.regrid_plan(dataclasses.replace(w, level=level, ijk=ijk), np.zeros(len(level)), max_level)
+    assert keys(l2, i2) == keys(level, ijk)
+    return level, ijk
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_plan_without_flags_keeps_the_leaf_set(amr, ndim):
+    w = inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5)
+    level, ijk = plan(amr, w, np.zeros(w.nblocks))
+    assert keys(level, ijk) == keys(w.level, w.ijk)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_plan_refines_flagged_blocks_and_restores_nesting(amr, ndim):
+    w = inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5)
+    old = keys(w.level, w.ijk)
+    r = np.random.Generator(np.random.PCG64(7))
+    flags = (r.random(w.nblocks) < 0.25).astype(np.int32)
+    level, ijk = plan(amr, w, flags)
+    new = keys(level, ijk)
+    for b in np.nonzero(flags)[0]:
+        l, p = int(w.level[b]), w.ijk[b]
+        assert (l, int(p[0]), int(p[1]), int(p[2])) not in new  # refined
+        assert (l + 1, 2 * int(p[0]), 2 * int(p[1]), 2 * int(p[2]) if ndim == 3 else 0) in new
+    check_one_level_change(ndim, old, new)
+    assert len(new) > len(old)
+
+
+def test_plan_level_cap(amr):
+    w = inputs.smooth_amr_state(2, nb1=4, seed=5)
+    top = int(w.level.max())
+    flags = (w.level == top).astype(np.int32)
+    level, ijk = plan(amr, w, flags, max_level=top)
+    assert level.max() == top
+    level, ijk = plan(amr, w, flags, max_level=top + 1)
+    assert level.max() == top + 1
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_plan_coarsens_only_complete_flagged_sibling_sets(amr, ndim):
+    w = inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5)
+    old = keys(w.level, w.ijk)
+    flags = -np.ones(w.nblocks, dtype=np.int32)
+    level, ijk = plan(amr, w, flags)
+    new = keys(level, ijk)
+    check_one_level_change(ndim, old, new)
+    assert len(new) < len(old)
+    # every coarsened parent had all its children as old leaves
+    for (l, i, j, k) in new - old:
+        assert (l + 1, 2 * i, 2 * j, 2 * k if ndim == 3 else 0) in old
+    # unflag one child of each coarsenable set: nothing of that set merges
+    par = {}
+    for b, (l, p) in enumerate(zip(w.level, w.ijk)):
+        par.setdefault((int(l) - 1, int(p[0]) >> 1, int(p[1]) >> 1, int(p[2]) >> 1), []).append(b)
+    flags2 = flags.copy()
+    for pk, kids in par.items():
+        if pk in new:
+            flags2[kids[0]] = 0
+    level2, ijk2 = plan(amr, w, flags2)
+    assert not ((keys(level2, ijk2) - old) & set(par.keys()))
+
+
+def test_plan_coarsening_respects_nesting(amr):
+    """2D, 2 x 1 base blocks: P = (1, 0, 0) and Q = (1, 1, 0) are refined, and
+    Q's child (2, 2, 0) is refined again.  Merging P's children alone would
+    put P beside level-3 leaves, so it is refused; when that level-3 set is
+    flagged too it merges first and then P's children can merge as well."""
+    base = (2, 1, 1)
+    leaves = set()
+    for a in (0, 1):
+        for b in (0, 1):
+            leaves.add((2, a, b, 0))  # children of P
+            if (a, b) != (0, 0):
+                leaves.add((2, 2 + a, b, 0))  # children of Q but (2, 2, 0)
+            leaves.add((3, 4 + a, b, 0))  # children of (2, 2, 0)
+    keys_ = sorted(leaves)
+    level = np.array([t[0] for t in keys_], dtype=np.int32)
+    ijk = np.array([t[1:] for t in keys_], dtype=np.int32)
+    w = inputs.uniform_state(2, base, [1.0, 0, 0, 0, 1.0, 0, 0, 0, 0], level=level, ijk=ijk)
+    w.base_blocks = base
+    p_kids = np.array([k[0] == 2 and k[1] < 2 for k in keys_])
+    lv, ij = plan(amr, w, np.where(p_kids, -1, 0))
+    assert keys(lv, ij) == leaves
+    l3 = np.array([k[0] == 3 for k in keys_])
+    lv, ij = plan(amr, w, np.where(p_kids | l3, -1, 0))
+    new = keys(lv, ij)
+    assert (1, 0, 0, 0) in new and (2, 2, 0, 0) in new and not any(k[0] == 3 for k in new)
+    check_one_level_change(2, leaves, new)
+
+
+# ---------------------------------------------------------------------------
+# the oracle's transfer
+
+
+def _totals(w, u):
+    vol = np.ones(w.nblocks)
+    for d in range(w.ndim):
+        vol = vol * (w.xmax[d] - w.xmin[d]) / (w.base_blocks[d] * w.nx * 2.0 ** (w.level - 1))
+    return np.array([np.sum(vol[:, None] * u[:, q].reshape(w.nblocks, -1)) for q in range(NV)])
+
+
+def _refine_and_coarsen(amr, w, seed):
+    r = np.random.Generator(np.random.PCG64(seed))
+    flags = np.where(r.random(w.nblocks) < 0.3, 1, -1).astype(np.int32)
+    return amr.regrid_plan(w, flags)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_oracle_regrid_keeps_uniform_state_exactly(amr, orc, ndim):
+    base, level, ijk = inputs.amr_test_hierarchy(ndim, nb1=4 if ndim == 2 else 2, seed=11)
+    w = inputs.uniform_state(ndim, base, [1.3, 0.4, -0.25, 0.15, 0.8, 0.6, -0.9, 0.3, 0.0], level=level, ijk=ijk)
+    w.base_blocks = base
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()[0, :, 0, 0] if ndim == 2 else sim.cons()[0, :, 0, 0, 0]
+    lv, ij = _refine_and_coarsen(amr, w, 3)
+    new = sim.regrid(lv, ij)
+    u = new.cons()
+    assert np.array_equal(u, np.broadcast_to(u0.reshape((1, NV) + (1,) * ndim), u.shape))
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_oracle_regrid_conserves(amr, orc, ndim):
+    w = inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5)
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    lv, ij = _refine_and_coarsen(amr, w, 4)
+    new = sim.regrid(lv, ij)
+    wn = dataclasses.replace(w, level=lv, ijk=ij)
+    t0, t1 = _totals(w, u0), _totals(wn, new.cons())
+    scale = _totals(w, np.abs(u0))
+    assert np.all(np.abs(t1 - t0)[:PSI] <= 1e-14 * scale[:PSI]), (t0, t1)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_oracle_refine_then_coarsen_is_the_identity(amr, orc, ndim):
+    w = inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5)
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    top = int(w.level.max())
+    flags = (w.level < top).astype(np.int32)  # refine everything below the top level
+    lv, ij = amr.regrid_plan(w, flags)
+    fine = sim.regrid(lv, ij)
+    back = fine.regrid(w.level, w.ijk)  # each refined block is the parent of its children again
+    np.testing.assert_allclose(back.cons(), u0, rtol=1e-14, atol=1e-15)
+
+
+def test_oracle_restriction_is_the_pairwise_mean(amr, orc):
+    w = inputs.smooth_amr_state(3, nb1=2, seed=5)
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    lv, ij = amr.regrid_plan(w, -np.ones(w.nblocks, dtype=np.int32))
+    new = sim.regrid(lv, ij)
+    un = new.cons()
+    old = {k: b for b, k in enumerate(sorted_keys(w.level, w.ijk))}
+    nkeys = sorted_keys(lv, ij)
+    checked = 0
+    for n, (l, i, j, k) in enumerate(nkeys):
+        if (l, i, j, k) in old:
+            assert np.array_equal(un[n], u0[old[(l, i, j, k)]])
+            continue
+        # rebuild the coarse block from the 8 children in the same pairwise order
+        c = {}
+        for e in (0, 1):
+            for b in (0, 1):
+                for a in (0, 1):
+                    c[(e, b, a)] = u0[old[(l + 1, 2 * i + a, 2 * j + b, 2 * k + e)]]
+        want = np.empty_like(un[n])
+        for z in range(16):
+            for y in range(16):
+                for x in range(16):
+                    ch = c[(z // 8, y // 8, x // 8)]
+                    fz, fy, fx = 2 * (z % 8), 2 * (y % 8), 2 * (x % 8)
+                    v = lambda dz, dy, dx: ch[:, fz + dz, fy + dy, fx + dx]  # noqa: E731
+                    want[:, z, y, x] = (((v(0, 0, 0) + v(0, 0, 1)) + (v(0, 1, 0) + v(0, 1, 1))) +
+                                        ((v(1, 0, 0) + v(1, 0, 1)) + (v(1, 1, 0) + v(1, 1, 1)))) * 0.125
+        assert np.array_equal(un[n], want)
+        checked += 1
+    assert checked > 0
+
+
+def sorted_keys(level, ijk):
+    return [(int(l), int(p[0]), int(p[1]), int(p[2])) for l, p in zip(level, ijk)]
+
+
+def test_oracle_prolongation_reproduces_linear_data(amr, orc):
+    """Refined blocks away from the domain boundary carry a linear field
+    exactly (the minmod slopes of linear data are unclipped)."""
+    n = 64
+    w = inputs.random_modes(n, 2, seed=1)
+    w.bc_lo, w.bc_hi = (1, 1, 1), (1, 1, 1)  # zero-gradient: no wrap-around jump
+    x, y, _ = inputs.cell_centres(2, w.nx, w.base_blocks, w.xmin, w.xmax, w.level, w.ijk)
+    for q in range(NV):
+        w.prim[:, q] = 1.0 + 0.1 * (q + 1) * x + 0.05 * (q - 3) * y
+    sim = orc.OracleSim(w)
+    interior = [b for b, p in enumerate(w.ijk) if 0 < p[0] < 3 and 0 < p[1] < 3]
+    flags = np.zeros(w.nblocks, dtype=np.int32)
+    flags[interior] = 1
+    lv, ij = amr.regrid_plan(w, flags)
+    new = sim.regrid(lv, ij)
+    un = new.cons()
+    wn = dataclasses.replace(w, level=lv, ijk=ij)
+    xn, yn, _ = inputs.cell_centres(2, w.nx, w.base_blocks, w.xmin, w.xmax, lv, ij)
+    for b in range(len(lv)):
+        if lv[b] != 2:
+            continue
+        rho = 1.0 + 0.1 * xn[b] - 0.15 * yn[b]
+        np.testing.assert_allclose(un[b, RHO], rho, rtol=1e-14)
+        bx = 1.0 + 0.6 * xn[b] + 0.1 * yn[b]
+        np.testing.assert_allclose(un[b, BX], bx, rtol=1e-14)
