@@ -103,7 +103,7 @@ def parse():
                     help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
     ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud"], default="random_modes")
     ap.add_argument("--limiter", choices=["vanleer", "koren", "cada3"], default="vanleer")
-    ap.add_argument("--flux", choices=["hll", "hlld"], default="hll")
+    ap.add_argument("--flux", choices=["hll", "hlld", "hllc"], default="hll")
     ap.add_argument("--regrid", action="store_true",
                     help="also time one regrid (coarsen the top level, refine every eighth block below)")
     ap.add_argument("--tune", default="auto",
@@ -182,7 +182,7 @@ def main():
     else:
         w = inputs.shock_cloud_amr()
     w.limiter = LIMITERS.index(args.limiter)
-    w.flux = 1 if args.flux == "hlld" else 0
+    w.flux = {"hll": 0, "hlld": 1, "hllc": 2}[args.flux]
     mixed = args.precision == "mixed"
     if mixed:
         args.path = "fused"

@@ -69,11 +69,13 @@ enum { AMRVAC_PATH_PLAIN = 0, AMRVAC_PATH_FUSED = 1 };
  * the unlimited third-order values (2 d+ + d-)/6 and (2 d- + d+)/6 in smooth
  * monotone regions. */
 enum { AMRVAC_LIM_VANLEER = 0, AMRVAC_LIM_KOREN = 1, AMRVAC_LIM_CADA3 = 2 };
-/* Interface flux schemes (Table tab:schemes_space), both on top of the GLM
- * interface values of (B_n, psi): HLL with Davis speed bounds, or HLLD
+/* Interface flux schemes (Table tab:schemes_space), all on top of the GLM
+ * interface values of (B_n, psi): HLL with Davis speed bounds; HLLD
  * (Miyoshi and Kusano 2005: contact, Alfven and fast waves, resolving
- * isolated contact and rotational discontinuities exactly). */
-enum { AMRVAC_FLUX_HLL = 0, AMRVAC_FLUX_HLLD = 1 };
+ * isolated contact and rotational discontinuities exactly); HLLC for MHD
+ * (Li 2005: contact and fast waves, with the tangential field and velocity
+ * of the star states from the HLL average; resolves isolated contacts). */
+enum { AMRVAC_FLUX_HLL = 0, AMRVAC_FLUX_HLLD = 1, AMRVAC_FLUX_HLLC = 2 };
 
 /* Grid and scheme description.  Physical boundary kinds per face follow the
  * paper's examples: periodic, zero-gradient ("continuous"), reflective

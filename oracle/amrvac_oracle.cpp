@@ -14,7 +14,7 @@
 //     a right state per face, with the 'vanleer', 'koren' or 'cada3'
 //     limiter and 2 ghost cells (Table t:limiters);
 //   * the HLL flux (Table tab:schemes_space; Harten et al. 1983), or HLLD
-//     (Miyoshi and Kusano 2005);
+//     (Miyoshi and Kusano 2005), or HLLC (Li 2005);
 //   * the 'glm' divergence control of Dedner et al. 2002 (Table t:divb);
 //   * the CFL coupling of the time step to the grid spacing ("Schemes and
 //     limiters for HD and MHD");
@@ -221,7 +221,7 @@ void glm_interface(double bnl, double bnr, double psl, double psr, double ch, do
   *ps = 0.5 * (psl + psr) - 0.5 * ch * (bnr - bnl);
 }
 
-enum { FLUX_HLL = 0, FLUX_HLLD = 1 };
+enum { FLUX_HLL = 0, FLUX_HLLD = 1, FLUX_HLLC = 2 };
 
 // HLLD (Miyoshi and Kusano 2005; the 'hlld' entry of Table
 // tab:schemes_space, used there with glm) on the seven components other than
@@ -318,6 +318,65 @@ void hlld_flux(const Cell& wl, const Cell& wr, const Cell& ul, const Cell& ur, c
   copy7(Fss);
 }
 
+// HLLC for MHD (Li 2005; the 'hllc' entry of Table tab:schemes_space) on the
+// seven components other than B_n and psi; bx is the normal field on both
+// sides.  S_L, S_R are the Davis bounds of the HLL flux and S_M the contact
+// speed.  The tangential field and velocity of both star states are those of
+// the HLL average state; density, momentum and energy of each star state
+// follow from the jump conditions across S_L or S_R with normal velocity
+// S_M and total pressure pT* = rho_L (S_L - u_L)(S_M - u_L) + pT_L.
+void hllc_flux(const Cell& wl, const Cell& wr, const Cell& ul, const Cell& ur, const double fl[NV],
+               const double fr[NV], int d, double bx, double gamma, double F[NV]) {
+  const int MN = MX + d;
+  int tan[2], k = 0;
+  for (int j = 0; j < 3; ++j)
+    if (j != d) tan[k++] = j;
+  auto copy7 = [&](const double* f) {
+    for (int q = 0; q < NV; ++q)
+      if (q != BX + d && q != PSI) F[q] = f[q];
+  };
+  const double cl = fast_speed(wl, d, gamma), cr = fast_speed(wr, d, gamma);
+  const double uln = wl.v[VX + d], urn = wr.v[VX + d];
+  const double S[2] = {std::min(uln - cl, urn - cr), std::max(uln + cl, urn + cr)};
+  if (S[0] >= 0.0) { copy7(fl); return; }
+  if (S[1] <= 0.0) { copy7(fr); return; }
+  // HLL average state
+  double uh[NV];
+  for (int q = 0; q < NV; ++q) uh[q] = (S[1] * ur.v[q] - S[0] * ul.v[q] - (fr[q] - fl[q])) / (S[1] - S[0]);
+  double pt[2];
+  for (int a = 0; a < 2; ++a) {
+    const Cell& w = a ? wr : wl;
+    pt[a] = w.v[PR] + 0.5 * (w.v[BX] * w.v[BX] + w.v[BY] * w.v[BY] + w.v[BZ] * w.v[BZ]);
+  }
+  const double rho[2] = {wl.v[RHO], wr.v[RHO]}, un[2] = {uln, urn};
+  const double sm = (rho[1] * un[1] * (S[1] - un[1]) - rho[0] * un[0] * (S[0] - un[0]) + pt[0] - pt[1]) /
+                    (rho[1] * (S[1] - un[1]) - rho[0] * (S[0] - un[0]));
+  const double pts = rho[0] * (S[0] - un[0]) * (sm - un[0]) + pt[0];
+  double bs[2], vs[2];
+  for (int t = 0; t < 2; ++t) {
+    bs[t] = uh[BX + tan[t]];
+    vs[t] = uh[MX + tan[t]] / uh[RHO];
+  }
+  const double vbs = sm * bx + vs[0] * bs[0] + vs[1] * bs[1];
+  const int a = sm >= 0.0 ? 0 : 1;
+  const Cell& w = a ? wr : wl;
+  const Cell& u = a ? ur : ul;
+  const double* f = a ? fr : fl;
+  const double sa = S[a] - un[a], sb = S[a] - sm;
+  Cell us = u;  // B_n and psi are not HLLC components
+  us.v[RHO] = rho[a] * sa / sb;
+  us.v[MN] = us.v[RHO] * sm;
+  for (int t = 0; t < 2; ++t) {
+    us.v[MX + tan[t]] = (rho[a] * w.v[VX + tan[t]] * sa + bx * (w.v[BX + tan[t]] - bs[t])) / sb;
+    us.v[BX + tan[t]] = bs[t];
+  }
+  const double vb = un[a] * bx + w.v[VX + tan[0]] * w.v[BX + tan[0]] + w.v[VX + tan[1]] * w.v[BX + tan[1]];
+  us.v[EN] = (u.v[EN] * sa - pt[a] * un[a] + pts * sm + bx * (vb - vbs)) / sb;
+  double Fs[NV];
+  for (int q = 0; q < NV; ++q) Fs[q] = f[q] + S[a] * (us.v[q] - u.v[q]);
+  copy7(Fs);
+}
+
 // Interface flux from the reconstructed left/right primitive states: GLM
 // interface values for (B_n, psi), then HLL with Davis speed bounds (or
 // HLLD) on the other seven components, built from the states with B_n
@@ -336,6 +395,10 @@ void face_flux(Cell wl, Cell wr, int d, double ch, double gamma, double F[NV], i
   F[PSI] = ch * ch * bn;
   if (flux == FLUX_HLLD) {
     hlld_flux(wl, wr, ul, ur, fl, fr, d, bn, gamma, F);
+    return;
+  }
+  if (flux == FLUX_HLLC) {
+    hllc_flux(wl, wr, ul, ur, fl, fr, d, bn, gamma, F);
     return;
   }
   const double cl = fast_speed(wl, d, gamma);
@@ -402,7 +465,7 @@ typedef struct {
   double small_density;
   double small_pressure;
   int limiter;  // 0 = 'vanleer', 1 = 'koren', 2 = 'cada3'
-  int flux;     // 0 = HLL, 1 = HLLD
+  int flux;     // 0 = HLL, 1 = HLLD, 2 = HLLC
 } oracle_params;
 
 }  // extern "C"
@@ -869,7 +932,7 @@ Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int*
   if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
   if (p->nstages < 1 || p->nstages > 5) throw std::invalid_argument("nstages must be 1 .. 5");
   if (p->limiter < LIM_VANLEER || p->limiter > LIM_CADA3) throw std::invalid_argument("unknown limiter");
-  if (p->flux != FLUX_HLL && p->flux != FLUX_HLLD) throw std::invalid_argument("unknown flux scheme");
+  if (p->flux != FLUX_HLL && p->flux != FLUX_HLLD && p->flux != FLUX_HLLC) throw std::invalid_argument("unknown flux scheme");
   if (s->P.nthreads < 1) s->P.nthreads = 1;
   for (int d = 0; d < s->ndim; ++d)
     if ((p->bc_lo[d] == BC_PERIODIC) != (p->bc_hi[d] == BC_PERIODIC))
@@ -1154,7 +1217,7 @@ void oracle_face_flux(const double* wl, const double* wr, int d, double ch, doub
   face_flux(a, b, d, ch, gamma, F);
 }
 int oracle_face_flux_kind(const double* wl, const double* wr, int d, double ch, double gamma, int flux, double* F) {
-  if (flux != FLUX_HLL && flux != FLUX_HLLD) return -1;
+  if (flux != FLUX_HLL && flux != FLUX_HLLD && flux != FLUX_HLLC) return -1;
   Cell a, b;
   std::memcpy(a.v, wl, sizeof(a.v));
   std::memcpy(b.v, wr, sizeof(b.v));

@@ -267,7 +267,7 @@ def glm_interface(bnl, bnr, psl, psr, ch):
 
 def face_flux(wl, wr, d: int, ch: float, gamma: float, flux: int = 0) -> np.ndarray:
     """Interface flux of the primitive states wl, wr along d: GLM interface
-    values, then HLL (flux = 0) or HLLD (flux = 1)."""
+    values, then HLL (flux = 0), HLLD (flux = 1) or HLLC (flux = 2)."""
     wl = np.ascontiguousarray(wl, dtype=np.float64)
     wr = np.ascontiguousarray(wr, dtype=np.float64)
     F = np.empty(NV)

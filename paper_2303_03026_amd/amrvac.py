@@ -18,7 +18,7 @@ NV = 9
 
 FP64, FP32_MIXED = 0, 1
 LIM_VANLEER, LIM_KOREN, LIM_CADA3 = 0, 1, 2
-FLUX_HLL, FLUX_HLLD = 0, 1
+FLUX_HLL, FLUX_HLLD, FLUX_HLLC = 0, 1, 2
 PATH_PLAIN, PATH_FUSED = 0, 1
 FLAG_SMALL_RHO, FLAG_SMALL_P, FLAG_BAD_DT = 1, 2, 4
 E_OK, E_ARG, E_HIP, E_NOMEM, E_NONPHYSICAL, E_STATE = 0, -1, -2, -3, -4, -5

@@ -29,7 +29,7 @@ struct PhysConst {
   double small_p;
   int fix;
   int limiter;  // LIM_* (the fused stage takes it as a template argument)
-  int flux;     // FLUX_HLL or FLUX_HLLD (likewise)
+  int flux;     // FLUX_HLL, FLUX_HLLD or FLUX_HLLC (likewise)
 };
 
 // Library-owned device status record.
@@ -366,13 +366,80 @@ __device__ __forceinline__ void hlld_glm_flux(R wl[NV], R wr[NV], R ch, R half_i
   F[I_PSI] = ch * ch * bn;
 }
 
-enum { FLUX_HLL = 0, FLUX_HLLD = 1 };
+// HLLC for MHD (Li 2005) with the same GLM interface values: Davis bounds
+// S_L, S_R as for HLL, contact speed S_M, star-region total pressure
+// pT* = rho_L (S_L - u_L)(S_M - u_L) + pT_L; both star states take the
+// tangential field and velocity of the HLL average state, and their density,
+// momentum and energy from the jump conditions across S_L or S_R.  Only the
+// side of the contact the interface lies on is assembled; selects drop the
+// star terms when every wave moves one way.
+template <int D, class R>
+__device__ __forceinline__ void hllc_glm_flux(R wl[NV], R wr[NV], R ch, R half_inv_ch, R gamma, R inv_gm1,
+                                              R F[NV]) {
+  constexpr int N = I_BX + D;
+  constexpr int T1 = D == 0 ? 1 : 0, T2 = D == 2 ? 1 : 2;
+  const R bn = R(0.5) * (wl[N] + wr[N]) - (wr[I_PSI] - wl[I_PSI]) * half_inv_ch;
+  const R ps = R(0.5) * (wl[I_PSI] + wr[I_PSI]) - R(0.5) * ch * (wr[N] - wl[N]);
+  wl[N] = bn;
+  wr[N] = bn;
+  const R rl = wl[I_RHO], rr = wr[I_RHO];
+  const R ul = wl[1 + D], ur = wr[1 + D];
+  const R b2l = wl[I_BX] * wl[I_BX] + wl[I_BY] * wl[I_BY] + wl[I_BZ] * wl[I_BZ];
+  const R b2r = wr[I_BX] * wr[I_BX] + wr[I_BY] * wr[I_BY] + wr[I_BZ] * wr[I_BZ];
+  const R ptl = wl[4] + R(0.5) * b2l, ptr = wr[4] + R(0.5) * b2r;
+  const R cl = cfast<D>(wl, rcp_(rl), b2l, gamma), cr = cfast<D>(wr, rcp_(rr), b2r, gamma);
+  const R sl = fmin(ul - cl, ur - cr), sr = fmax(ul + cl, ur + cr);
+  // HLL average of density and of the tangential momentum and field
+  const R isr = rcp_(sr - sl);
+  auto havg = [&](R ql, R qr, R fql, R fqr) { return (sr * qr - sl * ql - (fqr - fql)) * isr; };
+  const R rh = havg(rl, rr, rl * ul, rr * ur);
+  const R m1h = havg(rl * wl[1 + T1], rr * wr[1 + T1], rl * wl[1 + T1] * ul - wl[I_BX + T1] * bn,
+                     rr * wr[1 + T1] * ur - wr[I_BX + T1] * bn);
+  const R m2h = havg(rl * wl[1 + T2], rr * wr[1 + T2], rl * wl[1 + T2] * ul - wl[I_BX + T2] * bn,
+                     rr * wr[1 + T2] * ur - wr[I_BX + T2] * bn);
+  const R b1h = havg(wl[I_BX + T1], wr[I_BX + T1], ul * wl[I_BX + T1] - bn * wl[1 + T1],
+                     ur * wr[I_BX + T1] - bn * wr[1 + T1]);
+  const R b2h = havg(wl[I_BX + T2], wr[I_BX + T2], ul * wl[I_BX + T2] - bn * wl[1 + T2],
+                     ur * wr[I_BX + T2] - bn * wr[1 + T2]);
+  const R irh = rcp_(rh);
+  const R vs1 = m1h * irh, vs2 = m2h * irh;
+  const R sm = (rr * ur * (sr - ur) - rl * ul * (sl - ul) + ptl - ptr) * rcp_(rr * (sr - ur) - rl * (sl - ul));
+  const R pts = rl * (sl - ul) * (sm - ul) + ptl;
+  const R vbs = sm * bn + vs1 * b1h + vs2 * b2h;
+  // the side of the contact the interface lies on
+  const bool super = sl >= R(0) || sr <= R(0);
+  const bool right = sr <= R(0) || (!(sl >= R(0)) && sm < R(0));
+  const R* w = right ? wr : wl;
+  const R rho = right ? rr : rl, u = right ? ur : ul, pt = right ? ptr : ptl, b2 = right ? b2r : b2l;
+  const R S = right ? sr : sl, sa = S - u, isb = rcp_(S - sm);
+  const R v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+  const R e = w[4] * inv_gm1 + R(0.5) * rho * v2 + R(0.5) * b2;
+  const R vb = w[1] * w[I_BX] + w[2] * w[I_BY] + w[3] * w[I_BZ];
+  const R rs = rho * sa * isb;
+  const R ms1 = (rho * w[1 + T1] * sa + bn * (w[I_BX + T1] - b1h)) * isb;
+  const R ms2 = (rho * w[1 + T2] * sa + bn * (w[I_BX + T2] - b2h)) * isb;
+  const R es = (e * sa - pt * u + pts * sm + bn * (vb - vbs)) * isb;
+  auto hllc = [&](R uq, R usq, R fq) { return super ? fq : fq + S * (usq - uq); };
+  F[I_RHO] = hllc(rho, rs, rho * u);
+  F[1 + D] = hllc(rho * u, rs * sm, rho * u * u + pt - bn * bn);
+  F[1 + T1] = hllc(rho * w[1 + T1], ms1, rho * w[1 + T1] * u - w[I_BX + T1] * bn);
+  F[1 + T2] = hllc(rho * w[1 + T2], ms2, rho * w[1 + T2] * u - w[I_BX + T2] * bn);
+  F[I_EN] = hllc(e, es, (e + pt) * u - bn * vb);
+  F[I_BX + T1] = hllc(w[I_BX + T1], b1h, u * w[I_BX + T1] - bn * w[1 + T1]);
+  F[I_BX + T2] = hllc(w[I_BX + T2], b2h, u * w[I_BX + T2] - bn * w[1 + T2]);
+  F[N] = ps;
+  F[I_PSI] = ch * ch * bn;
+}
+
+enum { FLUX_HLL = 0, FLUX_HLLD = 1, FLUX_HLLC = 2 };
 
 // interface flux of the scheme chosen at compile time
 template <int FLX, int D, class R>
 __device__ __forceinline__ void face_flux(R wl[NV], R wr[NV], R ch, R half_inv_ch, R gamma, R inv_gm1, R F[NV]) {
   if (FLX == FLUX_HLLD)
     hlld_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
+  else if (FLX == FLUX_HLLC)
+    hllc_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
   else
     hll_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
 }
@@ -383,6 +450,8 @@ __device__ __forceinline__ void face_flux_rt(int flux, R wl[NV], R wr[NV], R ch,
                                              R F[NV]) {
   if (flux == FLUX_HLLD)
     hlld_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
+  else if (flux == FLUX_HLLC)
+    hllc_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
   else
     hll_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
 }

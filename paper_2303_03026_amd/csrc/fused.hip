@@ -1,6 +1,6 @@
 // Fused stage kernel for 16^ndim blocks: conserved -> primitive, limited
 // linear reconstruction (van Leer, Koren or Cada-Torrilhon), GLM interface +
-// HLL (or HLLD) fluxes in every direction, flux difference, psi damping and the SSPRK
+// HLL (or HLLD, HLLC) fluxes in every direction, flux difference, psi damping and the SSPRK
 // combination, in one launch.
 //
 // One 256-thread workgroup per block; thread t owns the (x, y) column
@@ -568,6 +568,8 @@ hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T
   do {                                                 \
     if (P.flux == FLUX_HLLD)                           \
       AMRVAC_FUSED_LAUNCH(ND, SPT, LM, FLUX_HLLD);     \
+    else if (P.flux == FLUX_HLLC)                      \
+      AMRVAC_FUSED_LAUNCH(ND, SPT, LM, FLUX_HLLC);     \
     else                                               \
       AMRVAC_FUSED_LAUNCH(ND, SPT, LM, FLUX_HLL);      \
   } while (0)

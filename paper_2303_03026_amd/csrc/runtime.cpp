@@ -74,7 +74,7 @@ int check_desc(const amrvac_grid_desc* g, std::string* why) {
   }
   if (!(g->gamma > 1.0) || !(g->cfl > 0.0) || !(g->glm_alpha >= 0.0)) { *why = "bad gamma/cfl/glm_alpha"; return AMRVAC_E_ARG; }
   if (g->limiter < AMRVAC_LIM_VANLEER || g->limiter > AMRVAC_LIM_CADA3) { *why = "bad limiter"; return AMRVAC_E_ARG; }
-  if (g->flux != AMRVAC_FLUX_HLL && g->flux != AMRVAC_FLUX_HLLD) { *why = "bad flux scheme"; return AMRVAC_E_ARG; }
+  if (g->flux < AMRVAC_FLUX_HLL || g->flux > AMRVAC_FLUX_HLLC) { *why = "bad flux scheme"; return AMRVAC_E_ARG; }
   return AMRVAC_OK;
 }
 

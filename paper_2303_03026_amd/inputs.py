@@ -55,7 +55,7 @@ class Workload:
     reflux: int = 1
     ng: int = 2
     limiter: int = 0  # 0 'vanleer', 1 'koren', 2 'cada3'
-    flux: int = 0     # 0 HLL, 1 HLLD
+    flux: int = 0     # 0 HLL, 1 HLLD, 2 HLLC
     bc_fixed_prim: np.ndarray = dataclasses.field(
         default_factory=lambda: np.zeros((3, 2, NV)))
 

@@ -946,3 +946,120 @@ def test_hlld_conditioning_on_the_low_beta_sheet(orc):
         floors.append(np.array([np.sum(np.abs(ub[:, q] - ua[:, q])) / np.sum(np.abs(ua[:, q])) for q in range(NV)]))
     assert np.max(floors[0][:PSI]) < 1e-13 and floors[0][PSI] < 2e-12, floors[0]
     assert np.max(floors[1]) > 2 * np.max(floors[0]), floors
+
+
+# ---------------------------------------------------------------------------
+# HLLC for MHD (Li 2005) with the GLM interface values
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_hllc_consistency_upwinding_and_contacts(orc, d):
+    """F(U, U) = F(U); every wave moving one way gives the upwind flux; an
+    isolated contact (moving either way) gets exactly the upwind flux, where
+    HLL adds diffusion."""
+    r = rng(41)
+    comps = [q for q in range(NV) if q not in (BX + d, PSI)]
+    for _ in range(100):
+        w = _rand_state(r)
+        F = orc.face_flux(w, w, d, 1.3, G53, flux=2)
+        np.testing.assert_allclose(F[comps], orc.phys_flux(w, d, G53)[comps], rtol=1e-13, atol=1e-14)
+        wl, wr = _rand_state(r), _rand_state(r)
+        wl[1 + d] = wr[1 + d] = 12.0
+        wr[BX + d] = wl[BX + d]
+        F = orc.face_flux(wl, wr, d, 1.3, G53, flux=2)
+        assert np.array_equal(F[comps], orc.phys_flux(wl, d, G53)[comps])
+    hll_miss = 0.0
+    for _ in range(60):
+        s = r.uniform(-0.4, 0.4)
+        wl, wr = _contact(r, d, s)
+        exact = orc.phys_flux(wl if s > 0 else wr, d, G53)
+        F = orc.face_flux(wl, wr, d, 1.3, G53, flux=2)
+        np.testing.assert_allclose(F[comps], exact[comps], rtol=1e-12, atol=1e-12)
+        hll_miss = max(hll_miss, np.max(np.abs(orc.face_flux(wl, wr, d, 1.3, G53) - exact)[comps]))
+    assert hll_miss > 1e-2
+
+
+def _toro_hllc(wl, wr, g):
+    """Toro's hydrodynamic HLLC flux (x direction, B = 0) with Davis speed
+    bounds, written out independently of the MHD form."""
+    def prim(w):
+        rho, u, v, ww, p = w[0], w[1], w[2], w[3], w[4]
+        E = p / (g - 1) + 0.5 * rho * (u * u + v * v + ww * ww)
+        U = np.array([rho, rho * u, rho * v, rho * ww, E])
+        F = np.array([rho * u, rho * u * u + p, rho * u * v, rho * u * ww, (E + p) * u])
+        return rho, u, p, E, U, F, math.sqrt(g * p / rho)
+    rl, ul, pl, El, Ul, Fl, al = prim(wl)
+    rr, ur, pr, Er, Ur, Fr, ar = prim(wr)
+    sl, sr = min(ul - al, ur - ar), max(ul + al, ur + ar)
+    if sl >= 0:
+        return Fl
+    if sr <= 0:
+        return Fr
+    ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) / (rl * (sl - ul) - rr * (sr - ur))
+    def star(rho, u, p, E, w, s):
+        c = rho * (s - u) / (s - ss)
+        return c * np.array([1.0, ss, w[2], w[3], E / rho + (ss - u) * (ss + p / (rho * (s - u)))])
+    if ss >= 0:
+        return Fl + sl * (star(rl, ul, pl, El, wl, sl) - Ul)
+    return Fr + sr * (star(rr, ur, pr, Er, wr, sr) - Ur)
+
+
+def test_hllc_reduces_to_hydro_hllc_without_field(orc):
+    r = rng(42)
+    for _ in range(300):
+        wl, wr = _rand_state(r), _rand_state(r)
+        wl[[BX, BY, BZ, PSI]] = 0.0
+        wr[[BX, BY, BZ, PSI]] = 0.0
+        wl[1], wr[1] = r.uniform(-2, 2), r.uniform(-2, 2)
+        F = orc.face_flux(wl, wr, 0, 1.3, G53, flux=2)
+        T = _toro_hllc(wl, wr, G53)
+        np.testing.assert_allclose(F[[RHO, VX, VY, VZ, PR]], T, rtol=1e-12, atol=1e-13)
+        assert np.all(F[[BY, BZ]] == 0.0)
+
+
+def test_hllc_alfven_wave_and_sod_against_hll(orc):
+    import exact_riemann as er
+
+    def alf(n, flux):
+        w = inputs.alfven_wave(n, 2)
+        w.flux = flux
+        sim = orc.OracleSim(w)
+        sim.steps_to_time(1.0 / math.sqrt(2.0))
+        e = np.mean(np.abs(sim.cons()[:, BZ] - w.prim[:, BZ])) / 1e-6
+        sim.close()
+        return e
+
+    def sod(n, flux):
+        w = inputs.sod(n, ndim=2)
+        w.flux = flux
+        sim = orc.OracleSim(w)
+        sim.steps_to_time(0.2)
+        g = inputs.blocks_to_global(sim.cons().swapaxes(0, 1), 2, w.nx, w.base_blocks)[RHO]
+        sim.close()
+        ex = er.cell_average_density(n, 0.2, 0.5, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+        return np.mean(np.abs(g[0] - ex))
+    e64, e128 = alf(64, 2), alf(128, 2)
+    assert math.log2(e64 / e128) >= 1.8, (e64, e128)
+    assert e128 <= alf(128, 0), e128
+    errs = [sod(n, 2) for n in (64, 128, 256)]
+    assert min(math.log2(errs[i] / errs[i + 1]) for i in range(2)) >= 0.6, errs
+    assert all(e < sod(n, 0) for e, n in zip(errs, (64, 128, 256))), errs
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_hllc_uniform_and_conservation(orc, ndim):
+    w = inputs.uniform_state(ndim, (3, 2, 2), _uniform_w())
+    w.flux = 2
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    sim.steps(3)
+    assert np.array_equal(sim.cons(), u0)
+    w = inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5 if ndim == 2 else 7)
+    w.flux = 2
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    t0 = _totals(w, u0)
+    sim.steps(3 if ndim == 3 else 10)
+    t1 = _totals(w, sim.cons())
+    rel = np.abs(t1 - t0) / _scale(w, u0)
+    assert np.all(rel[[RHO, VX, VY, VZ, PR, BX, BY, BZ]] < 1e-13), rel
