@@ -89,7 +89,7 @@ def measured_traffic(precision, tune, workload, n):
 # not 1; one state is 72 B per cell in FP64 and 40 B in FP32-mixed.
 
 
-LIMITERS = ("vanleer", "koren", "cada3")
+LIMITERS = ("vanleer", "koren", "cada3", "weno5", "wenoz5")
 
 
 def parse():
@@ -102,7 +102,8 @@ def parse():
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64",
                     help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
     ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud"], default="random_modes")
-    ap.add_argument("--limiter", choices=["vanleer", "koren", "cada3"], default="vanleer")
+    ap.add_argument("--limiter", choices=list(LIMITERS), default="vanleer",
+                    help="weno5 / wenoz5 need 3 ghost layers: FP64 plain path only")
     ap.add_argument("--flux", choices=["hll", "hlld", "hllc"], default="hll")
     ap.add_argument("--regrid", action="store_true",
                     help="also time one regrid (coarsen the top level, refine every eighth block below)")
@@ -184,6 +185,11 @@ def main():
     w.limiter = LIMITERS.index(args.limiter)
     w.flux = {"hll": 0, "hlld": 1, "hllc": 2}[args.flux]
     mixed = args.precision == "mixed"
+    if w.limiter >= 3:  # the five-cell WENO stencils: 3 ghost layers, plain FP64 path
+        if mixed:
+            sys.exit("bench: WENO reconstructions run on the FP64 plain path only")
+        w.ng = 3
+        args.path = "plain"
     if mixed:
         args.path = "fused"
     path = amrvac.PATH_FUSED if args.path == "fused" else amrvac.PATH_PLAIN
@@ -301,9 +307,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: 3D, %d leaf blocks of 16^3 + 2 ghost layers on %d level(s), %s GLM-MHD "
+        "config": {"workload": "%s: 3D, %d leaf blocks of 16^3 + %d ghost layers on %d level(s), %s GLM-MHD "
                                "state, SSPRK(3,3), CFL 0.8, %s, %s limiter, %s flux"
-                               % (w.name, w.nblocks, w.max_level, args.workload, "FP32-mixed" if mixed else "FP64",
+                               % (w.name, w.nblocks, w.ng, w.max_level, args.workload, "FP32-mixed" if mixed else "FP64",
                                   args.limiter, args.flux.upper()),
                    "path": args.path, "cells": cells, "stage_weights": [1.0, 0.25, 2.0 / 3.0],
                    "tune": None if tune is None else {"zseg": tune[0], "rotate": tune[1], "xcd": tune[2]}},
@@ -327,7 +333,7 @@ def main():
             small = inputs.current_sheet(n=48)
         else:
             small = inputs.shock_cloud_amr(base_n=32)
-        small.limiter, small.flux = w.limiter, w.flux
+        small.limiter, small.flux, small.ng = w.limiter, w.flux, w.ng
         out["cpu_baseline"] = cpu_baseline(w, small)
     print(json.dumps(out), flush=True)
 

@@ -68,7 +68,11 @@ enum { AMRVAC_PATH_PLAIN = 0, AMRVAC_PATH_FUSED = 1 };
  * face values are w + phi d+ / 2 and w - phi' d- / 2; koren and cada3 give
  * the unlimited third-order values (2 d+ + d-)/6 and (2 d- + d+)/6 in smooth
  * monotone regions. */
-enum { AMRVAC_LIM_VANLEER = 0, AMRVAC_LIM_KOREN = 1, AMRVAC_LIM_CADA3 = 2 };
+enum { AMRVAC_LIM_VANLEER = 0, AMRVAC_LIM_KOREN = 1, AMRVAC_LIM_CADA3 = 2, AMRVAC_LIM_WENO5 = 3, AMRVAC_LIM_WENOZ5 = 4 };
+/* The fifth-order reconstructions of Table t:limiters on 3 ghost cells
+ * (nghost = 3; the per-kernel FP64 path only): 'weno5' (Jiang and Shu 1996,
+ * eps = 1e-6) and 'wenoz5' (Borges et al. 2008, WENO-Z weights, eps =
+ * 1e-40), each face value from the five cells on its side. */
 /* Interface flux schemes (Table tab:schemes_space), all on top of the GLM
  * interface values of (B_n, psi): HLL with Davis speed bounds; HLLD
  * (Miyoshi and Kusano 2005: contact, Alfven and fast waves, resolving
@@ -84,8 +88,9 @@ enum { AMRVAC_FLUX_HLL = 0, AMRVAC_FLUX_HLLD = 1, AMRVAC_FLUX_HLLC = 2 };
 typedef struct {
   int ndim;               /* 2 or 3                                            */
   int block_nx;           /* interior cells per direction per block (even,     */
-                          /* 4..16; the fused path needs 16)                   */
-  int nghost;             /* ghost layers; must be 2 (van Leer stencil)        */
+                          /* 4..16; the fused path and FP32-mixed need 16)     */
+  int nghost;             /* ghost layers: 2, or 3 for weno5 / wenoz5 (the     */
+                          /* fused path and FP32-mixed need 2)                 */
   int precision;          /* AMRVAC_FP64 or AMRVAC_FP32_MIXED                  */
   int base_blocks[3];     /* blocks per direction on level 1 (z ignored in 2D) */
   int bc_lo[3];           /* AMRVAC_BC_* at the minimum face of each direction */

@@ -12,7 +12,8 @@
 //     tab:schemes_time: SSPRK(2,2), SSPRK(3,3), SSPRK(4,3) and SSPRK(5,4));
 //   * limited linear reconstruction of primitive variables giving a left and
 //     a right state per face, with the 'vanleer', 'koren' or 'cada3'
-//     limiter and 2 ghost cells (Table t:limiters);
+//     limiter and 2 ghost cells, or the fifth-order 'weno5' / 'wenoz5'
+//     reconstructions with 3 ghost cells (Table t:limiters);
 //   * the HLL flux (Table tab:schemes_space; Harten et al. 1983), or HLLD
 //     (Miyoshi and Kusano 2005), or HLLC (Li 2005);
 //   * the 'glm' divergence control of Dedner et al. 2002 (Table t:divb);
@@ -176,7 +177,35 @@ double cada3_phi(double th) {
   return std::max(0.0, std::min(p3, std::max(-0.5 * th, std::min(std::min(2.0 * th, p3), 1.6))));
 }
 
-enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2 };
+enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2, LIM_WENO5 = 3, LIM_WENOZ5 = 4 };
+
+// Fifth-order WENO value at the face between cells i and i+1, seen from cell
+// i, from cells i-2 .. i+2 (the 'weno5' and 'wenoz5' rows of Table
+// t:limiters, 3 ghost cells): the three third-order candidate polynomials
+// q_k, their smoothness indicators beta_k and the optimal weights
+// (0.1, 0.6, 0.3).  'weno5' (Jiang and Shu 1996): alpha_k = d_k / (eps +
+// beta_k)^2 with eps = 1e-6.  'wenoz5' (Borges et al. 2008): alpha_k = d_k
+// (1 + tau5 / (beta_k + eps)) with tau5 = |beta_0 - beta_2|, eps = 1e-40.
+double weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, bool z) {
+  const double q0 = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) / 6.0;
+  const double q1 = (-vm1 + 5.0 * v0 + 2.0 * vp1) / 6.0;
+  const double q2 = (2.0 * v0 + 5.0 * vp1 - vp2) / 6.0;
+  const double a0 = vm2 - 2.0 * vm1 + v0, b0 = vm2 - 4.0 * vm1 + 3.0 * v0;
+  const double a1 = vm1 - 2.0 * v0 + vp1, b1 = vm1 - vp1;
+  const double a2 = v0 - 2.0 * vp1 + vp2, b2 = 3.0 * v0 - 4.0 * vp1 + vp2;
+  const double beta[3] = {13.0 / 12.0 * a0 * a0 + 0.25 * b0 * b0, 13.0 / 12.0 * a1 * a1 + 0.25 * b1 * b1,
+                          13.0 / 12.0 * a2 * a2 + 0.25 * b2 * b2};
+  const double d[3] = {0.1, 0.6, 0.3};
+  double alpha[3];
+  if (z) {
+    const double tau5 = std::fabs(beta[0] - beta[2]);
+    for (int k = 0; k < 3; ++k) alpha[k] = d[k] * (1.0 + tau5 / (beta[k] + 1e-40));
+  } else {
+    for (int k = 0; k < 3; ++k) alpha[k] = d[k] / ((1e-6 + beta[k]) * (1e-6 + beta[k]));
+  }
+  const double sum = alpha[0] + alpha[1] + alpha[2];
+  return (alpha[0] * q0 + alpha[1] * q1 + alpha[2] * q2) / sum;
+}
 
 // The two face values of a cell with backward and forward differences dm, dp:
 // right face w + inc_right/2, left face w - inc_left/2.  The left face is the
@@ -464,7 +493,7 @@ typedef struct {
   double glm_alpha;
   double small_density;
   double small_pressure;
-  int limiter;  // 0 = 'vanleer', 1 = 'koren', 2 = 'cada3'
+  int limiter;  // 0 = 'vanleer', 1 = 'koren', 2 = 'cada3', 3 = 'weno5', 4 = 'wenoz5'
   int flux;     // 0 = HLL, 1 = HLLD, 2 = HLLC
 } oracle_params;
 
@@ -705,12 +734,24 @@ struct Sim {
               const Cell& wp = at(f);
               const Cell& wpp = at(f + 1);
               Cell wl, wr;
-              for (int q = 0; q < NV; ++q) {
-                double rm, lm, rp, lp;
-                face_increments(P.limiter, wm.v[q] - wmm.v[q], wp.v[q] - wm.v[q], &rm, &lm);
-                face_increments(P.limiter, wp.v[q] - wm.v[q], wpp.v[q] - wp.v[q], &rp, &lp);
-                wl.v[q] = wm.v[q] + 0.5 * rm;
-                wr.v[q] = wp.v[q] - 0.5 * lp;
+              if (P.limiter == LIM_WENO5 || P.limiter == LIM_WENOZ5) {
+                // five-point stencils f-3 .. f+1 (left state) and f+2 .. f-2
+                // (right state, mirrored)
+                const bool z = P.limiter == LIM_WENOZ5;
+                const Cell& wm3 = at(f - 3);
+                const Cell& wp2 = at(f + 2);
+                for (int q = 0; q < NV; ++q) {
+                  wl.v[q] = weno5_face(wm3.v[q], wmm.v[q], wm.v[q], wp.v[q], wpp.v[q], z);
+                  wr.v[q] = weno5_face(wp2.v[q], wpp.v[q], wp.v[q], wm.v[q], wmm.v[q], z);
+                }
+              } else {
+                for (int q = 0; q < NV; ++q) {
+                  double rm, lm, rp, lp;
+                  face_increments(P.limiter, wm.v[q] - wmm.v[q], wp.v[q] - wm.v[q], &rm, &lm);
+                  face_increments(P.limiter, wp.v[q] - wm.v[q], wpp.v[q] - wp.v[q], &rp, &lp);
+                  wl.v[q] = wm.v[q] + 0.5 * rm;
+                  wr.v[q] = wp.v[q] - 0.5 * lp;
+                }
               }
               if (!(wl.v[RHO] > 0.0) || !(wl.v[PR] > 0.0) || !(wr.v[RHO] > 0.0) || !(wr.v[PR] > 0.0)) {
                 wl = wm;
@@ -928,10 +969,12 @@ Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int*
   s->nx = p->nx;
   s->ng = p->ng;
   if (s->ndim != 2 && s->ndim != 3) throw std::invalid_argument("ndim must be 2 or 3");
-  if (s->ng != 2) throw std::invalid_argument("the van Leer stencil needs exactly 2 ghost layers");
+  if (s->ng != 2 && s->ng != 3) throw std::invalid_argument("ghost layers must be 2 or 3");
   if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
   if (p->nstages < 1 || p->nstages > 5) throw std::invalid_argument("nstages must be 1 .. 5");
-  if (p->limiter < LIM_VANLEER || p->limiter > LIM_CADA3) throw std::invalid_argument("unknown limiter");
+  if (p->limiter < LIM_VANLEER || p->limiter > LIM_WENOZ5) throw std::invalid_argument("unknown limiter");
+  if ((p->limiter == LIM_WENO5 || p->limiter == LIM_WENOZ5) && p->ng != 3)
+    throw std::invalid_argument("the fifth-order reconstructions need 3 ghost layers");
   if (p->flux != FLUX_HLL && p->flux != FLUX_HLLD && p->flux != FLUX_HLLC) throw std::invalid_argument("unknown flux scheme");
   if (s->P.nthreads < 1) s->P.nthreads = 1;
   for (int d = 0; d < s->ndim; ++d)
@@ -1202,6 +1245,9 @@ double oracle_fast_speed(const double* w, int d, double gamma) {
 }
 double oracle_vanleer(double dm, double dp) { return vanleer(dm, dp); }
 double oracle_minmod(double a, double b) { return minmod(a, b); }
+double oracle_weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, int z) {
+  return weno5_face(vm2, vm1, v0, vp1, vp2, z != 0);
+}
 int oracle_face_increments(int lim, double dm, double dp, double* inc_right, double* inc_left) {
   if (lim < LIM_VANLEER || lim > LIM_CADA3) return -1;
   face_increments(lim, dm, dp, inc_right, inc_left);

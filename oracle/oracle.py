@@ -65,6 +65,8 @@ def lib():
         _lib.oracle_fast_speed.restype = ctypes.c_double
         _lib.oracle_fast_speed.argtypes = [dp, ctypes.c_int, ctypes.c_double]
         _lib.oracle_face_increments.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        _lib.oracle_weno5_face.restype = ctypes.c_double
+        _lib.oracle_weno5_face.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int]
         _lib.oracle_vanleer.restype = ctypes.c_double
         _lib.oracle_vanleer.argtypes = [ctypes.c_double, ctypes.c_double]
         _lib.oracle_minmod.restype = ctypes.c_double
@@ -240,6 +242,12 @@ def cons_to_prim(u, gamma: float, small_rho: float = 0.0, small_p: float = 0.0, 
 def fast_speed(w, d: int, gamma: float) -> float:
     w = np.ascontiguousarray(w, dtype=np.float64)
     return lib().oracle_fast_speed(_dp(w), d, gamma)
+
+
+def weno5_face(vm2, vm1, v0, vp1, vp2, z: bool = False) -> float:
+    """WENO value at the face between cells i and i+1 from cells i-2 .. i+2
+    (z: the WENO-Z weights)."""
+    return lib().oracle_weno5_face(vm2, vm1, v0, vp1, vp2, 1 if z else 0)
 
 
 def face_increments(lim: int, dm: float, dp: float):

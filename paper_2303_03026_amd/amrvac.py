@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libamrvac.so")
 NV = 9
 
 FP64, FP32_MIXED = 0, 1
-LIM_VANLEER, LIM_KOREN, LIM_CADA3 = 0, 1, 2
+LIM_VANLEER, LIM_KOREN, LIM_CADA3, LIM_WENO5, LIM_WENOZ5 = 0, 1, 2, 3, 4
 FLUX_HLL, FLUX_HLLD, FLUX_HLLC = 0, 1, 2
 PATH_PLAIN, PATH_FUSED = 0, 1
 FLAG_SMALL_RHO, FLAG_SMALL_P, FLAG_BAD_DT = 1, 2, 4
@@ -210,7 +210,11 @@ class Simulation:
             raise AmrvacError(rc, self.lib.amrvac_last_error(None).decode())
         self.ctx = ctx
         if path != PATH_PLAIN:
-            self.set_path(path)
+            try:
+                self.set_path(path)
+            except AmrvacError:
+                self.close()
+                raise
         if set_initial:
             self.set_primitive(w.prim)
 

@@ -147,7 +147,7 @@ __device__ __forceinline__ R vl_slope(R dm, R dp) {
 //   koren:  s max(0, min(2a, (2b + a)/3, 2b))
 //   cada3:  s max(0, min((2b + a)/3, max(-a/2, min(2a, (2b + a)/3, 1.6 b))))
 // (the unlimited third-order value (2b + a)/3 in smooth monotone regions).
-enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2 };
+enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2, LIM_WENO5 = 3, LIM_WENOZ5 = 4 };
 
 template <int LIM, class R>
 __device__ __forceinline__ R lim_diff(R near, R far) {
@@ -492,6 +492,36 @@ __device__ __forceinline__ void reconstruct_face_lim(const R wm[NV], const R wa[
   positivity_fallback(wl, wr, wa, wb);
 }
 
+// Fifth-order WENO value at the face between cells i and i+1 seen from cell i
+// (cells i-2 .. i+2; 3 ghost layers): candidate polynomials q_k, smoothness
+// indicators beta_k, optimal weights (0.1, 0.6, 0.3); Jiang-Shu weights
+// d_k / (1e-6 + beta_k)^2, or with z the WENO-Z weights
+// d_k (1 + |beta_0 - beta_2| / (beta_k + 1e-40)).
+__device__ __forceinline__ double weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, bool z) {
+  const double q0 = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) * (1.0 / 6.0);
+  const double q1 = (-vm1 + 5.0 * v0 + 2.0 * vp1) * (1.0 / 6.0);
+  const double q2 = (2.0 * v0 + 5.0 * vp1 - vp2) * (1.0 / 6.0);
+  const double a0 = vm2 - 2.0 * vm1 + v0, b0 = vm2 - 4.0 * vm1 + 3.0 * v0;
+  const double a1 = vm1 - 2.0 * v0 + vp1, b1 = vm1 - vp1;
+  const double a2 = v0 - 2.0 * vp1 + vp2, b2 = 3.0 * v0 - 4.0 * vp1 + vp2;
+  const double be0 = (13.0 / 12.0) * a0 * a0 + 0.25 * b0 * b0;
+  const double be1 = (13.0 / 12.0) * a1 * a1 + 0.25 * b1 * b1;
+  const double be2 = (13.0 / 12.0) * a2 * a2 + 0.25 * b2 * b2;
+  double al0, al1, al2;
+  if (z) {
+    const double tau5 = fabs(be0 - be2);
+    al0 = 0.1 * (1.0 + div_(tau5, be0 + 1e-40));
+    al1 = 0.6 * (1.0 + div_(tau5, be1 + 1e-40));
+    al2 = 0.3 * (1.0 + div_(tau5, be2 + 1e-40));
+  } else {
+    const double e0 = 1e-6 + be0, e1 = 1e-6 + be1, e2 = 1e-6 + be2;
+    al0 = div_(0.1, e0 * e0);
+    al1 = div_(0.6, e1 * e1);
+    al2 = div_(0.3, e2 * e2);
+  }
+  return div_(al0 * q0 + al1 * q1 + al2 * q2, al0 + al1 + al2);
+}
+
 // the same with the limiter chosen at run time (the per-kernel path and the
 // coarse/fine flux correction)
 template <class R>
@@ -503,6 +533,24 @@ __device__ __forceinline__ void reconstruct_face(int lim, const R wm[NV], const 
     reconstruct_face_lim<LIM_CADA3>(wm, wa, wb, wp, wl, wr);
   else
     reconstruct_face_lim<LIM_VANLEER>(wm, wa, wb, wp, wl, wr);
+}
+
+// Face states from the six cells c[0..5] around the face between c[2] and
+// c[3] (3 ghost layers): the fifth-order WENO values for 'weno5' / 'wenoz5',
+// else the two-ghost-layer reconstruction from c[1..4]; first-order fallback
+// as always.
+__device__ __forceinline__ void reconstruct_face6(int lim, const double c[6][NV], double wl[NV], double wr[NV]) {
+  if (lim == LIM_WENO5 || lim == LIM_WENOZ5) {
+    const bool z = lim == LIM_WENOZ5;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      wl[q] = weno5_face(c[0][q], c[1][q], c[2][q], c[3][q], c[4][q], z);
+      wr[q] = weno5_face(c[5][q], c[4][q], c[3][q], c[2][q], c[1][q], z);
+    }
+    positivity_fallback(wl, wr, c[2], c[3]);
+  } else {
+    reconstruct_face(lim, c[1], c[2], c[3], c[4], wl, wr);
+  }
 }
 
 // ---------------------------------------------------------------------------

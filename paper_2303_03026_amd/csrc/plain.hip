@@ -259,23 +259,35 @@ __global__ void __launch_bounds__(256) k_flux(GridConst G, const double* __restr
     k = 0;
   }
   const double* base = prim + (long)b * NV * G.pcells;
-  double wm[NV], wa[NV], wb[NV], wp[NV];
-  long idx[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int a = f - 2 + s;
-    idx[s] = D == 0 ? pidx(G, a, j, k) : (D == 1 ? pidx(G, i, a, k) : pidx(G, i, j, a));
-  }
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const double* p = base + q * G.pcells;
-    wm[q] = p[idx[0]];
-    wa[q] = p[idx[1]];
-    wb[q] = p[idx[2]];
-    wp[q] = p[idx[3]];
-  }
   double wl[NV], wr[NV], F[NV];
-  reconstruct_face(P.limiter, wm, wa, wb, wp, wl, wr);
+  if (G.ng == 3) {  // six-cell stencil f-3 .. f+2
+    double c6[6][NV];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int a = f - 3 + s;
+      const long ix = D == 0 ? pidx(G, a, j, k) : (D == 1 ? pidx(G, i, a, k) : pidx(G, i, j, a));
+#pragma unroll
+      for (int q = 0; q < NV; ++q) c6[s][q] = base[q * G.pcells + ix];
+    }
+    reconstruct_face6(P.limiter, c6, wl, wr);
+  } else {
+    double wm[NV], wa[NV], wb[NV], wp[NV];
+    long idx[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int a = f - 2 + s;
+      idx[s] = D == 0 ? pidx(G, a, j, k) : (D == 1 ? pidx(G, i, a, k) : pidx(G, i, j, a));
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double* p = base + q * G.pcells;
+      wm[q] = p[idx[0]];
+      wa[q] = p[idx[1]];
+      wb[q] = p[idx[2]];
+      wp[q] = p[idx[3]];
+    }
+    reconstruct_face(P.limiter, wm, wa, wb, wp, wl, wr);
+  }
   const double ch = *ch_dev;
   face_flux_rt<D, double>(P.flux, wl, wr, ch, 0.5 / ch, P.gamma, P.inv_gm1, F);
   double* out = flux + (long)b * NV * G.nfaces + fi;
@@ -389,10 +401,8 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
                                                     int t2, typename SP::R ch, typename SP::R hic,
                                                     const PhysConst& P, typename SP::R F[NV]) {
   using R = typename SP::R;
-  R w4[4][NV];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int a = f - 2 + s;
+  R wl[NV], wr[NV];
+  auto cell = [&](int a, R w[NV]) {
     long c;
     if (D == 0) c = pidx(G, a, t1, t2);
     else if (D == 1) c = pidx(G, t1, a, t2);
@@ -400,9 +410,12 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
     double u[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) u[q] = SP::ld(S, q, c, G.pcells);
-    (void)cons_to_prim(u, w4[s], P);
-  }
-  R wl[NV], wr[NV];
+    (void)cons_to_prim(u, w, P);
+  };
+  // (the fused path, the only user, has 2 ghost layers: a four-cell stencil)
+  R w4[4][NV];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) cell(f - 2 + s, w4[s]);
   reconstruct_face(P.limiter, w4[0], w4[1], w4[2], w4[3], wl, wr);
   face_flux_rt<D, R>(P.flux, wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
 }

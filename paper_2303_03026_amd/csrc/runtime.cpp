@@ -57,7 +57,7 @@ struct JobRec {
 int check_desc(const amrvac_grid_desc* g, std::string* why) {
   if (!g) { *why = "null descriptor"; return AMRVAC_E_ARG; }
   if (g->ndim != 2 && g->ndim != 3) { *why = "ndim must be 2 or 3"; return AMRVAC_E_ARG; }
-  if (g->nghost != 2) { *why = "nghost must be 2 (van Leer stencil)"; return AMRVAC_E_ARG; }
+  if (g->nghost != 2 && g->nghost != 3) { *why = "nghost must be 2 or 3"; return AMRVAC_E_ARG; }
   if (g->block_nx < 4 || g->block_nx > 16 || (g->block_nx & 1)) { *why = "block_nx must be even, 4..16"; return AMRVAC_E_ARG; }
   if (g->precision != AMRVAC_FP64 && g->precision != AMRVAC_FP32_MIXED) { *why = "bad precision"; return AMRVAC_E_ARG; }
   for (int d = 0; d < g->ndim; ++d) {
@@ -73,8 +73,13 @@ int check_desc(const amrvac_grid_desc* g, std::string* why) {
     }
   }
   if (!(g->gamma > 1.0) || !(g->cfl > 0.0) || !(g->glm_alpha >= 0.0)) { *why = "bad gamma/cfl/glm_alpha"; return AMRVAC_E_ARG; }
-  if (g->limiter < AMRVAC_LIM_VANLEER || g->limiter > AMRVAC_LIM_CADA3) { *why = "bad limiter"; return AMRVAC_E_ARG; }
+  if (g->limiter < AMRVAC_LIM_VANLEER || g->limiter > AMRVAC_LIM_WENOZ5) { *why = "bad limiter"; return AMRVAC_E_ARG; }
+  if (g->limiter >= AMRVAC_LIM_WENO5 && g->nghost != 3) { *why = "weno5 / wenoz5 need nghost = 3"; return AMRVAC_E_ARG; }
   if (g->flux < AMRVAC_FLUX_HLL || g->flux > AMRVAC_FLUX_HLLC) { *why = "bad flux scheme"; return AMRVAC_E_ARG; }
+  if (g->precision == AMRVAC_FP32_MIXED && (g->block_nx != 16 || g->nghost != 2)) {
+    *why = "FP32-mixed storage runs on the fused path, which needs block_nx = 16 and nghost = 2";
+    return AMRVAC_E_ARG;
+  }
   return AMRVAC_OK;
 }
 
@@ -756,10 +761,6 @@ int create_single(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, const int
   *out = nullptr;
   std::string why;
   if (check_desc(g, &why) != AMRVAC_OK) { g_init_err = why; return AMRVAC_E_ARG; }
-  if (g->precision == AMRVAC_FP32_MIXED && g->block_nx != 16) {
-    g_init_err = "FP32-mixed storage runs on the fused path, which needs block_nx = 16";
-    return AMRVAC_E_ARG;
-  }
   if (nb < 1 || !level || !ijk || !slots || nslots < 1) { g_init_err = "need blocks, tables and slots"; return AMRVAC_E_ARG; }
   for (int s = 0; s < nslots; ++s)
     if (!slots[s]) { g_init_err = "null slot pointer"; return AMRVAC_E_ARG; }
@@ -1130,6 +1131,7 @@ int amrvac_set_path(amrvac_ctx* c, int path) {
   if (!c) return AMRVAC_E_ARG;
   if (path != AMRVAC_PATH_PLAIN && path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_ARG, "unknown path");
   if (path == AMRVAC_PATH_FUSED && c->G.nx != 16) return fail(c, AMRVAC_E_ARG, "the fused path needs block_nx = 16");
+  if (path == AMRVAC_PATH_FUSED && c->G.ng != 2) return fail(c, AMRVAC_E_ARG, "the fused path needs nghost = 2");
   if (path == AMRVAC_PATH_PLAIN && (c->g.precision != AMRVAC_FP64 || c->batch))
     return fail(c, AMRVAC_E_ARG, "the plain path is for single-job FP64 contexts");
   c->path = path;
@@ -1300,7 +1302,10 @@ int amrvac_batch_create(amrvac_ctx** out, const amrvac_grid_desc* shape, int cap
   *out = nullptr;
   std::string why;
   if (check_desc(shape, &why) != AMRVAC_OK) { g_init_err = why; return AMRVAC_E_ARG; }
-  if (shape->block_nx != 16) { g_init_err = "batch contexts run the fused path: block_nx must be 16"; return AMRVAC_E_ARG; }
+  if (shape->block_nx != 16 || shape->nghost != 2) {
+    g_init_err = "batch contexts run the fused path: block_nx must be 16 and nghost 2";
+    return AMRVAC_E_ARG;
+  }
   if (capacity_blocks < 1 || max_jobs < 1 || nstages < 2 || nstages > 5 || !slots) {
     g_init_err = "bad capacity, job count, stage count or slots";
     return AMRVAC_E_ARG;

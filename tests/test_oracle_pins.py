@@ -1063,3 +1063,119 @@ def test_hllc_uniform_and_conservation(orc, ndim):
     t1 = _totals(w, sim.cons())
     rel = np.abs(t1 - t0) / _scale(w, u0)
     assert np.all(rel[[RHO, VX, VY, VZ, PR, BX, BY, BZ]] < 1e-13), rel
+
+
+# ---------------------------------------------------------------------------
+# fifth-order WENO reconstructions on 3 ghost layers
+
+
+@pytest.mark.parametrize("z", [False, True])
+def test_weno_reconstruction_is_fifth_order(orc, z):
+    """Face values of sin(2 pi x) from its exact cell averages: the largest
+    error shrinks by 2^5 per halving of h."""
+    def err(n):
+        h = 1.0 / n
+        xs = (np.arange(n) + 0.5) * h
+        avg = (np.cos(2 * np.pi * (xs - h / 2)) - np.cos(2 * np.pi * (xs + h / 2))) / (2 * np.pi * h)
+        return max(abs(orc.weno5_face(*avg[i - 2:i + 3], z=z) - math.sin(2 * math.pi * (xs[i] + h / 2)))
+                   for i in range(2, n - 2))
+    e = [err(n) for n in (32, 64, 128)]
+    assert all(math.log2(e[i] / e[i + 1]) > 4.8 for i in range(2)), e
+
+
+@pytest.mark.parametrize("z", [False, True])
+def test_weno_is_essentially_non_oscillatory_at_a_jump(orc, z):
+    """Across a unit step the face values stay within the data range up to
+    the small-epsilon leak (the smooth one-sided stencil takes the weight)."""
+    for k in range(5):
+        v = [0.0] * (5 - k) + [1.0] * k  # the step at every position of the stencil
+        f = orc.weno5_face(*v, z=z)
+        assert -1e-6 <= f <= 1.0 + 1e-6, (k, f)
+    # linear data are reproduced exactly by every candidate, hence by WENO
+    assert orc.weno5_face(1.0, 2.0, 3.0, 4.0, 5.0, z=z) == pytest.approx(3.5, rel=1e-14)
+
+
+def _weno(w, lim):
+    w.limiter = lim
+    w.ng = 3
+    return w
+
+
+@pytest.mark.parametrize("lim", [3, 4])
+def test_weno_alfven_wave(orc, lim):
+    def err(n, lm, ng):
+        w = inputs.alfven_wave(n, 2)
+        w.limiter, w.ng = lm, ng
+        sim = orc.OracleSim(w)
+        sim.steps_to_time(1.0 / math.sqrt(2.0))
+        e = np.mean(np.abs(sim.cons()[:, BZ] - w.prim[:, BZ])) / 1e-6
+        sim.close()
+        return e
+    e64, e128 = err(64, lim, 3), err(128, lim, 3)
+    assert math.log2(e64 / e128) >= 2.8, (e64, e128)  # measured 3.16
+    assert e128 < 0.01 * err(128, 0, 2), e128  # measured 1.06e-6 against 3.0e-3
+
+
+@pytest.mark.parametrize("lim", [3, 4])
+def test_weno_sod(orc, lim):
+    import exact_riemann as er
+
+    def l1(n, lm, ng):
+        w = inputs.sod(n, ndim=2)
+        w.limiter, w.ng = lm, ng
+        sim = orc.OracleSim(w)
+        sim.steps_to_time(0.2)
+        g = inputs.blocks_to_global(sim.cons().swapaxes(0, 1), 2, w.nx, w.base_blocks)[RHO]
+        sim.close()
+        ex = er.cell_average_density(n, 0.2, 0.5, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+        return np.mean(np.abs(g[0] - ex))
+    errs = [l1(n, lim, 3) for n in (64, 128, 256)]
+    assert min(math.log2(errs[i] / errs[i + 1]) for i in range(2)) >= 0.6, errs
+    assert all(e < l1(n, 0, 2) for e, n in zip(errs, (64, 128, 256))), errs
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_weno_uniform_and_conservation(orc, ndim):
+    w = _weno(inputs.uniform_state(ndim, (3, 2, 2), _uniform_w()), 3)
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    sim.steps(3)
+    assert np.array_equal(sim.cons(), u0)
+    w = _weno(inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5 if ndim == 2 else 7), 4)
+    sim = orc.OracleSim(w)
+    u0 = sim.cons()
+    t0 = _totals(w, u0)
+    sim.steps(3 if ndim == 3 else 10)
+    t1 = _totals(w, sim.cons())
+    rel = np.abs(t1 - t0) / _scale(w, u0)
+    assert np.all(rel[[RHO, VX, VY, VZ, PR, BX, BY, BZ]] < 1e-13), rel
+
+
+def test_three_ghost_layers_change_nothing_for_two_layer_limiters(orc):
+    """A third ghost layer is filled but never read by the 2-layer stencils:
+    the results are bit-identical (AMR hierarchy, reflux included)."""
+    outs = []
+    for ng in (2, 3):
+        w = inputs.smooth_amr_state(3, nb1=2, seed=7)
+        w.ng = ng
+        sim = orc.OracleSim(w)
+        sim.steps(3)
+        outs.append(sim.cons())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_wenoz_weights_jump_where_the_outer_stencils_are_equally_rough(orc):
+    """A plateau between two equal jumps, (1, 2, 2, 2, 3): the outer
+    smoothness indicators are equal, so WENO-Z's tau5 = |beta_0 - beta_2| is
+    exactly zero and the weights fall back to the linear ones (the
+    fifth-order value 115/60); one ulp more on the last cell makes tau5
+    nonzero while the middle stencil is exactly smooth (beta_1 = 0), and with
+    eps = 1e-40 its weight jumps to one (value 2).  Jiang-Shu's eps = 1e-6
+    keeps its weights continuous.  This is why WENO-Z parity runs use data
+    without exact plateaus (piecewise-constant initial states are given a
+    small seeded perturbation)."""
+    v = [1.0, 2.0, 2.0, 2.0, 3.0]
+    vp = v[:4] + [float(np.nextafter(3.0, 4.0))]
+    assert orc.weno5_face(*v, z=True) == pytest.approx(115.0 / 60.0, abs=1e-15)
+    assert orc.weno5_face(*vp, z=True) == pytest.approx(2.0, abs=1e-15)
+    assert abs(orc.weno5_face(*v, z=False) - orc.weno5_face(*vp, z=False)) < 1e-15
