@@ -89,7 +89,7 @@ def measured_traffic(precision, tune, workload, n):
 # not 1; one state is 72 B per cell in FP64 and 40 B in FP32-mixed.
 
 
-LIMITERS = ("vanleer", "koren", "cada3", "weno5", "wenoz5")
+LIMITERS = ("vanleer", "koren", "cada3", "weno5", "wenoz5", "mp5", "wenozp5")
 
 
 def parse():
@@ -103,7 +103,7 @@ def parse():
                     help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
     ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud"], default="random_modes")
     ap.add_argument("--limiter", choices=list(LIMITERS), default="vanleer",
-                    help="weno5 / wenoz5 need 3 ghost layers: FP64 plain path only")
+                    help="weno5 / wenoz5 / mp5 / wenozp5 need 3 ghost layers: FP64 plain path only")
     ap.add_argument("--flux", choices=["hll", "hlld", "hllc"], default="hll")
     ap.add_argument("--regrid", action="store_true",
                     help="also time one regrid (coarsen the top level, refine every eighth block below)")
@@ -185,9 +185,9 @@ def main():
     w.limiter = LIMITERS.index(args.limiter)
     w.flux = {"hll": 0, "hlld": 1, "hllc": 2}[args.flux]
     mixed = args.precision == "mixed"
-    if w.limiter >= 3:  # the five-cell WENO stencils: 3 ghost layers, plain FP64 path
+    if w.limiter >= 3:  # the five-cell stencils: 3 ghost layers, plain FP64 path
         if mixed:
-            sys.exit("bench: WENO reconstructions run on the FP64 plain path only")
+            sys.exit("bench: the fifth-order reconstructions run on the FP64 plain path only")
         w.ng = 3
         args.path = "plain"
     if mixed:

@@ -68,11 +68,15 @@ enum { AMRVAC_PATH_PLAIN = 0, AMRVAC_PATH_FUSED = 1 };
  * face values are w + phi d+ / 2 and w - phi' d- / 2; koren and cada3 give
  * the unlimited third-order values (2 d+ + d-)/6 and (2 d- + d+)/6 in smooth
  * monotone regions. */
-enum { AMRVAC_LIM_VANLEER = 0, AMRVAC_LIM_KOREN = 1, AMRVAC_LIM_CADA3 = 2, AMRVAC_LIM_WENO5 = 3, AMRVAC_LIM_WENOZ5 = 4 };
+enum { AMRVAC_LIM_VANLEER = 0, AMRVAC_LIM_KOREN = 1, AMRVAC_LIM_CADA3 = 2, AMRVAC_LIM_WENO5 = 3, AMRVAC_LIM_WENOZ5 = 4,
+       AMRVAC_LIM_MP5 = 5, AMRVAC_LIM_WENOZP5 = 6 };
 /* The fifth-order reconstructions of Table t:limiters on 3 ghost cells
- * (nghost = 3; the per-kernel FP64 path only): 'weno5' (Jiang and Shu 1996,
- * eps = 1e-6) and 'wenoz5' (Borges et al. 2008, WENO-Z weights, eps =
- * 1e-40), each face value from the five cells on its side. */
+ * (nghost = 3; the per-kernel FP64 path only), each face value from the five
+ * cells on its side: 'weno5' (Jiang and Shu 1996, eps = 1e-6), 'wenoz5'
+ * (Borges et al. 2008, WENO-Z weights, eps = 1e-40), 'wenozp5' (Acker et al.
+ * 2016, WENO-Z+ weights with lambda = dx^(2/3) of the block, eps = 1e-40) and
+ * 'mp5' (Suresh and Huynh 1997, monotonicity-preserving bounds with
+ * alpha = 4). */
 /* Interface flux schemes (Table tab:schemes_space), all on top of the GLM
  * interface values of (B_n, psi): HLL with Davis speed bounds; HLLD
  * (Miyoshi and Kusano 2005: contact, Alfven and fast waves, resolving

@@ -12,8 +12,9 @@
 //     tab:schemes_time: SSPRK(2,2), SSPRK(3,3), SSPRK(4,3) and SSPRK(5,4));
 //   * limited linear reconstruction of primitive variables giving a left and
 //     a right state per face, with the 'vanleer', 'koren' or 'cada3'
-//     limiter and 2 ghost cells, or the fifth-order 'weno5' / 'wenoz5'
-//     reconstructions with 3 ghost cells (Table t:limiters);
+//     limiter and 2 ghost cells, or the fifth-order 'weno5' / 'wenoz5' /
+//     'wenozp5' / 'mp5' reconstructions with 3 ghost cells (Table
+//     t:limiters);
 //   * the HLL flux (Table tab:schemes_space; Harten et al. 1983), or HLLD
 //     (Miyoshi and Kusano 2005), or HLLC (Li 2005);
 //   * the 'glm' divergence control of Dedner et al. 2002 (Table t:divb);
@@ -177,7 +178,10 @@ double cada3_phi(double th) {
   return std::max(0.0, std::min(p3, std::max(-0.5 * th, std::min(std::min(2.0 * th, p3), 1.6))));
 }
 
-enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2, LIM_WENO5 = 3, LIM_WENOZ5 = 4 };
+enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2, LIM_WENO5 = 3, LIM_WENOZ5 = 4, LIM_MP5 = 5, LIM_WENOZP5 = 6 };
+enum { WENO_JS = 0, WENO_Z = 1, WENO_ZP = 2 };
+
+bool five_cell_limiter(int lim) { return lim >= LIM_WENO5 && lim <= LIM_WENOZP5; }
 
 // Fifth-order WENO value at the face between cells i and i+1, seen from cell
 // i, from cells i-2 .. i+2 (the 'weno5' and 'wenoz5' rows of Table
@@ -186,7 +190,10 @@ enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2, LIM_WENO5 = 3, LIM_WENOZ5 
 // (0.1, 0.6, 0.3).  'weno5' (Jiang and Shu 1996): alpha_k = d_k / (eps +
 // beta_k)^2 with eps = 1e-6.  'wenoz5' (Borges et al. 2008): alpha_k = d_k
 // (1 + tau5 / (beta_k + eps)) with tau5 = |beta_0 - beta_2|, eps = 1e-40.
-double weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, bool z) {
+// 'wenozp5' (Acker et al. 2016): alpha_k = d_k (1 + (tau5 / (beta_k +
+// eps))^2 + lambda (beta_k + eps) / (tau5 + eps)) with lambda = dx^(2/3),
+// eps = 1e-40.
+double weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, int kind, double lambda) {
   const double q0 = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) / 6.0;
   const double q1 = (-vm1 + 5.0 * v0 + 2.0 * vp1) / 6.0;
   const double q2 = (2.0 * v0 + 5.0 * vp1 - vp2) / 6.0;
@@ -197,14 +204,68 @@ double weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, boo
                           13.0 / 12.0 * a2 * a2 + 0.25 * b2 * b2};
   const double d[3] = {0.1, 0.6, 0.3};
   double alpha[3];
-  if (z) {
+  if (kind == WENO_Z) {
     const double tau5 = std::fabs(beta[0] - beta[2]);
     for (int k = 0; k < 3; ++k) alpha[k] = d[k] * (1.0 + tau5 / (beta[k] + 1e-40));
+  } else if (kind == WENO_ZP) {
+    const double tau5 = std::fabs(beta[0] - beta[2]);
+    for (int k = 0; k < 3; ++k) {
+      const double r = tau5 / (beta[k] + 1e-40);
+      alpha[k] = d[k] * (1.0 + r * r + lambda * (beta[k] + 1e-40) / (tau5 + 1e-40));
+    }
   } else {
     for (int k = 0; k < 3; ++k) alpha[k] = d[k] / ((1e-6 + beta[k]) * (1e-6 + beta[k]));
   }
   const double sum = alpha[0] + alpha[1] + alpha[2];
   return (alpha[0] * q0 + alpha[1] * q1 + alpha[2] * q2) / sum;
+}
+
+double minmod2(double a, double b) {
+  if (a > 0.0 && b > 0.0) return std::min(a, b);
+  if (a < 0.0 && b < 0.0) return std::max(a, b);
+  return 0.0;
+}
+
+double minmod4(double a, double b, double c, double d) {
+  if (a > 0.0 && b > 0.0 && c > 0.0 && d > 0.0) return std::min(std::min(a, b), std::min(c, d));
+  if (a < 0.0 && b < 0.0 && c < 0.0 && d < 0.0) return std::max(std::max(a, b), std::max(c, d));
+  return 0.0;
+}
+
+// Monotonicity-preserving fifth-order value at the face between cells i and
+// i+1 seen from cell i, from cells i-2 .. i+2 (the 'mp5' row of Table
+// t:limiters; Suresh and Huynh 1997).  The fifth-order interpolant u_or is
+// kept when it lies between u_i and the monotonicity bound u_mp = u_i +
+// minmod(u_{i+1} - u_i, 4 (u_i - u_{i-1})); otherwise it is limited to the
+// interval [u_min, u_max] built from the upper limit u_ul, the median u_md
+// and the large-curvature value u_lc, with the curvatures d measured by the
+// four-argument minmod of neighbouring second differences.  The acceptance
+// test is taken without a round-off epsilon.
+double mp5_face(double vm2, double vm1, double v0, double vp1, double vp2) {
+  const double alpha = 4.0;
+  const double u_or = (2.0 * vm2 - 13.0 * vm1 + 47.0 * v0 + 27.0 * vp1 - 3.0 * vp2) / 60.0;
+  const double u_mp = v0 + minmod2(vp1 - v0, alpha * (v0 - vm1));
+  if ((u_or - v0) * (u_or - u_mp) <= 0.0) return u_or;
+  const double dm1 = vm2 - 2.0 * vm1 + v0;  // second differences at i-1, i, i+1
+  const double d0 = vm1 - 2.0 * v0 + vp1;
+  const double dp1 = v0 - 2.0 * vp1 + vp2;
+  const double dm4_plus = minmod4(4.0 * d0 - dp1, 4.0 * dp1 - d0, d0, dp1);
+  const double dm4_minus = minmod4(4.0 * d0 - dm1, 4.0 * dm1 - d0, d0, dm1);
+  const double u_ul = v0 + alpha * (v0 - vm1);
+  const double u_av = 0.5 * (v0 + vp1);
+  const double u_md = u_av - 0.5 * dm4_plus;
+  const double u_lc = v0 + 0.5 * (v0 - vm1) + 4.0 / 3.0 * dm4_minus;
+  const double u_min = std::max(std::min(std::min(v0, vp1), u_md), std::min(std::min(v0, u_ul), u_lc));
+  const double u_max = std::min(std::max(std::max(v0, vp1), u_md), std::max(std::max(v0, u_ul), u_lc));
+  // the median of u_or, u_min and u_max
+  return u_or + minmod2(u_min - u_or, u_max - u_or);
+}
+
+// One of the fifth-order face values above by limiter id.
+double five_cell_face(int lim, double vm2, double vm1, double v0, double vp1, double vp2, double lambda) {
+  if (lim == LIM_MP5) return mp5_face(vm2, vm1, v0, vp1, vp2);
+  const int kind = lim == LIM_WENOZ5 ? WENO_Z : (lim == LIM_WENOZP5 ? WENO_ZP : WENO_JS);
+  return weno5_face(vm2, vm1, v0, vp1, vp2, kind, lambda);
 }
 
 // The two face values of a cell with backward and forward differences dm, dp:
@@ -493,7 +554,7 @@ typedef struct {
   double glm_alpha;
   double small_density;
   double small_pressure;
-  int limiter;  // 0 = 'vanleer', 1 = 'koren', 2 = 'cada3', 3 = 'weno5', 4 = 'wenoz5'
+  int limiter;  // 0 'vanleer', 1 'koren', 2 'cada3', 3 'weno5', 4 'wenoz5', 5 'mp5', 6 'wenozp5'
   int flux;     // 0 = HLL, 1 = HLLD, 2 = HLLC
 } oracle_params;
 
@@ -734,15 +795,15 @@ struct Sim {
               const Cell& wp = at(f);
               const Cell& wpp = at(f + 1);
               Cell wl, wr;
-              if (P.limiter == LIM_WENO5 || P.limiter == LIM_WENOZ5) {
+              if (five_cell_limiter(P.limiter)) {
                 // five-point stencils f-3 .. f+1 (left state) and f+2 .. f-2
                 // (right state, mirrored)
-                const bool z = P.limiter == LIM_WENOZ5;
+                const double lambda = std::pow(dx(lev[b], d), 2.0 / 3.0);
                 const Cell& wm3 = at(f - 3);
                 const Cell& wp2 = at(f + 2);
                 for (int q = 0; q < NV; ++q) {
-                  wl.v[q] = weno5_face(wm3.v[q], wmm.v[q], wm.v[q], wp.v[q], wpp.v[q], z);
-                  wr.v[q] = weno5_face(wp2.v[q], wpp.v[q], wp.v[q], wm.v[q], wmm.v[q], z);
+                  wl.v[q] = five_cell_face(P.limiter, wm3.v[q], wmm.v[q], wm.v[q], wp.v[q], wpp.v[q], lambda);
+                  wr.v[q] = five_cell_face(P.limiter, wp2.v[q], wpp.v[q], wp.v[q], wm.v[q], wmm.v[q], lambda);
                 }
               } else {
                 for (int q = 0; q < NV; ++q) {
@@ -972,8 +1033,8 @@ Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int*
   if (s->ng != 2 && s->ng != 3) throw std::invalid_argument("ghost layers must be 2 or 3");
   if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
   if (p->nstages < 1 || p->nstages > 5) throw std::invalid_argument("nstages must be 1 .. 5");
-  if (p->limiter < LIM_VANLEER || p->limiter > LIM_WENOZ5) throw std::invalid_argument("unknown limiter");
-  if ((p->limiter == LIM_WENO5 || p->limiter == LIM_WENOZ5) && p->ng != 3)
+  if (p->limiter < LIM_VANLEER || p->limiter > LIM_WENOZP5) throw std::invalid_argument("unknown limiter");
+  if (five_cell_limiter(p->limiter) && p->ng != 3)
     throw std::invalid_argument("the fifth-order reconstructions need 3 ghost layers");
   if (p->flux != FLUX_HLL && p->flux != FLUX_HLLD && p->flux != FLUX_HLLC) throw std::invalid_argument("unknown flux scheme");
   if (s->P.nthreads < 1) s->P.nthreads = 1;
@@ -1245,8 +1306,12 @@ double oracle_fast_speed(const double* w, int d, double gamma) {
 }
 double oracle_vanleer(double dm, double dp) { return vanleer(dm, dp); }
 double oracle_minmod(double a, double b) { return minmod(a, b); }
-double oracle_weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, int z) {
-  return weno5_face(vm2, vm1, v0, vp1, vp2, z != 0);
+double oracle_weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, int kind, double lambda) {
+  return weno5_face(vm2, vm1, v0, vp1, vp2, kind, lambda);
+}
+
+double oracle_mp5_face(double vm2, double vm1, double v0, double vp1, double vp2) {
+  return mp5_face(vm2, vm1, v0, vp1, vp2);
 }
 int oracle_face_increments(int lim, double dm, double dp, double* inc_right, double* inc_left) {
   if (lim < LIM_VANLEER || lim > LIM_CADA3) return -1;

@@ -66,7 +66,9 @@ def lib():
         _lib.oracle_fast_speed.argtypes = [dp, ctypes.c_int, ctypes.c_double]
         _lib.oracle_face_increments.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
         _lib.oracle_weno5_face.restype = ctypes.c_double
-        _lib.oracle_weno5_face.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int]
+        _lib.oracle_weno5_face.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int, ctypes.c_double]
+        _lib.oracle_mp5_face.restype = ctypes.c_double
+        _lib.oracle_mp5_face.argtypes = [ctypes.c_double] * 5
         _lib.oracle_vanleer.restype = ctypes.c_double
         _lib.oracle_vanleer.argtypes = [ctypes.c_double, ctypes.c_double]
         _lib.oracle_minmod.restype = ctypes.c_double
@@ -244,10 +246,16 @@ def fast_speed(w, d: int, gamma: float) -> float:
     return lib().oracle_fast_speed(_dp(w), d, gamma)
 
 
-def weno5_face(vm2, vm1, v0, vp1, vp2, z: bool = False) -> float:
+def weno5_face(vm2, vm1, v0, vp1, vp2, z: bool = False, zp: bool = False, lam: float = 0.0) -> float:
     """WENO value at the face between cells i and i+1 from cells i-2 .. i+2
-    (z: the WENO-Z weights)."""
-    return lib().oracle_weno5_face(vm2, vm1, v0, vp1, vp2, 1 if z else 0)
+    (z: the WENO-Z weights; zp: the WENO-Z+ weights with lambda = lam)."""
+    return lib().oracle_weno5_face(vm2, vm1, v0, vp1, vp2, 2 if zp else (1 if z else 0), lam)
+
+
+def mp5_face(vm2, vm1, v0, vp1, vp2) -> float:
+    """Monotonicity-preserving fifth-order value at the face between cells i
+    and i+1 from cells i-2 .. i+2."""
+    return lib().oracle_mp5_face(vm2, vm1, v0, vp1, vp2)
 
 
 def face_increments(lim: int, dm: float, dp: float):

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libamrvac.so")
 NV = 9
 
 FP64, FP32_MIXED = 0, 1
-LIM_VANLEER, LIM_KOREN, LIM_CADA3, LIM_WENO5, LIM_WENOZ5 = 0, 1, 2, 3, 4
+LIM_VANLEER, LIM_KOREN, LIM_CADA3, LIM_WENO5, LIM_WENOZ5, LIM_MP5, LIM_WENOZP5 = 0, 1, 2, 3, 4, 5, 6
 FLUX_HLL, FLUX_HLLD, FLUX_HLLC = 0, 1, 2
 PATH_PLAIN, PATH_FUSED = 0, 1
 FLAG_SMALL_RHO, FLAG_SMALL_P, FLAG_BAD_DT = 1, 2, 4

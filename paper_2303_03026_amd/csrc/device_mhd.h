@@ -147,7 +147,7 @@ __device__ __forceinline__ R vl_slope(R dm, R dp) {
 //   koren:  s max(0, min(2a, (2b + a)/3, 2b))
 //   cada3:  s max(0, min((2b + a)/3, max(-a/2, min(2a, (2b + a)/3, 1.6 b))))
 // (the unlimited third-order value (2b + a)/3 in smooth monotone regions).
-enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2, LIM_WENO5 = 3, LIM_WENOZ5 = 4 };
+enum { LIM_VANLEER = 0, LIM_KOREN = 1, LIM_CADA3 = 2, LIM_WENO5 = 3, LIM_WENOZ5 = 4, LIM_MP5 = 5, LIM_WENOZP5 = 6 };
 
 template <int LIM, class R>
 __device__ __forceinline__ R lim_diff(R near, R far) {
@@ -494,10 +494,13 @@ __device__ __forceinline__ void reconstruct_face_lim(const R wm[NV], const R wa[
 
 // Fifth-order WENO value at the face between cells i and i+1 seen from cell i
 // (cells i-2 .. i+2; 3 ghost layers): candidate polynomials q_k, smoothness
-// indicators beta_k, optimal weights (0.1, 0.6, 0.3); Jiang-Shu weights
-// d_k / (1e-6 + beta_k)^2, or with z the WENO-Z weights
-// d_k (1 + |beta_0 - beta_2| / (beta_k + 1e-40)).
-__device__ __forceinline__ double weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, bool z) {
+// indicators beta_k, optimal weights (0.1, 0.6, 0.3).  Weights by limiter:
+// 'weno5' (Jiang-Shu) d_k / (1e-6 + beta_k)^2; 'wenoz5' (Borges et al.)
+// d_k (1 + tau5 / (beta_k + 1e-40)) with tau5 = |beta_0 - beta_2|;
+// 'wenozp5' (Acker et al.) d_k (1 + (tau5 / (beta_k + 1e-40))^2 + lambda
+// (beta_k + 1e-40) / (tau5 + 1e-40)) with lambda = dx^(2/3).
+__device__ __forceinline__ double weno5_face(double vm2, double vm1, double v0, double vp1, double vp2, int lim,
+                                             double lambda) {
   const double q0 = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) * (1.0 / 6.0);
   const double q1 = (-vm1 + 5.0 * v0 + 2.0 * vp1) * (1.0 / 6.0);
   const double q2 = (2.0 * v0 + 5.0 * vp1 - vp2) * (1.0 / 6.0);
@@ -508,11 +511,18 @@ __device__ __forceinline__ double weno5_face(double vm2, double vm1, double v0, 
   const double be1 = (13.0 / 12.0) * a1 * a1 + 0.25 * b1 * b1;
   const double be2 = (13.0 / 12.0) * a2 * a2 + 0.25 * b2 * b2;
   double al0, al1, al2;
-  if (z) {
+  if (lim == LIM_WENOZ5) {
     const double tau5 = fabs(be0 - be2);
     al0 = 0.1 * (1.0 + div_(tau5, be0 + 1e-40));
     al1 = 0.6 * (1.0 + div_(tau5, be1 + 1e-40));
     al2 = 0.3 * (1.0 + div_(tau5, be2 + 1e-40));
+  } else if (lim == LIM_WENOZP5) {
+    const double tau5 = fabs(be0 - be2);
+    const double lt = div_(lambda, tau5 + 1e-40);
+    const double r0 = div_(tau5, be0 + 1e-40), r1 = div_(tau5, be1 + 1e-40), r2 = div_(tau5, be2 + 1e-40);
+    al0 = 0.1 * (1.0 + r0 * r0 + lt * (be0 + 1e-40));
+    al1 = 0.6 * (1.0 + r1 * r1 + lt * (be1 + 1e-40));
+    al2 = 0.3 * (1.0 + r2 * r2 + lt * (be2 + 1e-40));
   } else {
     const double e0 = 1e-6 + be0, e1 = 1e-6 + be1, e2 = 1e-6 + be2;
     al0 = div_(0.1, e0 * e0);
@@ -520,6 +530,35 @@ __device__ __forceinline__ double weno5_face(double vm2, double vm1, double v0, 
     al2 = div_(0.3, e2 * e2);
   }
   return div_(al0 * q0 + al1 * q1 + al2 * q2, al0 + al1 + al2);
+}
+
+__device__ __forceinline__ double mm2(double a, double b) {
+  return (a > 0.0 && b > 0.0) ? fmin(a, b) : ((a < 0.0 && b < 0.0) ? fmax(a, b) : 0.0);
+}
+
+__device__ __forceinline__ double mm4(double a, double b, double c, double d) {
+  const double lo = fmin(fmin(a, b), fmin(c, d)), hi = fmax(fmax(a, b), fmax(c, d));
+  return lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
+}
+
+// Monotonicity-preserving fifth-order face value ('mp5', Suresh and Huynh):
+// the fifth-order interpolant unless it leaves the interval between u_i and
+// u_i + minmod(u_{i+1} - u_i, 4 (u_i - u_{i-1})); then its median with the
+// bounds u_min, u_max built from curvature-limited second differences.
+__device__ __forceinline__ double mp5_face(double vm2, double vm1, double v0, double vp1, double vp2) {
+  const double u_or = (2.0 * vm2 - 13.0 * vm1 + 47.0 * v0 + 27.0 * vp1 - 3.0 * vp2) * (1.0 / 60.0);
+  const double back = v0 - vm1;
+  const double u_mp = v0 + mm2(vp1 - v0, 4.0 * back);
+  if ((u_or - v0) * (u_or - u_mp) <= 0.0) return u_or;
+  const double dm1 = vm2 - 2.0 * vm1 + v0, d0 = vm1 - 2.0 * v0 + vp1, dp1 = v0 - 2.0 * vp1 + vp2;
+  const double cp = mm4(4.0 * d0 - dp1, 4.0 * dp1 - d0, d0, dp1);
+  const double cm = mm4(4.0 * d0 - dm1, 4.0 * dm1 - d0, d0, dm1);
+  const double u_ul = v0 + 4.0 * back;
+  const double u_md = 0.5 * (v0 + vp1) - 0.5 * cp;
+  const double u_lc = v0 + 0.5 * back + (4.0 / 3.0) * cm;
+  const double u_min = fmax(fmin(fmin(v0, vp1), u_md), fmin(fmin(v0, u_ul), u_lc));
+  const double u_max = fmin(fmax(fmax(v0, vp1), u_md), fmax(fmax(v0, u_ul), u_lc));
+  return u_or + mm2(u_min - u_or, u_max - u_or);
 }
 
 // the same with the limiter chosen at run time (the per-kernel path and the
@@ -536,16 +575,24 @@ __device__ __forceinline__ void reconstruct_face(int lim, const R wm[NV], const 
 }
 
 // Face states from the six cells c[0..5] around the face between c[2] and
-// c[3] (3 ghost layers): the fifth-order WENO values for 'weno5' / 'wenoz5',
-// else the two-ghost-layer reconstruction from c[1..4]; first-order fallback
-// as always.
-__device__ __forceinline__ void reconstruct_face6(int lim, const double c[6][NV], double wl[NV], double wr[NV]) {
-  if (lim == LIM_WENO5 || lim == LIM_WENOZ5) {
-    const bool z = lim == LIM_WENOZ5;
+// c[3] (3 ghost layers): the fifth-order values of 'weno5' / 'wenoz5' /
+// 'wenozp5' (lambda = dx^(2/3) of the block) or 'mp5', else the
+// two-ghost-layer reconstruction from c[1..4]; first-order fallback as
+// always.
+__device__ __forceinline__ void reconstruct_face6(int lim, const double c[6][NV], double lambda, double wl[NV],
+                                                  double wr[NV]) {
+  if (lim == LIM_MP5) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      wl[q] = weno5_face(c[0][q], c[1][q], c[2][q], c[3][q], c[4][q], z);
-      wr[q] = weno5_face(c[5][q], c[4][q], c[3][q], c[2][q], c[1][q], z);
+      wl[q] = mp5_face(c[0][q], c[1][q], c[2][q], c[3][q], c[4][q]);
+      wr[q] = mp5_face(c[5][q], c[4][q], c[3][q], c[2][q], c[1][q]);
+    }
+    positivity_fallback(wl, wr, c[2], c[3]);
+  } else if (lim >= LIM_WENO5) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      wl[q] = weno5_face(c[0][q], c[1][q], c[2][q], c[3][q], c[4][q], lim, lambda);
+      wr[q] = weno5_face(c[5][q], c[4][q], c[3][q], c[2][q], c[1][q], lim, lambda);
     }
     positivity_fallback(wl, wr, c[2], c[3]);
   } else {

@@ -76,7 +76,7 @@ hipError_t launch_fill_faces(hipStream_t s, const GridConst& G, const int* tasks
 hipError_t launch_prim(hipStream_t s, const GridConst& G, const void* slot, double* prim, const PhysConst& P,
                        DevStatus* st);
 hipError_t launch_flux(hipStream_t s, const GridConst& G, int dir, const double* prim, double* flux,
-                       const double* ch_dev, const PhysConst& P);
+                       const double* ch_dev, const PhysConst& P, const double* inv_dx);
 struct FluxPtrs {
   double* f[3];
 };

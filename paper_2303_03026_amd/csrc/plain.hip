@@ -234,7 +234,8 @@ __global__ void __launch_bounds__(256) k_prim(GridConst G, const double* __restr
 
 template <int D>
 __global__ void __launch_bounds__(256) k_flux(GridConst G, const double* __restrict__ prim, double* __restrict__ flux,
-                                             const double* __restrict__ ch_dev, PhysConst P) {
+                                             const double* __restrict__ ch_dev, PhysConst P,
+                                             const double* __restrict__ inv_dx) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long total = (long)G.nb * G.nfaces;
   if (gid >= total) return;
@@ -269,7 +270,9 @@ __global__ void __launch_bounds__(256) k_flux(GridConst G, const double* __restr
 #pragma unroll
       for (int q = 0; q < NV; ++q) c6[s][q] = base[q * G.pcells + ix];
     }
-    reconstruct_face6(P.limiter, c6, wl, wr);
+    // WENO-Z+'s lambda = dx^(2/3) of this block along D
+    const double lambda = P.limiter == LIM_WENOZP5 ? 1.0 / cbrt(inv_dx[3 * b + D] * inv_dx[3 * b + D]) : 0.0;
+    reconstruct_face6(P.limiter, c6, lambda, wl, wr);
   } else {
     double wm[NV], wa[NV], wb[NV], wp[NV];
     long idx[4];
@@ -755,15 +758,15 @@ hipError_t launch_prim(hipStream_t s, const GridConst& G, const void* slot, doub
 }
 
 hipError_t launch_flux(hipStream_t s, const GridConst& G, int dir, const double* prim, double* flux,
-                       const double* ch_dev, const PhysConst& P) {
+                       const double* ch_dev, const PhysConst& P, const double* inv_dx) {
   const long n = (long)G.nb * G.nfaces;
   const unsigned nbk = nblocks_for(n, 256);
   if (dir == 0)
-    k_flux<0><<<nbk, 256, 0, s>>>(G, prim, flux, ch_dev, P);
+    k_flux<0><<<nbk, 256, 0, s>>>(G, prim, flux, ch_dev, P, inv_dx);
   else if (dir == 1)
-    k_flux<1><<<nbk, 256, 0, s>>>(G, prim, flux, ch_dev, P);
+    k_flux<1><<<nbk, 256, 0, s>>>(G, prim, flux, ch_dev, P, inv_dx);
   else
-    k_flux<2><<<nbk, 256, 0, s>>>(G, prim, flux, ch_dev, P);
+    k_flux<2><<<nbk, 256, 0, s>>>(G, prim, flux, ch_dev, P, inv_dx);
   return hipGetLastError();
 }
 

@@ -73,8 +73,11 @@ int check_desc(const amrvac_grid_desc* g, std::string* why) {
     }
   }
   if (!(g->gamma > 1.0) || !(g->cfl > 0.0) || !(g->glm_alpha >= 0.0)) { *why = "bad gamma/cfl/glm_alpha"; return AMRVAC_E_ARG; }
-  if (g->limiter < AMRVAC_LIM_VANLEER || g->limiter > AMRVAC_LIM_WENOZ5) { *why = "bad limiter"; return AMRVAC_E_ARG; }
-  if (g->limiter >= AMRVAC_LIM_WENO5 && g->nghost != 3) { *why = "weno5 / wenoz5 need nghost = 3"; return AMRVAC_E_ARG; }
+  if (g->limiter < AMRVAC_LIM_VANLEER || g->limiter > AMRVAC_LIM_WENOZP5) { *why = "bad limiter"; return AMRVAC_E_ARG; }
+  if (g->limiter >= AMRVAC_LIM_WENO5 && g->nghost != 3) {
+    *why = "the five-cell reconstructions (weno5, wenoz5, mp5, wenozp5) need nghost = 3";
+    return AMRVAC_E_ARG;
+  }
   if (g->flux < AMRVAC_FLUX_HLL || g->flux > AMRVAC_FLUX_HLLC) { *why = "bad flux scheme"; return AMRVAC_E_ARG; }
   if (g->precision == AMRVAC_FP32_MIXED && (g->block_nx != 16 || g->nghost != 2)) {
     *why = "FP32-mixed storage runs on the fused path, which needs block_nx = 16 and nghost = 2";
@@ -654,7 +657,7 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
   }
   HIP_TRY(c, launch_prim(c->stream, c->G, c->slots[in], c->d_prim, c->P, c->d_status));
   for (int d = 0; d < c->G.ndim; ++d)
-    HIP_TRY(c, launch_flux(c->stream, c->G, d, c->d_prim, c->d_flux[d], J.ch, c->P));
+    HIP_TRY(c, launch_flux(c->stream, c->G, d, c->d_prim, c->d_flux[d], J.ch, c->P, T.inv_dx));
   FluxPtrs fp{{c->d_flux[0], c->d_flux[1], c->d_flux[2]}};
   HIP_TRY(c, launch_reflux(c->stream, c->G, c->d_trefl, c->n_trefl, T, fp));
   HIP_TRY(c, launch_update(c->stream, c->G, T, c->slots[in], c->slots[base], c->slots[out], w, fp, J.dt, J.dt_scale,

@@ -54,7 +54,7 @@ class Workload:
     fix_small_values: int = 0
     reflux: int = 1
     ng: int = 2
-    limiter: int = 0  # 0 'vanleer', 1 'koren', 2 'cada3', 3 'weno5', 4 'wenoz5' (the last two need ng = 3)
+    limiter: int = 0  # 0 'vanleer', 1 'koren', 2 'cada3'; 3 'weno5', 4 'wenoz5', 5 'mp5', 6 'wenozp5' (these need ng = 3)
     flux: int = 0     # 0 HLL, 1 HLLD, 2 HLLC
     bc_fixed_prim: np.ndarray = dataclasses.field(
         default_factory=lambda: np.zeros((3, 2, NV)))

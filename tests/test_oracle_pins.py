@@ -1069,30 +1069,74 @@ def test_hllc_uniform_and_conservation(orc, ndim):
 # fifth-order WENO reconstructions on 3 ghost layers
 
 
-@pytest.mark.parametrize("z", [False, True])
-def test_weno_reconstruction_is_fifth_order(orc, z):
+FIVE_CELL = ["weno5", "wenoz5", "wenozp5", "mp5"]
+
+
+def _face5(orc, kind, v, h=1.0 / 64):
+    """A five-cell face value by limiter name (WENO-Z+ takes lambda = h^(2/3))."""
+    if kind == "mp5":
+        return orc.mp5_face(*v)
+    return orc.weno5_face(*v, z=kind == "wenoz5", zp=kind == "wenozp5", lam=h ** (2.0 / 3.0))
+
+
+@pytest.mark.parametrize("kind", FIVE_CELL)
+def test_five_cell_reconstruction_is_fifth_order(orc, kind):
     """Face values of sin(2 pi x) from its exact cell averages: the largest
-    error shrinks by 2^5 per halving of h."""
+    error shrinks by 2^5 per halving of h (for mp5 also through the smooth
+    extrema, where its curvature bounds must not clip)."""
     def err(n):
         h = 1.0 / n
         xs = (np.arange(n) + 0.5) * h
         avg = (np.cos(2 * np.pi * (xs - h / 2)) - np.cos(2 * np.pi * (xs + h / 2))) / (2 * np.pi * h)
-        return max(abs(orc.weno5_face(*avg[i - 2:i + 3], z=z) - math.sin(2 * math.pi * (xs[i] + h / 2)))
+        return max(abs(_face5(orc, kind, avg[i - 2:i + 3], h) - math.sin(2 * math.pi * (xs[i] + h / 2)))
                    for i in range(2, n - 2))
     e = [err(n) for n in (32, 64, 128)]
     assert all(math.log2(e[i] / e[i + 1]) > 4.8 for i in range(2)), e
 
 
-@pytest.mark.parametrize("z", [False, True])
-def test_weno_is_essentially_non_oscillatory_at_a_jump(orc, z):
-    """Across a unit step the face values stay within the data range up to
-    the small-epsilon leak (the smooth one-sided stencil takes the weight)."""
+@pytest.mark.parametrize("kind", FIVE_CELL)
+def test_five_cell_reconstruction_at_a_jump(orc, kind):
+    """Across a unit step the face values stay within the data range: up to
+    the small-epsilon leak for WENO (the smooth one-sided stencil takes the
+    weight), exactly for mp5 (monotonicity preserving)."""
+    slack = 0.0 if kind == "mp5" else 1e-6
     for k in range(5):
         v = [0.0] * (5 - k) + [1.0] * k  # the step at every position of the stencil
-        f = orc.weno5_face(*v, z=z)
-        assert -1e-6 <= f <= 1.0 + 1e-6, (k, f)
-    # linear data are reproduced exactly by every candidate, hence by WENO
-    assert orc.weno5_face(1.0, 2.0, 3.0, 4.0, 5.0, z=z) == pytest.approx(3.5, rel=1e-14)
+        f = _face5(orc, kind, v)
+        assert -slack <= f <= 1.0 + slack, (k, f)
+    # linear data are reproduced exactly by every candidate and by the
+    # fifth-order interpolant
+    assert _face5(orc, kind, [1.0, 2.0, 3.0, 4.0, 5.0]) == pytest.approx(3.5, rel=1e-14)
+
+
+def test_mp5_keeps_monotone_data_monotone(orc):
+    """On random monotone data the face value lies between the two cells
+    it separates (Suresh and Huynh's monotonicity condition) and mp5
+    returns the fifth-order interpolant wherever that already does."""
+    r = np.random.Generator(np.random.PCG64(71))
+    kept = 0
+    for _ in range(2000):
+        v = np.cumsum(r.exponential(size=5) * (r.random(5) < 0.7))
+        if r.random() < 0.5:
+            v = -v
+        f = orc.mp5_face(*v)
+        lo, hi = min(v[2], v[3]), max(v[2], v[3])
+        assert lo - 1e-14 * (1 + abs(lo)) <= f <= hi + 1e-14 * (1 + abs(hi)), (v, f)
+        u5 = (2 * v[0] - 13 * v[1] + 47 * v[2] + 27 * v[3] - 3 * v[4]) / 60.0
+        if lo < u5 < hi and (u5 - v[2]) * (u5 - (v[2] + np.sign(v[3] - v[2]) * min(abs(v[3] - v[2]), 4 * abs(v[2] - v[1])))) <= 0:
+            assert f == pytest.approx(u5, rel=1e-14, abs=1e-14)
+            kept += 1
+    assert kept > 100
+
+
+def test_wenozp_weights_when_the_outer_stencils_are_equally_rough(orc):
+    """With tau5 = 0 and beta_1 = 0 (a plateau between equal jumps,
+    (1, 2, 2, 2, 3)), WENO-Z+'s extra term lambda (beta_k + eps) / (tau5 +
+    eps) hands the weight to the two outer stencils in the ratio of their
+    optimal weights 0.1 : 0.3: the value is (q_0 + 3 q_2) / 4 = (10/6 + 3 *
+    11/6) / 4, for any positive lambda."""
+    for lam in (1e-3, 0.25, 1.0):
+        assert orc.weno5_face(1.0, 2.0, 2.0, 2.0, 3.0, zp=True, lam=lam) == pytest.approx(10.75 / 6.0, abs=1e-15)
 
 
 def _weno(w, lim):
@@ -1101,22 +1145,28 @@ def _weno(w, lim):
     return w
 
 
-@pytest.mark.parametrize("lim", [3, 4])
+@pytest.mark.parametrize("lim", [3, 4, 5, 6])
 def test_weno_alfven_wave(orc, lim):
-    def err(n, lm, ng):
+    """Linear Alfven wave along (1, 1) with SSPRK(5,4): every five-cell
+    reconstruction converges at fifth order (measured 4.99 - 5.08 over
+    N = 32, 64, 128; the fourth-order time error stays below the spatial
+    one), and at N = 128 its error is far below van Leer's (4e-8 against
+    3e-3 with SSPRK3).  With SSPRK3 the third-order time error dominates
+    (measured orders 2.6 - 3.5)."""
+    def err(n, lm, ng, nstages):
         w = inputs.alfven_wave(n, 2)
-        w.limiter, w.ng = lm, ng
+        w.limiter, w.ng, w.nstages = lm, ng, nstages
         sim = orc.OracleSim(w)
         sim.steps_to_time(1.0 / math.sqrt(2.0))
         e = np.mean(np.abs(sim.cons()[:, BZ] - w.prim[:, BZ])) / 1e-6
         sim.close()
         return e
-    e64, e128 = err(64, lim, 3), err(128, lim, 3)
-    assert math.log2(e64 / e128) >= 2.8, (e64, e128)  # measured 3.16
-    assert e128 < 0.01 * err(128, 0, 2), e128  # measured 1.06e-6 against 3.0e-3
+    e = [err(n, lim, 3, 5) for n in (32, 64, 128)]
+    assert min(math.log2(e[i] / e[i + 1]) for i in range(2)) >= 4.5, e
+    assert e[2] < 1e-3 * err(128, 0, 2, 3), e
 
 
-@pytest.mark.parametrize("lim", [3, 4])
+@pytest.mark.parametrize("lim", [3, 4, 5, 6])
 def test_weno_sod(orc, lim):
     import exact_riemann as er
 
@@ -1136,12 +1186,12 @@ def test_weno_sod(orc, lim):
 
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_weno_uniform_and_conservation(orc, ndim):
-    w = _weno(inputs.uniform_state(ndim, (3, 2, 2), _uniform_w()), 3)
+    w = _weno(inputs.uniform_state(ndim, (3, 2, 2), _uniform_w()), 3 if ndim == 2 else 6)
     sim = orc.OracleSim(w)
     u0 = sim.cons()
     sim.steps(3)
     assert np.array_equal(sim.cons(), u0)
-    w = _weno(inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5 if ndim == 2 else 7), 4)
+    w = _weno(inputs.smooth_amr_state(ndim, nb1=4 if ndim == 2 else 2, seed=5 if ndim == 2 else 7), 4 if ndim == 2 else 5)
     sim = orc.OracleSim(w)
     u0 = sim.cons()
     t0 = _totals(w, u0)
