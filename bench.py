@@ -101,7 +101,11 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64",
                     help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
-    ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud"], default="random_modes")
+    ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud", "kelvin_helmholtz"],
+                    default="random_modes",
+                    help="kelvin_helmholtz: the paper's 2D shear layer, 128 x 64 base with the interface band "
+                         "refined to --kh-levels levels (use with --limiter wenozp5 --flux hllc for its run)")
+    ap.add_argument("--kh-levels", type=int, default=6)
     ap.add_argument("--limiter", choices=list(LIMITERS), default="vanleer",
                     help="weno5 / wenoz5 / mp5 / wenozp5 need 3 ghost layers: FP64 plain path only")
     ap.add_argument("--flux", choices=["hll", "hlld", "hllc"], default="hll")
@@ -180,11 +184,14 @@ def main():
         w = inputs.random_modes(args.n, 3, seed=1)
     elif args.workload == "current_sheet":
         w = inputs.current_sheet(n=args.n)
+    elif args.workload == "kelvin_helmholtz":
+        w = inputs.kelvin_helmholtz(max_level=args.kh_levels)
     else:
         w = inputs.shock_cloud_amr()
     w.limiter = LIMITERS.index(args.limiter)
     w.flux = {"hll": 0, "hlld": 1, "hllc": 2}[args.flux]
     mixed = args.precision == "mixed"
+    w.ng = 2
     if w.limiter >= 3:  # the five-cell stencils: 3 ghost layers, plain FP64 path
         if mixed:
             sys.exit("bench: the fifth-order reconstructions run on the FP64 plain path only")
@@ -307,9 +314,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: 3D, %d leaf blocks of 16^3 + %d ghost layers on %d level(s), %s GLM-MHD "
+        "config": {"workload": "%s: %dD, %d leaf blocks of 16^%d + %d ghost layers on %d level(s), %s GLM-MHD "
                                "state, SSPRK(3,3), CFL 0.8, %s, %s limiter, %s flux"
-                               % (w.name, w.nblocks, w.ng, w.max_level, args.workload, "FP32-mixed" if mixed else "FP64",
+                               % (w.name, w.ndim, w.nblocks, w.ndim, w.ng, w.max_level, args.workload, "FP32-mixed" if mixed else "FP64",
                                   args.limiter, args.flux.upper()),
                    "path": args.path, "cells": cells, "stage_weights": [1.0, 0.25, 2.0 / 3.0],
                    "tune": None if tune is None else {"zseg": tune[0], "rotate": tune[1], "xcd": tune[2]}},
@@ -331,6 +338,8 @@ def main():
             small = inputs.random_modes(64, 3, seed=1)
         elif args.workload == "current_sheet":
             small = inputs.current_sheet(n=48)
+        elif args.workload == "kelvin_helmholtz":
+            small = inputs.kelvin_helmholtz(max_level=3)
         else:
             small = inputs.shock_cloud_amr(base_n=32)
         small.limiter, small.flux, small.ng = w.limiter, w.flux, w.ng

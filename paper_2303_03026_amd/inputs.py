@@ -421,6 +421,70 @@ def sod(n: int, ndim: int = 2, nx: int = 16, axis: int = 0) -> Workload:
                     level, ijk, prim, gamma=1.4, nstages=3)
 
 
+def shu_osher(n: int = 256, nx: int = 16, limiter: int = 6) -> Workload:
+    """Shu and Osher's shock / entropy-wave test as the paper runs it: x in
+    [-4.5, 4.5], a Mach-3 shock at x = -4 moving right into rho = 1 + 0.2
+    sin(5 x), v = 0, p = 1; left state (rho, v, p) = (3.857143, 2.629369,
+    10.333333) (the paper prints these rounded to 3.86, 2.63, 10.33);
+    gamma = 1.4, B = 0, HLL, SSPRK3, zero-gradient ends, final time 1.8.
+    One block thick (periodic) in y; 3 ghost layers for the five-cell
+    reconstructions (default 'wenozp5', the paper's choice)."""
+    base = (n // nx, 1, 1)
+    level, ijk = uniform_blocks(2, base)
+    xmin, xmax = (-4.5, 0.0, 0.0), (4.5, 9.0 / n * nx, 1.0)
+    x, _, _ = cell_centres(2, nx, base, xmin, xmax, level, ijk)
+    prim = np.zeros((len(level), NV, nx, nx))
+    left = x < -4.0
+    prim[:, RHO] = np.where(left, 3.857143, 1.0 + 0.2 * np.sin(5.0 * x))
+    prim[:, VX] = np.where(left, 2.629369, 0.0)
+    prim[:, PR] = np.where(left, 10.333333, 1.0)
+    return Workload("shu_osher_%d" % n, 2, nx, base, xmin, xmax, (BC_ZEROGRAD, BC_PERIODIC, BC_PERIODIC),
+                    (BC_ZEROGRAD, BC_PERIODIC, BC_PERIODIC), level, ijk, prim, gamma=1.4, nstages=3,
+                    ng=3 if limiter >= 3 else 2, limiter=limiter, flux=0)
+
+
+def kelvin_helmholtz(seed: int = 7, base: Tuple[int, int] = (8, 4), nx: int = 16, max_level: int = 1,
+                     band: float = 0.05, limiter: int = 6, flux: int = 2, nsteps: int = 10) -> Workload:
+    """The paper's 2D hydrodynamic Kelvin-Helmholtz shear layer: (x, y) in
+    [-1.5, 1.5] x [-0.75, 0.75], a sharp interface at y = 0 with rho = 1.5,
+    v_x = dV / 2.5 above and rho = 1, v_x = -1.5 dV / 2.5 below (dV = 0.2),
+    p = 1 / gamma, gamma = 5/3, B = 0, and v_y white noise of amplitude 1e-3
+    (uniform in [-1e-3, 1e-3), seeded, one draw per leaf cell in leaf order).
+    Base grid base * nx cells (the paper's 128 x 64); blocks whose y-range
+    comes within ``band`` of the interface are refined up to ``max_level``
+    with 2:1 nesting.  Periodic in x; reflective walls in y.  HLLC with
+    'wenozp5' on 3 ghost layers by default, as in the paper's run."""
+    b3 = (base[0], base[1], 1)
+    xmin, xmax = (-1.5, -0.75, 0.0), (1.5, 0.75, 1.0)
+    leaves = {(1, i, j, 0): True for j in range(base[1]) for i in range(base[0])}
+    for l in range(1, max_level):
+        hy = (xmax[1] - xmin[1]) / (base[1] << (l - 1))
+        for key in [k for k in leaves if k[0] == l]:
+            y0 = xmin[1] + key[2] * hy
+            if y0 - band <= 0.0 <= y0 + hy + band:
+                del leaves[key]
+                for a in (0, 1):
+                    for c in (0, 1):
+                        leaves[(l + 1, 2 * key[1] + a, 2 * key[2] + c, 0)] = True
+    leaves = nest_2to1(2, b3, leaves, periodic=(True, False, False))
+    keys = sorted(leaves.keys())
+    level = np.array([t[0] for t in keys], dtype=np.int32)
+    ijk = np.array([t[1:] for t in keys], dtype=np.int32)
+    _, y, _ = cell_centres(2, nx, b3, xmin, xmax, level, ijk)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gamma, dv = 5.0 / 3.0, 0.2
+    prim = np.zeros((len(level), NV, nx, nx))
+    up = y > 0.0
+    prim[:, RHO] = np.where(up, 1.5, 1.0)
+    prim[:, VX] = np.where(up, dv / 2.5, -1.5 * dv / 2.5)
+    prim[:, VY] = 1e-3 * rng.uniform(-1.0, 1.0, size=y.shape)
+    prim[:, PR] = 1.0 / gamma
+    return Workload("kelvin_helmholtz_%dx%d_l%d" % (base[0] * nx, base[1] * nx, max_level), 2, nx, b3, xmin, xmax,
+                    (BC_PERIODIC, BC_REFLECT, BC_PERIODIC), (BC_PERIODIC, BC_REFLECT, BC_PERIODIC), level, ijk,
+                    prim, gamma=gamma, nstages=3, nsteps=nsteps, ng=3 if limiter >= 3 else 2, limiter=limiter,
+                    flux=flux)
+
+
 def alfven_wave(n: int, ndim: int = 2, nx: int = 16, amp: float = 1e-6) -> Workload:
     """Small-amplitude linear Alfven wave on the periodic unit box with
     k = 2 pi (1, 1[, 1]), rho = 1, p = 1, B0 = unit vector along k, and a
