@@ -33,33 +33,33 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
                   "paper_2303_03026_amd/csrc/kernels.h", "paper_2303_03026_amd/csrc/runtime.cpp")
 MEASURED_TRAFFIC = {
-    ("419e65d90b3727cd", "f64"): {
-        (1, 0, 0): ((2854788, 1180193), (3636289, 1180191)),
-        (1, 0, 1): ((2714547, 1180115), (3560473, 1180268)),
-        (1, 1, 0): ((2859788, 1180036), (3645293, 1180425)),
-        (1, 1, 1): ((2697721, 1180027), (3552230, 1180479)),
-        (2, 0, 0): ((3058496, 1179932), (3850194, 1180132)),
-        (2, 0, 1): ((2945101, 1179940), (3802535, 1180154)),
-        (2, 1, 0): ((3078675, 1179925), (3861019, 1180223)),
-        (2, 1, 1): ((2930461, 1179969), (3782944, 1180302)),
-        (4, 0, 0): ((3511628, 1179727), (4302220, 1179847)),
-        (4, 0, 1): ((3165760, 1179755), (4043193, 1179817)),
-        (4, 1, 0): ((3520354, 1179781), (4303124, 1179841)),
-        (4, 1, 1): ((3149653, 1179769), (4073182, 1179840)),
+    ("6aec0c622e869ef6", "f64"): {
+        (1, 0, 0): ((2852830, 1180222), (3630379, 1180206)),
+        (1, 0, 1): ((2713136, 1180104), (3557017, 1180233)),
+        (1, 1, 0): ((2857122, 1179991), (3645883, 1180330)),
+        (1, 1, 1): ((2695534, 1179981), (3554766, 1180381)),
+        (2, 0, 0): ((3068154, 1179937), (3851338, 1180173)),
+        (2, 0, 1): ((2945692, 1179910), (3804114, 1180118)),
+        (2, 1, 0): ((3081703, 1179902), (3869356, 1180186)),
+        (2, 1, 1): ((2923362, 1179951), (3780648, 1180280)),
+        (4, 0, 0): ((3512885, 1179731), (4306998, 1179815)),
+        (4, 0, 1): ((3183272, 1179768), (4054537, 1179822)),
+        (4, 1, 0): ((3522239, 1179761), (4304334, 1179811)),
+        (4, 1, 1): ((3147059, 1179773), (4058612, 1179851)),
     },
-    ("419e65d90b3727cd", "mixed"): {
-        (1, 0, 0): ((1712810, 819472), (2186679, 819517)),
-        (1, 0, 1): ((1569941, 819438), (2072822, 819593)),
-        (1, 1, 0): ((1707001, 819455), (2173182, 819696)),
-        (1, 1, 1): ((1569254, 819462), (2073239, 819703)),
-        (2, 0, 0): ((1825204, 819362), (2303265, 819463)),
-        (2, 0, 1): ((1703662, 819357), (2212146, 819443)),
-        (2, 1, 0): ((1835171, 819392), (2306934, 819542)),
-        (2, 1, 1): ((1709562, 819388), (2214669, 819571)),
-        (4, 0, 0): ((2097072, 819237), (2558576, 819356)),
-        (4, 0, 1): ((1822827, 819235), (2366772, 819344)),
-        (4, 1, 0): ((2100911, 819260), (2561769, 819366)),
-        (4, 1, 1): ((1825759, 819242), (2365061, 819358)),
+    ("6aec0c622e869ef6", "mixed"): {
+        (1, 0, 0): ((1710954, 819483), (2183329, 819520)),
+        (1, 0, 1): ((1568827, 819491), (2071709, 819584)),
+        (1, 1, 0): ((1705871, 819423), (2169902, 819682)),
+        (1, 1, 1): ((1568808, 819475), (2078138, 819725)),
+        (2, 0, 0): ((1823200, 819394), (2299780, 819452)),
+        (2, 0, 1): ((1700963, 819354), (2213621, 819436)),
+        (2, 1, 0): ((1828639, 819409), (2306765, 819558)),
+        (2, 1, 1): ((1707232, 819391), (2217386, 819557)),
+        (4, 0, 0): ((2095945, 819247), (2558010, 819348)),
+        (4, 0, 1): ((1823176, 819228), (2366181, 819340)),
+        (4, 1, 0): ((2100468, 819250), (2563016, 819365)),
+        (4, 1, 1): ((1824365, 819238), (2367100, 819356)),
     },
 }
 FETCH_CAL, WRITE_CAL = 2.0, 1.0
