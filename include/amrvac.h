@@ -242,6 +242,27 @@ int amrvac_regrid_plan(const amrvac_grid_desc* g, int nb, const int* level, cons
 int amrvac_regrid(amrvac_ctx* c, int slot, int nb, const int* level, const int* ijk, void* const* slots, int nslots,
                   amrvac_ctx** out);
 
+/* Loehner's error indicator per leaf block, for refinement decisions (the
+ * paper's runs refine on weighted, user-chosen plasma quantities; this is
+ * the second-derivative estimator of Loehner 1987 in its per-direction form).
+ * For every interior cell, conserved variable q and direction d, with a, b,
+ * e the cell's lower neighbour, itself and its upper neighbour along d:
+ *   E_q = sqrt( sum_d (a - 2b + e)^2 /
+ *               sum_d (|e - b| + |b - a| + wavefilter (|e| + 2|b| + |a|))^2 )
+ * (0 where the denominator is 0); indicator[b] = max over the block's cells
+ * of sum_q weights[q] E_q.  Callers typically refine above a threshold
+ * (0.1 - 0.2) and coarsen below a fraction of it.  A variable that is zero
+ * up to roundoff gives a ratio of roundoff terms (order 1, not
+ * reproducible): weight only variables that carry the solution.
+ *   slot:          state to examine; its ghost cells are filled on the way
+ *   weights:       host [9] in conserved order (rho, m, e, B, psi), finite,
+ *                  >= 0, at least one positive
+ *   wavefilter:    finite, >= 0 (0.01 is usual)
+ *   indicator_dev: device [nb] doubles, caller-owned, block order of
+ *                  amrvac_init_blocks; written asynchronously on the stream
+ * AMRVAC_E_ARG for bad arguments, AMRVAC_E_STATE on batch contexts. */
+int amrvac_lohner(amrvac_ctx* c, int slot, const double* weights, double wavefilter, double* indicator_dev);
+
 /* Select the stage implementation: AMRVAC_PATH_PLAIN (separate primitive,
  * per-direction flux, reflux and update kernels; FP64 only, the default for
  * FP64 contexts) or AMRVAC_PATH_FUSED (one kernel per stage plus, on AMR

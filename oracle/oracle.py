@@ -215,6 +215,44 @@ class OracleSim:
         return out
 
 
+def lohner_indicator(w, padded: np.ndarray, weights, wavefilter: float = 0.01) -> np.ndarray:
+    """Loehner's (1987) second-derivative error indicator per block, in its
+    per-direction form, from ghost-filled blocks (OracleSim.padded(); only
+    face neighbours are read).  For every interior cell and conserved
+    variable q, with a, b, e the lower neighbour, the cell and the upper
+    neighbour along direction d:
+        E_q = sqrt(sum_d (a - 2b + e)^2
+                   / sum_d (|e - b| + |b - a| + wavefilter (|e| + 2|b| + |a|))^2),
+    0 where the denominator is 0; the block's indicator is the largest
+    sum_q weights[q] E_q over its cells."""
+    g, n, nd = w.ng, w.nx, w.ndim
+    out = np.zeros(padded.shape[0])
+    inner = slice(g, g + n)
+    for b in range(padded.shape[0]):
+        total = np.zeros((n,) * nd)
+        for q in range(NV):
+            if not weights[q] > 0.0:
+                continue
+            u = padded[b, q]
+            num = np.zeros((n,) * nd)
+            den = np.zeros((n,) * nd)
+            for d in range(nd):
+                ax = nd - 1 - d  # array axes run [.., z, y, x]
+                def shifted(o):
+                    sl = [inner] * nd
+                    sl[ax] = slice(g + o, g + o + n)
+                    return u[tuple(sl)]
+                a, c, e = shifted(-1), shifted(0), shifted(1)
+                num += (a - 2.0 * c + e) ** 2
+                den += (np.abs(e - c) + np.abs(c - a) + wavefilter * (np.abs(e) + 2.0 * np.abs(c) + np.abs(a))) ** 2
+            pos = den > 0.0
+            est = np.zeros_like(num)
+            est[pos] = np.sqrt(num[pos] / den[pos])
+            total += weights[q] * est
+        out[b] = total.max()
+    return out
+
+
 def run(w, nsteps: Optional[int] = None, nthreads: Optional[int] = None, check: bool = True):
     """Run a workload for nsteps (default w.nsteps); returns (cons, diag)."""
     sim = OracleSim(w, nthreads)

@@ -30,7 +30,7 @@ ABI_SYMBOLS = ("amrvac_slot_bytes", "amrvac_init_blocks", "amrvac_set_primitive"
                "amrvac_batch_create", "amrvac_batch_add_job", "amrvac_batch_step", "amrvac_batch_job_info",
                "amrvac_batch_get_job", "amrvac_batch_remove_job", "amrvac_batch_free_blocks",
                "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune", "amrvac_stage_cfl", "amrvac_combine",
-               "amrvac_regrid_plan", "amrvac_regrid")
+               "amrvac_regrid_plan", "amrvac_regrid", "amrvac_lohner")
 TUNE_MAX_CANDIDATES = 12
 SLOT_LEAD_FP64 = 16  # bytes before the first block of an FP64 slot
 
@@ -98,6 +98,7 @@ def load_library():
                                        ip, ip, ip]
     lib.amrvac_regrid.argtypes = [vp, ctypes.c_int, ctypes.c_int, ip, ip, ctypes.POINTER(vp), ctypes.c_int,
                                   ctypes.POINTER(vp)]
+    lib.amrvac_lohner.argtypes = [vp, ctypes.c_int, dp, ctypes.c_double, vp]
     lib.amrvac_advance.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.amrvac_set_path.argtypes = [vp, ctypes.c_int]
     lib.amrvac_sync_flags.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong), dp]
@@ -303,6 +304,26 @@ class Simulation:
     def combine(self, a_slot: int, b_slot: int, coef: float, out_slot: int):
         """out = a + coef (b - a) on the leaf interior cells (amrvac_combine)."""
         self._check(self.lib.amrvac_combine(self.ctx, a_slot, b_slot, coef, out_slot), self.ctx)
+
+    def lohner(self, weights=(1.0, 0, 0, 0, 0, 0, 0, 0, 0), wavefilter: float = 0.01, slot: int = 0) -> np.ndarray:
+        """Loehner's error indicator of every block (amrvac_lohner), weights
+        over the conserved variables (default: density only)."""
+        torch = self.torch
+        wts = np.ascontiguousarray(weights, dtype=np.float64)
+        if wts.shape != (NV,):
+            raise ValueError("weights must have 9 entries")
+        with torch.cuda.stream(self.stream):
+            ind = torch.empty(self.nb, dtype=torch.float64, device=self.device)
+        self._check(self.lib.amrvac_lohner(self.ctx, slot, wts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           float(wavefilter), ctypes.c_void_p(ind.data_ptr())), self.ctx)
+        self.stream.synchronize()
+        return ind.cpu().numpy()
+
+    def lohner_flags(self, refine: float = 0.2, coarsen_ratio: float = 0.125, **kw) -> np.ndarray:
+        """Per-block regrid flags from the Loehner indicator: 1 above refine,
+        -1 below refine * coarsen_ratio, else 0."""
+        ind = self.lohner(**kw)
+        return np.where(ind > refine, 1, np.where(ind < refine * coarsen_ratio, -1, 0)).astype(np.int32)
 
     def regrid_plan(self, flags, max_level: int = 12):
         """New leaf set (level, ijk) from per-block flags (see regrid_plan)."""

@@ -116,6 +116,15 @@ hipError_t launch_regrid(hipStream_t s, const GridConst& G, const Tables& Told, 
                          const void* old_slot, void* new_slot);
 
 // out = a + coef (b - a) on the leaf interior cells of the active blocks
+// Loehner indicator parameters: per-variable weights of the conserved
+// variables and the wave filter epsilon.
+struct LohnerParams {
+  double weight[NV];
+  double wavefilter;
+};
+
+hipError_t launch_lohner(hipStream_t s, const GridConst& G, const Tables& T, const void* slot, const LohnerParams& L,
+                         double* ind);
 hipError_t launch_combine(hipStream_t s, const GridConst& G, const Tables& T, const void* a, const void* b,
                           double coef, void* out);
 

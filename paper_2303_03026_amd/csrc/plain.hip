@@ -578,6 +578,84 @@ __global__ void __launch_bounds__(256) k_regrid(GridConst G, Tables Told, const 
 }
 
 // ---------------------------------------------------------------------------
+// Loehner's error indicator per block, one workgroup per active block.  For
+// every interior cell and every conserved variable q with weight w_q > 0,
+// E_q = sqrt(sum_d (a - 2b + e)^2 / sum_d (|e - b| + |b - a| + eps (|e| +
+// 2|b| + |a|))^2) over the directions d with (a, b, e) = the cell's
+// neighbours along d and itself; the block's indicator is the largest
+// sum_q w_q E_q.  Face neighbours across a same-level face are read in
+// place, all others from the block's own ghost cells (filled before).
+
+template <int NDIM, class SP>
+__global__ void __launch_bounds__(256) k_lohner(GridConst G, Tables T, const void* __restrict__ slot, LohnerParams L,
+                                               double* __restrict__ ind) {
+  const int blk = T.order[blockIdx.x];
+  const int nx = G.nx;
+  const long pc = G.pcells;
+  int lk[2 * NDIM], ln[2 * NDIM];
+#pragma unroll
+  for (int f = 0; f < 2 * NDIM; ++f) {
+    lk[f] = T.link[((long)blk * 6 + f) * LINK_INTS];
+    ln[f] = T.link[((long)blk * 6 + f) * LINK_INTS + 1];
+  }
+  const void* own = block_ptr<SP>(slot, blk, pc);
+  double r = 0.0;
+  for (int c = threadIdx.x; c < (int)G.icells; c += blockDim.x) {
+    const int i = c % nx, j = (c / nx) % nx, k = NDIM == 3 ? c / (nx * nx) : 0;
+    const long ic = pidx_n<NDIM>(G, i, j, k);
+    const void* bm[NDIM];
+    const void* bp[NDIM];
+    long im[NDIM], ip[NDIM];
+#pragma unroll
+    for (int ax = 0; ax < NDIM; ++ax) {
+      int m[3] = {i, j, k}, p[3] = {i, j, k};
+      m[ax] -= 1;
+      p[ax] += 1;
+      bm[ax] = own;
+      bp[ax] = own;
+      if (m[ax] < 0 && lk[2 * ax] == LINK_SAME) {
+        bm[ax] = block_ptr<SP>(slot, ln[2 * ax], pc);
+        m[ax] += nx;
+      }
+      if (p[ax] >= nx && lk[2 * ax + 1] == LINK_SAME) {
+        bp[ax] = block_ptr<SP>(slot, ln[2 * ax + 1], pc);
+        p[ax] -= nx;
+      }
+      im[ax] = pidx_n<NDIM>(G, m[0], m[1], m[2]);
+      ip[ax] = pidx_n<NDIM>(G, p[0], p[1], p[2]);
+    }
+    double e_sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if (!(L.weight[q] > 0.0)) continue;  // uniform over the launch
+      const double b = SP::ld(own, q, ic, pc);
+      double num = 0.0, den = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < NDIM; ++ax) {
+        const double a = SP::ld(bm[ax], q, im[ax], pc), e = SP::ld(bp[ax], q, ip[ax], pc);
+        const double d2 = a - 2.0 * b + e;
+        const double dd = fabs(e - b) + fabs(b - a) + L.wavefilter * (fabs(e) + 2.0 * fabs(b) + fabs(a));
+        num += d2 * d2;
+        den += dd * dd;
+      }
+      e_sum += L.weight[q] * (den > 0.0 ? sqrt(num / den) : 0.0);
+    }
+    r = fmax(r, e_sum);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
+  __shared__ double smax[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) smax[wave] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = smax[0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, smax[q]);
+    ind[blk] = m;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // out = a + coef (b - a) on the leaf interior cells, one thread per cell.
 // Both loads of a cell come before its store, so out may be a or b.
 
@@ -847,6 +925,23 @@ hipError_t launch_regrid(hipStream_t s, const GridConst& G, const Tables& Told, 
       k_regrid<2, StoreF64><<<nbk, 256, 0, s>>>(G, Told, tasks, ntasks, old_slot, new_slot);
     else
       k_regrid<2, StoreMixed><<<nbk, 256, 0, s>>>(G, Told, tasks, ntasks, old_slot, new_slot);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lohner(hipStream_t s, const GridConst& G, const Tables& T, const void* slot, const LohnerParams& L,
+                         double* ind) {
+  if (T.nactive <= 0) return hipSuccess;
+  if (G.ndim == 3) {
+    if (G.precision == 0)
+      k_lohner<3, StoreF64><<<T.nactive, 256, 0, s>>>(G, T, slot, L, ind);
+    else
+      k_lohner<3, StoreMixed><<<T.nactive, 256, 0, s>>>(G, T, slot, L, ind);
+  } else {
+    if (G.precision == 0)
+      k_lohner<2, StoreF64><<<T.nactive, 256, 0, s>>>(G, T, slot, L, ind);
+    else
+      k_lohner<2, StoreMixed><<<T.nactive, 256, 0, s>>>(G, T, slot, L, ind);
   }
   return hipGetLastError();
 }

@@ -990,6 +990,27 @@ int amrvac_combine(amrvac_ctx* c, int a, int b, double coef, int out) {
   return AMRVAC_OK;
 }
 
+int amrvac_lohner(amrvac_ctx* c, int slot, const double* weights, double wavefilter, double* indicator_dev) {
+  if (!c) return AMRVAC_E_ARG;
+  if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts have no per-context block indicator");
+  if (int rc = check_slot(c, slot)) return rc;
+  if (!weights || !indicator_dev) return fail(c, AMRVAC_E_ARG, "null weights or indicator pointer");
+  LohnerParams L{};
+  bool any = false;
+  for (int q = 0; q < NV; ++q) {
+    if (!(weights[q] >= 0.0) || !std::isfinite(weights[q])) return fail(c, AMRVAC_E_ARG, "weights must be finite and >= 0");
+    L.weight[q] = weights[q];
+    any = any || weights[q] > 0.0;
+  }
+  if (!any) return fail(c, AMRVAC_E_ARG, "at least one weight must be positive");
+  if (!(wavefilter >= 0.0) || !std::isfinite(wavefilter)) return fail(c, AMRVAC_E_ARG, "wavefilter must be finite and >= 0");
+  L.wavefilter = wavefilter;
+  if (int rc = ensure_tables(c)) return rc;
+  if (int rc = fill_slot(c, slot)) return rc;
+  HIP_TRY(c, launch_lohner(c->stream, c->G, c->tables(), c->slots[slot], L, indicator_dev));
+  return AMRVAC_OK;
+}
+
 int amrvac_regrid_plan(const amrvac_grid_desc* g, int nb, const int* level, const int* ijk, const int* flags,
                        int max_level, int cap, int* nb_new, int* level_out, int* ijk_out) {
   if (!g || !level || !ijk || !flags || !nb_new || nb < 1) return AMRVAC_E_ARG;

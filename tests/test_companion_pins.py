@@ -131,3 +131,59 @@ def test_kelvin_helmholtz_adaptive_run_conserves(amr, orc):
     for q in (RHO, VX, PR):  # PR holds the total energy in conserved form
         assert abs(t1[q] - t0[q]) <= 1e-13 * scale[q], (q, t0[q], t1[q])
     o.close()
+
+
+# ---------------------------------------------------------------------------
+# Loehner's refinement indicator (the oracle's, on ghost-filled blocks)
+
+
+def _padded_from(fn, ndim=2, n=16, g=2):
+    """A single ghost-filled block holding fn(x, y[, z]) at integer cell
+    coordinates (interior 0 .. n-1, ghosts outside)."""
+    ax = np.arange(-g, n + g, dtype=np.float64)
+    grids = np.meshgrid(*([ax] * ndim), indexing="ij")[::-1]  # array axes [.., z, y, x]
+    if ndim == 2:
+        y, x = grids[1], grids[0]
+        vals = fn(x.T, y.T, 0.0)
+    else:
+        vals = fn(*[a.transpose(2, 1, 0) for a in grids])
+    p = np.zeros((1, NV) + vals.shape)
+    p[0, RHO] = vals
+    return p
+
+
+def _w(ndim=2, n=16, g=2):
+    return dataclasses.replace(inputs.uniform_state(ndim, (1, 1, 1), [1.0] + [0.0] * 8), ng=g)
+
+
+def test_lohner_zero_on_linear_data_and_one_at_a_step(orc):
+    """Linear data have no second difference: the indicator is exactly 0.
+    At a step with no wave filter every cell beside the jump has E = 1 (its
+    one nonzero second difference equals the one nonzero first difference)."""
+    wt = [1.0] + [0.0] * 8
+    lin = _padded_from(lambda x, y, z: 3.0 * x - 2.0 * y + 5.0)
+    assert orc.lohner_indicator(_w(), lin, wt, 0.01)[0] == 0.0
+    step = _padded_from(lambda x, y, z: np.where(x >= 8, 4.0, 1.0))
+    assert orc.lohner_indicator(_w(), step, wt, 0.0)[0] == pytest.approx(1.0, abs=1e-15)
+    # the wave filter only lowers it
+    assert orc.lohner_indicator(_w(), step, wt, 0.01)[0] < 1.0
+
+
+def test_lohner_scale_invariant_and_smooth_data_vanish(orc):
+    """E(alpha u) = E(u) for alpha > 0 (each ratio is homogeneous of degree
+    0), and on a smooth monotone profile E falls as the grid is refined
+    (about h / 2 for exp(h x): it halves with h).  At a smooth extremum E is
+    1 without the wave filter, which is what the filter is for."""
+    wt = [1.0] + [0.0] * 8
+    rng = np.random.Generator(np.random.PCG64(81))
+    noisy = _padded_from(lambda x, y, z: 2.0 + np.sin(0.7 * x) * np.cos(0.3 * y)) + 0.0
+    noisy[0, RHO] += 0.01 * rng.uniform(-1, 1, size=noisy[0, RHO].shape)
+    base = orc.lohner_indicator(_w(), noisy, wt, 0.01)[0]
+    scaled = noisy.copy()
+    scaled[0, RHO] *= 37.5
+    assert orc.lohner_indicator(_w(), scaled, wt, 0.01)[0] == pytest.approx(base, rel=1e-13)
+    es = []
+    for h in (0.2, 0.1, 0.05):
+        es.append(orc.lohner_indicator(_w(), _padded_from(lambda x, y, z: np.exp(h * (x + 0.5 * y))), wt, 0.0)[0])
+    assert 1.9 < es[0] / es[1] < 2.1 and 1.9 < es[1] / es[2] < 2.1, es
+    assert es[2] < 0.03, es
