@@ -93,8 +93,9 @@ typedef struct {
   int ndim;               /* 2 or 3                                            */
   int block_nx;           /* interior cells per direction per block (even,     */
                           /* 4..16; the fused path and FP32-mixed need 16)     */
-  int nghost;             /* ghost layers: 2, or 3 for weno5 / wenoz5 (the     */
-                          /* fused path and FP32-mixed need 2)                 */
+  int nghost;             /* ghost layers: 2, or 3 for the five-cell           */
+                          /* reconstructions; block_nx >= 2 nghost (the fused  */
+                          /* path and FP32-mixed need 2)                       */
   int precision;          /* AMRVAC_FP64 or AMRVAC_FP32_MIXED                  */
   int base_blocks[3];     /* blocks per direction on level 1 (z ignored in 2D) */
   int bc_lo[3];           /* AMRVAC_BC_* at the minimum face of each direction */

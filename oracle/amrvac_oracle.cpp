@@ -1032,6 +1032,7 @@ Sim* build_sim(const oracle_params* p, int nblocks, const int* level, const int*
   if (s->ndim != 2 && s->ndim != 3) throw std::invalid_argument("ndim must be 2 or 3");
   if (s->ng != 2 && s->ng != 3) throw std::invalid_argument("ghost layers must be 2 or 3");
   if (s->nx < 4 || (s->nx & 1)) throw std::invalid_argument("nx must be even and >= 4");
+  if (2 * s->ng > s->nx) throw std::invalid_argument("nx must be at least twice the ghost depth (restriction)");
   if (p->nstages < 1 || p->nstages > 5) throw std::invalid_argument("nstages must be 1 .. 5");
   if (p->limiter < LIM_VANLEER || p->limiter > LIM_WENOZP5) throw std::invalid_argument("unknown limiter");
   if (five_cell_limiter(p->limiter) && p->ng != 3)

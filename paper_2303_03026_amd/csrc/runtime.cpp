@@ -59,6 +59,9 @@ int check_desc(const amrvac_grid_desc* g, std::string* why) {
   if (g->ndim != 2 && g->ndim != 3) { *why = "ndim must be 2 or 3"; return AMRVAC_E_ARG; }
   if (g->nghost != 2 && g->nghost != 3) { *why = "nghost must be 2 or 3"; return AMRVAC_E_ARG; }
   if (g->block_nx < 4 || g->block_nx > 16 || (g->block_nx & 1)) { *why = "block_nx must be even, 4..16"; return AMRVAC_E_ARG; }
+  // a coarse ghost layer of depth nghost is restricted from 2 nghost fine
+  // cells, which must lie inside the fine neighbour
+  if (2 * g->nghost > g->block_nx) { *why = "block_nx must be at least 2 nghost"; return AMRVAC_E_ARG; }
   if (g->precision != AMRVAC_FP64 && g->precision != AMRVAC_FP32_MIXED) { *why = "bad precision"; return AMRVAC_E_ARG; }
   for (int d = 0; d < g->ndim; ++d) {
     if (g->base_blocks[d] < 1) { *why = "base_blocks must be >= 1"; return AMRVAC_E_ARG; }

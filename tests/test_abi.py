@@ -66,6 +66,12 @@ def test_rejects_bad_descriptions(lib):
         setattr(g, field, val)
         rc, msg = _init(lib, w, desc=g)
         assert rc == amrvac.E_ARG, (field, msg)
+    # three ghost layers need blocks of at least 6 cells (a coarse ghost
+    # layer is restricted from 2 nghost fine cells inside the neighbour)
+    g = amrvac.make_desc(w)
+    g.nghost, g.block_nx, g.limiter = 3, 4, amrvac.LIM_WENO5
+    rc, msg = _init(lib, w, desc=g)
+    assert rc == amrvac.E_ARG and "2 nghost" in msg, msg
     g = amrvac.make_desc(w)
     g.bc_lo[0] = amrvac.FP64 + 1  # zero-gradient on one side only of a periodic pair
     rc, msg = _init(lib, w, desc=g)
