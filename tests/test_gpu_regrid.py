@@ -81,9 +81,11 @@ def test_transfer_matches_oracle(amr, orc, ndim, path):
     sim.close()
 
 
-@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("path", PATHS + ["plain-wenozp5"])
 def test_runs_on_after_regrid(amr, orc, path):
     w = inputs.smooth_amr_state(3, nb1=2, seed=7)
+    if path == "plain-wenozp5":  # three ghost layers through the regrid
+        w.limiter, w.ng = 6, 3
     sim = amr.Simulation(w, path=amr.PATH_FUSED if path == "fused" else amr.PATH_PLAIN)
     o = orc.OracleSim(w)
     sim.advance(2, nstages=3)
