@@ -33,33 +33,33 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
                   "paper_2303_03026_amd/csrc/kernels.h", "paper_2303_03026_amd/csrc/runtime.cpp")
 MEASURED_TRAFFIC = {
-    ("6aec0c622e869ef6", "f64"): {
-        (1, 0, 0): ((2852830, 1180222), (3630379, 1180206)),
-        (1, 0, 1): ((2713136, 1180104), (3557017, 1180233)),
-        (1, 1, 0): ((2857122, 1179991), (3645883, 1180330)),
-        (1, 1, 1): ((2695534, 1179981), (3554766, 1180381)),
-        (2, 0, 0): ((3068154, 1179937), (3851338, 1180173)),
-        (2, 0, 1): ((2945692, 1179910), (3804114, 1180118)),
-        (2, 1, 0): ((3081703, 1179902), (3869356, 1180186)),
-        (2, 1, 1): ((2923362, 1179951), (3780648, 1180280)),
-        (4, 0, 0): ((3512885, 1179731), (4306998, 1179815)),
-        (4, 0, 1): ((3183272, 1179768), (4054537, 1179822)),
-        (4, 1, 0): ((3522239, 1179761), (4304334, 1179811)),
-        (4, 1, 1): ((3147059, 1179773), (4058612, 1179851)),
+    ("a57c3d6d7d2840ab", "f64"): {
+        (1, 0, 0): ((2857382, 1180221), (3634990, 1180139)),
+        (1, 0, 1): ((2714176, 1180192), (3556887, 1180253)),
+        (1, 1, 0): ((2860682, 1179966), (3649581, 1180330)),
+        (1, 1, 1): ((2697097, 1180041), (3552272, 1180452)),
+        (2, 0, 0): ((3063653, 1179913), (3856980, 1180118)),
+        (2, 0, 1): ((2949035, 1179950), (3803320, 1180187)),
+        (2, 1, 0): ((3079812, 1179950), (3865770, 1180218)),
+        (2, 1, 1): ((2932618, 1179947), (3785074, 1180273)),
+        (4, 0, 0): ((3513630, 1179742), (4301462, 1179787)),
+        (4, 0, 1): ((3177833, 1179758), (4049955, 1179801)),
+        (4, 1, 0): ((3523167, 1179767), (4306917, 1179812)),
+        (4, 1, 1): ((3160711, 1179767), (4085487, 1179830)),
     },
-    ("6aec0c622e869ef6", "mixed"): {
-        (1, 0, 0): ((1710954, 819483), (2183329, 819520)),
-        (1, 0, 1): ((1568827, 819491), (2071709, 819584)),
-        (1, 1, 0): ((1705871, 819423), (2169902, 819682)),
-        (1, 1, 1): ((1568808, 819475), (2078138, 819725)),
-        (2, 0, 0): ((1823200, 819394), (2299780, 819452)),
-        (2, 0, 1): ((1700963, 819354), (2213621, 819436)),
-        (2, 1, 0): ((1828639, 819409), (2306765, 819558)),
-        (2, 1, 1): ((1707232, 819391), (2217386, 819557)),
-        (4, 0, 0): ((2095945, 819247), (2558010, 819348)),
-        (4, 0, 1): ((1823176, 819228), (2366181, 819340)),
-        (4, 1, 0): ((2100468, 819250), (2563016, 819365)),
-        (4, 1, 1): ((1824365, 819238), (2367100, 819356)),
+    ("a57c3d6d7d2840ab", "mixed"): {
+        (1, 0, 0): ((1710603, 819463), (2178351, 819524)),
+        (1, 0, 1): ((1574294, 819426), (2075730, 819543)),
+        (1, 1, 0): ((1707188, 819412), (2174156, 819648)),
+        (1, 1, 1): ((1574751, 819444), (2079466, 819660)),
+        (2, 0, 0): ((1824482, 819352), (2300564, 819426)),
+        (2, 0, 1): ((1705560, 819358), (2217544, 819411)),
+        (2, 1, 0): ((1828269, 819411), (2309536, 819517)),
+        (2, 1, 1): ((1711777, 819379), (2220183, 819508)),
+        (4, 0, 0): ((2097107, 819246), (2557878, 819334)),
+        (4, 0, 1): ((1828971, 819229), (2369645, 819324)),
+        (4, 1, 0): ((2101337, 819263), (2561498, 819370)),
+        (4, 1, 1): ((1829444, 819232), (2367773, 819347)),
     },
 }
 FETCH_CAL, WRITE_CAL = 2.0, 1.0
