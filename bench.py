@@ -111,6 +111,8 @@ def parse():
     ap.add_argument("--flux", choices=["hll", "hlld", "hllc"], default="hll")
     ap.add_argument("--regrid", action="store_true",
                     help="also time one regrid (coarsen the top level, refine every eighth block below)")
+    ap.add_argument("--lohner", action="store_true",
+                    help="also time the Loehner refinement indicator of the density (amrvac_lohner)")
     ap.add_argument("--tune", default="auto",
                     help="fused-stage launch shape: 'auto' (autotuner, before the warmup), 'default', or z,r,x")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -296,9 +298,20 @@ def main():
             times.append((time.perf_counter() - r0) * 1e3)
             new.close()
         regrid = {"ms": min(times), "blocks_in": int(w.nblocks), "blocks_out": int(len(lv)),
-                  "cells_out": int(len(lv)) * w.nx ** 3,
+                  "cells_out": int(len(lv)) * w.nx ** w.ndim,
                   "what": "amrvac_regrid wall time (new context, tables, ghost fill of the old slot, "
                           "transfer kernel, stream sync), best of 3"}
+    lohner = None
+    if args.lohner:
+        times = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            r0 = time.perf_counter()
+            ind = sim.lohner(weights=[1.0] + [0.0] * 8, wavefilter=0.01)
+            times.append((time.perf_counter() - r0) * 1e3)
+        lohner = {"ms": min(times), "blocks": int(w.nblocks), "refine_above_0.2": int((ind > 0.2).sum()),
+                  "what": "amrvac_lohner on the density, wall time (ghost fill, indicator kernel, copy of one "
+                          "double per block to the host, stream sync), best of 5"}
     sim.close()
 
     out = {
@@ -324,6 +337,7 @@ def main():
         "algorithmic_hbm_gbs_per_step": cells * 8 * state_bytes / (ms_per_step * 1e-3) / 1e9,
         "graph_ms_per_step": graph_ms,
         "regrid": regrid,
+        "lohner": lohner,
         "stage_ms": [sum(x) / K for x in stage_ms],
         "roofline": {"bound": "hbm", "kernel": "stage (%s path)" % args.path, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
