@@ -156,17 +156,16 @@ def regrid_plan(w, flags, max_level: int = 12, precision: int = FP64, level=None
         raise ValueError("one flag per block")
     P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))  # noqa: E731
     nb_new = ctypes.c_int()
-    rc = lib.amrvac_regrid_plan(ctypes.byref(desc), len(level), P(level), P(ijk), P(flags), max_level, 0,
-                                ctypes.byref(nb_new), None, None, None)
-    if rc not in (0, E_NOMEM):
-        raise AmrvacError(rc, lib.amrvac_last_error(None).decode())
-    lv = np.empty(nb_new.value, dtype=np.int32)
-    ij = np.empty((nb_new.value, 3), dtype=np.int32)
-    rc = lib.amrvac_regrid_plan(ctypes.byref(desc), len(level), P(level), P(ijk), P(flags), max_level, nb_new.value,
+    # every old leaf ends as at most 2^ndim new ones (one level change per
+    # block), so this capacity always suffices and one call does
+    cap = len(level) << w.ndim
+    lv = np.empty(cap, dtype=np.int32)
+    ij = np.empty((cap, 3), dtype=np.int32)
+    rc = lib.amrvac_regrid_plan(ctypes.byref(desc), len(level), P(level), P(ijk), P(flags), max_level, cap,
                                 ctypes.byref(nb_new), P(lv), P(ij))
     if rc != 0:
         raise AmrvacError(rc, lib.amrvac_last_error(None).decode())
-    return lv, ij
+    return lv[:nb_new.value].copy(), ij[:nb_new.value].copy()
 
 
 class Simulation:

@@ -16,6 +16,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
+#include <unordered_set>
 #include <set>
 #include <string>
 #include <tuple>
@@ -32,7 +34,28 @@ struct KeyL {
   int l;
   long i, j, k;
   bool operator<(const KeyL& o) const { return std::tie(l, i, j, k) < std::tie(o.l, o.i, o.j, o.k); }
+  bool operator==(const KeyL& o) const { return l == o.l && i == o.i && j == o.j && k == o.k; }
 };
+
+// Hash of a block key (splitmix64 finaliser over the packed coordinates):
+// the block tables and the regrid planner look blocks up by key hundreds of
+// thousands of times per call.
+struct KeyHash {
+  size_t operator()(const KeyL& q) const noexcept {
+    unsigned long long h = (unsigned long long)q.l;
+    h = h * 0x100000001B3ull ^ (unsigned long long)q.i;
+    h = h * 0x100000001B3ull ^ (unsigned long long)q.j;
+    h = h * 0x100000001B3ull ^ (unsigned long long)q.k;
+    h ^= h >> 30;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 27;
+    h *= 0x94D049BB133111EBull;
+    h ^= h >> 31;
+    return (size_t)h;
+  }
+};
+using KeyMap = std::unordered_map<KeyL, int, KeyHash>;
+using KeySet = std::unordered_set<KeyL, KeyHash>;
 
 // Validated tables of one job's hierarchy (pool ids already offset).
 struct JobBuild {
@@ -106,8 +129,10 @@ long long slot_bytes_of(const amrvac_grid_desc* g, long nb) {
 int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ijk, int first, JobBuild* out) {
   JobBuild& J = *out;
   const int ndim = g->ndim, nx = g->block_nx;
-  std::map<KeyL, int> leaf;
-  std::set<KeyL> refined;
+  KeyMap leaf;
+  KeySet refined;
+  leaf.reserve((size_t)nb * 2);
+  refined.reserve((size_t)nb);
   double vol = 0.0;
   for (int b = 0; b < nb; ++b) {
     const int l = level[b];
@@ -815,7 +840,7 @@ struct Planner {
   int ndim = 2;
   long base[3] = {1, 1, 1};
   bool per[3] = {false, false, false};
-  std::set<KeyL> leaves;
+  KeySet leaves;
 
   long nblk(int l, int d) const { return d < ndim ? base[d] << (l - 1) : 1; }
   // wrap q into the domain of level l; false outside a non-periodic side
@@ -1028,7 +1053,9 @@ int amrvac_regrid_plan(const amrvac_grid_desc* g, int nb, const int* level, cons
     P.per[d] = d < P.ndim && g->bc_lo[d] == AMRVAC_BC_PERIODIC;
   }
   const int lmax = std::min(std::max(max_level, 1), MAXLEV);
-  std::map<KeyL, int> old;
+  KeyMap old;
+  old.reserve((size_t)nb * 2);
+  P.leaves.reserve((size_t)nb * 4);
   for (int b = 0; b < nb; ++b) {
     const KeyL k{J.level[b], J.pos[3 * b], J.pos[3 * b + 1], J.pos[3 * b + 2]};
     old[k] = b;
@@ -1039,7 +1066,7 @@ int amrvac_regrid_plan(const amrvac_grid_desc* g, int nb, const int* level, cons
   P.nest();
   // coarsen complete sibling sets of old leaves that are all flagged, one
   // parent at a time, where nesting allows
-  std::set<KeyL> parents;
+  KeySet parents;
   for (const auto& kv : old)
     if (flags[kv.second] < 0 && kv.first.l > 1)
       parents.insert(KeyL{kv.first.l - 1, kv.first.i >> 1, kv.first.j >> 1, kv.first.k >> 1});
@@ -1075,8 +1102,12 @@ int amrvac_regrid_plan(const amrvac_grid_desc* g, int nb, const int* level, cons
   }
   *nb_new = (int)P.leaves.size();
   if (!level_out || !ijk_out || cap < *nb_new) return AMRVAC_E_NOMEM;
+  // (sorted by level, then position: the output does not depend on the
+  // hash containers' iteration order)
+  std::vector<KeyL> sorted(P.leaves.begin(), P.leaves.end());
+  std::sort(sorted.begin(), sorted.end());
   int n = 0;
-  for (const KeyL& k : P.leaves) {
+  for (const KeyL& k : sorted) {
     level_out[n] = k.l;
     ijk_out[3 * n] = (int)k.i;
     ijk_out[3 * n + 1] = (int)k.j;
@@ -1097,7 +1128,8 @@ int amrvac_regrid(amrvac_ctx* c, int slot, int nb, const int* level, const int* 
   // transfer tasks from the old leaf set
   const JobBuild& J = c->jobs[0].t;
   const int ndim = c->g.ndim;
-  std::map<KeyL, int> old;
+  KeyMap old;
+  old.reserve(J.level.size() * 2);
   for (int b = 0; b < (int)J.level.size(); ++b) old[KeyL{J.level[b], J.pos[3 * b], J.pos[3 * b + 1], J.pos[3 * b + 2]}] = b;
   std::vector<int> tasks((size_t)nb * REGRID_TASK_INTS, 0);
   for (int n = 0; n < nb; ++n) {
