@@ -101,11 +101,14 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64",
                     help="f64: all FP64; mixed: FP32 storage and face arithmetic, FP64 energy and CFL")
-    ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud", "kelvin_helmholtz"],
+    ap.add_argument("--workload", choices=["random_modes", "current_sheet", "shock_cloud", "kelvin_helmholtz",
+                                           "alfven_shock"],
                     default="random_modes",
                     help="kelvin_helmholtz: the paper's 2D shear layer, 128 x 64 base with the interface band "
-                         "refined to --kh-levels levels (use with --limiter wenozp5 --flux hllc for its run)")
-    ap.add_argument("--kh-levels", type=int, default=6)
+                         "refined to --levels levels (use with --limiter wenozp5 --flux hllc for its run); "
+                         "alfven_shock: the paper's 2D MHD shock-cloud test, 128^2 base with the cloud and the "
+                         "shock refined to --levels levels (use with --limiter koren and --flux hll/hllc/hlld)")
+    ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--limiter", choices=list(LIMITERS), default="vanleer",
                     help="weno5 / wenoz5 / mp5 / wenozp5 need 3 ghost layers: FP64 plain path only")
     ap.add_argument("--flux", choices=["hll", "hlld", "hllc"], default="hll")
@@ -187,7 +190,9 @@ def main():
     elif args.workload == "current_sheet":
         w = inputs.current_sheet(n=args.n)
     elif args.workload == "kelvin_helmholtz":
-        w = inputs.kelvin_helmholtz(max_level=args.kh_levels)
+        w = inputs.kelvin_helmholtz(max_level=args.levels)
+    elif args.workload == "alfven_shock":
+        w = inputs.alfven_shock_cloud(max_level=args.levels)
     else:
         w = inputs.shock_cloud_amr()
     w.limiter = LIMITERS.index(args.limiter)
@@ -354,6 +359,8 @@ def main():
             small = inputs.current_sheet(n=48)
         elif args.workload == "kelvin_helmholtz":
             small = inputs.kelvin_helmholtz(max_level=3)
+        elif args.workload == "alfven_shock":
+            small = inputs.alfven_shock_cloud(max_level=3)
         else:
             small = inputs.shock_cloud_amr(base_n=32)
         small.limiter, small.flux, small.ng = w.limiter, w.flux, w.ng

@@ -467,7 +467,7 @@ def kelvin_helmholtz(seed: int = 7, base: Tuple[int, int] = (8, 4), nx: int = 16
                     for c in (0, 1):
                         leaves[(l + 1, 2 * key[1] + a, 2 * key[2] + c, 0)] = True
     leaves = nest_2to1(2, b3, leaves, periodic=(True, False, False))
-    keys = sorted(leaves.keys())
+    keys = sorted(leaves.keys(), key=lambda t: (t[0], t[3], t[2], t[1]))  # x fastest within a level
     level = np.array([t[0] for t in keys], dtype=np.int32)
     ijk = np.array([t[1:] for t in keys], dtype=np.int32)
     _, y, _ = cell_centres(2, nx, b3, xmin, xmax, level, ijk)
@@ -483,6 +483,111 @@ def kelvin_helmholtz(seed: int = 7, base: Tuple[int, int] = (8, 4), nx: int = 16
                     (BC_PERIODIC, BC_REFLECT, BC_PERIODIC), (BC_PERIODIC, BC_REFLECT, BC_PERIODIC), level, ijk,
                     prim, gamma=gamma, nstages=3, nsteps=nsteps, ng=3 if limiter >= 3 else 2, limiter=limiter,
                     flux=flux)
+
+
+def alfven_shock_states(delta: float = 2.5, beta: float = 0.1, theta_deg: float = 40.0,
+                        gamma: float = 5.0 / 3.0):
+    """The paper's planar intermediate ('Alfven') shock: upstream at rest with
+    rho = 1, p = 1/gamma, plasma beta 2p/B^2 = beta and field (-B cos theta,
+    B sin theta); compression ratio delta.  In the shock frame (normal x,
+    upstream normal velocity -s) mass, tangential momentum and tangential
+    induction give u2 = s (1 - 1/delta), B_y2 = B_y1 (s^2 - v_A^2) /
+    (s^2/delta - v_A^2) with v_A^2 = B_x^2 / rho_1, v_2 = B_x (B_y2 - B_y1) /
+    (-rho_1 s), and normal momentum gives p_2; the energy jump leaves one
+    equation in s, solved by bisection on the intermediate branch v_A^2 <
+    s^2 < delta v_A^2 (where B_y changes sign).  Returns (upstream prim,
+    downstream prim, shock speed s); the shock moves towards +x."""
+    rho1, p1 = 1.0, 1.0 / gamma
+    b = math.sqrt(2.0 * p1 / beta)
+    th = math.radians(theta_deg)
+    bx, b1y = -b * math.cos(th), b * math.sin(th)
+    va2 = bx * bx / rho1
+    rho2 = delta * rho1
+
+    def downstream(sp):
+        j = -rho1 * sp
+        w1, w2 = -sp, -sp / delta
+        b2y = b1y * (sp * sp - va2) / (sp * sp / delta - va2)
+        v2 = bx * (b2y - b1y) / j
+        p2 = p1 + rho1 * sp * sp * (1.0 - 1.0 / delta) + 0.5 * (b1y * b1y - b2y * b2y)
+        e_in = j * (0.5 * w1 * w1 + gamma * p1 / ((gamma - 1.0) * rho1)) + w1 * b1y * b1y
+        e_out = j * (0.5 * (w2 * w2 + v2 * v2) + gamma * p2 / ((gamma - 1.0) * rho2)) + w2 * b2y * b2y - bx * v2 * b2y
+        return e_out - e_in, (rho2, sp * (1.0 - 1.0 / delta), v2, p2, b2y)
+
+    lo, hi = math.sqrt(va2) * (1.0 + 1e-9), math.sqrt(delta * va2) * (1.0 - 1e-9)
+    grid = np.linspace(lo, hi, 2001)
+    f = [downstream(x)[0] for x in grid]
+    brackets = [(grid[i], grid[i + 1]) for i in range(len(grid) - 1) if f[i] * f[i + 1] <= 0.0]
+    if len(brackets) != 1:
+        raise ValueError("no unique intermediate shock for these parameters")
+    a, c = brackets[0]
+    fa = downstream(a)[0]
+    for _ in range(200):
+        m = 0.5 * (a + c)
+        fm = downstream(m)[0]
+        if fm == 0.0 or m in (a, c):
+            break
+        if (fm < 0.0) == (fa < 0.0):
+            a, fa = m, fm
+        else:
+            c = m
+    sp = 0.5 * (a + c)
+    r2, u2, v2, p2, b2y = downstream(sp)[1]
+    up = np.array([rho1, 0.0, 0.0, 0.0, p1, bx, b1y, 0.0, 0.0])
+    down = np.array([r2, u2, v2, 0.0, p2, bx, b2y, 0.0, 0.0])
+    return up, down, sp
+
+
+def alfven_shock_cloud(seed: int = 12, base: Tuple[int, int] = (8, 8), nx: int = 16, max_level: int = 1,
+                       limiter: int = 1, flux: int = 0, nsteps: int = 10, cloud: bool = True) -> Workload:
+    """The paper's 2D MHD shock-cloud test ("Alfven hits Alfven"): (x, y) in
+    [-0.5, 3] x [-1, 2.5], the intermediate shock of alfven_shock_states at
+    x = -0.3 moving into the static medium (rho = 1, p = 1/gamma, gamma =
+    5/3), whose density in [0, 1] x [0, 1.5] is 1 + 0.5 I(x, y) with I in
+    [0, 256].  The paper's I is an image of Alfven; here it is a seeded
+    stand-in of the same range: 12 Gaussian blobs (centres uniform in the
+    rectangle, widths 0.03 .. 0.15, amplitudes 0.3 .. 1), their sum clipped
+    to 1 and scaled by 256.  Zero-gradient boundaries; SSPRK3 with 'koren'
+    by default.  Base grid base * nx cells (the paper's 128^2); blocks that
+    meet the cloud rectangle or the shock are refined up to ``max_level``
+    with 2:1 nesting."""
+    b3 = (base[0], base[1], 1)
+    xmin, xmax = (-0.5, -1.0, 0.0), (3.0, 2.5, 1.0)
+    leaves = {(1, i, j, 0): True for j in range(base[1]) for i in range(base[0])}
+    for l in range(1, max_level):
+        hx = (xmax[0] - xmin[0]) / (base[0] << (l - 1))
+        hy = (xmax[1] - xmin[1]) / (base[1] << (l - 1))
+        for key in [k for k in leaves if k[0] == l]:
+            x0, y0 = xmin[0] + key[1] * hx, xmin[1] + key[2] * hy
+            meets_cloud = cloud and x0 <= 1.0 and x0 + hx >= 0.0 and y0 <= 1.5 and y0 + hy >= 0.0
+            meets_shock = x0 <= -0.3 <= x0 + hx
+            if meets_cloud or meets_shock:
+                del leaves[key]
+                for a in (0, 1):
+                    for c in (0, 1):
+                        leaves[(l + 1, 2 * key[1] + a, 2 * key[2] + c, 0)] = True
+    leaves = nest_2to1(2, b3, leaves)
+    keys = sorted(leaves.keys(), key=lambda t: (t[0], t[3], t[2], t[1]))  # x fastest within a level
+    level = np.array([t[0] for t in keys], dtype=np.int32)
+    ijk = np.array([t[1:] for t in keys], dtype=np.int32)
+    x, y, _ = cell_centres(2, nx, b3, xmin, xmax, level, ijk)
+    up, down, _ = alfven_shock_states()
+    prim = np.zeros((len(level), NV, nx, nx))
+    post = x < -0.3
+    for q in range(NV):
+        prim[:, q] = np.where(post, down[q], up[q])
+    if cloud:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        img = np.zeros_like(x)
+        for _ in range(12):
+            cx, cy = rng.uniform(0.0, 1.0), rng.uniform(0.0, 1.5)
+            wdt, amp = rng.uniform(0.03, 0.15), rng.uniform(0.3, 1.0)
+            img += amp * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2.0 * wdt * wdt))
+        inside = (x >= 0.0) & (x <= 1.0) & (y >= 0.0) & (y <= 1.5)
+        prim[:, RHO] = np.where(inside, 1.0 + 0.5 * 256.0 * np.minimum(img, 1.0), prim[:, RHO])
+    zg = (BC_ZEROGRAD, BC_ZEROGRAD, BC_PERIODIC)
+    return Workload("alfven_shock_cloud_%dx%d_l%d" % (base[0] * nx, base[1] * nx, max_level), 2, nx, b3, xmin, xmax,
+                    zg, zg, level, ijk, prim, gamma=5.0 / 3.0, nstages=3, nsteps=nsteps, limiter=limiter, flux=flux)
 
 
 def alfven_wave(n: int, ndim: int = 2, nx: int = 16, amp: float = 1e-6) -> Workload:

@@ -187,3 +187,53 @@ def test_lohner_scale_invariant_and_smooth_data_vanish(orc):
         es.append(orc.lohner_indicator(_w(), _padded_from(lambda x, y, z: np.exp(h * (x + 0.5 * y))), wt, 0.0)[0])
     assert 1.9 < es[0] / es[1] < 2.1 and 1.9 < es[1] / es[2] < 2.1, es
     assert es[2] < 0.03, es
+
+
+# ---------------------------------------------------------------------------
+# the paper's MHD shock-cloud test: an intermediate ('Alfven') shock
+
+
+def test_alfven_shock_states_satisfy_the_jump_conditions(orc):
+    """The planar shock of the paper's shock-cloud test (compression 2.5,
+    upstream beta 0.1, field at 40 degrees to the normal): every conserved
+    component satisfies F(U2) - F(U1) = s (U2 - U1) with the oracle's own
+    flux, the tangential field changes sign (an intermediate shock: the
+    upstream normal speed exceeds the upstream normal Alfven speed, the
+    downstream one is below the downstream normal Alfven speed), and the
+    inputs are reproduced."""
+    gamma = 5.0 / 3.0
+    up, down, s = inputs.alfven_shock_states()
+    u1, u2 = orc.prim_to_cons(up, gamma), orc.prim_to_cons(down, gamma)
+    f1, f2 = orc.phys_flux(up, 0, gamma), orc.phys_flux(down, 0, gamma)
+    scale = np.abs(f1) + np.abs(f2) + abs(s) * (np.abs(u1) + np.abs(u2)) + 1e-300
+    assert np.all(np.abs((f2 - f1) - s * (u2 - u1)) <= 1e-13 * scale), (f2 - f1) - s * (u2 - u1)
+    assert down[RHO] / up[RHO] == pytest.approx(2.5, rel=1e-15)
+    assert 2.0 * up[PR] / (up[BX] ** 2 + up[BY] ** 2) == pytest.approx(0.1, rel=1e-13)
+    assert np.degrees(np.arctan2(up[BY], -up[BX])) == pytest.approx(40.0, rel=1e-13)
+    assert up[BY] * down[BY] < 0.0
+    va1 = abs(up[BX]) / np.sqrt(up[RHO])
+    va2 = abs(down[BX]) / np.sqrt(down[RHO])
+    assert s > va1 and (s - down[VX]) < va2, (s, va1, s - down[VX], va2)
+
+
+@pytest.mark.parametrize("flux", [0, 1, 2])
+def test_planar_intermediate_shock_moves_at_its_speed(orc, flux):
+    """The shock alone (no cloud) on the 128^2 base grid with 'koren': after
+    t = 0.3 the tangential field's sign change sits at x = -0.3 + s t within
+    two cells for HLL, HLLC and HLLD, and every row is the same (the planar
+    state stays planar bit for bit)."""
+    w = inputs.alfven_shock_cloud(max_level=1, flux=flux, cloud=False)
+    _, _, s = inputs.alfven_shock_states()
+    sim = orc.OracleSim(w)
+    t = 0.3
+    sim.steps_to_time(t)
+    g = inputs.blocks_to_global(sim.cons().swapaxes(0, 1), 2, w.nx, w.base_blocks)
+    sim.close()
+    by = g[BY]
+    assert np.array_equal(by, np.broadcast_to(by[0], by.shape))
+    dx = 3.5 / 128
+    x = -0.5 + (np.arange(128) + 0.5) * dx
+    cross = np.nonzero((by[0][:-1] < 0.0) & (by[0][1:] >= 0.0))[0]
+    assert len(cross) == 1, cross
+    xs = 0.5 * (x[cross[0]] + x[cross[0] + 1])
+    assert abs(xs - (-0.3 + s * t)) < 2.0 * dx, (xs, -0.3 + s * t)
