@@ -116,6 +116,10 @@ def parse():
                     help="also time one regrid (coarsen the top level, refine every eighth block below)")
     ap.add_argument("--lohner", action="store_true",
                     help="also time the Loehner refinement indicator of the density (amrvac_lohner)")
+    ap.add_argument("--adapt-every", type=int, default=0,
+                    help="also run an adaptive segment of --steps steps that regrids every N steps from the "
+                         "device Loehner indicator of the density (refine above 0.1, coarsen below 0.025, up to "
+                         "--levels levels; the AMR workloads)")
     ap.add_argument("--tune", default="auto",
                     help="fused-stage launch shape: 'auto' (autotuner, before the warmup), 'default', or z,r,x")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -306,6 +310,40 @@ def main():
                   "cells_out": int(len(lv)) * w.nx ** w.ndim,
                   "what": "amrvac_regrid wall time (new context, tables, ghost fill of the old slot, "
                           "transfer kernel, stream sync), best of 3"}
+    adaptive = None
+    if args.adapt_every > 0:
+        # an adaptive run: steps, and every N steps indicator -> plan -> regrid
+        # (the new context keeps the launch shape); wall time of everything
+        cur = sim
+        cell_updates, regrids, t_ind, t_regrid = 0, 0, 0.0, 0.0
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        for k in range(K):
+            cur.advance(1, nstages=3)
+            cell_updates += int(len(cur.level)) * w.nx ** w.ndim
+            if (k + 1) % args.adapt_every == 0 and k + 1 < K:
+                torch.cuda.synchronize()  # (the steps so far are not charged to the regrid)
+                r0 = time.perf_counter()
+                flags = cur.lohner_flags(refine=0.1, coarsen_ratio=0.25, weights=[1.0] + [0.0] * 8)
+                r1 = time.perf_counter()
+                lv, ij = cur.regrid_plan(flags, max_level=max(args.levels, int(w.level.max())))
+                new = cur.regrid(lv, ij)
+                if cur is not sim:
+                    cur.close()
+                cur = new
+                t_ind += r1 - r0
+                t_regrid += time.perf_counter() - r1
+                regrids += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - a0
+        adaptive = {"steps": K, "regrid_every": args.adapt_every, "regrids": regrids, "wall_s": wall,
+                    "ms_per_step": wall * 1e3 / K, "mcell_updates_per_s": cell_updates / wall / 1e6,
+                    "indicator_s": t_ind, "plan_and_regrid_s": t_regrid,
+                    "blocks_start": int(w.nblocks), "blocks_end": int(len(cur.level)),
+                    "what": "advance, then every N steps Loehner flags (device) -> plan (host) -> regrid (device); "
+                            "cell updates counted on the grid of each step"}
+        if cur is not sim:
+            cur.close()
     lohner = None
     if args.lohner:
         times = []
@@ -343,6 +381,7 @@ def main():
         "graph_ms_per_step": graph_ms,
         "regrid": regrid,
         "lohner": lohner,
+        "adaptive": adaptive,
         "stage_ms": [sum(x) / K for x in stage_ms],
         "roofline": {"bound": "hbm", "kernel": "stage (%s path)" % args.path, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
