@@ -33,33 +33,33 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
                   "paper_2303_03026_amd/csrc/kernels.h", "paper_2303_03026_amd/csrc/runtime.cpp")
 MEASURED_TRAFFIC = {
-    ("a57c3d6d7d2840ab", "f64"): {
-        (1, 0, 0): ((2857382, 1180221), (3634990, 1180139)),
-        (1, 0, 1): ((2714176, 1180192), (3556887, 1180253)),
-        (1, 1, 0): ((2860682, 1179966), (3649581, 1180330)),
-        (1, 1, 1): ((2697097, 1180041), (3552272, 1180452)),
-        (2, 0, 0): ((3063653, 1179913), (3856980, 1180118)),
-        (2, 0, 1): ((2949035, 1179950), (3803320, 1180187)),
-        (2, 1, 0): ((3079812, 1179950), (3865770, 1180218)),
-        (2, 1, 1): ((2932618, 1179947), (3785074, 1180273)),
-        (4, 0, 0): ((3513630, 1179742), (4301462, 1179787)),
-        (4, 0, 1): ((3177833, 1179758), (4049955, 1179801)),
-        (4, 1, 0): ((3523167, 1179767), (4306917, 1179812)),
-        (4, 1, 1): ((3160711, 1179767), (4085487, 1179830)),
+    ("a36dd00d61611f29", "f64"): {
+        (1, 0, 0): ((2855130, 1180185), (3631973, 1180199)),
+        (1, 0, 1): ((2712809, 1180116), (3556958, 1180234)),
+        (1, 1, 0): ((2859229, 1179994), (3649093, 1180402)),
+        (1, 1, 1): ((2695544, 1180008), (3550869, 1180461)),
+        (2, 0, 0): ((3072984, 1179928), (3858554, 1180123)),
+        (2, 0, 1): ((2943674, 1179947), (3803128, 1180166)),
+        (2, 1, 0): ((3083109, 1179903), (3859760, 1180186)),
+        (2, 1, 1): ((2928451, 1179969), (3777996, 1180273)),
+        (4, 0, 0): ((3514040, 1179722), (4298961, 1179810)),
+        (4, 0, 1): ((3169554, 1179747), (4066431, 1179821)),
+        (4, 1, 0): ((3520570, 1179756), (4307289, 1179833)),
+        (4, 1, 1): ((3140750, 1179775), (4074083, 1179859)),
     },
-    ("a57c3d6d7d2840ab", "mixed"): {
-        (1, 0, 0): ((1710603, 819463), (2178351, 819524)),
-        (1, 0, 1): ((1574294, 819426), (2075730, 819543)),
-        (1, 1, 0): ((1707188, 819412), (2174156, 819648)),
-        (1, 1, 1): ((1574751, 819444), (2079466, 819660)),
-        (2, 0, 0): ((1824482, 819352), (2300564, 819426)),
-        (2, 0, 1): ((1705560, 819358), (2217544, 819411)),
-        (2, 1, 0): ((1828269, 819411), (2309536, 819517)),
-        (2, 1, 1): ((1711777, 819379), (2220183, 819508)),
-        (4, 0, 0): ((2097107, 819246), (2557878, 819334)),
-        (4, 0, 1): ((1828971, 819229), (2369645, 819324)),
-        (4, 1, 0): ((2101337, 819263), (2561498, 819370)),
-        (4, 1, 1): ((1829444, 819232), (2367773, 819347)),
+    ("a36dd00d61611f29", "mixed"): {
+        (1, 0, 0): ((1712331, 819504), (2190389, 819515)),
+        (1, 0, 1): ((1568298, 819481), (2073440, 819571)),
+        (1, 1, 0): ((1707455, 819479), (2169571, 819678)),
+        (1, 1, 1): ((1568652, 819458), (2074584, 819697)),
+        (2, 0, 0): ((1829182, 819355), (2305834, 819448)),
+        (2, 0, 1): ((1704389, 819369), (2214793, 819447)),
+        (2, 1, 0): ((1832268, 819414), (2309631, 819540)),
+        (2, 1, 1): ((1709081, 819400), (2218237, 819531)),
+        (4, 0, 0): ((2097817, 819253), (2560112, 819364)),
+        (4, 0, 1): ((1824434, 819232), (2365462, 819338)),
+        (4, 1, 0): ((2101178, 819264), (2561525, 819378)),
+        (4, 1, 1): ((1822718, 819241), (2368329, 819363)),
     },
 }
 FETCH_CAL, WRITE_CAL = 2.0, 1.0
