@@ -417,8 +417,28 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
   };
   // (the fused path, the only user, has 2 ghost layers: a four-cell stencil)
   R w4[4][NV];
+  if constexpr (D == 0 && SP::kBytesPerCell == 72) {
+    // x faces: the four cells of a variable are consecutive in one row, so
+    // two 16-byte loads fetch them (with 16 + 16 nx x-cells per padded row,
+    // a 16-byte slot lead and a 16-byte aligned slot, padded x index 0 or nx
+    // starts on 16 bytes)
+    const long c0 = pidx(G, f - 2, t1, t2);
+    double u4[4][NV];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) cell(f - 2 + s, w4[s]);
+    for (int q = 0; q < NV; ++q) {
+      const double2* p2 = reinterpret_cast<const double2*>(static_cast<const double*>(S) + q * G.pcells + c0);
+      const double2 a = p2[0], b = p2[1];
+      u4[0][q] = a.x;
+      u4[1][q] = a.y;
+      u4[2][q] = b.x;
+      u4[3][q] = b.y;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) (void)cons_to_prim(u4[s], w4[s], P);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) cell(f - 2 + s, w4[s]);
+  }
   reconstruct_face(P.limiter, w4[0], w4[1], w4[2], w4[3], wl, wr);
   face_flux_rt<D, R>(P.flux, wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
 }
