@@ -125,3 +125,30 @@ def test_mixed_amr(amr, orc):
     rel, linf = errors(w, gpu, ref)
     report("smooth_amr_3d_4steps", rel, linf)
     assert np.all(rel <= 1e-6), rel
+
+
+def test_mixed_alfven_shock_cloud(amr, orc):
+    """The paper's MHD shock-cloud test (3 levels, koren + HLLD, 30 steps):
+    a strong intermediate shock and a density contrast of 129 in FP32
+    storage.  Bound 1e-6 (measured 3.4e-8, B_y)."""
+    w = inputs.alfven_shock_cloud(max_level=3, flux=1, nsteps=30)
+    ref, _ = orc.run(w)
+    gpu, fl = run_mixed(amr, w, w.nsteps)
+    assert fl[0] == 0
+    rel, linf = errors(w, gpu, ref)
+    report("alfven_shock_cloud_l3_30steps", rel, linf)
+    assert np.all(rel <= 1e-6), rel
+
+
+def test_mixed_kelvin_helmholtz(amr, orc):
+    """The shear layer (3 levels, van Leer + HLLC, 30 steps; B = 0, so the
+    field rows of the error are zero).  Bound 1e-6 (measured 1.3e-7, rho)."""
+    w = inputs.kelvin_helmholtz(max_level=3, limiter=0, flux=2, nsteps=30)
+    ref, _ = orc.run(w)
+    gpu, fl = run_mixed(amr, w, w.nsteps)
+    assert fl[0] == 0
+    with np.errstate(invalid="ignore"):
+        rel, linf = errors(w, gpu, ref)
+    rel = np.nan_to_num(rel)  # (0/0 for the field rows)
+    report("kelvin_helmholtz_l3_30steps", rel, linf)
+    assert np.all(rel <= 1e-6), rel
