@@ -173,7 +173,7 @@ def cpu_baseline(w, small):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: runs on one GPU only; --gpus %d is not supported "
               "(the multi-GPU decomposition is a design note, not code)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
