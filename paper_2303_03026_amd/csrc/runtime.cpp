@@ -124,32 +124,115 @@ long long slot_bytes_of(const amrvac_grid_desc* g, long nb) {
   return (long long)nb * pc * per + slot_lead(g->precision);
 }
 
+// Leaf / refined-slot lookup for build_job.  Per level a dense array over
+// the level's block slots (-1 empty, -2 refined, else the leaf's index) when
+// all levels together have at most kDenseSlots slots, else hash maps; block
+// tables are built for every init, batch admission and regrid, so this is
+// the hot part of validating a hierarchy.
+class BlockLookup {
+ public:
+  static constexpr long kDenseSlots = 1L << 24;
+  BlockLookup(int ndim, const int* base, int finest, int nb) : ndim_(ndim) {
+    long total = 0;
+    for (int l = 1; l <= finest; ++l) {
+      long n = 1;
+      for (int d = 0; d < 3; ++d) n *= d < ndim ? ((long)base[d] << (l - 1)) : 1;
+      total += n;
+      if (total > kDenseSlots) break;
+    }
+    dense_ = total <= kDenseSlots;
+    if (dense_) {
+      off_.assign(finest + 2, 0);
+      for (int l = 1; l <= finest; ++l) {
+        for (int d = 0; d < 3; ++d) dim_[l][d] = d < ndim ? ((long)base[d] << (l - 1)) : 1;
+        off_[l + 1] = off_[l] + dim_[l][0] * dim_[l][1] * dim_[l][2];
+      }
+      cells_.assign(off_[finest + 1], -1);
+      finest_ = finest;
+    } else {
+      leaf_.reserve((size_t)nb * 2);
+      refined_.reserve((size_t)nb);
+    }
+  }
+  // false if the slot already holds a leaf; a leaf on a refined slot (or the
+  // reverse) is recorded as an overlap
+  bool add_leaf(const KeyL& k, int id) {
+    if (!dense_) {
+      if (!leaf_.emplace(k, id).second) return false;
+      if (refined_.count(k)) overlap_ = true;
+      return true;
+    }
+    int& c = cells_[index(k)];
+    if (c >= 0) return false;
+    if (c == -2) overlap_ = true;
+    c = id;
+    return true;
+  }
+  void add_refined(const KeyL& k) {
+    if (!dense_) {
+      refined_.insert(k);
+      if (leaf_.count(k)) overlap_ = true;
+      return;
+    }
+    int& c = cells_[index(k)];
+    if (c >= 0) overlap_ = true;
+    else c = -2;
+  }
+  bool overlap() const { return overlap_; }
+  // the leaf's index at slot k of level k.l, or -1
+  int leaf(const KeyL& k) const {
+    if (!dense_) {
+      auto it = leaf_.find(k);
+      return it == leaf_.end() ? -1 : it->second;
+    }
+    if (k.l < 1 || k.l > finest_) return -1;
+    const int c = cells_[index(k)];
+    return c >= 0 ? c : -1;
+  }
+  bool refined(const KeyL& k) const {
+    if (!dense_) return refined_.count(k) != 0;
+    if (k.l < 1 || k.l > finest_) return false;
+    return cells_[index(k)] == -2;
+  }
+
+ private:
+  long index(const KeyL& k) const { return off_[k.l] + (k.k * dim_[k.l][1] + k.j) * dim_[k.l][0] + k.i; }
+  int ndim_;
+  bool dense_ = false, overlap_ = false;
+  int finest_ = 0;
+  long dim_[MAXLEV + 2][3] = {};
+  std::vector<long> off_;
+  std::vector<int> cells_;
+  KeyMap leaf_;
+  KeySet refined_;
+};
+
 // Validate a job's leaf blocks and build its tables with pool ids starting
 // at `first`.  Host only: no device call.
 int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ijk, int first, JobBuild* out) {
   JobBuild& J = *out;
   const int ndim = g->ndim, nx = g->block_nx;
-  KeyMap leaf;
-  KeySet refined;
-  leaf.reserve((size_t)nb * 2);
-  refined.reserve((size_t)nb);
-  double vol = 0.0;
   for (int b = 0; b < nb; ++b) {
     const int l = level[b];
     if (l < 1 || l > MAXLEV) { J.err = "level out of range 1..12"; return AMRVAC_E_ARG; }
-    long p[3] = {ijk[3 * b], ijk[3 * b + 1], ndim == 3 ? ijk[3 * b + 2] : 0};
+    const long p[3] = {ijk[3 * b], ijk[3 * b + 1], ndim == 3 ? ijk[3 * b + 2] : 0};
     for (int d = 0; d < ndim; ++d)
       if (p[d] < 0 || p[d] >= ((long)g->base_blocks[d] << (l - 1))) { J.err = "block outside the domain"; return AMRVAC_E_ARG; }
-    if (!leaf.emplace(KeyL{l, p[0], p[1], p[2]}, b).second) { J.err = "duplicate block"; return AMRVAC_E_ARG; }
     J.finest = std::max(J.finest, l);
+  }
+  BlockLookup look(ndim, g->base_blocks, J.finest, nb);
+  double vol = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const int l = level[b];
+    long p[3] = {ijk[3 * b], ijk[3 * b + 1], ndim == 3 ? ijk[3 * b + 2] : 0};
+    if (!look.add_leaf(KeyL{l, p[0], p[1], p[2]}, b)) { J.err = "duplicate block"; return AMRVAC_E_ARG; }
     vol += std::ldexp(1.0, -ndim * (l - 1));
     for (int m = l - 1; m >= 1; --m) {
       for (int d = 0; d < 3; ++d) p[d] >>= 1;
-      refined.insert(KeyL{m, p[0], p[1], p[2]});
+      look.add_refined(KeyL{m, p[0], p[1], p[2]});
     }
   }
-  for (const auto& kv : leaf)
-    if (refined.count(kv.first)) { J.err = "blocks overlap (a leaf is also refined)"; return AMRVAC_E_ARG; }
+  if (look.overlap()) { J.err = "blocks overlap (a leaf is also refined)"; return AMRVAC_E_ARG; }
   const double nbase = (double)g->base_blocks[0] * g->base_blocks[1] * (ndim == 3 ? g->base_blocks[2] : 1);
   if (std::fabs(vol - nbase) > 1e-9 * nbase) { J.err = "blocks do not tile the domain"; return AMRVAC_E_ARG; }
 
@@ -157,9 +240,9 @@ int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ij
   auto periodic = [&](int d) { return g->bc_lo[d] == AMRVAC_BC_PERIODIC; };
   // 2:1 nesting over faces, edges and corners: every slot next to a leaf of
   // level l is a leaf, refined into leaves, or inside a leaf of level l-1.
-  for (const auto& kv : leaf) {
-    const int l = kv.first.l;
-    const long p[3] = {kv.first.i, kv.first.j, kv.first.k};
+  for (int b = 0; b < nb; ++b) {
+    const int l = level[b];
+    const long p[3] = {ijk[3 * b], ijk[3 * b + 1], ndim == 3 ? ijk[3 * b + 2] : 0};
     for (int oz = (ndim == 3 ? -1 : 0); oz <= (ndim == 3 ? 1 : 0); ++oz)
       for (int oy = -1; oy <= 1; ++oy)
         for (int ox = -1; ox <= 1; ++ox) {
@@ -172,8 +255,8 @@ int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ij
             }
           if (skip) continue;
           const KeyL k{l, q[0], q[1], q[2]};
-          if (leaf.count(k)) continue;
-          if (refined.count(k)) {
+          if (look.leaf(k) >= 0) continue;
+          if (look.refined(k)) {
             const long off[3] = {ox, oy, oz};
             for (int cz = 0; cz < (ndim == 3 ? 2 : 1); ++cz)
               for (int cy = 0; cy < 2; ++cy)
@@ -186,11 +269,11 @@ int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ij
                   }
                   if (!adjacent) continue;
                   const KeyL ck{l + 1, 2 * q[0] + cx, 2 * q[1] + cy, ndim == 3 ? 2 * q[2] + cz : 0};
-                  if (!leaf.count(ck)) { J.err = "hierarchy is not 2:1 nested (finer by two)"; return AMRVAC_E_ARG; }
+                  if (look.leaf(ck) < 0) { J.err = "hierarchy is not 2:1 nested (finer by two)"; return AMRVAC_E_ARG; }
                 }
             continue;
           }
-          if (l >= 2 && leaf.count(KeyL{l - 1, q[0] >> 1, q[1] >> 1, ndim == 3 ? q[2] >> 1 : 0})) continue;
+          if (l >= 2 && look.leaf(KeyL{l - 1, q[0] >> 1, q[1] >> 1, ndim == 3 ? q[2] >> 1 : 0}) >= 0) continue;
           J.err = "hierarchy is not 2:1 nested (coarser by two)";
           return AMRVAC_E_ARG;
         }
@@ -225,15 +308,15 @@ int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ij
           }
           q[d] = (q[d] + nblk(l, d)) % nblk(l, d);
         }
-        auto it = leaf.find(KeyL{l, q[0], q[1], q[2]});
-        if (it != leaf.end()) {
+        const int same = look.leaf(KeyL{l, q[0], q[1], q[2]});
+        if (same >= 0) {
           Lk[0] = LINK_SAME;
-          Lk[1] = first + it->second;
+          Lk[1] = first + same;
           J.tfill.push_back(first + b);
           J.tfill.push_back(d * 2 + side);
           continue;
         }
-        if (refined.count(KeyL{l, q[0], q[1], q[2]})) {
+        if (look.refined(KeyL{l, q[0], q[1], q[2]})) {
           Lk[0] = LINK_FINE;
           const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
           for (int ob = 0; ob < (ndim == 3 ? 2 : 1); ++ob)
@@ -242,9 +325,9 @@ int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ij
               cq[d] += side ? 0 : 1;
               cq[ta] += oa;
               if (ndim == 3) cq[tb] += ob;
-              auto ci = leaf.find(KeyL{l + 1, cq[0], cq[1], cq[2]});
-              if (ci == leaf.end()) { J.err = "fine neighbour is not a leaf"; return AMRVAC_E_ARG; }
-              Lk[1 + ob * 2 + oa] = first + ci->second;
+              const int ci = look.leaf(KeyL{l + 1, cq[0], cq[1], cq[2]});
+              if (ci < 0) { J.err = "fine neighbour is not a leaf"; return AMRVAC_E_ARG; }
+              Lk[1 + ob * 2 + oa] = first + ci;
             }
           J.tfill.push_back(first + b);
           J.tfill.push_back(d * 2 + side);
@@ -252,10 +335,10 @@ int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ij
           J.trefl.push_back(d * 2 + side);
           continue;
         }
-        auto pi = leaf.find(KeyL{l - 1, q[0] >> 1, q[1] >> 1, ndim == 3 ? q[2] >> 1 : 0});
-        if (l < 2 || pi == leaf.end()) { J.err = "face neighbour not found (hierarchy not 2:1 nested)"; return AMRVAC_E_ARG; }
+        const int pi = l >= 2 ? look.leaf(KeyL{l - 1, q[0] >> 1, q[1] >> 1, ndim == 3 ? q[2] >> 1 : 0}) : -1;
+        if (pi < 0) { J.err = "face neighbour not found (hierarchy not 2:1 nested)"; return AMRVAC_E_ARG; }
         Lk[0] = LINK_COARSE;
-        Lk[1] = first + pi->second;
+        Lk[1] = first + pi;
         Lk[2] = l;
         J.tprol.push_back(first + b);
         J.tprol.push_back(d * 2 + side);
@@ -870,11 +953,16 @@ struct Planner {
     }
     return KeyL{0, 0, 0, 0};
   }
-  void refine(const KeyL& k) {
+  // replace leaf k by its children; the children are appended to *born
+  void refine(const KeyL& k, std::vector<KeyL>* born) {
     leaves.erase(k);
     for (int cz = 0; cz < (ndim == 3 ? 2 : 1); ++cz)
       for (int cy = 0; cy < 2; ++cy)
-        for (int cx = 0; cx < 2; ++cx) leaves.insert(KeyL{k.l + 1, 2 * k.i + cx, 2 * k.j + cy, ndim == 3 ? 2 * k.k + cz : 0});
+        for (int cx = 0; cx < 2; ++cx) {
+          const KeyL c{k.l + 1, 2 * k.i + cx, 2 * k.j + cy, ndim == 3 ? 2 * k.k + cz : 0};
+          leaves.insert(c);
+          born->push_back(c);
+        }
   }
   template <class F>
   void for_neighbours(const KeyL& k, F f) const {
@@ -888,21 +976,24 @@ struct Planner {
           f(q, off);
         }
   }
-  // refine leaves that are two levels coarser than a neighbour of a leaf
-  void nest() {
-    for (bool changed = true; changed;) {
-      changed = false;
-      std::vector<KeyL> todo;
-      for (const KeyL& k : leaves)
-        for_neighbours(k, [&](const long q[3], const long*) {
-          const int m = cover(k.l, q);
-          if (m != 0 && m < k.l - 1) todo.push_back(cover_key(k.l, q));
-        });
-      for (const KeyL& t : todo)
-        if (leaves.count(t)) {
-          refine(t);
-          changed = true;
+  // refine leaves that are two levels coarser than a neighbour of a leaf.
+  // The input set was 2:1 nested, so a violation needs a new leaf on its
+  // fine side: only the leaves born by refinement (and those born while
+  // restoring) are examined, as a work list.
+  void nest(std::vector<KeyL> work) {
+    while (!work.empty()) {
+      const KeyL k = work.back();
+      work.pop_back();
+      if (!leaves.count(k)) continue;  // refined again meanwhile
+      for_neighbours(k, [&](const long q[3], const long*) {
+        const int m = cover(k.l, q);
+        if (m != 0 && m < k.l - 1) {
+          const KeyL t = cover_key(k.l, q);
+          if (leaves.count(t)) refine(t, &work);
         }
+      });
+      // (a refinement above may have coarse neighbours of its own: its
+      // children are on the work list)
     }
   }
   // would the leaf parent (replacing its children) be next to a leaf two
@@ -1061,9 +1152,10 @@ int amrvac_regrid_plan(const amrvac_grid_desc* g, int nb, const int* level, cons
     old[k] = b;
     P.leaves.insert(k);
   }
+  std::vector<KeyL> born;
   for (const auto& kv : old)
-    if (flags[kv.second] > 0 && kv.first.l < lmax) P.refine(kv.first);
-  P.nest();
+    if (flags[kv.second] > 0 && kv.first.l < lmax) P.refine(kv.first, &born);
+  P.nest(std::move(born));
   // coarsen complete sibling sets of old leaves that are all flagged, one
   // parent at a time, where nesting allows
   KeySet parents;
