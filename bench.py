@@ -326,7 +326,10 @@ def main():
                 r0 = time.perf_counter()
                 flags = cur.lohner_flags(refine=0.1, coarsen_ratio=0.25, weights=[1.0] + [0.0] * 8)
                 r1 = time.perf_counter()
-                lv, ij = cur.regrid_plan(flags, max_level=max(args.levels, int(w.level.max())))
+                # (2D workloads may refine up to --levels; 3D ones keep their
+                # deepest level, as eight children per refinement fill HBM fast)
+                cap = max(args.levels, int(w.level.max())) if w.ndim == 2 else int(w.level.max())
+                lv, ij = cur.regrid_plan(flags, max_level=cap)
                 new = cur.regrid(lv, ij)
                 if cur is not sim:
                     cur.close()

@@ -842,6 +842,21 @@ int enqueue_step(amrvac_ctx* c, int nstages, double* dt, double* ch, double* kap
 
 int slots_for_stages(int nstages) { return nstages >= 5 ? 4 : (nstages >= 3 ? 3 : 2); }
 
+// The plain (per-kernel) FP64 path's primitive and face-flux scratch,
+// allocated on its first use: a context that only runs the fused path never
+// holds it (for 4096 blocks of 16^3 it is 6 GB).  Called by the entry points
+// before they enqueue work, so never inside a graph capture.
+int ensure_plain_scratch(amrvac_ctx* c) {
+  if (c->path != AMRVAC_PATH_PLAIN || c->d_prim) return AMRVAC_OK;
+  const size_t nb = (size_t)c->cap;
+  const size_t pcs = nb * NV * c->G.pcells * sizeof(double);
+  const size_t fcs = nb * NV * c->G.nfaces * sizeof(double);
+  if (int rc = dev_alloc(c, (void**)&c->d_prim, pcs)) return rc;
+  for (int d = 0; d < c->G.ndim; ++d)
+    if (int rc = dev_alloc(c, (void**)&c->d_flux[d], fcs)) return rc;
+  return AMRVAC_OK;
+}
+
 int stage_entry(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
                 const double* kappa_dev, bool fold_cfl) {
   if (!c) return AMRVAC_E_ARG;
@@ -858,6 +873,7 @@ int stage_entry(amrvac_ctx* c, int in, int base, int out, double w, const double
   if (!dt_dev || !ch_dev || !kappa_dev) return fail(c, AMRVAC_E_ARG, "null dt/c_h/kappa pointer");
   if (!(w > 0.0 && w <= 1.0)) return fail(c, AMRVAC_E_ARG, "stage weight must be in (0, 1]");
   if (int rc = ensure_tables(c)) return rc;
+  if (int rc = ensure_plain_scratch(c)) return rc;
   return stage_any(c, in, base, out, w, JobScalars{dt_dev, ch_dev, kappa_dev}, fold_cfl);
 }
 
@@ -894,13 +910,6 @@ int create_single(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, const int
   J.nb = nb;
   c->jobs.push_back(std::move(J));
   int rc = alloc_context(c);
-  if (!rc && g->precision == AMRVAC_FP64) {
-    // primitive and face-flux scratch of the plain (per-kernel) FP64 path
-    const size_t pcs = (size_t)nb * NV * c->G.pcells * sizeof(double);
-    const size_t fcs = (size_t)nb * NV * c->G.nfaces * sizeof(double);
-    rc = dev_alloc(c, (void**)&c->d_prim, pcs);
-    for (int d = 0; d < g->ndim && !rc; ++d) rc = dev_alloc(c, (void**)&c->d_flux[d], fcs);
-  }
   if (!rc) rc = upload_job_blocks(c, c->jobs[0], 0);
   if (!rc) rc = rebuild(c);
   if (!rc) {
@@ -1296,6 +1305,7 @@ int amrvac_advance(amrvac_ctx* c, int nsteps, int nstages, int use_graph) {
   if ((int)c->slots.size() < slots_for_stages(nstages)) return fail(c, AMRVAC_E_ARG, "not enough slots");
   if (nsteps < 0) return fail(c, AMRVAC_E_ARG, "negative step count");
   if (int rc = ensure_tables(c)) return rc;
+  if (int rc = ensure_plain_scratch(c)) return rc;
   double *dt = c->d_jdt, *ch = c->d_jch, *kap = c->d_jkappa;
   if (!use_graph) {
     for (int n = 0; n < nsteps; ++n)
