@@ -33,33 +33,33 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
                   "paper_2303_03026_amd/csrc/kernels.h", "paper_2303_03026_amd/csrc/runtime.cpp")
 MEASURED_TRAFFIC = {
-    ("a36dd00d61611f29", "f64"): {
-        (1, 0, 0): ((2855130, 1180185), (3631973, 1180199)),
-        (1, 0, 1): ((2712809, 1180116), (3556958, 1180234)),
-        (1, 1, 0): ((2859229, 1179994), (3649093, 1180402)),
-        (1, 1, 1): ((2695544, 1180008), (3550869, 1180461)),
-        (2, 0, 0): ((3072984, 1179928), (3858554, 1180123)),
-        (2, 0, 1): ((2943674, 1179947), (3803128, 1180166)),
-        (2, 1, 0): ((3083109, 1179903), (3859760, 1180186)),
-        (2, 1, 1): ((2928451, 1179969), (3777996, 1180273)),
-        (4, 0, 0): ((3514040, 1179722), (4298961, 1179810)),
-        (4, 0, 1): ((3169554, 1179747), (4066431, 1179821)),
-        (4, 1, 0): ((3520570, 1179756), (4307289, 1179833)),
-        (4, 1, 1): ((3140750, 1179775), (4074083, 1179859)),
+    ("c844569f5873c3a0", "f64"): {
+        (1, 0, 0): ((2853453, 1180208), (3633958, 1180177)),
+        (1, 0, 1): ((2714333, 1180126), (3559286, 1180284)),
+        (1, 1, 0): ((2859553, 1179961), (3650040, 1180436)),
+        (1, 1, 1): ((2700378, 1180005), (3551016, 1180506)),
+        (2, 0, 0): ((3068291, 1179909), (3846968, 1180159)),
+        (2, 0, 1): ((2943340, 1179949), (3800461, 1180165)),
+        (2, 1, 0): ((3080631, 1179931), (3857629, 1180228)),
+        (2, 1, 1): ((2925415, 1179976), (3784946, 1180279)),
+        (4, 0, 0): ((3512495, 1179738), (4303678, 1179809)),
+        (4, 0, 1): ((3174580, 1179791), (4068094, 1179826)),
+        (4, 1, 0): ((3521177, 1179759), (4300705, 1179839)),
+        (4, 1, 1): ((3146613, 1179781), (4055152, 1179847)),
     },
-    ("a36dd00d61611f29", "mixed"): {
-        (1, 0, 0): ((1712331, 819504), (2190389, 819515)),
-        (1, 0, 1): ((1568298, 819481), (2073440, 819571)),
-        (1, 1, 0): ((1707455, 819479), (2169571, 819678)),
-        (1, 1, 1): ((1568652, 819458), (2074584, 819697)),
-        (2, 0, 0): ((1829182, 819355), (2305834, 819448)),
-        (2, 0, 1): ((1704389, 819369), (2214793, 819447)),
-        (2, 1, 0): ((1832268, 819414), (2309631, 819540)),
-        (2, 1, 1): ((1709081, 819400), (2218237, 819531)),
-        (4, 0, 0): ((2097817, 819253), (2560112, 819364)),
-        (4, 0, 1): ((1824434, 819232), (2365462, 819338)),
-        (4, 1, 0): ((2101178, 819264), (2561525, 819378)),
-        (4, 1, 1): ((1822718, 819241), (2368329, 819363)),
+    ("c844569f5873c3a0", "mixed"): {
+        (1, 0, 0): ((1711942, 819503), (2179452, 819548)),
+        (1, 0, 1): ((1570125, 819484), (2071242, 819554)),
+        (1, 1, 0): ((1706703, 819482), (2172268, 819685)),
+        (1, 1, 1): ((1569218, 819449), (2077397, 819732)),
+        (2, 0, 0): ((1825838, 819375), (2299265, 819451)),
+        (2, 0, 1): ((1702172, 819353), (2215467, 819465)),
+        (2, 1, 0): ((1831283, 819409), (2309078, 819547)),
+        (2, 1, 1): ((1707388, 819394), (2217748, 819551)),
+        (4, 0, 0): ((2096221, 819254), (2558195, 819356)),
+        (4, 0, 1): ((1822831, 819238), (2365597, 819340)),
+        (4, 1, 0): ((2101347, 819266), (2564733, 819359)),
+        (4, 1, 1): ((1824099, 819245), (2362623, 819357)),
     },
 }
 FETCH_CAL, WRITE_CAL = 2.0, 1.0
