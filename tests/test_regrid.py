@@ -256,3 +256,48 @@ def test_oracle_prolongation_reproduces_linear_data(amr, orc):
         np.testing.assert_allclose(un[b, RHO], rho, rtol=1e-14)
         bx = 1.0 + 0.6 * xn[b] + 0.1 * yn[b]
         np.testing.assert_allclose(un[b, BX], bx, rtol=1e-14)
+
+
+def _corner_chain(levels):
+    """One base block refined at its (0,0,0) corner child again and again, up
+    to ``levels``: a valid 2:1-nested 3D hierarchy with zero-gradient
+    faces."""
+    leaves = {(1, 0, 0, 0)}
+    for l in range(1, levels):
+        leaves.discard((l, 0, 0, 0))
+        for a in (0, 1):
+            for b in (0, 1):
+                for c in (0, 1):
+                    leaves.add((l + 1, a, b, c))
+    keys = sorted(leaves)
+    level = np.array([k[0] for k in keys], dtype=np.int32)
+    ijk = np.array([k[1:] for k in keys], dtype=np.int32)
+    w = inputs.uniform_state(3, (1, 1, 1), [1.0, 0, 0, 0, 1.0, 0, 0, 0, 0], nx=4, bc_lo=(1, 1, 1), bc_hi=(1, 1, 1),
+                             level=level, ijk=ijk)
+    return w
+
+
+@pytest.mark.parametrize("levels", [8, 9])
+def test_block_tables_dense_and_hashed_lookup(amr, levels):
+    """Block tables index leaves with dense per-level arrays while the levels
+    hold at most 2^24 slots together, else with hash maps: 8 levels of a 3D
+    corner chain stay dense (2.4 M slots), 9 do not (19 M).  Both validate the
+    chain, keep it when no block is flagged, refine its finest block with
+    nesting restored, and refuse a duplicate and an overlapping block."""
+    w = _corner_chain(levels)
+    assert int(w.level.max()) == levels and w.nblocks == 1 + 7 * (levels - 1)
+    lv, ij = plan(amr, w, np.zeros(w.nblocks), max_level=levels + 1)
+    assert keys(lv, ij) == keys(w.level, w.ijk)
+    flags = np.where(w.level == levels, 1, 0)
+    flags[np.argmax((w.level == levels) & (w.ijk.sum(axis=1) == 0))] = 1
+    lv, ij = plan(amr, w, flags, max_level=levels + 1)
+    assert int(lv.max()) == levels + 1
+    check_one_level_change(3, keys(w.level, w.ijk), keys(lv, ij))
+    dup = dataclasses.replace(w, level=np.append(w.level, w.level[0]), ijk=np.vstack([w.ijk, w.ijk[:1]]))
+    with pytest.raises(amr.AmrvacError):
+        amr.regrid_plan(dup, np.zeros(dup.nblocks))
+    # a block of the coarsest level that covers refined ones
+    over = dataclasses.replace(w, level=np.append(w.level, 1).astype(np.int32),
+                               ijk=np.vstack([w.ijk, [[0, 0, 0]]]).astype(np.int32))
+    with pytest.raises(amr.AmrvacError):
+        amr.regrid_plan(over, np.zeros(over.nblocks))
