@@ -33,33 +33,33 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
                   "paper_2303_03026_amd/csrc/kernels.h", "paper_2303_03026_amd/csrc/runtime.cpp")
 MEASURED_TRAFFIC = {
-    ("c844569f5873c3a0", "f64"): {
-        (1, 0, 0): ((2853453, 1180208), (3633958, 1180177)),
-        (1, 0, 1): ((2714333, 1180126), (3559286, 1180284)),
-        (1, 1, 0): ((2859553, 1179961), (3650040, 1180436)),
-        (1, 1, 1): ((2700378, 1180005), (3551016, 1180506)),
-        (2, 0, 0): ((3068291, 1179909), (3846968, 1180159)),
-        (2, 0, 1): ((2943340, 1179949), (3800461, 1180165)),
-        (2, 1, 0): ((3080631, 1179931), (3857629, 1180228)),
-        (2, 1, 1): ((2925415, 1179976), (3784946, 1180279)),
-        (4, 0, 0): ((3512495, 1179738), (4303678, 1179809)),
-        (4, 0, 1): ((3174580, 1179791), (4068094, 1179826)),
-        (4, 1, 0): ((3521177, 1179759), (4300705, 1179839)),
-        (4, 1, 1): ((3146613, 1179781), (4055152, 1179847)),
+    ("85fbb682025e7cf6", "f64"): {
+        (1, 0, 0): ((2853971, 1180213), (3635124, 1180186)),
+        (1, 0, 1): ((2711750, 1180135), (3556114, 1180210)),
+        (1, 1, 0): ((2860358, 1179945), (3646867, 1180327)),
+        (1, 1, 1): ((2697082, 1180012), (3551265, 1180446)),
+        (2, 0, 0): ((3065565, 1179902), (3855293, 1180110)),
+        (2, 0, 1): ((2943412, 1179929), (3803694, 1180104)),
+        (2, 1, 0): ((3083797, 1179876), (3860799, 1180154)),
+        (2, 1, 1): ((2930331, 1179949), (3782540, 1180241)),
+        (4, 0, 0): ((3509365, 1179740), (4303084, 1179806)),
+        (4, 0, 1): ((3175818, 1179747), (4059770, 1179807)),
+        (4, 1, 0): ((3516348, 1179749), (4305320, 1179841)),
+        (4, 1, 1): ((3151064, 1179784), (4069100, 1179847)),
     },
-    ("c844569f5873c3a0", "mixed"): {
-        (1, 0, 0): ((1711942, 819503), (2179452, 819548)),
-        (1, 0, 1): ((1570125, 819484), (2071242, 819554)),
-        (1, 1, 0): ((1706703, 819482), (2172268, 819685)),
-        (1, 1, 1): ((1569218, 819449), (2077397, 819732)),
-        (2, 0, 0): ((1825838, 819375), (2299265, 819451)),
-        (2, 0, 1): ((1702172, 819353), (2215467, 819465)),
-        (2, 1, 0): ((1831283, 819409), (2309078, 819547)),
-        (2, 1, 1): ((1707388, 819394), (2217748, 819551)),
-        (4, 0, 0): ((2096221, 819254), (2558195, 819356)),
-        (4, 0, 1): ((1822831, 819238), (2365597, 819340)),
-        (4, 1, 0): ((2101347, 819266), (2564733, 819359)),
-        (4, 1, 1): ((1824099, 819245), (2362623, 819357)),
+    ("85fbb682025e7cf6", "mixed"): {
+        (1, 0, 0): ((1711248, 819487), (2175041, 819515)),
+        (1, 0, 1): ((1570383, 819447), (2071591, 819548)),
+        (1, 1, 0): ((1706729, 819438), (2170357, 819709)),
+        (1, 1, 1): ((1570718, 819457), (2076652, 819708)),
+        (2, 0, 0): ((1824812, 819363), (2300065, 819474)),
+        (2, 0, 1): ((1702641, 819348), (2214107, 819452)),
+        (2, 1, 0): ((1829813, 819384), (2308121, 819582)),
+        (2, 1, 1): ((1707661, 819384), (2216199, 819553)),
+        (4, 0, 0): ((2095719, 819257), (2557707, 819358)),
+        (4, 0, 1): ((1824226, 819233), (2366593, 819338)),
+        (4, 1, 0): ((2099225, 819257), (2563594, 819378)),
+        (4, 1, 1): ((1822572, 819235), (2365448, 819349)),
     },
 }
 FETCH_CAL, WRITE_CAL = 2.0, 1.0
@@ -203,11 +203,12 @@ def main():
     w.flux = {"hll": 0, "hlld": 1, "hllc": 2}[args.flux]
     mixed = args.precision == "mixed"
     w.ng = 2
-    if w.limiter >= 3:  # the five-cell stencils: 3 ghost layers, plain FP64 path
+    if w.limiter >= 3:  # the five-cell stencils: 3 ghost layers, FP64 (fused in 2D only)
         if mixed:
-            sys.exit("bench: the fifth-order reconstructions run on the FP64 plain path only")
+            sys.exit("bench: the fifth-order reconstructions run in FP64 only")
         w.ng = 3
-        args.path = "plain"
+        if w.ndim == 3:
+            args.path = "plain"
     if mixed:
         args.path = "fused"
     path = amrvac.PATH_FUSED if args.path == "fused" else amrvac.PATH_PLAIN
@@ -228,13 +229,13 @@ def main():
         print(json.dumps({"sweep_shapes": order, "launches_per_shape": ["w=1", "w<1"]}), flush=True)
         return
     tune_times = {}
-    if path == amrvac.PATH_FUSED and args.tune != "default":
+    if path == amrvac.PATH_FUSED and w.ng == 2 and args.tune != "default":
         if args.tune == "auto":
             print("bench: autotuning the fused stage", file=sys.stderr, flush=True)
             _, tune_times = sim.autotune(in_slot=0, out_slot=1, reps=3)
         else:
             sim.set_tune(*[int(v) for v in args.tune.split(",")])
-    tune = sim.get_tune() if path == amrvac.PATH_FUSED else None
+    tune = sim.get_tune() if path == amrvac.PATH_FUSED and w.ng == 2 else None
     weights = [(0, 0, 1, 1.0), (1, 0, 2, 0.25), (2, 0, 0, 2.0 / 3.0)]
 
     def step(events=None):

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamrvac.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["plain.hip", "fused.hip", "runtime.cpp"]
+SOURCES = ["plain.hip", "fused.hip", "fused5.hip", "runtime.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-Rpass-analysis=kernel-resource-usage", "-ffp-contract=on", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics"]

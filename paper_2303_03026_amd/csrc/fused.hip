@@ -541,7 +541,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                               const FusedTune& tune, const void* in, const void* base, void* out, double w,
                               const PhysConst& P, DevStatus* st, const JobCfl* cfl) {
-  if (G.nx != BN) return hipErrorInvalidValue;
+  if (G.nx != BN || G.ng != 2) return hipErrorInvalidValue;
   if (tune.zseg != 1 && tune.zseg != 2 && tune.zseg != 4) return hipErrorInvalidValue;
   if (T.nactive <= 0) return hipSuccess;
   const long items = (long)T.nactive * (G.ndim == 3 ? tune.zseg : 1);

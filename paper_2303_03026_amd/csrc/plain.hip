@@ -399,10 +399,11 @@ __global__ void __launch_bounds__(256) k_update(GridConst G, Tables T, const dou
 // coarse face flux used by the stage with the pairwise mean of the fine face
 // fluxes, i.e. out += w*dt*dL.  Both fluxes are recomputed from the stage
 // input (ghosts filled) exactly as the stage kernels compute them.
-template <int D, class SP>
+template <int D, class SP, bool SIX>
 __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const void* __restrict__ S, int f, int t1,
                                                     int t2, typename SP::R ch, typename SP::R hic,
-                                                    const PhysConst& P, typename SP::R F[NV]) {
+                                                    const PhysConst& P, const double* __restrict__ inv_dx, int blk,
+                                                    typename SP::R F[NV]) {
   using R = typename SP::R;
   R wl[NV], wr[NV];
   auto cell = [&](int a, R w[NV]) {
@@ -415,7 +416,20 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
     for (int q = 0; q < NV; ++q) u[q] = SP::ld(S, q, c, G.pcells);
     (void)cons_to_prim(u, w, P);
   };
-  // (the fused path, the only user, has 2 ghost layers: a four-cell stencil)
+  if constexpr (SIX && SP::kBytesPerCell == 72) {
+    if (G.ng == 3) {
+      // the fused path with three ghost layers (2D FP64): the six-cell
+      // stencil and face states of the per-kernel path's flux kernel
+      double c6[6][NV];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) cell(f - 3 + s, c6[s]);
+      const double lambda = P.limiter == LIM_WENOZP5 ? 1.0 / cbrt(inv_dx[3 * blk + D] * inv_dx[3 * blk + D]) : 0.0;
+      reconstruct_face6(P.limiter, c6, lambda, wl, wr);
+      face_flux_rt<D, R>(P.flux, wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
+      return;
+    }
+  }
+  // otherwise two ghost layers: a four-cell stencil
   R w4[4][NV];
   if constexpr (D == 0 && SP::kBytesPerCell == 72) {
     // x faces: the four cells of a variable are consecutive in one row, so
@@ -443,47 +457,80 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
   face_flux_rt<D, R>(P.flux, wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
 }
 
-template <int D, class SP>
+// In 2D each (task, face cell) takes a group of NS = 4 consecutive lanes
+// (the coarse face, the two fine faces, one idle lane): every lane evaluates
+// one face flux, so a correction costs one face evaluation of latency rather
+// than three, and the group's first lane gathers the fine fluxes and applies
+// the update.  In 3D (NS = 1) one lane evaluates all five faces: there the
+// tasks are many and the four-cell faces cheap, and idle lanes of eight-lane
+// groups cost more than the latency saved.
+template <int D, class SP, int NS, int NFINE>
 __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, JobScalars J,
                                                        const int* __restrict__ tasks, int ntasks,
                                                        const void* __restrict__ in, void* out, double w,
                                                        PhysConst P) {
+  static_assert((NS == 4 && NFINE == 2) || (NS == 1 && NFINE == 4), "2D: four lanes; 3D: one");
   const int* __restrict__ link = T.link;
   using R = typename SP::R;
   const int nx = G.nx;
   const int per = G.ndim == 3 ? nx * nx : nx;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)ntasks * per) return;
-  const int task = (int)(gid / per);
-  const int t = (int)(gid - (long)task * per);
+  // groups are aligned to NS lanes and NS divides 64: a group leaves
+  // together and never straddles two waves
+  if (gid >= (long)ntasks * per * NS) return;
+  const long item = gid / NS;
+  const int sub = (int)(gid - item * NS);
+  const int task = (int)(item / per);
+  const int t = (int)(item - (long)task * per);
   const int b = tasks[2 * task], face = tasks[2 * task + 1];
   if ((face >> 1) != D) return;
   const int side = face & 1;
   const int* L = link + ((long)b * 6 + face) * LINK_INTS;
   const int t1 = t % nx, t2 = G.ndim == 3 ? t / nx : 0;
   const int job = T.job[b];
-  const double dt = J.dt_scale * J.dt[job];
   const R ch = (R)J.ch[job], hic = (R)(0.5 / J.ch[job]);
   const long pc = G.pcells;
-  R Fc[NV], Ff[NV], v[2][2][NV];
-  face_flux_from_slot<D, SP>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, Fc);
-  const int ne = G.ndim == 3 ? 2 : 1;
-  // (unrolled: a run-time index into v would place it in scratch memory)
+  // fine face k = 2 e + a of the 2 x 2 (3D) or 2 x 1 (2D) behind this coarse face cell
+  auto fine_face = [&](int k, R Fo[NV]) {
+    const int a = k & 1, e = k >> 1;
+    const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
+    const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
+    const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
+    face_flux_from_slot<D, SP, NFINE == 2>(G, block_ptr<SP>(in, fb, pc), side ? 0 : nx, g1 - o1 * nx,
+                               G.ndim == 3 ? g2 - o2 * nx : 0, ch, hic, P, T.inv_dx, fb, Fo);
+  };
+  R F[NV], v[NFINE][NV];
+  if constexpr (NS == 1) {
+    face_flux_from_slot<D, SP, NFINE == 2>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, T.inv_dx, b, F);
+    // (unrolled: a run-time index into v would place it in scratch memory)
 #pragma unroll
-  for (int e = 0; e < 2; ++e)
+    for (int k = 0; k < NFINE; ++k) fine_face(k, v[k]);
+  } else {
+    if (sub == 0) {
+      face_flux_from_slot<D, SP, NFINE == 2>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, T.inv_dx, b, F);
+    } else if (sub <= NFINE) {
+      fine_face(sub - 1, F);
+    } else {
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      if (e >= ne) continue;
-      const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
-      const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
-      const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
-      face_flux_from_slot<D, SP>(G, block_ptr<SP>(in, fb, pc), side ? 0 : nx, g1 - o1 * nx,
-                                 G.ndim == 3 ? g2 - o2 * nx : 0, ch, hic, P, v[e][a]);
+      for (int q = 0; q < NV; ++q) F[q] = R(0);
     }
+    // every lane of the group is active here
+    const int first = (int)(threadIdx.x & 63) - sub;
 #pragma unroll
-  for (int q = 0; q < NV; ++q)
-    Ff[q] = G.ndim == 3 ? ((v[0][0][q] + v[0][1][q]) + (v[1][0][q] + v[1][1][q])) * R(0.25)
-                        : (v[0][0][q] + v[0][1][q]) * R(0.5);
+    for (int k = 0; k < NFINE; ++k)
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[k][q] = __shfl(F[q], first + 1 + k, 64);
+    if (sub != 0) return;
+  }
+  const double dt = J.dt_scale * J.dt[job];
+  R Ff[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    if constexpr (NFINE == 4)
+      Ff[q] = ((v[0][q] + v[1][q]) + (v[2][q] + v[3][q])) * R(0.25);
+    else
+      Ff[q] = (v[0][q] + v[1][q]) * R(0.5);
+  }
   const int cell_d = side ? nx - 1 : 0;
   long c;
   if (D == 0) c = pidx(G, cell_d, t1, t2);
@@ -493,7 +540,7 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, J
   void* o = block_ptr<SP>(out, b, pc);
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    const double df = (double)Ff[q] - (double)Fc[q];
+    const double df = (double)Ff[q] - (double)F[q];
     const double dl = side ? -df * idx : df * idx;
     SP::st(o, q, c, pc, SP::ld(o, q, c, pc) + w * dt * dl);
   }
@@ -882,10 +929,15 @@ hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables
   // one launch per direction, in order: a coarse cell next to finer leaves
   // across faces of two directions is corrected once per direction
   const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
-#define AMRVAC_REFLUX_LAUNCH(D, SPT)                                                                   \
-  if (count[D] > 0)                                                                                   \
-  k_reflux_correct<D, SPT><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(G, T, J, tasks + 2 * first[D], \
-                                                                           count[D], in, out, w, P)
+#define AMRVAC_REFLUX_LAUNCH(D, SPT)                                                                       \
+  if (count[D] > 0) {                                                                                     \
+    if (G.ndim == 3)                                                                                      \
+      k_reflux_correct<D, SPT, 1, 4><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(                    \
+          G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
+    else                                                                                                  \
+      k_reflux_correct<D, SPT, 4, 2><<<nblocks_for(count[D] * per * 4, 256), 256, 0, s>>>(                \
+          G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
+  }
   if (G.precision == 0) {
     AMRVAC_REFLUX_LAUNCH(0, StoreF64);
     AMRVAC_REFLUX_LAUNCH(1, StoreF64);

@@ -720,7 +720,7 @@ JobCfl cfl_state(amrvac_ctx* c, double* dt, double* ch, double* kappa) {
 // The fused stage can fold the next step's CFL rate into its output only
 // where nothing changes that output afterwards (no coarse/fine flux
 // correction).
-bool can_carry(const amrvac_ctx* c) { return c->path == AMRVAC_PATH_FUSED && c->n_trefl == 0; }
+bool can_carry(const amrvac_ctx* c) { return c->path == AMRVAC_PATH_FUSED && c->n_trefl == 0 && c->G.ng == 2; }
 
 int clear_if_dirty(amrvac_ctx* c) {
   if (c->acc_dirty) {
@@ -758,8 +758,12 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
       if (int rc = clear_if_dirty(c)) return rc;
       C = cfl_state(c, nullptr, nullptr, nullptr);
     }
-    HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->tune, c->slots[in], c->slots[base], c->slots[out], w,
-                                  c->P, c->d_status, fold ? &C : nullptr));
+    if (c->G.ng == 3)
+      HIP_TRY(c, launch_fused5_stage(c->stream, c->G, T, J, c->slots[in], c->slots[base], c->slots[out], w, c->P,
+                                     c->d_status));
+    else
+      HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->tune, c->slots[in], c->slots[base], c->slots[out], w,
+                                    c->P, c->d_status, fold ? &C : nullptr));
     if (fold) c->carry_slot = out;
     HIP_TRY(c, launch_reflux_correct(c->stream, c->G, T, J, c->d_trefl, c->refl_first, c->refl_count,
                                      c->slots[in], c->slots[out], w,
@@ -1291,7 +1295,8 @@ int amrvac_set_path(amrvac_ctx* c, int path) {
   if (!c) return AMRVAC_E_ARG;
   if (path != AMRVAC_PATH_PLAIN && path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_ARG, "unknown path");
   if (path == AMRVAC_PATH_FUSED && c->G.nx != 16) return fail(c, AMRVAC_E_ARG, "the fused path needs block_nx = 16");
-  if (path == AMRVAC_PATH_FUSED && c->G.ng != 2) return fail(c, AMRVAC_E_ARG, "the fused path needs nghost = 2");
+  if (path == AMRVAC_PATH_FUSED && c->G.ng != 2 && !(c->G.ng == 3 && c->G.ndim == 2 && c->g.precision == AMRVAC_FP64))
+    return fail(c, AMRVAC_E_ARG, "the fused path needs nghost = 2 (3 only for 2D FP64 grids)");
   if (path == AMRVAC_PATH_PLAIN && (c->g.precision != AMRVAC_FP64 || c->batch))
     return fail(c, AMRVAC_E_ARG, "the plain path is for single-job FP64 contexts");
   c->path = path;
@@ -1371,6 +1376,7 @@ int amrvac_autotune(amrvac_ctx* c, int in, int out, int reps, amrvac_tune* best,
   if (!c) return AMRVAC_E_ARG;
   if (c->batch) return fail(c, AMRVAC_E_STATE, "autotune a single-job context of the same shape");
   if (c->path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_STATE, "autotune needs the fused path");
+  if (c->G.ng != 2) return fail(c, AMRVAC_E_STATE, "autotune tunes the fused stage of two ghost layers");
   if (int rc = check_slot(c, in)) return rc;
   if (int rc = check_slot(c, out)) return rc;
   if (in == out) return fail(c, AMRVAC_E_ARG, "in and out slots must differ");

@@ -1,9 +1,10 @@
 """Fifth-order reconstructions on 3 ghost layers ('weno5': Jiang-Shu weights,
 'wenoz5': Borges et al.'s WENO-Z weights, 'wenozp5': Acker et al.'s WENO-Z+
 weights, 'mp5': Suresh and Huynh's monotonicity-preserving scheme), on the
-plain FP64 path, against the FP64 oracle.  The fused path, the
-mixed-precision path and the batch pool are built for 2 ghost layers and must
-refuse such a grid."""
+plain FP64 path, against the FP64 oracle.  The mixed-precision path, the
+batch pool and the fused path on 3D grids are built for 2 ghost layers and
+must refuse such a grid (the 2D fused path with 3 layers has its own
+tests)."""
 import numpy as np
 import pytest
 
