@@ -9,8 +9,8 @@
 // corners unused) live in LDS; halo cells across a face shared with a
 // same-level leaf are read in place from that neighbour's interior, the
 // others from this block's ghost cells (filled by the ghost kernels).  Each
-// thread computes the face on its left along x and the one below it along y;
-// the face fluxes of both directions are exchanged through LDS.  The arithmetic is the per-kernel path's step for step (same
+// thread evaluates one x face and one y face; neighbouring face fluxes come
+// by lane shuffles.  The arithmetic is the per-kernel path's step for step (same
 // primitive conversion, face states, flux and update order), so on grids
 // without coarse/fine faces the two paths agree bit for bit.
 #include <hip/hip_runtime.h>
@@ -33,12 +33,15 @@ constexpr int NF5 = BN5 + 1;        // faces per line
 __device__ __forceinline__ long cell5(const GridConst& G, int x, int y) { return (long)(y + NG5) * G.pn + (x + NG5); }
 
 template <bool W1>
-__global__ void __launch_bounds__(256, 2) k_stage_fused5(GridConst G, Tables T, JobScalars J, const void* __restrict__ in,
+__global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, JobScalars J, const void* __restrict__ in,
                                                          const void* base, void* out, double wgt, PhysConst P,
                                                          DevStatus* st) {
-  __shared__ double W[NV][P5 * S5];     // primitives, cell (x, y) at (y + 3) * S5 + (x + 3)
-  __shared__ double Fx[NV][NF5 * BN5];  // x-face fluxes: row * 17 + face
-  __shared__ double Fy[NV][NF5 * BN5];  // y-face fluxes: column * 17 + face
+  // primitives, cell (x, y) at (y + 3) * S5 + (x + 3); once all faces are
+  // evaluated the same storage carries the y flux differences to the cells'
+  // owners, cell (x, y) at y * NF5 + x
+  __shared__ double W[NV][P5 * S5];
+  __shared__ double Ex[NV][BN5];  // the 17th x face of each row
+  __shared__ double Ey[NV][BN5];  // the 17th y face of each column
   const int b = T.order[blockIdx.x];
   const int t = threadIdx.x, i = t & 15, j = t >> 4;
   const long PC = G.pcells;
@@ -104,13 +107,13 @@ __global__ void __launch_bounds__(256, 2) k_stage_fused5(GridConst G, Tables T, 
   // variable's six cells are read from LDS just before use (a few live
   // registers instead of all 54 values); the arithmetic is that of the
   // shared six-cell reconstruction.
-  auto face = [&](auto dir, int line, int f, double lambda, double (*Fo)[NF5 * BN5]) {
+  auto face = [&](auto dir, int line, int f, double lambda, double Fq[NV]) {
     constexpr int DIR = decltype(dir)::value;
     auto at = [&](int s) {
       const int a = f - NG5 + s;
       return DIR == 0 ? (line + NG5) * S5 + (a + NG5) : (a + NG5) * S5 + (line + NG5);
     };
-    double wl[NV], wr[NV], Fq[NV];
+    double wl[NV], wr[NV];
     if (lim >= LIM_WENO5) {
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
@@ -143,27 +146,49 @@ __global__ void __launch_bounds__(256, 2) k_stage_fused5(GridConst G, Tables T, 
       reconstruct_face(lim, c1, c2, c3, c4, wl, wr);
     }
     face_flux_rt<DIR, double>(P.flux, wl, wr, ch, 0.5 / ch, P.gamma, P.inv_gm1, Fq);
-#pragma unroll
-    for (int q = 0; q < NV; ++q) Fo[q][line * NF5 + f] = Fq[q];
   };
   using X = std::integral_constant<int, 0>;
   using Y = std::integral_constant<int, 1>;
 
-  // 2 x 16 x 17 faces on 4 waves: every thread its left face in row j and
-  // its lower face in column i; the 17th faces of the rows go to the first
-  // wave's lanes 0..15 and those of the columns to the second wave's, so no
-  // wave takes more than three face evaluations
-  face(X{}, j, i, lamx, Fx);
-  face(Y{}, i, j, lamy, Fy);
-  if (t < BN5) face(X{}, t, BN5, lamx, Fx);
-  else if (t >= 64 && t < 64 + BN5) face(Y{}, t - 64, BN5, lamy, Fy);
+  // 2 x 16 x 17 faces on 4 waves.  Along x thread t = (i, j) evaluates the
+  // left face of cell (i, j); along y it evaluates the lower face of cell
+  // (j, i) (transposed), so that in both directions the face above a thread's
+  // lies in the next lane of the same wave and reaches it by a lane shuffle.
+  // The 17th faces of the rows go to the first wave's lanes 0..15 and those
+  // of the columns to the second wave's, through LDS: no wave takes more
+  // than three face evaluations.
+  double fx[NV], fy[NV];
+  face(X{}, j, i, lamx, fx);
+  face(Y{}, j, i, lamy, fy);
+  if (t < BN5 || (t >= 64 && t < 64 + BN5)) {
+    double fe[NV];
+    if (t < BN5) {
+      face(X{}, t, BN5, lamx, fe);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) Ex[q][t] = fe[q];
+    } else {
+      face(Y{}, t - 64, BN5, lamy, fe);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) Ey[q][t - 64] = fe[q];
+    }
+  }
+  __syncthreads();  // every face evaluated: W is free, Ex / Ey written
+  const int up = (t & 63) + 1;
+  double dx[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double nx_ = __shfl(fx[q], up, 64), ny_ = __shfl(fy[q], up, 64);
+    dx[q] = (i < BN5 - 1 ? nx_ : Ex[q][j]) - fx[q];
+    // y difference of cell (j, i), handed to the thread that owns it
+    W[q][i * NF5 + j] = (i < BN5 - 1 ? ny_ : Ey[q][j]) - fy[q];
+  }
   __syncthreads();
   double L[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     L[q] = 0.0;
-    L[q] = L[q] + (Fx[q][j * NF5 + i + 1] - Fx[q][j * NF5 + i]) * idx;
-    L[q] = L[q] + (Fy[q][i * NF5 + j + 1] - Fy[q][i * NF5 + j]) * idy;
+    L[q] = L[q] + dx[q] * idx;
+    L[q] = L[q] + W[q][j * NF5 + i] * idy;
   }
 
   // update: L = -(sum_d dF_d / dx_d) - kappa psi; SSPRK combination
