@@ -185,6 +185,26 @@ int amrvac_stage(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double
 int amrvac_stage_cfl(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double w,
                      const double* dt_dev, const double* ch_dev, const double* kappa_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * amrvac_stage on the per-kernel (plain) FP64 path, with the same arguments,
+ * checks and result bit for bit, whose primitive and face-flux scratch is a
+ * static device array of AMRVAC_NOALLOC_SCRATCH_BYTES held by each GPU from
+ * the library's load until the process ends, instead of library allocations.
+ * It calls no allocating routine.  It runs the per-kernel kernels whatever
+ * path the context is set to; FP64 single-job contexts only (else
+ * AMRVAC_E_ARG, batch contexts AMRVAC_E_STATE).  A grid whose scratch
+ * (blocks x 9 x 8 B x (padded cells + ndim x faces per block), each part
+ * rounded up to 256 B) exceeds the array is rejected with AMRVAC_E_ARG and
+ * a message giving both sizes: 3D blocks of 16^3 need 1.52 MB each (up to
+ * 44 blocks), 2D blocks of 16^2 68 KB (up to 987).  Every call on a GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other contexts, other threads) race and must be ordered by the
+ * caller.  No part of the array needs to start cleared. */
+#define AMRVAC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int amrvac_stage_noalloc(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double w,
+                         const double* dt_dev, const double* ch_dev, const double* kappa_dev);
+
 /* Two-state combination on the leaf interior cells of every block:
  *   out = a + coef*(b - a)
  * (arithmetic in double; FP32-mixed slots round the result to their storage

@@ -30,7 +30,7 @@ ABI_SYMBOLS = ("amrvac_slot_bytes", "amrvac_init_blocks", "amrvac_set_primitive"
                "amrvac_batch_create", "amrvac_batch_add_job", "amrvac_batch_step", "amrvac_batch_job_info",
                "amrvac_batch_get_job", "amrvac_batch_remove_job", "amrvac_batch_free_blocks",
                "amrvac_set_tune", "amrvac_get_tune", "amrvac_autotune", "amrvac_stage_cfl", "amrvac_combine",
-               "amrvac_regrid_plan", "amrvac_regrid", "amrvac_lohner")
+               "amrvac_regrid_plan", "amrvac_regrid", "amrvac_lohner", "amrvac_stage_noalloc")
 TUNE_MAX_CANDIDATES = 12
 SLOT_LEAD_FP64 = 16  # bytes before the first block of an FP64 slot
 
@@ -93,6 +93,7 @@ def load_library():
     lib.amrvac_cfl_dt.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.amrvac_stage.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
     lib.amrvac_stage_cfl.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+    lib.amrvac_stage_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]
     lib.amrvac_combine.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]
     lib.amrvac_regrid_plan.argtypes = [ctypes.POINTER(GridDesc), ctypes.c_int, ip, ip, ip, ctypes.c_int, ctypes.c_int,
                                        ip, ip, ip]
@@ -299,6 +300,12 @@ class Simulation:
         fn = self.lib.amrvac_stage_cfl if cfl else self.lib.amrvac_stage
         self._check(fn(self.ctx, in_slot, base_slot, out_slot, weight, self.dt_ptr, self.ch_ptr, self.kappa_ptr),
                     self.ctx)
+
+    def stage_noalloc(self, in_slot: int, base_slot: int, out_slot: int, weight: float):
+        """amrvac_stage_noalloc: the per-kernel FP64 stage on the library's
+        static device scratch (no allocation)."""
+        self._check(self.lib.amrvac_stage_noalloc(self.ctx, in_slot, base_slot, out_slot, weight, self.dt_ptr,
+                                                  self.ch_ptr, self.kappa_ptr), self.ctx)
 
     def combine(self, a_slot: int, b_slot: int, coef: float, out_slot: int):
         """out = a + coef (b - a) on the leaf interior cells (amrvac_combine)."""

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <unordered_set>
 #include <set>
@@ -387,6 +388,50 @@ int build_job(const amrvac_grid_desc* g, int nb, const int* level, const int* ij
   return AMRVAC_OK;
 }
 
+
+// Scratch of amrvac_stage_noalloc: the per-kernel path's primitive and
+// face-flux buffers, for callers that cannot allocate device memory.  Each
+// device holds its own copy from the load of the library's code object until
+// the process ends.  Host code reaches it only through the per-device
+// address that hipGetSymbolAddress gives (the name itself is a host-side
+// stand-in, not a device address); that address is looked up once per
+// device, with the device current, by the init entry point.
+static __device__ __align__(256) unsigned char scratch[AMRVAC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+hipError_t g_scratch_err[kScratchDevices] = {};
+bool g_scratch_bound[kScratchDevices] = {};
+
+// Look up this device's copy of the scratch array (dev must be current).
+void bind_scratch(int dev) {
+  if (dev < 0 || dev >= kScratchDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_bound[dev]) return;
+  g_scratch_bound[dev] = true;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[dev] = e;
+  if (e == hipSuccess)
+    g_scratch_ptr[dev] = p;
+  else
+    (void)hipGetLastError();  // the error is kept here, not left for the next launch check
+}
+
+// This device's copy, or null with the lookup's error.
+void* scratch_of(int dev, hipError_t* err) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kScratchDevices || !g_scratch_bound[dev]) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
 thread_local std::string g_init_err;
 
 }  // namespace
@@ -745,6 +790,22 @@ int cfl_of_slot(amrvac_ctx* c, int slot, double* dt, double* ch, double* kap) {
   return AMRVAC_OK;
 }
 
+// The per-kernel (plain) FP64 stage on the given primitive and face-flux
+// scratch: conserved -> primitive over interior and face ghost cells, face
+// fluxes per direction, flux correction at coarse/fine faces, update.
+int plain_stage(amrvac_ctx* c, int in, int base, int out, double w, const JobScalars& J, double* prim,
+                double* const flux[3]) {
+  const Tables T = c->tables();
+  HIP_TRY(c, launch_prim(c->stream, c->G, c->slots[in], prim, c->P, c->d_status));
+  for (int d = 0; d < c->G.ndim; ++d)
+    HIP_TRY(c, launch_flux(c->stream, c->G, d, prim, flux[d], J.ch, c->P, T.inv_dx));
+  FluxPtrs fp{{flux[0], flux[1], flux[2]}};
+  HIP_TRY(c, launch_reflux(c->stream, c->G, c->d_trefl, c->n_trefl, T, fp));
+  HIP_TRY(c, launch_update(c->stream, c->G, T, c->slots[in], c->slots[base], c->slots[out], w, fp, J.dt, J.dt_scale,
+                           J.kappa));
+  return AMRVAC_OK;
+}
+
 // fold_cfl: on the fused path without flux corrections, also leave the CFL
 // rate of out in the accumulators (carry_slot = out).
 int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScalars& J, bool fold_cfl = false) {
@@ -770,14 +831,7 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
                                      c->P));
     return AMRVAC_OK;
   }
-  HIP_TRY(c, launch_prim(c->stream, c->G, c->slots[in], c->d_prim, c->P, c->d_status));
-  for (int d = 0; d < c->G.ndim; ++d)
-    HIP_TRY(c, launch_flux(c->stream, c->G, d, c->d_prim, c->d_flux[d], J.ch, c->P, T.inv_dx));
-  FluxPtrs fp{{c->d_flux[0], c->d_flux[1], c->d_flux[2]}};
-  HIP_TRY(c, launch_reflux(c->stream, c->G, c->d_trefl, c->n_trefl, T, fp));
-  HIP_TRY(c, launch_update(c->stream, c->G, T, c->slots[in], c->slots[base], c->slots[out], w, fp, J.dt, J.dt_scale,
-                           J.kappa));
-  return AMRVAC_OK;
+  return plain_stage(c, in, base, out, w, J, c->d_prim, c->d_flux);
 }
 
 // cfl -> [fill -> stage] x nstages on slots 0, 1, 2 with per-job scalars;
@@ -861,21 +915,29 @@ int ensure_plain_scratch(amrvac_ctx* c) {
   return AMRVAC_OK;
 }
 
-int stage_entry(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
-                const double* kappa_dev, bool fold_cfl) {
-  if (!c) return AMRVAC_E_ARG;
+// Argument checks shared by the stage entry points (base becomes out when
+// w == 1, where it is not read).
+int stage_args(amrvac_ctx* c, int in, int* base, int out, double w, const double* dt_dev, const double* ch_dev,
+               const double* kappa_dev) {
   if (c->batch) return fail(c, AMRVAC_E_STATE, "batch contexts step with amrvac_batch_step");
   if (int rc = check_slot(c, in)) return rc;
   if (int rc = check_slot(c, out)) return rc;
   if (w != 1.0) {
-    if (int rc = check_slot(c, base)) return rc;
+    if (int rc = check_slot(c, *base)) return rc;
   } else {
-    base = out;
+    *base = out;
   }
   if (in == out) return fail(c, AMRVAC_E_ARG, "in and out slots must differ");
-  if (base == in && w != 1.0) return fail(c, AMRVAC_E_ARG, "base must differ from in");
+  if (*base == in && w != 1.0) return fail(c, AMRVAC_E_ARG, "base must differ from in");
   if (!dt_dev || !ch_dev || !kappa_dev) return fail(c, AMRVAC_E_ARG, "null dt/c_h/kappa pointer");
   if (!(w > 0.0 && w <= 1.0)) return fail(c, AMRVAC_E_ARG, "stage weight must be in (0, 1]");
+  return AMRVAC_OK;
+}
+
+int stage_entry(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
+                const double* kappa_dev, bool fold_cfl) {
+  if (!c) return AMRVAC_E_ARG;
+  if (int rc = stage_args(c, in, &base, out, w, dt_dev, ch_dev, kappa_dev)) return rc;
   if (int rc = ensure_tables(c)) return rc;
   if (int rc = ensure_plain_scratch(c)) return rc;
   return stage_any(c, in, base, out, w, JobScalars{dt_dev, ch_dev, kappa_dev}, fold_cfl);
@@ -909,6 +971,7 @@ int create_single(amrvac_ctx** out, const amrvac_grid_desc* g, int nb, const int
   c->slots.clear();
   for (int k = 0; k < nslots; ++k) c->slots.push_back(static_cast<char*>(slots[k]) + slot_lead(g->precision));
   (void)hipGetDevice(&c->device);
+  bind_scratch(c->device);
   J.used = true;
   J.first = 0;
   J.nb = nb;
@@ -1107,6 +1170,32 @@ int amrvac_stage(amrvac_ctx* c, int in, int base, int out, double w, const doubl
 int amrvac_stage_cfl(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev, const double* ch_dev,
                      const double* kappa_dev) {
   return stage_entry(c, in, base, out, w, dt_dev, ch_dev, kappa_dev, true);
+}
+
+int amrvac_stage_noalloc(amrvac_ctx* c, int in, int base, int out, double w, const double* dt_dev,
+                         const double* ch_dev, const double* kappa_dev) {
+  if (!c) return AMRVAC_E_ARG;
+  if (c->g.precision != AMRVAC_FP64)
+    return fail(c, AMRVAC_E_ARG, "amrvac_stage_noalloc runs the per-kernel FP64 path: FP64 contexts only");
+  if (int rc = stage_args(c, in, &base, out, w, dt_dev, ch_dev, kappa_dev)) return rc;
+  if (c->dirty) return fail(c, AMRVAC_E_STATE, "the block tables need a rebuild, which allocates");
+  // primitives of every padded cell, then the face fluxes of each direction,
+  // each part starting on a 256-byte boundary
+  const size_t prim_bytes = ((size_t)c->G.nb * NV * c->G.pcells * sizeof(double) + 255) & ~(size_t)255;
+  const size_t flux_bytes = ((size_t)c->G.nb * NV * c->G.nfaces * sizeof(double) + 255) & ~(size_t)255;
+  const size_t need = prim_bytes + (size_t)c->G.ndim * flux_bytes;
+  if (need > (size_t)AMRVAC_NOALLOC_SCRATCH_BYTES)
+    return fail(c, AMRVAC_E_ARG,
+                "amrvac_stage_noalloc: this grid needs " + std::to_string(need) +
+                    " bytes of scratch, more than the static array's " +
+                    std::to_string((size_t)AMRVAC_NOALLOC_SCRATCH_BYTES) + " (AMRVAC_NOALLOC_SCRATCH_BYTES)");
+  hipError_t e;
+  char* p = static_cast<char*>(scratch_of(c->device, &e));
+  if (!p) return fail(c, AMRVAC_E_HIP, std::string("static scratch address not available: ") + hipGetErrorString(e));
+  double* flux[3] = {nullptr, nullptr, nullptr};
+  for (int d = 0; d < c->G.ndim; ++d) flux[d] = reinterpret_cast<double*>(p + prim_bytes + (size_t)d * flux_bytes);
+  touch_slot(c, out);
+  return plain_stage(c, in, base, out, w, JobScalars{dt_dev, ch_dev, kappa_dev}, reinterpret_cast<double*>(p), flux);
 }
 
 int amrvac_combine(amrvac_ctx* c, int a, int b, double coef, int out) {
