@@ -15,6 +15,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# the same oracle built with multiply-add contraction: a second roundoff
+# sample for the parity floor, never a reference
+LIB_FMA_PATH = os.path.join(HERE, "liboracle_fma.so")
 NV = 9
 
 
@@ -32,16 +35,22 @@ class Params(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(fma: bool = False):
+    """The oracle library (fma=True: its contracted build, see LIB_FMA_PATH)."""
+    path = LIB_FMA_PATH if fma else LIB_PATH
+    if path not in _libs:
+        if not os.path.exists(path):
             from . import build as _build
             _build.build()
-        _lib = ctypes.CDLL(LIB_PATH)
+        _libs[path] = _setup(ctypes.CDLL(path))
+    return _libs[path]
+
+
+def _setup(_lib):
+    if True:
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         _lib.oracle_create.restype = ctypes.c_void_p
@@ -126,16 +135,17 @@ def make_params(w, nthreads: Optional[int] = None, nstages: Optional[int] = None
 class OracleSim:
     """One oracle simulation; state lives in the C++ library."""
 
-    def __init__(self, w, nthreads: Optional[int] = None, nstages: Optional[int] = None):
+    def __init__(self, w, nthreads: Optional[int] = None, nstages: Optional[int] = None, fma: bool = False):
+        self._lib = lib(fma)
         self.w = w
         self.params = make_params(w, nthreads, nstages)
         self.level = np.ascontiguousarray(w.level, dtype=np.int32)
         self.ijk = np.ascontiguousarray(w.ijk, dtype=np.int32)
         prim = np.ascontiguousarray(w.prim, dtype=np.float64)
-        self.h = lib().oracle_create(ctypes.byref(self.params), len(self.level), _ip(self.level),
+        self.h = self._lib.oracle_create(ctypes.byref(self.params), len(self.level), _ip(self.level),
                                      _ip(self.ijk), _dp(prim))
         if not self.h:
-            raise ValueError("oracle_create: " + lib().oracle_last_error().decode())
+            raise ValueError("oracle_create: " + self._lib.oracle_last_error().decode())
         self.shape = (len(self.level), NV) + (w.nx,) * w.ndim
 
     def regrid(self, level, ijk) -> "OracleSim":
@@ -149,16 +159,17 @@ class OracleSim:
         w = dataclasses.replace(self.w, level=level, ijk=ijk,
                                 prim=np.zeros((len(level), NV) + (self.w.nx,) * self.w.ndim))
         new = OracleSim.__new__(OracleSim)
+        new._lib = self._lib
         new.w, new.params, new.level, new.ijk = w, self.params, level, ijk
-        new.h = lib().oracle_regrid(self.h, len(level), _ip(level), _ip(ijk))
+        new.h = self._lib.oracle_regrid(self.h, len(level), _ip(level), _ip(ijk))
         if not new.h:
-            raise ValueError("oracle_regrid: " + lib().oracle_last_error().decode())
+            raise ValueError("oracle_regrid: " + self._lib.oracle_last_error().decode())
         new.shape = (len(level), NV) + (w.nx,) * w.ndim
         return new
 
     def close(self):
         if self.h:
-            lib().oracle_destroy(self.h)
+            self._lib.oracle_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -167,51 +178,51 @@ class OracleSim:
     def steps(self, n: int, check: bool = True) -> np.ndarray:
         """Advance n SSPRK steps; returns [n, 4] (dt, c_h, kappa, flags)."""
         diag = np.zeros((max(n, 1), 4))
-        rc = lib().oracle_steps(self.h, n, _dp(diag))
+        rc = self._lib.oracle_steps(self.h, n, _dp(diag))
         if rc == -1:
-            raise RuntimeError("oracle: " + lib().oracle_last_error().decode())
+            raise RuntimeError("oracle: " + self._lib.oracle_last_error().decode())
         if rc != 0 and check:
             raise FloatingPointError("oracle: non-physical state or invalid dt (flags=%d)" % self.flags())
         return diag[:n]
 
     def steps_to_time(self, t_end: float, max_steps: int = 1000000) -> int:
-        n = lib().oracle_steps_to_time(self.h, t_end, max_steps)
+        n = self._lib.oracle_steps_to_time(self.h, t_end, max_steps)
         if n == -1:
-            raise RuntimeError("oracle: " + lib().oracle_last_error().decode())
+            raise RuntimeError("oracle: " + self._lib.oracle_last_error().decode())
         if n < 0:
             raise FloatingPointError("oracle: non-physical state or invalid dt (flags=%d)" % self.flags())
         return n
 
     def euler_stage(self, dt: float, ch: float, kappa: float):
-        if lib().oracle_euler_stage(self.h, dt, ch, kappa) != 0:
-            raise RuntimeError("oracle: " + lib().oracle_last_error().decode())
+        if self._lib.oracle_euler_stage(self.h, dt, ch, kappa) != 0:
+            raise RuntimeError("oracle: " + self._lib.oracle_last_error().decode())
 
     def cfl(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        fl = lib().oracle_cfl(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        fl = self._lib.oracle_cfl(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
         return a.value, b.value, c.value, fl
 
     def flags(self) -> int:
-        return lib().oracle_flags(self.h)
+        return self._lib.oracle_flags(self.h)
 
     def fix_count(self) -> int:
-        return lib().oracle_fix_count(self.h)
+        return self._lib.oracle_fix_count(self.h)
 
     def cons(self) -> np.ndarray:
         out = np.empty(self.shape)
-        lib().oracle_get_cons(self.h, _dp(out))
+        self._lib.oracle_get_cons(self.h, _dp(out))
         return out
 
     def set_cons(self, u: np.ndarray):
         u = np.ascontiguousarray(u, dtype=np.float64)
         assert u.shape == self.shape
-        lib().oracle_set_cons(self.h, _dp(u))
+        self._lib.oracle_set_cons(self.h, _dp(u))
 
     def padded(self) -> np.ndarray:
         pn = self.w.nx + 2 * self.w.ng
         out = np.empty((len(self.level), NV) + (pn,) * self.w.ndim)
-        if lib().oracle_fill_padded(self.h, _dp(out)) != 0:
-            raise RuntimeError("oracle: " + lib().oracle_last_error().decode())
+        if self._lib.oracle_fill_padded(self.h, _dp(out)) != 0:
+            raise RuntimeError("oracle: " + self._lib.oracle_last_error().decode())
         return out
 
 
@@ -253,9 +264,10 @@ def lohner_indicator(w, padded: np.ndarray, weights, wavefilter: float = 0.01) -
     return out
 
 
-def run(w, nsteps: Optional[int] = None, nthreads: Optional[int] = None, check: bool = True):
-    """Run a workload for nsteps (default w.nsteps); returns (cons, diag)."""
-    sim = OracleSim(w, nthreads)
+def run(w, nsteps: Optional[int] = None, nthreads: Optional[int] = None, check: bool = True, fma: bool = False):
+    """Run a workload for nsteps (default w.nsteps); returns (cons, diag).
+    fma=True runs the contracted build (a roundoff sample, not a reference)."""
+    sim = OracleSim(w, nthreads, fma=fma)
     try:
         diag = sim.steps(w.nsteps if nsteps is None else nsteps, check=check)
         return sim.cons(), diag

@@ -82,6 +82,10 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libamrvac.so is not built (run __graft_entry__.build() or "
                           "python paper_2303_03026_amd/build.py)")
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    # (one runtime per process; loaded the other way round, two runtimes
+    # would each initialise the device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
     lib.amrvac_slot_bytes.argtypes = [ctypes.POINTER(GridDesc), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]

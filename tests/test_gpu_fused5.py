@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 from paper_2303_03026_amd import inputs
-from test_gpu_parity import assert_parity, rel_l1
+from test_gpu_parity import assert_parity
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -52,19 +53,12 @@ CASES = [("orszag_tang_2d", lambda: inputs.orszag_tang_2d(nsteps=40)),
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("lim,lname", LIMS, ids=[n for _, n in LIMS])
 def test_parity_with_oracle(amr, orc, lim, lname, name, make):
-    """Each variable within the larger of 1e-12 and ten times the oracle's
-    own one-ulp floor (its result from the input raised by one ulp)."""
+    """The FP64 bars of tests/parity.py, with the oracle's roundoff floor."""
     w = weno(make(), lim)
-    ref, _ = orc.run(w)
-    wp = weno(make(), lim)
-    wp.prim = np.nextafter(wp.prim, np.inf)
-    pert, _ = orc.run(wp, nsteps=w.nsteps)
-    floor = rel_l1(w, pert, ref)
+    ref, f1, fi = parity.oracle_floor(orc, lambda: weno(make(), lim))
     gpu, fl = run(amr, w, w.nsteps, "fused")
     assert fl[0] == 0
-    err = assert_parity(w, gpu, ref, tol=np.inf, label="fused5 %s %s" % (lname, name))
-    print("one-ulp floor %s" % " ".join("%.1e" % f for f in floor), flush=True)
-    assert np.all(err <= np.maximum(1e-12, 10.0 * floor)), (err, floor)
+    assert_parity(w, gpu, ref, label="fused5 %s %s" % (lname, name), floor=(f1, fi))
 
 
 @pytest.mark.parametrize("flux", [0, 1, 2], ids=["hll", "hlld", "hllc"])

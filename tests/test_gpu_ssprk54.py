@@ -9,6 +9,7 @@ import pytest
 
 from paper_2303_03026_amd import inputs
 from test_gpu_parity import assert_parity, rel_l1
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -58,14 +59,22 @@ CASES = [("random_modes_3d_48", lambda: inputs.random_modes(48, 3, seed=41, nste
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_parity_with_oracle(amr, orc, name, make, path):
-    w = make()
-    if name == "smooth_amr_3d":
-        w.nsteps = 4
-    w.nstages = 5
-    ref, _ = orc.run(w)
+    def build():
+        w = make()
+        if name == "smooth_amr_3d":
+            w.nsteps = 4
+        w.nstages = 5
+        return w
+    w = build()
+    if name == "current_sheet_32":  # beta = 0.01: measured against the oracle's roundoff floor
+        ref, f1, fi = parity.oracle_floor(orc, build)
+        floor = (f1, fi)
+    else:
+        ref, _ = orc.run(w)
+        floor = None
     gpu, fl = run_gpu(amr, w, w.nsteps, path)
     assert fl[0] == 0
-    assert_parity(w, gpu, ref, label="ssprk54 %s %s" % (name, path))
+    assert_parity(w, gpu, ref, label="ssprk54 %s %s" % (name, path), floor=floor)
 
 
 def test_graph_equals_eager(amr):

@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 from paper_2303_03026_amd import inputs
-from test_gpu_parity import assert_parity, rel_l1
+from test_gpu_parity import assert_parity
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -63,17 +64,6 @@ def perturbed(w, seed=68):
     return w
 
 
-def oracle_floor(orc, w, make):
-    """Relative L1 per variable between the oracle's result and its result
-    from the same input raised by one ulp: how far roundoff alone moves this
-    case."""
-    ref, _ = orc.run(w)
-    wp = make()
-    wp.prim = np.nextafter(wp.prim, np.inf)
-    pert, _ = orc.run(wp, nsteps=w.nsteps)
-    return ref, rel_l1(w, pert, ref)
-
-
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("lim,lname", LIMS, ids=[n for _, n in LIMS])
 def test_parity_with_oracle(amr, orc, lim, lname, name, make):
@@ -86,21 +76,18 @@ def test_parity_with_oracle(amr, orc, lim, lname, name, make):
 
 
 def parity_within_floor(amr, orc, build, label, nslots=None):
-    """GPU against oracle, each variable held to the larger of 1e-12 and ten
-    times the oracle's own one-ulp floor, measured here.  psi grows from the
-    divergence error of the reconstruction, which these fifth-order schemes
-    make small (L1 psi / L1 B ~ 1e-4 on random modes), so roundoff is large
-    relative to psi: its floor reaches 1.2e-12 (mp5, random modes), and 1e-11
-    for the shock cloud's transverse fields and psi; every other variable's
-    floor is about 1e-15."""
+    """The FP64 bars of tests/parity.py with the oracle's roundoff floor,
+    measured here.  psi grows from the divergence error of the
+    reconstruction, which these fifth-order schemes make small (L1 psi / L1
+    B ~ 1e-4 on random modes), so roundoff is large relative to psi: its
+    floor reaches 1.2e-12 (mp5, random modes), and 1e-11 for the shock
+    cloud's transverse fields and psi; every other variable's floor is about
+    1e-15."""
     w = build()
-    ref, floor = oracle_floor(orc, w, build)
+    ref, f1, fi = parity.oracle_floor(orc, build)
     gpu, fl = run_gpu(amr, w, w.nsteps, nslots=nslots)
     assert fl[0] == 0
-    err = assert_parity(w, gpu, ref, tol=np.inf, label=label)
-    tol = np.maximum(1e-12, 10.0 * floor)
-    print("one-ulp floor %s" % " ".join("%.1e" % f for f in floor), flush=True)
-    assert np.all(err <= tol), (err, tol)
+    assert_parity(w, gpu, ref, label=label, floor=(f1, fi))
 
 
 @pytest.mark.parametrize("lim,lname", LIMS, ids=[n for _, n in LIMS])
