@@ -22,47 +22,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mcell-updates/s + HBM GB/s (FP64 vs FP32/batched); p50/p99 job latency"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per stage launch measured with rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch; FETCH scaled by 2.0 and WRITE by 1.0, the
-# factors a plain 1 GiB device copy gives), on the random-mode 256^3 grid,
-# per launch shape (zseg, rotate, xcd): (w == 1, w < 1) pairs of (fetch KiB,
-# write KiB), from `bench.py --sweep-shapes --calib-copy` under
-# `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE`.  They describe the
-# kernel sources whose hash is the key; after any change to those sources the
-# figure is reported as null.
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 VALU instruction
+# per 4 cycles per SIMD (16 lanes; FP64 add/mul/fma at full rate on gfx950)
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4.0
+# Counter figures of the fused stage (rocprofv3 --pmc, per launch shape),
+# committed under profiles/ as a JSON block, with the hash of the kernel
+# sources they were taken from; a source change makes them unusable (null).
+COUNTER_PROFILE = "profiles/stage_fused_counters_by_shape_random_modes_256.md"
 KERNEL_SOURCES = ("paper_2303_03026_amd/csrc/fused.hip", "paper_2303_03026_amd/csrc/device_mhd.h",
-                  "paper_2303_03026_amd/csrc/kernels.h", "paper_2303_03026_amd/csrc/runtime.cpp")
-MEASURED_TRAFFIC = {
-    ("85fbb682025e7cf6", "f64"): {
-        (1, 0, 0): ((2853971, 1180213), (3635124, 1180186)),
-        (1, 0, 1): ((2711750, 1180135), (3556114, 1180210)),
-        (1, 1, 0): ((2860358, 1179945), (3646867, 1180327)),
-        (1, 1, 1): ((2697082, 1180012), (3551265, 1180446)),
-        (2, 0, 0): ((3065565, 1179902), (3855293, 1180110)),
-        (2, 0, 1): ((2943412, 1179929), (3803694, 1180104)),
-        (2, 1, 0): ((3083797, 1179876), (3860799, 1180154)),
-        (2, 1, 1): ((2930331, 1179949), (3782540, 1180241)),
-        (4, 0, 0): ((3509365, 1179740), (4303084, 1179806)),
-        (4, 0, 1): ((3175818, 1179747), (4059770, 1179807)),
-        (4, 1, 0): ((3516348, 1179749), (4305320, 1179841)),
-        (4, 1, 1): ((3151064, 1179784), (4069100, 1179847)),
-    },
-    ("85fbb682025e7cf6", "mixed"): {
-        (1, 0, 0): ((1711248, 819487), (2175041, 819515)),
-        (1, 0, 1): ((1570383, 819447), (2071591, 819548)),
-        (1, 1, 0): ((1706729, 819438), (2170357, 819709)),
-        (1, 1, 1): ((1570718, 819457), (2076652, 819708)),
-        (2, 0, 0): ((1824812, 819363), (2300065, 819474)),
-        (2, 0, 1): ((1702641, 819348), (2214107, 819452)),
-        (2, 1, 0): ((1829813, 819384), (2308121, 819582)),
-        (2, 1, 1): ((1707661, 819384), (2216199, 819553)),
-        (4, 0, 0): ((2095719, 819257), (2557707, 819358)),
-        (4, 0, 1): ((1824226, 819233), (2366593, 819338)),
-        (4, 1, 0): ((2099225, 819257), (2563594, 819378)),
-        (4, 1, 1): ((1822572, 819235), (2365448, 819349)),
-    },
-}
-FETCH_CAL, WRITE_CAL = 2.0, 1.0
+                  "paper_2303_03026_amd/csrc/kernels.h")
 
 
 def kernel_hash():
@@ -74,16 +42,33 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision, tune, workload, n):
-    """Counter bytes per stage launch (mean over one step's three stages),
-    or None when no measurement matches the current kernel and shape."""
+def stage_counters(precision, tune, workload, n):
+    """Counter figures per stage launch of the fused stage for this launch
+    shape, from the committed profile, as (fetch + write HBM bytes, VALU
+    wave-instructions), each the mean over one step's three stages; None
+    when no profile matches the current kernel sources and shape."""
     if workload != "random_modes" or n != 256 or tune is None:
         return None
-    m = MEASURED_TRAFFIC.get((kernel_hash(), precision), {}).get(tuple(tune))
-    if m is None:
+    path = os.path.join(ROOT, COUNTER_PROFILE)
+    try:
+        with open(path) as f:
+            text = f.read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        prof = json.loads(block)
+    except (OSError, IndexError, ValueError):
         return None
-    per = [(f * FETCH_CAL + w * WRITE_CAL) * 1024.0 for f, w in m]
-    return (per[0] + 2 * per[1]) / 3.0
+    if prof.get("kernel_sources_sha16") != kernel_hash():
+        return None
+    rec = prof.get("shapes", {}).get(precision, {}).get("%d,%d,%d" % tuple(tune))
+    if rec is None:
+        return None
+    fc, wc = prof["calibration"]["fetch"], prof["calibration"]["write"]
+    # launches per step: one with w == 1, two with w < 1
+    per = [(r["fetch_kib"] * fc + r["write_kib"] * wc) * 1024.0 for r in (rec["w1"], rec["w_lt1"])]
+    valu = [r["valu_insts"] for r in (rec["w1"], rec["w_lt1"])]
+    return (per[0] + 2 * per[1]) / 3.0, (valu[0] + 2 * valu[1]) / 3.0
+
+
 # Algorithmic HBM bytes per cell for one stage launch: read the input state,
 # write the output state, and read the base state when the stage weight is
 # not 1; one state is 72 B per cell in FP64 and 40 B in FP32-mixed.
@@ -123,6 +108,10 @@ def parse():
     ap.add_argument("--tune", default="auto",
                     help="fused-stage launch shape: 'auto' (autotuner, before the warmup), 'default', or z,r,x")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the other forms (plain FP64, FP32-mixed, current sheet, shock cloud, served)")
+    ap.add_argument("--form-steps", type=int, default=20, help="timed steps of each other form")
+    ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the served form (0: none)")
     ap.add_argument("--no-graph-pass", action="store_true")
     ap.add_argument("--sweep-shapes", action="store_true",
                     help="profiling helper: run one w=1 and one w<1 fused stage per launch shape, in the "
@@ -170,6 +159,137 @@ def cpu_baseline(w, small):
             "cpu_model": cpu_model()}
 
 
+def make_workload(name, n=256, levels=6):
+    from paper_2303_03026_amd import inputs
+    if name == "random_modes":
+        return inputs.random_modes(n, 3, seed=1)
+    if name == "current_sheet":
+        return inputs.current_sheet(n=n if n != 256 else 192)
+    if name == "kelvin_helmholtz":
+        return inputs.kelvin_helmholtz(max_level=levels)
+    if name == "alfven_shock":
+        return inputs.alfven_shock_cloud(max_level=levels)
+    return inputs.shock_cloud_amr()
+
+
+def roofline(avg_ms, bytes_per_launch, counters, kernel):
+    """Roofline of the stage kernel: algorithmic HBM bytes per launch over
+    the live average launch time against the 8 TB/s peak; beside it the
+    counter traffic and the VALU issue fraction from the committed profile
+    for this launch shape (null without one)."""
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic, valu = (None, None) if counters is None else counters
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
+            "traffic_frac": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "valu": None if valu is None else {
+                "wave_insts_per_launch": valu, "peak_wave_insts_per_s": VALU_PEAK_WAVE_INSTS,
+                "frac": valu / (avg_ms * 1e-3) / VALU_PEAK_WAVE_INSTS}}
+
+
+def time_grid(w, path, mixed, steps, warmup, tune_mode="auto", graph_pass=False, keep=False, label=None):
+    """Time `steps` SSPRK(3,3) steps of workload w (inputs in HBM before the
+    timed region): per step the CFL reduction, then per stage a ghost fill
+    and the stage, the last stage folding the next step's CFL rate in where
+    it can.  Every stage launch is bracketed by HIP events on the library's
+    stream.  Returns the form's record (and the simulation with keep)."""
+    import torch
+    from paper_2303_03026_amd import amrvac
+    pth = amrvac.PATH_FUSED if path == "fused" else amrvac.PATH_PLAIN
+    sim = amrvac.Simulation(w, path=pth, precision=amrvac.FP32_MIXED if mixed else amrvac.FP64)
+    state_bytes = 40.0 if mixed else 72.0
+    stream = sim.stream
+    fused2 = pth == amrvac.PATH_FUSED and w.ng == 2
+    tune_times = {}
+    if fused2 and tune_mode != "default":
+        if tune_mode == "auto":
+            print("bench: autotuning the fused stage (%s)" % (label or w.name), file=sys.stderr, flush=True)
+            _, tune_times = sim.autotune(in_slot=0, out_slot=1, reps=3)
+        else:
+            sim.set_tune(*[int(v) for v in tune_mode.split(",")])
+    tune = sim.get_tune() if fused2 else None
+    weights = [(0, 0, 1, 1.0), (1, 0, 2, 0.25), (2, 0, 0, 2.0 / 3.0)]
+
+    def step(events=None):
+        sim.cfl(0)
+        for s, (i, b, o, wt) in enumerate(weights):
+            sim.fill(i)
+            if events is not None:
+                events[s][0].record(stream)
+            sim.stage(i, b, o, wt, cfl=(s == len(weights) - 1))
+            if events is not None:
+                events[s][1].record(stream)
+
+    for _ in range(warmup):
+        step()
+    sim.sync_flags()
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(3)]
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    flags, nfix, last_dt, rc = sim.sync_flags(raise_on_error=False)
+    if rc != 0:
+        print("bench: non-physical state flagged (flags=%d)" % flags, file=sys.stderr)
+        sys.exit(3)
+    cells = w.interior_cells
+    stage_ms = [[evs[k][s][0].elapsed_time(evs[k][s][1]) for k in range(steps)] for s in range(3)]
+    avg_ms = sum(sum(x) for x in stage_ms) / (3 * steps)
+    # per cell: stage 1 reads in and writes out; stages 2 and 3 also read base
+    bytes_per_launch = cells * state_bytes * (2 + 3 + 3) / 3.0
+    counters = (stage_counters("mixed" if mixed else "f64", tune, w.workload_name, w.n_linear)
+                if fused2 and w.limiter == 0 and w.flux == 0 else None)
+    rec = {"workload": label or w.name, "path": path, "precision": "fp32-mixed" if mixed else "fp64",
+           "blocks": int(w.nblocks), "cells": cells, "steps": steps, "warmup": warmup,
+           "ms_per_step": (t1 - t0) * 1e3 / steps, "mcell_updates_per_s": cells * steps / (t1 - t0) / 1e6,
+           "stage_ms": [sum(x) / steps for x in stage_ms],
+           "roofline": roofline(avg_ms, bytes_per_launch, counters, "stage (%s path)" % path),
+           "tune": None if tune is None else {"zseg": tune[0], "rotate": tune[1], "xcd": tune[2]},
+           "autotune_ms_per_launch": {"%d,%d,%d" % k: round(v, 4) for k, v in tune_times.items()}}
+    if graph_pass:
+        sim.advance(2, graph=True)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        sim.advance(steps, graph=True)
+        torch.cuda.synchronize()
+        rec["graph_ms_per_step"] = (time.perf_counter() - g0) * 1e3 / steps
+        sim.sync_flags()
+    if keep:
+        return rec, sim
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return rec
+
+
+def served(njobs, load=0.8, budget_gb=32.0):
+    """A short served stream of the serving mix (2D 32^2..256^2 and 3D
+    32^3..128^3 random-mode jobs, 20..500 steps, half FP32-mixed): all jobs
+    at once (the saturated rate), then Poisson arrivals at `load` times that
+    rate; latency is completion minus arrival."""
+    from paper_2303_03026_amd import inputs, serve
+    jobs = inputs.serving_jobs(njobs, seed=4, rate=1.0)
+    print("bench: serving %d jobs" % njobs, file=sys.stderr, flush=True)
+    eng = serve.ServingEngine(budget_bytes=budget_gb * 1e9)
+    sat = eng.run([dict(j, arrival=0.0) for j in jobs], log_every=5.0)
+    rate_sat = len(jobs) / sat["wall_s"]
+    res = eng.run(jobs, time_scale=1.0 / (load * rate_sat), log_every=5.0)
+    eng.close()
+    for r in (sat, res):
+        r.pop("results", None)
+    return {"workload": "serving mix, %d jobs (seed 4), %d GB pools" % (njobs, budget_gb),
+            "saturated": {"wall_s": sat["wall_s"], "mcell_updates_per_s": sat["mcell_updates_per_s"],
+                          "latency_p50_s": sat["latency_p50_s"], "latency_p99_s": sat["latency_p99_s"]},
+            "load": load,
+            "mcell_updates_per_s": res["mcell_updates_per_s"], "wall_s": res["wall_s"],
+            "latency_p50_s": res["latency_p50_s"], "latency_p99_s": res["latency_p99_s"],
+            "latency_max_s": res["latency_max_s"], "queue_p99_s": res["queue_p99_s"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -177,7 +297,7 @@ def main():
               "(the multi-GPU decomposition is a design note, not code)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2303_03026_amd import amrvac, inputs
+    from paper_2303_03026_amd import amrvac
 
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -188,17 +308,9 @@ def main():
         torch.cuda.synchronize()
         print("bench: calibration copy of %d bytes done" % a.numel(), file=sys.stderr, flush=True)
         del a, bcopy
-    print("bench: generating %d^3 %s input" % (args.n, args.workload), file=sys.stderr, flush=True)
-    if args.workload == "random_modes":
-        w = inputs.random_modes(args.n, 3, seed=1)
-    elif args.workload == "current_sheet":
-        w = inputs.current_sheet(n=args.n)
-    elif args.workload == "kelvin_helmholtz":
-        w = inputs.kelvin_helmholtz(max_level=args.levels)
-    elif args.workload == "alfven_shock":
-        w = inputs.alfven_shock_cloud(max_level=args.levels)
-    else:
-        w = inputs.shock_cloud_amr()
+    print("bench: generating the %s input" % args.workload, file=sys.stderr, flush=True)
+    w = make_workload(args.workload, args.n, args.levels)
+    w.workload_name, w.n_linear = args.workload, args.n
     w.limiter = LIMITERS.index(args.limiter)
     w.flux = {"hll": 0, "hlld": 1, "hllc": 2}[args.flux]
     mixed = args.precision == "mixed"
@@ -211,11 +323,8 @@ def main():
             args.path = "plain"
     if mixed:
         args.path = "fused"
-    path = amrvac.PATH_FUSED if args.path == "fused" else amrvac.PATH_PLAIN
-    sim = amrvac.Simulation(w, path=path, precision=amrvac.FP32_MIXED if mixed else amrvac.FP64)
-    state_bytes = 40.0 if mixed else 72.0
-    stream = sim.stream
     if args.sweep_shapes:
+        sim = amrvac.Simulation(w, path=amrvac.PATH_FUSED, precision=amrvac.FP32_MIXED if mixed else amrvac.FP64)
         order = amrvac.tune_candidates(3)
         sim.cfl(0)
         for shape in order:
@@ -228,70 +337,16 @@ def main():
         sim.close()
         print(json.dumps({"sweep_shapes": order, "launches_per_shape": ["w=1", "w<1"]}), flush=True)
         return
-    tune_times = {}
-    if path == amrvac.PATH_FUSED and w.ng == 2 and args.tune != "default":
-        if args.tune == "auto":
-            print("bench: autotuning the fused stage", file=sys.stderr, flush=True)
-            _, tune_times = sim.autotune(in_slot=0, out_slot=1, reps=3)
-        else:
-            sim.set_tune(*[int(v) for v in args.tune.split(",")])
-    tune = sim.get_tune() if path == amrvac.PATH_FUSED and w.ng == 2 else None
-    weights = [(0, 0, 1, 1.0), (1, 0, 2, 0.25), (2, 0, 0, 2.0 / 3.0)]
-
-    def step(events=None):
-        # the last stage folds the next step's CFL rate in (fused path), so
-        # cfl() is then only the final reduction
-        sim.cfl(0)
-        for s, (i, b, o, wt) in enumerate(weights):
-            sim.fill(i)
-            if events is not None:
-                events[s][0].record(stream)
-            sim.stage(i, b, o, wt, cfl=(s == len(weights) - 1))
-            if events is not None:
-                events[s][1].record(stream)
-
-    print("bench: warmup %d steps (path=%s)" % (args.warmup, args.path), file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    sim.sync_flags()
 
     K = args.steps
-    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(3)]
-           for _ in range(K)]
-    print("bench: timing %d steps" % K, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(K):
-        step(evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    flags, nfix, last_dt, rc = sim.sync_flags(raise_on_error=False)
-    if rc != 0:
-        print("bench: non-physical state flagged (flags=%d)" % flags, file=sys.stderr)
-        sys.exit(3)
-    ms_per_step = (t1 - t0) * 1e3 / K
-    cells = w.interior_cells
-    value = cells * K / (t1 - t0) / 1e6
-
-    # dominant kernel: the stage update (per-launch average over the timed region)
-    stage_ms = [[evs[k][s][0].elapsed_time(evs[k][s][1]) for k in range(K)] for s in range(3)]
-    avg_ms = sum(sum(x) for x in stage_ms) / (3 * K)
-    # per cell: stage 1 reads in, writes out; stages 2 and 3 also read base
-    bytes_per_launch = cells * state_bytes * (2 + 3 + 3) / 3.0
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-
-    traffic = (measured_traffic(args.precision, tune, args.workload, args.n)
-               if args.path == "fused" and args.limiter == "vanleer" and args.flux == "hll" else None)
-
-    graph_ms = None
-    if not args.no_graph_pass:
-        sim.advance(2, graph=True)
-        torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        sim.advance(K, graph=True)
-        torch.cuda.synchronize()
-        graph_ms = (time.perf_counter() - g0) * 1e3 / K
-        sim.sync_flags()
+    print("bench: headline form, %d warmup + %d timed steps (path=%s)" % (args.warmup, K, args.path),
+          file=sys.stderr, flush=True)
+    head, sim = time_grid(w, args.path, mixed, K, args.warmup, args.tune, graph_pass=not args.no_graph_pass,
+                          keep=True, label=args.workload)
+    workload_desc = ("%s: %dD, %d leaf blocks of 16^%d + %d ghost layers on %d level(s), %s GLM-MHD state, "
+                     "SSPRK(3,3), CFL 0.8, %s, %s limiter, %s flux"
+                     % (w.name, w.ndim, w.nblocks, w.ndim, w.ng, w.max_level, args.workload,
+                        "FP32-mixed" if mixed else "FP64", args.limiter, args.flux.upper()))
     regrid = None
     if args.regrid:
         # one regrid of the current state: coarsen every top-level sibling
@@ -360,42 +415,63 @@ def main():
                   "what": "amrvac_lohner on the density, wall time (ghost fill, indicator kernel, copy of one "
                           "double per block to the host, stream sync), best of 5"}
     sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    # the other forms of the same path on the same GPU, each with its own
+    # roofline (default run only: the benchmark's own workload, FP64 fused)
+    forms = None
+    default_run = (args.workload == "random_modes" and args.n == 256 and args.path == "fused" and not mixed
+                   and args.limiter == "vanleer" and args.flux == "hll")
+    if default_run and not args.no_forms:
+        fk = max(5, min(K, args.form_steps))
+        forms = {}
+        print("bench: forms, %d timed steps each" % fk, file=sys.stderr, flush=True)
+        forms["plain_fp64_random_modes_256"] = time_grid(w, "plain", False, max(3, fk // 4), 1,
+                                                          label="random_modes_256")
+        forms["fused_mixed_random_modes_256"] = time_grid(w, "fused", True, fk, args.warmup,
+                                                          label="random_modes_256")
+        for name in ("current_sheet", "shock_cloud"):
+            wf = make_workload(name)
+            wf.workload_name, wf.n_linear = name, 192 if name == "current_sheet" else 128
+            label = "current_sheet_192" if name == "current_sheet" else "shock_cloud_amr_3levels"
+            forms["fused_fp64_" + label] = time_grid(wf, "fused", False, fk, args.warmup, label=label)
+            if name == "current_sheet":
+                forms["fused_mixed_" + label] = time_grid(wf, "fused", True, fk, args.warmup, label=label)
+        if args.serve_jobs > 0:
+            forms["served_mix"] = served(args.serve_jobs)
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["mcell_updates_per_s"],
         "unit": "Mcell-updates/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %dD, %d leaf blocks of 16^%d + %d ghost layers on %d level(s), %s GLM-MHD "
-                               "state, SSPRK(3,3), CFL 0.8, %s, %s limiter, %s flux"
-                               % (w.name, w.ndim, w.nblocks, w.ndim, w.ng, w.max_level, args.workload, "FP32-mixed" if mixed else "FP64",
-                                  args.limiter, args.flux.upper()),
-                   "path": args.path, "cells": cells, "stage_weights": [1.0, 0.25, 2.0 / 3.0],
-                   "tune": None if tune is None else {"zseg": tune[0], "rotate": tune[1], "xcd": tune[2]}},
-        "autotune_ms_per_launch": {"%d,%d,%d" % k: round(v, 4) for k, v in tune_times.items()},
-        "algorithmic_hbm_gbs_per_step": cells * 8 * state_bytes / (ms_per_step * 1e-3) / 1e9,
-        "graph_ms_per_step": graph_ms,
+        "config": {"workload": workload_desc,
+                   "path": args.path, "cells": head["cells"], "stage_weights": [1.0, 0.25, 2.0 / 3.0],
+                   "tune": head["tune"]},
+        "autotune_ms_per_launch": head["autotune_ms_per_launch"],
+        "algorithmic_hbm_gbs_per_step": head["cells"] * 8 * (40.0 if mixed else 72.0)
+        / (head["ms_per_step"] * 1e-3) / 1e9,
+        "graph_ms_per_step": head.get("graph_ms_per_step"),
         "regrid": regrid,
         "lohner": lohner,
         "adaptive": adaptive,
-        "stage_ms": [sum(x) / K for x in stage_ms],
-        "roofline": {"bound": "hbm", "kernel": "stage (%s path)" % args.path, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
-                     # the counter traffic of this launch shape over the live launch time
-                     "traffic_gbs": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
-                     "traffic_frac": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "stage_ms": head["stage_ms"],
+        "roofline": head["roofline"],
+        "forms": forms,
     }
     if not args.no_cpu_baseline:
+        from paper_2303_03026_amd import inputs
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        wc = make_workload(args.workload, args.n, args.levels)
         if args.workload == "random_modes":
             small = inputs.random_modes(64, 3, seed=1)
         elif args.workload == "current_sheet":
@@ -406,8 +482,10 @@ def main():
             small = inputs.alfven_shock_cloud(max_level=3)
         else:
             small = inputs.shock_cloud_amr(base_n=32)
-        small.limiter, small.flux, small.ng = w.limiter, w.flux, w.ng
-        out["cpu_baseline"] = cpu_baseline(w, small)
+        wc.limiter, wc.flux, wc.ng = LIMITERS.index(args.limiter), {"hll": 0, "hlld": 1, "hllc": 2}[args.flux], \
+            (3 if LIMITERS.index(args.limiter) >= 3 else 2)
+        small.limiter, small.flux, small.ng = wc.limiter, wc.flux, wc.ng
+        out["cpu_baseline"] = cpu_baseline(wc, small)
     print(json.dumps(out), flush=True)
 
 

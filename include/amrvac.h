@@ -122,7 +122,10 @@ int amrvac_slot_bytes(const amrvac_grid_desc* g, int nblocks, size_t* bytes);
 /* Bytes before the first block in an FP64 slot (see the layout above). */
 #define AMRVAC_SLOT_LEAD_FP64 16
 
-/* Create a context.  level[nb] (1-based) and ijk[nb][3] (block position on
+/* Create a context on a block-based quadtree (2D) or octree (3D) hierarchy
+ * with refinement ratio 2 (section "Open source strategy with MPI-AMRVAC");
+ * only leaf blocks are advanced, with one time step for all levels.
+ * level[nb] (1-based) and ijk[nb][3] (block position on
  * its level, z ignored in 2D) are HOST arrays describing the leaf blocks;
  * they must tile the domain without overlap and be 2:1 nested across faces,
  * edges and corners, else AMRVAC_E_ARG.  slots[nslots] are device pointers

@@ -3,13 +3,22 @@
 // HLL (or HLLD, HLLC) fluxes in every direction, flux difference, psi damping and the SSPRK
 // combination, in one launch.
 //
-// One 256-thread workgroup per block; thread t owns the (x, y) column
-// i = t % 16, j = t / 16.  In 3D the workgroup marches through the z planes:
-// the z stencil lives in a per-thread register queue (primitives of planes
-// k and k+1, the left face state of the next z face and the previous z
-// flux), while the x and y stencils of the current plane go through LDS:
-// one plane of primitives with its 2-deep x/y halo, plus one buffer that
-// holds first the slopes and then the face fluxes of one direction.
+// One 256-thread workgroup per block (or per z segment of a block); thread t
+// owns the (x, y) column i = t % 16, j = t / 16, so that an x line of the
+// block is one 16-lane row of a wave and a wave holds four lines.  In 3D
+// the workgroup marches through the z planes: the z stencil lives in a
+// per-thread register queue (primitives of plane k+1, the left face state of
+// the next z face and the accumulated flux difference), while the x and y
+// stencils of the current plane read one LDS plane of primitives with its
+// 2-deep x/y halo.  Each face reads its four cells from the plane and forms
+// the limited differences of its two cells itself.  Thread (i, j) evaluates
+// the left x face and the lower y face of its cell; the right x face comes
+// from the next lane of its row (a DPP row shift) and the upper y face from
+// the same lane of the next line of its wave (a wave shuffle), so neither
+// face fluxes nor slopes go through LDS.  Only the faces that leave a wave
+// are exchanged in LDS: the 17th face of every x line and y column (done by
+// two waves per plane) and the y faces of the first line of each wave.  Two
+// workgroup barriers per plane: the plane is complete, the faces are done.
 // Halo cells across faces shared with a same-level leaf are read directly
 // from that neighbour's interior; only faces towards finer or coarser
 // leaves and physical boundaries need filled ghost cells.
@@ -21,10 +30,10 @@ namespace {
 
 constexpr int BN = 16;          // block cells per direction
 constexpr int BP = BN + 4;      // padded extent
-// LDS row strides, one double (or float) longer than the data so that the
-// strided (y-direction and 17th-face) accesses of 16 lanes hit distinct banks
-constexpr int WROW = BP + 1;       // plane of primitives: BP rows of BP cells
-constexpr int SLOPE_ROW = BN + 3;  // slopes: BN lines of cells -1..16
+// LDS row stride of the plane, one value longer than the data so that the
+// strided 17th-face accesses of 16 lanes hit distinct banks
+constexpr int WROW = BP + 1;
+constexpr int PLANE = BP * WROW;  // LDS values per variable of one plane
 
 // Workgroup barrier that orders LDS accesses only.  Every exchange between
 // the threads of a workgroup in this kernel goes through LDS, so global loads
@@ -53,54 +62,49 @@ __device__ __forceinline__ void load_cons(const void* __restrict__ U, long pc, l
   for (int q = 0; q < NV; ++q) u[q] = SP::ld(U, q, c, pc);
 }
 
-// Reconstruct the face between LDS cells (line, f-1) and (line, f) along DIR
-// from the plane primitives and the slope buffer, which holds each cell's
-// right-face difference (van Leer: the slope, the same for both faces; the
-// asymmetric limiters form cell f's left-face difference here, from the
-// cell after it); first-order fallback when rho or p is not positive on
-// either side.
-template <int DIR, int LIM, class R>
-__device__ __forceinline__ void face_states(const R (*__restrict__ Wp)[BP * WROW], const R (*__restrict__ Sl)[SLOPE_ROW * BN], int line, int f,
-                                            R wl[NV], R wr[NV]) {
-  R wm[NV], wp[NV];
+// Interface flux along DIR of the face between the LDS plane cells base + s
+// and base + 2 s, from the four cells base, base + s, base + 2 s, base + 3 s
+// of its line (i-2 .. i+1): both cells' limited differences, the face
+// states, the first-order fallback where rho or p is not positive on either
+// side (the two cells are re-read only in waves where some lane needs
+// them), then the GLM + HLL / HLLD / HLLC flux.
+template <int DIR, int LIM, int FLX, class R>
+__device__ __forceinline__ void lds_face(const R (*__restrict__ Wp)[PLANE], int base, int s,
+                                         R ch, R hic, R gamma, R inv_gm1, R F[NV]) {
+  R wl[NV], wr[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    if (DIR == 0) {
-      wm[q] = Wp[q][(line + 2) * WROW + f + 1];
-      wp[q] = Wp[q][(line + 2) * WROW + f + 2];
-    } else {
-      wm[q] = Wp[q][(f + 1) * WROW + line + 2];
-      wp[q] = Wp[q][(f + 2) * WROW + line + 2];
-    }
-    wl[q] = wm[q] + R(0.5) * Sl[q][line * SLOPE_ROW + f];
-    if (LIM == LIM_VANLEER) {
-      wr[q] = wp[q] - R(0.5) * Sl[q][line * SLOPE_ROW + f + 1];
-    } else {
-      const R wpp = DIR == 0 ? Wp[q][(line + 2) * WROW + f + 3] : Wp[q][(f + 3) * WROW + line + 2];
-      wr[q] = wp[q] - R(0.5) * lim_diff<LIM>(wp[q] - wm[q], wpp - wp[q]);
+    const R a = Wp[q][base], b = Wp[q][base + s], c = Wp[q][base + 2 * s], d = Wp[q][base + 3 * s];
+    R rb, lb, rc, lc;
+    cell_increments<LIM>(b - a, c - b, rb, lb);
+    cell_increments<LIM>(c - b, d - c, rc, lc);
+    wl[q] = b + R(0.5) * rb;
+    wr[q] = c - R(0.5) * lc;
+  }
+  const bool bad = !((wl[I_RHO] > R(0)) && (wl[4] > R(0)) && (wr[I_RHO] > R(0)) && (wr[4] > R(0)));
+  if (__any(bad)) {
+    asm volatile("");  // keeps the branch wave-uniform
+    if (bad) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        wl[q] = Wp[q][base + s];
+        wr[q] = Wp[q][base + 2 * s];
+      }
     }
   }
-  positivity_fallback(wl, wr, wm, wp);
+  face_flux<FLX, DIR, R>(wl, wr, ch, hic, gamma, inv_gm1, F);
 }
 
-// Right-face limited difference along DIR of LDS cell (line, a), a in -1..16
-// (van Leer: the slope)
-template <int DIR, int LIM, class R>
-__device__ __forceinline__ void cell_slope(const R (*__restrict__ Wp)[BP * WROW], R (*__restrict__ Sl)[SLOPE_ROW * BN], int line, int a) {
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    R m, c, p;
-    if (DIR == 0) {
-      m = Wp[q][(line + 2) * WROW + a + 1];
-      c = Wp[q][(line + 2) * WROW + a + 2];
-      p = Wp[q][(line + 2) * WROW + a + 3];
-    } else {
-      m = Wp[q][(a + 1) * WROW + line + 2];
-      c = Wp[q][(a + 2) * WROW + line + 2];
-      p = Wp[q][(a + 3) * WROW + line + 2];
-    }
-    Sl[q][line * SLOPE_ROW + a + 1] = LIM == LIM_VANLEER ? vl_slope(c - m, p - c) : lim_diff<LIM>(p - c, c - m);
-  }
+// The value of the next lane of this lane's 16-lane row (a DPP row shift;
+// the last lane of a row gets 0).
+__device__ __forceinline__ float row_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double row_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x101, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x101, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // Halo cell h (0..127) of a plane's x/y stencil: h < 64 are the x-halo
@@ -128,51 +132,6 @@ struct FaceConst {
   R ch, hic, gamma, inv_gm1;
 };
 
-// One in-plane direction: slopes -> sync -> face fluxes -> sync -> flux
-// difference of this thread's cell added to acc (scaled by 1/dx); the
-// energy difference is accumulated in double (acc_e).
-// The halo slopes (cells -1 and 16 of every line) and the 17th face of every
-// line are done by the lanes of wave xw (extra lane e = t - 64 xw).
-template <int DIR, int LIM, int FLX, class R>
-__device__ __forceinline__ void plane_direction(const R (*__restrict__ Wp)[BP * WROW], R (*__restrict__ Sl)[SLOPE_ROW * BN],
-                                                R (*__restrict__ Fl)[(BN + 1) * BN], int t, int i, int j, int xw,
-                                                const FaceConst<R>& K, double inv_dx, R acc[NV], double& acc_e,
-                                                bool drain_vmem) {
-  const int line = DIR == 0 ? j : i;
-  const int f = DIR == 0 ? i : j;
-  const int e = t - 64 * xw;
-  cell_slope<DIR, LIM>(Wp, Sl, line, f);
-  if ((unsigned)e < 32u) cell_slope<DIR, LIM>(Wp, Sl, e & 15, e < 16 ? -1 : BN);
-  lds_barrier();
-  {
-    R wl[NV], wr[NV], F[NV];
-    face_states<DIR, LIM>(Wp, Sl, line, f, wl, wr);
-    face_flux<FLX, DIR, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, F);
-#pragma unroll
-    for (int q = 0; q < NV; ++q) Fl[q][line * (BN + 1) + f] = F[q];
-  }
-  if ((unsigned)e < 16u) {  // the 17th face of line e
-    R wl[NV], wr[NV], F[NV];
-    face_states<DIR, LIM>(Wp, Sl, e, BN, wl, wr);
-    face_flux<FLX, DIR, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, F);
-#pragma unroll
-    for (int q = 0; q < NV; ++q) Fl[q][e * (BN + 1) + BN] = F[q];
-  }
-  // a wave with direct global->LDS loads in flight completes them before the
-  // barrier that publishes them (vmcnt(0); expcnt and lgkmcnt untouched)
-  if (drain_vmem) __builtin_amdgcn_s_waitcnt(0x0F70);
-  lds_barrier();
-  const R idr = (R)inv_dx;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const R hi = Fl[q][line * (BN + 1) + f + 1], lo = Fl[q][line * (BN + 1) + f];
-    if (q == I_EN)
-      acc_e = acc_e + ((double)hi - (double)lo) * inv_dx;
-    else
-      acc[q] = acc[q] + (hi - lo) * idr;
-  }
-}
-
 // W1: the stage weight is 1 (out = in + dt L(in)), so base is not read.
 // CFL: also fold the CFL rate of every output cell into the job's running
 // maximum (C.rate_bits, C.nan), as the time-step pass would from out.
@@ -186,9 +145,9 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
   using R = typename SP::R;
   using PD = Pad<NDIM>;
   constexpr long PC = PD::cells;
-  __shared__ R Wp[NV][BP * WROW];          // primitives of the current plane (+ x/y halo)
-  __shared__ R Sl[NV][SLOPE_ROW * BN];   // slopes of one direction, cells -1..16 per line
-  __shared__ R Fl[NV][(BN + 1) * BN];    // face fluxes of one direction, faces 0..16 per line
+  __shared__ R Wp[NV][PLANE];    // primitives of the current plane (+ x/y halo)
+  __shared__ R Xf[NV][2 * BN];   // 17th faces: x face 16 of line j at j, y face 16 of column i at 16 + i
+  __shared__ R Bd[3][NV][BN];    // y faces of the first line of waves 1..3 (the next line of waves 0..2)
   // LDS staging of the next plane's 128 halo cells (3D; conserved, storage
   // precision), written by direct global->LDS loads (global_load_lds) of one
   // wave while the current plane is computed, so the halo's memory latency
@@ -397,23 +356,117 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
     double uc[NV];
     if (NDIM == 3) load_z(k + 2, uc);
 
-    // who does this plane's extra work: the halo threads of parity par and
-    // the waves xw / yw for the x / y halo slopes and 17th faces; with
-    // tune.rot the four parts go to four different waves, rotating with the
-    // plane, else to threads 0..127 and wave 0
-    const int rk = k + slot;
-    const int par = parity(k);
-    const int xw = tune.rot ? 2 * (1 - par) + ((rk >> 1) & 1) : 0;
-    const int yw = tune.rot ? (xw ^ 1) : 0;
+    // who does this plane's extra work: the halo cells of the next plane go
+    // to the threads of that plane's parity (waves 0, 1 or 2, 3), the 17th x
+    // faces to wave xw and the 17th y faces to wave yw, the other two waves;
+    // with tune.rot the pairs alternate with the plane
+    const int xw = parity(k + 1) ? 0 : 2, yw = xw + 1;
+    const int wave = t >> 6;
 
     // plane k's primitives (own cells and halo) are complete in LDS, and the
-    // staging buffer has been read
+    // staging buffer and the previous plane's exchanged faces have been read
     lds_barrier();
     const bool staging = stager && k + 1 < k1;
     if (staging) stage_halo(k + 1);
 
-    plane_direction<0, LIM, FLX, R>(Wp, Sl, Fl, t, i, j, xw, K, idx, acc, acc_e, false);
-    plane_direction<1, LIM, FLX, R>(Wp, Sl, Fl, t, i, j, yw, K, idy, acc, acc_e, staging);
+    // the 17th faces: x face 16 of line l (cells 14 .. 17) by lane l of wave
+    // xw, y face 16 of column l by lane l of wave yw
+    {
+      const int l = t & 63;
+      if (wave == xw && l < BN) {
+        R F[NV];
+        lds_face<0, LIM, FLX, R>(Wp, (l + 2) * WROW + BN, 1, K.ch, K.hic, K.gamma, K.inv_gm1, F);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Xf[q][l] = F[q];
+      }
+      if (wave == yw && l < BN) {
+        R F[NV];
+        lds_face<1, LIM, FLX, R>(Wp, BN * WROW + l + 2, WROW, K.ch, K.hic, K.gamma, K.inv_gm1, F);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Xf[q][BN + l] = F[q];
+      }
+    }
+    // x: the left face of this cell (cells i-2 .. i+1 of line j); its right
+    // face is the next lane's left face (lane 15: the 17th face, from LDS).
+    // dX = F(i+1) - F(i) (the energy's in double); lane 15 holds -F(i)
+    // until the barrier, then adds F(16): the same difference, bit for bit.
+    R dX[NV];
+    double dXe;
+    {
+      R F[NV];
+      lds_face<0, LIM, FLX, R>(Wp, (j + 2) * WROW + i, 1, K.ch, K.hic, K.gamma, K.inv_gm1, F);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const R hi = row_next(F[q]);
+        if (q == I_EN)
+          dXe = (double)hi - (double)F[q];
+        else
+          dX[q] = hi - F[q];
+      }
+    }
+    // y: the lower face of this cell (cells j-2 .. j+1 of column i); its
+    // upper face is the lower face of the same lane of the next line of the
+    // wave, or for a wave's last line that of the next wave's first line
+    // (exchanged in LDS) or the 17th face; that line holds -F(j) until the
+    // barrier
+    R dY[NV];
+    double dYe;
+    {
+      R F[NV];
+      lds_face<1, LIM, FLX, R>(Wp, j * WROW + i + 2, WROW, K.ch, K.hic, K.gamma, K.inv_gm1, F);
+      const bool last = (j & 3) == 3;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const R up = __shfl_down(F[q], BN, 64);
+        const R hi = last ? R(0) : up;
+        if (q == I_EN)
+          dYe = (double)hi - (double)F[q];
+        else
+          dY[q] = hi - F[q];
+      }
+      if ((j & 3) == 0 && wave > 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Bd[wave - 1][q][i] = F[q];
+      }
+    }
+    // a wave with direct global->LDS loads in flight completes them before the
+    // barrier that publishes them (vmcnt(0); expcnt and lgkmcnt untouched)
+    if (staging) __builtin_amdgcn_s_waitcnt(0x0F70);
+    // every face of the plane is done and exchanged
+    lds_barrier();
+    if (i == BN - 1) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        if (q == I_EN)
+          dXe = (double)Xf[q][j] + dXe;
+        else
+          dX[q] = Xf[q][j] + dX[q];
+      }
+    }
+    if ((j & 3) == 3) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const R hi = wave < 3 ? Bd[wave][q][i] : Xf[q][BN + i];
+        if (q == I_EN)
+          dYe = (double)hi + dYe;
+        else
+          dY[q] = hi + dY[q];
+      }
+    }
+    // flux differences over dx, x then y (the energy in double)
+    {
+      const R idxr = (R)idx, idyr = (R)idy;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        if (q == I_EN) {
+          acc_e = acc_e + dXe * idx;
+          acc_e = acc_e + dYe * idy;
+        } else {
+          acc[q] = acc[q] + dX[q] * idxr;
+          acc[q] = acc[q] + dY[q] * idyr;
+        }
+      }
+    }
 
     // this plane's conserved state and the stage base, issued as one group
     const long c = PD::at(i, j, k);

@@ -1,31 +1,44 @@
 """FP32-mixed path (FP32 storage and face arithmetic; FP64 energy, pressure
 recovery, small-value fix and CFL) against the FP64 CPU oracle.
 
-There is no bitwise pin for FP32 arithmetic; the bar is a stated bound on a
-normalised L1 error per conserved variable, and the L-infinity error is
-reported beside it.  Normalisation (volume-weighted sums over leaf cells):
-  rho, e:            L1(err) / L1(reference)
-  m_x, m_y, m_z:     L1(err) / L1(sqrt(2 rho e))   (momentum scale)
-  B_x, B_y, B_z, psi: L1(err) / L1(|B|)            (field scale)
-Vector components are normalised by their vector's scale because a single
-component can be near zero everywhere (the current sheet's momentum), where
-a plain relative error measures nothing but the size of that component.
-Bounds: 1e-6 for the random-mode field (50 steps), the 3-level AMR state and
-one step of the full 192^3 sheet; 1e-5 for the 48^3 sheet over 200 steps.
-"""
-import json
-import os
+There is no bitwise pin for FP32 arithmetic; each case states a bound per
+conserved variable on the relative L1 error and on the element-wise relative
+L-inf error (tests/mixed_error.py: plain relative errors, except for a
+variable identically zero at the start, which is measured against the
+magnitude of its vector).  The bounds are about three times the values
+measured on MI355X, rounded up:
 
+  random modes 64^3, 50 steps (the benchmark's field)     L1 5e-7, L-inf 1e-6
+  current sheet 48^3, 200 steps (beta = 0.01)             L1 1e-6, L-inf 1e-5,
+      momentum m_x, m_z 1.5e-3 / 2e-3 and m_y 2e-5 / 2e-5 (measured 5.0e-4,
+      1.1e-4, 4.2e-6): the momentum (|v| ~ 5e-3) is driven by differences of
+      the total pressure 0.505, whose FP32 rounding is 3e-8 at every face
+  current sheet 192^3, 1 step                             L1 1e-7, L-inf 5e-7,
+      momentum 1.5e-5 / 4e-5
+  shock cloud 32^3 base, 3 levels, 100 steps              L1 5e-7, L-inf 2e-6
+  smooth AMR 3D, 4 steps                                  L1 5e-7, L-inf 2e-6,
+      psi 2e-5 / 2e-4 (psi ~ 0.01 |B|: its FP32 error is that of B)
+  Alfven shock-cloud, 3 levels, koren + HLLD, 30 steps   L1 5e-7, L-inf 2e-6
+  Kelvin-Helmholtz, 3 levels, van Leer + HLLC, 30 steps   L1 5e-7, L-inf 3e-6,
+      m_y 3e-4 / 5e-4 (the 1e-3 noise and the growing mode)
+"""
 import numpy as np
 import pytest
 
 from paper_2303_03026_amd import inputs
+import mixed_error
 
 pytestmark = pytest.mark.gpu
 
 NV = 9
-PSI = 8
-NAMES = ["rho", "m_x", "m_y", "m_z", "e", "B_x", "B_y", "B_z", "psi"]
+NAMES = mixed_error.NAMES
+
+
+def per_var(default, **over):
+    b = np.full(NV, float(default))
+    for k, v in over.items():
+        b[NAMES.index(k)] = v
+    return b
 
 
 @pytest.fixture(scope="module")
@@ -39,33 +52,6 @@ def orc():
     from oracle import oracle
     oracle.lib()
     return oracle
-
-
-def errors(w, gpu, ref):
-    v = np.ones(w.nblocks)
-    for d in range(w.ndim):
-        v = v * (w.xmax[d] - w.xmin[d]) / (w.base_blocks[d] * w.nx * 2.0 ** (w.level - 1))
-    vb = v.reshape((-1,) + (1,) * (w.ndim + 1))
-    diff = np.abs(gpu - ref)
-    axes = tuple(i for i in range(gpu.ndim) if i != 1)
-    l1 = np.sum(vb * diff, axis=axes)
-    v3 = vb[:, 0]
-    mscale = np.sum(v3 * np.sqrt(np.maximum(2.0 * ref[:, 0] * ref[:, 4], 0.0)))
-    bscale = np.sum(v3 * np.sqrt(ref[:, 5] ** 2 + ref[:, 6] ** 2 + ref[:, 7] ** 2))
-    scale = np.array([np.sum(vb * np.abs(ref[:, 0:1])), mscale, mscale, mscale,
-                      np.sum(vb * np.abs(ref[:, 4:5])), bscale, bscale, bscale, bscale])
-    rel = l1 / scale
-    linf = np.max(diff.reshape(diff.shape[0], NV, -1).transpose(1, 0, 2).reshape(NV, -1), axis=1)
-    return rel, linf
-
-
-def report(label, rel, linf):
-    rec = {"case": label, "rel_l1": dict(zip(NAMES, map(float, rel))), "linf": dict(zip(NAMES, map(float, linf)))}
-    print(json.dumps(rec), flush=True)
-    out = os.environ.get("AMRVAC_MIXED_REPORT")
-    if out:
-        with open(out, "a") as f:
-            f.write(json.dumps(rec) + "\n")
 
 
 def run_mixed(amr, w, nsteps):
@@ -88,67 +74,51 @@ def test_mixed_uniform_state_bit_identical(amr):
         sim.close()
 
 
+def mixed_case(amr, orc, w, label, b1, bi, nsteps=None):
+    n = w.nsteps if nsteps is None else nsteps
+    ref, _ = orc.run(w, n)
+    gpu, fl = run_mixed(amr, w, n)
+    assert fl[0] == 0
+    l1, linf = mixed_error.errors(w, gpu, ref)
+    mixed_error.check(label, l1, linf, b1, bi)
+
+
 def test_mixed_random_modes(amr, orc):
-    w = inputs.random_modes(64, 3, seed=7, nsteps=50)
-    ref, _ = orc.run(w)
-    gpu, fl = run_mixed(amr, w, w.nsteps)
-    rel, linf = errors(w, gpu, ref)
-    report("random_modes_64_50steps", rel, linf)
-    assert np.all(rel <= 1e-6), rel
+    mixed_case(amr, orc, inputs.random_modes(64, 3, seed=7, nsteps=50), "random_modes_64_x50", 5e-7, 1e-6)
 
 
 def test_mixed_current_sheet(amr, orc):
     """beta = 0.01: the pressure is 1% of the energy; FP64 energy and
     pressure recovery keep FP32 storage usable."""
-    w = inputs.current_sheet(n=48, nsteps=200)
-    ref, _ = orc.run(w)
-    gpu, fl = run_mixed(amr, w, w.nsteps)
-    assert fl[0] == 0
-    rel, linf = errors(w, gpu, ref)
-    report("current_sheet_48_200steps", rel, linf)
-    assert np.all(rel <= 1e-5), rel
+    mixed_case(amr, orc, inputs.current_sheet(n=48, nsteps=200), "current_sheet_48_x200",
+               per_var(1e-6, m_x=1.5e-3, m_y=2e-5, m_z=1.5e-3), per_var(1e-5, m_x=2e-3, m_y=2e-5, m_z=2e-3))
 
 
 def test_mixed_full_current_sheet_one_step(amr, orc):
-    w = inputs.current_sheet(n=192)
-    ref, _ = orc.run(w, 1)
-    gpu, fl = run_mixed(amr, w, 1)
-    rel, linf = errors(w, gpu, ref)
-    report("current_sheet_192_1step", rel, linf)
-    assert np.all(rel <= 1e-6), rel
+    mixed_case(amr, orc, inputs.current_sheet(n=192), "current_sheet_192_x1",
+               per_var(1e-7, m_x=1.5e-5, m_y=1.5e-5, m_z=1.5e-5), per_var(5e-7, m_x=4e-5, m_y=4e-5, m_z=4e-5),
+               nsteps=1)
+
+
+def test_mixed_shock_cloud(amr, orc):
+    mixed_case(amr, orc, inputs.shock_cloud_amr(base_n=32, nsteps=100), "shock_cloud_32_x100", 5e-7, 2e-6)
 
 
 def test_mixed_amr(amr, orc):
-    w = inputs.smooth_amr_state(3, nb1=2, seed=7)
-    ref, _ = orc.run(w, 4)
-    gpu, fl = run_mixed(amr, w, 4)
-    rel, linf = errors(w, gpu, ref)
-    report("smooth_amr_3d_4steps", rel, linf)
-    assert np.all(rel <= 1e-6), rel
+    mixed_case(amr, orc, inputs.smooth_amr_state(3, nb1=2, seed=7), "smooth_amr_3d_x4",
+               per_var(5e-7, psi=2e-5), per_var(2e-6, psi=2e-4), nsteps=4)
 
 
 def test_mixed_alfven_shock_cloud(amr, orc):
     """The paper's MHD shock-cloud test (3 levels, koren + HLLD, 30 steps):
     a strong intermediate shock and a density contrast of 129 in FP32
-    storage.  Bound 1e-6 (measured 3.4e-8, B_y)."""
-    w = inputs.alfven_shock_cloud(max_level=3, flux=1, nsteps=30)
-    ref, _ = orc.run(w)
-    gpu, fl = run_mixed(amr, w, w.nsteps)
-    assert fl[0] == 0
-    rel, linf = errors(w, gpu, ref)
-    report("alfven_shock_cloud_l3_30steps", rel, linf)
-    assert np.all(rel <= 1e-6), rel
+    storage."""
+    mixed_case(amr, orc, inputs.alfven_shock_cloud(max_level=3, flux=1, nsteps=30), "alfven_shock_cloud_l3_x30",
+               5e-7, 2e-6)
 
 
 def test_mixed_kelvin_helmholtz(amr, orc):
     """The shear layer (3 levels, van Leer + HLLC, 30 steps; B = 0, so the
-    field rows of the error are zero).  Bound 1e-6 (measured 1.3e-7, rho)."""
-    w = inputs.kelvin_helmholtz(max_level=3, limiter=0, flux=2, nsteps=30)
-    ref, _ = orc.run(w)
-    gpu, fl = run_mixed(amr, w, w.nsteps)
-    assert fl[0] == 0
-    with np.errstate(invalid="ignore"):
-        rel, linf = errors(w, gpu, ref)
-    rel = np.nan_to_num(rel)  # (0/0 for the field rows)
-    report("kelvin_helmholtz_l3_30steps", rel, linf)
-    assert np.all(rel <= 1e-6), rel
+    field rows are exactly zero on both sides)."""
+    mixed_case(amr, orc, inputs.kelvin_helmholtz(max_level=3, limiter=0, flux=2, nsteps=30),
+               "kelvin_helmholtz_l3_x30", per_var(5e-7, m_y=3e-4), per_var(3e-6, m_y=5e-4))

@@ -1,11 +1,14 @@
 """Batch (serving) contexts: several independent jobs resident in one block
 pool, advanced together with per-job dt; each job's result is the same alone
 and in the mix (bit for bit: no arithmetic couples jobs), and matches the
-CPU oracle."""
+CPU oracle (FP64 jobs to the bars of tests/parity.py, FP32-mixed jobs to
+the bounds of tests/mixed_error.py)."""
 import numpy as np
 import pytest
 
 from paper_2303_03026_amd import inputs
+import mixed_error
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -21,10 +24,6 @@ def orc():
     from oracle import oracle
     oracle.lib()
     return oracle
-
-
-def rel_l1(a, b):
-    return np.array([np.sum(np.abs(a[:, q] - b[:, q])) / max(np.sum(np.abs(b[:, q])), 1e-300) for q in range(9)])
 
 
 def alone(amr, w, nsteps, precision):
@@ -58,10 +57,16 @@ def test_job_alone_equals_in_mix_3d(amr, orc, precision):
     for w, got in zip(ws, outs):
         ref = alone(amr, w, w.nsteps, precision)
         assert np.array_equal(got, ref), w.name
-    if precision == 0:
-        for w, got in zip(ws, outs):
-            ref, _ = orc.run(w)
-            assert np.all(rel_l1(got, ref)[:8] <= 1e-12), w.name
+    for w, got in zip(ws, outs):
+        ref, _ = orc.run(w)
+        if precision == 0:  # the FP64 bars, all nine variables
+            parity.check(w, got, ref, "served %s" % w.name)
+        else:  # the FP32-mixed bounds of these short runs (test_gpu_mixed.py)
+            l1, linf = mixed_error.errors(w, got, ref)
+            b1, bi = np.full(9, 1e-6), np.full(9, 5e-6)
+            if w.name.startswith("smooth_amr"):  # psi ~ 0.01 |B|: its FP32 error is that of B
+                b1[8], bi[8] = 2e-5, 2e-4
+            mixed_error.check("served mixed %s" % w.name, l1, linf, b1, bi)
 
 
 def test_job_alone_equals_in_mix_2d(amr):

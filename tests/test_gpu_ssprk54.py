@@ -8,8 +8,9 @@ import numpy as np
 import pytest
 
 from paper_2303_03026_amd import inputs
-from test_gpu_parity import assert_parity, rel_l1
+from test_gpu_parity import assert_parity
 import parity
+import mixed_error
 
 pytestmark = pytest.mark.gpu
 
@@ -107,9 +108,10 @@ def test_mixed_precision_bound(amr, orc):
     ref, _ = orc.run(w)
     got, fl = run_gpu(amr, w, w.nsteps, "fused", precision=1)
     assert fl[0] == 0
-    err = rel_l1(w, got, ref)
-    # rho and e relative; the small components by the field / momentum scale
-    assert err[0] < 1e-6 and err[4] < 1e-6, err
+    # every variable: relative L1 1e-6 and L-inf 5e-6 (tests/mixed_error.py;
+    # measured on MI355X at most 2.8e-7 and 1.9e-6 on these 10-step runs)
+    l1, linf = mixed_error.errors(w, got, ref)
+    mixed_error.check("mixed %s" % w.name, l1, linf, 1e-6, 5e-6)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
