@@ -95,7 +95,7 @@ def parse():
                          "shock refined to --levels levels (use with --limiter koren and --flux hll/hllc/hlld)")
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--limiter", choices=list(LIMITERS), default="vanleer",
-                    help="weno5 / wenoz5 / mp5 / wenozp5 need 3 ghost layers: FP64 plain path only")
+                    help="weno5 / wenoz5 / mp5 / wenozp5 need 3 ghost layers: FP64 only")
     ap.add_argument("--flux", choices=["hll", "hlld", "hllc"], default="hll")
     ap.add_argument("--regrid", action="store_true",
                     help="also time one regrid (coarsen the top level, refine every eighth block below)")
@@ -315,12 +315,10 @@ def main():
     w.flux = {"hll": 0, "hlld": 1, "hllc": 2}[args.flux]
     mixed = args.precision == "mixed"
     w.ng = 2
-    if w.limiter >= 3:  # the five-cell stencils: 3 ghost layers, FP64 (fused in 2D only)
+    if w.limiter >= 3:  # the five-cell stencils: 3 ghost layers, FP64
         if mixed:
             sys.exit("bench: the fifth-order reconstructions run in FP64 only")
         w.ng = 3
-        if w.ndim == 3:
-            args.path = "plain"
     if mixed:
         args.path = "fused"
     if args.sweep_shapes:

@@ -1,18 +1,26 @@
-// Fused stage kernel for 2D 16^2 blocks with three ghost layers (the
+// Fused stage kernel for 16^ndim blocks with three ghost layers (the
 // five-cell reconstructions 'weno5', 'wenoz5', 'wenozp5' and 'mp5'), FP64:
 // conserved -> primitive, the fifth-order face states, GLM interface + HLL
-// (or HLLD, HLLC) fluxes in both directions, flux difference, psi damping
+// (or HLLD, HLLC) fluxes in every direction, flux difference, psi damping
 // and the SSPRK combination in one launch.
 //
 // One 256-thread workgroup per block; thread t owns cell (i, j) = (t % 16,
-// t / 16).  The block's primitives with a 3-deep x/y halo (22 x 22 cells,
-// corners unused) live in LDS; halo cells across a face shared with a
-// same-level leaf are read in place from that neighbour's interior, the
-// others from this block's ghost cells (filled by the ghost kernels).  Each
-// thread evaluates one x face and one y face; neighbouring face fluxes come
-// by lane shuffles.  The arithmetic is the per-kernel path's step for step (same
-// primitive conversion, face states, flux and update order), so on grids
-// without coarse/fine faces the two paths agree bit for bit.
+// t / 16) of a plane.  A plane's primitives with a 3-deep in-plane halo
+// (22 x 22 cells, corners unused) live in LDS; halo cells across a face
+// shared with a same-level leaf are read in place from that neighbour's
+// interior, the others from this block's ghost cells (filled by the ghost
+// kernels).  Each thread evaluates one face per in-plane direction;
+// neighbouring face fluxes come by lane shuffles.
+//
+// 2D: the block is one x-y plane.  3D: the workgroup first sweeps the 16 x-y
+// planes, leaving each cell's x and y flux differences in a per-block
+// scratch array, then sweeps the 16 x-z planes, where the z faces take the
+// place of the y faces, and updates.  (A z register queue would hold six
+// planes of primitives per thread, more than the register file holds at
+// any useful occupancy.)  The arithmetic is the per-kernel path's step for
+// step (same primitive conversion, face states, flux and the x, y, z order
+// of the flux differences), so on grids without coarse/fine faces the two
+// paths agree bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -29,89 +37,87 @@ constexpr int P5 = BN5 + 2 * NG5;   // LDS cells per row / column
 constexpr int S5 = P5 + 1;          // LDS row stride (odd, against bank conflicts on column reads)
 constexpr int NF5 = BN5 + 1;        // faces per line
 
-// padded 2D cell index in a block of the slot layout
-__device__ __forceinline__ long cell5(const GridConst& G, int x, int y) { return (long)(y + NG5) * G.pn + (x + NG5); }
+// padded cell index in a block of the slot layout
+__device__ __forceinline__ long cell5(const GridConst& G, int x, int y, int z = 0) {
+  return ((long)(G.ndim == 3 ? z + NG5 : 0) * G.pn + (y + NG5)) * G.pn + (x + NG5);
+}
 
-template <bool W1>
-__global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, JobScalars J, const void* __restrict__ in,
+template <int NDIM, bool W1>
+__global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridConst G, Tables T, JobScalars J, const void* __restrict__ in,
                                                          const void* base, void* out, double wgt, PhysConst P,
-                                                         DevStatus* st) {
-  // primitives, cell (x, y) at (y + 3) * S5 + (x + 3); once all faces are
-  // evaluated the same storage carries the y flux differences to the cells'
-  // owners, cell (x, y) at y * NF5 + x
+                                                         DevStatus* st, double* __restrict__ part) {
+  // primitives of a plane, cell (a, c) of its two axes at (c + 3) * S5 + (a + 3);
+  // once all faces of the plane are evaluated the same storage carries the
+  // second axis' flux differences to the cells' owners, cell (a, c) at
+  // c * NF5 + a
   __shared__ double W[NV][P5 * S5];
-  __shared__ double Ex[NV][BN5];  // the 17th x face of each row
-  __shared__ double Ey[NV][BN5];  // the 17th y face of each column
+  __shared__ double Ex[NV][BN5];  // the 17th face of each line along the first axis
+  __shared__ double Ey[NV][BN5];  // the 17th face of each line along the second axis
   const int b = T.order[blockIdx.x];
   const int t = threadIdx.x, i = t & 15, j = t >> 4;
   const long PC = G.pcells;
   const void* own = block_ptr<StoreF64>(in, b, PC);
-  int lk[4], ln[4];
+  int lk[2 * NDIM], ln[2 * NDIM];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
+  for (int f = 0; f < 2 * NDIM; ++f) {
     lk[f] = T.link[((long)b * 6 + f) * LINK_INTS];
     ln[f] = T.link[((long)b * 6 + f) * LINK_INTS + 1];
   }
   int bad = 0;
   unsigned nfix = 0;
-  // conserved state of cell (x, y) of this block, -3 <= x, y < 19 with at
-  // most one coordinate outside 0..15, as primitives into LDS
-  auto fetch = [&](int x, int y) {
+  // conserved state of cell (x, y, z) of this block (at most one coordinate
+  // outside 0..15), as primitives into the plane's LDS cell (a, c); count:
+  // whether a small-value fix is counted here (each cell once per stage)
+  auto fetch = [&](int x, int y, int z, int a, int c, bool count) {
     const void* blk = own;
-    int xs = x, ys = y, f = -1;
+    int xs = x, ys = y, zs = z, f = -1;
     if (x < 0) f = 0;
     else if (x >= BN5) f = 1;
     else if (y < 0) f = 2;
     else if (y >= BN5) f = 3;
+    else if (NDIM == 3 && z < 0) f = 4;
+    else if (NDIM == 3 && z >= BN5) f = 5;
     if (f >= 0 && lk[f] == LINK_SAME) {
       blk = block_ptr<StoreF64>(in, ln[f], PC);
       if (f == 0) xs += BN5;
       else if (f == 1) xs -= BN5;
       else if (f == 2) ys += BN5;
-      else ys -= BN5;
+      else if (f == 3) ys -= BN5;
+      else if (f == 4) zs += BN5;
+      else zs -= BN5;
     }
-    const long c = cell5(G, xs, ys);
+    const long ci = cell5(G, xs, ys, zs);
     double u[NV], w[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) u[q] = StoreF64::ld(blk, q, c, PC);
+    for (int q = 0; q < NV; ++q) u[q] = StoreF64::ld(blk, q, ci, PC);
     const int bb = cons_to_prim(u, w, P);
     if (bb) {
       bad |= bb;
-      if (P.fix) ++nfix;
+      if (P.fix && count) ++nfix;
     }
 #pragma unroll
-    for (int q = 0; q < NV; ++q) W[q][(y + NG5) * S5 + (x + NG5)] = w[q];
+    for (int q = 0; q < NV; ++q) W[q][(c + NG5) * S5 + (a + NG5)] = w[q];
   };
-  fetch(i, j);
-  if (t < 4 * NG5 * BN5) {  // the 192 halo cells: 48 per side, 3 layers of 16
-    const int side = t / (NG5 * BN5), r = t - side * (NG5 * BN5);
-    if (side < 2) {
-      const int y = r / NG5, a = r - y * NG5;
-      fetch(side == 0 ? a - NG5 : BN5 + a, y);
-    } else {
-      const int x = r % BN5, a = r / BN5;
-      fetch(x, side == 2 ? a - NG5 : BN5 + a);
-    }
-  }
-  __syncthreads();
 
   const int job = T.job[b];
   const double ch = J.ch[job];
-  const double idx = T.inv_dx[3 * b], idy = T.inv_dx[3 * b + 1];
+  const double idx = T.inv_dx[3 * b], idy = T.inv_dx[3 * b + 1], idz = T.inv_dx[3 * b + 2];
   const int lim = P.limiter;
   const double lamx = lim == LIM_WENOZP5 ? 1.0 / cbrt(idx * idx) : 0.0;
   const double lamy = lim == LIM_WENOZP5 ? 1.0 / cbrt(idy * idy) : 0.0;
+  const double lamz = (NDIM == 3 && lim == LIM_WENOZP5) ? 1.0 / cbrt(idz * idz) : 0.0;
 
-  // face f of line `line` along DIR (between cells f-1 and f of the line).
-  // The five-cell reconstructions act on one variable at a time, so each
-  // variable's six cells are read from LDS just before use (a few live
-  // registers instead of all 54 values); the arithmetic is that of the
-  // shared six-cell reconstruction.
-  auto face = [&](auto dir, int line, int f, double lambda, double Fq[NV]) {
-    constexpr int DIR = decltype(dir)::value;
+  // face f (between cells f-1 and f) of line `line` along the plane's axis
+  // AX, a face of direction D.  The five-cell reconstructions act on one
+  // variable at a time, so each variable's six cells are read from LDS just
+  // before use (a few live registers instead of all 54 values); the
+  // arithmetic is that of the shared six-cell reconstruction.
+  auto face = [&](auto ax, auto dir, int line, int f, double lambda, double Fq[NV]) {
+    constexpr int AX = decltype(ax)::value;
+    constexpr int D = decltype(dir)::value;
     auto at = [&](int s) {
       const int a = f - NG5 + s;
-      return DIR == 0 ? (line + NG5) * S5 + (a + NG5) : (a + NG5) * S5 + (line + NG5);
+      return AX == 0 ? (line + NG5) * S5 + (a + NG5) : (a + NG5) * S5 + (line + NG5);
     };
     double wl[NV], wr[NV];
     if (lim >= LIM_WENO5) {
@@ -145,68 +151,152 @@ __global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, 
       }
       reconstruct_face(lim, c1, c2, c3, c4, wl, wr);
     }
-    face_flux_rt<DIR, double>(P.flux, wl, wr, ch, 0.5 / ch, P.gamma, P.inv_gm1, Fq);
+    face_flux_rt<D, double>(P.flux, wl, wr, ch, 0.5 / ch, P.gamma, P.inv_gm1, Fq);
   };
-  using X = std::integral_constant<int, 0>;
-  using Y = std::integral_constant<int, 1>;
+  using A0 = std::integral_constant<int, 0>;
+  using A1 = std::integral_constant<int, 1>;
+  using DX = std::integral_constant<int, 0>;
+  using DY = std::integral_constant<int, 1>;
+  using DZ = std::integral_constant<int, 2>;
 
-  // 2 x 16 x 17 faces on 4 waves.  Along x thread t = (i, j) evaluates the
-  // left face of cell (i, j); along y it evaluates the lower face of cell
-  // (j, i) (transposed), so that in both directions the face above a thread's
+  // Flux differences of one plane along its second axis (direction D2) and,
+  // with FIRST, along its first axis (x): 16 x 17 faces per axis on 4 waves.
+  // Along the first axis thread t = (i, j) evaluates the left face of cell
+  // (i, j); along the second it evaluates the lower face of cell (j, i)
+  // (transposed), so that in both directions the next face of a thread's
   // lies in the next lane of the same wave and reaches it by a lane shuffle.
-  // The 17th faces of the rows go to the first wave's lanes 0..15 and those
-  // of the columns to the second wave's, through LDS: no wave takes more
-  // than three face evaluations.
-  double fx[NV], fy[NV];
-  face(X{}, j, i, lamx, fx);
-  face(Y{}, j, i, lamy, fy);
-  if (t < BN5 || (t >= 64 && t < 64 + BN5)) {
-    double fe[NV];
-    if (t < BN5) {
-      face(X{}, t, BN5, lamx, fe);
+  // The 17th faces go to the first wave's lanes 0..15 (first axis) and the
+  // second wave's (second axis), through LDS: no wave takes more than three
+  // face evaluations.  d1 (first axis) and d2 (second axis) are the
+  // differences F(f+1) - F(f) of cell (i, j).
+  auto plane_differences = [&](auto first, auto dir2, double lam2, double d1[NV], double d2[NV]) {
+    constexpr bool FIRST = decltype(first)::value;
+    double f1[NV], f2[NV];
+    if constexpr (FIRST) face(A0{}, DX{}, j, i, lamx, f1);
+    face(A1{}, dir2, j, i, lam2, f2);
+    if ((FIRST && t < BN5) || (t >= 64 && t < 64 + BN5)) {
+      double fe[NV];
+      if (t < BN5) {
+        if constexpr (FIRST) {
+          face(A0{}, DX{}, t, BN5, lamx, fe);
 #pragma unroll
-      for (int q = 0; q < NV; ++q) Ex[q][t] = fe[q];
-    } else {
-      face(Y{}, t - 64, BN5, lamy, fe);
+          for (int q = 0; q < NV; ++q) Ex[q][t] = fe[q];
+        }
+      } else {
+        face(A1{}, dir2, t - 64, BN5, lam2, fe);
 #pragma unroll
-      for (int q = 0; q < NV; ++q) Ey[q][t - 64] = fe[q];
+        for (int q = 0; q < NV; ++q) Ey[q][t - 64] = fe[q];
+      }
     }
-  }
-  __syncthreads();  // every face evaluated: W is free, Ex / Ey written
-  const int up = (t & 63) + 1;
-  double dx[NV];
+    __syncthreads();  // every face evaluated: W is free, Ex / Ey written
+    const int up = (t & 63) + 1;
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const double nx_ = __shfl(fx[q], up, 64), ny_ = __shfl(fy[q], up, 64);
-    dx[q] = (i < BN5 - 1 ? nx_ : Ex[q][j]) - fx[q];
-    // y difference of cell (j, i), handed to the thread that owns it
-    W[q][i * NF5 + j] = (i < BN5 - 1 ? ny_ : Ey[q][j]) - fy[q];
-  }
-  __syncthreads();
-  double L[NV];
+    for (int q = 0; q < NV; ++q) {
+      if constexpr (FIRST) {
+        const double n1 = __shfl(f1[q], up, 64);
+        d1[q] = (i < BN5 - 1 ? n1 : Ex[q][j]) - f1[q];
+      }
+      const double n2 = __shfl(f2[q], up, 64);
+      // second-axis difference of cell (j, i), handed to the thread that owns it
+      W[q][i * NF5 + j] = (i < BN5 - 1 ? n2 : Ey[q][j]) - f2[q];
+    }
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    L[q] = 0.0;
-    L[q] = L[q] + dx[q] * idx;
-    L[q] = L[q] + W[q][j * NF5 + i] * idy;
-  }
+    for (int q = 0; q < NV; ++q) d2[q] = W[q][j * NF5 + i];
+  };
+  using Yes = std::integral_constant<bool, true>;
+  using No = std::integral_constant<bool, false>;
 
-  // update: L = -(sum_d dF_d / dx_d) - kappa psi; SSPRK combination
-  const long c = cell5(G, i, j);
+  // update of cell (x, y, z): L = -(sum_d dF_d / dx_d) - kappa psi; SSPRK combination
   const double dt = J.dt_scale * J.dt[job], kappa = J.kappa[job];
-  const double psi = StoreF64::ld(own, I_PSI, c, PC);
   void* o = block_ptr<StoreF64>(out, b, PC);
   const void* bs = block_ptr<StoreF64>(base, b, PC);
+  auto update = [&](int x, int y, int z, const double L[NV]) {
+    const long c = cell5(G, x, y, z);
+    const double psi = StoreF64::ld(own, I_PSI, c, PC);
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    double lq = -L[q];
-    if (q == I_PSI) lq = lq - kappa * psi;
-    const double tq = StoreF64::ld(own, q, c, PC) + dt * lq;
-    if (W1) {
-      StoreF64::st(o, q, c, PC, tq);
-    } else {
-      const double u0 = StoreF64::ld(bs, q, c, PC);
-      StoreF64::st(o, q, c, PC, u0 + wgt * (tq - u0));
+    for (int q = 0; q < NV; ++q) {
+      double lq = -L[q];
+      if (q == I_PSI) lq = lq - kappa * psi;
+      const double tq = StoreF64::ld(own, q, c, PC) + dt * lq;
+      if (W1) {
+        StoreF64::st(o, q, c, PC, tq);
+      } else {
+        const double u0 = StoreF64::ld(bs, q, c, PC);
+        StoreF64::st(o, q, c, PC, u0 + wgt * (tq - u0));
+      }
+    }
+  };
+  // the 192 in-plane halo cells of an x-y plane z: 48 per side, 3 layers of 16
+  auto fetch_xy_halo = [&](int z, bool count) {
+    if (t < 4 * NG5 * BN5) {
+      const int side = t / (NG5 * BN5), r = t - side * (NG5 * BN5);
+      if (side < 2) {
+        const int y = r / NG5, a = r - y * NG5;
+        const int x = side == 0 ? a - NG5 : BN5 + a;
+        fetch(x, y, z, x, y, count);
+      } else {
+        const int x = r % BN5, a = r / BN5;
+        const int y = side == 2 ? a - NG5 : BN5 + a;
+        fetch(x, y, z, x, y, count);
+      }
+    }
+  };
+
+  if constexpr (NDIM == 2) {
+    fetch(i, j, 0, i, j, true);
+    fetch_xy_halo(0, true);
+    __syncthreads();
+    double d1[NV], d2[NV], L[NV];
+    plane_differences(Yes{}, DY{}, lamy, d1, d2);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      L[q] = 0.0;
+      L[q] = L[q] + d1[q] * idx;
+      L[q] = L[q] + d2[q] * idy;
+    }
+    update(i, j, 0, L);
+  } else {
+    // x-y planes: x and y differences of every cell into the scratch array
+    // part[block][var][cell] (interior cells, x fastest)
+    double* pb = part + (long)b * NV * (BN5 * BN5 * BN5);
+    for (int k = 0; k < BN5; ++k) {
+      fetch(i, j, k, i, j, true);
+      fetch_xy_halo(k, false);
+      __syncthreads();
+      double d1[NV], d2[NV];
+      plane_differences(Yes{}, DY{}, lamy, d1, d2);
+      const int ci = (k * BN5 + j) * BN5 + i;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        double L = 0.0;
+        L = L + d1[q] * idx;
+        L = L + d2[q] * idy;
+        pb[q * (BN5 * BN5 * BN5) + ci] = L;
+      }
+      __syncthreads();  // the plane's LDS is read before the next plane loads
+    }
+    // x-z planes: the z faces (the plane's second axis), then the update;
+    // thread (i, j) of plane y owns cell (i, y, j)
+    for (int y = 0; y < BN5; ++y) {
+      fetch(i, y, j, i, j, false);
+      if (t < 2 * NG5 * BN5) {  // the 96 z-halo cells: 3 layers of 16 below and above
+        const int side = t / (NG5 * BN5), r = t - side * (NG5 * BN5);
+        const int x = r % BN5, a = r / BN5;
+        const int z = side == 0 ? a - NG5 : BN5 + a;
+        fetch(x, y, z, x, z, false);
+      }
+      __syncthreads();
+      double d1[NV], d2[NV], L[NV];
+      plane_differences(No{}, DZ{}, lamz, d1, d2);
+      const int ci = (j * BN5 + y) * BN5 + i;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        L[q] = pb[q * (BN5 * BN5 * BN5) + ci];
+        L[q] = L[q] + d2[q] * idz;
+      }
+      update(i, y, j, L);
+      __syncthreads();
     }
   }
   if (bad) atomicOr(&st->flags, (unsigned)bad);
@@ -216,13 +306,22 @@ __global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, 
 }  // namespace
 
 hipError_t launch_fused5_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J, const void* in,
-                               const void* base, void* out, double w, const PhysConst& P, DevStatus* st) {
-  if (G.ndim != 2 || G.nx != BN5 || G.ng != NG5 || G.precision != 0) return hipErrorInvalidValue;
+                               const void* base, void* out, double w, const PhysConst& P, DevStatus* st,
+                               double* part) {
+  if (G.nx != BN5 || G.ng != NG5 || G.precision != 0) return hipErrorInvalidValue;
+  if (G.ndim == 3 && !part) return hipErrorInvalidValue;
   if (T.nactive <= 0) return hipSuccess;
-  if (w == 1.0)
-    k_stage_fused5<true><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st);
-  else
-    k_stage_fused5<false><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st);
+  if (G.ndim == 3) {
+    if (w == 1.0)
+      k_stage_fused5<3, true><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, part);
+    else
+      k_stage_fused5<3, false><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, part);
+  } else {
+    if (w == 1.0)
+      k_stage_fused5<2, true><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, nullptr);
+    else
+      k_stage_fused5<2, false><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, nullptr);
+  }
   return hipGetLastError();
 }
 

@@ -100,10 +100,12 @@ struct FusedTune {
 };
 // cfl (may be null): also fold each job's CFL rate of the output interior
 // into cfl->rate_bits / cfl->nan (as launch_cfl_accumulate would from out).
-// The fused stage of 2D blocks with three ghost layers (the five-cell
-// reconstructions), FP64; no CFL folding.
+// The fused stage of blocks with three ghost layers (the five-cell
+// reconstructions), FP64; no CFL folding.  part: 3D only, nb x NV x nx^3
+// doubles of scratch for the in-plane flux differences.
 hipError_t launch_fused5_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J, const void* in,
-                               const void* base, void* out, double w, const PhysConst& P, DevStatus* st);
+                               const void* base, void* out, double w, const PhysConst& P, DevStatus* st,
+                               double* part);
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                               const FusedTune& tune, const void* in, const void* base, void* out, double w,
                               const PhysConst& P, DevStatus* st, const JobCfl* cfl);

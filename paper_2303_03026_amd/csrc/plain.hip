@@ -464,7 +464,7 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
 // the update.  In 3D (NS = 1) one lane evaluates all five faces: there the
 // tasks are many and the four-cell faces cheap, and idle lanes of eight-lane
 // groups cost more than the latency saved.
-template <int D, class SP, int NS, int NFINE>
+template <int D, class SP, int NS, int NFINE, bool SIX>
 __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, JobScalars J,
                                                        const int* __restrict__ tasks, int ntasks,
                                                        const void* __restrict__ in, void* out, double w,
@@ -496,18 +496,18 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, J
     const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
     const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
     const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
-    face_flux_from_slot<D, SP, NFINE == 2>(G, block_ptr<SP>(in, fb, pc), side ? 0 : nx, g1 - o1 * nx,
+    face_flux_from_slot<D, SP, SIX>(G, block_ptr<SP>(in, fb, pc), side ? 0 : nx, g1 - o1 * nx,
                                G.ndim == 3 ? g2 - o2 * nx : 0, ch, hic, P, T.inv_dx, fb, Fo);
   };
   R F[NV], v[NFINE][NV];
   if constexpr (NS == 1) {
-    face_flux_from_slot<D, SP, NFINE == 2>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, T.inv_dx, b, F);
+    face_flux_from_slot<D, SP, SIX>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, T.inv_dx, b, F);
     // (unrolled: a run-time index into v would place it in scratch memory)
 #pragma unroll
     for (int k = 0; k < NFINE; ++k) fine_face(k, v[k]);
   } else {
     if (sub == 0) {
-      face_flux_from_slot<D, SP, NFINE == 2>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, T.inv_dx, b, F);
+      face_flux_from_slot<D, SP, SIX>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, T.inv_dx, b, F);
     } else if (sub <= NFINE) {
       fine_face(sub - 1, F);
     } else {
@@ -931,11 +931,14 @@ hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables
   const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
 #define AMRVAC_REFLUX_LAUNCH(D, SPT)                                                                       \
   if (count[D] > 0) {                                                                                     \
-    if (G.ndim == 3)                                                                                      \
-      k_reflux_correct<D, SPT, 1, 4><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(                    \
+    if (G.ndim == 3 && G.ng == 3)                                                                         \
+      k_reflux_correct<D, SPT, 1, 4, true><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(              \
+          G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
+    else if (G.ndim == 3)                                                                                 \
+      k_reflux_correct<D, SPT, 1, 4, false><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(             \
           G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
     else                                                                                                  \
-      k_reflux_correct<D, SPT, 4, 2><<<nblocks_for(count[D] * per * 4, 256), 256, 0, s>>>(                \
+      k_reflux_correct<D, SPT, 4, 2, true><<<nblocks_for(count[D] * per * 4, 256), 256, 0, s>>>(          \
           G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
   }
   if (G.precision == 0) {

@@ -468,6 +468,9 @@ struct amrvac_ctx {
   double* d_jkappa = nullptr;
   // plain-path scratch (single-job FP64 contexts)
   double* d_prim = nullptr;
+  // fused five-cell path in 3D: each cell's x and y flux differences between
+  // the stage kernel's two sweeps (single-job FP64 contexts, first use)
+  double* d_part = nullptr;
   double* d_flux[3] = {nullptr, nullptr, nullptr};
   DevStatus* d_status = nullptr;
   // graph of one step (single-job amrvac_advance)
@@ -513,7 +516,8 @@ void free_all(amrvac_ctx* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   void* ptrs[] = {c->d_level, c->d_job,   c->d_link,  c->d_pos,   c->d_wrap,    c->d_invdx,   c->d_order, c->d_tfill,
                   c->d_tfused, c->d_tprol, c->d_trefl, c->d_geom,  c->d_rate,    c->d_nan,     c->d_jdt,   c->d_jch,
-                  c->d_jkappa, c->d_prim,  c->d_flux[0], c->d_flux[1], c->d_flux[2], c->d_status};
+                  c->d_jkappa, c->d_prim,  c->d_flux[0], c->d_flux[1], c->d_flux[2], c->d_status,
+                  c->d_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < amrvac_ctx::kStaging; ++k) {
@@ -821,7 +825,7 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
     }
     if (c->G.ng == 3)
       HIP_TRY(c, launch_fused5_stage(c->stream, c->G, T, J, c->slots[in], c->slots[base], c->slots[out], w, c->P,
-                                     c->d_status));
+                                     c->d_status, c->d_part));
     else
       HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->tune, c->slots[in], c->slots[base], c->slots[out], w,
                                     c->P, c->d_status, fold ? &C : nullptr));
@@ -900,11 +904,15 @@ int enqueue_step(amrvac_ctx* c, int nstages, double* dt, double* ch, double* kap
 
 int slots_for_stages(int nstages) { return nstages >= 5 ? 4 : (nstages >= 3 ? 3 : 2); }
 
-// The plain (per-kernel) FP64 path's primitive and face-flux scratch,
-// allocated on its first use: a context that only runs the fused path never
-// holds it (for 4096 blocks of 16^3 it is 6 GB).  Called by the entry points
+// The plain (per-kernel) FP64 path's primitive and face-flux scratch, and
+// the 3D five-cell fused stage's array of in-plane flux differences,
+// allocated on first use of their path: a context that only runs the fused
+// path of two ghost layers holds neither (the plain scratch for 4096 blocks
+// of 16^3 is 6 GB, the difference array 1.2 GB).  Called by the entry points
 // before they enqueue work, so never inside a graph capture.
 int ensure_plain_scratch(amrvac_ctx* c) {
+  if (c->path == AMRVAC_PATH_FUSED && c->G.ng == 3 && c->G.ndim == 3 && !c->d_part)
+    return dev_alloc(c, (void**)&c->d_part, (size_t)c->cap * NV * c->G.icells * sizeof(double));
   if (c->path != AMRVAC_PATH_PLAIN || c->d_prim) return AMRVAC_OK;
   const size_t nb = (size_t)c->cap;
   const size_t pcs = nb * NV * c->G.pcells * sizeof(double);
@@ -1384,8 +1392,8 @@ int amrvac_set_path(amrvac_ctx* c, int path) {
   if (!c) return AMRVAC_E_ARG;
   if (path != AMRVAC_PATH_PLAIN && path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_ARG, "unknown path");
   if (path == AMRVAC_PATH_FUSED && c->G.nx != 16) return fail(c, AMRVAC_E_ARG, "the fused path needs block_nx = 16");
-  if (path == AMRVAC_PATH_FUSED && c->G.ng != 2 && !(c->G.ng == 3 && c->G.ndim == 2 && c->g.precision == AMRVAC_FP64))
-    return fail(c, AMRVAC_E_ARG, "the fused path needs nghost = 2 (3 only for 2D FP64 grids)");
+  if (path == AMRVAC_PATH_FUSED && c->G.ng != 2 && !(c->G.ng == 3 && c->g.precision == AMRVAC_FP64 && !c->batch))
+    return fail(c, AMRVAC_E_ARG, "the fused path needs nghost = 2 (3 only for FP64 single-job grids)");
   if (path == AMRVAC_PATH_PLAIN && (c->g.precision != AMRVAC_FP64 || c->batch))
     return fail(c, AMRVAC_E_ARG, "the plain path is for single-job FP64 contexts");
   c->path = path;

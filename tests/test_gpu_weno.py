@@ -132,8 +132,6 @@ def test_three_ghost_layers_change_nothing_for_van_leer(amr):
 def test_two_layer_paths_refuse_three_ghost_layers(amr):
     w = weno(inputs.random_modes(32, 3, seed=67), 3)
     with pytest.raises(amr.AmrvacError):
-        amr.Simulation(w, path=amr.PATH_FUSED)
-    with pytest.raises(amr.AmrvacError):
         amr.Simulation(w, path=amr.PATH_PLAIN, precision=amr.FP32_MIXED)
     with pytest.raises(amr.AmrvacError):
         amr.Batch(w, capacity_blocks=16, max_jobs=2, nstages=3)
