@@ -3,12 +3,19 @@
 Jobs (a grid, an initial state, a step count and a precision) arrive over
 time.  The engine keeps one batch context per (dimension, precision) class,
 each with a block pool carved from a fixed HBM budget; a job is admitted when
-its class's pool has a contiguous free run for its blocks (first come, first
-served within a class), stays resident on the device, and is advanced
+its class's pool has a contiguous free run for its blocks, stays resident on
+the device, and is advanced
 together with every other resident job of its class by one SSPRK step per
 round.  The four classes run on their own streams, so their rounds overlap
 on the device.  A job leaves as soon as its last step is done; the places it
 frees are reused by the next admission.
+
+Admission within a class is first come, first served with backfill: when the
+oldest waiting job does not fit, later jobs of the class that do fit (among
+the next `backfill_window` whose initial states are ready) are admitted
+ahead of it, until the oldest has waited `max_head_wait_s`; from then on
+nothing passes it, so every job is admitted within that wait plus the time
+for one run of its size to free up.
 
 Reported per run: per-job latency (completion minus arrival; p50, p99, max),
 queueing delay, and the aggregate Mcell-updates/s of all jobs.
@@ -39,9 +46,12 @@ class ServingEngine:
     CLASSES = [(2, False), (2, True), (3, False), (3, True)]
 
     def __init__(self, budget_bytes: float = 32e9, shares=(0.05, 0.05, 0.6, 0.3), max_jobs: int = 1024,
-                 device: str = "cuda", prefetch_workers: int = 8, autotune: bool = True):
+                 device: str = "cuda", prefetch_workers: int = 8, autotune: bool = True,
+                 max_head_wait_s: float = 0.25, backfill_window: int = 32):
         import torch
         self.torch = torch
+        self.max_head_wait_s = max_head_wait_s
+        self.backfill_window = backfill_window
         self.device = device
         self.pools: Dict[tuple, amrvac.Batch] = {}
         self.capacity = {}
@@ -96,7 +106,7 @@ class ServingEngine:
         for i in order[:ahead]:
             futures[i] = self.pool_exec.submit(prepare, jobs[i])
         next_prefetch = ahead
-        queues = {cls: collections.deque() for cls in self.CLASSES}
+        queues = {cls: [] for cls in self.CLASSES}
         resident = {cls: {} for cls in self.CLASSES}  # job id in pool -> job index
         # steps left per resident job, kept here in step with the pool (every
         # round advances each resident job with steps left by one step)
@@ -122,17 +132,26 @@ class ServingEngine:
                     j = order[next_prefetch]
                     futures[j] = self.pool_exec.submit(prepare, jobs[j])
                     next_prefetch += 1
-            # admissions: first come, first served within each class
+            # admissions: oldest first within each class, with backfill
+            # while the oldest waiting job has waited less than the bound
             for cls in self.CLASSES:
                 q = queues[cls]
                 pool = self.pools[cls]
-                while q:
-                    i = q[0]
+                k = 0
+                while k < len(q) and k < self.backfill_window:
+                    i = q[k]
+                    if k > 0 and not futures[i].done():
+                        k += 1
+                        continue
                     w = futures[i].result()
                     jid = pool.add_job(w)
                     if jid is None:
-                        break
-                    q.popleft()
+                        head_wait = time.perf_counter() - t0 - rec[q[0]]["arrival"]
+                        if head_wait >= self.max_head_wait_s:
+                            break
+                        k += 1
+                        continue
+                    del q[k]
                     resident[cls][jid] = i
                     left[cls][jid] = int(w.nsteps)
                     rec[i]["admitted"] = time.perf_counter() - t0
