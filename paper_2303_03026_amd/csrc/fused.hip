@@ -138,10 +138,11 @@ struct FaceConst {
 // Work item w (one z segment of one block) is run by workgroup g with
 // w = (g % 8) * per_xcd + g / 8 when tune.xcd is set (each XCD gets a
 // contiguous run of the Morton-ordered list), else w = g.
-template <int NDIM, class SP, bool W1, bool CFL, int LIM, int FLX>
+template <int NDIM, class SP, bool W1, bool CFL, int LIM, int FLX, bool REG>
 __global__ void __launch_bounds__(256, SP::kWavesPerEU)
 k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, const void* __restrict__ in,
-              const void* base, void* out, double wgt, PhysConst P, DevStatus* st, JobCfl C) {
+              const void* base, void* out, double wgt, PhysConst P, DevStatus* st, JobCfl C,
+              typename SP::R* __restrict__ freg) {
   using R = typename SP::R;
   using PD = Pad<NDIM>;
   constexpr long PC = PD::cells;
@@ -189,6 +190,34 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
   };
   const int sb0 = face_src(0), sb1 = face_src(1), sb2 = face_src(2), sb3 = face_src(3);
   const int sh0 = face_shift(0), sh1 = face_shift(1), sh2 = face_shift(2), sh3 = face_shift(3);
+  // Flux registers of the faces towards finer or coarser leaves (freg is
+  // null when no coarse/fine correction follows): the face fluxes evaluated
+  // there are stored for the correction pass, [face][var][face cell] of this
+  // block; bit f of regs marks face f.  With CFL and C.skip_fine the cells
+  // next to faces towards finer leaves (bit f of skips) are left to the pass
+  // after that correction.
+  constexpr int NFC = NDIM == 3 ? BN * BN : BN;
+  // (REG: the instantiation for grids with coarse/fine correction; freg is
+  // then not null)
+  unsigned regs = 0, skips = 0;
+  if constexpr (REG) {
+#pragma unroll
+    for (int f = 0; f < 2 * NDIM; ++f) {
+      const int kd = T.link[((long)b * 6 + f) * LINK_INTS];
+      if (kd == LINK_FINE || kd == LINK_COARSE) regs |= 1u << f;
+      if (CFL && C.skip_fine && kd == LINK_FINE) skips |= 1u << f;
+    }
+  }
+  R* const rgb = freg + (long)b * 6 * NV * NFC;
+  // store the NV fluxes of one face cell; the address is formed here (the
+  // empty asm keeps the compiler from hoisting nine addresses per face out
+  // of the plane loop, which would cost registers the stage does not have)
+  auto put_reg = [&](int f, int cell, const R Fv[NV]) {
+    R* p = rgb + f * NV * NFC + cell;
+    asm volatile("" : "+v"(p));
+#pragma unroll
+    for (int q = 0; q < NV; ++q) p[q * NFC] = Fv[q];
+  };
   const int job = T.job[b];
   const double dt = J.dt_scale * J.dt[job], kappa = J.kappa[job], chd = J.ch[job];
   const FaceConst<R> K{(R)chd, (R)(0.5 / chd), (R)P.gamma, (R)P.inv_gm1};
@@ -325,6 +354,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
       }
       positivity_fallback(wl, wr, wm1, wa);
       face_flux<FLX, 2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
+      if ((regs & 16u) && k0 == 0) put_reg(4, j * BN + i, fz);
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
         if (q == I_EN) {
@@ -362,6 +392,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
     // with tune.rot the pairs alternate with the plane
     const int xw = parity(k + 1) ? 0 : 2, yw = xw + 1;
     const int wave = t >> 6;
+    const int kofs = NDIM == 3 ? k * BN : 0;  // register cells of this plane's x and y faces
 
     // plane k's primitives (own cells and halo) are complete in LDS, and the
     // staging buffer and the previous plane's exchanged faces have been read
@@ -378,12 +409,14 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
         lds_face<0, LIM, FLX, R>(Wp, (l + 2) * WROW + BN, 1, K.ch, K.hic, K.gamma, K.inv_gm1, F);
 #pragma unroll
         for (int q = 0; q < NV; ++q) Xf[q][l] = F[q];
+        if (regs & 2u) put_reg(1, kofs + l, F);
       }
       if (wave == yw && l < BN) {
         R F[NV];
         lds_face<1, LIM, FLX, R>(Wp, BN * WROW + l + 2, WROW, K.ch, K.hic, K.gamma, K.inv_gm1, F);
 #pragma unroll
         for (int q = 0; q < NV; ++q) Xf[q][BN + l] = F[q];
+        if (regs & 8u) put_reg(3, kofs + l, F);
       }
     }
     // x: the left face of this cell (cells i-2 .. i+1 of line j); its right
@@ -395,6 +428,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
     {
       R F[NV];
       lds_face<0, LIM, FLX, R>(Wp, (j + 2) * WROW + i, 1, K.ch, K.hic, K.gamma, K.inv_gm1, F);
+      if ((regs & 1u) && i == 0) put_reg(0, kofs + j, F);
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
         const R hi = row_next(F[q]);
@@ -414,6 +448,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
     {
       R F[NV];
       lds_face<1, LIM, FLX, R>(Wp, j * WROW + i + 2, WROW, K.ch, K.hic, K.gamma, K.inv_gm1, F);
+      if ((regs & 4u) && j == 0) put_reg(2, kofs + i, F);
       const bool last = (j & 3) == 3;
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
@@ -492,6 +527,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
       }
       positivity_fallback(wl, wr, wa, wb);
       face_flux<FLX, 2, R>(wl, wr, K.ch, K.hic, K.gamma, K.inv_gm1, fz);
+      if ((regs & 32u) && k == BN - 1) put_reg(5, j * BN + i, fz);
       // fz becomes F_z(k+1/2)/dz (the energy term in double, in fze); it is
       // added here and its negative seeds the next plane's accumulator
 #pragma unroll
@@ -537,7 +573,11 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
       SP::st(o, q, c, PC, res);
       if (CFL) un[q] = SP::as_stored(q, res);
     }
-    if (CFL) {
+    // (bit f of the cell's faces: the block faces it touches)
+    const unsigned cell_faces = (i == 0 ? 1u : 0u) | (i == BN - 1 ? 2u : 0u) | (j == 0 ? 4u : 0u) |
+                                (j == BN - 1 ? 8u : 0u) | (NDIM == 3 && k == 0 ? 16u : 0u) |
+                                (NDIM == 3 && k == BN - 1 ? 32u : 0u);
+    if (CFL && !(cell_faces & skips)) {
       const double rate = cell_rate<NDIM>(un, P, idx, idy, idz, bad);
       if (isnan(rate))
         rnan = 1;
@@ -593,7 +633,7 @@ k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, 
 
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                               const FusedTune& tune, const void* in, const void* base, void* out, double w,
-                              const PhysConst& P, DevStatus* st, const JobCfl* cfl) {
+                              const PhysConst& P, DevStatus* st, const JobCfl* cfl, void* freg) {
   if (G.nx != BN || G.ng != 2) return hipErrorInvalidValue;
   if (tune.zseg != 1 && tune.zseg != 2 && tune.zseg != 4) return hipErrorInvalidValue;
   if (T.nactive <= 0) return hipSuccess;
@@ -601,8 +641,15 @@ hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T
   const int per_xcd = (int)((items + 7) / 8);
   const unsigned grid = tune.xcd ? 8u * (unsigned)per_xcd : (unsigned)items;
   const JobCfl C = cfl ? *cfl : JobCfl{};
-#define AMRVAC_FUSED_KERNEL(ND, SPT, W1, CF, LM, FX) \
-  k_stage_fused<ND, SPT, W1, CF, LM, FX><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, P, st, C)
+#define AMRVAC_FUSED_KERNEL(ND, SPT, W1, CF, LM, FX)                                                         \
+  do {                                                                                                      \
+    if (freg)                                                                                               \
+      k_stage_fused<ND, SPT, W1, CF, LM, FX, true><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out, w, \
+                                                                         P, st, C, static_cast<SPT::R*>(freg)); \
+    else                                                                                                    \
+      k_stage_fused<ND, SPT, W1, CF, LM, FX, false><<<grid, 256, 0, s>>>(G, T, J, tune, per_xcd, in, base, out,  \
+                                                                          w, P, st, C, nullptr);            \
+  } while (0)
 #define AMRVAC_FUSED_LAUNCH(ND, SPT, LM, FX)               \
   do {                                                     \
     if (cfl) {                                             \

@@ -60,6 +60,10 @@ struct JobCfl {
   double* ch;
   double* kappa;
   int njobs;
+  // nonzero: the cells next to faces towards finer leaves are left out of
+  // the folded rate (the coarse/fine flux correction changes them after the
+  // stage; launch_cfl_reflux_cells folds them in afterwards)
+  int skip_fine = 0;
 };
 
 struct FixedBC {
@@ -106,14 +110,28 @@ struct FusedTune {
 hipError_t launch_fused5_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J, const void* in,
                                const void* base, void* out, double w, const PhysConst& P, DevStatus* st,
                                double* part);
+// freg (may be null): flux registers, [cap][6 faces][NV][face cells] in the
+// face precision (face cells nx^2 in 3D, nx in 2D, transverse index t1 + nx
+// t2 with t1 along the face's first transverse axis: y for x faces, x
+// otherwise).  The stage stores there the face fluxes it evaluates on block
+// faces towards finer or coarser leaves.
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                               const FusedTune& tune, const void* in, const void* base, void* out, double w,
-                              const PhysConst& P, DevStatus* st, const JobCfl* cfl);
-// tasks: (block, face) pairs grouped by direction; direction d's are pairs
-// first[d] .. first[d] + count[d] - 1 (host arrays)
+                              const PhysConst& P, DevStatus* st, const JobCfl* cfl, void* freg);
+// Coarse/fine flux correction of out.  tasks: (block, face) pairs grouped by
+// direction; direction d's are pairs first[d] .. first[d] + count[d] - 1
+// (host arrays).  With freg (the registers the fused stage filled) the
+// fluxes are read from there; without (three ghost layers) they are
+// evaluated again from in.
 hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                                  const int* tasks, const int first[3], const int count[3], const void* in,
-                                 void* out, double w, const PhysConst& P);
+                                 void* out, double w, const PhysConst& P, const void* freg);
+// After the correction of a stage that folded its CFL rate with
+// C.skip_fine: fold in the rates of the corrected cells (the coarse cells
+// next to each task's face).
+hipError_t launch_cfl_reflux_cells(hipStream_t s, const GridConst& G, const Tables& T, const int* tasks,
+                                   int ntasks, const void* slot, const PhysConst& P, DevStatus* st,
+                                   const JobCfl& C);
 
 // regrid transfer tasks: kind, new block, up to 8 sources (see k_regrid)
 enum { REGRID_COPY = 0, REGRID_PROLONG = 1, REGRID_RESTRICT = 2 };

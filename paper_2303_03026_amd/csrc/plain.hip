@@ -34,7 +34,10 @@ __device__ __forceinline__ long pidx_n(const GridConst& G, int i, int j, int k) 
   return ((long)kk * G.pn + (j + G.ng)) * G.pn + (i + G.ng);
 }
 
-template <int NDIM, class SP>
+// UNI: a task's ghost cells are a multiple of 64, so each wave lies in one
+// task and its block, face, links and positions are wave-uniform (scalar
+// loads, no divergence between the kinds of task).
+template <int NDIM, class SP, bool UNI>
 __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __restrict__ tasks, int ntasks, Tables T,
                                                    void* __restrict__ slot, PhysConst P, FixedBC fixed) {
   const int* __restrict__ link = T.link;
@@ -43,7 +46,8 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
   const int ncell = NDIM == 3 ? ng * nx * nx : ng * nx;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long)ntasks * ncell) return;
-  const int task = (int)(gid / ncell);
+  int task = (int)(gid / ncell);
+  if (UNI) task = __builtin_amdgcn_readfirstlane(task);
   const int t = (int)(gid - (long)task * ncell);
   const int b = tasks[2 * task];
   const int face = tasks[2 * task + 1];
@@ -469,7 +473,7 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, J
                                                        const int* __restrict__ tasks, int ntasks,
                                                        const void* __restrict__ in, void* out, double w,
                                                        PhysConst P) {
-  static_assert((NS == 4 && NFINE == 2) || (NS == 1 && NFINE == 4), "2D: four lanes; 3D: one");
+  static_assert((NS == 4 && NFINE == 2) || (NS == 8 && NFINE == 4), "2D: four lanes; 3D: eight");
   const int* __restrict__ link = T.link;
   using R = typename SP::R;
   const int nx = G.nx;
@@ -500,28 +504,21 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, J
                                G.ndim == 3 ? g2 - o2 * nx : 0, ch, hic, P, T.inv_dx, fb, Fo);
   };
   R F[NV], v[NFINE][NV];
-  if constexpr (NS == 1) {
+  if (sub == 0) {
     face_flux_from_slot<D, SP, SIX>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, T.inv_dx, b, F);
-    // (unrolled: a run-time index into v would place it in scratch memory)
-#pragma unroll
-    for (int k = 0; k < NFINE; ++k) fine_face(k, v[k]);
+  } else if (sub <= NFINE) {
+    fine_face(sub - 1, F);
   } else {
-    if (sub == 0) {
-      face_flux_from_slot<D, SP, SIX>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, T.inv_dx, b, F);
-    } else if (sub <= NFINE) {
-      fine_face(sub - 1, F);
-    } else {
 #pragma unroll
-      for (int q = 0; q < NV; ++q) F[q] = R(0);
-    }
-    // every lane of the group is active here
-    const int first = (int)(threadIdx.x & 63) - sub;
-#pragma unroll
-    for (int k = 0; k < NFINE; ++k)
-#pragma unroll
-      for (int q = 0; q < NV; ++q) v[k][q] = __shfl(F[q], first + 1 + k, 64);
-    if (sub != 0) return;
+    for (int q = 0; q < NV; ++q) F[q] = R(0);
   }
+  // every lane of the group is active here
+  const int first = (int)(threadIdx.x & 63) - sub;
+#pragma unroll
+  for (int k = 0; k < NFINE; ++k)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[k][q] = __shfl(F[q], first + 1 + k, 64);
+  if (sub != 0) return;
   const double dt = J.dt_scale * J.dt[job];
   R Ff[NV];
 #pragma unroll
@@ -544,6 +541,119 @@ __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, J
     const double dl = side ? -df * idx : df * idx;
     SP::st(o, q, c, pc, SP::ld(o, q, c, pc) + w * dt * dl);
   }
+}
+
+// The same correction from the flux registers the fused stage filled: one
+// thread per (task, coarse face cell) reads the coarse face flux and the
+// fluxes of the 2^(d-1) fine faces behind it (those fine blocks' registers
+// on the opposite face) and applies the same update in the same order.
+template <int D, class SP, int NFINE>
+__global__ void __launch_bounds__(256) k_reflux_apply(GridConst G, Tables T, JobScalars J,
+                                                     const int* __restrict__ tasks, int ntasks,
+                                                     const typename SP::R* __restrict__ freg, void* out, double w) {
+  using R = typename SP::R;
+  const int* __restrict__ link = T.link;
+  const int nx = G.nx;
+  const int nfc = G.ndim == 3 ? nx * nx : nx;  // face cells per register
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)ntasks * nfc) return;
+  const int task = (int)(gid / nfc);
+  const int t = (int)(gid - (long)task * nfc);
+  const int b = tasks[2 * task], face = tasks[2 * task + 1];
+  if ((face >> 1) != D) return;
+  const int side = face & 1;
+  const int* L = link + ((long)b * 6 + face) * LINK_INTS;
+  const int t1 = t % nx, t2 = G.ndim == 3 ? t / nx : 0;
+  auto reg = [&](int blk, int f) { return freg + (long)(blk * 6 + f) * NV * nfc; };
+  R F[NV], v[NFINE][NV];
+  const R* rc = reg(b, face);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) F[q] = rc[q * nfc + t];
+#pragma unroll
+  for (int k = 0; k < NFINE; ++k) {
+    const int a = k & 1, e = k >> 1;
+    const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
+    const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
+    const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
+    const R* rf = reg(fb, face ^ 1);
+    const int cf = (G.ndim == 3 ? (g2 - o2 * nx) * nx : 0) + (g1 - o1 * nx);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[k][q] = rf[q * nfc + cf];
+  }
+  const int job = T.job[b];
+  const double dt = J.dt_scale * J.dt[job];
+  R Ff[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    if constexpr (NFINE == 4)
+      Ff[q] = ((v[0][q] + v[1][q]) + (v[2][q] + v[3][q])) * R(0.25);
+    else
+      Ff[q] = (v[0][q] + v[1][q]) * R(0.5);
+  }
+  const int cell_d = side ? nx - 1 : 0;
+  long c;
+  if (D == 0) c = pidx(G, cell_d, t1, t2);
+  else if (D == 1) c = pidx(G, t1, cell_d, t2);
+  else c = pidx(G, t1, t2, cell_d);
+  const double idx = T.inv_dx[3 * b + D];
+  void* o = block_ptr<SP>(out, b, G.pcells);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double df = (double)Ff[q] - (double)F[q];
+    const double dl = side ? -df * idx : df * idx;
+    SP::st(o, q, c, G.pcells, SP::ld(o, q, c, G.pcells) + w * dt * dl);
+  }
+}
+
+// CFL rate of the cells a flux correction changed (the coarse cells next to
+// each task's face), after all corrections: one thread per (task, cell),
+// folded into the job's accumulators as the stage folds the others.
+template <class SP>
+__global__ void __launch_bounds__(256) k_cfl_reflux_cells(GridConst G, Tables T, const int* __restrict__ tasks,
+                                                         int ntasks, const void* __restrict__ slot, PhysConst P,
+                                                         DevStatus* st, JobCfl C) {
+  const int nx = G.nx;
+  const int nfc = G.ndim == 3 ? nx * nx : nx;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = gid < (long)ntasks * nfc;
+  double rate = 0.0;
+  int bad = 0, nan_seen = 0, job = 0;
+  if (live) {
+    const int task = (int)(gid / nfc);
+    const int t = (int)(gid - (long)task * nfc);
+    const int b = tasks[2 * task], face = tasks[2 * task + 1];
+    const int d = face >> 1, cd = (face & 1) ? nx - 1 : 0;
+    const int t1 = t % nx, t2 = G.ndim == 3 ? t / nx : 0;
+    long c;
+    if (d == 0) c = pidx(G, cd, t1, t2);
+    else if (d == 1) c = pidx(G, t1, cd, t2);
+    else c = pidx(G, t1, t2, cd);
+    job = T.job[b];
+    const void* blk = block_ptr<SP>(slot, b, G.pcells);
+    double u[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) u[q] = SP::ld(blk, q, c, G.pcells);
+    const double ix = T.inv_dx[3 * b], iy = T.inv_dx[3 * b + 1], iz = T.inv_dx[3 * b + 2];
+    const double r = G.ndim == 3 ? cell_rate<3>(u, P, ix, iy, iz, bad) : cell_rate<2>(u, P, ix, iy, iz, bad);
+    if (isnan(r))
+      nan_seen = 1;
+    else
+      rate = r;
+  }
+  if (nfc % 64 == 0) {
+    // a wave lies in one task, so in one job: wave max, one atomic
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rate = fmax(rate, __shfl_xor(rate, off, 64));
+    const int anynan = __any(nan_seen);
+    if (live && (threadIdx.x & 63) == 0) {
+      atomicMax(&C.rate_bits[job], (unsigned long long)__double_as_longlong(rate));
+      if (anynan) atomicOr(&C.nan[job], 1u);
+    }
+  } else if (live) {
+    atomicMax(&C.rate_bits[job], (unsigned long long)__double_as_longlong(rate));
+    if (nan_seen) atomicOr(&C.nan[job], 1u);
+  }
+  if (bad) atomicOr(&st->flags, (unsigned)bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -881,16 +991,24 @@ hipError_t launch_fill_faces(hipStream_t s, const GridConst& G, const int* tasks
   if (ntasks <= 0) return hipSuccess;
   const long ncell = (long)G.ng * G.nx * (G.ndim == 3 ? G.nx : 1);
   const unsigned nbk = nblocks_for((long)ntasks * ncell, 256);
+  const bool uni = ncell % 64 == 0;
   if (G.ndim == 3) {
-    if (G.precision == 0)
-      k_fill_faces<3, StoreF64><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
-    else
-      k_fill_faces<3, StoreMixed><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+    if (G.precision == 0) {
+      if (uni)
+        k_fill_faces<3, StoreF64, true><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+      else
+        k_fill_faces<3, StoreF64, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+    } else {
+      if (uni)
+        k_fill_faces<3, StoreMixed, true><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+      else
+        k_fill_faces<3, StoreMixed, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+    }
   } else {
     if (G.precision == 0)
-      k_fill_faces<2, StoreF64><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+      k_fill_faces<2, StoreF64, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
     else
-      k_fill_faces<2, StoreMixed><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+      k_fill_faces<2, StoreMixed, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
   }
   return hipGetLastError();
 }
@@ -925,17 +1043,23 @@ hipError_t launch_reflux(hipStream_t s, const GridConst& G, const int* tasks, in
 
 hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                                  const int* tasks, const int first[3], const int count[3], const void* in,
-                                 void* out, double w, const PhysConst& P) {
+                                 void* out, double w, const PhysConst& P, const void* freg) {
   // one launch per direction, in order: a coarse cell next to finer leaves
   // across faces of two directions is corrected once per direction
   const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
 #define AMRVAC_REFLUX_LAUNCH(D, SPT)                                                                       \
   if (count[D] > 0) {                                                                                     \
-    if (G.ndim == 3 && G.ng == 3)                                                                         \
-      k_reflux_correct<D, SPT, 1, 4, true><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(              \
+    if (freg && G.ndim == 3)                                                                              \
+      k_reflux_apply<D, SPT, 4><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(                         \
+          G, T, J, tasks + 2 * first[D], count[D], static_cast<const SPT::R*>(freg), out, w);              \
+    else if (freg)                                                                                        \
+      k_reflux_apply<D, SPT, 2><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(                         \
+          G, T, J, tasks + 2 * first[D], count[D], static_cast<const SPT::R*>(freg), out, w);              \
+    else if (G.ndim == 3 && G.ng == 3)                                                                    \
+      k_reflux_correct<D, SPT, 8, 4, true><<<nblocks_for(count[D] * per * 8, 256), 256, 0, s>>>(          \
           G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
     else if (G.ndim == 3)                                                                                 \
-      k_reflux_correct<D, SPT, 1, 4, false><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(             \
+      k_reflux_correct<D, SPT, 8, 4, false><<<nblocks_for(count[D] * per * 8, 256), 256, 0, s>>>(         \
           G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
     else                                                                                                  \
       k_reflux_correct<D, SPT, 4, 2, true><<<nblocks_for(count[D] * per * 4, 256), 256, 0, s>>>(          \
@@ -951,6 +1075,18 @@ hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables
     if (G.ndim == 3) AMRVAC_REFLUX_LAUNCH(2, StoreMixed);
   }
 #undef AMRVAC_REFLUX_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_reflux_cells(hipStream_t s, const GridConst& G, const Tables& T, const int* tasks,
+                                   int ntasks, const void* slot, const PhysConst& P, DevStatus* st,
+                                   const JobCfl& C) {
+  if (ntasks <= 0) return hipSuccess;
+  const long n = (long)ntasks * (G.ndim == 3 ? G.nx * G.nx : G.nx);
+  if (G.precision == 0)
+    k_cfl_reflux_cells<StoreF64><<<nblocks_for(n, 256), 256, 0, s>>>(G, T, tasks, ntasks, slot, P, st, C);
+  else
+    k_cfl_reflux_cells<StoreMixed><<<nblocks_for(n, 256), 256, 0, s>>>(G, T, tasks, ntasks, slot, P, st, C);
   return hipGetLastError();
 }
 

@@ -471,6 +471,9 @@ struct amrvac_ctx {
   // fused five-cell path in 3D: each cell's x and y flux differences between
   // the stage kernel's two sweeps (single-job FP64 contexts, first use)
   double* d_part = nullptr;
+  // fused path of two ghost layers with coarse/fine flux correction: the
+  // flux registers the stage fills and the correction reads (first use)
+  void* d_freg = nullptr;
   double* d_flux[3] = {nullptr, nullptr, nullptr};
   DevStatus* d_status = nullptr;
   // graph of one step (single-job amrvac_advance)
@@ -517,7 +520,7 @@ void free_all(amrvac_ctx* c) {
   void* ptrs[] = {c->d_level, c->d_job,   c->d_link,  c->d_pos,   c->d_wrap,    c->d_invdx,   c->d_order, c->d_tfill,
                   c->d_tfused, c->d_tprol, c->d_trefl, c->d_geom,  c->d_rate,    c->d_nan,     c->d_jdt,   c->d_jch,
                   c->d_jkappa, c->d_prim,  c->d_flux[0], c->d_flux[1], c->d_flux[2], c->d_status,
-                  c->d_part};
+                  c->d_part,  c->d_freg};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < amrvac_ctx::kStaging; ++k) {
@@ -767,9 +770,16 @@ JobCfl cfl_state(amrvac_ctx* c, double* dt, double* ch, double* kappa) {
 }
 
 // The fused stage can fold the next step's CFL rate into its output only
-// where nothing changes that output afterwards (no coarse/fine flux
-// correction).
-bool can_carry(const amrvac_ctx* c) { return c->path == AMRVAC_PATH_FUSED && c->n_trefl == 0 && c->G.ng == 2; }
+// where nothing changes that output afterwards: with coarse/fine flux
+// correction the stage leaves out the cells next to faces towards finer
+// leaves, and a pass after the correction folds those in.
+bool can_carry(const amrvac_ctx* c) { return c->path == AMRVAC_PATH_FUSED && c->G.ng == 2; }
+
+// flux registers for the fused stage of two ghost layers, when a coarse/fine
+// correction follows it (else null: the correction evaluates its fluxes)
+void* stage_freg(const amrvac_ctx* c) {
+  return c->path == AMRVAC_PATH_FUSED && c->G.ng == 2 && c->n_trefl > 0 ? c->d_freg : nullptr;
+}
 
 int clear_if_dirty(amrvac_ctx* c) {
   if (c->acc_dirty) {
@@ -817,22 +827,27 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
   touch_slot(c, out);
   if (c->path == AMRVAC_PATH_FUSED) {
     const bool fold = fold_cfl && can_carry(c);
+    const bool corr = c->n_trefl > 0;
+    void* freg = stage_freg(c);
     JobCfl C{};
     if (fold) {
       drop_carry(c);
       if (int rc = clear_if_dirty(c)) return rc;
       C = cfl_state(c, nullptr, nullptr, nullptr);
+      C.skip_fine = corr ? 1 : 0;
     }
     if (c->G.ng == 3)
       HIP_TRY(c, launch_fused5_stage(c->stream, c->G, T, J, c->slots[in], c->slots[base], c->slots[out], w, c->P,
                                      c->d_status, c->d_part));
     else
       HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->tune, c->slots[in], c->slots[base], c->slots[out], w,
-                                    c->P, c->d_status, fold ? &C : nullptr));
-    if (fold) c->carry_slot = out;
+                                    c->P, c->d_status, fold ? &C : nullptr, freg));
     HIP_TRY(c, launch_reflux_correct(c->stream, c->G, T, J, c->d_trefl, c->refl_first, c->refl_count,
-                                     c->slots[in], c->slots[out], w,
-                                     c->P));
+                                     c->slots[in], c->slots[out], w, c->P, freg));
+    if (fold && corr)
+      HIP_TRY(c, launch_cfl_reflux_cells(c->stream, c->G, T, c->d_trefl, c->n_trefl, c->slots[out], c->P,
+                                         c->d_status, C));
+    if (fold) c->carry_slot = out;
     return AMRVAC_OK;
   }
   return plain_stage(c, in, base, out, w, J, c->d_prim, c->d_flux);
@@ -904,13 +919,20 @@ int enqueue_step(amrvac_ctx* c, int nstages, double* dt, double* ch, double* kap
 
 int slots_for_stages(int nstages) { return nstages >= 5 ? 4 : (nstages >= 3 ? 3 : 2); }
 
-// The plain (per-kernel) FP64 path's primitive and face-flux scratch, and
-// the 3D five-cell fused stage's array of in-plane flux differences,
-// allocated on first use of their path: a context that only runs the fused
-// path of two ghost layers holds neither (the plain scratch for 4096 blocks
-// of 16^3 is 6 GB, the difference array 1.2 GB).  Called by the entry points
+// The plain (per-kernel) FP64 path's primitive and face-flux scratch, the
+// 3D five-cell fused stage's array of in-plane flux differences, and the
+// flux registers of the fused path of two ghost layers on grids with
+// coarse/fine flux correction (110 KB per 16^3 block in FP64), allocated on
+// first use of their path: a context that only runs the fused path on a
+// uniform grid holds none of them (the plain scratch for 4096 blocks of
+// 16^3 is 6 GB, the difference array 1.2 GB).  Called by the entry points
 // before they enqueue work, so never inside a graph capture.
 int ensure_plain_scratch(amrvac_ctx* c) {
+  if (c->path == AMRVAC_PATH_FUSED && c->G.ng == 2 && c->n_trefl > 0 && !c->d_freg) {
+    const size_t nfc = c->G.ndim == 3 ? (size_t)c->G.nx * c->G.nx : (size_t)c->G.nx;
+    const size_t rbytes = c->G.precision == 0 ? sizeof(double) : sizeof(float);
+    return dev_alloc(c, &c->d_freg, (size_t)c->cap * 6 * NV * nfc * rbytes);
+  }
   if (c->path == AMRVAC_PATH_FUSED && c->G.ng == 3 && c->G.ndim == 3 && !c->d_part)
     return dev_alloc(c, (void**)&c->d_part, (size_t)c->cap * NV * c->G.icells * sizeof(double));
   if (c->path != AMRVAC_PATH_PLAIN || c->d_prim) return AMRVAC_OK;
@@ -1508,11 +1530,11 @@ int amrvac_autotune(amrvac_ctx* c, int in, int out, int reps, amrvac_tune* best,
   const Tables T = c->tables();
   for (size_t k = 0; k < cand.size() && e == hipSuccess && rc == AMRVAC_OK; ++k) {
     e = launch_fused_stage(c->stream, c->G, T, J, cand[k], c->slots[in], c->slots[out], c->slots[out], 1.0, c->P,
-                           c->d_status, nullptr);
+                           c->d_status, nullptr, stage_freg(c));
     if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
     for (int r = 0; r < reps && e == hipSuccess; ++r)
       e = launch_fused_stage(c->stream, c->G, T, J, cand[k], c->slots[in], c->slots[out], c->slots[out], 1.0,
-                             c->P, c->d_status, nullptr);
+                             c->P, c->d_status, nullptr, stage_freg(c));
     if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&times[k], e0, e1);
@@ -1653,6 +1675,7 @@ int amrvac_batch_step(amrvac_ctx* c) {
   if (!c->batch) return fail(c, AMRVAC_E_STATE, "not a batch context");
   if (int rc = ensure_tables(c)) return rc;
   if (c->n_order == 0) return AMRVAC_OK;
+  if (int rc = ensure_plain_scratch(c)) return rc;
   if (int rc = enqueue_step(c, c->batch_stages, c->d_jdt, c->d_jch, c->d_jkappa)) return rc;
   for (int j = 0; j < c->njob_cap; ++j) {
     JobRec& J = c->jobs[j];
