@@ -75,6 +75,11 @@ struct FixedBC {
 // one for prolongation (run after the first)
 hipError_t launch_fill_faces(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const Tables& T,
                              void* slot, const PhysConst& P, const FixedBC& fixed);
+// The faces towards coarser leaves (prolongation tasks) only, one thread per
+// fine ghost layer and coarse cell across the face; results equal those of
+// launch_fill_faces on the same tasks.
+hipError_t launch_prolong_faces(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const Tables& T,
+                                void* slot);
 
 // plain stage (single-job FP64 contexts; scalars are element 0) -------------
 hipError_t launch_prim(hipStream_t s, const GridConst& G, const void* slot, double* prim, const PhysConst& P,

@@ -135,73 +135,126 @@ __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __re
         out[q] = (bc == 2 && (q == I_MX + d || q == I_BX + d)) ? -v : v;
       }
     }
-  } else {  // LINK_COARSE: conservative minmod-limited linear prolongation
-    const int cb = L[1];
-    const void* src = block_ptr<SP>(slot, cb, pc);
-    int lc[3] = {0, 0, 0};
-    int odd[3] = {0, 0, 0};
-#pragma unroll
-    for (int ax = 0; ax < NDIM; ++ax) {
-      const long n = T.wrap[3 * b + ax];
-      long g = (long)pos[3 * b + ax] * nx + c[ax];
-      g = (g + n) % n;
-      odd[ax] = (int)(g & 1);
-      lc[ax] = (int)((g >> 1) - (long)pos[3 * cb + ax] * nx);
-    }
-    // The coarse cell lc is interior to cb (the fine ghost lies over cb's
-    // face); a slope neighbour steps out of cb by one cell along one axis
-    // at most, into a face ghost slab of cb.  With a same-level leaf across
-    // that face the cell is read in place from its interior (that slab is
-    // not filled on the fused path); across faces towards finer leaves or
-    // the domain boundary it is cb's own ghost cell, filled before this
-    // pass.  (A face of cb towards a coarser leaf is never reached: the
-    // fine block would then touch that leaf across an edge, which 2:1
-    // nesting excludes.)
-    const long i0 = pidx_n<NDIM>(G, lc[0], lc[1], lc[2]);
-    // block ids, not pointers, are selected (keeps the loads global ones);
-    // the links of all of cb's faces are read at once
-    int lk[2 * NDIM], ln[2 * NDIM];
-#pragma unroll
-    for (int f = 0; f < 2 * NDIM; ++f) {
-      lk[f] = link[((long)cb * 6 + f) * LINK_INTS];
-      ln[f] = link[((long)cb * 6 + f) * LINK_INTS + 1];
-    }
-    int bm[3], bp[3];
-    long im[3], ip[3];
-#pragma unroll
-    for (int ax = 0; ax < NDIM; ++ax) {
-      int m[3] = {lc[0], lc[1], lc[2]}, p[3] = {lc[0], lc[1], lc[2]};
-      m[ax] -= 1;
-      p[ax] += 1;
-      bm[ax] = cb;
-      bp[ax] = cb;
-      if (m[ax] < 0 && lk[2 * ax] == LINK_SAME) {
-        bm[ax] = ln[2 * ax];
-        m[ax] += nx;
-      }
-      if (p[ax] >= nx && lk[2 * ax + 1] == LINK_SAME) {
-        bp[ax] = ln[2 * ax + 1];
-        p[ax] -= nx;
-      }
-      im[ax] = pidx_n<NDIM>(G, m[0], m[1], m[2]);
-      ip[ax] = pidx_n<NDIM>(G, p[0], p[1], p[2]);
-    }
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const double uc = SP::ld(src, q, i0, pc);
-      double r = uc;
-#pragma unroll
-      for (int ax = 0; ax < NDIM; ++ax) {
-        const double sg = odd[ax] ? 0.25 : -0.25;
-        const double um = SP::ld(block_ptr<SP>(static_cast<const void*>(slot), bm[ax], pc), q, im[ax], pc);
-        const double up = SP::ld(block_ptr<SP>(static_cast<const void*>(slot), bp[ax], pc), q, ip[ax], pc);
-        r = r + sg * minmod2(uc - um, up - uc);
-      }
-      out[q] = r;
-    }
+  } else {
+    return;  // faces towards coarser leaves: k_prolong_faces
   }
 #pragma unroll
   for (int q = 0; q < NV; ++q) SP::st(dst, q, di, pc, out[q]);
+}
+
+// Prolongation of the ghost cells of faces towards coarser leaves (the
+// COARSE tasks of k_fill_faces, same arithmetic): one thread per (fine
+// ghost layer, coarse cell across the face), writing the 2^(d-1) fine ghost
+// cells of that layer over the coarse cell, so the coarse cell and its
+// slope neighbours are read once for all of them.  Threads per task:
+// ng (nx/2)^(d-1).
+template <int NDIM, class SP, bool UNI>
+__global__ void __launch_bounds__(256) k_prolong_faces(GridConst G, const int* __restrict__ tasks, int ntasks,
+                                                      Tables T, void* __restrict__ slot) {
+  const int* __restrict__ link = T.link;
+  const int* __restrict__ pos = T.pos;
+  const int nx = G.nx, ng = G.ng, hx = nx / 2;
+  const int ncell = NDIM == 3 ? ng * hx * hx : ng * hx;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)ntasks * ncell) return;
+  int task = (int)(gid / ncell);
+  if (UNI) task = __builtin_amdgcn_readfirstlane(task);
+  const int t = (int)(gid - (long)task * ncell);
+  const int b = tasks[2 * task];
+  const int face = tasks[2 * task + 1];
+  const int d = face >> 1, side = face & 1;
+  const int* L = link + ((long)b * 6 + face) * LINK_INTS;
+  const int ta = d == 0 ? 1 : 0;  // first transverse axis
+  const int tb = d == 2 ? 1 : 2;  // second transverse axis (z in 2D: unused)
+  const long pc = G.pcells;
+  void* dst = block_ptr<SP>(slot, b, pc);
+  // fine ghost layer a along d, coarse transverse indices c1 (along ta), c2
+  const int a = t % ng, c1 = (t / ng) % hx, c2 = NDIM == 3 ? t / (ng * hx) : 0;
+  const int gd = side ? nx + a : a - ng;  // ghost coordinate along d
+  int c[3] = {0, 0, 0};  // the first of the fine cells (even transverse offsets)
+  c[d] = gd;
+  c[ta] = 2 * c1;
+  if (NDIM == 3) c[tb] = 2 * c2;
+  const int cb = L[1];
+  const void* src = block_ptr<SP>(slot, cb, pc);
+  int lc[3] = {0, 0, 0};
+  int odd_d = 0;
+#pragma unroll
+  for (int ax = 0; ax < NDIM; ++ax) {
+    const long n = T.wrap[3 * b + ax];
+    long g = (long)pos[3 * b + ax] * nx + c[ax];
+    g = (g + n) % n;
+    if (ax == d) odd_d = (int)(g & 1);
+    lc[ax] = (int)((g >> 1) - (long)pos[3 * cb + ax] * nx);
+  }
+  // slope neighbours of lc as in k_fill_faces: in place across same-level
+  // faces of cb, else cb's own ghost cells (filled before this pass)
+  const long i0 = pidx_n<NDIM>(G, lc[0], lc[1], lc[2]);
+  int lk[2 * NDIM], ln[2 * NDIM];
+#pragma unroll
+  for (int f = 0; f < 2 * NDIM; ++f) {
+    lk[f] = link[((long)cb * 6 + f) * LINK_INTS];
+    ln[f] = link[((long)cb * 6 + f) * LINK_INTS + 1];
+  }
+  int bm[3], bp[3];
+  long im[3], ip[3];
+#pragma unroll
+  for (int ax = 0; ax < NDIM; ++ax) {
+    int m[3] = {lc[0], lc[1], lc[2]}, p[3] = {lc[0], lc[1], lc[2]};
+    m[ax] -= 1;
+    p[ax] += 1;
+    bm[ax] = cb;
+    bp[ax] = cb;
+    if (m[ax] < 0 && lk[2 * ax] == LINK_SAME) {
+      bm[ax] = ln[2 * ax];
+      m[ax] += nx;
+    }
+    if (p[ax] >= nx && lk[2 * ax + 1] == LINK_SAME) {
+      bp[ax] = ln[2 * ax + 1];
+      p[ax] -= nx;
+    }
+    im[ax] = pidx_n<NDIM>(G, m[0], m[1], m[2]);
+    ip[ax] = pidx_n<NDIM>(G, p[0], p[1], p[2]);
+  }
+  // fine cell k: offsets (k & 1) along ta and (k >> 1) along tb; its parity
+  // along a transverse axis is its offset (the block's first cell sits at an
+  // even global index), along d that of its ghost coordinate
+  constexpr int NF = NDIM == 3 ? 4 : 2;
+  long di[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    int f3[3] = {c[0], c[1], c[2]};
+    f3[ta] += k & 1;
+    if (NDIM == 3) f3[tb] += k >> 1;
+    di[k] = pidx_n<NDIM>(G, f3[0], f3[1], f3[2]);
+  }
+  // every load before the first store (sources and destination share the
+  // slot)
+  double uc[NV], sl[NV][3];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    uc[q] = SP::ld(src, q, i0, pc);
+#pragma unroll
+    for (int ax = 0; ax < NDIM; ++ax) {
+      const double um = SP::ld(block_ptr<SP>(static_cast<const void*>(slot), bm[ax], pc), q, im[ax], pc);
+      const double up = SP::ld(block_ptr<SP>(static_cast<const void*>(slot), bp[ax], pc), q, ip[ax], pc);
+      sl[q][ax] = minmod2(uc[q] - um, up - uc[q]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double r = uc[q];
+#pragma unroll
+      for (int ax = 0; ax < NDIM; ++ax) {
+        const int odd = ax == d ? odd_d : (ax == ta ? (k & 1) : (k >> 1));
+        const double sg = odd ? 0.25 : -0.25;
+        r = r + sg * sl[q][ax];
+      }
+      SP::st(dst, q, di[k], pc, r);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -461,13 +514,14 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
   face_flux_rt<D, R>(P.flux, wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
 }
 
-// In 2D each (task, face cell) takes a group of NS = 4 consecutive lanes
-// (the coarse face, the two fine faces, one idle lane): every lane evaluates
-// one face flux, so a correction costs one face evaluation of latency rather
-// than three, and the group's first lane gathers the fine fluxes and applies
-// the update.  In 3D (NS = 1) one lane evaluates all five faces: there the
-// tasks are many and the four-cell faces cheap, and idle lanes of eight-lane
-// groups cost more than the latency saved.
+// The correction that evaluates its face fluxes again (three ghost layers,
+// where the stage keeps no flux registers): each (task, face cell) takes a
+// group of NS consecutive lanes, 4 in 2D (the coarse face, the two fine
+// faces, one idle lane) and 8 in 3D (the coarse face, the four fine faces,
+// three idle lanes).  Every lane evaluates one face flux, so a correction
+// costs one six-cell face evaluation of latency and registers rather than
+// three or five, and the group's first lane gathers the fine fluxes and
+// applies the update.
 template <int D, class SP, int NS, int NFINE, bool SIX>
 __global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, JobScalars J,
                                                        const int* __restrict__ tasks, int ntasks,
@@ -1009,6 +1063,34 @@ hipError_t launch_fill_faces(hipStream_t s, const GridConst& G, const int* tasks
       k_fill_faces<2, StoreF64, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
     else
       k_fill_faces<2, StoreMixed, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot, P, fixed);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_faces(hipStream_t s, const GridConst& G, const int* tasks, int ntasks, const Tables& T,
+                                void* slot) {
+  if (ntasks <= 0) return hipSuccess;
+  const long hx = G.nx / 2;
+  const long ncell = (long)G.ng * hx * (G.ndim == 3 ? hx : 1);
+  const unsigned nbk = nblocks_for((long)ntasks * ncell, 256);
+  const bool uni = ncell % 64 == 0;
+  if (G.ndim == 3) {
+    if (G.precision == 0) {
+      if (uni)
+        k_prolong_faces<3, StoreF64, true><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot);
+      else
+        k_prolong_faces<3, StoreF64, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot);
+    } else {
+      if (uni)
+        k_prolong_faces<3, StoreMixed, true><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot);
+      else
+        k_prolong_faces<3, StoreMixed, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot);
+    }
+  } else {
+    if (G.precision == 0)
+      k_prolong_faces<2, StoreF64, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot);
+    else
+      k_prolong_faces<2, StoreMixed, false><<<nbk, 256, 0, s>>>(G, tasks, ntasks, T, slot);
   }
   return hipGetLastError();
 }

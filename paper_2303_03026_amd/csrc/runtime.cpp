@@ -761,7 +761,7 @@ int fill_slot(amrvac_ctx* c, int slot) {
   const bool fused = c->path == AMRVAC_PATH_FUSED;
   HIP_TRY(c, launch_fill_faces(c->stream, c->G, fused ? c->d_tfused : c->d_tfill, fused ? c->n_tfused : c->n_tfill,
                                T, c->slots[slot], c->P, c->fixed));
-  HIP_TRY(c, launch_fill_faces(c->stream, c->G, c->d_tprol, c->n_tprol, T, c->slots[slot], c->P, c->fixed));
+  HIP_TRY(c, launch_prolong_faces(c->stream, c->G, c->d_tprol, c->n_tprol, T, c->slots[slot]));
   return AMRVAC_OK;
 }
 
