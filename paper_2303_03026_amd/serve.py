@@ -10,12 +10,16 @@ round.  The four classes run on their own streams, so their rounds overlap
 on the device.  A job leaves as soon as its last step is done; the places it
 frees are reused by the next admission.
 
-Admission within a class is first come, first served with backfill: when the
-oldest waiting job does not fit, later jobs of the class that do fit (among
-the next `backfill_window` whose initial states are ready) are admitted
-ahead of it, until the oldest has waited `max_head_wait_s`; from then on
-nothing passes it, so every job is admitted within that wait plus the time
-for one run of its size to free up.
+Jobs that arrive together are queued largest (cells x steps) first, so that
+a burst does not end with one long job running alone.  Initial states are
+built on worker threads in queue order; admission never waits for one (a
+job whose state is not ready yet is passed over until it is).  Admission
+within a class is first come, first served with backfill: when the oldest
+waiting job does not fit, later jobs of the class that do fit (among the
+next `backfill_window` whose initial states are ready) are admitted ahead
+of it, until the oldest has waited `max_head_wait_s`; from then on nothing
+passes it, so every job is admitted within that wait plus the time for one
+run of its size to free up.
 
 Reported per run: per-job latency (completion minus arrival; p50, p99, max),
 queueing delay, and the aggregate Mcell-updates/s of all jobs.
@@ -92,7 +96,11 @@ class ServingEngine:
         multiplied by time_scale).  Returns latency/throughput statistics and
         the final states of the job ids in keep_results."""
         torch = self.torch
-        order = sorted(range(len(jobs)), key=lambda i: jobs[i]["arrival"])
+        # arrival order; among jobs that arrive together, the largest
+        # (cells x steps) first, so that a burst does not end on a long job
+        # left running alone
+        order = sorted(range(len(jobs)),
+                       key=lambda i: (jobs[i]["arrival"], -(jobs[i]["n"] ** jobs[i]["ndim"]) * jobs[i]["steps"]))
         futures = {}
         ahead = 64
 
@@ -140,12 +148,18 @@ class ServingEngine:
                 k = 0
                 while k < len(q) and k < self.backfill_window:
                     i = q[k]
-                    if k > 0 and not futures[i].done():
+                    if not futures[i].done():
+                        # initial state still being built: never wait for it
+                        # here (the device would idle); it is admitted once
+                        # ready, in queue order among the ready ones
                         k += 1
                         continue
                     w = futures[i].result()
                     jid = pool.add_job(w)
                     if jid is None:
+                        # no room: later ready jobs that fit pass it only
+                        # while the oldest waiting job has waited less than
+                        # the bound
                         head_wait = time.perf_counter() - t0 - rec[q[0]]["arrival"]
                         if head_wait >= self.max_head_wait_s:
                             break
