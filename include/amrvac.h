@@ -354,7 +354,9 @@ int amrvac_reset_flags(amrvac_ctx* c);
  * -------------------------------------------------------------------------*/
 
 /* Create a batch context.  shape supplies ndim, block_nx (must be 16),
- * precision and the physics every job must share; nstages as in
+ * nghost (2, or 3 for the five-cell reconstructions in FP64), precision
+ * and the physics every job must share (including limiter and flux);
+ * nstages as in
  * amrvac_advance; slots are 2 (nstages = 2), 3 (nstages = 3, 4) or 4 (nstages = 5)
  * caller-owned DEVICE buffers of
  * amrvac_slot_bytes(shape, capacity_blocks) bytes each (the block pool);

@@ -1414,8 +1414,8 @@ int amrvac_set_path(amrvac_ctx* c, int path) {
   if (!c) return AMRVAC_E_ARG;
   if (path != AMRVAC_PATH_PLAIN && path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_ARG, "unknown path");
   if (path == AMRVAC_PATH_FUSED && c->G.nx != 16) return fail(c, AMRVAC_E_ARG, "the fused path needs block_nx = 16");
-  if (path == AMRVAC_PATH_FUSED && c->G.ng != 2 && !(c->G.ng == 3 && c->g.precision == AMRVAC_FP64 && !c->batch))
-    return fail(c, AMRVAC_E_ARG, "the fused path needs nghost = 2 (3 only for FP64 single-job grids)");
+  if (path == AMRVAC_PATH_FUSED && c->G.ng != 2 && !(c->G.ng == 3 && c->g.precision == AMRVAC_FP64))
+    return fail(c, AMRVAC_E_ARG, "the fused path needs nghost = 2 (3 only in FP64)");
   if (path == AMRVAC_PATH_PLAIN && (c->g.precision != AMRVAC_FP64 || c->batch))
     return fail(c, AMRVAC_E_ARG, "the plain path is for single-job FP64 contexts");
   c->path = path;
@@ -1588,8 +1588,8 @@ int amrvac_batch_create(amrvac_ctx** out, const amrvac_grid_desc* shape, int cap
   *out = nullptr;
   std::string why;
   if (check_desc(shape, &why) != AMRVAC_OK) { g_init_err = why; return AMRVAC_E_ARG; }
-  if (shape->block_nx != 16 || shape->nghost != 2) {
-    g_init_err = "batch contexts run the fused path: block_nx must be 16 and nghost 2";
+  if (shape->block_nx != 16 || (shape->nghost != 2 && !(shape->nghost == 3 && shape->precision == AMRVAC_FP64))) {
+    g_init_err = "batch contexts run the fused path: block_nx must be 16 and nghost 2 (3 in FP64)";
     return AMRVAC_E_ARG;
   }
   if (capacity_blocks < 1 || max_jobs < 1 || nstages < 2 || nstages > 5 || !slots) {
@@ -1631,7 +1631,8 @@ int amrvac_batch_add_job(amrvac_ctx* c, const amrvac_grid_desc* g, int nb, const
   std::string why;
   if (check_desc(g, &why) != AMRVAC_OK) return fail(c, AMRVAC_E_ARG, why);
   const amrvac_grid_desc& s = c->g;
-  if (g->ndim != s.ndim || g->block_nx != s.block_nx || g->precision != s.precision || g->gamma != s.gamma ||
+  if (g->ndim != s.ndim || g->block_nx != s.block_nx || g->nghost != s.nghost || g->precision != s.precision ||
+      g->gamma != s.gamma ||
       g->small_density != s.small_density || g->small_pressure != s.small_pressure ||
       g->fix_small_values != s.fix_small_values || g->limiter != s.limiter || g->flux != s.flux ||
       std::memcmp(g->bc_fixed_prim, s.bc_fixed_prim, sizeof(s.bc_fixed_prim)) != 0)

@@ -2,7 +2,10 @@
 pool, advanced together with per-job dt; each job's result is the same alone
 and in the mix (bit for bit: no arithmetic couples jobs), and matches the
 CPU oracle (FP64 jobs to the bars of tests/parity.py, FP32-mixed jobs to
-the bounds of tests/mixed_error.py)."""
+the bounds of tests/mixed_error.py).  FP64 pools also take the five-cell
+reconstructions on three ghost layers."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -83,6 +86,42 @@ def test_job_alone_equals_in_mix_2d(amr):
     for w, got in zip(ws, outs):
         ref = alone(amr, w, w.nsteps, 0)
         assert np.array_equal(got, ref), w.name
+
+
+def weno(w, lim=6, flux=2):
+    w.limiter, w.flux, w.ng = lim, flux, 3
+    return w
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_five_cell_jobs_alone_equal_in_mix(amr, orc, ndim):
+    """FP64 pools with three ghost layers ('wenozp5' + HLLC): the fused
+    five-cell stage over every resident job's blocks; each job equals its
+    single-job run bit for bit and meets the FP64 bars with the oracle's
+    roundoff floor."""
+    shape = weno(inputs.random_modes(32, ndim, seed=0))
+    batch = amr.Batch(shape, capacity_blocks=300 if ndim == 3 else 400, max_jobs=8)
+    if ndim == 3:
+        makes = [lambda: weno(inputs.random_modes(32, 3, seed=31, nsteps=5)),
+                 lambda: weno(inputs.random_modes(48, 3, seed=32, nsteps=3)),
+                 lambda: weno(dataclasses.replace(inputs.smooth_amr_state(3, nb1=2, seed=33), nsteps=4))]
+    else:
+        makes = [lambda: weno(inputs.random_modes(64, 2, seed=34, nsteps=6)),
+                 lambda: weno(dataclasses.replace(inputs.smooth_amr_state(2, nb1=4, seed=35), nsteps=4)),
+                 lambda: weno(inputs.random_modes(128, 2, seed=36, nsteps=3))]
+    ws = [m() for m in makes]
+    ids = [batch.add_job(w) for w in ws]
+    assert all(i is not None for i in ids)
+    while any(batch.job_info(i)[1] > 0 for i in ids):
+        batch.step()
+    outs = [batch.get_job(i) for i in ids]
+    batch.sync_flags()
+    batch.close()
+    for w, got in zip(ws, outs):
+        assert np.array_equal(got, alone(amr, w, w.nsteps, 0)), w.name
+    for make, w, got in zip(makes, ws, outs):
+        ref, f1, fi = parity.oracle_floor(orc, make)
+        parity.check(w, got, ref, "served five-cell %s" % w.name, f1, fi)
 
 
 def test_admission_by_pool_room_and_reuse(amr):

@@ -1,9 +1,9 @@
 """Fifth-order reconstructions on 3 ghost layers ('weno5': Jiang-Shu weights,
 'wenoz5': Borges et al.'s WENO-Z weights, 'wenozp5': Acker et al.'s WENO-Z+
 weights, 'mp5': Suresh and Huynh's monotonicity-preserving scheme), on the
-plain FP64 path, against the FP64 oracle.  The mixed-precision path, the
-batch pool and the fused path on 3D grids are built for 2 ghost layers and
-must refuse such a grid (the 2D fused path with 3 layers has its own
+plain FP64 path, against the FP64 oracle.  The mixed-precision path and
+FP32-mixed batch pools are built for 2 ghost layers and must refuse such a
+grid (the fused path and FP64 batch pools with 3 layers have their own
 tests)."""
 import numpy as np
 import pytest
@@ -134,7 +134,7 @@ def test_two_layer_paths_refuse_three_ghost_layers(amr):
     with pytest.raises(amr.AmrvacError):
         amr.Simulation(w, path=amr.PATH_PLAIN, precision=amr.FP32_MIXED)
     with pytest.raises(amr.AmrvacError):
-        amr.Batch(w, capacity_blocks=16, max_jobs=2, nstages=3)
+        amr.Batch(w, capacity_blocks=16, max_jobs=2, nstages=3, precision=amr.FP32_MIXED)
     w2 = inputs.random_modes(32, 3, seed=67)
     w2.limiter = 3  # WENO on 2 ghost layers: the stencil does not fit
     with pytest.raises(amr.AmrvacError):
