@@ -71,8 +71,8 @@ enum { AMRVAC_PATH_PLAIN = 0, AMRVAC_PATH_FUSED = 1 };
 enum { AMRVAC_LIM_VANLEER = 0, AMRVAC_LIM_KOREN = 1, AMRVAC_LIM_CADA3 = 2, AMRVAC_LIM_WENO5 = 3, AMRVAC_LIM_WENOZ5 = 4,
        AMRVAC_LIM_MP5 = 5, AMRVAC_LIM_WENOZP5 = 6 };
 /* The fifth-order reconstructions of Table t:limiters on 3 ghost cells
- * (nghost = 3; FP64 only: the per-kernel path, and the fused path on 2D
- * grids), each face value from the five
+ * (nghost = 3; FP64 on the per-kernel and the fused path, FP32-mixed on
+ * the fused path with the nonlinear weights in FP64), each face value from the five
  * cells on its side: 'weno5' (Jiang and Shu 1996, eps = 1e-6), 'wenoz5'
  * (Borges et al. 2008, WENO-Z weights, eps = 1e-40), 'wenozp5' (Acker et al.
  * 2016, WENO-Z+ weights with lambda = dx^(2/3) of the block, eps = 1e-40) and
@@ -95,8 +95,7 @@ typedef struct {
   int block_nx;           /* interior cells per direction per block (even,     */
                           /* 4..16; the fused path and FP32-mixed need 16)     */
   int nghost;             /* ghost layers: 2, or 3 for the five-cell           */
-                          /* reconstructions; block_nx >= 2 nghost (FP32-mixed */
-                          /* needs 2, the fused path 2 or, for 2D FP64, 3)     */
+                          /* reconstructions; block_nx >= 2 nghost            */
   int precision;          /* AMRVAC_FP64 or AMRVAC_FP32_MIXED                  */
   int base_blocks[3];     /* blocks per direction on level 1 (z ignored in 2D) */
   int bc_lo[3];           /* AMRVAC_BC_* at the minimum face of each direction */
@@ -291,8 +290,8 @@ int amrvac_lohner(amrvac_ctx* c, int slot, const double* weights, double wavefil
 /* Select the stage implementation: AMRVAC_PATH_PLAIN (separate primitive,
  * per-direction flux, reflux and update kernels; FP64 only, the default for
  * FP64 contexts) or AMRVAC_PATH_FUSED (one kernel per stage plus, on AMR
- * grids, a coarse/fine flux correction; needs block_nx = 16 and nghost = 2,
- * or nghost = 3 on 2D FP64 grids; the only path of FP32-mixed contexts).
+ * grids, a coarse/fine flux correction; needs block_nx = 16; the only path
+ * of FP32-mixed contexts).
  * AMRVAC_E_ARG if the context cannot run it. */
 int amrvac_set_path(amrvac_ctx* c, int path);
 
@@ -354,7 +353,7 @@ int amrvac_reset_flags(amrvac_ctx* c);
  * -------------------------------------------------------------------------*/
 
 /* Create a batch context.  shape supplies ndim, block_nx (must be 16),
- * nghost (2, or 3 for the five-cell reconstructions in FP64), precision
+ * nghost (2, or 3 for the five-cell reconstructions), precision
  * and the physics every job must share (including limiter and flux);
  * nstages as in
  * amrvac_advance; slots are 2 (nstages = 2), 3 (nstages = 3, 4) or 4 (nstages = 5)

@@ -574,25 +574,39 @@ __device__ __forceinline__ void reconstruct_face(int lim, const R wm[NV], const 
     reconstruct_face_lim<LIM_VANLEER>(wm, wa, wb, wp, wl, wr);
 }
 
+// The five-cell face values at face precision R: the stored (R) cell
+// values are promoted and the value is computed in FP64, then rounded to R.
+// (In FP32 the WENO-Z+ term (tau5 / (beta + 1e-40))^2 overflows and 1e-40
+// is not representable, so the nonlinear weights stay FP64 on the mixed
+// path too.)
+template <class R>
+__device__ __forceinline__ R weno5_face_r(R vm2, R vm1, R v0, R vp1, R vp2, int lim, double lambda) {
+  return (R)weno5_face((double)vm2, (double)vm1, (double)v0, (double)vp1, (double)vp2, lim, lambda);
+}
+template <class R>
+__device__ __forceinline__ R mp5_face_r(R vm2, R vm1, R v0, R vp1, R vp2) {
+  return (R)mp5_face((double)vm2, (double)vm1, (double)v0, (double)vp1, (double)vp2);
+}
+
 // Face states from the six cells c[0..5] around the face between c[2] and
 // c[3] (3 ghost layers): the fifth-order values of 'weno5' / 'wenoz5' /
 // 'wenozp5' (lambda = dx^(2/3) of the block) or 'mp5', else the
 // two-ghost-layer reconstruction from c[1..4]; first-order fallback as
 // always.
-__device__ __forceinline__ void reconstruct_face6(int lim, const double c[6][NV], double lambda, double wl[NV],
-                                                  double wr[NV]) {
+template <class R>
+__device__ __forceinline__ void reconstruct_face6(int lim, const R c[6][NV], double lambda, R wl[NV], R wr[NV]) {
   if (lim == LIM_MP5) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      wl[q] = mp5_face(c[0][q], c[1][q], c[2][q], c[3][q], c[4][q]);
-      wr[q] = mp5_face(c[5][q], c[4][q], c[3][q], c[2][q], c[1][q]);
+      wl[q] = mp5_face_r(c[0][q], c[1][q], c[2][q], c[3][q], c[4][q]);
+      wr[q] = mp5_face_r(c[5][q], c[4][q], c[3][q], c[2][q], c[1][q]);
     }
     positivity_fallback(wl, wr, c[2], c[3]);
   } else if (lim >= LIM_WENO5) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      wl[q] = weno5_face(c[0][q], c[1][q], c[2][q], c[3][q], c[4][q], lim, lambda);
-      wr[q] = weno5_face(c[5][q], c[4][q], c[3][q], c[2][q], c[1][q], lim, lambda);
+      wl[q] = weno5_face_r(c[0][q], c[1][q], c[2][q], c[3][q], c[4][q], lim, lambda);
+      wr[q] = weno5_face_r(c[5][q], c[4][q], c[3][q], c[2][q], c[1][q], lim, lambda);
     }
     positivity_fallback(wl, wr, c[2], c[3]);
   } else {

@@ -1,8 +1,13 @@
 // Fused stage kernel for 16^ndim blocks with three ghost layers (the
-// five-cell reconstructions 'weno5', 'wenoz5', 'wenozp5' and 'mp5'), FP64:
-// conserved -> primitive, the fifth-order face states, GLM interface + HLL
-// (or HLLD, HLLC) fluxes in every direction, flux difference, psi damping
-// and the SSPRK combination in one launch.
+// five-cell reconstructions 'weno5', 'wenoz5', 'wenozp5' and 'mp5'), FP64 or
+// FP32-mixed: conserved -> primitive, the fifth-order face states, GLM
+// interface + HLL (or HLLD, HLLC) fluxes in every direction, flux
+// difference, psi damping and the SSPRK combination in one launch.
+//
+// FP32-mixed: FP32 storage, primitives, face states and fluxes; the
+// nonlinear weights of the five-cell values in FP64 (from the FP32 cells);
+// the energy's flux differences and update, the pressure recovery and the
+// small-value check in FP64 -- the split of the two-ghost-layer mixed stage.
 //
 // One 256-thread workgroup per block; thread t owns cell (i, j) = (t % 16,
 // t / 16) of a plane.  A plane's primitives with a 3-deep in-plane halo
@@ -42,21 +47,24 @@ __device__ __forceinline__ long cell5(const GridConst& G, int x, int y, int z = 
   return ((long)(G.ndim == 3 ? z + NG5 : 0) * G.pn + (y + NG5)) * G.pn + (x + NG5);
 }
 
-template <int NDIM, bool W1>
+template <int NDIM, class SP, bool W1>
 __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridConst G, Tables T, JobScalars J, const void* __restrict__ in,
                                                          const void* base, void* out, double wgt, PhysConst P,
                                                          DevStatus* st, double* __restrict__ part) {
+  using R = typename SP::R;
   // primitives of a plane, cell (a, c) of its two axes at (c + 3) * S5 + (a + 3);
   // once all faces of the plane are evaluated the same storage carries the
   // second axis' flux differences to the cells' owners, cell (a, c) at
   // c * NF5 + a
-  __shared__ double W[NV][P5 * S5];
-  __shared__ double Ex[NV][BN5];  // the 17th face of each line along the first axis
-  __shared__ double Ey[NV][BN5];  // the 17th face of each line along the second axis
+  __shared__ R W[NV][P5 * S5];
+  __shared__ R Ex[NV][BN5];  // the 17th face of each line along the first axis
+  __shared__ R Ey[NV][BN5];  // the 17th face of each line along the second axis
+  // mixed: the energy's second-axis differences on their way
+  __shared__ double De[std::is_same<typename SP::R, double>::value ? 1 : BN5 * NF5];
   const int b = T.order[blockIdx.x];
   const int t = threadIdx.x, i = t & 15, j = t >> 4;
   const long PC = G.pcells;
-  const void* own = block_ptr<StoreF64>(in, b, PC);
+  const void* own = block_ptr<SP>(in, b, PC);
   int lk[2 * NDIM], ln[2 * NDIM];
 #pragma unroll
   for (int f = 0; f < 2 * NDIM; ++f) {
@@ -78,7 +86,7 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
     else if (NDIM == 3 && z < 0) f = 4;
     else if (NDIM == 3 && z >= BN5) f = 5;
     if (f >= 0 && lk[f] == LINK_SAME) {
-      blk = block_ptr<StoreF64>(in, ln[f], PC);
+      blk = block_ptr<SP>(in, ln[f], PC);
       if (f == 0) xs += BN5;
       else if (f == 1) xs -= BN5;
       else if (f == 2) ys += BN5;
@@ -87,9 +95,10 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
       else zs -= BN5;
     }
     const long ci = cell5(G, xs, ys, zs);
-    double u[NV], w[NV];
+    double u[NV];
+    R w[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) u[q] = StoreF64::ld(blk, q, ci, PC);
+    for (int q = 0; q < NV; ++q) u[q] = SP::ld(blk, q, ci, PC);
     const int bb = cons_to_prim(u, w, P);
     if (bb) {
       bad |= bb;
@@ -112,28 +121,28 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
   // variable at a time, so each variable's six cells are read from LDS just
   // before use (a few live registers instead of all 54 values); the
   // arithmetic is that of the shared six-cell reconstruction.
-  auto face = [&](auto ax, auto dir, int line, int f, double lambda, double Fq[NV]) {
+  auto face = [&](auto ax, auto dir, int line, int f, double lambda, R Fq[NV]) {
     constexpr int AX = decltype(ax)::value;
     constexpr int D = decltype(dir)::value;
     auto at = [&](int s) {
       const int a = f - NG5 + s;
       return AX == 0 ? (line + NG5) * S5 + (a + NG5) : (a + NG5) * S5 + (line + NG5);
     };
-    double wl[NV], wr[NV];
+    R wl[NV], wr[NV];
     if (lim >= LIM_WENO5) {
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        const double v0 = W[q][at(0)], v1 = W[q][at(1)], v2 = W[q][at(2)];
-        const double v3 = W[q][at(3)], v4 = W[q][at(4)], v5 = W[q][at(5)];
+        const R v0 = W[q][at(0)], v1 = W[q][at(1)], v2 = W[q][at(2)];
+        const R v3 = W[q][at(3)], v4 = W[q][at(4)], v5 = W[q][at(5)];
         if (lim == LIM_MP5) {
-          wl[q] = mp5_face(v0, v1, v2, v3, v4);
-          wr[q] = mp5_face(v5, v4, v3, v2, v1);
+          wl[q] = mp5_face_r(v0, v1, v2, v3, v4);
+          wr[q] = mp5_face_r(v5, v4, v3, v2, v1);
         } else {
-          wl[q] = weno5_face(v0, v1, v2, v3, v4, lim, lambda);
-          wr[q] = weno5_face(v5, v4, v3, v2, v1, lim, lambda);
+          wl[q] = weno5_face_r(v0, v1, v2, v3, v4, lim, lambda);
+          wr[q] = weno5_face_r(v5, v4, v3, v2, v1, lim, lambda);
         }
       }
-      double cl[NV], cr[NV];
+      R cl[NV], cr[NV];
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
         cl[q] = W[q][at(2)];
@@ -141,7 +150,7 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
       }
       positivity_fallback(wl, wr, cl, cr);
     } else {
-      double c1[NV], c2[NV], c3[NV], c4[NV];
+      R c1[NV], c2[NV], c3[NV], c4[NV];
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
         c1[q] = W[q][at(1)];
@@ -151,7 +160,7 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
       }
       reconstruct_face(lim, c1, c2, c3, c4, wl, wr);
     }
-    face_flux_rt<D, double>(P.flux, wl, wr, ch, 0.5 / ch, P.gamma, P.inv_gm1, Fq);
+    face_flux_rt<D, R>(P.flux, wl, wr, (R)ch, (R)(0.5 / ch), (R)P.gamma, (R)P.inv_gm1, Fq);
   };
   using A0 = std::integral_constant<int, 0>;
   using A1 = std::integral_constant<int, 1>;
@@ -169,13 +178,18 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
   // second wave's (second axis), through LDS: no wave takes more than three
   // face evaluations.  d1 (first axis) and d2 (second axis) are the
   // differences F(f+1) - F(f) of cell (i, j).
+  // next - this of two face fluxes: at face precision, the energy's in FP64
+  auto diff = [&](int q, R next, R f) -> double {
+    return q == I_EN ? (double)next - (double)f : (double)(next - f);
+  };
+  constexpr bool kMixed = !std::is_same<R, double>::value;
   auto plane_differences = [&](auto first, auto dir2, double lam2, double d1[NV], double d2[NV]) {
     constexpr bool FIRST = decltype(first)::value;
-    double f1[NV], f2[NV];
+    R f1[NV], f2[NV];
     if constexpr (FIRST) face(A0{}, DX{}, j, i, lamx, f1);
     face(A1{}, dir2, j, i, lam2, f2);
     if ((FIRST && t < BN5) || (t >= 64 && t < 64 + BN5)) {
-      double fe[NV];
+      R fe[NV];
       if (t < BN5) {
         if constexpr (FIRST) {
           face(A0{}, DX{}, t, BN5, lamx, fe);
@@ -193,38 +207,62 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       if constexpr (FIRST) {
-        const double n1 = __shfl(f1[q], up, 64);
-        d1[q] = (i < BN5 - 1 ? n1 : Ex[q][j]) - f1[q];
+        const R n1 = __shfl(f1[q], up, 64);
+        d1[q] = diff(q, i < BN5 - 1 ? n1 : Ex[q][j], f1[q]);
       }
-      const double n2 = __shfl(f2[q], up, 64);
-      // second-axis difference of cell (j, i), handed to the thread that owns it
-      W[q][i * NF5 + j] = (i < BN5 - 1 ? n2 : Ey[q][j]) - f2[q];
+      const R n2 = __shfl(f2[q], up, 64);
+      // second-axis difference of cell (j, i), handed to the thread that owns
+      // it (the mixed energy's through a double array)
+      const double dd = diff(q, i < BN5 - 1 ? n2 : Ey[q][j], f2[q]);
+      if (kMixed && q == I_EN)
+        De[i * NF5 + j] = dd;
+      else
+        W[q][i * NF5 + j] = (R)dd;
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NV; ++q) d2[q] = W[q][j * NF5 + i];
+    for (int q = 0; q < NV; ++q) d2[q] = (kMixed && q == I_EN) ? De[j * NF5 + i] : (double)W[q][j * NF5 + i];
+  };
+  // L + d / dx at face precision (the energy in FP64)
+  auto accum = [&](int q, double Lq, double d, double id) -> double {
+    if (!kMixed || q == I_EN) return Lq + d * id;
+    return (double)((R)Lq + (R)d * (R)id);
   };
   using Yes = std::integral_constant<bool, true>;
   using No = std::integral_constant<bool, false>;
 
   // update of cell (x, y, z): L = -(sum_d dF_d / dx_d) - kappa psi; SSPRK combination
   const double dt = J.dt_scale * J.dt[job], kappa = J.kappa[job];
-  void* o = block_ptr<StoreF64>(out, b, PC);
-  const void* bs = block_ptr<StoreF64>(base, b, PC);
+  void* o = block_ptr<SP>(out, b, PC);
+  const void* bs = block_ptr<SP>(base, b, PC);
+  // (the energy in FP64, the rest at face precision)
   auto update = [&](int x, int y, int z, const double L[NV]) {
     const long c = cell5(G, x, y, z);
-    const double psi = StoreF64::ld(own, I_PSI, c, PC);
+    const double psi = SP::ld(own, I_PSI, c, PC);
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      double lq = -L[q];
-      if (q == I_PSI) lq = lq - kappa * psi;
-      const double tq = StoreF64::ld(own, q, c, PC) + dt * lq;
-      if (W1) {
-        StoreF64::st(o, q, c, PC, tq);
+      const double uq = SP::ld(own, q, c, PC);
+      double res;
+      if (q == I_EN) {
+        const double tq = uq + dt * (-L[q]);
+        if (W1) {
+          res = tq;
+        } else {
+          const double u0 = SP::ld(bs, q, c, PC);
+          res = u0 + wgt * (tq - u0);
+        }
       } else {
-        const double u0 = StoreF64::ld(bs, q, c, PC);
-        StoreF64::st(o, q, c, PC, u0 + wgt * (tq - u0));
+        R lq = -(R)L[q];
+        if (q == I_PSI) lq = lq - (R)kappa * (R)psi;
+        const R tq = (R)uq + (R)dt * lq;
+        if (W1) {
+          res = (double)tq;
+        } else {
+          const R u0 = (R)SP::ld(bs, q, c, PC);
+          res = (double)(u0 + (R)wgt * (tq - u0));
+        }
       }
+      SP::st(o, q, c, PC, res);
     }
   };
   // the 192 in-plane halo cells of an x-y plane z: 48 per side, 3 layers of 16
@@ -252,8 +290,8 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       L[q] = 0.0;
-      L[q] = L[q] + d1[q] * idx;
-      L[q] = L[q] + d2[q] * idy;
+      L[q] = accum(q, L[q], d1[q], idx);
+      L[q] = accum(q, L[q], d2[q], idy);
     }
     update(i, j, 0, L);
   } else {
@@ -270,8 +308,8 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
         double L = 0.0;
-        L = L + d1[q] * idx;
-        L = L + d2[q] * idy;
+        L = accum(q, L, d1[q], idx);
+        L = accum(q, L, d2[q], idy);
         pb[q * (BN5 * BN5 * BN5) + ci] = L;
       }
       __syncthreads();  // the plane's LDS is read before the next plane loads
@@ -293,7 +331,7 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
         L[q] = pb[q * (BN5 * BN5 * BN5) + ci];
-        L[q] = L[q] + d2[q] * idz;
+        L[q] = accum(q, L[q], d2[q], idz);
       }
       update(i, y, j, L);
       __syncthreads();
@@ -308,20 +346,31 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
 hipError_t launch_fused5_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J, const void* in,
                                const void* base, void* out, double w, const PhysConst& P, DevStatus* st,
                                double* part) {
-  if (G.nx != BN5 || G.ng != NG5 || G.precision != 0) return hipErrorInvalidValue;
+  if (G.nx != BN5 || G.ng != NG5) return hipErrorInvalidValue;
   if (G.ndim == 3 && !part) return hipErrorInvalidValue;
   if (T.nactive <= 0) return hipSuccess;
-  if (G.ndim == 3) {
-    if (w == 1.0)
-      k_stage_fused5<3, true><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, part);
+#define AMRVAC_F5(ND, SPT, W1) \
+  k_stage_fused5<ND, SPT, W1><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, ND == 3 ? part : nullptr)
+#define AMRVAC_F5_W(ND, SPT)    \
+  do {                          \
+    if (w == 1.0)               \
+      AMRVAC_F5(ND, SPT, true); \
+    else                        \
+      AMRVAC_F5(ND, SPT, false); \
+  } while (0)
+  if (G.precision == 0) {
+    if (G.ndim == 3)
+      AMRVAC_F5_W(3, StoreF64);
     else
-      k_stage_fused5<3, false><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, part);
+      AMRVAC_F5_W(2, StoreF64);
   } else {
-    if (w == 1.0)
-      k_stage_fused5<2, true><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, nullptr);
+    if (G.ndim == 3)
+      AMRVAC_F5_W(3, StoreMixed);
     else
-      k_stage_fused5<2, false><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, nullptr);
+      AMRVAC_F5_W(2, StoreMixed);
   }
+#undef AMRVAC_F5_W
+#undef AMRVAC_F5
   return hipGetLastError();
 }
 

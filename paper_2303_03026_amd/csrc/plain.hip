@@ -473,11 +473,12 @@ __device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const vo
     for (int q = 0; q < NV; ++q) u[q] = SP::ld(S, q, c, G.pcells);
     (void)cons_to_prim(u, w, P);
   };
-  if constexpr (SIX && SP::kBytesPerCell == 72) {
+  if constexpr (SIX) {
     if (G.ng == 3) {
-      // the fused path with three ghost layers (2D FP64): the six-cell
-      // stencil and face states of the per-kernel path's flux kernel
-      double c6[6][NV];
+      // the fused path with three ghost layers: the six-cell stencil and
+      // face states of the fused five-cell stage (primitives at face
+      // precision, FP64 weights)
+      R c6[6][NV];
 #pragma unroll
       for (int s = 0; s < 6; ++s) cell(f - 3 + s, c6[s]);
       const double lambda = P.limiter == LIM_WENOZP5 ? 1.0 / cbrt(inv_dx[3 * blk + D] * inv_dx[3 * blk + D]) : 0.0;

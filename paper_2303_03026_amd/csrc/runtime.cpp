@@ -106,8 +106,8 @@ int check_desc(const amrvac_grid_desc* g, std::string* why) {
     return AMRVAC_E_ARG;
   }
   if (g->flux < AMRVAC_FLUX_HLL || g->flux > AMRVAC_FLUX_HLLC) { *why = "bad flux scheme"; return AMRVAC_E_ARG; }
-  if (g->precision == AMRVAC_FP32_MIXED && (g->block_nx != 16 || g->nghost != 2)) {
-    *why = "FP32-mixed storage runs on the fused path, which needs block_nx = 16 and nghost = 2";
+  if (g->precision == AMRVAC_FP32_MIXED && g->block_nx != 16) {
+    *why = "FP32-mixed storage runs on the fused path, which needs block_nx = 16";
     return AMRVAC_E_ARG;
   }
   return AMRVAC_OK;
@@ -1414,8 +1414,8 @@ int amrvac_set_path(amrvac_ctx* c, int path) {
   if (!c) return AMRVAC_E_ARG;
   if (path != AMRVAC_PATH_PLAIN && path != AMRVAC_PATH_FUSED) return fail(c, AMRVAC_E_ARG, "unknown path");
   if (path == AMRVAC_PATH_FUSED && c->G.nx != 16) return fail(c, AMRVAC_E_ARG, "the fused path needs block_nx = 16");
-  if (path == AMRVAC_PATH_FUSED && c->G.ng != 2 && !(c->G.ng == 3 && c->g.precision == AMRVAC_FP64))
-    return fail(c, AMRVAC_E_ARG, "the fused path needs nghost = 2 (3 only in FP64)");
+  if (path == AMRVAC_PATH_FUSED && c->G.ng != 2 && c->G.ng != 3)
+    return fail(c, AMRVAC_E_ARG, "the fused path needs nghost = 2 or 3");
   if (path == AMRVAC_PATH_PLAIN && (c->g.precision != AMRVAC_FP64 || c->batch))
     return fail(c, AMRVAC_E_ARG, "the plain path is for single-job FP64 contexts");
   c->path = path;
@@ -1588,8 +1588,8 @@ int amrvac_batch_create(amrvac_ctx** out, const amrvac_grid_desc* shape, int cap
   *out = nullptr;
   std::string why;
   if (check_desc(shape, &why) != AMRVAC_OK) { g_init_err = why; return AMRVAC_E_ARG; }
-  if (shape->block_nx != 16 || (shape->nghost != 2 && !(shape->nghost == 3 && shape->precision == AMRVAC_FP64))) {
-    g_init_err = "batch contexts run the fused path: block_nx must be 16 and nghost 2 (3 in FP64)";
+  if (shape->block_nx != 16) {
+    g_init_err = "batch contexts run the fused path: block_nx must be 16";
     return AMRVAC_E_ARG;
   }
   if (capacity_blocks < 1 || max_jobs < 1 || nstages < 2 || nstages > 5 || !slots) {

@@ -2,7 +2,7 @@
 pool, advanced together with per-job dt; each job's result is the same alone
 and in the mix (bit for bit: no arithmetic couples jobs), and matches the
 CPU oracle (FP64 jobs to the bars of tests/parity.py, FP32-mixed jobs to
-the bounds of tests/mixed_error.py).  FP64 pools also take the five-cell
+the bounds of tests/mixed_error.py).  Pools also take the five-cell
 reconstructions on three ghost layers."""
 import dataclasses
 
@@ -93,14 +93,15 @@ def weno(w, lim=6, flux=2):
     return w
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 @pytest.mark.parametrize("ndim", [2, 3])
-def test_five_cell_jobs_alone_equal_in_mix(amr, orc, ndim):
-    """FP64 pools with three ghost layers ('wenozp5' + HLLC): the fused
-    five-cell stage over every resident job's blocks; each job equals its
-    single-job run bit for bit and meets the FP64 bars with the oracle's
-    roundoff floor."""
+def test_five_cell_jobs_alone_equal_in_mix(amr, orc, ndim, precision):
+    """Pools with three ghost layers ('wenozp5' + HLLC): the fused five-cell
+    stage over every resident job's blocks; each job equals its single-job
+    run bit for bit and meets the FP64 bars with the oracle's roundoff floor,
+    or the FP32-mixed five-cell bounds of test_gpu_fused5.py."""
     shape = weno(inputs.random_modes(32, ndim, seed=0))
-    batch = amr.Batch(shape, capacity_blocks=300 if ndim == 3 else 400, max_jobs=8)
+    batch = amr.Batch(shape, capacity_blocks=300 if ndim == 3 else 400, max_jobs=8, precision=precision)
     if ndim == 3:
         makes = [lambda: weno(inputs.random_modes(32, 3, seed=31, nsteps=5)),
                  lambda: weno(inputs.random_modes(48, 3, seed=32, nsteps=3)),
@@ -118,10 +119,18 @@ def test_five_cell_jobs_alone_equal_in_mix(amr, orc, ndim):
     batch.sync_flags()
     batch.close()
     for w, got in zip(ws, outs):
-        assert np.array_equal(got, alone(amr, w, w.nsteps, 0)), w.name
+        assert np.array_equal(got, alone(amr, w, w.nsteps, precision)), w.name
     for make, w, got in zip(makes, ws, outs):
-        ref, f1, fi = parity.oracle_floor(orc, make)
-        parity.check(w, got, ref, "served five-cell %s" % w.name, f1, fi)
+        if precision == 0:
+            ref, f1, fi = parity.oracle_floor(orc, make)
+            parity.check(w, got, ref, "served five-cell %s" % w.name, f1, fi)
+        else:
+            ref, _ = orc.run(w)
+            l1, linf = mixed_error.errors(w, got, ref)
+            b1, bi = np.full(9, 1e-6), np.full(9, 3e-6)
+            if w.name.startswith("smooth_amr"):
+                b1[8], bi[8] = 4e-5, 6e-4
+            mixed_error.check("served five-cell mixed %s" % w.name, l1, linf, b1, bi)
 
 
 def test_admission_by_pool_room_and_reuse(amr):

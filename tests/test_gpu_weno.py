@@ -1,10 +1,8 @@
 """Fifth-order reconstructions on 3 ghost layers ('weno5': Jiang-Shu weights,
 'wenoz5': Borges et al.'s WENO-Z weights, 'wenozp5': Acker et al.'s WENO-Z+
 weights, 'mp5': Suresh and Huynh's monotonicity-preserving scheme), on the
-plain FP64 path, against the FP64 oracle.  The mixed-precision path and
-FP32-mixed batch pools are built for 2 ghost layers and must refuse such a
-grid (the fused path and FP64 batch pools with 3 layers have their own
-tests)."""
+plain FP64 path, against the FP64 oracle (the fused path, FP32-mixed and
+batch pools with 3 layers have their own tests)."""
 import numpy as np
 import pytest
 
@@ -129,12 +127,12 @@ def test_three_ghost_layers_change_nothing_for_van_leer(amr):
     assert np.array_equal(outs[0], outs[1])
 
 
-def test_two_layer_paths_refuse_three_ghost_layers(amr):
+def test_plain_path_refuses_mixed_and_five_cells_need_three_layers(amr):
     w = weno(inputs.random_modes(32, 3, seed=67), 3)
+    sim = amr.Simulation(w, path=amr.PATH_FUSED, precision=amr.FP32_MIXED)
     with pytest.raises(amr.AmrvacError):
-        amr.Simulation(w, path=amr.PATH_PLAIN, precision=amr.FP32_MIXED)
-    with pytest.raises(amr.AmrvacError):
-        amr.Batch(w, capacity_blocks=16, max_jobs=2, nstages=3, precision=amr.FP32_MIXED)
+        sim.set_path(amr.PATH_PLAIN)  # the per-kernel path is FP64 only
+    sim.close()
     w2 = inputs.random_modes(32, 3, seed=67)
     w2.limiter = 3  # WENO on 2 ghost layers: the stencil does not fit
     with pytest.raises(amr.AmrvacError):
