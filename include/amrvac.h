@@ -182,8 +182,9 @@ int amrvac_stage(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double
  * out_slot skips its pass over the state: the usual last stage of an SSPRK
  * step.  The held rate is dropped when anything else writes out_slot, when
  * amrvac_cfl_dt runs on another slot or when the block tables change.  On
- * the plain path and on grids with coarse/fine flux corrections (which
- * change the output after the stage) it is exactly amrvac_stage. */
+ * grids with coarse/fine flux corrections (which change the coarse cells
+ * next to finer leaves after the stage) those cells are folded in after the
+ * correction.  On the plain path it is exactly amrvac_stage. */
 int amrvac_stage_cfl(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double w,
                      const double* dt_dev, const double* ch_dev, const double* kappa_dev);
 

@@ -47,10 +47,19 @@ __device__ __forceinline__ long cell5(const GridConst& G, int x, int y, int z = 
   return ((long)(G.ndim == 3 ? z + NG5 : 0) * G.pn + (y + NG5)) * G.pn + (x + NG5);
 }
 
-template <int NDIM, class SP, bool W1>
+// REG: the instantiation for grids with a coarse/fine flux correction; the
+// face fluxes evaluated on block faces towards finer or coarser leaves are
+// stored in the flux registers freg ([block][face][var][face cell], face cell
+// t1 + 16 t2 with t1 along the face's first transverse axis: y for x faces,
+// x otherwise) for the correction pass.
+// CFL: also fold the CFL rate of every output cell into the job's running
+// maximum (C.rate_bits, C.nan), leaving out the cells next to faces towards
+// finer leaves when C.skip_fine (the flux correction changes them later).
+template <int NDIM, class SP, bool W1, bool REG, bool CFL>
 __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridConst G, Tables T, JobScalars J, const void* __restrict__ in,
                                                          const void* base, void* out, double wgt, PhysConst P,
-                                                         DevStatus* st, double* __restrict__ part) {
+                                                         DevStatus* st, double* __restrict__ part,
+                                                         typename SP::R* __restrict__ freg, JobCfl C) {
   using R = typename SP::R;
   // primitives of a plane, cell (a, c) of its two axes at (c + 3) * S5 + (a + 3);
   // once all faces of the plane are evaluated the same storage carries the
@@ -108,6 +117,29 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
     for (int q = 0; q < NV; ++q) W[q][(c + NG5) * S5 + (a + NG5)] = w[q];
   };
 
+  // faces with flux registers (bit f: block face f)
+  constexpr int NFC = NDIM == 3 ? BN5 * BN5 : BN5;
+  unsigned regs = 0, skips = 0;
+  if constexpr (REG) {
+#pragma unroll
+    for (int f = 0; f < 2 * NDIM; ++f)
+      if (lk[f] == LINK_FINE || lk[f] == LINK_COARSE) regs |= 1u << f;
+  }
+  if constexpr (CFL) {
+#pragma unroll
+    for (int f = 0; f < 2 * NDIM; ++f)
+      if (C.skip_fine && lk[f] == LINK_FINE) skips |= 1u << f;
+  }
+  double rmax = 0.0;  // CFL: running max of this thread's output cells
+  int rnan = 0;
+  // store the NV fluxes of one face cell (the address is formed here: the
+  // empty asm keeps the compiler from hoisting it out of the plane loops)
+  auto put_reg = [&](int f, int cell, const R Fv[NV]) {
+    R* p = freg + ((long)b * 6 + f) * NV * NFC + cell;
+    asm volatile("" : "+v"(p));
+#pragma unroll
+    for (int q = 0; q < NV; ++q) p[q * NFC] = Fv[q];
+  };
   const int job = T.job[b];
   const double ch = J.ch[job];
   const double idx = T.inv_dx[3 * b], idy = T.inv_dx[3 * b + 1], idz = T.inv_dx[3 * b + 2];
@@ -183,11 +215,18 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
     return q == I_EN ? (double)next - (double)f : (double)(next - f);
   };
   constexpr bool kMixed = !std::is_same<R, double>::value;
-  auto plane_differences = [&](auto first, auto dir2, double lam2, double d1[NV], double d2[NV]) {
+  // pl: the plane's index along its normal (register cells pl * 16 + line)
+  auto plane_differences = [&](auto first, auto dir2, double lam2, int pl, double d1[NV], double d2[NV]) {
     constexpr bool FIRST = decltype(first)::value;
+    constexpr int D2 = decltype(dir2)::value;
+    const int rofs = NDIM == 3 ? pl * BN5 : 0;
     R f1[NV], f2[NV];
-    if constexpr (FIRST) face(A0{}, DX{}, j, i, lamx, f1);
+    if constexpr (FIRST) {
+      face(A0{}, DX{}, j, i, lamx, f1);
+      if (REG && (regs & 1u) && i == 0) put_reg(0, rofs + j, f1);
+    }
     face(A1{}, dir2, j, i, lam2, f2);
+    if (REG && (regs & (1u << (2 * D2))) && i == 0) put_reg(2 * D2, rofs + j, f2);
     if ((FIRST && t < BN5) || (t >= 64 && t < 64 + BN5)) {
       R fe[NV];
       if (t < BN5) {
@@ -195,11 +234,13 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
           face(A0{}, DX{}, t, BN5, lamx, fe);
 #pragma unroll
           for (int q = 0; q < NV; ++q) Ex[q][t] = fe[q];
+          if (REG && (regs & 2u)) put_reg(1, rofs + t, fe);
         }
       } else {
         face(A1{}, dir2, t - 64, BN5, lam2, fe);
 #pragma unroll
         for (int q = 0; q < NV; ++q) Ey[q][t - 64] = fe[q];
+        if (REG && (regs & (2u << (2 * D2)))) put_reg(2 * D2 + 1, rofs + t - 64, fe);
       }
     }
     __syncthreads();  // every face evaluated: W is free, Ex / Ey written
@@ -239,6 +280,7 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
   auto update = [&](int x, int y, int z, const double L[NV]) {
     const long c = cell5(G, x, y, z);
     const double psi = SP::ld(own, I_PSI, c, PC);
+    double un[NV];  // CFL: the output cell as a later load would see it
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       const double uq = SP::ld(own, q, c, PC);
@@ -263,6 +305,19 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
         }
       }
       SP::st(o, q, c, PC, res);
+      if (CFL) un[q] = SP::as_stored(q, res);
+    }
+    if (CFL) {
+      const unsigned cell_faces = (x == 0 ? 1u : 0u) | (x == BN5 - 1 ? 2u : 0u) | (y == 0 ? 4u : 0u) |
+                                  (y == BN5 - 1 ? 8u : 0u) | (NDIM == 3 && z == 0 ? 16u : 0u) |
+                                  (NDIM == 3 && z == BN5 - 1 ? 32u : 0u);
+      if (!(cell_faces & skips)) {
+        const double rate = cell_rate<NDIM>(un, P, idx, idy, idz, bad);
+        if (isnan(rate))
+          rnan = 1;
+        else
+          rmax = fmax(rmax, rate);
+      }
     }
   };
   // the 192 in-plane halo cells of an x-y plane z: 48 per side, 3 layers of 16
@@ -286,7 +341,7 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
     fetch_xy_halo(0, true);
     __syncthreads();
     double d1[NV], d2[NV], L[NV];
-    plane_differences(Yes{}, DY{}, lamy, d1, d2);
+    plane_differences(Yes{}, DY{}, lamy, 0, d1, d2);
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       L[q] = 0.0;
@@ -303,7 +358,7 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
       fetch_xy_halo(k, false);
       __syncthreads();
       double d1[NV], d2[NV];
-      plane_differences(Yes{}, DY{}, lamy, d1, d2);
+      plane_differences(Yes{}, DY{}, lamy, k, d1, d2);
       const int ci = (k * BN5 + j) * BN5 + i;
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
@@ -326,7 +381,7 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
       }
       __syncthreads();
       double d1[NV], d2[NV], L[NV];
-      plane_differences(No{}, DZ{}, lamz, d1, d2);
+      plane_differences(No{}, DZ{}, lamz, y, d1, d2);
       const int ci = (j * BN5 + y) * BN5 + i;
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
@@ -337,6 +392,27 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
       __syncthreads();
     }
   }
+  if (CFL) {
+    // workgroup max (wave max, then over the four waves in LDS), one atomic
+    // per workgroup on the job's word (non-negative doubles order as their
+    // bit patterns)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+    __shared__ double wmax[4];
+    __shared__ int wnan[4];
+    const int lane = t & 63, wave = t >> 6;
+    const int anynan = __any(rnan);
+    if (lane == 0) {
+      wmax[wave] = rmax;
+      wnan[wave] = anynan;
+    }
+    __syncthreads();
+    if (t == 0) {
+      const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+      atomicMax(&C.rate_bits[job], (unsigned long long)__double_as_longlong(m));
+      if (wnan[0] | wnan[1] | wnan[2] | wnan[3]) atomicOr(&C.nan[job], 1u);
+    }
+  }
   if (bad) atomicOr(&st->flags, (unsigned)bad);
   if (nfix) atomicAdd(&st->nfix, (unsigned long long)nfix);
 }
@@ -345,12 +421,29 @@ __global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridCon
 
 hipError_t launch_fused5_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J, const void* in,
                                const void* base, void* out, double w, const PhysConst& P, DevStatus* st,
-                               double* part) {
+                               double* part, void* freg, const JobCfl* cfl) {
   if (G.nx != BN5 || G.ng != NG5) return hipErrorInvalidValue;
   if (G.ndim == 3 && !part) return hipErrorInvalidValue;
   if (T.nactive <= 0) return hipSuccess;
-#define AMRVAC_F5(ND, SPT, W1) \
-  k_stage_fused5<ND, SPT, W1><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, ND == 3 ? part : nullptr)
+  const JobCfl C = cfl ? *cfl : JobCfl{};
+  double* const pt = G.ndim == 3 ? part : nullptr;
+#define AMRVAC_F5_K(ND, SPT, W1, RG, CF)                                                                        \
+  k_stage_fused5<ND, SPT, W1, RG, CF><<<T.nactive, 256, 0, s>>>(G, T, J, in, base, out, w, P, st, pt,            \
+                                                                 static_cast<SPT::R*>(freg), C)
+#define AMRVAC_F5(ND, SPT, W1)                    \
+  do {                                            \
+    if (freg) {                                   \
+      if (cfl)                                    \
+        AMRVAC_F5_K(ND, SPT, W1, true, true);     \
+      else                                        \
+        AMRVAC_F5_K(ND, SPT, W1, true, false);    \
+    } else {                                      \
+      if (cfl)                                    \
+        AMRVAC_F5_K(ND, SPT, W1, false, true);    \
+      else                                        \
+        AMRVAC_F5_K(ND, SPT, W1, false, false);   \
+    }                                             \
+  } while (0)
 #define AMRVAC_F5_W(ND, SPT)    \
   do {                          \
     if (w == 1.0)               \
@@ -371,6 +464,7 @@ hipError_t launch_fused5_stage(hipStream_t s, const GridConst& G, const Tables& 
   }
 #undef AMRVAC_F5_W
 #undef AMRVAC_F5
+#undef AMRVAC_F5_K
   return hipGetLastError();
 }
 

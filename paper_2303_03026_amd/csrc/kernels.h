@@ -110,11 +110,12 @@ struct FusedTune {
 // cfl (may be null): also fold each job's CFL rate of the output interior
 // into cfl->rate_bits / cfl->nan (as launch_cfl_accumulate would from out).
 // The fused stage of blocks with three ghost layers (the five-cell
-// reconstructions), FP64; no CFL folding.  part: 3D only, nb x NV x nx^3
-// doubles of scratch for the in-plane flux differences.
+// reconstructions), FP64 or FP32-mixed.  part: 3D only, nb x NV x nx^3
+// doubles of scratch for the in-plane flux differences.  freg and cfl (may
+// be null): flux registers and CFL folding as for launch_fused_stage.
 hipError_t launch_fused5_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J, const void* in,
                                const void* base, void* out, double w, const PhysConst& P, DevStatus* st,
-                               double* part);
+                               double* part, void* freg, const JobCfl* cfl);
 // freg (may be null): flux registers, [cap][6 faces][NV][face cells] in the
 // face precision (face cells nx^2 in 3D, nx in 2D, transverse index t1 + nx
 // t2 with t1 along the face's first transverse axis: y for x faces, x
@@ -126,8 +127,7 @@ hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T
 // Coarse/fine flux correction of out.  tasks: (block, face) pairs grouped by
 // direction; direction d's are pairs first[d] .. first[d] + count[d] - 1
 // (host arrays).  With freg (the registers the fused stage filled) the
-// fluxes are read from there; without (three ghost layers) they are
-// evaluated again from in.
+// fluxes are read from there; without they are evaluated again from in.
 hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                                  const int* tasks, const int first[3], const int count[3], const void* in,
                                  void* out, double w, const PhysConst& P, const void* freg);

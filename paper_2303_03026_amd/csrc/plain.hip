@@ -695,14 +695,18 @@ __global__ void __launch_bounds__(256) k_cfl_reflux_cells(GridConst G, Tables T,
     else
       rate = r;
   }
-  if (nfc % 64 == 0) {
-    // a wave lies in one task, so in one job: wave max, one atomic
+  // when every live lane of the wave is in one job (always in a single-job
+  // context; in batch pools unless a wave spans two jobs' tasks): wave max,
+  // one atomic; else one atomic per lane.  Lane 0 is live whenever any lane
+  // is (live lanes come first).
+  const int jw = __shfl(job, 0, 64);
+  if (__all(!live || job == jw)) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) rate = fmax(rate, __shfl_xor(rate, off, 64));
     const int anynan = __any(nan_seen);
     if (live && (threadIdx.x & 63) == 0) {
-      atomicMax(&C.rate_bits[job], (unsigned long long)__double_as_longlong(rate));
-      if (anynan) atomicOr(&C.nan[job], 1u);
+      atomicMax(&C.rate_bits[jw], (unsigned long long)__double_as_longlong(rate));
+      if (anynan) atomicOr(&C.nan[jw], 1u);
     }
   } else if (live) {
     atomicMax(&C.rate_bits[job], (unsigned long long)__double_as_longlong(rate));

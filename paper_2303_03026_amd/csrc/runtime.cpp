@@ -773,12 +773,12 @@ JobCfl cfl_state(amrvac_ctx* c, double* dt, double* ch, double* kappa) {
 // where nothing changes that output afterwards: with coarse/fine flux
 // correction the stage leaves out the cells next to faces towards finer
 // leaves, and a pass after the correction folds those in.
-bool can_carry(const amrvac_ctx* c) { return c->path == AMRVAC_PATH_FUSED && c->G.ng == 2; }
+bool can_carry(const amrvac_ctx* c) { return c->path == AMRVAC_PATH_FUSED; }
 
-// flux registers for the fused stage of two ghost layers, when a coarse/fine
-// correction follows it (else null: the correction evaluates its fluxes)
+// flux registers for the fused stage, when a coarse/fine correction follows
+// it (else null)
 void* stage_freg(const amrvac_ctx* c) {
-  return c->path == AMRVAC_PATH_FUSED && c->G.ng == 2 && c->n_trefl > 0 ? c->d_freg : nullptr;
+  return c->path == AMRVAC_PATH_FUSED && c->n_trefl > 0 ? c->d_freg : nullptr;
 }
 
 int clear_if_dirty(amrvac_ctx* c) {
@@ -838,7 +838,7 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
     }
     if (c->G.ng == 3)
       HIP_TRY(c, launch_fused5_stage(c->stream, c->G, T, J, c->slots[in], c->slots[base], c->slots[out], w, c->P,
-                                     c->d_status, c->d_part));
+                                     c->d_status, c->d_part, freg, fold ? &C : nullptr));
     else
       HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->tune, c->slots[in], c->slots[base], c->slots[out], w,
                                     c->P, c->d_status, fold ? &C : nullptr, freg));
@@ -921,20 +921,20 @@ int slots_for_stages(int nstages) { return nstages >= 5 ? 4 : (nstages >= 3 ? 3 
 
 // The plain (per-kernel) FP64 path's primitive and face-flux scratch, the
 // 3D five-cell fused stage's array of in-plane flux differences, and the
-// flux registers of the fused path of two ghost layers on grids with
-// coarse/fine flux correction (110 KB per 16^3 block in FP64), allocated on
+// flux registers of the fused path on grids with coarse/fine flux
+// correction (110 KB per 16^3 block in FP64), allocated on
 // first use of their path: a context that only runs the fused path on a
 // uniform grid holds none of them (the plain scratch for 4096 blocks of
 // 16^3 is 6 GB, the difference array 1.2 GB).  Called by the entry points
 // before they enqueue work, so never inside a graph capture.
 int ensure_plain_scratch(amrvac_ctx* c) {
-  if (c->path == AMRVAC_PATH_FUSED && c->G.ng == 2 && c->n_trefl > 0 && !c->d_freg) {
+  if (c->path == AMRVAC_PATH_FUSED && c->n_trefl > 0 && !c->d_freg) {
     const size_t nfc = c->G.ndim == 3 ? (size_t)c->G.nx * c->G.nx : (size_t)c->G.nx;
     const size_t rbytes = c->G.precision == 0 ? sizeof(double) : sizeof(float);
-    return dev_alloc(c, &c->d_freg, (size_t)c->cap * 6 * NV * nfc * rbytes);
+    if (int rc = dev_alloc(c, &c->d_freg, (size_t)c->cap * 6 * NV * nfc * rbytes)) return rc;
   }
   if (c->path == AMRVAC_PATH_FUSED && c->G.ng == 3 && c->G.ndim == 3 && !c->d_part)
-    return dev_alloc(c, (void**)&c->d_part, (size_t)c->cap * NV * c->G.icells * sizeof(double));
+    if (int rc = dev_alloc(c, (void**)&c->d_part, (size_t)c->cap * NV * c->G.icells * sizeof(double))) return rc;
   if (c->path != AMRVAC_PATH_PLAIN || c->d_prim) return AMRVAC_OK;
   const size_t nb = (size_t)c->cap;
   const size_t pcs = nb * NV * c->G.pcells * sizeof(double);
