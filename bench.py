@@ -173,19 +173,24 @@ def make_workload(name, n=256, levels=6):
 
 
 def roofline(avg_ms, bytes_per_launch, counters, kernel):
-    """Roofline of the stage kernel: algorithmic HBM bytes per launch over
-    the live average launch time against the 8 TB/s peak; beside it the
-    counter traffic and the VALU issue fraction from the committed profile
-    for this launch shape (null without one)."""
+    """Roofline of the stage kernel over its live average launch time.  With
+    the committed counter profile for these kernel sources and this launch
+    shape, the bound is the VALU issue rate ("alu": VALU wave-instructions
+    per launch from the profile over the launch time, against the 614.4 G/s
+    issue peak), which is what limits the stage; the HBM view (algorithmic
+    bytes per launch against 8 TB/s, and the profile's counter traffic) is
+    kept beside it.  Without a matching profile only the HBM view exists."""
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic, valu = (None, None) if counters is None else counters
-    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
-            "traffic_frac": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "valu": None if valu is None else {
-                "wave_insts_per_launch": valu, "peak_wave_insts_per_s": VALU_PEAK_WAVE_INSTS,
-                "frac": valu / (avg_ms * 1e-3) / VALU_PEAK_WAVE_INSTS}}
+    hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": bytes_per_launch,
+           "traffic_frac": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if valu is None:
+        return dict(hbm, kernel=kernel, avg_launch_ms=avg_ms, valu=None)
+    rate = valu / (avg_ms * 1e-3)
+    return {"bound": "alu", "kernel": kernel, "achieved": rate, "peak": VALU_PEAK_WAVE_INSTS,
+            "unit": "VALU wave-instructions/s", "frac": rate / VALU_PEAK_WAVE_INSTS, "traffic": traffic,
+            "avg_launch_ms": avg_ms, "valu_wave_insts_per_launch": valu, "hbm": hbm}
 
 
 def time_grid(w, path, mixed, steps, warmup, tune_mode="auto", graph_pass=False, keep=False, label=None):
