@@ -111,7 +111,7 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other forms (plain FP64, FP32-mixed, current sheet, shock cloud, served)")
     ap.add_argument("--form-steps", type=int, default=20, help="timed steps of each other form")
-    ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the served form (0: none)")
+    ap.add_argument("--serve-jobs", type=int, default=2000, help="jobs of the served form (0: none)")
     ap.add_argument("--no-graph-pass", action="store_true")
     ap.add_argument("--sweep-shapes", action="store_true",
                     help="profiling helper: run one w=1 and one w<1 fused stage per launch shape, in the "
