@@ -124,13 +124,13 @@ hipError_t launch_fused5_stage(hipStream_t s, const GridConst& G, const Tables& 
 hipError_t launch_fused_stage(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
                               const FusedTune& tune, const void* in, const void* base, void* out, double w,
                               const PhysConst& P, DevStatus* st, const JobCfl* cfl, void* freg);
-// Coarse/fine flux correction of out.  tasks: (block, face) pairs grouped by
-// direction; direction d's are pairs first[d] .. first[d] + count[d] - 1
-// (host arrays).  With freg (the registers the fused stage filled) the
-// fluxes are read from there; without they are evaluated again from in.
-hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
-                                 const int* tasks, const int first[3], const int count[3], const void* in,
-                                 void* out, double w, const PhysConst& P, const void* freg);
+// Coarse/fine flux correction of out from the flux registers freg that the
+// fused stage filled.  tasks: (block, face) pairs grouped by direction;
+// direction d's are pairs first[d] .. first[d] + count[d] - 1 (host arrays).
+// hipErrorInvalidValue if there are tasks and freg is null.
+hipError_t launch_reflux_apply(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
+                               const int* tasks, const int first[3], const int count[3], void* out, double w,
+                               const void* freg);
 // After the correction of a stage that folded its CFL rate with
 // C.skip_fine: fold in the rates of the corrected cells (the coarse cells
 // next to each task's face).

@@ -453,155 +453,12 @@ __global__ void __launch_bounds__(256) k_update(GridConst G, Tables T, const dou
 
 // Flux correction after a fused stage, direction D only (so no two tasks
 // touch one cell): for each coarse cell next to finer leaves, replace the
-// coarse face flux used by the stage with the pairwise mean of the fine face
-// fluxes, i.e. out += w*dt*dL.  Both fluxes are recomputed from the stage
-// input (ghosts filled) exactly as the stage kernels compute them.
-template <int D, class SP, bool SIX>
-__device__ __forceinline__ void face_flux_from_slot(const GridConst& G, const void* __restrict__ S, int f, int t1,
-                                                    int t2, typename SP::R ch, typename SP::R hic,
-                                                    const PhysConst& P, const double* __restrict__ inv_dx, int blk,
-                                                    typename SP::R F[NV]) {
-  using R = typename SP::R;
-  R wl[NV], wr[NV];
-  auto cell = [&](int a, R w[NV]) {
-    long c;
-    if (D == 0) c = pidx(G, a, t1, t2);
-    else if (D == 1) c = pidx(G, t1, a, t2);
-    else c = pidx(G, t1, t2, a);
-    double u[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) u[q] = SP::ld(S, q, c, G.pcells);
-    (void)cons_to_prim(u, w, P);
-  };
-  if constexpr (SIX) {
-    if (G.ng == 3) {
-      // the fused path with three ghost layers: the six-cell stencil and
-      // face states of the fused five-cell stage (primitives at face
-      // precision, FP64 weights)
-      R c6[6][NV];
-#pragma unroll
-      for (int s = 0; s < 6; ++s) cell(f - 3 + s, c6[s]);
-      const double lambda = P.limiter == LIM_WENOZP5 ? 1.0 / cbrt(inv_dx[3 * blk + D] * inv_dx[3 * blk + D]) : 0.0;
-      reconstruct_face6(P.limiter, c6, lambda, wl, wr);
-      face_flux_rt<D, R>(P.flux, wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
-      return;
-    }
-  }
-  // otherwise two ghost layers: a four-cell stencil
-  R w4[4][NV];
-  if constexpr (D == 0 && SP::kBytesPerCell == 72) {
-    // x faces: the four cells of a variable are consecutive in one row, so
-    // two 16-byte loads fetch them (with 16 + 16 nx x-cells per padded row,
-    // a 16-byte slot lead and a 16-byte aligned slot, padded x index 0 or nx
-    // starts on 16 bytes)
-    const long c0 = pidx(G, f - 2, t1, t2);
-    double u4[4][NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const double2* p2 = reinterpret_cast<const double2*>(static_cast<const double*>(S) + q * G.pcells + c0);
-      const double2 a = p2[0], b = p2[1];
-      u4[0][q] = a.x;
-      u4[1][q] = a.y;
-      u4[2][q] = b.x;
-      u4[3][q] = b.y;
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) (void)cons_to_prim(u4[s], w4[s], P);
-  } else {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) cell(f - 2 + s, w4[s]);
-  }
-  reconstruct_face(P.limiter, w4[0], w4[1], w4[2], w4[3], wl, wr);
-  face_flux_rt<D, R>(P.flux, wl, wr, ch, hic, (R)P.gamma, (R)P.inv_gm1, F);
-}
-
-// The correction that evaluates its face fluxes again (three ghost layers,
-// where the stage keeps no flux registers): each (task, face cell) takes a
-// group of NS consecutive lanes, 4 in 2D (the coarse face, the two fine
-// faces, one idle lane) and 8 in 3D (the coarse face, the four fine faces,
-// three idle lanes).  Every lane evaluates one face flux, so a correction
-// costs one six-cell face evaluation of latency and registers rather than
-// three or five, and the group's first lane gathers the fine fluxes and
-// applies the update.
-template <int D, class SP, int NS, int NFINE, bool SIX>
-__global__ void __launch_bounds__(256) k_reflux_correct(GridConst G, Tables T, JobScalars J,
-                                                       const int* __restrict__ tasks, int ntasks,
-                                                       const void* __restrict__ in, void* out, double w,
-                                                       PhysConst P) {
-  static_assert((NS == 4 && NFINE == 2) || (NS == 8 && NFINE == 4), "2D: four lanes; 3D: eight");
-  const int* __restrict__ link = T.link;
-  using R = typename SP::R;
-  const int nx = G.nx;
-  const int per = G.ndim == 3 ? nx * nx : nx;
-  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  // groups are aligned to NS lanes and NS divides 64: a group leaves
-  // together and never straddles two waves
-  if (gid >= (long)ntasks * per * NS) return;
-  const long item = gid / NS;
-  const int sub = (int)(gid - item * NS);
-  const int task = (int)(item / per);
-  const int t = (int)(item - (long)task * per);
-  const int b = tasks[2 * task], face = tasks[2 * task + 1];
-  if ((face >> 1) != D) return;
-  const int side = face & 1;
-  const int* L = link + ((long)b * 6 + face) * LINK_INTS;
-  const int t1 = t % nx, t2 = G.ndim == 3 ? t / nx : 0;
-  const int job = T.job[b];
-  const R ch = (R)J.ch[job], hic = (R)(0.5 / J.ch[job]);
-  const long pc = G.pcells;
-  // fine face k = 2 e + a of the 2 x 2 (3D) or 2 x 1 (2D) behind this coarse face cell
-  auto fine_face = [&](int k, R Fo[NV]) {
-    const int a = k & 1, e = k >> 1;
-    const int g1 = 2 * t1 + a, g2 = 2 * t2 + e;
-    const int o1 = g1 >= nx ? 1 : 0, o2 = g2 >= nx ? 1 : 0;
-    const int fb = L[1 + (G.ndim == 3 ? o2 * 2 : 0) + o1];
-    face_flux_from_slot<D, SP, SIX>(G, block_ptr<SP>(in, fb, pc), side ? 0 : nx, g1 - o1 * nx,
-                               G.ndim == 3 ? g2 - o2 * nx : 0, ch, hic, P, T.inv_dx, fb, Fo);
-  };
-  R F[NV], v[NFINE][NV];
-  if (sub == 0) {
-    face_flux_from_slot<D, SP, SIX>(G, block_ptr<SP>(in, b, pc), side ? nx : 0, t1, t2, ch, hic, P, T.inv_dx, b, F);
-  } else if (sub <= NFINE) {
-    fine_face(sub - 1, F);
-  } else {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) F[q] = R(0);
-  }
-  // every lane of the group is active here
-  const int first = (int)(threadIdx.x & 63) - sub;
-#pragma unroll
-  for (int k = 0; k < NFINE; ++k)
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[k][q] = __shfl(F[q], first + 1 + k, 64);
-  if (sub != 0) return;
-  const double dt = J.dt_scale * J.dt[job];
-  R Ff[NV];
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    if constexpr (NFINE == 4)
-      Ff[q] = ((v[0][q] + v[1][q]) + (v[2][q] + v[3][q])) * R(0.25);
-    else
-      Ff[q] = (v[0][q] + v[1][q]) * R(0.5);
-  }
-  const int cell_d = side ? nx - 1 : 0;
-  long c;
-  if (D == 0) c = pidx(G, cell_d, t1, t2);
-  else if (D == 1) c = pidx(G, t1, cell_d, t2);
-  else c = pidx(G, t1, t2, cell_d);
-  const double idx = T.inv_dx[3 * b + D];
-  void* o = block_ptr<SP>(out, b, pc);
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const double df = (double)Ff[q] - (double)F[q];
-    const double dl = side ? -df * idx : df * idx;
-    SP::st(o, q, c, pc, SP::ld(o, q, c, pc) + w * dt * dl);
-  }
-}
-
-// The same correction from the flux registers the fused stage filled: one
-// thread per (task, coarse face cell) reads the coarse face flux and the
-// fluxes of the 2^(d-1) fine faces behind it (those fine blocks' registers
-// on the opposite face) and applies the same update in the same order.
+// coarse face flux the stage used with the pairwise mean of the fine face
+// fluxes, i.e. out += w*dt*dL.  The fluxes come from the flux registers the
+// fused stage filled as it evaluated those faces: one thread per (task,
+// coarse face cell) reads the coarse face flux and the fluxes of the
+// 2^(d-1) fine faces behind it (those fine blocks' registers on the
+// opposite face).
 template <int D, class SP, int NFINE>
 __global__ void __launch_bounds__(256) k_reflux_apply(GridConst G, Tables T, JobScalars J,
                                                      const int* __restrict__ tasks, int ntasks,
@@ -1128,29 +985,21 @@ hipError_t launch_reflux(hipStream_t s, const GridConst& G, const int* tasks, in
   return hipGetLastError();
 }
 
-hipError_t launch_reflux_correct(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
-                                 const int* tasks, const int first[3], const int count[3], const void* in,
-                                 void* out, double w, const PhysConst& P, const void* freg) {
+hipError_t launch_reflux_apply(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J,
+                               const int* tasks, const int first[3], const int count[3], void* out, double w,
+                               const void* freg) {
   // one launch per direction, in order: a coarse cell next to finer leaves
   // across faces of two directions is corrected once per direction
   const long per = G.ndim == 3 ? (long)G.nx * G.nx : G.nx;
+  if (!freg && (count[0] > 0 || count[1] > 0 || count[2] > 0)) return hipErrorInvalidValue;
 #define AMRVAC_REFLUX_LAUNCH(D, SPT)                                                                       \
   if (count[D] > 0) {                                                                                     \
-    if (freg && G.ndim == 3)                                                                              \
+    if (G.ndim == 3)                                                                                      \
       k_reflux_apply<D, SPT, 4><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(                         \
           G, T, J, tasks + 2 * first[D], count[D], static_cast<const SPT::R*>(freg), out, w);              \
-    else if (freg)                                                                                        \
+    else                                                                                                  \
       k_reflux_apply<D, SPT, 2><<<nblocks_for(count[D] * per, 256), 256, 0, s>>>(                         \
           G, T, J, tasks + 2 * first[D], count[D], static_cast<const SPT::R*>(freg), out, w);              \
-    else if (G.ndim == 3 && G.ng == 3)                                                                    \
-      k_reflux_correct<D, SPT, 8, 4, true><<<nblocks_for(count[D] * per * 8, 256), 256, 0, s>>>(          \
-          G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
-    else if (G.ndim == 3)                                                                                 \
-      k_reflux_correct<D, SPT, 8, 4, false><<<nblocks_for(count[D] * per * 8, 256), 256, 0, s>>>(         \
-          G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
-    else                                                                                                  \
-      k_reflux_correct<D, SPT, 4, 2, true><<<nblocks_for(count[D] * per * 4, 256), 256, 0, s>>>(          \
-          G, T, J, tasks + 2 * first[D], count[D], in, out, w, P);                                        \
   }
   if (G.precision == 0) {
     AMRVAC_REFLUX_LAUNCH(0, StoreF64);

@@ -842,8 +842,8 @@ int stage_any(amrvac_ctx* c, int in, int base, int out, double w, const JobScala
     else
       HIP_TRY(c, launch_fused_stage(c->stream, c->G, T, J, c->tune, c->slots[in], c->slots[base], c->slots[out], w,
                                     c->P, c->d_status, fold ? &C : nullptr, freg));
-    HIP_TRY(c, launch_reflux_correct(c->stream, c->G, T, J, c->d_trefl, c->refl_first, c->refl_count,
-                                     c->slots[in], c->slots[out], w, c->P, freg));
+    HIP_TRY(c, launch_reflux_apply(c->stream, c->G, T, J, c->d_trefl, c->refl_first, c->refl_count,
+                                   c->slots[out], w, freg));
     if (fold && corr)
       HIP_TRY(c, launch_cfl_reflux_cells(c->stream, c->G, T, c->d_trefl, c->n_trefl, c->slots[out], c->P,
                                          c->d_status, C));

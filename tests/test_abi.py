@@ -43,7 +43,13 @@ def test_slot_bytes(lib):
     g.precision = amrvac.FP32_MIXED
     assert lib.amrvac_slot_bytes(ctypes.byref(g), 16, ctypes.byref(n)) == 0
     assert n.value == 16 * 20 * 20 * 40
+    # three ghost layers (the five-cell reconstructions) in FP32-mixed too
     g.nghost = 3
+    assert lib.amrvac_slot_bytes(ctypes.byref(g), 16, ctypes.byref(n)) == 0
+    assert n.value == 16 * 22 * 22 * 40
+    # FP32-mixed runs on the fused path only, whose blocks are 16 cells wide
+    g.nghost = 2
+    g.block_nx = 8
     assert lib.amrvac_slot_bytes(ctypes.byref(g), 16, ctypes.byref(n)) == amrvac.E_ARG
 
 
