@@ -72,6 +72,44 @@ def oracle_floor(orc, make, nsteps=None):
     return ref, f1, fi
 
 
+def oracle_progress(orc, w, nsteps=None, fma=False, chunk=5, label=""):
+    """The oracle's conserved state after nsteps (default w.nsteps), advanced
+    in runs of chunk steps on one simulation (the same steps as one run),
+    printing a line after each run: the full-size grids take minutes."""
+    n = w.nsteps if nsteps is None else nsteps
+    sim = orc.OracleSim(w, None, fma=fma)
+    try:
+        done = 0
+        while done < n:
+            k = min(chunk, n - done)
+            sim.steps(k)
+            done += k
+            print("oracle%s %s: %d/%d steps" % (" (contracted)" if fma else "", label, done, n), flush=True)
+        return sim.cons()
+    finally:
+        sim.close()
+
+
+def over_fixed_bars(w, gpu, ref):
+    """True when some variable misses a fixed bar (so the oracle's roundoff
+    floor decides whether the case passes)."""
+    e1, ei = rel_l1(w, gpu, ref), rel_linf(gpu, ref)
+    return bool(np.any(e1 > L1_BAR) or np.any(ei > LINF_BAR))
+
+
+def floor_progress(orc, make, ref, label, chunk=5):
+    """(floor L1, floor L-inf) as in oracle_floor, for a reference already
+    computed, with the oracle runs reporting progress."""
+    w = make()
+    wp = make()
+    wp.prim = raise_one_ulp(np.asarray(wp.prim))
+    pert = oracle_progress(orc, wp, chunk=chunk, label=label + " +1 ulp")
+    fma = oracle_progress(orc, make(), fma=True, chunk=chunk, label=label)
+    f1 = np.maximum(rel_l1(w, pert, ref), rel_l1(w, fma, ref))
+    fi = np.maximum(rel_linf(pert, ref), rel_linf(fma, ref))
+    return f1, fi
+
+
 def bars(floor_l1=None, floor_linf=None):
     """Per-variable (L1, L-inf) bars and the variables whose bar was raised to
     twice the oracle's floor."""
