@@ -41,7 +41,6 @@ template <int NDIM, class SP, bool UNI>
 __global__ void __launch_bounds__(256) k_fill_faces(GridConst G, const int* __restrict__ tasks, int ntasks, Tables T,
                                                    void* __restrict__ slot, PhysConst P, FixedBC fixed) {
   const int* __restrict__ link = T.link;
-  const int* __restrict__ pos = T.pos;
   const int nx = G.nx, ng = G.ng;
   const int ncell = NDIM == 3 ? ng * nx * nx : ng * nx;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;

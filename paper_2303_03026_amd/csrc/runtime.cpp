@@ -133,7 +133,7 @@ long long slot_bytes_of(const amrvac_grid_desc* g, long nb) {
 class BlockLookup {
  public:
   static constexpr long kDenseSlots = 1L << 24;
-  BlockLookup(int ndim, const int* base, int finest, int nb) : ndim_(ndim) {
+  BlockLookup(int ndim, const int* base, int finest, int nb) {
     long total = 0;
     for (int l = 1; l <= finest; ++l) {
       long n = 1;
@@ -198,7 +198,6 @@ class BlockLookup {
 
  private:
   long index(const KeyL& k) const { return off_[k.l] + (k.k * dim_[k.l][1] + k.j) * dim_[k.l][0] + k.i; }
-  int ndim_;
   bool dense_ = false, overlap_ = false;
   int finest_ = 0;
   long dim_[MAXLEV + 2][3] = {};
