@@ -16,17 +16,29 @@ measured on MI355X, rounded up:
   current sheet 192^3, 1 step                             L1 1e-7, L-inf 5e-7,
       momentum 1.5e-5 / 4e-5
   shock cloud 32^3 base, 3 levels, 100 steps              L1 5e-7, L-inf 2e-6
+  the full grids at their stated lengths (AMRVAC_FULL_LENGTH=1; the oracle
+  takes minutes per case):
+    random modes 256^3, 50 steps                          L1 1e-6, L-inf 2e-6
+      (measured 3.2e-7 m_x, 6.1e-7 rho)
+    shock cloud 128^3 base, 100 steps                     L1 5e-7, L-inf 2e-6
+      (measured 1.5e-7, 7.0e-7)
+    current sheet 192^3, 200 steps                        L1 1.5e-6, L-inf 1e-5,
+      m_x, m_z 2e-3 / 3e-3, m_y 2e-4 / 1.5e-4 (measured m_x 6.1e-4 / 8.9e-4,
+      m_y 6.7e-5 / 4.5e-5, m_z 1.7e-4 / 3.1e-4, rho 4.6e-7 / 3.6e-6)
   smooth AMR 3D, 4 steps                                  L1 5e-7, L-inf 2e-6,
       psi 2e-5 / 2e-4 (psi ~ 0.01 |B|: its FP32 error is that of B)
   Alfven shock-cloud, 3 levels, koren + HLLD, 30 steps   L1 5e-7, L-inf 2e-6
   Kelvin-Helmholtz, 3 levels, van Leer + HLLC, 30 steps   L1 5e-7, L-inf 3e-6,
       m_y 3e-4 / 5e-4 (the 1e-3 noise and the growing mode)
 """
+import os
+
 import numpy as np
 import pytest
 
 from paper_2303_03026_amd import inputs
 import mixed_error
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -122,3 +134,25 @@ def test_mixed_kelvin_helmholtz(amr, orc):
     field rows are exactly zero on both sides)."""
     mixed_case(amr, orc, inputs.kelvin_helmholtz(max_level=3, limiter=0, flux=2, nsteps=30),
                "kelvin_helmholtz_l3_x30", per_var(5e-7, m_y=3e-4), per_var(3e-6, m_y=5e-4))
+
+
+FULL = {
+    "random_modes_256_x50": (lambda: inputs.random_modes(256, 3, seed=1, nsteps=50), 1e-6, 2e-6),
+    "shock_cloud_128_x100": (lambda: inputs.shock_cloud_amr(nsteps=100), 5e-7, 2e-6),
+    "current_sheet_192_x200": (lambda: inputs.current_sheet(192, nsteps=200),
+                               per_var(1.5e-6, m_x=2e-3, m_y=2e-4, m_z=2e-3),
+                               per_var(1e-5, m_x=3e-3, m_y=1.5e-4, m_z=3e-3)),
+}
+
+
+@pytest.mark.skipif(os.environ.get("AMRVAC_FULL_LENGTH") != "1",
+                    reason="full-size run at the stated length: the oracle takes minutes (AMRVAC_FULL_LENGTH=1)")
+@pytest.mark.parametrize("name", list(FULL))
+def test_mixed_full_size_at_stated_length(amr, orc, name):
+    make, b1, bi = FULL[name]
+    w = make()
+    ref = parity.oracle_progress(orc, w, chunk=10, label=name)
+    gpu, fl = run_mixed(amr, make(), w.nsteps)
+    assert fl[0] == 0
+    l1, li = mixed_error.errors(w, gpu, ref)
+    mixed_error.check(name, l1, li, b1, bi)
