@@ -55,8 +55,14 @@ __device__ __forceinline__ long cell5(const GridConst& G, int x, int y, int z = 
 // CFL: also fold the CFL rate of every output cell into the job's running
 // maximum (C.rate_bits, C.nan), leaving out the cells next to faces towards
 // finer leaves when C.skip_fine (the flux correction changes them later).
+// Three workgroups per CU (at most 168 VGPRs; the 3D instances spill a few
+// hundred bytes per lane): a plane's 17th faces leave some waves idle at
+// the barrier after the face evaluations (in the x-z sweep a single wave
+// works through them), and a third resident workgroup fills those slots.
+// With two per CU (256 VGPRs, little spilling) the 3D stage took 12% (FP64)
+// and 24% (FP32-mixed) longer; with four, FP64 lost that gain again.
 template <int NDIM, class SP, bool W1, bool REG, bool CFL>
-__global__ void __launch_bounds__(256, NDIM == 3 ? 2 : 3) k_stage_fused5(GridConst G, Tables T, JobScalars J, const void* __restrict__ in,
+__global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, JobScalars J, const void* __restrict__ in,
                                                          const void* base, void* out, double wgt, PhysConst P,
                                                          DevStatus* st, double* __restrict__ part,
                                                          typename SP::R* __restrict__ freg, JobCfl C) {

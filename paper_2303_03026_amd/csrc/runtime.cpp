@@ -771,8 +771,13 @@ JobCfl cfl_state(amrvac_ctx* c, double* dt, double* ch, double* kappa) {
 // The fused stage can fold the next step's CFL rate into its output only
 // where nothing changes that output afterwards: with coarse/fine flux
 // correction the stage leaves out the cells next to faces towards finer
-// leaves, and a pass after the correction folds those in.
-bool can_carry(const amrvac_ctx* c) { return c->path == AMRVAC_PATH_FUSED; }
+// leaves, and a pass after the correction folds those in.  The 3D stage
+// with three ghost layers does not fold: there the folding instance's
+// launch takes 0.5-0.6 ms longer on 256^3 (the extra live state of the
+// update spills at 168 VGPRs) while the separate CFL pass takes 0.2-0.35 ms.
+bool can_carry(const amrvac_ctx* c) {
+  return c->path == AMRVAC_PATH_FUSED && !(c->G.ng == 3 && c->G.ndim == 3);
+}
 
 // flux registers for the fused stage, when a coarse/fine correction follows
 // it (else null)
