@@ -14,13 +14,13 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamrvac.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["plain.hip", "fused.hip", "fused5.hip", "runtime.cpp"]
+SOURCES = ["fused5.hip", "fused5_hllc.hip", "fused5_hlld.hip", "fused.hip", "plain.hip", "runtime.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-Rpass-analysis=kernel-resource-usage", "-ffp-contract=on", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics"]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 6) -> str:
     objs = []
     procs = []
     for src in SOURCES:
