@@ -54,11 +54,14 @@ __device__ __forceinline__ long cell5(const GridConst& G, int x, int y, int z = 
   return ((long)(G.ndim == 3 ? z + NG5 : 0) * G.pn + (y + NG5)) * G.pn + (x + NG5);
 }
 
-// REG: the instantiation for grids with a coarse/fine flux correction; the
-// face fluxes evaluated on block faces towards finer or coarser leaves are
-// stored in the flux registers freg ([block][face][var][face cell], face cell
-// t1 + 16 t2 with t1 along the face's first transverse axis: y for x faces,
-// x otherwise) for the correction pass.
+// freg (grids with a coarse/fine flux correction; else null): the face
+// fluxes evaluated on block faces towards finer or coarser leaves are stored
+// in these flux registers ([block][face][var][face cell], face cell t1 + 16
+// t2 with t1 along the face's first transverse axis: y for x faces, x
+// otherwise) for the correction pass.  One instance serves both cases: a
+// separate instance without the register stores was measured slower (its
+// register allocation spills 448 against 176 B per lane in 3D FP64, and a
+// c1 step with 'wenozp5' + HLLC took 19.3 against 16.5 ms).
 // CFL: also fold the CFL rate of every output cell into the job's running
 // maximum (C.rate_bits, C.nan), leaving out the cells next to faces towards
 // finer leaves when C.skip_fine (the flux correction changes them later).
@@ -68,7 +71,7 @@ __device__ __forceinline__ long cell5(const GridConst& G, int x, int y, int z = 
 // works through them), and a third resident workgroup fills those slots.
 // With two per CU (256 VGPRs, little spilling) the 3D stage took 12% (FP64)
 // and 24% (FP32-mixed) longer; with four, FP64 lost that gain again.
-template <int NDIM, class SP, bool W1, bool REG, bool CFL, int LIM, int FLX>
+template <int NDIM, class SP, bool W1, bool CFL, int LIM, int FLX>
 __global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, JobScalars J, const void* __restrict__ in,
                                                          const void* base, void* out, double wgt, PhysConst P,
                                                          DevStatus* st, double* __restrict__ part,
@@ -133,7 +136,7 @@ __global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, 
   // faces with flux registers (bit f: block face f)
   constexpr int NFC = NDIM == 3 ? BN5 * BN5 : BN5;
   unsigned regs = 0, skips = 0;
-  if constexpr (REG) {
+  if (freg) {
 #pragma unroll
     for (int f = 0; f < 2 * NDIM; ++f)
       if (lk[f] == LINK_FINE || lk[f] == LINK_COARSE) regs |= 1u << f;
@@ -236,10 +239,10 @@ __global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, 
     R f1[NV], f2[NV];
     if constexpr (FIRST) {
       face(A0{}, DX{}, j, i, lamx, f1);
-      if (REG && (regs & 1u) && i == 0) put_reg(0, rofs + j, f1);
+      if ((regs & 1u) && i == 0) put_reg(0, rofs + j, f1);
     }
     face(A1{}, dir2, j, i, lam2, f2);
-    if (REG && (regs & (1u << (2 * D2))) && i == 0) put_reg(2 * D2, rofs + j, f2);
+    if ((regs & (1u << (2 * D2))) && i == 0) put_reg(2 * D2, rofs + j, f2);
     if ((FIRST && t < BN5) || (t >= 64 && t < 64 + BN5)) {
       R fe[NV];
       if (t < BN5) {
@@ -247,13 +250,13 @@ __global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, 
           face(A0{}, DX{}, t, BN5, lamx, fe);
 #pragma unroll
           for (int q = 0; q < NV; ++q) Ex[q][t] = fe[q];
-          if (REG && (regs & 2u)) put_reg(1, rofs + t, fe);
+          if (regs & 2u) put_reg(1, rofs + t, fe);
         }
       } else {
         face(A1{}, dir2, t - 64, BN5, lam2, fe);
 #pragma unroll
         for (int q = 0; q < NV; ++q) Ey[q][t - 64] = fe[q];
-        if (REG && (regs & (2u << (2 * D2)))) put_reg(2 * D2 + 1, rofs + t - 64, fe);
+        if (regs & (2u << (2 * D2))) put_reg(2 * D2 + 1, rofs + t - 64, fe);
       }
     }
     __syncthreads();  // every face evaluated: W is free, Ex / Ey written
@@ -430,45 +433,34 @@ __global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, 
   if (nfix) atomicAdd(&st->nfix, (unsigned long long)nfix);
 }
 
-template <int ND, class SPT, bool W1, bool RG, bool CF, int LIM, int FLX>
+template <int ND, class SPT, bool W1, bool CF, int LIM, int FLX>
 hipError_t f5_launch(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J, const void* in,
                      const void* base, void* out, double w, const PhysConst& P, DevStatus* st, double* pt,
                      void* freg, const JobCfl& C) {
-  k_stage_fused5<ND, SPT, W1, RG, CF, LIM, FLX><<<T.nactive, 256, 0, s>>>(
+  k_stage_fused5<ND, SPT, W1, CF, LIM, FLX><<<T.nactive, 256, 0, s>>>(
       G, T, J, in, base, out, w, P, st, pt, static_cast<typename SPT::R*>(freg), C);
   return hipGetLastError();
 }
 
-// the instance for (w == 1, flux registers, CFL fold); the 3D stage does not
-// fold the CFL rate (the runtime never asks it to), so those instances are
-// not built
+// the instance for (w == 1, CFL fold); the 3D stage does not fold the CFL
+// rate (the runtime never asks it to), so those instances are not built
 template <int ND, class SPT, int LIM, int FLX>
 hipError_t f5_dispatch(hipStream_t s, const GridConst& G, const Tables& T, const JobScalars& J, const void* in,
                        const void* base, void* out, double w, const PhysConst& P, DevStatus* st, double* pt,
                        void* freg, const JobCfl* cfl) {
   const JobCfl C = cfl ? *cfl : JobCfl{};
-  const bool w1 = w == 1.0, rg = freg != nullptr;
+  const bool w1 = w == 1.0;
 #define AMRVAC_F5_ARGS s, G, T, J, in, base, out, w, P, st, pt, freg, C
   if constexpr (ND == 3) {
     if (cfl) return hipErrorInvalidValue;
-    if (w1)
-      return rg ? f5_launch<3, SPT, true, true, false, LIM, FLX>(AMRVAC_F5_ARGS)
-                : f5_launch<3, SPT, true, false, false, LIM, FLX>(AMRVAC_F5_ARGS);
-    return rg ? f5_launch<3, SPT, false, true, false, LIM, FLX>(AMRVAC_F5_ARGS)
-              : f5_launch<3, SPT, false, false, false, LIM, FLX>(AMRVAC_F5_ARGS);
+    return w1 ? f5_launch<3, SPT, true, false, LIM, FLX>(AMRVAC_F5_ARGS)
+              : f5_launch<3, SPT, false, false, LIM, FLX>(AMRVAC_F5_ARGS);
   } else {
-    if (w1) {
-      if (rg)
-        return cfl ? f5_launch<2, SPT, true, true, true, LIM, FLX>(AMRVAC_F5_ARGS)
-                   : f5_launch<2, SPT, true, true, false, LIM, FLX>(AMRVAC_F5_ARGS);
-      return cfl ? f5_launch<2, SPT, true, false, true, LIM, FLX>(AMRVAC_F5_ARGS)
-                 : f5_launch<2, SPT, true, false, false, LIM, FLX>(AMRVAC_F5_ARGS);
-    }
-    if (rg)
-      return cfl ? f5_launch<2, SPT, false, true, true, LIM, FLX>(AMRVAC_F5_ARGS)
-                 : f5_launch<2, SPT, false, true, false, LIM, FLX>(AMRVAC_F5_ARGS);
-    return cfl ? f5_launch<2, SPT, false, false, true, LIM, FLX>(AMRVAC_F5_ARGS)
-               : f5_launch<2, SPT, false, false, false, LIM, FLX>(AMRVAC_F5_ARGS);
+    if (w1)
+      return cfl ? f5_launch<2, SPT, true, true, LIM, FLX>(AMRVAC_F5_ARGS)
+                 : f5_launch<2, SPT, true, false, LIM, FLX>(AMRVAC_F5_ARGS);
+    return cfl ? f5_launch<2, SPT, false, true, LIM, FLX>(AMRVAC_F5_ARGS)
+               : f5_launch<2, SPT, false, false, LIM, FLX>(AMRVAC_F5_ARGS);
   }
 #undef AMRVAC_F5_ARGS
 }
