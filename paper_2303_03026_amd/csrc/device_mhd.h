@@ -510,24 +510,41 @@ __device__ __forceinline__ double weno5_face(double vm2, double vm1, double v0, 
   const double be0 = (13.0 / 12.0) * a0 * a0 + 0.25 * b0 * b0;
   const double be1 = (13.0 / 12.0) * a1 * a1 + 0.25 * b1 * b1;
   const double be2 = (13.0 / 12.0) * a2 * a2 + 0.25 * b2 * b2;
+  // the three reciprocals of the weights come from one reciprocal of their
+  // product (the refined hardware reciprocal is the costly operation here);
+  // the factors are at least 1e-40 (1e-12 for 'weno5'), so the product does
+  // not underflow, and it overflows only for cell values beyond about 1e50
+  auto rcp3 = [](double x0, double x1, double x2, double& r0, double& r1, double& r2) {
+    const double x01 = x0 * x1;
+    const double r = rcp_(x01 * x2);
+    r0 = r * (x1 * x2);
+    r1 = r * (x0 * x2);
+    r2 = r * x01;
+  };
   double al0, al1, al2;
-  if (lim == LIM_WENOZ5) {
+  if (lim == LIM_WENOZ5 || lim == LIM_WENOZP5) {
     const double tau5 = fabs(be0 - be2);
-    al0 = 0.1 * (1.0 + div_(tau5, be0 + 1e-40));
-    al1 = 0.6 * (1.0 + div_(tau5, be1 + 1e-40));
-    al2 = 0.3 * (1.0 + div_(tau5, be2 + 1e-40));
-  } else if (lim == LIM_WENOZP5) {
-    const double tau5 = fabs(be0 - be2);
-    const double lt = div_(lambda, tau5 + 1e-40);
-    const double r0 = div_(tau5, be0 + 1e-40), r1 = div_(tau5, be1 + 1e-40), r2 = div_(tau5, be2 + 1e-40);
-    al0 = 0.1 * (1.0 + r0 * r0 + lt * (be0 + 1e-40));
-    al1 = 0.6 * (1.0 + r1 * r1 + lt * (be1 + 1e-40));
-    al2 = 0.3 * (1.0 + r2 * r2 + lt * (be2 + 1e-40));
+    const double e0 = be0 + 1e-40, e1 = be1 + 1e-40, e2 = be2 + 1e-40;
+    double i0, i1, i2;
+    rcp3(e0, e1, e2, i0, i1, i2);
+    const double r0 = tau5 * i0, r1 = tau5 * i1, r2 = tau5 * i2;
+    if (lim == LIM_WENOZ5) {
+      al0 = 0.1 * (1.0 + r0);
+      al1 = 0.6 * (1.0 + r1);
+      al2 = 0.3 * (1.0 + r2);
+    } else {
+      const double lt = div_(lambda, tau5 + 1e-40);
+      al0 = 0.1 * (1.0 + r0 * r0 + lt * e0);
+      al1 = 0.6 * (1.0 + r1 * r1 + lt * e1);
+      al2 = 0.3 * (1.0 + r2 * r2 + lt * e2);
+    }
   } else {
     const double e0 = 1e-6 + be0, e1 = 1e-6 + be1, e2 = 1e-6 + be2;
-    al0 = div_(0.1, e0 * e0);
-    al1 = div_(0.6, e1 * e1);
-    al2 = div_(0.3, e2 * e2);
+    double i0, i1, i2;
+    rcp3(e0 * e0, e1 * e1, e2 * e2, i0, i1, i2);
+    al0 = 0.1 * i0;
+    al1 = 0.6 * i1;
+    al2 = 0.3 * i2;
   }
   return div_(al0 * q0 + al1 * q1 + al2 * q2, al0 + al1 + al2);
 }
