@@ -132,6 +132,14 @@ struct FaceConst {
   R ch, hic, gamma, inv_gm1;
 };
 
+// Waves per SIMD the stage is built for: FP64 3D holds the z queue beside a
+// face evaluation (two waves, 230-256 VGPRs); in 2D there is no z queue and
+// three waves fit (at most 168 VGPRs; measured on the 6-level Alfven
+// shock-cloud grid with HLLD, 0.79 against 0.83 ms per step, HLL and HLLC
+// unchanged).
+template <class SP>
+constexpr int kWavesPerEU2D = SP::kWavesPerEU < 3 ? 3 : SP::kWavesPerEU;
+
 // W1: the stage weight is 1 (out = in + dt L(in)), so base is not read.
 // CFL: also fold the CFL rate of every output cell into the job's running
 // maximum (C.rate_bits, C.nan), as the time-step pass would from out.
@@ -139,7 +147,7 @@ struct FaceConst {
 // w = (g % 8) * per_xcd + g / 8 when tune.xcd is set (each XCD gets a
 // contiguous run of the Morton-ordered list), else w = g.
 template <int NDIM, class SP, bool W1, bool CFL, int LIM, int FLX, bool REG>
-__global__ void __launch_bounds__(256, SP::kWavesPerEU)
+__global__ void __launch_bounds__(256, NDIM == 2 ? kWavesPerEU2D<SP> : SP::kWavesPerEU)
 k_stage_fused(GridConst G, Tables T, JobScalars J, FusedTune tune, int per_xcd, const void* __restrict__ in,
               const void* base, void* out, double wgt, PhysConst P, DevStatus* st, JobCfl C,
               typename SP::R* __restrict__ freg) {
