@@ -533,10 +533,12 @@ __device__ __forceinline__ double weno5_face(double vm2, double vm1, double v0, 
       al1 = 0.6 * (1.0 + r1);
       al2 = 0.3 * (1.0 + r2);
     } else {
-      const double lt = div_(lambda, tau5 + 1e-40);
-      al0 = 0.1 * (1.0 + r0 * r0 + lt * e0);
-      al1 = 0.6 * (1.0 + r1 * r1 + lt * e1);
-      al2 = 0.3 * (1.0 + r2 * r2 + lt * e2);
+      // the weights times tau5 + 1e-40 (their ratios are what counts), which
+      // takes the quotient lambda / (tau5 + 1e-40) out
+      const double tp = tau5 + 1e-40;
+      al0 = 0.1 * (tp + (tp * r0) * r0 + lambda * e0);
+      al1 = 0.6 * (tp + (tp * r1) * r1 + lambda * e1);
+      al2 = 0.3 * (tp + (tp * r2) * r2 + lambda * e2);
     }
   } else {
     const double e0 = 1e-6 + be0, e1 = 1e-6 + be1, e2 = 1e-6 + be2;
