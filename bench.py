@@ -10,6 +10,7 @@ inside the timed region) and the CPU oracle timed on a bounded sample of the
 same workload.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -40,6 +41,41 @@ def kernel_hash():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+# The same for the fused stage with three ghost layers ('wenozp5' + HLLC on
+# random modes 256^3): VALU wave-instructions per launch.
+COUNTER_PROFILE5 = "profiles/stage_fused5_wave_states_random_modes_256.md"
+KERNEL_SOURCES5 = tuple("paper_2303_03026_amd/csrc/" + f for f in (
+    "fused5_stage.h", "fused5.hip", "fused5_hllc.hip", "fused5_hlld.hip", "device_mhd.h", "kernels.h"))
+
+
+def kernel_hash5():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES5:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stage5_counters(precision, workload, n, limiter, flux):
+    """(None, VALU wave-instructions per launch, the mean over one step's
+    three stages) of the five-cell stage from the committed profile, or None
+    when it does not match the kernel sources, the scheme or the grid."""
+    if workload != "random_modes" or n != 256 or limiter != LIMITERS.index("wenozp5") or flux != 2:
+        return None
+    try:
+        with open(os.path.join(ROOT, COUNTER_PROFILE5)) as f:
+            prof = json.loads(f.read().split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if prof.get("kernel_sources_sha16") != kernel_hash5():
+        return None
+    rec = prof.get("valu_insts", {}).get(precision)
+    if rec is None:
+        return None
+    return None, (rec["w1"] + 2 * rec["w_lt1"]) / 3.0
 
 
 def stage_counters(precision, tune, workload, n):
@@ -246,8 +282,12 @@ def time_grid(w, path, mixed, steps, warmup, tune_mode="auto", graph_pass=False,
     avg_ms = sum(sum(x) for x in stage_ms) / (3 * steps)
     # per cell: stage 1 reads in and writes out; stages 2 and 3 also read base
     bytes_per_launch = cells * state_bytes * (2 + 3 + 3) / 3.0
-    counters = (stage_counters("mixed" if mixed else "f64", tune, w.workload_name, w.n_linear)
-                if fused2 and w.limiter == 0 and w.flux == 0 else None)
+    if fused2 and w.limiter == 0 and w.flux == 0:
+        counters = stage_counters("mixed" if mixed else "f64", tune, w.workload_name, w.n_linear)
+    elif pth == amrvac.PATH_FUSED and w.ng == 3:
+        counters = stage5_counters("mixed" if mixed else "f64", w.workload_name, w.n_linear, w.limiter, w.flux)
+    else:
+        counters = None
     rec = {"workload": label or w.name, "path": path, "precision": "fp32-mixed" if mixed else "fp64",
            "blocks": int(w.nblocks), "cells": cells, "steps": steps, "warmup": warmup,
            "ms_per_step": (t1 - t0) * 1e3 / steps, "mcell_updates_per_s": cells * steps / (t1 - t0) / 1e6,
@@ -439,6 +479,13 @@ def main():
             forms["fused_fp64_" + label] = time_grid(wf, "fused", False, fk, args.warmup, label=label)
             if name == "current_sheet":
                 forms["fused_mixed_" + label] = time_grid(wf, "fused", True, fk, args.warmup, label=label)
+        # the fifth-order reconstruction on the same grid (three ghost layers)
+        w5 = dataclasses.replace(w, limiter=LIMITERS.index("wenozp5"), flux=2, ng=3)
+        w5.workload_name, w5.n_linear = "random_modes", 256
+        label = "random_modes_256_wenozp5_hllc"
+        forms["fused_fp64_" + label] = time_grid(w5, "fused", False, fk, args.warmup, label=label)
+        forms["fused_mixed_" + label] = time_grid(w5, "fused", True, fk, args.warmup, label=label)
+        del w5
         if args.serve_jobs > 0:
             forms["served_mix"] = served(args.serve_jobs)
 
