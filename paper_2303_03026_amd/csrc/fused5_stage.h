@@ -222,9 +222,9 @@ __global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, 
   // (i, j); along the second it evaluates the lower face of cell (j, i)
   // (transposed), so that in both directions the next face of a thread's
   // lies in the next lane of the same wave and reaches it by a lane shuffle.
-  // The 17th faces go to the first wave's lanes 0..15 (first axis) and the
-  // second wave's (second axis), through LDS: no wave takes more than three
-  // face evaluations.  d1 (first axis) and d2 (second axis) are the
+  // The 17th faces go to lanes 0..15 of two waves that change with the
+  // plane (first axis and second axis), through LDS: no wave takes more than
+  // three face evaluations.  d1 (first axis) and d2 (second axis) are the
   // differences F(f+1) - F(f) of cell (i, j).
   // next - this of two face fluxes: at face precision, the energy's in FP64
   auto diff = [&](int q, R next, R f) -> double {
@@ -243,20 +243,28 @@ __global__ void __launch_bounds__(256, 3) k_stage_fused5(GridConst G, Tables T, 
     }
     face(A1{}, dir2, j, i, lam2, f2);
     if ((regs & (1u << (2 * D2))) && i == 0) put_reg(2 * D2, rofs + j, f2);
-    if ((FIRST && t < BN5) || (t >= 64 && t < 64 + BN5)) {
-      R fe[NV];
-      if (t < BN5) {
-        if constexpr (FIRST) {
-          face(A0{}, DX{}, t, BN5, lamx, fe);
+    {
+      // the 17th faces: first axis on wave pl % 4, second axis on wave
+      // (pl + 2) % 4, so that the extra pass moves between the SIMDs from
+      // plane to plane (with it always on waves 0 and 1 the 3D stage took
+      // 3% (FP64) and 5% (FP32-mixed) longer)
+      const int wv = t >> 6, ln = t & 63;
+      const int xw = FIRST ? (pl & 3) : -1, yw = (pl + 2) & 3;
+      if ((wv == xw || wv == yw) && ln < BN5) {
+        R fe[NV];
+        if (wv == xw) {
+          if constexpr (FIRST) {
+            face(A0{}, DX{}, ln, BN5, lamx, fe);
 #pragma unroll
-          for (int q = 0; q < NV; ++q) Ex[q][t] = fe[q];
-          if (regs & 2u) put_reg(1, rofs + t, fe);
+            for (int q = 0; q < NV; ++q) Ex[q][ln] = fe[q];
+            if (regs & 2u) put_reg(1, rofs + ln, fe);
+          }
+        } else {
+          face(A1{}, dir2, ln, BN5, lam2, fe);
+#pragma unroll
+          for (int q = 0; q < NV; ++q) Ey[q][ln] = fe[q];
+          if (regs & (2u << (2 * D2))) put_reg(2 * D2 + 1, rofs + ln, fe);
         }
-      } else {
-        face(A1{}, dir2, t - 64, BN5, lam2, fe);
-#pragma unroll
-        for (int q = 0; q < NV; ++q) Ey[q][t - 64] = fe[q];
-        if (regs & (2u << (2 * D2))) put_reg(2 * D2 + 1, rofs + t - 64, fe);
       }
     }
     __syncthreads();  // every face evaluated: W is free, Ex / Ey written
