@@ -185,7 +185,7 @@ int amrvac_stage(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double
  * grids with coarse/fine flux corrections (which change the coarse cells
  * next to finer leaves after the stage) those cells are folded in after the
  * correction.  On the plain path, and for 3D contexts with three ghost
- * layers (whose folding stage costs more than the separate pass), it is
+ * layers (whose folding stage is no cheaper than the separate pass), it is
  * exactly amrvac_stage. */
 int amrvac_stage_cfl(amrvac_ctx* c, int in_slot, int base_slot, int out_slot, double w,
                      const double* dt_dev, const double* ch_dev, const double* kappa_dev);

@@ -772,9 +772,9 @@ JobCfl cfl_state(amrvac_ctx* c, double* dt, double* ch, double* kappa) {
 // where nothing changes that output afterwards: with coarse/fine flux
 // correction the stage leaves out the cells next to faces towards finer
 // leaves, and a pass after the correction folds those in.  The 3D stage
-// with three ghost layers does not fold: there the folding instance's
-// launch takes 0.5-0.6 ms longer on 256^3 (the extra live state of the
-// update spills at 168 VGPRs) while the separate CFL pass takes 0.2-0.35 ms.
+// with three ghost layers does not fold: on 256^3 a step with the folding
+// instance and no separate CFL pass was no faster in FP64 and 0.3 ms slower
+// in FP32-mixed (the update's extra live state at 168 VGPRs).
 bool can_carry(const amrvac_ctx* c) {
   return c->path == AMRVAC_PATH_FUSED && !(c->G.ng == 3 && c->G.ndim == 3);
 }
