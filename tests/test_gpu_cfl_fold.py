@@ -34,11 +34,21 @@ def manual(amr, w, nsteps, precision, fold):
     return out, dts
 
 
+def five_cell(w):
+    w.limiter, w.flux, w.ng = 6, 2, 3  # 'wenozp5' + HLLC
+    return w
+
+
 CASES = [("random_modes_3d_64", lambda: inputs.random_modes(64, 3, seed=2), 0),
          ("random_modes_3d_64_mixed", lambda: inputs.random_modes(64, 3, seed=3), 1),
          ("current_sheet_48", lambda: inputs.current_sheet(48, nsteps=4), 0),
          ("random_modes_2d_128", lambda: inputs.random_modes(128, 2, seed=4), 0),
-         ("smooth_amr_3d", lambda: inputs.smooth_amr_state(3, nb1=2, seed=5), 0)]
+         ("smooth_amr_3d", lambda: inputs.smooth_amr_state(3, nb1=2, seed=5), 0),
+         # three ghost layers: the 2D stage folds, the 3D one leaves the rate
+         # to the separate pass; either way the steps are the same
+         ("wenozp5_2d_64", lambda: five_cell(inputs.random_modes(64, 2, seed=6)), 0),
+         ("wenozp5_3d_32", lambda: five_cell(inputs.random_modes(32, 3, seed=7)), 0),
+         ("wenozp5_3d_32_mixed", lambda: five_cell(inputs.random_modes(32, 3, seed=8)), 1)]
 
 
 @pytest.mark.parametrize("name,make,precision", CASES, ids=[c[0] for c in CASES])
