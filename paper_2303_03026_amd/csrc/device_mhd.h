@@ -444,7 +444,7 @@ __device__ __forceinline__ void face_flux(R wl[NV], R wr[NV], R ch, R half_inv_c
     hll_glm_flux<D, R>(wl, wr, ch, half_inv_ch, gamma, inv_gm1, F);
 }
 
-// ... and at run time (the per-kernel path and the flux correction)
+// ... and at run time (the per-kernel path)
 template <int D, class R>
 __device__ __forceinline__ void face_flux_rt(int flux, R wl[NV], R wr[NV], R ch, R half_inv_ch, R gamma, R inv_gm1,
                                              R F[NV]) {
@@ -580,8 +580,8 @@ __device__ __forceinline__ double mp5_face(double vm2, double vm1, double v0, do
   return u_or + mm2(u_min - u_or, u_max - u_or);
 }
 
-// the same with the limiter chosen at run time (the per-kernel path and the
-// coarse/fine flux correction)
+// the same with the limiter chosen at run time (the per-kernel path, and the
+// fused stage with three ghost layers run with a two-ghost-layer limiter)
 template <class R>
 __device__ __forceinline__ void reconstruct_face(int lim, const R wm[NV], const R wa[NV], const R wb[NV],
                                                  const R wp[NV], R wl[NV], R wr[NV]) {
